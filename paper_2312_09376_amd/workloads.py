@@ -1,0 +1,102 @@
+"""Seeded synthetic inputs for RBT solves.
+
+This module is the only code shared by the HIP path's tests/benchmark and the
+CPU oracle: it draws matrices and right-hand sides and holds none of the
+method's arithmetic (no butterflies, no elimination, no solves).
+
+Matrix families (all square, FP64, column-major when handed to the device):
+  randn      i.i.d. N(0,1) entries (the paper's `randn` family, Table 1)
+  hostile    randn with the leading 8x8 block scaled by 1e-12: elimination
+             without pivoting meets tiny leading pivots unless transformed
+  shifted    N(0,1)/sqrt(n) + I (well conditioned, for exact-solution checks)
+  orthog     A_ij = sqrt(2/(n+1)) sin(i j pi/(n+1)), symmetric orthogonal
+             (Sec. 6.3 failure study), so A^-1 = A
+  logcond    Q1 diag(sigma) Q2^T with sigma log-spaced over [1/cond, 1] and
+             random orthogonal Q1, Q2 (products of Householder reflectors)
+Host draws use NumPy's PCG64 with the given seed; device draws (large n) use
+torch's seeded generator on the GPU.
+"""
+import math
+
+import numpy as np
+
+MATRIX_SEED = 42   # the paper's tester seeds: matrix 42, right-hand side 64
+RHS_SEED = 64
+RBT_SEED = 2023
+
+
+def randn(n, k, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.asfortranarray(rng.standard_normal((n, k)))
+
+
+def randn_matrix(n, seed=MATRIX_SEED):
+    return randn(n, n, seed)
+
+
+def hostile(n, seed=MATRIX_SEED, block=8, scale=1e-12):
+    A = randn_matrix(n, seed)
+    b = min(block, n)
+    A[:b, :b] *= scale
+    return A
+
+
+def shifted(n, seed=MATRIX_SEED):
+    A = randn_matrix(n, seed) / math.sqrt(n)
+    A[np.diag_indices(n)] += 1.0
+    return A
+
+
+def orthog(n):
+    i = np.arange(1, n + 1, dtype=np.float64)
+    return np.asfortranarray(math.sqrt(2.0 / (n + 1)) * np.sin(np.outer(i, i) * math.pi / (n + 1)))
+
+
+def householder_orthogonal(n, seed, reflectors=8):
+    """Dense orthogonal matrix: product of `reflectors` random Householder
+    reflectors I - 2 v v^T / (v^T v)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Q = np.eye(n)
+    for _ in range(reflectors):
+        v = rng.standard_normal(n)
+        Q -= np.outer(2.0 * v / (v @ v), v @ Q)
+    return Q
+
+
+def logcond(n, seed=MATRIX_SEED, cond=1e6):
+    sigma = np.logspace(0.0, -math.log10(cond), n) if n > 1 else np.ones(1)
+    Q1 = householder_orthogonal(n, seed)
+    Q2 = householder_orthogonal(n, seed + 1)
+    return np.asfortranarray((Q1 * sigma) @ Q2.T)
+
+
+def batch_sizes(count=2048, lo=37, hi=1500, rhs_lo=1, rhs_hi=16, seed=7):
+    """Sizes of a batch of independent systems: n ~ U{lo..hi}, nrhs ~ U{rhs_lo..rhs_hi}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = rng.integers(lo, hi + 1, size=count)
+    k = rng.integers(rhs_lo, rhs_hi + 1, size=count)
+    return n.astype(np.int64), k.astype(np.int64)
+
+
+# ---- device-side draws for sizes where host generation would dominate ----
+
+def device_randn(n, k, seed, device="cuda", dtype=None):
+    """Column-major (n x k) FP64 N(0,1) tensor drawn on the device."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    t = torch.randn((k, n), generator=g, device=device, dtype=dtype or torch.float64)
+    return t.t()   # stride (1, n): column-major view
+
+
+def device_hostile(n, seed=MATRIX_SEED, block=8, scale=1e-12, device="cuda"):
+    A = device_randn(n, n, seed, device)
+    b = min(block, n)
+    A[:b, :b] *= scale
+    return A
+
+
+def device_shifted(n, seed=MATRIX_SEED, device="cuda"):
+    A = device_randn(n, n, seed, device) / math.sqrt(n)
+    A.diagonal().add_(1.0)
+    return A
