@@ -1,0 +1,162 @@
+/*
+ * rbt.h - C ABI of the MI355X (gfx950) generalized random butterfly
+ * transform (RBT) solver.
+ *
+ * Method: Lindquist, Luszczek, Dongarra, "Generalizing Random Butterfly
+ * Transforms to Arbitrary Matrix Sizes" (ACM TOMS; arXiv 2312.09376).
+ * A x = b is rewritten as (U^T A V)(V^-1 x) = U^T b (Sec. 1, Eq. 1); the
+ * transformed matrix is factored by Gaussian elimination with no pivoting
+ * (GENP), the two triangular systems are solved and x = V x~ is recovered.
+ * U and V are depth-d generalized (semi-Parker) RBTs (Sec. 3, Eq. 2-4)
+ * truncated to any n.
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are column-major. Element (i, j) of A is A[i + j * lda].
+ *   - Sizes and leading dimensions are int64_t; a leading dimension must be
+ *     >= max(1, rows).
+ *   - Pointers named d* or documented as "device" point to device memory
+ *     (hipMalloc'd or torch CUDA/HIP tensors); the caller owns all memory.
+ *     The library never frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream). Device
+ *     work is enqueued asynchronously on it; the entry point returns after
+ *     enqueueing unless documented otherwise.
+ *   - Return value: 0 on success; -i if argument i (1-based) is invalid (the
+ *     check is synchronous and nothing is enqueued); RBT_ERR_HIP if a HIP
+ *     runtime call failed; RBT_ERR_WORKSPACE if the workspace is too small;
+ *     RBT_ERR_UNSUPPORTED for a configuration this build does not implement.
+ *   - Packed coefficients: U and V are n x depth FP64 arrays (ld = n) whose
+ *     column k is the diagonal of R_{k+1} (Sec. 3, packed storage of Alg. 1).
+ *     Layer 1 is the single full-size butterfly of Eq. 3.
+ *   - Butterfly structure: non-tiled reference size m = 2^d ceil(n/2^d)
+ *     (Sec. 3, after Alg. 1) and global half-sizes h_l = m / 2^l in layer l.
+ *     In layer l, index i pairs with i + h_l (top half) or i - h_l (bottom
+ *     half) when that index is < n; otherwise it is unpaired and only scaled
+ *     (Eq. 2: factor 1, not 1/sqrt 2).
+ *   - Coefficients are exp(r/20), r uniform on [-1, 1) (Sec. 6 setup), drawn
+ *     from a counter-based SplitMix64 stream (Steele, Lea, Flood 2014):
+ *     draw(seed, c) = SplitMix64 output number c from state `seed`,
+ *     c = 128 i + 64 side + (layer - 1), side 0 = U, 1 = V;
+ *     r = 2 (draw >> 11) 2^-53 - 1.
+ */
+#ifndef RBT_H
+#define RBT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RBT_ERR_HIP (-100)
+#define RBT_ERR_WORKSPACE (-101)
+#define RBT_ERR_UNSUPPORTED (-102)
+
+/* Largest supported depth. */
+#define RBT_MAX_DEPTH 16
+
+/* Precision of the factorization. */
+#define RBT_FP64 0
+#define RBT_FP32 1
+#define RBT_BF16 2
+
+/* Direction of a one-sided butterfly application. */
+#define RBT_OP_T 0 /* B <- C^T B : forward side (b~ = U^T b, Eq. 1) */
+#define RBT_OP_N 1 /* B <- C B   : undo side (x = V x~, Eq. 1)       */
+
+/* Library ABI version (major * 10000 + minor * 100 + patch). */
+int rbt_version(void);
+
+/* Host only. Butterfly structure, for inspection and tests.
+ * partner: host array of n * depth int64; on return partner[(l-1) * n + i]
+ * is the index paired with i in layer l, or -1 if i is unpaired there
+ * (Sec. 3, Eq. 2-4, Alg. 1 loop nest). n >= 0, 0 <= depth <= RBT_MAX_DEPTH. */
+int rbt_structure(int64_t n, int depth, int64_t *partner);
+
+/* Host only. Packed coefficients U, V (host arrays of n * depth doubles each,
+ * column-major, ld = n) for (n, depth, seed), per the generator above.
+ * Index i's coefficient in layer l depends only on (seed, side, l, i). */
+int rbt_generate(int64_t n, int depth, uint64_t seed, double *U, double *V);
+
+/* Device. Same coefficients written to device arrays dU, dV (n * depth
+ * doubles each); exp is the device library's, within 2 ulp of the host's. */
+int rbt_generate_device(int64_t n, int depth, uint64_t seed, double *dU, double *dV,
+                        void *stream);
+
+/* Device. Two-sided transform Out = U^T A V (Eq. 1), all depth layers in
+ * one pass over HBM for depth <= 3 (the single-pass fusion suggested at the
+ * end of Sec. 3), ceil(depth / 3) passes otherwise.
+ * A: n x n FP64 (lda); Out: n x n (ldo) of type out_prec (RBT_FP64 or
+ * RBT_FP32). Out may equal A (in place) only when out_prec == RBT_FP64 and
+ * ldo == lda. dU, dV: packed device coefficients. */
+int rbt_transform2(int64_t n, const double *A, int64_t lda, void *Out, int64_t ldo, int out_prec,
+                   const double *dU, const double *dV, int depth, void *stream);
+
+/* Device. One-sided transform of an n x nrhs FP64 block B (ldb), in place:
+ * op = RBT_OP_T: B <- C^T B (layers d..1: mix, then scale);
+ * op = RBT_OP_N: B <- C B   (layers 1..d: scale, then mix).
+ * dC: packed device coefficients (U or V). */
+int rbt_transform_vec(int64_t n, int64_t nrhs, double *B, int64_t ldb, const double *dC, int depth,
+                      int op, void *stream);
+
+/* Workspace (bytes) needed by rbt_genp / rbt_getrs / rbt_solve_ex /
+ * rbt_solve_refine / rbt_solve_backward for these sizes and precision. */
+size_t rbt_workspace_size(int64_t n, int64_t nrhs, int depth, int precision);
+
+/* Device. GENP of the n x n FP64 matrix A (lda) in place: unit-lower L
+ * strictly below the diagonal, U on and above (Sec. 1, step 2; no pivoting,
+ * no perturbation). info_dev (device int32, nullable) receives 0 or k > 0
+ * when U(k,k) is exactly zero (1-based, first such k); elimination goes on
+ * with IEEE Inf/NaN. work: device workspace of at least
+ * rbt_workspace_size(n, 0, 0, RBT_FP64) bytes, 256-byte aligned; on return
+ * it holds the inverted diagonal blocks used by rbt_getrs, so pass the same
+ * workspace, untouched, to rbt_getrs. */
+int rbt_genp(int64_t n, double *A, int64_t lda, int32_t *info_dev, void *work, size_t work_bytes,
+             void *stream);
+
+/* Device. Solve with the factors of rbt_genp (same `work`, untouched):
+ * trans = 0: B <- (L U)^-1 B; trans = 1: B <- (L U)^-T B.
+ * B: n x nrhs FP64 (ldb), in place. */
+int rbt_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu, double *B, int64_t ldb,
+              int trans, void *work, size_t work_bytes, void *stream);
+
+/* Device. The whole method (Eq. 1): A (n x n, lda) is overwritten by the
+ * L\U factors of A~ = U^T A V, B (n x nrhs, ldb) by X = A^-1 B. Coefficients
+ * are generated on the device from (depth, seed). info_dev: as rbt_genp.
+ * work: >= rbt_workspace_size(n, nrhs, depth, RBT_FP64) bytes; on return
+ * it holds U, V and the factor data needed by rbt_solve_backward. */
+int rbt_solve_ex(int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_t ldb, int depth,
+                 uint64_t seed, int32_t *info_dev, void *work, size_t work_bytes, void *stream);
+
+/* Device. As rbt_solve_ex, but the library allocates its workspace with
+ * hipMallocAsync/hipFreeAsync on `stream`. */
+int rbt_solve(int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_t ldb, int depth,
+              uint64_t seed, void *stream);
+
+/* Device. The method with stationary iterative refinement in FP64
+ * (Sec. 5): A (n x n, lda) is read only and kept for the residuals; LU
+ * (n x n, ldlu) receives the factors of A~; X (n x nrhs, ldx) receives the
+ * solution of A X = B (B: n x nrhs, ldb, read only). Refinement steps
+ * X += V (LU)^-1 U^T (B - A X) run until the backward error of Eq. 7
+ * (infinity norms, maximum over columns) is <= tol or max_iter steps are
+ * done. iters_dev (device int32) and berr_dev (device double) receive the
+ * step count and the final backward error (both nullable). This entry point
+ * synchronizes `stream` once per refinement step to test convergence. */
+int rbt_solve_refine(int64_t n, int64_t nrhs, const double *A, int64_t lda, double *LU,
+                     int64_t ldlu, const double *B, int64_t ldb, double *X, int64_t ldx, int depth,
+                     uint64_t seed, double tol, int max_iter, int32_t *iters_dev, double *berr_dev,
+                     int32_t *info_dev, void *work, size_t work_bytes, void *stream);
+
+/* Device. Backward error of Eq. 7 for n x nrhs X against A (n x n) and B:
+ * max over columns of ||B - A X||_inf / (||A||_inf ||X||_inf + ||B||_inf),
+ * written to berr_dev (device double). work: >= rbt_workspace_size(n, nrhs,
+ * 0, RBT_FP64) bytes. */
+int rbt_backward_error(int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *X,
+                       int64_t ldx, const double *B, int64_t ldb, double *berr_dev, void *work,
+                       size_t work_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBT_H */

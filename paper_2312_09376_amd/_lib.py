@@ -1,0 +1,69 @@
+"""ctypes loader for librbt.so: the C ABI of include/rbt.h, nothing else.
+
+The library is loaded from this package directory. There is no fallback:
+if it is missing, load() raises.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbt.so")
+
+RBT_ERR_HIP = -100
+RBT_ERR_WORKSPACE = -101
+RBT_ERR_UNSUPPORTED = -102
+RBT_MAX_DEPTH = 16
+RBT_FP64, RBT_FP32, RBT_BF16 = 0, 1, 2
+RBT_OP_T, RBT_OP_N = 0, 1
+
+i64, i32, u64, dbl, sz = ctypes.c_int64, ctypes.c_int, ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t
+vp = ctypes.c_void_p
+
+# name -> (restype, argtypes); keep in the order of include/rbt.h
+SIGNATURES = {
+    "rbt_version": (i32, []),
+    "rbt_structure": (i32, [i64, i32, vp]),
+    "rbt_generate": (i32, [i64, i32, u64, vp, vp]),
+    "rbt_generate_device": (i32, [i64, i32, u64, vp, vp, vp]),
+    "rbt_transform2": (i32, [i64, vp, i64, vp, i64, i32, vp, vp, i32, vp]),
+    "rbt_transform_vec": (i32, [i64, i64, vp, i64, vp, i32, i32, vp]),
+    "rbt_workspace_size": (sz, [i64, i64, i32, i32]),
+    "rbt_genp": (i32, [i64, vp, i64, vp, vp, sz, vp]),
+    "rbt_getrs": (i32, [i64, i64, vp, i64, vp, i64, i32, vp, sz, vp]),
+    "rbt_solve_ex": (i32, [i64, i64, vp, i64, vp, i64, i32, u64, vp, vp, sz, vp]),
+    "rbt_solve": (i32, [i64, i64, vp, i64, vp, i64, i32, u64, vp]),
+    "rbt_solve_refine": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, u64, dbl, i32,
+                               vp, vp, vp, vp, sz, vp]),
+    "rbt_backward_error": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, vp, sz, vp]),
+}
+
+_lib = None
+
+
+class RBTError(RuntimeError):
+    pass
+
+
+def load(path=None):
+    """Load librbt.so and declare every exported symbol's signature."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RBTError(f"librbt.so not built at {p}: run `python -m paper_2312_09376_amd.build`")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def check(rc, name):
+    if rc != 0:
+        what = {RBT_ERR_HIP: "HIP runtime error", RBT_ERR_WORKSPACE: "workspace too small",
+                RBT_ERR_UNSUPPORTED: "unsupported configuration"}.get(rc, f"invalid argument {-rc}")
+        raise RBTError(f"{name} failed ({rc}): {what}")

@@ -1,0 +1,343 @@
+// Butterfly kernels for gfx950: coefficient draw, the fused two-sided
+// transform A~ = U^T A V (Eq. 1, Eq. 3) and the one-sided transforms
+// b~ = U^T b and x = V x~.
+//
+// Index algebra (Sec. 3, Alg. 1 with non-tiled m = 2^d ceil(n/2^d)): with
+// q = m / 2^d write i = r + t q. Layer l has half-size h_l = 2^(d-l) q, so
+// its butterflies pair i with the index whose t differs in bit (d-l), when
+// that index is < n (else i is unpaired: Eq. 2 keeps it, factor 1). Layers
+// lo..hi therefore act on independent groups of 2^(hi-lo+1) indices; the
+// two-sided transform acts on independent 2^P x 2^P blocks of A. Each lane
+// owns one block: it reads the block once, applies every layer of the pass
+// in registers and writes it back, so a pass moves each element of A
+// through HBM exactly once (the fusion noted at the end of Sec. 3). With
+// depth <= 3 one pass does the whole transform.
+//
+// Lanes of a wavefront own consecutive r, so every load and store of the
+// block is a coalesced run along a column (column-major A). No LDS staging
+// is needed: the block members of one lane are q rows apart, and the
+// neighbouring lanes fill in the rows between them.
+//
+// Per layer and side: mix pairs (a, b) -> (a + b, a - b), then scale by the
+// coefficient of the output index times 1/sqrt(2) when the index is paired
+// (the normalisation folded into the diagonal, as Sec. 3 notes for the
+// 4dn^2 flop count).
+#include <cmath>
+
+#include "internal.h"
+
+namespace rbt {
+
+namespace {
+
+constexpr double kInvSqrt2 = 0.70710678118654752440;
+
+__device__ __forceinline__ uint64_t splitmix_at(uint64_t seed, uint64_t c) {
+  uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(256) k_generate(int64_t n, int d, uint64_t seed,
+                                                  double *__restrict__ U,
+                                                  double *__restrict__ V) {
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t total = 2 * n * d;
+  if (idx >= total) return;
+  const int side = idx >= n * d ? 1 : 0;
+  const int64_t rem = idx - side * n * d;
+  const int layer = int(rem / n) + 1;
+  const int64_t i = rem % n;
+  const uint64_t c = 128ull * uint64_t(i) + 64ull * uint64_t(side) + uint64_t(layer - 1);
+  const double u = double(splitmix_at(seed, c) >> 11) * 0x1.0p-53;
+  const double r = 2.0 * u - 1.0;
+  const double v = exp(r / 20.0);
+  (side ? V : U)[rem] = v;
+}
+
+// Geometry of one pass over layers lo..hi (P = hi - lo + 1 <= 3).
+struct Pass {
+  int64_t n, q;
+  int d, lo, hi;
+  int64_t stride;   // 2^(d-hi) q : partner distance of layer hi
+  int64_t ngroups;  // m / 2^P
+};
+
+__device__ __forceinline__ int64_t group_base(const Pass &ps, int64_t g) {
+  const int64_t r = g % ps.q;
+  const int64_t rest = g / ps.q;
+  const int lowbits = ps.d - ps.hi;
+  const int64_t tl = rest & ((int64_t(1) << lowbits) - 1);
+  const int64_t th = rest >> lowbits;
+  return r + ps.q * (tl + (th << (ps.d - ps.lo + 1)));
+}
+
+template <typename T>
+__device__ __forceinline__ T convert_out(double x);
+template <>
+__device__ __forceinline__ double convert_out<double>(double x) { return x; }
+template <>
+__device__ __forceinline__ float convert_out<float>(double x) { return float(x); }
+
+// Two-sided pass. Thread (gx, gy) owns row group gx and column group gy.
+template <int P, typename TO>
+__global__ void __launch_bounds__(256) k_transform2(const double *__restrict__ A, int64_t lda,
+                                                    TO *__restrict__ Out, int64_t ldo,
+                                                    const double *__restrict__ U,
+                                                    const double *__restrict__ V, Pass ps) {
+  constexpr int G = 1 << P;
+  const int64_t gr = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (gr >= ps.ngroups) return;
+  const int64_t rb = group_base(ps, gr);
+  if (rb >= ps.n) return;
+  int64_t ri[G];
+  bool rv[G];
+#pragma unroll
+  for (int p = 0; p < G; ++p) {
+    ri[p] = rb + p * ps.stride;
+    rv[p] = ri[p] < ps.n;
+  }
+  for (int64_t gc = blockIdx.y; gc < ps.ngroups; gc += gridDim.y) {
+    const int64_t cb = group_base(ps, gc);
+    if (cb >= ps.n) continue;
+    int64_t ci[G];
+    bool cv[G];
+#pragma unroll
+    for (int p = 0; p < G; ++p) {
+      ci[p] = cb + p * ps.stride;
+      cv[p] = ci[p] < ps.n;
+    }
+    double x[G][G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        x[r][c] = (rv[r] && cv[c]) ? A[ri[r] + ci[c] * lda] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int bit = 0; bit < P; ++bit) {
+      // layer l = hi - bit pairs block members p and p ^ (1 << bit)
+      const int l = ps.hi - bit;
+      const int64_t off = int64_t(l - 1) * ps.n;
+      double fr[G], fc[G];
+#pragma unroll
+      for (int p = 0; p < G; ++p) {
+        const int p2 = p ^ (1 << bit);
+        const double sr = (rv[p] && rv[p2]) ? kInvSqrt2 : 1.0;
+        const double sc = (cv[p] && cv[p2]) ? kInvSqrt2 : 1.0;
+        fr[p] = rv[p] ? U[off + ri[p]] * sr : 0.0;
+        fc[p] = cv[p] ? V[off + ci[p]] * sc : 0.0;
+      }
+      // rows
+#pragma unroll
+      for (int p = 0; p < G; ++p) {
+        if (p & (1 << bit)) continue;
+        const int p2 = p | (1 << bit);
+        if (!rv[p2]) continue;
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+          const double a = x[p][c], b = x[p2][c];
+          x[p][c] = a + b;
+          x[p2][c] = a - b;
+        }
+      }
+      // columns
+#pragma unroll
+      for (int p = 0; p < G; ++p) {
+        if (p & (1 << bit)) continue;
+        const int p2 = p | (1 << bit);
+        if (!cv[p2]) continue;
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+          const double a = x[r][p], b = x[r][p2];
+          x[r][p] = a + b;
+          x[r][p2] = a - b;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < G; ++r)
+#pragma unroll
+        for (int c = 0; c < G; ++c) x[r][c] *= fr[r] * fc[c];
+    }
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        if (rv[r] && cv[c]) Out[ri[r] + ci[c] * ldo] = convert_out<TO>(x[r][c]);
+      }
+    }
+  }
+}
+
+// One-sided pass on an n x nrhs block. op T: layers hi..lo, mix then scale;
+// op N: layers lo..hi, scale then mix.
+template <int P, int OP>
+__global__ void __launch_bounds__(256) k_transform_vec(double *__restrict__ B, int64_t ldb,
+                                                       int64_t nrhs,
+                                                       const double *__restrict__ C, Pass ps) {
+  constexpr int G = 1 << P;
+  const int64_t gr = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (gr >= ps.ngroups) return;
+  const int64_t rb = group_base(ps, gr);
+  if (rb >= ps.n) return;
+  int64_t ri[G];
+  bool rv[G];
+#pragma unroll
+  for (int p = 0; p < G; ++p) {
+    ri[p] = rb + p * ps.stride;
+    rv[p] = ri[p] < ps.n;
+  }
+  for (int64_t j = blockIdx.y; j < nrhs; j += gridDim.y) {
+    double x[G];
+#pragma unroll
+    for (int p = 0; p < G; ++p) x[p] = rv[p] ? B[ri[p] + j * ldb] : 0.0;
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+      const int bit = (OP == RBT_OP_T) ? s : P - 1 - s;
+      const int l = ps.hi - bit;
+      const int64_t off = int64_t(l - 1) * ps.n;
+      double f[G];
+#pragma unroll
+      for (int p = 0; p < G; ++p) {
+        const int p2 = p ^ (1 << bit);
+        f[p] = rv[p] ? C[off + ri[p]] * ((rv[p2]) ? kInvSqrt2 : 1.0) : 0.0;
+      }
+      if (OP == RBT_OP_N) {
+        // scale by the coefficient of the input index (R_l before O_l);
+        // the 1/sqrt(2) of a pair is common to both members, so it can be
+        // applied before the mix as well
+#pragma unroll
+        for (int p = 0; p < G; ++p) x[p] *= f[p];
+      }
+#pragma unroll
+      for (int p = 0; p < G; ++p) {
+        if (p & (1 << bit)) continue;
+        const int p2 = p | (1 << bit);
+        if (!rv[p2]) continue;
+        const double a = x[p], b = x[p2];
+        x[p] = a + b;
+        x[p2] = a - b;
+      }
+      if (OP == RBT_OP_T) {
+#pragma unroll
+        for (int p = 0; p < G; ++p) x[p] *= f[p];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < G; ++p)
+      if (rv[p]) B[ri[p] + j * ldb] = x[p];
+  }
+}
+
+Pass make_pass(const Geometry &g, int lo, int hi) {
+  Pass ps;
+  ps.n = g.n;
+  ps.q = g.q;
+  ps.d = g.d;
+  ps.lo = lo;
+  ps.hi = hi;
+  ps.stride = g.q << (g.d - hi);
+  ps.ngroups = g.m >> (hi - lo + 1);
+  return ps;
+}
+
+template <typename TO>
+hipError_t launch_pass2(const Pass &ps, const double *A, int64_t lda, TO *out, int64_t ldo,
+                        const double *U, const double *V, hipStream_t s) {
+  const int P = ps.hi - ps.lo + 1;
+  const int64_t gy = ps.ngroups < 65535 ? ps.ngroups : 65535;
+  dim3 grid(unsigned((ps.ngroups + 255) / 256), unsigned(gy));
+  switch (P) {
+    case 0: hipLaunchKernelGGL((k_transform2<0, TO>), grid, dim3(256), 0, s, A, lda, out, ldo, U, V, ps); break;
+    case 1: hipLaunchKernelGGL((k_transform2<1, TO>), grid, dim3(256), 0, s, A, lda, out, ldo, U, V, ps); break;
+    case 2: hipLaunchKernelGGL((k_transform2<2, TO>), grid, dim3(256), 0, s, A, lda, out, ldo, U, V, ps); break;
+    default: hipLaunchKernelGGL((k_transform2<3, TO>), grid, dim3(256), 0, s, A, lda, out, ldo, U, V, ps); break;
+  }
+  return hipGetLastError();
+}
+
+template <int OP>
+hipError_t launch_pass_vec(const Pass &ps, double *B, int64_t ldb, int64_t nrhs, const double *C,
+                           hipStream_t s) {
+  const int P = ps.hi - ps.lo + 1;
+  dim3 grid(unsigned((ps.ngroups + 255) / 256), unsigned(nrhs < 65535 ? nrhs : 65535));
+  switch (P) {
+    case 1: hipLaunchKernelGGL((k_transform_vec<1, OP>), grid, dim3(256), 0, s, B, ldb, nrhs, C, ps); break;
+    case 2: hipLaunchKernelGGL((k_transform_vec<2, OP>), grid, dim3(256), 0, s, B, ldb, nrhs, C, ps); break;
+    default: hipLaunchKernelGGL((k_transform_vec<3, OP>), grid, dim3(256), 0, s, B, ldb, nrhs, C, ps); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_generate(int64_t n, int d, uint64_t seed, double *U, double *V, hipStream_t s) {
+  const int64_t total = 2 * n * d;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_generate, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, n, d, seed,
+                     U, V);
+  return hipGetLastError();
+}
+
+// Layers are processed in passes of at most three, from layer d down to 1
+// (the order of U^T A V); rows and columns of a pass commute. Depth 0 is the
+// identity (a copy or conversion when out of place).
+hipError_t launch_transform2(const Geometry &g, const double *A, int64_t lda, void *out,
+                             int64_t ldo, int out_prec, const double *U, const double *V,
+                             hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  if (g.d == 0) {
+    if (out_prec == RBT_FP64 && (const void *)A == out) return hipSuccess;
+    Pass ps;
+    ps.n = g.n; ps.q = g.n; ps.d = 0; ps.lo = 1; ps.hi = 0; ps.stride = g.n; ps.ngroups = g.n;
+    if (out_prec == RBT_FP32) return launch_pass2<float>(ps, A, lda, (float *)out, ldo, U, V, s);
+    return launch_pass2<double>(ps, A, lda, (double *)out, ldo, U, V, s);
+  }
+  const double *src = A;
+  int64_t lds = lda;
+  int hi = g.d;
+  while (hi >= 1) {
+    const int lo = hi - 2 >= 1 ? hi - 2 : 1;
+    const Pass ps = make_pass(g, lo, hi);
+    hipError_t e;
+    if (lo == 1 && out_prec == RBT_FP32) {
+      e = launch_pass2<float>(ps, src, lds, (float *)out, ldo, U, V, s);
+    } else {
+      // passes before the last run on the FP64 output (the API layer only
+      // allows depth > 3 with an FP64 output)
+      e = launch_pass2<double>(ps, src, lds, (double *)out, ldo, U, V, s);
+      src = (const double *)out;
+      lds = ldo;
+    }
+    if (e != hipSuccess) return e;
+    hi = lo - 1;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_transform_vec(const Geometry &g, int64_t nrhs, double *B, int64_t ldb,
+                                const double *C, int op, hipStream_t s) {
+  if (g.n == 0 || nrhs == 0 || g.d == 0) return hipSuccess;
+  if (op == RBT_OP_T) {
+    int hi = g.d;
+    while (hi >= 1) {
+      const int lo = hi - 2 >= 1 ? hi - 2 : 1;
+      hipError_t e = launch_pass_vec<RBT_OP_T>(make_pass(g, lo, hi), B, ldb, nrhs, C, s);
+      if (e != hipSuccess) return e;
+      hi = lo - 1;
+    }
+  } else {
+    int lo = 1;
+    while (lo <= g.d) {
+      const int hi = lo + 2 <= g.d ? lo + 2 : g.d;
+      hipError_t e = launch_pass_vec<RBT_OP_N>(make_pass(g, lo, hi), B, ldb, nrhs, C, s);
+      if (e != hipSuccess) return e;
+      lo = hi + 1;
+    }
+  }
+  return hipSuccess;
+}
+
+}  // namespace rbt

@@ -1,0 +1,236 @@
+// FP64 matrix-core GEMM for gfx950: C (M x N) = A B or C -= A B, column-major.
+//
+// Used for the trailing update of the blocked elimination (A22 -= L21 U12,
+// K = block size) and, with a triangular operand taken from a packed block
+// inverse, for the block triangular solves (L21 = A21 U11^-1,
+// U12 = L11^-1 A12, and the forward/backward solves).
+//
+// Tiling: 256 threads = 4 wavefronts in a 2 x 2 grid, block tile 128 x 128,
+// wavefront tile 64 x 64 = 4 x 4 MFMA tiles of v_mfma_f64_16x16x4_f64,
+// K staged through LDS in slices of 16 with a register-prefetched double
+// buffer (one barrier per slice).
+//
+// Operand order: each MFMA computes a 16 x 16 tile of C^T (first operand a
+// B^T fragment, second an A^T fragment). The accumulator layout of the
+// instruction (lane l holds rows 4 (l/16) + v, column l % 16 of its output)
+// then gives every group of 16 lanes 16 consecutive rows of one column of C,
+// so epilogue loads and stores are 128-byte contiguous runs.
+//
+// In place: when C aliases A (or B) the caller guarantees that a block tile
+// reads only the rows (columns) it writes, i.e. N <= 128 (M <= 128); all
+// reads of the K loop complete before the epilogue writes.
+//
+// Block ids are remapped so that consecutive tiles land on the same XCD
+// (gfx950 dispatches workgroups round-robin over its 8 XCDs), and tiles are
+// ordered down a column of C first, so one XCD's L2 keeps reusing the same
+// B columns.
+#include "internal.h"
+
+namespace rbt {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int PADA = 4;  // As row stride BM + 4 doubles
+constexpr int PADB = 1;  // Bs row stride BK + 1 doubles (odd: conflict-free column reads)
+
+// Effective A(m, k) for the operand modes.
+template <OpA OA>
+__device__ __forceinline__ double load_a(const double *A, int64_t lda, int64_t m, int64_t k,
+                                         int64_t M, int64_t K) {
+  if (m >= M || k >= K) return 0.0;
+  if constexpr (OA == OpA::General) {
+    return A[m + k * lda];
+  } else if constexpr (OA == OpA::GeneralT) {
+    return A[k + m * lda];
+  } else if constexpr (OA == OpA::UnitLower) {
+    return m > k ? A[m + k * lda] : (m == k ? 1.0 : 0.0);
+  } else if constexpr (OA == OpA::Upper) {
+    return m <= k ? A[m + k * lda] : 0.0;
+  } else if constexpr (OA == OpA::UnitLowerT) {
+    return k > m ? A[k + m * lda] : (m == k ? 1.0 : 0.0);
+  } else {  // UpperT
+    return k <= m ? A[k + m * lda] : 0.0;
+  }
+}
+
+template <OpB OB>
+__device__ __forceinline__ double load_b(const double *B, int64_t ldb, int64_t k, int64_t n,
+                                         int64_t K, int64_t N) {
+  if (k >= K || n >= N) return 0.0;
+  if constexpr (OB == OpB::General) {
+    return B[k + n * ldb];
+  } else {  // Upper
+    return k <= n ? B[k + n * ldb] : 0.0;
+  }
+}
+
+// A storage is contiguous along m for General/UnitLower/Upper, along k for
+// the transposed modes; pick the load pattern that coalesces.
+template <OpA OA>
+constexpr bool a_m_contiguous() {
+  return OA == OpA::General || OA == OpA::UnitLower || OA == OpA::Upper;
+}
+
+template <OpA OA, OpB OB, Acc AC>
+__global__ void __launch_bounds__(256, 2)
+    k_dgemm(int64_t M, int64_t N, int64_t K, const double *__restrict__ A, int64_t lda,
+            const double *__restrict__ B, int64_t ldb, double *C, int64_t ldc, int tiles_m,
+            int total) {
+  __shared__ double As[2][BK][BM + PADA];
+  __shared__ double Bs[2][BN][BK + PADB];
+
+  // XCD-aware remap, then column-major tile order
+  int pid = blockIdx.x;
+  const int full = (total / 8) * 8;
+  if (pid < full) pid = (pid % 8) * (total / 8) + pid / 8;
+  const int tm = pid % tiles_m, tn = pid / tiles_m;
+  const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  // per-thread load coordinates
+  // A, m-contiguous: 4 passes, each: column (tid / 64) + 4p, rows 2 (tid % 64) + {0,1}
+  // A, k-contiguous: row m = tid / 2, k = 8 (tid % 2) + 0..7
+  // B: column n = tid / 2, k = 8 (tid % 2) + 0..7
+  double ra[8], rb[8];
+
+  auto load_stage = [&](int64_t k0) {
+    if constexpr (a_m_contiguous<OA>()) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int64_t k = k0 + (tid >> 6) + 4 * p;
+        const int64_t m = m0 + 2 * (tid & 63);
+        ra[2 * p] = load_a<OA>(A, lda, m, k, M, K);
+        ra[2 * p + 1] = load_a<OA>(A, lda, m + 1, k, M, K);
+      }
+    } else {
+      const int64_t m = m0 + (tid >> 1);
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const int64_t k = k0 + 8 * (tid & 1) + p;
+        ra[p] = load_a<OA>(A, lda, m, k, M, K);
+      }
+    }
+    const int64_t n = n0 + (tid >> 1);
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int64_t k = k0 + 8 * (tid & 1) + p;
+      rb[p] = load_b<OB>(B, ldb, k, n, K, N);
+    }
+  };
+
+  auto store_stage = [&](int s) {
+    if constexpr (a_m_contiguous<OA>()) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int k = (tid >> 6) + 4 * p;
+        const int m = 2 * (tid & 63);
+        As[s][k][m] = ra[2 * p];
+        As[s][k][m + 1] = ra[2 * p + 1];
+      }
+    } else {
+      const int m = tid >> 1;
+#pragma unroll
+      for (int p = 0; p < 8; ++p) As[s][8 * (tid & 1) + p][m] = ra[p];
+    }
+    const int n = tid >> 1;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) Bs[s][n][8 * (tid & 1) + p] = rb[p];
+  };
+
+  load_stage(0);
+  store_stage(0);
+  __syncthreads();
+
+  int cur = 0;
+  for (int64_t k0 = 0; k0 < K; k0 += BK) {
+    const bool has_next = k0 + BK < K;
+    if (has_next) load_stage(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      double af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = As[cur][kk * 4 + lk][wm * 64 + i * 16 + l16];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[j] = Bs[cur][wn * 64 + j * 16 + l16][kk * 4 + lk];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j], af[i], acc[i][j], 0, 0, 0);
+    }
+    if (has_next) store_stage(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  // epilogue: lane holds C[m0 + wm*64 + i*16 + l16][n0 + wn*64 + j*16 + 4*lk + v]
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t row = m0 + wm * 64 + i * 16 + l16;
+    if (row >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t col = n0 + wn * 64 + j * 16 + 4 * lk + v;
+        if (col < N) {
+          double *p = C + row + col * ldc;
+          if constexpr (AC == Acc::Subtract)
+            *p = *p - acc[i][j][v];
+          else
+            *p = acc[i][j][v];
+        }
+      }
+    }
+  }
+}
+
+template <OpA OA, OpB OB, Acc AC>
+hipError_t launch_t(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                    const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t s) {
+  const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
+  const int64_t total = tm * tn;
+  if (total > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_dgemm<OA, OB, AC>), dim3(unsigned(total)), dim3(256), 0, s, M, N, K, A,
+                     lda, B, ldb, C, ldc, int(tm), int(total));
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, OpA opa,
+                        const double *B, int64_t ldb, OpB opb, double *C, int64_t ldc, Acc acc,
+                        hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (K <= 0) {
+    if (acc == Acc::Subtract) return hipSuccess;
+    return hipErrorInvalidValue;  // C = 0 is never requested by the solver
+  }
+#define RBT_GEMM_CASE(OA_, OB_, AC_)                                              \
+  if (opa == OA_ && opb == OB_ && acc == AC_)                                    \
+    return launch_t<OA_, OB_, AC_>(M, N, K, A, lda, B, ldb, C, ldc, s);
+  RBT_GEMM_CASE(OpA::General, OpB::General, Acc::Subtract)
+  RBT_GEMM_CASE(OpA::GeneralT, OpB::General, Acc::Subtract)
+  RBT_GEMM_CASE(OpA::General, OpB::Upper, Acc::Overwrite)
+  RBT_GEMM_CASE(OpA::UnitLower, OpB::General, Acc::Overwrite)
+  RBT_GEMM_CASE(OpA::Upper, OpB::General, Acc::Overwrite)
+  RBT_GEMM_CASE(OpA::UnitLowerT, OpB::General, Acc::Overwrite)
+  RBT_GEMM_CASE(OpA::UpperT, OpB::General, Acc::Overwrite)
+#undef RBT_GEMM_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace rbt

@@ -1,0 +1,177 @@
+"""Thin PyTorch binding of the C ABI (include/rbt.h).
+
+Argument marshalling only: every step of the method runs in librbt's HIP
+kernels. Tensors are column-major (stride (1, ld)): build one from a
+row-major tensor with `colmajor(t)`. Device work is enqueued on torch's
+current HIP stream; the library's workspace is a torch allocation.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import RBT_FP32, RBT_FP64, RBT_OP_N, RBT_OP_T, check  # noqa: F401
+
+
+def colmajor(t):
+    """Column-major copy (or the tensor itself when it already is one)."""
+    if t.dim() == 1:
+        t = t.reshape(-1, 1)
+    if t.stride(0) == 1 and t.stride(1) >= max(1, t.shape[0]):
+        return t
+    return t.t().contiguous().t()
+
+
+def _ld(t):
+    if t.dim() != 2 or t.stride(0) != 1 or t.stride(1) < max(1, t.shape[0]):
+        raise ValueError("expected a column-major 2-D tensor (stride (1, ld), ld >= rows)")
+    return t.stride(1)
+
+
+def _dev_f64(t, name):
+    if not (t.is_cuda and t.dtype == torch.float64):
+        raise TypeError(f"{name} must be a float64 tensor on a HIP device")
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def lib():
+    return _lib.load()
+
+
+# ------------------------------------------------------------------ host
+
+def structure(n, depth):
+    """(depth, n) int64 array: partner[l-1, i] or -1 (host call)."""
+    out = np.zeros((depth, n), dtype=np.int64)
+    check(lib().rbt_structure(n, depth, out.ctypes.data_as(ctypes.c_void_p)), "rbt_structure")
+    return out
+
+
+def generate(n, depth, seed):
+    """Packed coefficients (n x depth, column-major) computed on the host."""
+    U = np.zeros((depth, n), dtype=np.float64)
+    V = np.zeros((depth, n), dtype=np.float64)
+    check(lib().rbt_generate(n, depth, seed, U.ctypes.data_as(ctypes.c_void_p),
+                             V.ctypes.data_as(ctypes.c_void_p)), "rbt_generate")
+    return U.T, V.T
+
+
+def workspace_size(n, nrhs, depth, precision=RBT_FP64):
+    return int(lib().rbt_workspace_size(n, nrhs, depth, precision))
+
+
+def _workspace(n, nrhs, depth, device, precision=RBT_FP64):
+    nbytes = max(workspace_size(n, nrhs, depth, precision), 256)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------- device
+
+def generate_device(n, depth, seed, device="cuda"):
+    U = torch.empty((depth, n), dtype=torch.float64, device=device)
+    V = torch.empty((depth, n), dtype=torch.float64, device=device)
+    check(lib().rbt_generate_device(n, depth, seed, _p(U), _p(V), _stream(U.device)),
+          "rbt_generate_device")
+    return U.t(), V.t()
+
+
+def transform2(A, U, V, depth, out=None, out_dtype=torch.float64):
+    """Out = U^T A V; in place when out is A."""
+    _dev_f64(A, "A")
+    n = A.shape[0]
+    if out is None:
+        out = torch.empty_strided((n, n), (1, max(1, n)), dtype=out_dtype, device=A.device)
+    prec = RBT_FP64 if out.dtype == torch.float64 else RBT_FP32
+    check(lib().rbt_transform2(n, _p(A), _ld(A), _p(out), _ld(out), prec, _p(U), _p(V), depth,
+                               _stream(A.device)), "rbt_transform2")
+    return out
+
+
+def transform_vec(B, C, depth, op):
+    """In place: B <- C^T B (op=RBT_OP_T) or B <- C B (op=RBT_OP_N)."""
+    _dev_f64(B, "B")
+    check(lib().rbt_transform_vec(B.shape[0], B.shape[1], _p(B), _ld(B), _p(C), depth, op,
+                                  _stream(B.device)), "rbt_transform_vec")
+    return B
+
+
+def genp(A, info=None, work=None):
+    """In-place elimination without pivoting. Returns (A, info, work)."""
+    _dev_f64(A, "A")
+    n = A.shape[0]
+    work = work if work is not None else _workspace(n, 0, 0, A.device)
+    info = info if info is not None else torch.zeros(1, dtype=torch.int32, device=A.device)
+    check(lib().rbt_genp(n, _p(A), _ld(A), _p(info), _p(work), work.numel(), _stream(A.device)),
+          "rbt_genp")
+    return A, info, work
+
+
+def getrs(LU, B, work, trans=0):
+    _dev_f64(B, "B")
+    n = LU.shape[0]
+    check(lib().rbt_getrs(n, B.shape[1], _p(LU), _ld(LU), _p(B), _ld(B), trans, _p(work),
+                          work.numel(), _stream(B.device)), "rbt_getrs")
+    return B
+
+
+def solve_(A, B, depth=2, seed=2023, info=None, work=None):
+    """In place: A <- L\\U of U^T A V, B <- X. Returns (A, B, info, work)."""
+    _dev_f64(A, "A")
+    _dev_f64(B, "B")
+    n, k = A.shape[0], B.shape[1]
+    work = work if work is not None else _workspace(n, k, depth, A.device)
+    info = info if info is not None else torch.zeros(1, dtype=torch.int32, device=A.device)
+    check(lib().rbt_solve_ex(n, k, _p(A), _ld(A), _p(B), _ld(B), depth, seed, _p(info), _p(work),
+                             work.numel(), _stream(A.device)), "rbt_solve_ex")
+    return A, B, info, work
+
+
+def solve(A, B, depth=2, seed=2023):
+    """X = A^-1 B by the RBT method; A and B are left unchanged."""
+    A2 = colmajor(A)
+    A2 = A2.clone() if A2.data_ptr() == A.data_ptr() else A2
+    B2 = colmajor(B)
+    B2 = B2.clone() if B2.data_ptr() == B.data_ptr() else B2
+    _, X, info, _ = solve_(A2, B2, depth, seed)
+    return X, A2, info
+
+
+def solve_refine(A, B, depth=2, seed=2023, tol=None, max_iter=10, LU=None, X=None, work=None):
+    """Out-of-place solve with FP64 refinement. Returns (X, LU, iters, berr, info, work)."""
+    A = colmajor(A)
+    B = colmajor(B)
+    _dev_f64(A, "A")
+    _dev_f64(B, "B")
+    n, k = A.shape[0], B.shape[1]
+    if tol is None:
+        tol = 10.0 * n * 2.0 ** -52
+    dev = A.device
+    LU = LU if LU is not None else torch.empty_strided((n, n), (1, max(1, n)), dtype=torch.float64, device=dev)
+    X = X if X is not None else torch.empty_strided((n, k), (1, max(1, n)), dtype=torch.float64, device=dev)
+    work = work if work is not None else _workspace(n, k, depth, dev)
+    iters = torch.zeros(1, dtype=torch.int32, device=dev)
+    berr = torch.zeros(1, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    check(lib().rbt_solve_refine(n, k, _p(A), _ld(A), _p(LU), _ld(LU), _p(B), _ld(B), _p(X), _ld(X),
+                                 depth, seed, float(tol), int(max_iter), _p(iters), _p(berr),
+                                 _p(info), _p(work), work.numel(), _stream(dev)), "rbt_solve_refine")
+    return X, LU, iters, berr, info, work
+
+
+def backward_error(A, X, B, work=None):
+    """Eq. 7 (infinity norms), maximum over columns, as a device scalar."""
+    A, X, B = colmajor(A), colmajor(X), colmajor(B)
+    n, k = A.shape[0], X.shape[1]
+    work = work if work is not None else _workspace(n, k, 0, A.device)
+    berr = torch.zeros(1, dtype=torch.float64, device=A.device)
+    check(lib().rbt_backward_error(n, k, _p(A), _ld(A), _p(X), _ld(X), _p(B), _ld(B), _p(berr),
+                                   _p(work), work.numel(), _stream(A.device)), "rbt_backward_error")
+    return berr

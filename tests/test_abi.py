@@ -1,0 +1,86 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/rbt.h declares, its host-only entry points match the oracle
+bit-exactly, and argument errors are reported as -i without touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import coeffs, structure
+from paper_2312_09376_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "rbt.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rbt_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, f"{name} missing from the binding's signature table"
+
+
+def test_version(lib):
+    assert lib.rbt_version() >= 100
+
+
+@pytest.mark.parametrize("d", [0, 1, 2, 3, 4, 6])
+def test_structure_bit_exact(lib, d):
+    for n in list(range(0, 70)) + [127, 128, 129, 1000, 1001, 1003, 4099]:
+        out = np.full(max(1, n * d), -7, dtype=np.int64)
+        assert lib.rbt_structure(n, d, out.ctypes.data_as(ctypes.c_void_p)) == 0
+        if n == 0 or d == 0:
+            continue
+        expect = np.array(structure.partners(n, d), dtype=np.int64).reshape(-1)
+        assert np.array_equal(out[: n * d], expect), (n, d)
+
+
+@pytest.mark.parametrize("n,d,seed", [(1, 1, 0), (17, 2, 2023), (1003, 2, 42), (300, 5, 2 ** 64 - 1)])
+def test_generate_bit_exact(lib, n, d, seed):
+    U = np.zeros(n * d)
+    V = np.zeros(n * d)
+    assert lib.rbt_generate(n, d, seed, U.ctypes.data_as(ctypes.c_void_p),
+                            V.ctypes.data_as(ctypes.c_void_p)) == 0
+    Uo, Vo = coeffs.generate(n, d, seed)
+    assert np.array_equal(U.reshape(d, n).T, Uo)
+    assert np.array_equal(V.reshape(d, n).T, Vo)
+
+
+def test_argument_errors(lib):
+    vp = ctypes.c_void_p
+    buf = np.zeros(64, dtype=np.int64)
+    assert lib.rbt_structure(-1, 2, buf.ctypes.data_as(vp)) == -1
+    assert lib.rbt_structure(4, -1, buf.ctypes.data_as(vp)) == -2
+    assert lib.rbt_structure(4, 17, buf.ctypes.data_as(vp)) == -2
+    assert lib.rbt_structure(4, 2, None) == -3
+    assert lib.rbt_generate(-3, 2, 1, None, None) == -1
+    assert lib.rbt_generate(3, 2, 1, None, None) == -4
+    dummy = vp(0x1000)   # never dereferenced: every call below fails validation first
+    assert lib.rbt_solve_ex(-1, 1, dummy, 1, dummy, 1, 2, 0, None, dummy, 1 << 20, None) == -1
+    assert lib.rbt_solve_ex(4, -1, dummy, 4, dummy, 4, 2, 0, None, dummy, 1 << 20, None) == -2
+    assert lib.rbt_solve_ex(4, 1, dummy, 3, dummy, 4, 2, 0, None, dummy, 1 << 20, None) == -4
+    assert lib.rbt_solve_ex(4, 1, dummy, 4, dummy, 3, 2, 0, None, dummy, 1 << 20, None) == -6
+    assert lib.rbt_solve_ex(4, 1, dummy, 4, dummy, 4, 99, 0, None, dummy, 1 << 20, None) == -7
+    assert lib.rbt_solve_ex(4, 1, dummy, 4, dummy, 4, 2, 0, None, dummy, 16, None) == _lib.RBT_ERR_WORKSPACE
+    assert lib.rbt_genp(5, dummy, 4, None, dummy, 1 << 20, None) == -3
+    assert lib.rbt_getrs(5, 1, dummy, 5, dummy, 5, 2, dummy, 1 << 20, None) == -7
+    assert lib.rbt_transform2(5, dummy, 5, dummy, 5, 7, dummy, dummy, 2, None) == -6
+    assert lib.rbt_transform_vec(5, 1, dummy, 5, dummy, 2, 9, None) == -7
+    assert lib.rbt_solve_refine(5, 1, dummy, 5, dummy, 5, dummy, 5, dummy, 5, 2, 0, -1.0, 3,
+                                None, None, None, dummy, 1 << 30, None) == -13
+
+
+def test_workspace_size_monotone(lib):
+    a = lib.rbt_workspace_size(1000, 1, 2, 0)
+    b = lib.rbt_workspace_size(1000, 64, 2, 0)
+    c = lib.rbt_workspace_size(2000, 1, 2, 0)
+    assert 0 < a < b and a < c
+    assert lib.rbt_workspace_size(-1, 1, 2, 0) == 0

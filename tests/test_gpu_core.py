@@ -1,0 +1,209 @@
+"""GPU parity of the FP64 path against the oracle: coefficients, the fused
+two-sided transform, one-sided transforms, GENP, block solves, the full
+method and refinement.  All inputs are seeded; the oracle draws its own
+coefficients and never sees a value computed by the GPU."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import coeffs, solve as osolve, transform as otr
+from paper_2312_09376_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+EPS = 2.0 ** -52
+SIZES = [1, 2, 3, 5, 9, 16, 127, 128, 129, 300, 1000, 1001, 1003]
+
+
+@pytest.fixture(scope="module")
+def rbt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_09376_amd import rbt as r
+    r.lib()
+    return r
+
+
+def dev(a):
+    """Host array -> column-major float64 device tensor (stride (1, rows))."""
+    a = np.asarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a[:, None]
+    return torch.from_numpy(np.ascontiguousarray(a.T)).cuda().t()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def relfro(a, b):
+    den = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
+
+
+def test_device_coefficients_match_host(rbt):
+    for (n, d, seed) in [(1, 1, 0), (1003, 2, 2023), (4099, 3, 7)]:
+        U, V = rbt.generate_device(n, d, seed)
+        Uo, Vo = coeffs.generate(n, d, seed)
+        for G, O in ((host(U), Uo), (host(V), Vo)):
+            ulp = np.abs(G - O) / np.spacing(O)
+            assert ulp.max() <= 2, (n, d, ulp.max())
+
+
+@pytest.mark.parametrize("d", [0, 1, 2, 3, 4, 5])
+def test_transform2_matches_oracle(rbt, d):
+    for n in SIZES:
+        A = workloads.randn_matrix(n, seed=n + 10 * d)
+        Uo, Vo = coeffs.generate(n, d, 2023)
+        expect = otr.two_sided(A, Uo, Vo, d)
+        U, V = rbt.generate_device(n, d, 2023)
+        Ad = dev(A)
+        out = rbt.transform2(Ad, U, V, d)                  # out of place
+        assert relfro(host(out), expect) <= 1e-14, (n, d)
+        assert np.array_equal(host(Ad), A)                 # input untouched
+        rbt.transform2(Ad, U, V, d, out=Ad)                # in place
+        assert relfro(host(Ad), expect) <= 1e-14, (n, d)
+
+
+def test_transform2_fp32_output_and_ld(rbt):
+    n, d = 1001, 2
+    A = workloads.randn_matrix(n, seed=3)
+    Uo, Vo = coeffs.generate(n, d, 5)
+    expect = otr.two_sided(A, Uo, Vo, d)
+    U, V = rbt.generate_device(n, d, 5)
+    big = torch.empty_strided((n + 7, n), (1, n + 7), dtype=torch.float64, device="cuda")
+    big.zero_()
+    big[:n, :].copy_(dev(A))
+    Ad = big[:n, :]
+    out = torch.empty_strided((n, n), (1, n + 3), dtype=torch.float32, device="cuda")
+    rbt.transform2(Ad, U, V, d, out=out)
+    got = host(out).astype(np.float64)
+    assert np.abs(got - expect).max() <= 2 * np.abs(expect).max() * 2.0 ** -24
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5])
+def test_transform_vec_matches_oracle(rbt, d):
+    for n in SIZES:
+        B = workloads.randn(n, 3, seed=n)
+        Uo, Vo = coeffs.generate(n, d, 11)
+        U, V = rbt.generate_device(n, d, 11)
+        Bt = rbt.transform_vec(dev(B), U, d, rbt.RBT_OP_T)
+        assert relfro(host(Bt), otr.apply_transpose_left(B, Uo, d)) <= 1e-14
+        Bn = rbt.transform_vec(dev(B), V, d, rbt.RBT_OP_N)
+        assert relfro(host(Bn), otr.apply_left(B, Vo, d)) <= 1e-14
+
+
+@pytest.mark.parametrize("n", [1, 5, 127, 128, 129, 300, 515])
+def test_genp_matches_oracle(rbt, n):
+    A = workloads.shifted(n, seed=n)
+    LUo, info_o = osolve.genp_unblocked(A)
+    LU, info, work = rbt.genp(dev(A))
+    torch.cuda.synchronize()
+    assert int(info.item()) == info_o == 0
+    L = host(LU)
+    assert np.abs(L - LUo).max() <= 1e-12 * max(1.0, np.abs(LUo).max())
+
+
+def test_genp_randn_reconstruction(rbt):
+    n = 700
+    A = workloads.randn_matrix(n, seed=1)
+    Uo, Vo = coeffs.generate(n, 2, 2023)
+    At = otr.two_sided(A, Uo, Vo, 2)
+    LUo, _ = osolve.genp_unblocked(At)
+    LU, info, _ = rbt.genp(dev(At))
+    L = host(LU)
+    Lm = np.tril(L, -1) + np.eye(n)
+    Um = np.triu(L)
+    res = np.abs(Lm @ Um - At).max() / (np.abs(Lm).max() * np.abs(Um).max())
+    assert res <= 20 * n * EPS
+    growth = np.abs(LUo).max()
+    assert np.abs(L - LUo).max() <= 1e-11 * growth
+
+
+def test_genp_zero_pivot_info(rbt):
+    A = np.eye(200)
+    A[130, 130] = 0.0
+    A[130, 131] = 1.0
+    A[131, 130] = 1.0
+    _, info, _ = rbt.genp(dev(A))
+    assert int(info.item()) == 131
+    _, info_o = osolve.genp_unblocked(A)
+    assert info_o == 131
+
+
+@pytest.mark.parametrize("n,k", [(1, 1), (129, 3), (300, 1), (515, 70)])
+def test_getrs_both_transposes(rbt, n, k):
+    A = workloads.shifted(n, seed=n + 1)
+    B = workloads.randn(n, k, seed=9)
+    LUo, _ = osolve.genp_unblocked(A)
+    LU, info, work = rbt.genp(dev(A))
+    X = rbt.getrs(LU, dev(B), work, trans=0)
+    assert relfro(host(X), osolve.lu_solve(LUo, B)) <= 1e-12
+    Xt = rbt.getrs(LU, dev(B), work, trans=1)
+    expect_t = osolve.backward_unit_lower_transposed(LUo, osolve.forward_upper_transposed(LUo, B))
+    assert relfro(host(Xt), expect_t) <= 1e-12
+
+
+@pytest.mark.parametrize("n,k,d", [(1, 1, 2), (5, 2, 2), (129, 1, 2), (1000, 1, 2), (1001, 1, 2),
+                                   (1003, 4, 2), (777, 3, 3), (300, 2, 1), (257, 1, 5)])
+def test_solve_matches_oracle(rbt, n, k, d):
+    A = workloads.shifted(n, seed=n)
+    B = workloads.randn(n, k, seed=64)
+    Uo, Vo = coeffs.generate(n, d, 2023)
+    Xo, _, info_o = osolve.rbt_solve(A, B, Uo, Vo, d)
+    _, X, info, _ = rbt.solve_(dev(A), dev(B), d, 2023)
+    assert int(info.item()) == info_o == 0
+    assert relfro(host(X), Xo) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [1000, 1001, 1003])
+def test_solve_randn_backward_error(rbt, n):
+    A = workloads.randn_matrix(n)
+    B = workloads.randn(n, 1, seed=64)
+    _, X, info, _ = rbt.solve_(dev(A), dev(B), 2, 2023)
+    be = osolve.backward_error(A, host(X), B)
+    assert be <= 10 * n * EPS, be
+    Uo, Vo = coeffs.generate(n, 2, 2023)
+    Xo, _, _ = osolve.rbt_solve(A, B, Uo, Vo, 2)
+    kappa_bound = np.abs(Xo - np.linalg.solve(A, B)).max() / np.abs(Xo).max()
+    assert np.abs(host(X) - Xo).max() / np.abs(Xo).max() <= max(1e-10, 100 * kappa_bound)
+
+
+def test_hostile_matrix(rbt):
+    n = 1000
+    A = workloads.hostile(n)
+    B = workloads.randn(n, 1, seed=64)
+    _, X0, _, _ = rbt.solve_(dev(A), dev(B), 0, 2023)
+    _, X2, _, _ = rbt.solve_(dev(A), dev(B), 2, 2023)
+    assert osolve.backward_error(A, host(X0), B) > 1e-9
+    assert osolve.backward_error(A, host(X2), B) <= 10 * n * EPS
+
+
+@pytest.mark.parametrize("n,k", [(1003, 1), (640, 5)])
+def test_refine_and_backward_error(rbt, n, k):
+    A = workloads.randn_matrix(n, seed=n)
+    B = workloads.randn(n, k, seed=64)
+    X, LU, iters, berr, info, work = rbt.solve_refine(dev(A), dev(B), 2, 2023, tol=0.0, max_iter=2)
+    torch.cuda.synchronize()
+    assert int(iters.item()) == 2
+    # after two steps the residual is rounding noise: both sides report a
+    # backward error at the unit-roundoff level
+    assert float(berr.item()) <= 4 * EPS
+    assert osolve.backward_error(A, host(X), B) <= 4 * EPS
+    Uo, Vo = coeffs.generate(n, 2, 2023)
+    Xo, LUo, _ = osolve.rbt_solve(A, B, Uo, Vo, 2)
+    Xr, _, _ = osolve.refine(A, B, Xo, LUo, Uo, Vo, 2, tol=0.0, max_iter=2)
+    kappa = np.linalg.cond(A)
+    assert relfro(host(X), Xr) <= 100 * kappa * EPS
+
+
+def test_backward_error_kernel(rbt):
+    n, k = 1001, 3
+    A = workloads.randn_matrix(n, seed=5)
+    B = workloads.randn(n, k, seed=6)
+    X = np.linalg.solve(A, B) + 1e-6 * workloads.randn(n, k, seed=7)
+    be_o = osolve.backward_error(A, X, B)
+    be = rbt.backward_error(dev(A), dev(X), dev(B))
+    assert math.isclose(float(be.item()), be_o, rel_tol=1e-9)
