@@ -99,26 +99,23 @@ int rbt_transform2(int64_t n, const double *A, int64_t lda, void *Out, int64_t l
 int rbt_transform_vec(int64_t n, int64_t nrhs, double *B, int64_t ldb, const double *dC, int depth,
                       int op, void *stream);
 
-/* Workspace (bytes) needed by rbt_genp / rbt_getrs / rbt_solve_ex /
- * rbt_solve_refine / rbt_solve_backward for these sizes and precision. */
+/* Workspace (bytes) needed by rbt_solve_ex / rbt_solve_refine /
+ * rbt_backward_error for these sizes and precision (0 for invalid
+ * arguments). */
 size_t rbt_workspace_size(int64_t n, int64_t nrhs, int depth, int precision);
 
 /* Device. GENP of the n x n FP64 matrix A (lda) in place: unit-lower L
  * strictly below the diagonal, U on and above (Sec. 1, step 2; no pivoting,
- * no perturbation). info_dev (device int32, nullable) receives 0 or k > 0
- * when U(k,k) is exactly zero (1-based, first such k); elimination goes on
- * with IEEE Inf/NaN. work: device workspace of at least
- * rbt_workspace_size(n, 0, 0, RBT_FP64) bytes, 256-byte aligned; on return
- * it holds the inverted diagonal blocks used by rbt_getrs, so pass the same
- * workspace, untouched, to rbt_getrs. */
-int rbt_genp(int64_t n, double *A, int64_t lda, int32_t *info_dev, void *work, size_t work_bytes,
-             void *stream);
+ * no perturbation). Blocked right-looking with 128 x 128 diagonal blocks.
+ * info_dev (device int32, nullable) receives 0 or k > 0 when U(k,k) is
+ * exactly zero (1-based, first such k); the elimination goes on with IEEE
+ * Inf/NaN. */
+int rbt_genp(int64_t n, double *A, int64_t lda, int32_t *info_dev, void *stream);
 
-/* Device. Solve with the factors of rbt_genp (same `work`, untouched):
- * trans = 0: B <- (L U)^-1 B; trans = 1: B <- (L U)^-T B.
- * B: n x nrhs FP64 (ldb), in place. */
+/* Device. Solve with the factors of rbt_genp: trans = 0: B <- (L U)^-1 B;
+ * trans = 1: B <- (L U)^-T B. B: n x nrhs FP64 (ldb), in place. */
 int rbt_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu, double *B, int64_t ldb,
-              int trans, void *work, size_t work_bytes, void *stream);
+              int trans, void *stream);
 
 /* Device. The whole method (Eq. 1): A (n x n, lda) is overwritten by the
  * L\U factors of A~ = U^T A V, B (n x nrhs, ldb) by X = A^-1 B. Coefficients
@@ -154,6 +151,26 @@ int rbt_solve_refine(int64_t n, int64_t nrhs, const double *A, int64_t lda, doub
 int rbt_backward_error(int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *X,
                        int64_t ldx, const double *B, int64_t ldb, double *berr_dev, void *work,
                        size_t work_bytes, void *stream);
+
+/* Stage timing, for measurement. When enabled, the composite entry points
+ * (rbt_solve_ex, rbt_solve_refine, rbt_genp) record a pair of HIP events on
+ * their stream around each stage:
+ *   0 coefficient draw          work = bytes written
+ *   1 two-sided transform       work = algorithmic bytes (read + write of A)
+ *   2 one-sided transforms      work = algorithmic bytes
+ *   3 diagonal-block factor     work = flops (factor + both inverses)
+ *   4 panel block solves        work = flops
+ *   5 trailing update GEMM      work = flops, 2 rem^2 kb per launch
+ *   6 triangular solves         work = flops
+ *   7 residual / norms / Eq. 7  work = bytes of A read
+ * Disabled by default. Not thread safe. */
+#define RBT_STAGE_COUNT 8
+int rbt_timing_enable(int on);
+
+/* Waits for the recorded events and writes, for stages 0..nstages-1, the
+ * summed elapsed milliseconds, the number of timed scopes and the summed
+ * work (any output pointer may be NULL); then resets the counters. */
+int rbt_timing_read(int nstages, double *ms, int64_t *launches, double *work);
 
 #ifdef __cplusplus
 }

@@ -28,14 +28,19 @@ SIGNATURES = {
     "rbt_transform2": (i32, [i64, vp, i64, vp, i64, i32, vp, vp, i32, vp]),
     "rbt_transform_vec": (i32, [i64, i64, vp, i64, vp, i32, i32, vp]),
     "rbt_workspace_size": (sz, [i64, i64, i32, i32]),
-    "rbt_genp": (i32, [i64, vp, i64, vp, vp, sz, vp]),
-    "rbt_getrs": (i32, [i64, i64, vp, i64, vp, i64, i32, vp, sz, vp]),
+    "rbt_genp": (i32, [i64, vp, i64, vp, vp]),
+    "rbt_getrs": (i32, [i64, i64, vp, i64, vp, i64, i32, vp]),
     "rbt_solve_ex": (i32, [i64, i64, vp, i64, vp, i64, i32, u64, vp, vp, sz, vp]),
     "rbt_solve": (i32, [i64, i64, vp, i64, vp, i64, i32, u64, vp]),
     "rbt_solve_refine": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, u64, dbl, i32,
                                vp, vp, vp, vp, sz, vp]),
     "rbt_backward_error": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, vp, sz, vp]),
+    "rbt_timing_enable": (i32, [i32]),
+    "rbt_timing_read": (i32, [i32, vp, vp, vp]),
 }
+RBT_STAGE_COUNT = 8
+STAGES = ["generate", "transform2", "transform_vec", "diag", "panel", "trailing", "solve",
+          "residual"]
 
 _lib = None
 

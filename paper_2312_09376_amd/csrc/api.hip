@@ -2,6 +2,7 @@
 // the launch sequence of the method (Eq. 1 and the three steps under it).
 #include <cstdio>
 #include <cstdlib>
+#include <vector>
 
 #include "internal.h"
 
@@ -13,26 +14,67 @@ void report_hip_error(hipError_t e, const char *what, const char *file, int line
                  what, file, line);
 }
 
+// ---- stage timing ----
+// When enabled, composite entry points bracket each stage with a pair of HIP
+// events on the caller's stream; rbt_timing_read waits for them and returns
+// per-stage totals. Off by default (no events are recorded).
+namespace {
+struct TimingState {
+  bool on = false;
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  double work[kStageCount] = {};
+  int64_t launches[kStageCount] = {};
+};
+TimingState &timing() {
+  static TimingState t;
+  return t;
+}
+}  // namespace
+
+StageScope::StageScope(int stage, hipStream_t s, double work) : stage_(stage), s_(s) {
+  TimingState &t = timing();
+  if (!t.on) return;
+  if (hipEventCreate(&start_) != hipSuccess) {
+    start_ = nullptr;
+    return;
+  }
+  hipEventRecord(start_, s_);
+  t.work[stage] += work;
+  t.launches[stage] += 1;
+}
+
+StageScope::~StageScope() {
+  if (start_ == nullptr) return;
+  hipEvent_t end = nullptr;
+  if (hipEventCreate(&end) != hipSuccess) {
+    hipEventDestroy(start_);
+    return;
+  }
+  hipEventRecord(end, s_);
+  timing().recs.push_back({stage_, start_, end});
+}
+
 namespace {
 
 inline int64_t nblocks(int64_t n) { return (n + kNB - 1) / kNB; }
 
-// Workspace layout. The packed block inverses come first so that rbt_genp,
-// rbt_getrs and the composite entry points agree on where they live.
+// Workspace layout of the composite entry points.
 struct Layout {
-  size_t winv, coef, resid, partial, small, total;
-  size_t o_winv, o_coef, o_resid, o_partial, o_small;
+  size_t coef, resid, partial, small, total;
+  size_t o_coef, o_resid, o_partial, o_small;
 };
 
 Layout layout(int64_t n, int64_t nrhs, int d) {
   Layout L{};
-  L.winv = align256(size_t(nblocks(n)) * kNB * kNB * sizeof(double));
   L.coef = align256(size_t(2) * n * d * sizeof(double));
   L.resid = align256(size_t(n) * nrhs * sizeof(double));
-  L.partial = align256(size_t(rowabs_chunks(n)) * n * sizeof(double));
-  L.small = align256((3 * size_t(nrhs) + 8) * sizeof(double)) + 256;
-  L.o_winv = 0;
-  L.o_coef = L.o_winv + L.winv;
+  L.partial = align256(resid_scratch_doubles(n, nrhs) * sizeof(double));
+  L.small = 512;
+  L.o_coef = 0;
   L.o_resid = L.o_coef + L.coef;
   L.o_partial = L.o_resid + L.resid;
   L.o_small = L.o_partial + L.partial;
@@ -50,81 +92,105 @@ inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 // Blocked right-looking elimination without pivoting (block kNB):
 //   factor A11 (and invert its triangles), L21 = A21 U11^-1,
 //   U12 = L11^-1 A12, A22 -= L21 U12.
-int genp_fp64(int64_t n, double *A, int64_t lda, int32_t *info, double *winv, hipStream_t s) {
+int genp_fp64(int64_t n, double *A, int64_t lda, int32_t *info, hipStream_t s) {
   if (info) RBT_HIP_CHECK(launch_fill_i32(info, 0, s));
   for (int64_t k = 0; k < n; k += kNB) {
     const int kb = int(n - k < kNB ? n - k : kNB);
     double *A11 = A + k + k * lda;
-    double *W = winv + (k / kNB) * kNB * kNB;
-    RBT_HIP_CHECK(launch_diag_lu(kb, A11, lda, W, k, info, s));
+    {
+      StageScope t(kStageDiag, s, 4.0 / 3.0 * double(kb) * kb * kb);
+      RBT_HIP_CHECK(launch_diag_lu(kb, A11, lda, k, info, s));
+    }
     const int64_t rem = n - k - kb;
     if (rem <= 0) continue;
     double *A21 = A + (k + kb) + k * lda;
     double *A12 = A + k + (k + kb) * lda;
     double *A22 = A + (k + kb) + (k + kb) * lda;
-    RBT_HIP_CHECK(launch_dgemm(rem, kb, kb, A21, lda, OpA::General, W, kNB, OpB::Upper, A21, lda,
-                               Acc::Overwrite, s));
-    RBT_HIP_CHECK(launch_dgemm(kb, rem, kb, W, kNB, OpA::UnitLower, A12, lda, OpB::General, A12,
-                               lda, Acc::Overwrite, s));
-    RBT_HIP_CHECK(launch_dgemm(rem, rem, kb, A21, lda, OpA::General, A12, lda, OpB::General, A22,
-                               lda, Acc::Subtract, s));
+    {
+      StageScope t(kStagePanel, s, 2.0 * double(rem) * kb * kb);
+      RBT_HIP_CHECK(launch_trsm_right_upper(kb, rem, A11, lda, A21, lda, s));
+      RBT_HIP_CHECK(launch_trsm_left(TriMode::LN, kb, rem, A11, lda, A12, lda, s));
+    }
+    {
+      StageScope t(kStageTrailing, s, 2.0 * double(rem) * rem * kb);
+      RBT_HIP_CHECK(launch_dgemm(rem, rem, kb, A21, lda, OpA::General, A12, lda, OpB::General,
+                                 A22, lda, Acc::SubtractTrailing, s));
+    }
   }
   return 0;
 }
 
-// B <- (LU)^-1 B (trans = 0) or (LU)^-T B (trans = 1), by block solves with
-// the packed diagonal-block inverses and GEMM updates.
+// B <- (LU)^-1 B (trans = 0) or (LU)^-T B (trans = 1): block solves with the
+// diagonal blocks (k_trsm.hip) and updates of the remaining rows, by the
+// FMA kernel for few right-hand sides and the matrix-core GEMM otherwise.
 int getrs_fp64(int64_t n, int64_t nrhs, const double *LU, int64_t ld, double *B, int64_t ldb,
-               int trans, const double *winv, hipStream_t s) {
+               int trans, hipStream_t s) {
   if (n == 0 || nrhs == 0) return 0;
   const int64_t nb = nblocks(n);
+  const bool skinny = nrhs <= kSkinnyMax;
   auto kb_of = [&](int64_t blk) { return int(n - blk * kNB < kNB ? n - blk * kNB : kNB); };
+  // Y (M x nrhs) -= op(A) (M x kb) X (kb x nrhs)
+  auto update = [&](int64_t M, int kb, const double *Ab, bool tr, const double *X,
+                    double *Y) -> hipError_t {
+    if (M <= 0) return hipSuccess;
+    if (skinny) return launch_skinny_update(M, nrhs, kb, Ab, ld, tr, X, ldb, Y, ldb, s);
+    return launch_dgemm(M, nrhs, kb, Ab, ld, tr ? OpA::GeneralT : OpA::General, X, ldb,
+                        OpB::General, Y, ldb, Acc::Subtract, s);
+  };
   if (trans == 0) {
     for (int64_t blk = 0; blk < nb; ++blk) {  // L Y = B
       const int64_t k = blk * kNB;
       const int kb = kb_of(blk);
-      const double *W = winv + blk * kNB * kNB;
-      RBT_HIP_CHECK(launch_dgemm(kb, nrhs, kb, W, kNB, OpA::UnitLower, B + k, ldb, OpB::General,
-                                 B + k, ldb, Acc::Overwrite, s));
-      const int64_t rem = n - k - kb;
-      if (rem > 0)
-        RBT_HIP_CHECK(launch_dgemm(rem, nrhs, kb, LU + (k + kb) + k * ld, ld, OpA::General, B + k,
-                                   ldb, OpB::General, B + k + kb, ldb, Acc::Subtract, s));
+      const double *T = LU + k + k * ld;
+      RBT_HIP_CHECK(launch_trsm_left(TriMode::LN, kb, nrhs, T, ld, B + k, ldb, s));
+      RBT_HIP_CHECK(update(n - k - kb, kb, LU + (k + kb) + k * ld, false, B + k, B + k + kb));
     }
     for (int64_t blk = nb - 1; blk >= 0; --blk) {  // U X = Y
       const int64_t k = blk * kNB;
       const int kb = kb_of(blk);
-      const double *W = winv + blk * kNB * kNB;
-      RBT_HIP_CHECK(launch_dgemm(kb, nrhs, kb, W, kNB, OpA::Upper, B + k, ldb, OpB::General,
-                                 B + k, ldb, Acc::Overwrite, s));
-      if (k > 0)
-        RBT_HIP_CHECK(launch_dgemm(k, nrhs, kb, LU + k * ld, ld, OpA::General, B + k, ldb,
-                                   OpB::General, B, ldb, Acc::Subtract, s));
+      const double *T = LU + k + k * ld;
+      RBT_HIP_CHECK(launch_trsm_left(TriMode::UN, kb, nrhs, T, ld, B + k, ldb, s));
+      RBT_HIP_CHECK(update(k, kb, LU + k * ld, false, B + k, B));
     }
   } else {
     for (int64_t blk = 0; blk < nb; ++blk) {  // U^T Z = B
       const int64_t k = blk * kNB;
       const int kb = kb_of(blk);
-      const double *W = winv + blk * kNB * kNB;
-      RBT_HIP_CHECK(launch_dgemm(kb, nrhs, kb, W, kNB, OpA::UpperT, B + k, ldb, OpB::General,
-                                 B + k, ldb, Acc::Overwrite, s));
-      const int64_t rem = n - k - kb;
-      if (rem > 0)
-        RBT_HIP_CHECK(launch_dgemm(rem, nrhs, kb, LU + k + (k + kb) * ld, ld, OpA::GeneralT,
-                                   B + k, ldb, OpB::General, B + k + kb, ldb, Acc::Subtract, s));
+      const double *T = LU + k + k * ld;
+      RBT_HIP_CHECK(launch_trsm_left(TriMode::UT, kb, nrhs, T, ld, B + k, ldb, s));
+      RBT_HIP_CHECK(update(n - k - kb, kb, LU + k + (k + kb) * ld, true, B + k, B + k + kb));
     }
     for (int64_t blk = nb - 1; blk >= 0; --blk) {  // L^T W = Z
       const int64_t k = blk * kNB;
       const int kb = kb_of(blk);
-      const double *W = winv + blk * kNB * kNB;
-      RBT_HIP_CHECK(launch_dgemm(kb, nrhs, kb, W, kNB, OpA::UnitLowerT, B + k, ldb, OpB::General,
-                                 B + k, ldb, Acc::Overwrite, s));
-      if (k > 0)
-        RBT_HIP_CHECK(launch_dgemm(k, nrhs, kb, LU + k, ld, OpA::GeneralT, B + k, ldb,
-                                   OpB::General, B, ldb, Acc::Subtract, s));
+      const double *T = LU + k + k * ld;
+      RBT_HIP_CHECK(launch_trsm_left(TriMode::LT, kb, nrhs, T, ld, B + k, ldb, s));
+      RBT_HIP_CHECK(update(k, kb, LU + k, true, B + k, B));
     }
   }
   return 0;
+}
+
+// Stage-timed wrappers of the launches used by the composite entry points.
+hipError_t generate_t(int64_t n, int d, uint64_t seed, double *U, double *V, hipStream_t s) {
+  StageScope t(kStageGenerate, s, 16.0 * double(n) * d);
+  return launch_generate(n, d, seed, U, V, s);
+}
+hipError_t transform2_t(const Geometry &g, const double *A, int64_t lda, void *out, int64_t ldo,
+                        int prec, const double *U, const double *V, hipStream_t s) {
+  const double elt_out = prec == RBT_FP32 ? 4.0 : 8.0;
+  StageScope t(kStageTransform2, s, (8.0 + elt_out) * double(g.n) * g.n);
+  return launch_transform2(g, A, lda, out, ldo, prec, U, V, s);
+}
+hipError_t transform_vec_t(const Geometry &g, int64_t nrhs, double *B, int64_t ldb,
+                           const double *C, int op, hipStream_t s) {
+  StageScope t(kStageTransformVec, s, 16.0 * double(g.n) * nrhs);
+  return launch_transform_vec(g, nrhs, B, ldb, C, op, s);
+}
+int getrs_t(int64_t n, int64_t nrhs, const double *LU, int64_t ld, double *B, int64_t ldb,
+            int trans, hipStream_t s) {
+  StageScope t(kStageSolve, s, 2.0 * double(n) * n * nrhs);
+  return getrs_fp64(n, nrhs, LU, ld, B, ldb, trans, s);
 }
 
 bool bad_depth(int d) { return d < 0 || d > RBT_MAX_DEPTH; }
@@ -181,19 +247,15 @@ extern "C" int rbt_transform_vec(int64_t n, int64_t nrhs, double *B, int64_t ldb
   return 0;
 }
 
-extern "C" int rbt_genp(int64_t n, double *A, int64_t lda, int32_t *info_dev, void *work,
-                        size_t work_bytes, void *stream) {
+extern "C" int rbt_genp(int64_t n, double *A, int64_t lda, int32_t *info_dev, void *stream) {
   if (n < 0) return -1;
   if (n > 0 && A == nullptr) return -2;
   if (lda < (n > 1 ? n : 1)) return -3;
-  const Layout L = layout(n, 0, 0);
-  if (n > 0 && work == nullptr) return -5;
-  if (work_bytes < L.winv) return RBT_ERR_WORKSPACE;
-  return genp_fp64(n, A, lda, info_dev, at<double>(work, L.o_winv), S(stream));
+  return genp_fp64(n, A, lda, info_dev, S(stream));
 }
 
 extern "C" int rbt_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu, double *B,
-                         int64_t ldb, int trans, void *work, size_t work_bytes, void *stream) {
+                         int64_t ldb, int trans, void *stream) {
   if (n < 0) return -1;
   if (nrhs < 0) return -2;
   if (n > 0 && LU == nullptr) return -3;
@@ -201,10 +263,7 @@ extern "C" int rbt_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu
   if (n > 0 && nrhs > 0 && B == nullptr) return -5;
   if (ldb < (n > 1 ? n : 1)) return -6;
   if (trans != 0 && trans != 1) return -7;
-  const Layout L = layout(n, 0, 0);
-  if (n > 0 && work == nullptr) return -8;
-  if (work_bytes < L.winv) return RBT_ERR_WORKSPACE;
-  return getrs_fp64(n, nrhs, LU, ldlu, B, ldb, trans, at<double>(work, L.o_winv), S(stream));
+  return getrs_fp64(n, nrhs, LU, ldlu, B, ldb, trans, S(stream));
 }
 
 extern "C" int rbt_solve_ex(int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_t ldb,
@@ -225,15 +284,14 @@ extern "C" int rbt_solve_ex(int64_t n, int64_t nrhs, double *A, int64_t lda, dou
   const Geometry g = geometry(n, depth);
   double *U = at<double>(work, L.o_coef);
   double *V = U + n * depth;
-  double *winv = at<double>(work, L.o_winv);
-  RBT_HIP_CHECK(launch_generate(n, depth, seed, U, V, s));
-  RBT_HIP_CHECK(launch_transform2(g, A, lda, A, lda, RBT_FP64, U, V, s));
-  RBT_HIP_CHECK(launch_transform_vec(g, nrhs, B, ldb, U, RBT_OP_T, s));
-  int rc = genp_fp64(n, A, lda, info_dev, winv, s);
+  RBT_HIP_CHECK(generate_t(n, depth, seed, U, V, s));
+  RBT_HIP_CHECK(transform2_t(g, A, lda, A, lda, RBT_FP64, U, V, s));
+  RBT_HIP_CHECK(transform_vec_t(g, nrhs, B, ldb, U, RBT_OP_T, s));
+  int rc = genp_fp64(n, A, lda, info_dev, s);
   if (rc) return rc;
-  rc = getrs_fp64(n, nrhs, A, lda, B, ldb, 0, winv, s);
+  rc = getrs_t(n, nrhs, A, lda, B, ldb, 0, s);
   if (rc) return rc;
-  RBT_HIP_CHECK(launch_transform_vec(g, nrhs, B, ldb, V, RBT_OP_N, s));
+  RBT_HIP_CHECK(transform_vec_t(g, nrhs, B, ldb, V, RBT_OP_N, s));
   return 0;
 }
 
@@ -266,17 +324,10 @@ extern "C" int rbt_backward_error(int64_t n, int64_t nrhs, const double *A, int6
   if (work_bytes < L.total) return RBT_ERR_WORKSPACE;
   hipStream_t s = S(stream);
   double *R = at<double>(work, L.o_resid);
-  double *partial = at<double>(work, L.o_partial);
+  double *scratch = at<double>(work, L.o_partial);
   double *small = at<double>(work, L.o_small);
-  if (n == 0 || nrhs == 0) {
-    RBT_HIP_CHECK(hipMemsetAsync(berr_dev, 0, sizeof(double), s));
-    return 0;
-  }
-  RBT_HIP_CHECK(launch_anorm(n, A, lda, partial, small, s));
-  RBT_HIP_CHECK(launch_copy_cols(n, nrhs, B, ldb, R, n, s));
-  RBT_HIP_CHECK(launch_dgemm(n, nrhs, n, A, lda, OpA::General, X, ldx, OpB::General, R, n,
-                             Acc::Subtract, s));
-  RBT_HIP_CHECK(launch_berr(n, nrhs, R, n, X, ldx, B, ldb, small, small + 8, berr_dev, s));
+  RBT_HIP_CHECK(launch_residual_berr(n, nrhs, A, lda, X, ldx, B, ldb, R, n, true, scratch, small,
+                                     berr_dev, s));
   return 0;
 }
 
@@ -305,45 +356,43 @@ extern "C" int rbt_solve_refine(int64_t n, int64_t nrhs, const double *A, int64_
   double *small = at<double>(work, L.o_small);
   double *berr = berr_dev ? berr_dev : small + 1;
   if (n == 0 || nrhs == 0) {
-    RBT_HIP_CHECK(hipMemsetAsync(berr, 0, sizeof(double), s));
-    if (iters_dev) RBT_HIP_CHECK(hipMemsetAsync(iters_dev, 0, sizeof(int32_t), s));
+    RBT_HIP_CHECK(launch_fill_f64(berr, 0.0, s));
+    if (iters_dev) RBT_HIP_CHECK(launch_fill_i32(iters_dev, 0, s));
     return 0;
   }
   const Geometry g = geometry(n, depth);
   double *U = at<double>(work, L.o_coef);
   double *V = U + n * depth;
-  double *winv = at<double>(work, L.o_winv);
   double *R = at<double>(work, L.o_resid);
-  double *partial = at<double>(work, L.o_partial);
+  double *scratch = at<double>(work, L.o_partial);
   double *anorm = small;
-  double *colstat = small + 8;
 
-  RBT_HIP_CHECK(launch_generate(n, depth, seed, U, V, s));
-  RBT_HIP_CHECK(launch_transform2(g, A, lda, LU, ldlu, RBT_FP64, U, V, s));
-  int rc = genp_fp64(n, LU, ldlu, info_dev, winv, s);
+  RBT_HIP_CHECK(generate_t(n, depth, seed, U, V, s));
+  RBT_HIP_CHECK(transform2_t(g, A, lda, LU, ldlu, RBT_FP64, U, V, s));
+  int rc = genp_fp64(n, LU, ldlu, info_dev, s);
   if (rc) return rc;
   RBT_HIP_CHECK(launch_copy_cols(n, nrhs, B, ldb, X, ldx, s));
-  RBT_HIP_CHECK(launch_transform_vec(g, nrhs, X, ldx, U, RBT_OP_T, s));
-  rc = getrs_fp64(n, nrhs, LU, ldlu, X, ldx, 0, winv, s);
+  RBT_HIP_CHECK(transform_vec_t(g, nrhs, X, ldx, U, RBT_OP_T, s));
+  rc = getrs_t(n, nrhs, LU, ldlu, X, ldx, 0, s);
   if (rc) return rc;
-  RBT_HIP_CHECK(launch_transform_vec(g, nrhs, X, ldx, V, RBT_OP_N, s));
-  RBT_HIP_CHECK(launch_anorm(n, A, lda, partial, anorm, s));
+  RBT_HIP_CHECK(transform_vec_t(g, nrhs, X, ldx, V, RBT_OP_N, s));
 
   int it = 0;
   for (;;) {
-    RBT_HIP_CHECK(launch_copy_cols(n, nrhs, B, ldb, R, n, s));
-    RBT_HIP_CHECK(launch_dgemm(n, nrhs, n, A, lda, OpA::General, X, ldx, OpB::General, R, n,
-                               Acc::Subtract, s));
-    RBT_HIP_CHECK(launch_berr(n, nrhs, R, n, X, ldx, B, ldb, anorm, colstat, berr, s));
+    {
+      StageScope t(kStageResidual, s, 8.0 * double(n) * n);
+      RBT_HIP_CHECK(launch_residual_berr(n, nrhs, A, lda, X, ldx, B, ldb, R, n, it == 0, scratch,
+                                         anorm, berr, s));
+    }
     if (it >= max_iter) break;
     double be_host = 0.0;
     RBT_HIP_CHECK(hipMemcpyAsync(&be_host, berr, sizeof(double), hipMemcpyDeviceToHost, s));
     RBT_HIP_CHECK(hipStreamSynchronize(s));
     if (be_host <= tol) break;
-    RBT_HIP_CHECK(launch_transform_vec(g, nrhs, R, n, U, RBT_OP_T, s));
-    rc = getrs_fp64(n, nrhs, LU, ldlu, R, n, 0, winv, s);
+    RBT_HIP_CHECK(transform_vec_t(g, nrhs, R, n, U, RBT_OP_T, s));
+    rc = getrs_t(n, nrhs, LU, ldlu, R, n, 0, s);
     if (rc) return rc;
-    RBT_HIP_CHECK(launch_transform_vec(g, nrhs, R, n, V, RBT_OP_N, s));
+    RBT_HIP_CHECK(transform_vec_t(g, nrhs, R, n, V, RBT_OP_N, s));
     RBT_HIP_CHECK(launch_axpy_cols(n, nrhs, R, n, X, ldx, s));
     ++it;
   }
@@ -352,4 +401,34 @@ extern "C" int rbt_solve_refine(int64_t n, int64_t nrhs, const double *A, int64_
     RBT_HIP_CHECK(hipStreamSynchronize(s));
   }
   return 0;
+}
+
+extern "C" int rbt_timing_enable(int on) {
+  timing().on = (on != 0);
+  return 0;
+}
+
+extern "C" int rbt_timing_read(int nstages, double *ms, int64_t *launches, double *work) {
+  if (nstages < 0) return -1;
+  TimingState &t = timing();
+  double acc[kStageCount] = {};
+  int rc = 0;
+  for (auto &r : t.recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) rc = RBT_ERR_HIP;
+    float e = 0.0f;
+    if (rc == 0 && hipEventElapsedTime(&e, r.a, r.b) == hipSuccess) acc[r.stage] += e;
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  t.recs.clear();
+  for (int i = 0; i < nstages && i < kStageCount; ++i) {
+    if (ms) ms[i] = acc[i];
+    if (launches) launches[i] = t.launches[i];
+    if (work) work[i] = t.work[i];
+  }
+  for (int i = 0; i < kStageCount; ++i) {
+    t.launches[i] = 0;
+    t.work[i] = 0.0;
+  }
+  return rc;
 }

@@ -38,6 +38,26 @@ inline Geometry geometry(int64_t n, int d) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// ---- stage timing (api.hip) ----
+enum Stage {
+  kStageGenerate = 0,  // coefficient draw
+  kStageTransform2,    // two-sided transform; work = bytes moved (algorithmic)
+  kStageTransformVec,  // one-sided transforms; work = bytes moved
+  kStageDiag,          // diagonal-block factor + inverse; work = flops (2/3 kb^3 + 2/3 kb^3)
+  kStagePanel,         // L21 / U12 block solves as GEMMs; work = flops
+  kStageTrailing,      // trailing update A22 -= L21 U12; work = flops 2 rem^2 kb
+  kStageSolve,         // block triangular solves; work = flops
+  kStageResidual,      // residual, norms, backward error; work = bytes of A read
+  kStageCount
+};
+struct StageScope {
+  StageScope(int stage, hipStream_t s, double work);
+  ~StageScope();
+  int stage_;
+  hipStream_t s_;
+  hipEvent_t start_ = nullptr;
+};
+
 // ---- kernel launchers (each defined next to its kernels) ----
 
 // k_butterfly.hip
@@ -63,27 +83,51 @@ enum class OpB {
   General,  // B(k, n) = B[k + n ldb]
   Upper     // upper part of W (U^-1)
 };
-enum class Acc { Overwrite, Subtract };
+// SubtractTrailing computes the same as Subtract; it is a separate kernel
+// instance so profilers can tell the trailing update of the elimination
+// apart from the small updates of the solves.
+enum class Acc { Overwrite, Subtract, SubtractTrailing };
 hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, OpA opa,
                         const double *B, int64_t ldb, OpB opb, double *C, int64_t ldc, Acc acc,
                         hipStream_t s);
 
-// k_getrf.hip : factor the kb x kb diagonal block in place, write the packed
-// inverses to Winv (ld kNB); first exact zero pivot -> *info = gofs + c + 1.
-hipError_t launch_diag_lu(int kb, double *A, int64_t lda, double *Winv, int64_t gofs,
-                          int32_t *info, hipStream_t s);
+// k_getrf.hip : factor the kb x kb diagonal block in place (kb <= kNB);
+// first exact zero pivot -> *info = gofs + c + 1.
+hipError_t launch_diag_lu(int kb, double *A, int64_t lda, int64_t gofs, int32_t *info,
+                          hipStream_t s);
+
+// k_trsm.hip : triangular solves with a factored diagonal block T (kb <= kNB).
+enum class TriMode {
+  LN,  // L X = B   (unit lower)
+  UN,  // U X = B   (upper)
+  UT,  // U^T X = B
+  LT   // L^T X = B (unit upper)
+};
+hipError_t launch_trsm_left(TriMode mode, int kb, int64_t N, const double *T, int64_t ldt,
+                            double *B, int64_t ldb, hipStream_t s);
+// X U = B in place, B: M x kb
+hipError_t launch_trsm_right_upper(int kb, int64_t M, const double *T, int64_t ldt, double *B,
+                                   int64_t ldb, hipStream_t s);
 
 // k_solve.hip
-int64_t rowabs_chunks(int64_t n);
-hipError_t launch_anorm(int64_t n, const double *A, int64_t lda, double *partial, double *out,
-                        hipStream_t s);
-hipError_t launch_berr(int64_t n, int64_t nrhs, const double *R, int64_t ldr, const double *X,
-                       int64_t ldx, const double *B, int64_t ldb, const double *anorm,
-                       double *colstat, double *berr, hipStream_t s);
+constexpr int64_t kSkinnyMax = 16;  // right-hand sides handled by the FMA kernels
+// Y (M x N) -= op(A) (M x K) X (K x N), N <= kSkinnyMax, K <= kNB
+hipError_t launch_skinny_update(int64_t M, int64_t N, int K, const double *A, int64_t lda,
+                                bool trans, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                                hipStream_t s);
+// doubles of scratch needed by launch_residual_berr
+size_t resid_scratch_doubles(int64_t n, int64_t nrhs);
+// R = B - A X; berr = Eq. 7 (max over columns); with_anorm: also ||A||_inf -> *anorm
+// (otherwise *anorm is read)
+hipError_t launch_residual_berr(int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                                const double *X, int64_t ldx, const double *B, int64_t ldb,
+                                double *R, int64_t ldr, bool with_anorm, double *scratch,
+                                double *anorm, double *berr, hipStream_t s);
 hipError_t launch_axpy_cols(int64_t n, int64_t nrhs, const double *D, int64_t ldd, double *X,
                             int64_t ldx, hipStream_t s);
 hipError_t launch_copy_cols(int64_t n, int64_t nrhs, const double *S, int64_t lds, double *D,
                             int64_t ldd, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, hipStream_t s);
 
 }  // namespace rbt

@@ -11,10 +11,11 @@
 // buffer (one barrier per slice).
 //
 // Operand order: each MFMA computes a 16 x 16 tile of C^T (first operand a
-// B^T fragment, second an A^T fragment). The accumulator layout of the
-// instruction (lane l holds rows 4 (l/16) + v, column l % 16 of its output)
-// then gives every group of 16 lanes 16 consecutive rows of one column of C,
-// so epilogue loads and stores are 128-byte contiguous runs.
+// B^T fragment, second an A^T fragment). The accumulator layout of the f64
+// instruction (lane l, element v holds output row l/16 + 4v, column l % 16;
+// checked on the device) then gives every group of 16 lanes 16 consecutive
+// rows of one column of C, so epilogue loads and stores are 128-byte
+// contiguous runs.
 //
 // In place: when C aliases A (or B) the caller guarantees that a block tile
 // reads only the rows (columns) it writes, i.e. N <= 128 (M <= 128); all
@@ -76,8 +77,8 @@ constexpr bool a_m_contiguous() {
 
 template <OpA OA, OpB OB, Acc AC>
 __global__ void __launch_bounds__(256, 2)
-    k_dgemm(int64_t M, int64_t N, int64_t K, const double *__restrict__ A, int64_t lda,
-            const double *__restrict__ B, int64_t ldb, double *C, int64_t ldc, int tiles_m,
+    k_dgemm(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, const double *B,
+            int64_t ldb, double *C, int64_t ldc, int tiles_m,
             int total) {
   __shared__ double As[2][BK][BM + PADA];
   __shared__ double Bs[2][BN][BK + PADB];
@@ -176,7 +177,7 @@ __global__ void __launch_bounds__(256, 2)
     cur ^= 1;
   }
 
-  // epilogue: lane holds C[m0 + wm*64 + i*16 + l16][n0 + wn*64 + j*16 + 4*lk + v]
+  // epilogue: lane holds C[m0 + wm*64 + i*16 + l16][n0 + wn*64 + j*16 + lk + 4*v]
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t row = m0 + wm * 64 + i * 16 + l16;
@@ -185,10 +186,10 @@ __global__ void __launch_bounds__(256, 2)
     for (int j = 0; j < 4; ++j) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t col = n0 + wn * 64 + j * 16 + 4 * lk + v;
+        const int64_t col = n0 + wn * 64 + j * 16 + lk + 4 * v;
         if (col < N) {
           double *p = C + row + col * ldc;
-          if constexpr (AC == Acc::Subtract)
+          if constexpr (AC != Acc::Overwrite)
             *p = *p - acc[i][j][v];
           else
             *p = acc[i][j][v];
@@ -216,13 +217,14 @@ hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, const double *A, int64_
                         hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (K <= 0) {
-    if (acc == Acc::Subtract) return hipSuccess;
+    if (acc != Acc::Overwrite) return hipSuccess;
     return hipErrorInvalidValue;  // C = 0 is never requested by the solver
   }
 #define RBT_GEMM_CASE(OA_, OB_, AC_)                                              \
   if (opa == OA_ && opb == OB_ && acc == AC_)                                    \
     return launch_t<OA_, OB_, AC_>(M, N, K, A, lda, B, ldb, C, ldc, s);
   RBT_GEMM_CASE(OpA::General, OpB::General, Acc::Subtract)
+  RBT_GEMM_CASE(OpA::General, OpB::General, Acc::SubtractTrailing)
   RBT_GEMM_CASE(OpA::GeneralT, OpB::General, Acc::Subtract)
   RBT_GEMM_CASE(OpA::General, OpB::Upper, Acc::Overwrite)
   RBT_GEMM_CASE(OpA::UnitLower, OpB::General, Acc::Overwrite)

@@ -1,41 +1,112 @@
-// Small kernels around the solve: infinity norms and the backward error of
-// Eq. 7, column updates for iterative refinement (Sec. 5), fills and copies.
-// The residual product B - A X itself runs on the matrix-core GEMM.
+// Kernels around the solve for few right-hand sides: block updates of the
+// triangular solves, the residual B - A X with the row sums of |A| for
+// ||A||_inf fused into the same pass over A, the backward error of Eq. 7,
+// and the column updates of iterative refinement (Sec. 5).
+//
+// These are HBM-bound (one read of the matrix, a few columns of output), so
+// they run as plain FMA kernels with lanes along rows (coalesced column
+// runs of the column-major matrix) and the small right-hand-side block in
+// LDS; the matrix-core GEMM is kept for wide right-hand sides.
 #include "internal.h"
 
 namespace rbt {
 
 namespace {
 
-constexpr int kRowsPerBlock = 256;
-constexpr int64_t kColChunk = 512;
+constexpr int kRows = 256;       // rows per workgroup
+constexpr int64_t kChunk = 256;  // columns per split-K chunk of the residual
 
-// partial[chunk * n + i] = sum_{j in chunk} |A[i, j]|
-__global__ void __launch_bounds__(256) k_rowabs_partial(int64_t n, const double *__restrict__ A,
-                                                        int64_t lda,
-                                                        double *__restrict__ partial) {
-  const int64_t i = int64_t(blockIdx.x) * kRowsPerBlock + threadIdx.x;
-  if (i >= n) return;
-  const int64_t j0 = int64_t(blockIdx.y) * kColChunk;
-  const int64_t j1 = j0 + kColChunk < n ? j0 + kColChunk : n;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int64_t j = j0;
-  for (; j + 4 <= j1; j += 4) {
-    s0 += fabs(A[i + j * lda]);
-    s1 += fabs(A[i + (j + 1) * lda]);
-    s2 += fabs(A[i + (j + 2) * lda]);
-    s3 += fabs(A[i + (j + 3) * lda]);
+// Y (M x N) -= op(A) (M x K) X (K x N), N <= NMAX <= 16, K <= kNB.
+// TRANS: op(A)(m, k) = A[k + m lda] (transposed storage).
+template <int NMAX, bool TRANS>
+__global__ void __launch_bounds__(kRows) k_skinny_update(int64_t M, int N, int K,
+                                                         const double *__restrict__ A,
+                                                         int64_t lda,
+                                                         const double *__restrict__ X,
+                                                         int64_t ldx, double *Y, int64_t ldy) {
+  __shared__ double xs[kNB][NMAX];
+  for (int idx = threadIdx.x; idx < K * NMAX; idx += kRows) {
+    const int k = idx / NMAX, n = idx % NMAX;
+    xs[k][n] = n < N ? X[k + int64_t(n) * ldx] : 0.0;
   }
-  for (; j < j1; ++j) s0 += fabs(A[i + j * lda]);
-  partial[int64_t(blockIdx.y) * n + i] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  const int64_t m = int64_t(blockIdx.x) * kRows + threadIdx.x;
+  if (m >= M) return;
+  double acc[NMAX];
+#pragma unroll
+  for (int n = 0; n < NMAX; ++n) acc[n] = 0.0;
+#pragma unroll 8
+  for (int k = 0; k < K; ++k) {
+    const double a = TRANS ? A[k + m * lda] : A[m + int64_t(k) * lda];
+#pragma unroll
+    for (int n = 0; n < NMAX; ++n) acc[n] += a * xs[k][n];
+  }
+#pragma unroll
+  for (int n = 0; n < NMAX; ++n)
+    if (n < N) Y[m + int64_t(n) * ldy] -= acc[n];
 }
 
-__device__ __forceinline__ double block_max(double v, double *sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
+// partial[(c N + n) M + m] = sum_{k in chunk c} A[m, k] X[k, n];
+// ABS: abspart[c M + m] = sum_{k in chunk c} |A[m, k]|.
+template <int NMAX, bool ABS>
+__global__ void __launch_bounds__(kRows) k_gemv_partial(int64_t M, int N, int64_t K,
+                                                        const double *__restrict__ A,
+                                                        int64_t lda,
+                                                        const double *__restrict__ X,
+                                                        int64_t ldx,
+                                                        double *__restrict__ partial,
+                                                        double *__restrict__ abspart) {
+  __shared__ double xs[kChunk][NMAX];
+  const int64_t c = blockIdx.y;
+  const int64_t k0 = c * kChunk;
+  const int kc = int((K - k0) < kChunk ? (K - k0) : kChunk);
+  for (int idx = threadIdx.x; idx < kc * NMAX; idx += kRows) {
+    const int k = idx / NMAX, n = idx % NMAX;
+    xs[k][n] = n < N ? X[(k0 + k) + int64_t(n) * ldx] : 0.0;
+  }
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+  const int64_t m = int64_t(blockIdx.x) * kRows + threadIdx.x;
+  if (m >= M) return;
+  double acc[NMAX];
+#pragma unroll
+  for (int n = 0; n < NMAX; ++n) acc[n] = 0.0;
+  double s0 = 0.0, s1 = 0.0;
+  const double *Ap = A + m + k0 * lda;
+  int k = 0;
+#pragma unroll 4
+  for (; k + 2 <= kc; k += 2) {
+    const double a0 = Ap[int64_t(k) * lda];
+    const double a1 = Ap[int64_t(k + 1) * lda];
+#pragma unroll
+    for (int n = 0; n < NMAX; ++n) acc[n] += a0 * xs[k][n] + a1 * xs[k + 1][n];
+    if (ABS) {
+      s0 += fabs(a0);
+      s1 += fabs(a1);
+    }
+  }
+  for (; k < kc; ++k) {
+    const double a0 = Ap[int64_t(k) * lda];
+#pragma unroll
+    for (int n = 0; n < NMAX; ++n) acc[n] += a0 * xs[k][n];
+    if (ABS) s0 += fabs(a0);
+  }
+#pragma unroll
+  for (int n = 0; n < NMAX; ++n)
+    if (n < N) partial[(c * N + n) * M + m] = acc[n];
+  if (ABS) abspart[c * M + m] = s0 + s1;
+}
+
+__device__ __forceinline__ double nanmax(double a, double b) {
+  // NaN-propagating maximum: a NaN residual must never look converged
+  return (b > a || b != b) ? b : a;
+}
+
+// Block-wide NaN-propagating max of one value per thread (kRows threads).
+__device__ double block_nanmax(double v, double *sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kRows / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = nanmax(sh[threadIdx.x], sh[threadIdx.x + s]);
     __syncthreads();
   }
   const double r = sh[0];
@@ -43,55 +114,142 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
   return r;
 }
 
-// stats[0] = ||A||_inf = max_i sum_c partial[c * n + i]
-__global__ void __launch_bounds__(256) k_anorm(int64_t n, int64_t chunks,
-                                               const double *__restrict__ partial,
-                                               double *__restrict__ out) {
-  __shared__ double sh[256];
-  double m = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
-    double s = 0.0;
-    for (int64_t c = 0; c < chunks; ++c) s += partial[c * n + i];
-    m = fmax(m, s);
+// R = B - sum_c partial; per workgroup: max_m |R[:, n]|, |X[:, n]|, |B[:, n]|
+// and (ABS) max_m sum_c abspart = a block maximum of the row sums of |A|.
+// blockstat[(blk * (3 NMAX + 1)) + ...] layout: [3 n + 0..2] per column, then anorm.
+template <int NMAX, bool ABS>
+__global__ void __launch_bounds__(kRows) k_resid_reduce(
+    int64_t M, int N, int64_t chunks, const double *__restrict__ partial,
+    const double *__restrict__ abspart, const double *__restrict__ Bm, int64_t ldb,
+    const double *__restrict__ X, int64_t ldx, double *__restrict__ R, int64_t ldr,
+    double *__restrict__ blockstat) {
+  __shared__ double sh[kRows];
+  const int64_t m = int64_t(blockIdx.x) * kRows + threadIdx.x;
+  const bool ok = m < M;
+  double *bs = blockstat + int64_t(blockIdx.x) * (3 * NMAX + 1);
+  for (int n = 0; n < N; ++n) {
+    double r = 0.0, xv = 0.0, bv = 0.0;
+    if (ok) {
+      double s = 0.0;
+      for (int64_t c = 0; c < chunks; ++c) s += partial[(c * N + n) * M + m];
+      bv = Bm[m + int64_t(n) * ldb];
+      r = bv - s;
+      R[m + int64_t(n) * ldr] = r;
+      xv = X[m + int64_t(n) * ldx];
+    }
+    const double mr = block_nanmax(fabs(r), sh);
+    const double mx = block_nanmax(fabs(xv), sh);
+    const double mb = block_nanmax(fabs(bv), sh);
+    if (threadIdx.x == 0) {
+      bs[3 * n] = mr;
+      bs[3 * n + 1] = mx;
+      bs[3 * n + 2] = mb;
+    }
   }
-  m = block_max(m, sh);
+  if (ABS) {
+    double s = 0.0;
+    if (ok)
+      for (int64_t c = 0; c < chunks; ++c) s += abspart[c * M + m];
+    const double ma = block_nanmax(s, sh);
+    if (threadIdx.x == 0) bs[3 * NMAX] = ma;
+  }
+}
+
+// Final reduction over workgroups: anorm (if ABS) and the backward error.
+template <int NMAX, bool ABS>
+__global__ void __launch_bounds__(kRows) k_berr_blocks(int64_t nblk, int N,
+                                                       const double *__restrict__ blockstat,
+                                                       double *__restrict__ anorm,
+                                                       double *__restrict__ berr) {
+  __shared__ double sh[kRows];
+  const int stride = 3 * NMAX + 1;
+  double a;
+  if (ABS) {
+    double v = 0.0;
+    for (int64_t b = threadIdx.x; b < nblk; b += kRows) v = nanmax(v, blockstat[b * stride + 3 * NMAX]);
+    a = block_nanmax(v, sh);
+    if (threadIdx.x == 0) anorm[0] = a;
+  } else {
+    a = anorm[0];
+  }
+  double be = 0.0;
+  for (int n = 0; n < N; ++n) {
+    double r = 0.0, x = 0.0, bb = 0.0;
+    for (int64_t b = threadIdx.x; b < nblk; b += kRows) {
+      r = nanmax(r, blockstat[b * stride + 3 * n]);
+      x = nanmax(x, blockstat[b * stride + 3 * n + 1]);
+      bb = nanmax(bb, blockstat[b * stride + 3 * n + 2]);
+    }
+    r = block_nanmax(r, sh);
+    x = block_nanmax(x, sh);
+    bb = block_nanmax(bb, sh);
+    be = nanmax(be, r / (a * x + bb));
+  }
+  if (threadIdx.x == 0) berr[0] = be;
+}
+
+// ---- wide right-hand sides (N > 16): GEMM residual, separate norms ----
+
+// partial[c * n + i] = sum_{j in chunk c} |A[i, j]|
+__global__ void __launch_bounds__(kRows) k_rowabs_partial(int64_t n, const double *__restrict__ A,
+                                                         int64_t lda,
+                                                         double *__restrict__ partial) {
+  const int64_t i = int64_t(blockIdx.x) * kRows + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j0 = int64_t(blockIdx.y) * kChunk;
+  const int64_t j1 = j0 + kChunk < n ? j0 + kChunk : n;
+  double s0 = 0.0, s1 = 0.0;
+  int64_t j = j0;
+  for (; j + 2 <= j1; j += 2) {
+    s0 += fabs(A[i + j * lda]);
+    s1 += fabs(A[i + (j + 1) * lda]);
+  }
+  for (; j < j1; ++j) s0 += fabs(A[i + j * lda]);
+  partial[int64_t(blockIdx.y) * n + i] = s0 + s1;
+}
+
+// blockstat[blk] = max over the block's rows of sum_c partial
+__global__ void __launch_bounds__(kRows) k_rowabs_reduce(int64_t n, int64_t chunks,
+                                                        const double *__restrict__ partial,
+                                                        double *__restrict__ blockstat) {
+  __shared__ double sh[kRows];
+  const int64_t i = int64_t(blockIdx.x) * kRows + threadIdx.x;
+  double s = 0.0;
+  if (i < n)
+    for (int64_t c = 0; c < chunks; ++c) s += partial[c * n + i];
+  const double m = block_nanmax(s, sh);
+  if (threadIdx.x == 0) blockstat[blockIdx.x] = m;
+}
+
+__global__ void __launch_bounds__(kRows) k_max_reduce(int64_t nblk, const double *__restrict__ v,
+                                                     double *__restrict__ out) {
+  __shared__ double sh[kRows];
+  double m = 0.0;
+  for (int64_t b = threadIdx.x; b < nblk; b += kRows) m = nanmax(m, v[b]);
+  m = block_nanmax(m, sh);
   if (threadIdx.x == 0) out[0] = m;
 }
 
 // colstat[3 c + {0,1,2}] = max |R[:, c]|, max |X[:, c]|, max |B[:, c]|
-__global__ void __launch_bounds__(256) k_colmax(int64_t n, const double *__restrict__ R,
-                                                int64_t ldr, const double *__restrict__ X,
-                                                int64_t ldx, const double *__restrict__ B,
-                                                int64_t ldb, double *__restrict__ colstat) {
-  __shared__ double sh[256];
+__global__ void __launch_bounds__(kRows) k_colmax(int64_t n, const double *__restrict__ R,
+                                                 int64_t ldr, const double *__restrict__ X,
+                                                 int64_t ldx, const double *__restrict__ B,
+                                                 int64_t ldb, double *__restrict__ colstat) {
+  __shared__ double sh[kRows];
   const int64_t c = blockIdx.x;
   double mr = 0.0, mx = 0.0, mb = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
-    // NaN-propagating maxima: a NaN residual must not look converged
-    const double vr = fabs(R[i + c * ldr]);
-    const double vx = fabs(X[i + c * ldx]);
-    const double vb = fabs(B[i + c * ldb]);
-    mr = (vr > mr || vr != vr) ? vr : mr;
-    mx = (vx > mx || vx != vx) ? vx : mx;
-    mb = fmax(mb, vb);
+  for (int64_t i = threadIdx.x; i < n; i += kRows) {
+    mr = nanmax(mr, fabs(R[i + c * ldr]));
+    mx = nanmax(mx, fabs(X[i + c * ldx]));
+    mb = nanmax(mb, fabs(B[i + c * ldb]));
   }
-  sh[threadIdx.x] = mr;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      const double a = sh[threadIdx.x], b = sh[threadIdx.x + s];
-      sh[threadIdx.x] = (b > a || b != b) ? b : a;
-    }
-    __syncthreads();
-  }
-  const double rr = sh[0];
-  __syncthreads();
-  const double xx = block_max(mx, sh);
-  const double bb = block_max(mb, sh);
+  mr = block_nanmax(mr, sh);
+  mx = block_nanmax(mx, sh);
+  mb = block_nanmax(mb, sh);
   if (threadIdx.x == 0) {
-    colstat[3 * c] = rr;
-    colstat[3 * c + 1] = xx;
-    colstat[3 * c + 2] = bb;
+    colstat[3 * c] = mr;
+    colstat[3 * c + 1] = mx;
+    colstat[3 * c + 2] = mb;
   }
 }
 
@@ -101,25 +259,23 @@ __global__ void k_berr_final(int64_t nrhs, const double *__restrict__ colstat,
   if (threadIdx.x != 0) return;
   const double a = anorm[0];
   double m = 0.0;
-  for (int64_t c = 0; c < nrhs; ++c) {
-    const double v = colstat[3 * c] / (a * colstat[3 * c + 1] + colstat[3 * c + 2]);
-    m = (v > m || v != v) ? v : m;
-  }
+  for (int64_t c = 0; c < nrhs; ++c)
+    m = nanmax(m, colstat[3 * c] / (a * colstat[3 * c + 1] + colstat[3 * c + 2]));
   berr[0] = m;
 }
 
-__global__ void __launch_bounds__(256) k_axpy_cols(int64_t n, int64_t nrhs,
-                                                   const double *__restrict__ D, int64_t ldd,
-                                                   double *__restrict__ X, int64_t ldx) {
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+__global__ void __launch_bounds__(kRows) k_axpy_cols(int64_t n, int64_t nrhs,
+                                                    const double *__restrict__ D, int64_t ldd,
+                                                    double *__restrict__ X, int64_t ldx) {
+  const int64_t i = int64_t(blockIdx.x) * kRows + threadIdx.x;
   if (i >= n) return;
   for (int64_t c = blockIdx.y; c < nrhs; c += gridDim.y) X[i + c * ldx] += D[i + c * ldd];
 }
 
-__global__ void __launch_bounds__(256) k_copy_cols(int64_t n, int64_t nrhs,
-                                                   const double *__restrict__ S, int64_t lds,
-                                                   double *__restrict__ D, int64_t ldd) {
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+__global__ void __launch_bounds__(kRows) k_copy_cols(int64_t n, int64_t nrhs,
+                                                    const double *__restrict__ S, int64_t lds,
+                                                    double *__restrict__ D, int64_t ldd) {
+  const int64_t i = int64_t(blockIdx.x) * kRows + threadIdx.x;
   if (i >= n) return;
   for (int64_t c = blockIdx.y; c < nrhs; c += gridDim.y) D[i + c * ldd] = S[i + c * lds];
 }
@@ -128,30 +284,101 @@ __global__ void k_fill_i32(int32_t *p, int32_t v) {
   if (threadIdx.x == 0) p[0] = v;
 }
 
+__global__ void k_fill_f64(double *p, double v) {
+  if (threadIdx.x == 0) p[0] = v;
+}
+
 dim3 col_grid(int64_t n, int64_t nrhs) {
-  return dim3(unsigned((n + 255) / 256), unsigned(nrhs < 65535 ? nrhs : 65535));
+  return dim3(unsigned((n + kRows - 1) / kRows), unsigned(nrhs < 65535 ? nrhs : 65535));
+}
+
+template <int NMAX>
+hipError_t skinny_t(int64_t M, int N, int K, const double *A, int64_t lda, bool trans,
+                    const double *X, int64_t ldx, double *Y, int64_t ldy, hipStream_t s) {
+  const dim3 grid(unsigned((M + kRows - 1) / kRows));
+  if (trans)
+    hipLaunchKernelGGL((k_skinny_update<NMAX, true>), grid, dim3(kRows), 0, s, M, N, K, A, lda, X, ldx, Y, ldy);
+  else
+    hipLaunchKernelGGL((k_skinny_update<NMAX, false>), grid, dim3(kRows), 0, s, M, N, K, A, lda, X, ldx, Y, ldy);
+  return hipGetLastError();
+}
+
+template <int NMAX>
+hipError_t resid_t(int64_t n, int N, const double *A, int64_t lda, const double *X, int64_t ldx,
+                   const double *B, int64_t ldb, double *R, int64_t ldr, bool with_anorm,
+                   double *partial, double *abspart, double *blockstat, double *anorm,
+                   double *berr, hipStream_t s) {
+  const int64_t chunks = (n + kChunk - 1) / kChunk;
+  const int64_t nblk = (n + kRows - 1) / kRows;
+  const dim3 g2 = dim3(unsigned(nblk), unsigned(chunks));
+  if (with_anorm) {
+    hipLaunchKernelGGL((k_gemv_partial<NMAX, true>), g2, dim3(kRows), 0, s, n, N, n, A, lda, X, ldx, partial, abspart);
+    hipLaunchKernelGGL((k_resid_reduce<NMAX, true>), dim3(unsigned(nblk)), dim3(kRows), 0, s, n, N, chunks, partial, abspart, B, ldb, X, ldx, R, ldr, blockstat);
+    hipLaunchKernelGGL((k_berr_blocks<NMAX, true>), dim3(1), dim3(kRows), 0, s, nblk, N, blockstat, anorm, berr);
+  } else {
+    hipLaunchKernelGGL((k_gemv_partial<NMAX, false>), g2, dim3(kRows), 0, s, n, N, n, A, lda, X, ldx, partial, abspart);
+    hipLaunchKernelGGL((k_resid_reduce<NMAX, false>), dim3(unsigned(nblk)), dim3(kRows), 0, s, n, N, chunks, partial, abspart, B, ldb, X, ldx, R, ldr, blockstat);
+    hipLaunchKernelGGL((k_berr_blocks<NMAX, false>), dim3(1), dim3(kRows), 0, s, nblk, N, blockstat, anorm, berr);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
 
-int64_t rowabs_chunks(int64_t n) { return (n + kColChunk - 1) / kColChunk; }
-
-hipError_t launch_anorm(int64_t n, const double *A, int64_t lda, double *partial, double *out,
-                        hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  const int64_t chunks = rowabs_chunks(n);
-  hipLaunchKernelGGL(k_rowabs_partial, dim3(unsigned((n + 255) / 256), unsigned(chunks)),
-                     dim3(256), 0, s, n, A, lda, partial);
-  hipLaunchKernelGGL(k_anorm, dim3(1), dim3(256), 0, s, n, chunks, partial, out);
-  return hipGetLastError();
+size_t resid_scratch_doubles(int64_t n, int64_t nrhs) {
+  const int64_t chunks = (n + kChunk - 1) / kChunk;
+  const int64_t nblk = (n + kRows - 1) / kRows;
+  const int64_t nn = nrhs < 1 ? 1 : nrhs;
+  // partial (chunks * max(nrhs,16) * n) + abspart (chunks * n) + blockstat + colstat
+  const int64_t w = nn > kSkinnyMax ? 0 : nn;
+  return size_t(chunks) * n * (w + 1) + size_t(nblk) * (3 * kSkinnyMax + 1) + 3 * size_t(nn) + 64;
 }
 
-hipError_t launch_berr(int64_t n, int64_t nrhs, const double *R, int64_t ldr, const double *X,
-                       int64_t ldx, const double *B, int64_t ldb, const double *anorm,
-                       double *colstat, double *berr, hipStream_t s) {
-  if (n == 0 || nrhs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_colmax, dim3(unsigned(nrhs)), dim3(256), 0, s, n, R, ldr, X, ldx, B, ldb,
-                     colstat);
+hipError_t launch_skinny_update(int64_t M, int64_t N, int K, const double *A, int64_t lda,
+                                bool trans, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                                hipStream_t s) {
+  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  if (K > kNB || N > kSkinnyMax) return hipErrorInvalidValue;
+  if (N <= 1) return skinny_t<1>(M, int(N), K, A, lda, trans, X, ldx, Y, ldy, s);
+  if (N <= 4) return skinny_t<4>(M, int(N), K, A, lda, trans, X, ldx, Y, ldy, s);
+  if (N <= 8) return skinny_t<8>(M, int(N), K, A, lda, trans, X, ldx, Y, ldy, s);
+  return skinny_t<16>(M, int(N), K, A, lda, trans, X, ldx, Y, ldy, s);
+}
+
+hipError_t launch_residual_berr(int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                                const double *X, int64_t ldx, const double *B, int64_t ldb,
+                                double *R, int64_t ldr, bool with_anorm, double *scratch,
+                                double *anorm, double *berr, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) {
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, berr, 0.0);
+    return hipGetLastError();
+  }
+  const int64_t chunks = (n + kChunk - 1) / kChunk;
+  const int64_t nblk = (n + kRows - 1) / kRows;
+  if (nrhs <= kSkinnyMax) {
+    double *partial = scratch;
+    double *abspart = partial + chunks * n * nrhs;
+    double *blockstat = abspart + chunks * n;
+    const int N = int(nrhs);
+    if (N <= 1) return resid_t<1>(n, N, A, lda, X, ldx, B, ldb, R, ldr, with_anorm, partial, abspart, blockstat, anorm, berr, s);
+    if (N <= 4) return resid_t<4>(n, N, A, lda, X, ldx, B, ldb, R, ldr, with_anorm, partial, abspart, blockstat, anorm, berr, s);
+    if (N <= 8) return resid_t<8>(n, N, A, lda, X, ldx, B, ldb, R, ldr, with_anorm, partial, abspart, blockstat, anorm, berr, s);
+    return resid_t<16>(n, N, A, lda, X, ldx, B, ldb, R, ldr, with_anorm, partial, abspart, blockstat, anorm, berr, s);
+  }
+  // wide: norms by their own pass, residual by the matrix-core GEMM
+  double *abspart = scratch;
+  double *blockstat = abspart + chunks * n;
+  double *colstat = blockstat + nblk * (3 * kSkinnyMax + 1);
+  if (with_anorm) {
+    hipLaunchKernelGGL(k_rowabs_partial, dim3(unsigned(nblk), unsigned(chunks)), dim3(kRows), 0, s, n, A, lda, abspart);
+    hipLaunchKernelGGL(k_rowabs_reduce, dim3(unsigned(nblk)), dim3(kRows), 0, s, n, chunks, abspart, blockstat);
+    hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(kRows), 0, s, nblk, blockstat, anorm);
+  }
+  hipLaunchKernelGGL(k_copy_cols, col_grid(n, nrhs), dim3(kRows), 0, s, n, nrhs, B, ldb, R, ldr);
+  hipError_t e = launch_dgemm(n, nrhs, n, A, lda, OpA::General, X, ldx, OpB::General, R, ldr,
+                              Acc::Subtract, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colmax, dim3(unsigned(nrhs)), dim3(kRows), 0, s, n, R, ldr, X, ldx, B, ldb, colstat);
   hipLaunchKernelGGL(k_berr_final, dim3(1), dim3(64), 0, s, nrhs, colstat, anorm, berr);
   return hipGetLastError();
 }
@@ -159,19 +386,24 @@ hipError_t launch_berr(int64_t n, int64_t nrhs, const double *R, int64_t ldr, co
 hipError_t launch_axpy_cols(int64_t n, int64_t nrhs, const double *D, int64_t ldd, double *X,
                             int64_t ldx, hipStream_t s) {
   if (n == 0 || nrhs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_axpy_cols, col_grid(n, nrhs), dim3(256), 0, s, n, nrhs, D, ldd, X, ldx);
+  hipLaunchKernelGGL(k_axpy_cols, col_grid(n, nrhs), dim3(kRows), 0, s, n, nrhs, D, ldd, X, ldx);
   return hipGetLastError();
 }
 
 hipError_t launch_copy_cols(int64_t n, int64_t nrhs, const double *S, int64_t lds, double *D,
                             int64_t ldd, hipStream_t s) {
   if (n == 0 || nrhs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_cols, col_grid(n, nrhs), dim3(256), 0, s, n, nrhs, S, lds, D, ldd);
+  hipLaunchKernelGGL(k_copy_cols, col_grid(n, nrhs), dim3(kRows), 0, s, n, nrhs, S, lds, D, ldd);
   return hipGetLastError();
 }
 
 hipError_t launch_fill_i32(int32_t *p, int32_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, p, v);
   return hipGetLastError();
 }
 

@@ -1,0 +1,210 @@
+// Block triangular solves with a factored kb x kb diagonal block (kb <= 128)
+// of the elimination, 16 rows (columns) at a time: the update from the
+// blocks already solved runs on the FP64 matrix cores, and each 16 x 16
+// diagonal block is solved by plain substitution (one lane per right-hand
+// side), so the rounding behaviour is that of ordinary forward/back
+// substitution. (Multiplying by explicit inverses of the diagonal blocks,
+// even 16 x 16 ones, raised the backward error several-fold on N(0,1)
+// matrices with large growth.)
+//
+// Left solves, op(T) X = B in place (B: kb x N):
+//   LN  T = L (unit lower)     forward  (panel U12 = L11^-1 A12, L y = b)
+//   UN  T = U (upper)          backward (U x = y)
+//   UT  T = U^T (lower)        forward  (U^T z = g, adjoint solves)
+//   LT  T = L^T (unit upper)   backward (L^T w = z)
+//   X_I = T_II \ (B_I - sum_{J before I} T_IJ X_J)
+// Each wavefront owns 16 columns of B in an LDS strip; a workgroup of four
+// covers 64 columns.
+//
+// Right solve, X U = B in place (B: M x kb) for the panel L21 = A21 U11^-1:
+//   X_J = (B_J - sum_{I<J} X_I U_IJ) / U_JJ
+// Each wavefront owns 16 rows of B.
+//
+// MFMA: v_mfma_f64_16x16x4_f64 with the standard operand order; its output
+// element (lane l, v) is row l/16 + 4v, column l % 16.
+#include "internal.h"
+
+namespace rbt {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int NB = kNB;  // 128
+constexpr int IB = 16;
+
+template <TriMode MODE>
+constexpr bool forward_order() {
+  return MODE == TriMode::LN || MODE == TriMode::UT;
+}
+
+// Off-diagonal entry (i, j) of op(T) (i, j in different 16-blocks, both < kb).
+template <TriMode MODE>
+__device__ __forceinline__ double tri_off(const double *T, int64_t ldt, int i, int j) {
+  if constexpr (MODE == TriMode::LN || MODE == TriMode::UN)
+    return T[i + int64_t(j) * ldt];
+  else
+    return T[j + int64_t(i) * ldt];
+}
+
+template <TriMode MODE>
+__global__ void __launch_bounds__(256) k_trsm_left(int kb, int64_t N, const double *T,
+                                                   int64_t ldt, double *B, int64_t ldb) {
+  __shared__ double strip_all[4][NB * IB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  double *strip = strip_all[wave];
+  const int64_t col0 = int64_t(blockIdx.x) * 64 + wave * 16;
+
+  for (int idx = lane; idx < NB * IB; idx += 64) {
+    const int row = idx % NB, c = idx / NB;
+    const int64_t col = col0 + c;
+    strip[row * IB + c] = (row < kb && col < N) ? B[row + col * ldb] : 0.0;
+  }
+  __syncthreads();
+
+  const int nbk = (kb + IB - 1) / IB;
+  for (int step = 0; step < nbk; ++step) {
+    const int I = forward_order<MODE>() ? step : nbk - 1 - step;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    const int ia = IB * I + l16;  // row of op(T) this lane feeds
+    for (int s2 = 0; s2 < step; ++s2) {
+      const int J = forward_order<MODE>() ? s2 : nbk - 1 - s2;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int kx = IB * J + 4 * kk + lk;
+        const double a = (ia < kb && kx < kb) ? tri_off<MODE>(T, ldt, ia, kx) : 0.0;
+        const double bv = strip[kx * IB + l16];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) strip[(IB * I + lk + 4 * v) * IB + l16] -= acc[v];
+    __syncthreads();
+    // substitution inside the diagonal block: lane c < 16 owns column c
+    const int bs = kb - IB * I < IB ? kb - IB * I : IB;
+    if (lane < IB) {
+      const int o = IB * I;
+      double x[IB];
+#pragma unroll
+      for (int i = 0; i < IB; ++i) x[i] = strip[(o + i) * IB + lane];
+      if constexpr (forward_order<MODE>()) {
+#pragma unroll
+        for (int j = 0; j < IB; ++j) {
+          if (j < bs) {
+            if constexpr (MODE == TriMode::UT) x[j] = x[j] / T[(o + j) + int64_t(o + j) * ldt];
+#pragma unroll
+            for (int i = j + 1; i < IB; ++i)
+              if (i < bs) x[i] -= tri_off<MODE>(T, ldt, o + i, o + j) * x[j];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = IB - 1; j >= 0; --j) {
+          if (j < bs) {
+            if constexpr (MODE == TriMode::UN) x[j] = x[j] / T[(o + j) + int64_t(o + j) * ldt];
+#pragma unroll
+            for (int i = 0; i < j; ++i) x[i] -= tri_off<MODE>(T, ldt, o + i, o + j) * x[j];
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < IB; ++i) strip[(o + i) * IB + lane] = (i < bs) ? x[i] : 0.0;
+    }
+    __syncthreads();
+  }
+
+  for (int idx = lane; idx < NB * IB; idx += 64) {
+    const int row = idx % NB, c = idx / NB;
+    const int64_t col = col0 + c;
+    if (row < kb && col < N) B[row + col * ldb] = strip[row * IB + c];
+  }
+}
+
+constexpr int RS = NB + 1;  // row stride of the right-solve strip (odd: conflict-free)
+
+__global__ void __launch_bounds__(256) k_trsm_right_upper(int kb, int64_t M, const double *T,
+                                                          int64_t ldt, double *B, int64_t ldb) {
+  __shared__ double strip_all[4][IB * RS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  double *strip = strip_all[wave];
+  const int64_t row0 = int64_t(blockIdx.x) * 64 + wave * 16;
+
+  for (int idx = lane; idx < IB * NB; idx += 64) {
+    const int r = idx % IB, c = idx / IB;
+    const int64_t row = row0 + r;
+    strip[r * RS + c] = (row < M && c < kb) ? B[row + int64_t(c) * ldb] : 0.0;
+  }
+  __syncthreads();
+
+  const int nbk = (kb + IB - 1) / IB;
+  for (int J = 0; J < nbk; ++J) {
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    const int jc = IB * J + l16;  // column of U this lane feeds
+    for (int I = 0; I < J; ++I) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int kx = IB * I + 4 * kk + lk;
+        const double a = strip[l16 * RS + kx];
+        const double bv = (kx < kb && jc < kb) ? T[kx + int64_t(jc) * ldt] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) strip[(lk + 4 * v) * RS + IB * J + l16] -= acc[v];
+    __syncthreads();
+    // substitution inside the diagonal block: lane r < 16 owns row r
+    const int bs = kb - IB * J < IB ? kb - IB * J : IB;
+    if (lane < IB) {
+      const int o = IB * J;
+      double x[IB];
+#pragma unroll
+      for (int c = 0; c < IB; ++c) x[c] = strip[lane * RS + o + c];
+#pragma unroll
+      for (int c = 0; c < IB; ++c) {
+        if (c < bs) {
+          x[c] = x[c] / T[(o + c) + int64_t(o + c) * ldt];
+#pragma unroll
+          for (int c2 = c + 1; c2 < IB; ++c2)
+            if (c2 < bs) x[c2] -= x[c] * T[(o + c) + int64_t(o + c2) * ldt];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < IB; ++c) strip[lane * RS + o + c] = (c < bs) ? x[c] : 0.0;
+    }
+    __syncthreads();
+  }
+
+  for (int idx = lane; idx < IB * NB; idx += 64) {
+    const int r = idx % IB, c = idx / IB;
+    const int64_t row = row0 + r;
+    if (row < M && c < kb) B[row + int64_t(c) * ldb] = strip[r * RS + c];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_trsm_left(TriMode mode, int kb, int64_t N, const double *T, int64_t ldt,
+                            double *B, int64_t ldb, hipStream_t s) {
+  if (kb <= 0 || N <= 0) return hipSuccess;
+  if (kb > kNB) return hipErrorInvalidValue;
+  const dim3 grid(unsigned((N + 63) / 64));
+  switch (mode) {
+    case TriMode::LN: hipLaunchKernelGGL(k_trsm_left<TriMode::LN>, grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb); break;
+    case TriMode::UN: hipLaunchKernelGGL(k_trsm_left<TriMode::UN>, grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb); break;
+    case TriMode::UT: hipLaunchKernelGGL(k_trsm_left<TriMode::UT>, grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb); break;
+    case TriMode::LT: hipLaunchKernelGGL(k_trsm_left<TriMode::LT>, grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_right_upper(int kb, int64_t M, const double *T, int64_t ldt, double *B,
+                                   int64_t ldb, hipStream_t s) {
+  if (kb <= 0 || M <= 0) return hipSuccess;
+  if (kb > kNB) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_trsm_right_upper, dim3(unsigned((M + 63) / 64)), dim3(256), 0, s, kb, M,
+                     T, ldt, B, ldb);
+  return hipGetLastError();
+}
+
+}  // namespace rbt

@@ -14,19 +14,32 @@ from . import _lib
 from ._lib import RBT_FP32, RBT_FP64, RBT_OP_N, RBT_OP_T, check  # noqa: F401
 
 
+def _colmajor_ld(t):
+    """Leading dimension of a column-major 2-D tensor, or None if it is not
+    one. Strides of size-1 dimensions are ignored (torch leaves them free)."""
+    if t.dim() != 2:
+        return None
+    rows, cols = t.shape
+    if rows > 1 and t.stride(0) != 1:
+        return None
+    ld = t.stride(1) if cols > 1 else max(1, rows)
+    return ld if ld >= max(1, rows) else None
+
+
 def colmajor(t):
-    """Column-major copy (or the tensor itself when it already is one)."""
+    """Column-major view of t (itself when it already is one, else a copy)."""
     if t.dim() == 1:
         t = t.reshape(-1, 1)
-    if t.stride(0) == 1 and t.stride(1) >= max(1, t.shape[0]):
+    if _colmajor_ld(t) is not None:
         return t
     return t.t().contiguous().t()
 
 
 def _ld(t):
-    if t.dim() != 2 or t.stride(0) != 1 or t.stride(1) < max(1, t.shape[0]):
+    ld = _colmajor_ld(t)
+    if ld is None:
         raise ValueError("expected a column-major 2-D tensor (stride (1, ld), ld >= rows)")
-    return t.stride(1)
+    return ld
 
 
 def _dev_f64(t, name):
@@ -103,22 +116,21 @@ def transform_vec(B, C, depth, op):
     return B
 
 
-def genp(A, info=None, work=None):
-    """In-place elimination without pivoting. Returns (A, info, work)."""
+def genp(A, info=None):
+    """In-place elimination without pivoting. Returns (A, info)."""
     _dev_f64(A, "A")
     n = A.shape[0]
-    work = work if work is not None else _workspace(n, 0, 0, A.device)
     info = info if info is not None else torch.zeros(1, dtype=torch.int32, device=A.device)
-    check(lib().rbt_genp(n, _p(A), _ld(A), _p(info), _p(work), work.numel(), _stream(A.device)),
-          "rbt_genp")
-    return A, info, work
+    check(lib().rbt_genp(n, _p(A), _ld(A), _p(info), _stream(A.device)), "rbt_genp")
+    return A, info
 
 
-def getrs(LU, B, work, trans=0):
+def getrs(LU, B, trans=0):
+    """B <- (LU)^-1 B (trans=0) or (LU)^-T B (trans=1), in place."""
     _dev_f64(B, "B")
     n = LU.shape[0]
-    check(lib().rbt_getrs(n, B.shape[1], _p(LU), _ld(LU), _p(B), _ld(B), trans, _p(work),
-                          work.numel(), _stream(B.device)), "rbt_getrs")
+    check(lib().rbt_getrs(n, B.shape[1], _p(LU), _ld(LU), _p(B), _ld(B), trans,
+                          _stream(B.device)), "rbt_getrs")
     return B
 
 
@@ -175,3 +187,20 @@ def backward_error(A, X, B, work=None):
     check(lib().rbt_backward_error(n, k, _p(A), _ld(A), _p(X), _ld(X), _p(B), _ld(B), _p(berr),
                                    _p(work), work.numel(), _stream(A.device)), "rbt_backward_error")
     return berr
+
+
+def timing_enable(on=True):
+    """Record HIP events around each stage of the composite entry points."""
+    check(lib().rbt_timing_enable(1 if on else 0), "rbt_timing_enable")
+
+
+def timing_read():
+    """Per-stage totals since the last read: {stage: (ms, launches, work)}."""
+    n = _lib.RBT_STAGE_COUNT
+    ms = np.zeros(n)
+    cnt = np.zeros(n, dtype=np.int64)
+    work = np.zeros(n)
+    check(lib().rbt_timing_read(n, ms.ctypes.data_as(ctypes.c_void_p),
+                                cnt.ctypes.data_as(ctypes.c_void_p),
+                                work.ctypes.data_as(ctypes.c_void_p)), "rbt_timing_read")
+    return {name: (float(ms[i]), int(cnt[i]), float(work[i])) for i, name in enumerate(_lib.STAGES)}

@@ -99,7 +99,7 @@ def test_transform_vec_matches_oracle(rbt, d):
 def test_genp_matches_oracle(rbt, n):
     A = workloads.shifted(n, seed=n)
     LUo, info_o = osolve.genp_unblocked(A)
-    LU, info, work = rbt.genp(dev(A))
+    LU, info = rbt.genp(dev(A))
     torch.cuda.synchronize()
     assert int(info.item()) == info_o == 0
     L = host(LU)
@@ -112,14 +112,23 @@ def test_genp_randn_reconstruction(rbt):
     Uo, Vo = coeffs.generate(n, 2, 2023)
     At = otr.two_sided(A, Uo, Vo, 2)
     LUo, _ = osolve.genp_unblocked(At)
-    LU, info, _ = rbt.genp(dev(At))
+    LU, info = rbt.genp(dev(At))
     L = host(LU)
     Lm = np.tril(L, -1) + np.eye(n)
     Um = np.triu(L)
     res = np.abs(Lm @ Um - At).max() / (np.abs(Lm).max() * np.abs(Um).max())
     assert res <= 20 * n * EPS
-    growth = np.abs(LUo).max()
-    assert np.abs(L - LUo).max() <= 1e-11 * growth
+    # Elementwise agreement of L and U with the oracle is not a fixed
+    # tolerance here: without pivoting, rounding differences are amplified by
+    # the conditioning of the leading minors of an N(0,1) matrix. The unique
+    # quantity is A~ = L U (checked above); the oracle's factors satisfy the
+    # same bound, and both solve with a small backward error.
+    Lo = np.tril(LUo, -1) + np.eye(n)
+    res_o = np.abs(Lo @ np.triu(LUo) - At).max() / (np.abs(Lo).max() * np.abs(np.triu(LUo)).max())
+    assert res_o <= 20 * n * EPS
+    b = workloads.randn(n, 1, seed=3)
+    x = osolve.lu_solve(L, b)
+    assert osolve.backward_error(At, x, b) <= 10 * n * EPS
 
 
 def test_genp_zero_pivot_info(rbt):
@@ -127,7 +136,7 @@ def test_genp_zero_pivot_info(rbt):
     A[130, 130] = 0.0
     A[130, 131] = 1.0
     A[131, 130] = 1.0
-    _, info, _ = rbt.genp(dev(A))
+    _, info = rbt.genp(dev(A))
     assert int(info.item()) == 131
     _, info_o = osolve.genp_unblocked(A)
     assert info_o == 131
@@ -138,10 +147,10 @@ def test_getrs_both_transposes(rbt, n, k):
     A = workloads.shifted(n, seed=n + 1)
     B = workloads.randn(n, k, seed=9)
     LUo, _ = osolve.genp_unblocked(A)
-    LU, info, work = rbt.genp(dev(A))
-    X = rbt.getrs(LU, dev(B), work, trans=0)
+    LU, info = rbt.genp(dev(A))
+    X = rbt.getrs(LU, dev(B), trans=0)
     assert relfro(host(X), osolve.lu_solve(LUo, B)) <= 1e-12
-    Xt = rbt.getrs(LU, dev(B), work, trans=1)
+    Xt = rbt.getrs(LU, dev(B), trans=1)
     expect_t = osolve.backward_unit_lower_transposed(LUo, osolve.forward_upper_transposed(LUo, B))
     assert relfro(host(Xt), expect_t) <= 1e-12
 
