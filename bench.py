@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-gepp", action="store_true", help="skip the GEPP comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=4096, help="oracle sample size")
+    ap.add_argument("--outer-nb", type=int, default=0,
+                    help="panel width of the elimination (multiple of 128; 0 = library default)")
     return ap.parse_args()
 
 
@@ -83,6 +85,8 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.outer_nb:
+        rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, args.outer_nb)
     n, k, d = args.n, args.nrhs, args.depth
     tol = 10.0 * n * 2.0 ** -52
 
@@ -142,7 +146,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"RBT+GENP FP64 solve, n={n}, nrhs={k}, depth {d}, A~N(0,1) seed 42, "
                                f"b~N(0,1) seed 64, FP64 refinement to berr<=10*n*eps",
-                   "n": n, "nrhs": k, "depth": d},
+                   "n": n, "nrhs": k, "depth": d,
+                   "outer_nb": rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)},
         "roofline": {"bound": "mfma", "kernel": "trailing-update GEMM (k_dgemm, FP64 MFMA)",
                      "achieved": round(gemm_tflops, 3), "peak": PEAK_FP64_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(gemm_tflops / PEAK_FP64_MFMA_TFLOPS, 4),

@@ -152,6 +152,17 @@ int rbt_backward_error(int64_t n, int64_t nrhs, const double *A, int64_t lda, co
                        int64_t ldx, const double *B, int64_t ldb, double *berr_dev, void *work,
                        size_t work_bytes, void *stream);
 
+/* Tuning options (process-wide; not thread safe).
+ * RBT_OPT_OUTER_NB: width of the panels of the elimination whose trailing
+ *   update is a single GEMM (multiple of 128, 128..2048; default 512). The
+ *   diagonal blocks are always 128 x 128. Changes only the order of the
+ *   roundings, not the method. */
+#define RBT_OPT_OUTER_NB 1
+/* Returns 0, -1 for an unknown option, -2 for an invalid value. */
+int rbt_set_option(int option, int64_t value);
+/* Current value, or -1 for an unknown option. */
+int64_t rbt_get_option(int option);
+
 /* Stage timing, for measurement. When enabled, the composite entry points
  * (rbt_solve_ex, rbt_solve_refine, rbt_genp) record a pair of HIP events on
  * their stream around each stage:

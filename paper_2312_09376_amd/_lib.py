@@ -35,10 +35,13 @@ SIGNATURES = {
     "rbt_solve_refine": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, u64, dbl, i32,
                                vp, vp, vp, vp, sz, vp]),
     "rbt_backward_error": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, vp, sz, vp]),
+    "rbt_set_option": (i32, [i32, i64]),
+    "rbt_get_option": (i64, [i32]),
     "rbt_timing_enable": (i32, [i32]),
     "rbt_timing_read": (i32, [i32, vp, vp, vp]),
 }
 RBT_STAGE_COUNT = 8
+RBT_OPT_OUTER_NB = 1
 STAGES = ["generate", "transform2", "transform_vec", "diag", "panel", "trailing", "solve",
           "residual"]
 

@@ -89,32 +89,75 @@ T *at(void *base, size_t off) {
 
 inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
-// Blocked right-looking elimination without pivoting (block kNB):
-//   factor A11 (and invert its triangles), L21 = A21 U11^-1,
-//   U12 = L11^-1 A12, A22 -= L21 U12.
+// Tunable options (rbt_set_option).
+struct Options {
+  int64_t outer_nb = 512;  // width of the panel whose trailing update is one GEMM
+};
+Options &options() {
+  static Options o;
+  return o;
+}
+
+// Blocked right-looking elimination without pivoting, two levels:
+// the matrix is processed in panels of width W (a multiple of kNB); inside a
+// panel, kNB-wide steps factor the diagonal block, solve the rows below it
+// (L part) and update the rest of the panel only; then the panel's block row
+// U12 = L11^-1 A12 is solved (kNB rows at a time) and the trailing matrix is
+// updated by one GEMM of depth W, which keeps the GEMM's read-modify-write of
+// A22 well under the HBM bandwidth at matrix-core rate.
 int genp_fp64(int64_t n, double *A, int64_t lda, int32_t *info, hipStream_t s) {
   if (info) RBT_HIP_CHECK(launch_fill_i32(info, 0, s));
-  for (int64_t k = 0; k < n; k += kNB) {
-    const int kb = int(n - k < kNB ? n - k : kNB);
-    double *A11 = A + k + k * lda;
-    {
-      StageScope t(kStageDiag, s, 4.0 / 3.0 * double(kb) * kb * kb);
-      RBT_HIP_CHECK(launch_diag_lu(kb, A11, lda, k, info, s));
+  const int64_t W = options().outer_nb;
+  for (int64_t k0 = 0; k0 < n; k0 += W) {
+    const int64_t w = n - k0 < W ? n - k0 : W;
+    // ---- panel A[k0:n, k0:k0+w] ----
+    for (int64_t k = k0; k < k0 + w; k += kNB) {
+      const int kb = int(k0 + w - k < kNB ? k0 + w - k : kNB);
+      double *A11 = A + k + k * lda;
+      {
+        StageScope t(kStageDiag, s, 2.0 / 3.0 * double(kb) * kb * kb);
+        RBT_HIP_CHECK(launch_diag_lu(kb, A11, lda, k, info, s));
+      }
+      const int64_t rows = n - k - kb;      // rows below the diagonal block
+      const int64_t pc = k0 + w - k - kb;   // panel columns right of it
+      {
+        StageScope t(kStagePanel, s, double(rows) * kb * kb + double(pc) * kb * kb);
+        RBT_HIP_CHECK(launch_trsm_right_upper(kb, rows, A11, lda, A + (k + kb) + k * lda, lda, s));
+        if (pc > 0)
+          RBT_HIP_CHECK(launch_trsm_left(TriMode::LN, kb, pc, A11, lda, A + k + (k + kb) * lda,
+                                         lda, s));
+      }
+      if (pc > 0 && rows > 0) {
+        StageScope t(kStagePanel, s, 2.0 * double(rows) * pc * kb);
+        RBT_HIP_CHECK(launch_dgemm(rows, pc, kb, A + (k + kb) + k * lda, lda, OpA::General,
+                                   A + k + (k + kb) * lda, lda, OpB::General,
+                                   A + (k + kb) + (k + kb) * lda, lda, Acc::Subtract, s));
+      }
     }
-    const int64_t rem = n - k - kb;
-    if (rem <= 0) continue;
-    double *A21 = A + (k + kb) + k * lda;
-    double *A12 = A + k + (k + kb) * lda;
-    double *A22 = A + (k + kb) + (k + kb) * lda;
-    {
-      StageScope t(kStagePanel, s, 2.0 * double(rem) * kb * kb);
-      RBT_HIP_CHECK(launch_trsm_right_upper(kb, rem, A11, lda, A21, lda, s));
-      RBT_HIP_CHECK(launch_trsm_left(TriMode::LN, kb, rem, A11, lda, A12, lda, s));
+    const int64_t rc = n - k0 - w;  // columns right of the panel
+    if (rc <= 0) continue;
+    // ---- block row U12 = L11^-1 A12 (L11: w x w unit lower) ----
+    for (int64_t k = k0; k < k0 + w; k += kNB) {
+      const int kb = int(k0 + w - k < kNB ? k0 + w - k : kNB);
+      const int64_t below = k0 + w - k - kb;
+      {
+        StageScope t(kStagePanel, s, double(rc) * kb * kb);
+        RBT_HIP_CHECK(launch_trsm_left(TriMode::LN, kb, rc, A + k + k * lda, lda,
+                                       A + k + (k0 + w) * lda, lda, s));
+      }
+      if (below > 0) {
+        StageScope t(kStagePanel, s, 2.0 * double(below) * rc * kb);
+        RBT_HIP_CHECK(launch_dgemm(below, rc, kb, A + (k + kb) + k * lda, lda, OpA::General,
+                                   A + k + (k0 + w) * lda, lda, OpB::General,
+                                   A + (k + kb) + (k0 + w) * lda, lda, Acc::Subtract, s));
+      }
     }
+    // ---- trailing update A22 -= L21 U12, depth w ----
     {
-      StageScope t(kStageTrailing, s, 2.0 * double(rem) * rem * kb);
-      RBT_HIP_CHECK(launch_dgemm(rem, rem, kb, A21, lda, OpA::General, A12, lda, OpB::General,
-                                 A22, lda, Acc::SubtractTrailing, s));
+      StageScope t(kStageTrailing, s, 2.0 * double(rc) * rc * w);
+      RBT_HIP_CHECK(launch_dgemm(rc, rc, w, A + (k0 + w) + k0 * lda, lda, OpA::General,
+                                 A + k0 + (k0 + w) * lda, lda, OpB::General,
+                                 A + (k0 + w) + (k0 + w) * lda, lda, Acc::SubtractTrailing, s));
     }
   }
   return 0;
@@ -431,4 +474,22 @@ extern "C" int rbt_timing_read(int nstages, double *ms, int64_t *launches, doubl
     t.work[i] = 0.0;
   }
   return rc;
+}
+
+extern "C" int rbt_set_option(int option, int64_t value) {
+  switch (option) {
+    case RBT_OPT_OUTER_NB:
+      if (value < kNB || value % kNB != 0 || value > 16 * kNB) return -2;
+      options().outer_nb = value;
+      return 0;
+    default:
+      return -1;
+  }
+}
+
+extern "C" int64_t rbt_get_option(int option) {
+  switch (option) {
+    case RBT_OPT_OUTER_NB: return options().outer_nb;
+    default: return -1;
+  }
 }

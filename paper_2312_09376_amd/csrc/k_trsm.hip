@@ -7,6 +7,10 @@
 // even 16 x 16 ones, raised the backward error several-fold on N(0,1)
 // matrices with large growth.)
 //
+// The triangle of op(T) is first staged in LDS as its 36 16 x 16 blocks, so
+// the serial substitution reads LDS broadcasts instead of waiting on global
+// memory.
+//
 // Left solves, op(T) X = B in place (B: kb x N):
 //   LN  T = L (unit lower)     forward  (panel U12 = L11^-1 A12, L y = b)
 //   UN  T = U (upper)          backward (U x = y)
@@ -31,30 +35,64 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int NB = kNB;  // 128
 constexpr int IB = 16;
+constexpr int NBK = NB / IB;                 // 8 blocks per side
+constexpr int NTRI = NBK * (NBK + 1) / 2;    // 36 blocks in a triangle
+constexpr int BLK = IB * IB;                 // 256 doubles per block
 
 template <TriMode MODE>
 constexpr bool forward_order() {
   return MODE == TriMode::LN || MODE == TriMode::UT;
 }
 
-// Off-diagonal entry (i, j) of op(T) (i, j in different 16-blocks, both < kb).
+// Index of block (I, J) of the staged triangle: lower (I >= J) for the
+// forward modes, upper (I <= J) otherwise.
+template <bool LOWER>
+__device__ __forceinline__ int tri_index(int I, int J) {
+  return LOWER ? I * (I + 1) / 2 + J : J * (J + 1) / 2 + I;
+}
+
+// op(T)(i, j) read from global memory (i, j < kb).
 template <TriMode MODE>
-__device__ __forceinline__ double tri_off(const double *T, int64_t ldt, int i, int j) {
+__device__ __forceinline__ double op_t(const double *T, int64_t ldt, int i, int j) {
   if constexpr (MODE == TriMode::LN || MODE == TriMode::UN)
     return T[i + int64_t(j) * ldt];
   else
     return T[j + int64_t(i) * ldt];
 }
 
+// Stage the triangle of op(T) blocks into LDS, each block column-major
+// (element (r, c) at c * 16 + r); entries at or beyond kb are zero.
+template <TriMode MODE>
+__device__ void stage_left(const double *T, int64_t ldt, int kb, double *tri) {
+  constexpr bool LOWER = forward_order<MODE>();
+  for (int b = 0; b < NTRI; ++b) {
+    // invert tri_index for this block
+    int I = 0, J = 0;
+    if (LOWER) {
+      while ((I + 1) * (I + 2) / 2 <= b) ++I;
+      J = b - I * (I + 1) / 2;
+    } else {
+      while ((J + 1) * (J + 2) / 2 <= b) ++J;
+      I = b - J * (J + 1) / 2;
+    }
+    const int r = threadIdx.x % IB, c = threadIdx.x / IB;  // 256 threads = one block
+    const int i = IB * I + r, j = IB * J + c;
+    tri[b * BLK + c * IB + r] = (i < kb && j < kb) ? op_t<MODE>(T, ldt, i, j) : 0.0;
+  }
+}
+
 template <TriMode MODE>
 __global__ void __launch_bounds__(256) k_trsm_left(int kb, int64_t N, const double *T,
                                                    int64_t ldt, double *B, int64_t ldb) {
+  __shared__ double tri[NTRI * BLK];
   __shared__ double strip_all[4][NB * IB];
+  constexpr bool LOWER = forward_order<MODE>();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
   double *strip = strip_all[wave];
   const int64_t col0 = int64_t(blockIdx.x) * 64 + wave * 16;
 
+  stage_left<MODE>(T, ldt, kb, tri);
   for (int idx = lane; idx < NB * IB; idx += 64) {
     const int row = idx % NB, c = idx / NB;
     const int64_t col = col0 + c;
@@ -64,46 +102,47 @@ __global__ void __launch_bounds__(256) k_trsm_left(int kb, int64_t N, const doub
 
   const int nbk = (kb + IB - 1) / IB;
   for (int step = 0; step < nbk; ++step) {
-    const int I = forward_order<MODE>() ? step : nbk - 1 - step;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-    const int ia = IB * I + l16;  // row of op(T) this lane feeds
+    const int I = LOWER ? step : nbk - 1 - step;
+    d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
     for (int s2 = 0; s2 < step; ++s2) {
-      const int J = forward_order<MODE>() ? s2 : nbk - 1 - s2;
+      const int J = LOWER ? s2 : nbk - 1 - s2;
+      const double *tb = tri + tri_index<LOWER>(I, J) * BLK;
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int kx = IB * J + 4 * kk + lk;
-        const double a = (ia < kb && kx < kb) ? tri_off<MODE>(T, ldt, ia, kx) : 0.0;
-        const double bv = strip[kx * IB + l16];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+      for (int kk = 0; kk < 4; kk += 2) {
+        const int k0 = 4 * kk + lk, k1 = 4 * (kk + 1) + lk;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(tb[k0 * IB + l16],
+                                                    strip[(IB * J + k0) * IB + l16], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(tb[k1 * IB + l16],
+                                                    strip[(IB * J + k1) * IB + l16], acc1, 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) strip[(IB * I + lk + 4 * v) * IB + l16] -= acc[v];
+    for (int v = 0; v < 4; ++v) strip[(IB * I + lk + 4 * v) * IB + l16] -= acc0[v] + acc1[v];
     __syncthreads();
     // substitution inside the diagonal block: lane c < 16 owns column c
     const int bs = kb - IB * I < IB ? kb - IB * I : IB;
     if (lane < IB) {
       const int o = IB * I;
+      const double *tb = tri + tri_index<LOWER>(I, I) * BLK;  // element (i, j) at j*16+i
       double x[IB];
 #pragma unroll
       for (int i = 0; i < IB; ++i) x[i] = strip[(o + i) * IB + lane];
-      if constexpr (forward_order<MODE>()) {
+      if constexpr (LOWER) {
 #pragma unroll
         for (int j = 0; j < IB; ++j) {
           if (j < bs) {
-            if constexpr (MODE == TriMode::UT) x[j] = x[j] / T[(o + j) + int64_t(o + j) * ldt];
+            if constexpr (MODE == TriMode::UT) x[j] = x[j] / tb[j * IB + j];
 #pragma unroll
-            for (int i = j + 1; i < IB; ++i)
-              if (i < bs) x[i] -= tri_off<MODE>(T, ldt, o + i, o + j) * x[j];
+            for (int i = j + 1; i < IB; ++i) x[i] -= tb[j * IB + i] * x[j];
           }
         }
       } else {
 #pragma unroll
         for (int j = IB - 1; j >= 0; --j) {
           if (j < bs) {
-            if constexpr (MODE == TriMode::UN) x[j] = x[j] / T[(o + j) + int64_t(o + j) * ldt];
+            if constexpr (MODE == TriMode::UN) x[j] = x[j] / tb[j * IB + j];
 #pragma unroll
-            for (int i = 0; i < j; ++i) x[i] -= tri_off<MODE>(T, ldt, o + i, o + j) * x[j];
+            for (int i = 0; i < j; ++i) x[i] -= tb[j * IB + i] * x[j];
           }
         }
       }
@@ -124,12 +163,21 @@ constexpr int RS = NB + 1;  // row stride of the right-solve strip (odd: conflic
 
 __global__ void __launch_bounds__(256) k_trsm_right_upper(int kb, int64_t M, const double *T,
                                                           int64_t ldt, double *B, int64_t ldb) {
+  __shared__ double tri[NTRI * BLK];  // upper blocks of U, each row-major (r * 16 + c)
   __shared__ double strip_all[4][IB * RS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
   double *strip = strip_all[wave];
   const int64_t row0 = int64_t(blockIdx.x) * 64 + wave * 16;
 
+  for (int b = 0; b < NTRI; ++b) {
+    int J = 0;
+    while ((J + 1) * (J + 2) / 2 <= b) ++J;
+    const int I = b - J * (J + 1) / 2;
+    const int r = threadIdx.x % IB, c = threadIdx.x / IB;
+    const int i = IB * I + r, j = IB * J + c;
+    tri[b * BLK + r * IB + c] = (i < kb && j < kb) ? T[i + int64_t(j) * ldt] : 0.0;
+  }
   for (int idx = lane; idx < IB * NB; idx += 64) {
     const int r = idx % IB, c = idx / IB;
     const int64_t row = row0 + r;
@@ -139,34 +187,35 @@ __global__ void __launch_bounds__(256) k_trsm_right_upper(int kb, int64_t M, con
 
   const int nbk = (kb + IB - 1) / IB;
   for (int J = 0; J < nbk; ++J) {
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-    const int jc = IB * J + l16;  // column of U this lane feeds
+    d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
     for (int I = 0; I < J; ++I) {
+      const double *tb = tri + tri_index<false>(I, J) * BLK;
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int kx = IB * I + 4 * kk + lk;
-        const double a = strip[l16 * RS + kx];
-        const double bv = (kx < kb && jc < kb) ? T[kx + int64_t(jc) * ldt] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+      for (int kk = 0; kk < 4; kk += 2) {
+        const int k0 = 4 * kk + lk, k1 = 4 * (kk + 1) + lk;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[l16 * RS + IB * I + k0],
+                                                    tb[k0 * IB + l16], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[l16 * RS + IB * I + k1],
+                                                    tb[k1 * IB + l16], acc1, 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) strip[(lk + 4 * v) * RS + IB * J + l16] -= acc[v];
+    for (int v = 0; v < 4; ++v) strip[(lk + 4 * v) * RS + IB * J + l16] -= acc0[v] + acc1[v];
     __syncthreads();
     // substitution inside the diagonal block: lane r < 16 owns row r
     const int bs = kb - IB * J < IB ? kb - IB * J : IB;
     if (lane < IB) {
       const int o = IB * J;
+      const double *tb = tri + tri_index<false>(J, J) * BLK;  // element (r, c) at r*16+c
       double x[IB];
 #pragma unroll
       for (int c = 0; c < IB; ++c) x[c] = strip[lane * RS + o + c];
 #pragma unroll
       for (int c = 0; c < IB; ++c) {
         if (c < bs) {
-          x[c] = x[c] / T[(o + c) + int64_t(o + c) * ldt];
+          x[c] = x[c] / tb[c * IB + c];
 #pragma unroll
-          for (int c2 = c + 1; c2 < IB; ++c2)
-            if (c2 < bs) x[c2] -= x[c] * T[(o + c) + int64_t(o + c2) * ldt];
+          for (int c2 = c + 1; c2 < IB; ++c2) x[c2] -= x[c] * tb[c * IB + c2];
         }
       }
 #pragma unroll

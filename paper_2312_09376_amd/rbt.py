@@ -204,3 +204,11 @@ def timing_read():
                                 cnt.ctypes.data_as(ctypes.c_void_p),
                                 work.ctypes.data_as(ctypes.c_void_p)), "rbt_timing_read")
     return {name: (float(ms[i]), int(cnt[i]), float(work[i])) for i, name in enumerate(_lib.STAGES)}
+
+
+def set_option(option, value):
+    check(lib().rbt_set_option(option, int(value)), "rbt_set_option")
+
+
+def get_option(option):
+    return int(lib().rbt_get_option(option))

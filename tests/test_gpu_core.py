@@ -169,15 +169,22 @@ def test_solve_matches_oracle(rbt, n, k, d):
 
 @pytest.mark.parametrize("n", [1000, 1001, 1003])
 def test_solve_randn_backward_error(rbt, n):
+    """Depth-2 RBT carries no bound on growth (Sec. 4): on these N(0,1)
+    matrices the oracle's own unrefined backward error ranges from 1e-13 to
+    9e-12 (growth up to 2.5e5 at n = 1000). The GPU must stay in the same
+    accuracy class as the oracle, and refinement (Sec. 5) must bring it to
+    10 n eps."""
     A = workloads.randn_matrix(n)
     B = workloads.randn(n, 1, seed=64)
     _, X, info, _ = rbt.solve_(dev(A), dev(B), 2, 2023)
     be = osolve.backward_error(A, host(X), B)
-    assert be <= 10 * n * EPS, be
     Uo, Vo = coeffs.generate(n, 2, 2023)
     Xo, _, _ = osolve.rbt_solve(A, B, Uo, Vo, 2)
-    kappa_bound = np.abs(Xo - np.linalg.solve(A, B)).max() / np.abs(Xo).max()
-    assert np.abs(host(X) - Xo).max() / np.abs(Xo).max() <= max(1e-10, 100 * kappa_bound)
+    be_o = osolve.backward_error(A, Xo, B)
+    assert be <= max(10 * n * EPS, 10 * be_o), (be, be_o)
+    Xr, _, iters, berr, _, _ = rbt.solve_refine(dev(A), dev(B), 2, 2023, max_iter=5)
+    assert float(berr.item()) <= 10 * n * EPS
+    assert osolve.backward_error(A, host(Xr), B) <= 10 * n * EPS
 
 
 def test_hostile_matrix(rbt):
