@@ -21,10 +21,12 @@
 // reads only the rows (columns) it writes, i.e. N <= 128 (M <= 128); all
 // reads of the K loop complete before the epilogue writes.
 //
-// Block ids are remapped so that consecutive tiles land on the same XCD
-// (gfx950 dispatches workgroups round-robin over its 8 XCDs), and tiles are
-// ordered down a column of C first, so one XCD's L2 keeps reusing the same
-// B columns.
+// Block ids are remapped so that each XCD (gfx950 dispatches workgroups
+// round-robin over its 8 XCDs) receives a contiguous range of tiles, and
+// that range is walked in groups of 8 tile rows: the ~64 workgroups resident
+// on one XCD then cover an 8 x 8 block of C tiles and share 8 row panels of
+// A and 8 column panels of B through the XCD's L2, instead of streaming a
+// different A panel per workgroup.
 #include "internal.h"
 
 namespace rbt {
@@ -32,8 +34,10 @@ namespace rbt {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 
 constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int GM = 8;    // tile rows per ordering group
 constexpr int PADA = 4;  // As row stride BM + 4 doubles
 constexpr int PADB = 1;  // Bs row stride BK + 1 doubles (odd: conflict-free column reads)
 
@@ -83,11 +87,17 @@ __global__ void __launch_bounds__(256, 2)
   __shared__ double As[2][BK][BM + PADA];
   __shared__ double Bs[2][BN][BK + PADB];
 
-  // XCD-aware remap, then column-major tile order
+  // XCD-aware remap, then grouped tile order (groups of GM tile rows,
+  // column-major inside a group)
   int pid = blockIdx.x;
   const int full = (total / 8) * 8;
   if (pid < full) pid = (pid % 8) * (total / 8) + pid / 8;
-  const int tm = pid % tiles_m, tn = pid / tiles_m;
+  const int tiles_n = total / tiles_m;
+  const int group = pid / (GM * tiles_n);
+  const int first_m = group * GM;
+  const int gsize = (tiles_m - first_m) < GM ? (tiles_m - first_m) : GM;
+  const int in_group = pid - group * GM * tiles_n;
+  const int tm = first_m + in_group % gsize, tn = in_group / gsize;
   const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
 
   const int tid = threadIdx.x;
@@ -107,7 +117,33 @@ __global__ void __launch_bounds__(256, 2)
   // B: column n = tid / 2, k = 8 (tid % 2) + 0..7
   double ra[8], rb[8];
 
+  // Interior tiles of the plain product take unguarded 16-byte loads (the
+  // operands are only 8-byte aligned in general, which these loads accept);
+  // edge tiles and the last, partial K slice take the guarded path.
+  const bool interior = (OA == OpA::General) && (OB == OpB::General) && (m0 + BM <= M) &&
+                        (n0 + BN <= N);
+  auto load_stage_fast = [&](int64_t k0) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int64_t k = k0 + (tid >> 6) + 4 * p;
+      const d2u v = *reinterpret_cast<const d2u *>(A + (m0 + 2 * (tid & 63)) + k * lda);
+      ra[2 * p] = v[0];
+      ra[2 * p + 1] = v[1];
+    }
+    const double *bp = B + (k0 + 8 * (tid & 1)) + (n0 + (tid >> 1)) * ldb;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const d2u v = *reinterpret_cast<const d2u *>(bp + 2 * p);
+      rb[2 * p] = v[0];
+      rb[2 * p + 1] = v[1];
+    }
+  };
+
   auto load_stage = [&](int64_t k0) {
+    if (interior && k0 + BK <= K) {
+      load_stage_fast(k0);
+      return;
+    }
     if constexpr (a_m_contiguous<OA>()) {
 #pragma unroll
       for (int p = 0; p < 4; ++p) {

@@ -44,6 +44,24 @@ constexpr bool forward_order() {
   return MODE == TriMode::LN || MODE == TriMode::UT;
 }
 
+// (I, J) of staged block b: lower triangle enumerated row by row
+// (b = I (I + 1) / 2 + J, J <= I); the upper triangle is its transpose.
+struct BlockIJ {
+  int i[NTRI], j[NTRI];
+};
+constexpr BlockIJ lower_blocks() {
+  BlockIJ t{};
+  int b = 0;
+  for (int I = 0; I < NBK; ++I)
+    for (int J = 0; J <= I; ++J) {
+      t.i[b] = I;
+      t.j[b] = J;
+      ++b;
+    }
+  return t;
+}
+__constant__ constexpr BlockIJ kLower = lower_blocks();
+
 // Index of block (I, J) of the staged triangle: lower (I >= J) for the
 // forward modes, upper (I <= J) otherwise.
 template <bool LOWER>
@@ -61,23 +79,55 @@ __device__ __forceinline__ double op_t(const double *T, int64_t ldt, int i, int 
 }
 
 // Stage the triangle of op(T) blocks into LDS, each block column-major
-// (element (r, c) at c * 16 + r); entries at or beyond kb are zero.
+// (element (r, c) at c * 16 + r); entries at or beyond kb are zero. Loads
+// are issued in batches of 12 blocks before any is stored.
 template <TriMode MODE>
 __device__ void stage_left(const double *T, int64_t ldt, int kb, double *tri) {
   constexpr bool LOWER = forward_order<MODE>();
-  for (int b = 0; b < NTRI; ++b) {
-    // invert tri_index for this block
-    int I = 0, J = 0;
-    if (LOWER) {
-      while ((I + 1) * (I + 2) / 2 <= b) ++I;
-      J = b - I * (I + 1) / 2;
-    } else {
-      while ((J + 1) * (J + 2) / 2 <= b) ++J;
-      I = b - J * (J + 1) / 2;
+  const int r = threadIdx.x % IB, c = threadIdx.x / IB;  // 256 threads = one block
+#pragma unroll
+  for (int b0 = 0; b0 < NTRI; b0 += 12) {
+    double v[12];
+#pragma unroll
+    for (int u = 0; u < 12; ++u) {
+      const int b = b0 + u;
+      const int I = LOWER ? kLower.i[b] : kLower.j[b];
+      const int J = LOWER ? kLower.j[b] : kLower.i[b];
+      const int i = IB * I + r, j = IB * J + c;
+      v[u] = (i < kb && j < kb) ? op_t<MODE>(T, ldt, i, j) : 0.0;
     }
-    const int r = threadIdx.x % IB, c = threadIdx.x / IB;  // 256 threads = one block
-    const int i = IB * I + r, j = IB * J + c;
-    tri[b * BLK + c * IB + r] = (i < kb && j < kb) ? op_t<MODE>(T, ldt, i, j) : 0.0;
+#pragma unroll
+    for (int u = 0; u < 12; ++u) tri[(b0 + u) * BLK + c * IB + r] = v[u];
+  }
+}
+
+// Load / store a wavefront's 128 x 16 strip of B (column c at strip[row * 16 + c]).
+__device__ __forceinline__ void strip_load(double *strip, const double *B, int64_t ldb, int kb,
+                                           int64_t col0, int64_t N, int lane) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    double v[16];
+#pragma unroll
+    for (int c = 0; c < IB; ++c) {
+      const int row = lane + 64 * h;
+      const int64_t col = col0 + c;
+      v[c] = (row < kb && col < N) ? B[row + col * ldb] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < IB; ++c) strip[(lane + 64 * h) * IB + c] = v[c];
+  }
+}
+
+__device__ __forceinline__ void strip_store(const double *strip, double *B, int64_t ldb, int kb,
+                                            int64_t col0, int64_t N, int lane) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int c = 0; c < IB; ++c) {
+      const int row = lane + 64 * h;
+      const int64_t col = col0 + c;
+      if (row < kb && col < N) B[row + col * ldb] = strip[row * IB + c];
+    }
   }
 }
 
@@ -93,11 +143,7 @@ __global__ void __launch_bounds__(256) k_trsm_left(int kb, int64_t N, const doub
   const int64_t col0 = int64_t(blockIdx.x) * 64 + wave * 16;
 
   stage_left<MODE>(T, ldt, kb, tri);
-  for (int idx = lane; idx < NB * IB; idx += 64) {
-    const int row = idx % NB, c = idx / NB;
-    const int64_t col = col0 + c;
-    strip[row * IB + c] = (row < kb && col < N) ? B[row + col * ldb] : 0.0;
-  }
+  strip_load(strip, B, ldb, kb, col0, N, lane);
   __syncthreads();
 
   const int nbk = (kb + IB - 1) / IB;
@@ -152,11 +198,7 @@ __global__ void __launch_bounds__(256) k_trsm_left(int kb, int64_t N, const doub
     __syncthreads();
   }
 
-  for (int idx = lane; idx < NB * IB; idx += 64) {
-    const int row = idx % NB, c = idx / NB;
-    const int64_t col = col0 + c;
-    if (row < kb && col < N) B[row + col * ldb] = strip[row * IB + c];
-  }
+  strip_store(strip, B, ldb, kb, col0, N, lane);
 }
 
 constexpr int RS = NB + 1;  // row stride of the right-solve strip (odd: conflict-free)
@@ -170,18 +212,36 @@ __global__ void __launch_bounds__(256) k_trsm_right_upper(int kb, int64_t M, con
   double *strip = strip_all[wave];
   const int64_t row0 = int64_t(blockIdx.x) * 64 + wave * 16;
 
-  for (int b = 0; b < NTRI; ++b) {
-    int J = 0;
-    while ((J + 1) * (J + 2) / 2 <= b) ++J;
-    const int I = b - J * (J + 1) / 2;
+  {
     const int r = threadIdx.x % IB, c = threadIdx.x / IB;
-    const int i = IB * I + r, j = IB * J + c;
-    tri[b * BLK + r * IB + c] = (i < kb && j < kb) ? T[i + int64_t(j) * ldt] : 0.0;
+#pragma unroll
+    for (int b0 = 0; b0 < NTRI; b0 += 12) {
+      double v[12];
+#pragma unroll
+      for (int u = 0; u < 12; ++u) {
+        const int b = b0 + u;  // upper block (I, J) = transpose of lower entry b
+        const int i = IB * kLower.j[b] + r, j = IB * kLower.i[b] + c;
+        v[u] = (i < kb && j < kb) ? T[i + int64_t(j) * ldt] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 12; ++u) tri[(b0 + u) * BLK + r * IB + c] = v[u];
+    }
   }
-  for (int idx = lane; idx < IB * NB; idx += 64) {
-    const int r = idx % IB, c = idx / IB;
+  {
+    // strip: 16 rows x 128 columns; lane = (row = lane % 16, column group lane / 16)
+    const int r = lane % IB, cg = lane / IB;
     const int64_t row = row0 + r;
-    strip[r * RS + c] = (row < M && c < kb) ? B[row + int64_t(c) * ldb] : 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int c = cg + 4 * (16 * h + u);
+        v[u] = (row < M && c < kb) ? B[row + int64_t(c) * ldb] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) strip[r * RS + cg + 4 * (16 * h + u)] = v[u];
+    }
   }
   __syncthreads();
 
@@ -224,10 +284,14 @@ __global__ void __launch_bounds__(256) k_trsm_right_upper(int kb, int64_t M, con
     __syncthreads();
   }
 
-  for (int idx = lane; idx < IB * NB; idx += 64) {
-    const int r = idx % IB, c = idx / IB;
+  {
+    const int r = lane % IB, cg = lane / IB;
     const int64_t row = row0 + r;
-    if (row < M && c < kb) B[row + int64_t(c) * ldb] = strip[r * RS + c];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int c = cg + 4 * u;
+      if (row < M && c < kb) B[row + int64_t(c) * ldb] = strip[r * RS + c];
+    }
   }
 }
 
