@@ -99,7 +99,7 @@ int rbt_transform2(int64_t n, const double *A, int64_t lda, void *Out, int64_t l
 int rbt_transform_vec(int64_t n, int64_t nrhs, double *B, int64_t ldb, const double *dC, int depth,
                       int op, void *stream);
 
-/* Workspace (bytes) needed by rbt_solve_ex / rbt_solve_refine /
+/* Workspace (bytes) needed by rbt_getrs / rbt_solve_ex / rbt_solve_refine /
  * rbt_backward_error for these sizes and precision (0 for invalid
  * arguments). */
 size_t rbt_workspace_size(int64_t n, int64_t nrhs, int depth, int precision);
@@ -113,9 +113,12 @@ size_t rbt_workspace_size(int64_t n, int64_t nrhs, int depth, int precision);
 int rbt_genp(int64_t n, double *A, int64_t lda, int32_t *info_dev, void *stream);
 
 /* Device. Solve with the factors of rbt_genp: trans = 0: B <- (L U)^-1 B;
- * trans = 1: B <- (L U)^-T B. B: n x nrhs FP64 (ldb), in place. */
+ * trans = 1: B <- (L U)^-T B. B: n x nrhs FP64 (ldb), in place.
+ * work: device scratch of rbt_workspace_size(n, nrhs, 0, RBT_FP64) bytes
+ * (for nrhs <= 16 it receives the inverses of the 128 x 128 diagonal blocks,
+ * which the solve applies with one step of refinement per block). */
 int rbt_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu, double *B, int64_t ldb,
-              int trans, void *stream);
+              int trans, void *work, size_t work_bytes, void *stream);
 
 /* Device. The whole method (Eq. 1): A (n x n, lda) is overwritten by the
  * L\U factors of A~ = U^T A V, B (n x nrhs, ldb) by X = A^-1 B. Coefficients
@@ -154,7 +157,7 @@ int rbt_backward_error(int64_t n, int64_t nrhs, const double *A, int64_t lda, co
 
 /* Tuning options (process-wide; not thread safe).
  * RBT_OPT_OUTER_NB: width of the panels of the elimination whose trailing
- *   update is a single GEMM (multiple of 128, 128..2048; default 512). The
+ *   update is a single GEMM (multiple of 128, 128..2048; default 1024). The
  *   diagonal blocks are always 128 x 128. Changes only the order of the
  *   roundings, not the method. */
 #define RBT_OPT_OUTER_NB 1

@@ -29,7 +29,7 @@ SIGNATURES = {
     "rbt_transform_vec": (i32, [i64, i64, vp, i64, vp, i32, i32, vp]),
     "rbt_workspace_size": (sz, [i64, i64, i32, i32]),
     "rbt_genp": (i32, [i64, vp, i64, vp, vp]),
-    "rbt_getrs": (i32, [i64, i64, vp, i64, vp, i64, i32, vp]),
+    "rbt_getrs": (i32, [i64, i64, vp, i64, vp, i64, i32, vp, sz, vp]),
     "rbt_solve_ex": (i32, [i64, i64, vp, i64, vp, i64, i32, u64, vp, vp, sz, vp]),
     "rbt_solve": (i32, [i64, i64, vp, i64, vp, i64, i32, u64, vp]),
     "rbt_solve_refine": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, u64, dbl, i32,

@@ -62,19 +62,23 @@ namespace {
 
 inline int64_t nblocks(int64_t n) { return (n + kNB - 1) / kNB; }
 
-// Workspace layout of the composite entry points.
+// Workspace layout of the composite entry points. The inverses of the
+// diagonal blocks (for the few-right-hand-side solves) come first, so that
+// rbt_getrs and the composite entry points agree on where they live.
 struct Layout {
-  size_t coef, resid, partial, small, total;
-  size_t o_coef, o_resid, o_partial, o_small;
+  size_t winv, coef, resid, partial, small, total;
+  size_t o_winv, o_coef, o_resid, o_partial, o_small;
 };
 
 Layout layout(int64_t n, int64_t nrhs, int d) {
   Layout L{};
+  L.winv = align256(size_t(diag_inv_doubles(n)) * sizeof(double));
   L.coef = align256(size_t(2) * n * d * sizeof(double));
   L.resid = align256(size_t(n) * nrhs * sizeof(double));
   L.partial = align256(resid_scratch_doubles(n, nrhs) * sizeof(double));
   L.small = 512;
-  L.o_coef = 0;
+  L.o_winv = 0;
+  L.o_coef = L.o_winv + L.winv;
   L.o_resid = L.o_coef + L.coef;
   L.o_partial = L.o_resid + L.resid;
   L.o_small = L.o_partial + L.partial;
@@ -91,7 +95,7 @@ inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Tunable options (rbt_set_option).
 struct Options {
-  int64_t outer_nb = 512;  // width of the panel whose trailing update is one GEMM
+  int64_t outer_nb = 1024;  // width of the panel whose trailing update is one GEMM
 };
 Options &options() {
   static Options o;
@@ -167,16 +171,22 @@ int genp_fp64(int64_t n, double *A, int64_t lda, int32_t *info, hipStream_t s) {
 // diagonal blocks (k_trsm.hip) and updates of the remaining rows, by the
 // FMA kernel for few right-hand sides and the matrix-core GEMM otherwise.
 int getrs_fp64(int64_t n, int64_t nrhs, const double *LU, int64_t ld, double *B, int64_t ldb,
-               int trans, hipStream_t s) {
+               int trans, const double *winv, hipStream_t s) {
   if (n == 0 || nrhs == 0) return 0;
+  if (nrhs <= kSkinnyMax) {
+    // one fused launch per diagonal block: inverse + one refinement step
+    RBT_HIP_CHECK(launch_trsv_sweep(trans ? TriMode::UT : TriMode::LN, n, nrhs, LU, ld, winv, B,
+                                    ldb, s));
+    RBT_HIP_CHECK(launch_trsv_sweep(trans ? TriMode::LT : TriMode::UN, n, nrhs, LU, ld, winv, B,
+                                    ldb, s));
+    return 0;
+  }
   const int64_t nb = nblocks(n);
-  const bool skinny = nrhs <= kSkinnyMax;
   auto kb_of = [&](int64_t blk) { return int(n - blk * kNB < kNB ? n - blk * kNB : kNB); };
-  // Y (M x nrhs) -= op(A) (M x kb) X (kb x nrhs)
+  // Y (M x nrhs) -= op(A) (M x kb) X (kb x nrhs) on the matrix cores
   auto update = [&](int64_t M, int kb, const double *Ab, bool tr, const double *X,
                     double *Y) -> hipError_t {
     if (M <= 0) return hipSuccess;
-    if (skinny) return launch_skinny_update(M, nrhs, kb, Ab, ld, tr, X, ldb, Y, ldb, s);
     return launch_dgemm(M, nrhs, kb, Ab, ld, tr ? OpA::GeneralT : OpA::General, X, ldb,
                         OpB::General, Y, ldb, Acc::Subtract, s);
   };
@@ -231,9 +241,17 @@ hipError_t transform_vec_t(const Geometry &g, int64_t nrhs, double *B, int64_t l
   return launch_transform_vec(g, nrhs, B, ldb, C, op, s);
 }
 int getrs_t(int64_t n, int64_t nrhs, const double *LU, int64_t ld, double *B, int64_t ldb,
-            int trans, hipStream_t s) {
+            int trans, const double *winv, hipStream_t s) {
   StageScope t(kStageSolve, s, 2.0 * double(n) * n * nrhs);
-  return getrs_fp64(n, nrhs, LU, ld, B, ldb, trans, s);
+  return getrs_fp64(n, nrhs, LU, ld, B, ldb, trans, winv, s);
+}
+// Inverses of the diagonal blocks, needed by the few-right-hand-side solves.
+int diag_inverses_t(int64_t n, int64_t nrhs, const double *LU, int64_t ld, double *winv,
+                    hipStream_t s) {
+  if (nrhs > kSkinnyMax || n == 0) return 0;
+  StageScope t(kStageSolve, s, 2.0 / 3.0 * double(n) * kNB * kNB);
+  RBT_HIP_CHECK(launch_diag_inverses(n, LU, ld, winv, s));
+  return 0;
 }
 
 bool bad_depth(int d) { return d < 0 || d > RBT_MAX_DEPTH; }
@@ -298,7 +316,7 @@ extern "C" int rbt_genp(int64_t n, double *A, int64_t lda, int32_t *info_dev, vo
 }
 
 extern "C" int rbt_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu, double *B,
-                         int64_t ldb, int trans, void *stream) {
+                         int64_t ldb, int trans, void *work, size_t work_bytes, void *stream) {
   if (n < 0) return -1;
   if (nrhs < 0) return -2;
   if (n > 0 && LU == nullptr) return -3;
@@ -306,7 +324,14 @@ extern "C" int rbt_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu
   if (n > 0 && nrhs > 0 && B == nullptr) return -5;
   if (ldb < (n > 1 ? n : 1)) return -6;
   if (trans != 0 && trans != 1) return -7;
-  return getrs_fp64(n, nrhs, LU, ldlu, B, ldb, trans, S(stream));
+  const Layout L = layout(n, nrhs, 0);
+  if (n > 0 && work == nullptr) return -8;
+  if (work_bytes < L.winv) return RBT_ERR_WORKSPACE;
+  hipStream_t s = S(stream);
+  double *winv = at<double>(work, L.o_winv);
+  int rc = diag_inverses_t(n, nrhs, LU, ldlu, winv, s);
+  if (rc) return rc;
+  return getrs_fp64(n, nrhs, LU, ldlu, B, ldb, trans, winv, s);
 }
 
 extern "C" int rbt_solve_ex(int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_t ldb,
@@ -330,9 +355,12 @@ extern "C" int rbt_solve_ex(int64_t n, int64_t nrhs, double *A, int64_t lda, dou
   RBT_HIP_CHECK(generate_t(n, depth, seed, U, V, s));
   RBT_HIP_CHECK(transform2_t(g, A, lda, A, lda, RBT_FP64, U, V, s));
   RBT_HIP_CHECK(transform_vec_t(g, nrhs, B, ldb, U, RBT_OP_T, s));
+  double *winv = at<double>(work, L.o_winv);
   int rc = genp_fp64(n, A, lda, info_dev, s);
   if (rc) return rc;
-  rc = getrs_t(n, nrhs, A, lda, B, ldb, 0, s);
+  rc = diag_inverses_t(n, nrhs, A, lda, winv, s);
+  if (rc) return rc;
+  rc = getrs_t(n, nrhs, A, lda, B, ldb, 0, winv, s);
   if (rc) return rc;
   RBT_HIP_CHECK(transform_vec_t(g, nrhs, B, ldb, V, RBT_OP_N, s));
   return 0;
@@ -412,11 +440,14 @@ extern "C" int rbt_solve_refine(int64_t n, int64_t nrhs, const double *A, int64_
 
   RBT_HIP_CHECK(generate_t(n, depth, seed, U, V, s));
   RBT_HIP_CHECK(transform2_t(g, A, lda, LU, ldlu, RBT_FP64, U, V, s));
+  double *winv = at<double>(work, L.o_winv);
   int rc = genp_fp64(n, LU, ldlu, info_dev, s);
+  if (rc) return rc;
+  rc = diag_inverses_t(n, nrhs, LU, ldlu, winv, s);
   if (rc) return rc;
   RBT_HIP_CHECK(launch_copy_cols(n, nrhs, B, ldb, X, ldx, s));
   RBT_HIP_CHECK(transform_vec_t(g, nrhs, X, ldx, U, RBT_OP_T, s));
-  rc = getrs_t(n, nrhs, LU, ldlu, X, ldx, 0, s);
+  rc = getrs_t(n, nrhs, LU, ldlu, X, ldx, 0, winv, s);
   if (rc) return rc;
   RBT_HIP_CHECK(transform_vec_t(g, nrhs, X, ldx, V, RBT_OP_N, s));
 
@@ -433,7 +464,7 @@ extern "C" int rbt_solve_refine(int64_t n, int64_t nrhs, const double *A, int64_
     RBT_HIP_CHECK(hipStreamSynchronize(s));
     if (be_host <= tol) break;
     RBT_HIP_CHECK(transform_vec_t(g, nrhs, R, n, U, RBT_OP_T, s));
-    rc = getrs_t(n, nrhs, LU, ldlu, R, n, 0, s);
+    rc = getrs_t(n, nrhs, LU, ldlu, R, n, 0, winv, s);
     if (rc) return rc;
     RBT_HIP_CHECK(transform_vec_t(g, nrhs, R, n, V, RBT_OP_N, s));
     RBT_HIP_CHECK(launch_axpy_cols(n, nrhs, R, n, X, ldx, s));

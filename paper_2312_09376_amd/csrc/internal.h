@@ -108,6 +108,12 @@ hipError_t launch_trsm_left(TriMode mode, int kb, int64_t N, const double *T, in
 // X U = B in place, B: M x kb
 hipError_t launch_trsm_right_upper(int kb, int64_t M, const double *T, int64_t ldt, double *B,
                                    int64_t ldb, hipStream_t s);
+// Inverses of all kNB x kNB diagonal blocks of the factors of an n x n
+// elimination: block b's L^-1 at W + b * 2 kNB^2 and U^-1 at
+// W + b * 2 kNB^2 + kNB^2 (ld kNB). Needs diag_inv_doubles(n) doubles.
+hipError_t launch_diag_inverses(int64_t n, const double *LU, int64_t ld, double *W,
+                                hipStream_t s);
+inline int64_t diag_inv_doubles(int64_t n) { return ((n + kNB - 1) / kNB) * 2 * kNB * kNB; }
 
 // k_solve.hip
 constexpr int64_t kSkinnyMax = 16;  // right-hand sides handled by the FMA kernels
@@ -115,6 +121,10 @@ constexpr int64_t kSkinnyMax = 16;  // right-hand sides handled by the FMA kerne
 hipError_t launch_skinny_update(int64_t M, int64_t N, int K, const double *A, int64_t lda,
                                 bool trans, const double *X, int64_t ldx, double *Y, int64_t ldy,
                                 hipStream_t s);
+// Triangular sweep with op(A) of the factors for nrhs <= kSkinnyMax, using
+// the diagonal-block inverses of launch_diag_inverses (one launch per block).
+hipError_t launch_trsv_sweep(TriMode mode, int64_t n, int64_t nrhs, const double *LU, int64_t ld,
+                             const double *Winv, double *B, int64_t ldb, hipStream_t s);
 // doubles of scratch needed by launch_residual_berr
 size_t resid_scratch_doubles(int64_t n, int64_t nrhs);
 // R = B - A X; berr = Eq. 7 (max over columns); with_anorm: also ||A||_inf -> *anorm

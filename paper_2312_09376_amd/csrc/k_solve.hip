@@ -46,6 +46,166 @@ __global__ void __launch_bounds__(kRows) k_skinny_update(int64_t M, int N, int K
     if (n < N) Y[m + int64_t(n) * ldy] -= acc[n];
 }
 
+// One step of a blocked triangular sweep for few right-hand sides
+// (N <= NMAX), used by the solves after the elimination. Block `cur` of the
+// solution is final (cur < 0: none yet); this launch
+//   - workgroup 0: subtracts block cur's contribution from block `nxt` and
+//     solves block nxt with the precomputed inverse of its diagonal block and
+//     one step of refinement, x = Di r, x += Di (r - T x), which keeps the
+//     backward error of substitution (the inverse alone does not);
+//   - workgroups 1..: subtract block cur's contribution from the rows beyond
+//     block nxt (below it for forward sweeps, above it for backward ones).
+// op(A)(m, k) of the four sweeps, A = the L\U factors (ld):
+//   LN L (forward), UN U (backward), UT U^T (forward), LT L^T (backward).
+// Dinv: LN L^-1, UN U^-1 (stored), UT (U^-1)^T, LT (L^-1)^T (read transposed).
+template <TriMode MODE>
+__device__ __forceinline__ double op_a(const double *A, int64_t ld, int64_t m, int64_t k) {
+  if constexpr (MODE == TriMode::LN || MODE == TriMode::UN)
+    return A[m + k * ld];
+  else
+    return A[k + m * ld];
+}
+
+template <int NMAX, TriMode MODE>
+__global__ void __launch_bounds__(kRows) k_trsv_step(int64_t n, int N, const double *A,
+                                                     int64_t ld, const double *Winv, double *B,
+                                                     int64_t ldb, int64_t cur, int64_t nxt) {
+  constexpr bool FWD = (MODE == TriMode::LN || MODE == TriMode::UT);
+  constexpr bool UNIT = (MODE == TriMode::LN || MODE == TriMode::LT);
+  constexpr int H = kNB / 2;  // each half-workgroup covers 64 of the 128 columns
+  __shared__ double xs[kNB][NMAX];        // block cur of the solution
+  __shared__ double vs[kNB][NMAX];        // operand vector of the current product
+  __shared__ double part[2][kNB][NMAX];   // half sums
+  const int t = threadIdx.x;
+  const int64_t c0 = cur * kNB;
+  const int cb = cur < 0 ? 0 : int(n - c0 < kNB ? n - c0 : kNB);
+  for (int idx = t; idx < kNB * NMAX; idx += kRows) {
+    const int k = idx / NMAX, c = idx % NMAX;
+    xs[k][c] = (k < cb && c < N) ? B[(c0 + k) + int64_t(c) * ldb] : 0.0;
+  }
+  __syncthreads();
+
+  if (blockIdx.x > 0) {
+    // rows beyond block nxt: B[m] -= op(A)[m, block cur] x_cur
+    int64_t m;
+    if (FWD) {
+      m = (nxt + 1) * kNB + int64_t(blockIdx.x - 1) * kRows + t;
+      if (m >= n) return;
+    } else {
+      m = int64_t(blockIdx.x - 1) * kRows + t;
+      if (m >= nxt * kNB) return;
+    }
+    double acc[NMAX];
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) acc[c] = 0.0;
+#pragma unroll 16
+    for (int k = 0; k < kNB; ++k) {
+      const double a = (k < cb) ? op_a<MODE>(A, ld, m, c0 + k) : 0.0;
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) acc[c] += a * xs[k][c];
+    }
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c)
+      if (c < N) B[m + int64_t(c) * ldb] -= acc[c];
+    return;
+  }
+
+  // ---- workgroup 0: block nxt ----
+  const int64_t r0 = nxt * kNB;
+  const int kb = int(n - r0 < kNB ? n - r0 : kNB);
+  const double *Di = Winv + nxt * 2 * kNB * kNB +
+                     ((MODE == TriMode::LN || MODE == TriMode::LT) ? 0 : kNB * kNB);
+  const int i = t & (kNB - 1), h = t >> 7;  // row, column half
+  const bool row = i < kb;
+  // Half-sum of a 128 x 128 product with vector vec (LDS), entry(i, j) given.
+  auto half_product = [&](auto entry, const double (*vec)[NMAX]) {
+    double acc[NMAX];
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) acc[c] = 0.0;
+    auto chunk = [&](int q) {  // a batch of 16 independent loads
+      double e[16];
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) e[jj] = entry(i, H * h + q + jj);
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj)
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c) acc[c] += e[jj] * vec[H * h + q + jj][c];
+    };
+    if constexpr (NMAX == 1) {
+#pragma unroll
+      for (int q = 0; q < H; q += 16) chunk(q);
+    } else {
+#pragma nounroll
+      for (int q = 0; q < H; q += 16) chunk(q);
+    }
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) part[h][i][c] = acc[c];
+  };
+  // product entries (zero outside the valid block / triangle)
+  auto e_cross = [&](int ii, int jj) -> double {
+    return (ii < kb && jj < cb) ? op_a<MODE>(A, ld, r0 + ii, c0 + jj) : 0.0;
+  };
+  auto e_dinv = [&](int ii, int jj) -> double {
+    if (ii >= kb || jj >= kb) return 0.0;
+    return (MODE == TriMode::LN || MODE == TriMode::UN) ? Di[ii + jj * kNB] : Di[jj + ii * kNB];
+  };
+  auto e_tdiag = [&](int ii, int jj) -> double {
+    if (ii >= kb || jj >= kb) return 0.0;
+    if (ii == jj) return UNIT ? 1.0 : op_a<MODE>(A, ld, r0 + ii, r0 + jj);
+    if (FWD ? (jj > ii) : (jj < ii)) return 0.0;
+    return op_a<MODE>(A, ld, r0 + ii, r0 + jj);
+  };
+
+  // r = b - op(A)[nxt, cur] x_cur  -> vs
+  half_product(e_cross, xs);
+  __syncthreads();
+  double r[NMAX];
+  if (h == 0) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) {
+      const double bv = (row && c < N) ? B[(r0 + i) + int64_t(c) * ldb] : 0.0;
+      r[c] = bv - (part[0][i][c] + part[1][i][c]);
+      vs[i][c] = r[c];
+    }
+  }
+  __syncthreads();
+  // x = Di r
+  half_product(e_dinv, vs);
+  __syncthreads();
+  double x[NMAX];
+  if (h == 0) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) x[c] = part[0][i][c] + part[1][i][c];
+  }
+  __syncthreads();
+  if (h == 0) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) vs[i][c] = x[c];
+  }
+  __syncthreads();
+  // res = r - T x
+  half_product(e_tdiag, vs);
+  __syncthreads();
+  if (h == 0) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) r[c] -= part[0][i][c] + part[1][i][c];
+  }
+  __syncthreads();
+  if (h == 0) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) vs[i][c] = r[c];
+  }
+  __syncthreads();
+  // x += Di res
+  half_product(e_dinv, vs);
+  __syncthreads();
+  if (h == 0 && row) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c)
+      if (c < N) B[(r0 + i) + int64_t(c) * ldb] = x[c] + (part[0][i][c] + part[1][i][c]);
+  }
+}
+
 // partial[(c N + n) M + m] = sum_{k in chunk c} A[m, k] X[k, n];
 // ABS: abspart[c M + m] = sum_{k in chunk c} |A[m, k]|.
 template <int NMAX, bool ABS>
@@ -323,7 +483,45 @@ hipError_t resid_t(int64_t n, int N, const double *A, int64_t lda, const double 
   return hipGetLastError();
 }
 
+template <int NMAX, TriMode MODE>
+hipError_t trsv_sweep_t(int64_t n, int N, const double *LU, int64_t ld, const double *Winv,
+                        double *B, int64_t ldb, hipStream_t s) {
+  constexpr bool FWD = (MODE == TriMode::LN || MODE == TriMode::UT);
+  const int64_t nb = (n + kNB - 1) / kNB;
+  for (int64_t i = 0; i < nb; ++i) {
+    const int64_t nxt = FWD ? i : nb - 1 - i;
+    const int64_t cur = i == 0 ? -1 : (FWD ? nxt - 1 : nxt + 1);
+    const int64_t rest = FWD ? (n - (nxt + 1) * kNB) : nxt * kNB;  // rows beyond block nxt
+    const int64_t extra = (cur < 0 || rest <= 0) ? 0 : (rest + kRows - 1) / kRows;
+    hipLaunchKernelGGL((k_trsv_step<NMAX, MODE>), dim3(unsigned(1 + extra)), dim3(kRows), 0, s, n,
+                       N, LU, ld, Winv, B, ldb, cur, nxt);
+  }
+  return hipGetLastError();
+}
+
+template <int NMAX>
+hipError_t trsv_sweep_n(TriMode mode, int64_t n, int N, const double *LU, int64_t ld,
+                        const double *Winv, double *B, int64_t ldb, hipStream_t s) {
+  switch (mode) {
+    case TriMode::LN: return trsv_sweep_t<NMAX, TriMode::LN>(n, N, LU, ld, Winv, B, ldb, s);
+    case TriMode::UN: return trsv_sweep_t<NMAX, TriMode::UN>(n, N, LU, ld, Winv, B, ldb, s);
+    case TriMode::UT: return trsv_sweep_t<NMAX, TriMode::UT>(n, N, LU, ld, Winv, B, ldb, s);
+    default: return trsv_sweep_t<NMAX, TriMode::LT>(n, N, LU, ld, Winv, B, ldb, s);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_trsv_sweep(TriMode mode, int64_t n, int64_t nrhs, const double *LU, int64_t ld,
+                             const double *Winv, double *B, int64_t ldb, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return hipSuccess;
+  if (nrhs > kSkinnyMax) return hipErrorInvalidValue;
+  const int N = int(nrhs);
+  if (N <= 1) return trsv_sweep_n<1>(mode, n, N, LU, ld, Winv, B, ldb, s);
+  if (N <= 4) return trsv_sweep_n<4>(mode, n, N, LU, ld, Winv, B, ldb, s);
+  if (N <= 8) return trsv_sweep_n<8>(mode, n, N, LU, ld, Winv, B, ldb, s);
+  return trsv_sweep_n<16>(mode, n, N, LU, ld, Winv, B, ldb, s);
+}
 
 size_t resid_scratch_doubles(int64_t n, int64_t nrhs) {
   const int64_t chunks = (n + kChunk - 1) / kChunk;

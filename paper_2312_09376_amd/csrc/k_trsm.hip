@@ -3,13 +3,14 @@
 // blocks already solved runs on the FP64 matrix cores, and each 16 x 16
 // diagonal block is solved by plain substitution (one lane per right-hand
 // side), so the rounding behaviour is that of ordinary forward/back
-// substitution. (Multiplying by explicit inverses of the diagonal blocks,
-// even 16 x 16 ones, raised the backward error several-fold on N(0,1)
-// matrices with large growth.)
+// substitution except that a division by a pivot is a multiplication by its
+// reciprocal (within one rounding of the quotient). (Multiplying by explicit
+// inverses of the diagonal blocks, even 16 x 16 ones, raised the backward
+// error several-fold on N(0,1) matrices with large growth.)
 //
-// The triangle of op(T) is first staged in LDS as its 36 16 x 16 blocks, so
-// the serial substitution reads LDS broadcasts instead of waiting on global
-// memory.
+// LDS holds the right-hand-side strips and the eight 16 x 16 diagonal blocks
+// (80 KB, two workgroups per CU); the off-diagonal operands of each step are
+// prefetched from global memory into registers before its MFMA chain.
 //
 // Left solves, op(T) X = B in place (B: kb x N):
 //   LN  T = L (unit lower)     forward  (panel U12 = L11^-1 A12, L y = b)
@@ -17,8 +18,7 @@
 //   UT  T = U^T (lower)        forward  (U^T z = g, adjoint solves)
 //   LT  T = L^T (unit upper)   backward (L^T w = z)
 //   X_I = T_II \ (B_I - sum_{J before I} T_IJ X_J)
-// Each wavefront owns 16 columns of B in an LDS strip; a workgroup of four
-// covers 64 columns.
+// Each wavefront owns 16 columns of B; a workgroup of four covers 64.
 //
 // Right solve, X U = B in place (B: M x kb) for the panel L21 = A21 U11^-1:
 //   X_J = (B_J - sum_{I<J} X_I U_IJ) / U_JJ
@@ -35,38 +35,16 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int NB = kNB;  // 128
 constexpr int IB = 16;
-constexpr int NBK = NB / IB;                 // 8 blocks per side
-constexpr int NTRI = NBK * (NBK + 1) / 2;    // 36 blocks in a triangle
-constexpr int BLK = IB * IB;                 // 256 doubles per block
+constexpr int NBK = NB / IB;  // 8 diagonal blocks
+constexpr int BLK = IB * IB;  // 256 doubles per block
 
 template <TriMode MODE>
 constexpr bool forward_order() {
   return MODE == TriMode::LN || MODE == TriMode::UT;
 }
-
-// (I, J) of staged block b: lower triangle enumerated row by row
-// (b = I (I + 1) / 2 + J, J <= I); the upper triangle is its transpose.
-struct BlockIJ {
-  int i[NTRI], j[NTRI];
-};
-constexpr BlockIJ lower_blocks() {
-  BlockIJ t{};
-  int b = 0;
-  for (int I = 0; I < NBK; ++I)
-    for (int J = 0; J <= I; ++J) {
-      t.i[b] = I;
-      t.j[b] = J;
-      ++b;
-    }
-  return t;
-}
-__constant__ constexpr BlockIJ kLower = lower_blocks();
-
-// Index of block (I, J) of the staged triangle: lower (I >= J) for the
-// forward modes, upper (I <= J) otherwise.
-template <bool LOWER>
-__device__ __forceinline__ int tri_index(int I, int J) {
-  return LOWER ? I * (I + 1) / 2 + J : J * (J + 1) / 2 + I;
+template <TriMode MODE>
+constexpr bool unit_diag() {
+  return MODE == TriMode::LN || MODE == TriMode::LT;
 }
 
 // op(T)(i, j) read from global memory (i, j < kb).
@@ -78,88 +56,86 @@ __device__ __forceinline__ double op_t(const double *T, int64_t ldt, int i, int 
     return T[j + int64_t(i) * ldt];
 }
 
-// Stage the triangle of op(T) blocks into LDS, each block column-major
-// (element (r, c) at c * 16 + r); entries at or beyond kb are zero. Loads
-// are issued in batches of 12 blocks before any is stored.
-template <TriMode MODE>
-__device__ void stage_left(const double *T, int64_t ldt, int kb, double *tri) {
-  constexpr bool LOWER = forward_order<MODE>();
-  const int r = threadIdx.x % IB, c = threadIdx.x / IB;  // 256 threads = one block
-#pragma unroll
-  for (int b0 = 0; b0 < NTRI; b0 += 12) {
-    double v[12];
-#pragma unroll
-    for (int u = 0; u < 12; ++u) {
-      const int b = b0 + u;
-      const int I = LOWER ? kLower.i[b] : kLower.j[b];
-      const int J = LOWER ? kLower.j[b] : kLower.i[b];
-      const int i = IB * I + r, j = IB * J + c;
-      v[u] = (i < kb && j < kb) ? op_t<MODE>(T, ldt, i, j) : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 12; ++u) tri[(b0 + u) * BLK + c * IB + r] = v[u];
+// BATCH: blockIdx.y selects diagonal block b of an n x n factor (T and B
+// offset by b * kNB (1 + ldt) and b * bstride, kb = min(kNB, n - b kNB)), and
+// the right-hand side is the identity (X = op(T_bb)^-1): used to form the
+// inverses of the diagonal blocks once per factorization.
+template <TriMode MODE, bool BATCH>
+__global__ void __launch_bounds__(256, 2) k_trsm_left(int kb, int64_t N, const double *T,
+                                                      int64_t ldt, double *B, int64_t ldb,
+                                                      int64_t n, int64_t bstride) {
+  if constexpr (BATCH) {
+    const int64_t b = blockIdx.y;
+    const int64_t r0 = b * NB;
+    kb = int(n - r0 < NB ? n - r0 : NB);
+    N = kb;
+    T += r0 + r0 * ldt;
+    B += b * bstride;
   }
-}
-
-// Load / store a wavefront's 128 x 16 strip of B (column c at strip[row * 16 + c]).
-__device__ __forceinline__ void strip_load(double *strip, const double *B, int64_t ldb, int kb,
-                                           int64_t col0, int64_t N, int lane) {
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    double v[16];
-#pragma unroll
-    for (int c = 0; c < IB; ++c) {
-      const int row = lane + 64 * h;
-      const int64_t col = col0 + c;
-      v[c] = (row < kb && col < N) ? B[row + col * ldb] : 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < IB; ++c) strip[(lane + 64 * h) * IB + c] = v[c];
-  }
-}
-
-__device__ __forceinline__ void strip_store(const double *strip, double *B, int64_t ldb, int kb,
-                                            int64_t col0, int64_t N, int lane) {
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-#pragma unroll
-    for (int c = 0; c < IB; ++c) {
-      const int row = lane + 64 * h;
-      const int64_t col = col0 + c;
-      if (row < kb && col < N) B[row + col * ldb] = strip[row * IB + c];
-    }
-  }
-}
-
-template <TriMode MODE>
-__global__ void __launch_bounds__(256) k_trsm_left(int kb, int64_t N, const double *T,
-                                                   int64_t ldt, double *B, int64_t ldb) {
-  __shared__ double tri[NTRI * BLK];
-  __shared__ double strip_all[4][NB * IB];
-  constexpr bool LOWER = forward_order<MODE>();
+  __shared__ double dblk[NBK * BLK];        // diagonal blocks of op(T), element (i,j) at j*16+i
+  __shared__ double strip_all[4][NB * IB];  // per wavefront: row-major 128 x 16
+  constexpr bool FWD = forward_order<MODE>();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
   double *strip = strip_all[wave];
   const int64_t col0 = int64_t(blockIdx.x) * 64 + wave * 16;
 
-  stage_left<MODE>(T, ldt, kb, tri);
-  strip_load(strip, B, ldb, kb, col0, N, lane);
+  {  // stage the diagonal blocks (reciprocal on the diagonal of non-unit modes)
+    const int i = threadIdx.x % IB, j = threadIdx.x / IB;
+    double v[NBK];
+#pragma unroll
+    for (int b = 0; b < NBK; ++b) {
+      const int gi = IB * b + i, gj = IB * b + j;
+      v[b] = (gi < kb && gj < kb) ? op_t<MODE>(T, ldt, gi, gj) : (i == j ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int b = 0; b < NBK; ++b) {
+      if (!unit_diag<MODE>() && i == j) v[b] = 1.0 / v[b];
+      dblk[b * BLK + j * IB + i] = v[b];
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {  // strip: lane = row (two halves), 16 columns
+    const int row = lane + 64 * h;
+    double v[IB];
+#pragma unroll
+    for (int c = 0; c < IB; ++c) {
+      const int64_t col = col0 + c;
+      if constexpr (BATCH)
+        v[c] = (row < kb && col < N && row == col) ? 1.0 : 0.0;
+      else
+        v[c] = (row < kb && col < N) ? B[row + col * ldb] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < IB; ++c) strip[row * IB + c] = v[c];
+  }
   __syncthreads();
 
   const int nbk = (kb + IB - 1) / IB;
   for (int step = 0; step < nbk; ++step) {
-    const int I = LOWER ? step : nbk - 1 - step;
-    d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    for (int s2 = 0; s2 < step; ++s2) {
-      const int J = LOWER ? s2 : nbk - 1 - s2;
-      const double *tb = tri + tri_index<LOWER>(I, J) * BLK;
+    const int I = FWD ? step : nbk - 1 - step;
+    const int ia = IB * I + l16;
+    // prefetch this step's off-diagonal operands: op(T)[ia][16 J + 4 kk + lk]
+    double a[NBK - 1][4];
 #pragma unroll
-      for (int kk = 0; kk < 4; kk += 2) {
-        const int k0 = 4 * kk + lk, k1 = 4 * (kk + 1) + lk;
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(tb[k0 * IB + l16],
-                                                    strip[(IB * J + k0) * IB + l16], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(tb[k1 * IB + l16],
-                                                    strip[(IB * J + k1) * IB + l16], acc1, 0, 0, 0);
+    for (int s2 = 0; s2 < NBK - 1; ++s2) {
+      const int J = FWD ? s2 : nbk - 1 - s2;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int kx = IB * J + 4 * kk + lk;
+        a[s2][kk] = (s2 < step && ia < kb && kx < kb) ? op_t<MODE>(T, ldt, ia, kx) : 0.0;
+      }
+    }
+    d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s2 = 0; s2 < NBK - 1; ++s2) {
+      if (s2 < step) {
+        const int J = FWD ? s2 : nbk - 1 - s2;
+        const int k0 = IB * J + lk;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2][0], strip[(k0) * IB + l16], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2][1], strip[(k0 + 4) * IB + l16], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2][2], strip[(k0 + 8) * IB + l16], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2][3], strip[(k0 + 12) * IB + l16], acc1, 0, 0, 0);
       }
     }
 #pragma unroll
@@ -169,15 +145,15 @@ __global__ void __launch_bounds__(256) k_trsm_left(int kb, int64_t N, const doub
     const int bs = kb - IB * I < IB ? kb - IB * I : IB;
     if (lane < IB) {
       const int o = IB * I;
-      const double *tb = tri + tri_index<LOWER>(I, I) * BLK;  // element (i, j) at j*16+i
+      const double *tb = dblk + I * BLK;
       double x[IB];
 #pragma unroll
       for (int i = 0; i < IB; ++i) x[i] = strip[(o + i) * IB + lane];
-      if constexpr (LOWER) {
+      if constexpr (FWD) {
 #pragma unroll
         for (int j = 0; j < IB; ++j) {
           if (j < bs) {
-            if constexpr (MODE == TriMode::UT) x[j] = x[j] / tb[j * IB + j];
+            if constexpr (!unit_diag<MODE>()) x[j] *= tb[j * IB + j];
 #pragma unroll
             for (int i = j + 1; i < IB; ++i) x[i] -= tb[j * IB + i] * x[j];
           }
@@ -186,7 +162,7 @@ __global__ void __launch_bounds__(256) k_trsm_left(int kb, int64_t N, const doub
 #pragma unroll
         for (int j = IB - 1; j >= 0; --j) {
           if (j < bs) {
-            if constexpr (MODE == TriMode::UN) x[j] = x[j] / tb[j * IB + j];
+            if constexpr (!unit_diag<MODE>()) x[j] *= tb[j * IB + j];
 #pragma unroll
             for (int i = 0; i < j; ++i) x[i] -= tb[j * IB + i] * x[j];
           }
@@ -198,15 +174,22 @@ __global__ void __launch_bounds__(256) k_trsm_left(int kb, int64_t N, const doub
     __syncthreads();
   }
 
-  strip_store(strip, B, ldb, kb, col0, N, lane);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int row = lane + 64 * h;
+#pragma unroll
+    for (int c = 0; c < IB; ++c) {
+      const int64_t col = col0 + c;
+      if (row < kb && col < N) B[row + col * ldb] = strip[row * IB + c];
+    }
+  }
 }
 
-constexpr int RS = NB + 1;  // row stride of the right-solve strip (odd: conflict-free)
-
-__global__ void __launch_bounds__(256) k_trsm_right_upper(int kb, int64_t M, const double *T,
-                                                          int64_t ldt, double *B, int64_t ldb) {
-  __shared__ double tri[NTRI * BLK];  // upper blocks of U, each row-major (r * 16 + c)
-  __shared__ double strip_all[4][IB * RS];
+__global__ void __launch_bounds__(256, 2) k_trsm_right_upper(int kb, int64_t M, const double *T,
+                                                             int64_t ldt, double *B,
+                                                             int64_t ldb) {
+  __shared__ double dblk[NBK * BLK];        // diagonal blocks of U, element (r,c) at r*16+c
+  __shared__ double strip_all[4][NB * IB];  // per wavefront: column-major 16 x 128
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
   double *strip = strip_all[wave];
@@ -214,21 +197,20 @@ __global__ void __launch_bounds__(256) k_trsm_right_upper(int kb, int64_t M, con
 
   {
     const int r = threadIdx.x % IB, c = threadIdx.x / IB;
+    double v[NBK];
 #pragma unroll
-    for (int b0 = 0; b0 < NTRI; b0 += 12) {
-      double v[12];
+    for (int b = 0; b < NBK; ++b) {
+      const int gi = IB * b + r, gj = IB * b + c;
+      v[b] = (gi < kb && gj < kb) ? T[gi + int64_t(gj) * ldt] : (r == c ? 1.0 : 0.0);
+    }
 #pragma unroll
-      for (int u = 0; u < 12; ++u) {
-        const int b = b0 + u;  // upper block (I, J) = transpose of lower entry b
-        const int i = IB * kLower.j[b] + r, j = IB * kLower.i[b] + c;
-        v[u] = (i < kb && j < kb) ? T[i + int64_t(j) * ldt] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 12; ++u) tri[(b0 + u) * BLK + r * IB + c] = v[u];
+    for (int b = 0; b < NBK; ++b) {
+      if (r == c) v[b] = 1.0 / v[b];
+      dblk[b * BLK + r * IB + c] = v[b];
     }
   }
   {
-    // strip: 16 rows x 128 columns; lane = (row = lane % 16, column group lane / 16)
+    // lane = (row r = lane % 16, column group lane / 16): columns cg + 4u
     const int r = lane % IB, cg = lane / IB;
     const int64_t row = row0 + r;
 #pragma unroll
@@ -240,46 +222,55 @@ __global__ void __launch_bounds__(256) k_trsm_right_upper(int kb, int64_t M, con
         v[u] = (row < M && c < kb) ? B[row + int64_t(c) * ldb] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u) strip[r * RS + cg + 4 * (16 * h + u)] = v[u];
+      for (int u = 0; u < 16; ++u) strip[(cg + 4 * (16 * h + u)) * IB + r] = v[u];
     }
   }
   __syncthreads();
 
   const int nbk = (kb + IB - 1) / IB;
   for (int J = 0; J < nbk; ++J) {
-    d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    for (int I = 0; I < J; ++I) {
-      const double *tb = tri + tri_index<false>(I, J) * BLK;
+    const int jc = IB * J + l16;  // column of U this lane feeds
+    double b[NBK - 1][4];
 #pragma unroll
-      for (int kk = 0; kk < 4; kk += 2) {
-        const int k0 = 4 * kk + lk, k1 = 4 * (kk + 1) + lk;
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[l16 * RS + IB * I + k0],
-                                                    tb[k0 * IB + l16], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[l16 * RS + IB * I + k1],
-                                                    tb[k1 * IB + l16], acc1, 0, 0, 0);
+    for (int I = 0; I < NBK - 1; ++I) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int kx = IB * I + 4 * kk + lk;
+        b[I][kk] = (I < J && kx < kb && jc < kb) ? T[kx + int64_t(jc) * ldt] : 0.0;
+      }
+    }
+    d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int I = 0; I < NBK - 1; ++I) {
+      if (I < J) {
+        const int k0 = IB * I + lk;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0) * IB + l16], b[I][0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 4) * IB + l16], b[I][1], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 8) * IB + l16], b[I][2], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 12) * IB + l16], b[I][3], acc1, 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) strip[(lk + 4 * v) * RS + IB * J + l16] -= acc0[v] + acc1[v];
+    for (int v = 0; v < 4; ++v) strip[(IB * J + l16) * IB + lk + 4 * v] -= acc0[v] + acc1[v];
     __syncthreads();
     // substitution inside the diagonal block: lane r < 16 owns row r
     const int bs = kb - IB * J < IB ? kb - IB * J : IB;
     if (lane < IB) {
       const int o = IB * J;
-      const double *tb = tri + tri_index<false>(J, J) * BLK;  // element (r, c) at r*16+c
+      const double *tb = dblk + J * BLK;
       double x[IB];
 #pragma unroll
-      for (int c = 0; c < IB; ++c) x[c] = strip[lane * RS + o + c];
+      for (int c = 0; c < IB; ++c) x[c] = strip[(o + c) * IB + lane];
 #pragma unroll
       for (int c = 0; c < IB; ++c) {
         if (c < bs) {
-          x[c] = x[c] / tb[c * IB + c];
+          x[c] *= tb[c * IB + c];
 #pragma unroll
           for (int c2 = c + 1; c2 < IB; ++c2) x[c2] -= x[c] * tb[c * IB + c2];
         }
       }
 #pragma unroll
-      for (int c = 0; c < IB; ++c) strip[lane * RS + o + c] = (c < bs) ? x[c] : 0.0;
+      for (int c = 0; c < IB; ++c) strip[(o + c) * IB + lane] = (c < bs) ? x[c] : 0.0;
     }
     __syncthreads();
   }
@@ -290,7 +281,7 @@ __global__ void __launch_bounds__(256) k_trsm_right_upper(int kb, int64_t M, con
 #pragma unroll
     for (int u = 0; u < 32; ++u) {
       const int c = cg + 4 * u;
-      if (row < M && c < kb) B[row + int64_t(c) * ldb] = strip[r * RS + c];
+      if (row < M && c < kb) B[row + int64_t(c) * ldb] = strip[c * IB + r];
     }
   }
 }
@@ -303,11 +294,25 @@ hipError_t launch_trsm_left(TriMode mode, int kb, int64_t N, const double *T, in
   if (kb > kNB) return hipErrorInvalidValue;
   const dim3 grid(unsigned((N + 63) / 64));
   switch (mode) {
-    case TriMode::LN: hipLaunchKernelGGL(k_trsm_left<TriMode::LN>, grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb); break;
-    case TriMode::UN: hipLaunchKernelGGL(k_trsm_left<TriMode::UN>, grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb); break;
-    case TriMode::UT: hipLaunchKernelGGL(k_trsm_left<TriMode::UT>, grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb); break;
-    case TriMode::LT: hipLaunchKernelGGL(k_trsm_left<TriMode::LT>, grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb); break;
+    case TriMode::LN: hipLaunchKernelGGL((k_trsm_left<TriMode::LN, false>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, int64_t(0), int64_t(0)); break;
+    case TriMode::UN: hipLaunchKernelGGL((k_trsm_left<TriMode::UN, false>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, int64_t(0), int64_t(0)); break;
+    case TriMode::UT: hipLaunchKernelGGL((k_trsm_left<TriMode::UT, false>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, int64_t(0), int64_t(0)); break;
+    case TriMode::LT: hipLaunchKernelGGL((k_trsm_left<TriMode::LT, false>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, int64_t(0), int64_t(0)); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_inverses(int64_t n, const double *LU, int64_t ld, double *W,
+                                hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = (n + NB - 1) / NB;
+  if (nb > 65535) return hipErrorInvalidValue;
+  const dim3 grid(2, unsigned(nb));  // 2 x 64 columns of each 128 x 128 block
+  // L^-1 at W + b * 2 kNB^2, U^-1 at W + b * 2 kNB^2 + kNB^2, each ld kNB
+  hipLaunchKernelGGL((k_trsm_left<TriMode::LN, true>), grid, dim3(256), 0, s, NB, int64_t(NB), LU,
+                     ld, W, int64_t(NB), n, int64_t(2 * NB * NB));
+  hipLaunchKernelGGL((k_trsm_left<TriMode::UN, true>), grid, dim3(256), 0, s, NB, int64_t(NB), LU,
+                     ld, W + NB * NB, int64_t(NB), n, int64_t(2 * NB * NB));
   return hipGetLastError();
 }
 

@@ -125,12 +125,13 @@ def genp(A, info=None):
     return A, info
 
 
-def getrs(LU, B, trans=0):
+def getrs(LU, B, trans=0, work=None):
     """B <- (LU)^-1 B (trans=0) or (LU)^-T B (trans=1), in place."""
     _dev_f64(B, "B")
     n = LU.shape[0]
-    check(lib().rbt_getrs(n, B.shape[1], _p(LU), _ld(LU), _p(B), _ld(B), trans,
-                          _stream(B.device)), "rbt_getrs")
+    work = work if work is not None else _workspace(n, B.shape[1], 0, B.device)
+    check(lib().rbt_getrs(n, B.shape[1], _p(LU), _ld(LU), _p(B), _ld(B), trans, _p(work),
+                          work.numel(), _stream(B.device)), "rbt_getrs")
     return B
 
 

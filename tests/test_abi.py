@@ -71,7 +71,8 @@ def test_argument_errors(lib):
     assert lib.rbt_solve_ex(4, 1, dummy, 4, dummy, 4, 99, 0, None, dummy, 1 << 20, None) == -7
     assert lib.rbt_solve_ex(4, 1, dummy, 4, dummy, 4, 2, 0, None, dummy, 16, None) == _lib.RBT_ERR_WORKSPACE
     assert lib.rbt_genp(5, dummy, 4, None, None) == -3
-    assert lib.rbt_getrs(5, 1, dummy, 5, dummy, 5, 2, None) == -7
+    assert lib.rbt_getrs(5, 1, dummy, 5, dummy, 5, 2, dummy, 1 << 20, None) == -7
+    assert lib.rbt_getrs(5, 1, dummy, 5, dummy, 5, 0, dummy, 8, None) == _lib.RBT_ERR_WORKSPACE
     assert lib.rbt_transform2(5, dummy, 5, dummy, 5, 7, dummy, dummy, 2, None) == -6
     assert lib.rbt_transform_vec(5, 1, dummy, 5, dummy, 2, 9, None) == -7
     assert lib.rbt_solve_refine(5, 1, dummy, 5, dummy, 5, dummy, 5, dummy, 5, 2, 0, -1.0, 3,
