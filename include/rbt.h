@@ -155,6 +155,21 @@ int rbt_backward_error(int64_t n, int64_t nrhs, const double *A, int64_t lda, co
                        int64_t ldx, const double *B, int64_t ldb, double *berr_dev, void *work,
                        size_t work_bytes, void *stream);
 
+/* Device. Adjoint of X = A^-1 B for a loss with dL/dX = G (all FP64,
+ * column-major): dB = Lambda = A^-T G and dA = -Lambda X^T. With
+ * A = U^-T A~ V^-1 (Eq. 1), A^-T = U A~^-T V^T, so Lambda is formed through
+ * the same butterflies and the saved factors of A~: G^ = V^T G, solve
+ * U_f^T Z = G^ then L^T W = Z, Lambda = U W.
+ * LU: the L\U factors of A~ left by rbt_solve_ex (or the LU output of
+ * rbt_solve_refine) for the same (depth, seed); X: the forward solution
+ * (only read when dA != NULL); G: n x nrhs; dB: n x nrhs output (may not
+ * alias G); dA: n x n output, nullable (skipped). work: >=
+ * rbt_workspace_size(n, nrhs, depth, RBT_FP64) bytes. */
+int rbt_solve_backward(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu, const double *X,
+                       int64_t ldx, const double *G, int64_t ldg, double *dA, int64_t ldda,
+                       double *dB, int64_t lddb, int depth, uint64_t seed, void *work,
+                       size_t work_bytes, void *stream);
+
 /* Tuning options (process-wide; not thread safe).
  * RBT_OPT_OUTER_NB: width of the panels of the elimination whose trailing
  *   update is a single GEMM (multiple of 128, 128..2048; default 1024). The

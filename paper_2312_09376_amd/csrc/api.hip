@@ -524,3 +524,41 @@ extern "C" int64_t rbt_get_option(int option) {
     default: return -1;
   }
 }
+
+extern "C" int rbt_solve_backward(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu,
+                                  const double *X, int64_t ldx, const double *G, int64_t ldg,
+                                  double *dA, int64_t ldda, double *dB, int64_t lddb, int depth,
+                                  uint64_t seed, void *work, size_t work_bytes, void *stream) {
+  if (n < 0) return -1;
+  if (nrhs < 0) return -2;
+  if (n > 0 && LU == nullptr) return -3;
+  if (ldlu < (n > 1 ? n : 1)) return -4;
+  if (n > 0 && nrhs > 0 && dA != nullptr && X == nullptr) return -5;
+  if (ldx < (n > 1 ? n : 1)) return -6;
+  if (n > 0 && nrhs > 0 && G == nullptr) return -7;
+  if (ldg < (n > 1 ? n : 1)) return -8;
+  if (dA != nullptr && ldda < (n > 1 ? n : 1)) return -10;
+  if (n > 0 && nrhs > 0 && dB == nullptr) return -11;
+  if (lddb < (n > 1 ? n : 1)) return -12;
+  if (bad_depth(depth)) return -13;
+  const Layout L = layout(n, nrhs, depth);
+  if (n > 0 && work == nullptr) return -15;
+  if (work_bytes < L.total) return RBT_ERR_WORKSPACE;
+  if (n == 0) return 0;
+  hipStream_t s = S(stream);
+  const Geometry g = geometry(n, depth);
+  double *U = at<double>(work, L.o_coef);
+  double *V = U + n * depth;
+  double *winv = at<double>(work, L.o_winv);
+  // Lambda = A^-T G = U (A~^-T (V^T G)),  A~ = U^T A V = L U_f
+  RBT_HIP_CHECK(generate_t(n, depth, seed, U, V, s));
+  RBT_HIP_CHECK(launch_copy_cols(n, nrhs, G, ldg, dB, lddb, s));
+  RBT_HIP_CHECK(transform_vec_t(g, nrhs, dB, lddb, V, RBT_OP_T, s));
+  int rc = diag_inverses_t(n, nrhs, LU, ldlu, winv, s);
+  if (rc) return rc;
+  rc = getrs_t(n, nrhs, LU, ldlu, dB, lddb, 1, winv, s);
+  if (rc) return rc;
+  RBT_HIP_CHECK(transform_vec_t(g, nrhs, dB, lddb, U, RBT_OP_N, s));
+  if (dA != nullptr) RBT_HIP_CHECK(launch_neg_outer(n, nrhs, dB, lddb, X, ldx, dA, ldda, s));
+  return 0;
+}

@@ -137,6 +137,10 @@ hipError_t launch_axpy_cols(int64_t n, int64_t nrhs, const double *D, int64_t ld
                             int64_t ldx, hipStream_t s);
 hipError_t launch_copy_cols(int64_t n, int64_t nrhs, const double *S, int64_t lds, double *D,
                             int64_t ldd, hipStream_t s);
+// dA = -L X^T (n x n) for L, X of n x nrhs
+hipError_t launch_neg_outer(int64_t n, int64_t nrhs, const double *Lm, int64_t ldl,
+                            const double *X, int64_t ldx, double *dA, int64_t ldda,
+                            hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, hipStream_t s);
 

@@ -440,6 +440,41 @@ __global__ void __launch_bounds__(kRows) k_copy_cols(int64_t n, int64_t nrhs,
   for (int64_t c = blockIdx.y; c < nrhs; c += gridDim.y) D[i + c * ldd] = S[i + c * lds];
 }
 
+// dA = -L X^T (n x n, rank nrhs): lanes along rows of dA, so every store is
+// a coalesced column run; the kernel is bound by the n^2 writes.
+__global__ void __launch_bounds__(kRows) k_neg_outer(int64_t n, int64_t nrhs,
+                                                    const double *__restrict__ Lm, int64_t ldl,
+                                                    const double *__restrict__ X, int64_t ldx,
+                                                    double *__restrict__ dA, int64_t ldda) {
+  const int64_t i = int64_t(blockIdx.x) * kRows + threadIdx.x;
+  if (i >= n) return;
+  constexpr int KC = 16;
+  for (int64_t j0 = int64_t(blockIdx.y) * 16; j0 < n; j0 += int64_t(gridDim.y) * 16) {
+    double acc[16];
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
+    for (int64_t k0 = 0; k0 < nrhs; k0 += KC) {
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        const int64_t k = k0 + kk;
+        if (k < nrhs) {
+          const double l = Lm[i + k * ldl];
+#pragma unroll
+          for (int jj = 0; jj < 16; ++jj) {
+            const int64_t j = j0 + jj;
+            acc[jj] += (j < n) ? l * X[j + k * ldx] : 0.0;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      const int64_t j = j0 + jj;
+      if (j < n) dA[i + j * ldda] = -acc[jj];
+    }
+  }
+}
+
 __global__ void k_fill_i32(int32_t *p, int32_t v) {
   if (threadIdx.x == 0) p[0] = v;
 }
@@ -592,6 +627,16 @@ hipError_t launch_copy_cols(int64_t n, int64_t nrhs, const double *S, int64_t ld
                             int64_t ldd, hipStream_t s) {
   if (n == 0 || nrhs == 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy_cols, col_grid(n, nrhs), dim3(kRows), 0, s, n, nrhs, S, lds, D, ldd);
+  return hipGetLastError();
+}
+
+hipError_t launch_neg_outer(int64_t n, int64_t nrhs, const double *Lm, int64_t ldl,
+                            const double *X, int64_t ldx, double *dA, int64_t ldda,
+                            hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t cols = (n + 15) / 16;
+  const dim3 grid(unsigned((n + kRows - 1) / kRows), unsigned(cols < 1024 ? cols : 1024));
+  hipLaunchKernelGGL(k_neg_outer, grid, dim3(kRows), 0, s, n, nrhs, Lm, ldl, X, ldx, dA, ldda);
   return hipGetLastError();
 }
 

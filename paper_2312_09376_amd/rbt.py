@@ -213,3 +213,57 @@ def set_option(option, value):
 
 def get_option(option):
     return int(lib().rbt_get_option(option))
+
+
+def solve_backward(LU, X, G, depth=2, seed=2023, need_dA=True, work=None):
+    """Adjoint of X = A^-1 B: returns (dA, dB) = (-A^-T G X^T, A^-T G).
+
+    LU are the factors of U^T A V from the forward solve with the same
+    (depth, seed); X is the forward solution. dA is None when not needed.
+    """
+    LU, X, G = colmajor(LU), colmajor(X), colmajor(G)
+    _dev_f64(LU, "LU")
+    _dev_f64(G, "G")
+    n, k = LU.shape[0], G.shape[1]
+    dev = LU.device
+    dB = torch.empty_strided((n, k), (1, max(1, n)), dtype=torch.float64, device=dev)
+    dA = torch.empty_strided((n, n), (1, max(1, n)), dtype=torch.float64, device=dev) if need_dA else None
+    work = work if work is not None else _workspace(n, k, depth, dev)
+    check(lib().rbt_solve_backward(n, k, _p(LU), _ld(LU), _p(X), _ld(X), _p(G), _ld(G), _p(dA),
+                                   _ld(dA) if dA is not None else max(1, n), _p(dB), _ld(dB),
+                                   depth, seed, _p(work), work.numel(), _stream(dev)),
+          "rbt_solve_backward")
+    return dA, dB
+
+
+class RBTSolve(torch.autograd.Function):
+    """X = A^-1 B by the RBT method, differentiable in A and B.
+
+    Forward: the FP64 solve with refinement (A is kept for the residuals);
+    backward: the adjoint through the same butterflies and saved factors
+    (rbt_solve_backward)."""
+
+    @staticmethod
+    def forward(ctx, A, B, depth=2, seed=2023, max_iter=10):
+        vec = B.dim() == 1
+        B2 = B.reshape(-1, 1) if vec else B
+        X, LU, _, _, _, _ = solve_refine(A.detach(), B2.detach(), depth, seed, max_iter=max_iter)
+        ctx.save_for_backward(LU, X)
+        ctx.depth, ctx.seed, ctx.vec = depth, seed, vec
+        out = X.reshape(-1) if vec else X
+        return out.clone(memory_format=torch.contiguous_format)
+
+    @staticmethod
+    def backward(ctx, G):
+        LU, X = ctx.saved_tensors
+        G2 = G.reshape(-1, 1) if ctx.vec else G
+        dA, dB = solve_backward(LU, X, G2.contiguous(), ctx.depth, ctx.seed,
+                                need_dA=ctx.needs_input_grad[0])
+        if ctx.vec:
+            dB = dB.reshape(-1)
+        return dA, dB, None, None, None
+
+
+def rbt_solve(A, B, depth=2, seed=2023, max_iter=10):
+    """Differentiable X = A^-1 B (FP64 tensors on the device)."""
+    return RBTSolve.apply(A, B, depth, seed, max_iter)
