@@ -25,6 +25,15 @@ METRIC = "solve TFLOP/s (2/3·n³) RBT+GENP vs GEPP at n=20000; backward error; 
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per trailing-update launch, from FETCH_SIZE and WRITE_SIZE counter
+# runs (rocprofv3 --pmc) scaled by what the same counters read for a plain copy
+# of known size (FETCH x 2.000, WRITE x 1.000). Valid only for the kernel
+# source and the workload they were taken on: reported as null otherwise.
+TRAILING_TRAFFIC = {"source": "paper_2312_09376_amd/csrc/k_gemm.hip",
+                    "sha256": "b69180937539ca298702ab98419575983b7e9a29a355c9afeb4baa75ce7e1056",
+                    "n": 20000, "nrhs": 1, "depth": 2, "outer_nb": 1024,
+                    "bytes_per_launch": 6.901e9}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -41,7 +50,58 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=4096, help="oracle sample size")
     ap.add_argument("--outer-nb", type=int, default=0,
                     help="panel width of the elimination (multiple of 128; 0 = library default)")
+    ap.add_argument("--mode", choices=["solve", "copy"], default="solve",
+                    help="solve: the benchmarked step; copy: a plain FP64 matrix copy through the "
+                         "transform kernel at depth 0 (reference point for HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_mode(args):
+    """Depth-0 transform = plain out-of-place copy of an n x n FP64 matrix
+    (8 n^2 bytes read, 8 n^2 bytes written per launch)."""
+    import torch
+    from paper_2312_09376_amd import rbt, workloads
+    n = args.n
+    A = workloads.device_randn(n, n, workloads.MATRIX_SEED)
+    out = torch.empty_strided((n, n), (1, n), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        rbt.transform2(A, None, None, 0, out=out)
+    torch.cuda.synchronize()
+    rbt.timing_read()
+    rbt.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rbt.transform2(A, None, None, 0, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rbt.timing_enable(False)
+    ms, cnt, nbytes = rbt.timing_read()["transform2"]
+    gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    print(json.dumps({
+        "metric": "FP64 matrix copy GB/s (reference point for HBM byte counters)",
+        "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"copy of an n x n FP64 matrix, n={n}", "n": n,
+                   "bytes_per_launch": 16 * n * n},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None},
+        "cpu_baseline": None}), flush=True)
+
+
+def measured_traffic(n, nrhs, depth, outer_nb):
+    import hashlib
+    t = TRAILING_TRAFFIC
+    try:
+        with open(os.path.join(ROOT, t["source"]), "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if digest != t["sha256"] or (n, nrhs, depth, outer_nb) != (t["n"], t["nrhs"], t["depth"],
+                                                                t["outer_nb"]):
+        return None
+    return t["bytes_per_launch"]
 
 
 def cpu_baseline(n, nrhs, depth, seed):
@@ -85,6 +145,9 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.mode == "copy":
+        copy_mode(args)
+        return
     if args.outer_nb:
         rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, args.outer_nb)
     n, k, d = args.n, args.nrhs, args.depth
@@ -126,6 +189,11 @@ def main():
     info_v = int(info.item())
 
     tr_ms, tr_cnt, tr_work = stages["trailing"]
+    # algorithmic bytes of a trailing update: read + write A22 (16 rc^2) and
+    # read L21, U12 (16 rc w); with flops 2 rc^2 w this is 8/w + 8/rc per flop
+    W = rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)
+    tr_bytes = sum(16.0 * rc * rc + 16.0 * rc * W for rc in
+                   (n - k0 - W for k0 in range(0, n, W)) if rc > 0) * args.steps
     gemm_avg_ms = tr_ms / max(tr_cnt, 1)
     gemm_tflops = tr_work / (tr_ms * 1e-3) / 1e12 if tr_ms > 0 else 0.0
     k1_ms, k1_cnt, k1_bytes = stages["transform2"]
@@ -151,7 +219,10 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "trailing-update GEMM (k_dgemm, FP64 MFMA)",
                      "achieved": round(gemm_tflops, 3), "peak": PEAK_FP64_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(gemm_tflops / PEAK_FP64_MFMA_TFLOPS, 4),
-                     "traffic": None, "launches": tr_cnt,
+                     "traffic": measured_traffic(n, k, d, rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)),
+                     "traffic_unit": "bytes per launch (HBM read + write, counter runs)",
+                     "algorithmic_bytes_per_launch": tr_bytes / max(tr_cnt, 1),
+                     "launches": tr_cnt,
                      "avg_launch_ms": round(gemm_avg_ms, 4),
                      "flops_per_launch": tr_work / max(tr_cnt, 1)},
         "berr": berr,

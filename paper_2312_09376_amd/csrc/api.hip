@@ -290,8 +290,7 @@ extern "C" int rbt_transform2(int64_t n, const double *A, int64_t lda, void *Out
   if (n > 0 && depth > 0 && dU == nullptr) return -7;
   if (n > 0 && depth > 0 && dV == nullptr) return -8;
   if (bad_depth(depth)) return -9;
-  RBT_HIP_CHECK(launch_transform2(geometry(n, depth), A, lda, Out, ldo, out_prec, dU, dV,
-                                  S(stream)));
+  RBT_HIP_CHECK(transform2_t(geometry(n, depth), A, lda, Out, ldo, out_prec, dU, dV, S(stream)));
   return 0;
 }
 
