@@ -24,6 +24,8 @@ if ROOT not in sys.path:
 METRIC = "solve TFLOP/s (2/3·n³) RBT+GENP vs GEPP at n=20000; backward error; GB/s"
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 
 # HBM bytes per trailing-update launch, from FETCH_SIZE and WRITE_SIZE counter
 # runs (rocprofv3 --pmc) scaled by what the same counters read for a plain copy
@@ -50,9 +52,14 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=4096, help="oracle sample size")
     ap.add_argument("--outer-nb", type=int, default=0,
                     help="panel width of the elimination (multiple of 128; 0 = library default)")
-    ap.add_argument("--mode", choices=["solve", "copy"], default="solve",
-                    help="solve: the benchmarked step; copy: a plain FP64 matrix copy through the "
-                         "transform kernel at depth 0 (reference point for HBM byte counters)")
+    ap.add_argument("--mode", choices=["solve", "mixed", "copy"], default="solve",
+                    help="solve: the FP64 step (default); mixed: FP32/BF16 elimination with FP64 "
+                         "refinement; copy: a plain FP64 matrix copy through the transform kernel "
+                         "at depth 0 (reference point for HBM byte counters)")
+    ap.add_argument("--prec", choices=["fp32", "bf16"], default="fp32", help="mixed mode")
+    ap.add_argument("--solver", choices=["classic", "gmres"], default="classic", help="mixed mode")
+    ap.add_argument("--matrix", choices=["randn", "logcond", "dominant"], default="randn",
+                    help="mixed mode: N(0,1), Q1 diag(10^-6 .. 1) Q2^T, or I + 0.3 N(0,1)/sqrt(n)")
     return ap.parse_args()
 
 
@@ -104,6 +111,83 @@ def measured_traffic(n, nrhs, depth, outer_nb):
     return t["bytes_per_launch"]
 
 
+def mixed_mode(args):
+    """One step = rbt_solve_mixed: transform to FP32, elimination with FP32 or
+    BF16 updates, FP64 refinement to 10 n eps (or max_iter)."""
+    import torch
+    from paper_2312_09376_amd import rbt, workloads
+    if args.outer_nb:
+        rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, args.outer_nb)
+    n, k, d = args.n, args.nrhs, args.depth
+    tol = 10.0 * n * 2.0 ** -52
+    prec = rbt.RBT_FP32 if args.prec == "fp32" else rbt.RBT_BF16
+    solver = rbt.RBT_IR_CLASSIC if args.solver == "classic" else rbt.RBT_IR_GMRES
+    if args.matrix == "randn":
+        A = workloads.device_randn(n, n, workloads.MATRIX_SEED)
+    elif args.matrix == "logcond":
+        A = workloads.device_logcond(n, workloads.MATRIX_SEED)
+    else:
+        A = workloads.device_randn(n, n, workloads.MATRIX_SEED) * (0.3 / math.sqrt(n))
+        A.diagonal().add_(1.0)
+    B = workloads.device_randn(n, k, workloads.RHS_SEED)
+    LU = torch.empty_strided((n, n), (1, n), dtype=torch.float32, device="cuda")
+    X = torch.empty_strided((n, k), (1, n), dtype=torch.float64, device="cuda")
+    work = rbt._workspace(n, k, d, A.device, prec)
+    torch.cuda.synchronize()
+
+    def step():
+        return rbt.solve_mixed(A, B, d, args.seed, prec=prec, solver=solver, tol=tol,
+                               max_iter=args.max_iter, LU=LU, X=X, work=work)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    rbt.timing_read()
+    rbt.timing_enable(True)
+    iters = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, it, be, info, _ = step()
+        iters.append(it)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rbt.timing_enable(False)
+    stages = rbt.timing_read()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    flops = (2.0 / 3.0) * n ** 3
+    berr = float(be.item())
+    tr_ms, tr_cnt, tr_work = stages["trailing"]
+    peak = PEAK_FP32_MFMA_TFLOPS if args.prec == "fp32" else PEAK_BF16_MFMA_TFLOPS
+    gemm_tflops = tr_work / (tr_ms * 1e-3) / 1e12 if tr_ms > 0 else 0.0
+    W = rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)
+    tr_bytes = sum(8.0 * rc * rc + 8.0 * rc * W for rc in
+                   (n - k0 - W for k0 in range(0, n, W)) if rc > 0) * args.steps
+    out = {
+        "metric": f"mixed-precision solve TFLOP/s (2/3·n³, FP64-accurate result), "
+                  f"{args.prec.upper()} elimination + FP64 {args.solver} refinement",
+        "value": round(flops / (ms_step * 1e-3) / 1e12, 4), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": f"RBT+GENP {args.prec.upper()} elimination, FP64 {args.solver} "
+                               f"refinement to berr<=10*n*eps, n={n}, nrhs={k}, depth {d}, "
+                               f"A={args.matrix} seed 42, b~N(0,1) seed 64",
+                   "n": n, "nrhs": k, "depth": d, "outer_nb": W, "matrix": args.matrix},
+        "roofline": {"bound": "mfma",
+                     "kernel": f"trailing-update GEMM (k_sgemm, {args.prec.upper()} MFMA)",
+                     "achieved": round(gemm_tflops, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(gemm_tflops / peak, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": tr_bytes / max(tr_cnt, 1),
+                     "launches": tr_cnt, "avg_launch_ms": round(tr_ms / max(tr_cnt, 1), 4),
+                     "flops_per_launch": tr_work / max(tr_cnt, 1)},
+        "berr": berr, "berr_tol": tol, "converged": berr <= tol,
+        "ir_steps": [int(i.item()) for i in iters], "info": int(info.item()),
+        "stages_ms_per_step": {s_: round(v[0] / args.steps, 3) for s_, v in stages.items()},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(n, nrhs, depth, seed):
     """The oracle, as it stands, on the host cores: one full solve (coefficients,
     transform, elimination, solves, refinement to the same tolerance)."""
@@ -147,6 +231,9 @@ def main():
     torch.cuda.set_device(0)
     if args.mode == "copy":
         copy_mode(args)
+        return
+    if args.mode == "mixed":
+        mixed_mode(args)
         return
     if args.outer_nb:
         rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, args.outer_nb)

@@ -100,8 +100,8 @@ int rbt_transform_vec(int64_t n, int64_t nrhs, double *B, int64_t ldb, const dou
                       int op, void *stream);
 
 /* Workspace (bytes) needed by rbt_getrs / rbt_solve_ex / rbt_solve_refine /
- * rbt_backward_error for these sizes and precision (0 for invalid
- * arguments). */
+ * rbt_backward_error (precision RBT_FP64) or rbt_solve_mixed (RBT_FP32,
+ * RBT_BF16) for these sizes (0 for invalid arguments). */
 size_t rbt_workspace_size(int64_t n, int64_t nrhs, int depth, int precision);
 
 /* Device. GENP of the n x n FP64 matrix A (lda) in place: unit-lower L
@@ -146,6 +146,37 @@ int rbt_solve_refine(int64_t n, int64_t nrhs, const double *A, int64_t lda, doub
                      int64_t ldlu, const double *B, int64_t ldb, double *X, int64_t ldx, int depth,
                      uint64_t seed, double tol, int max_iter, int32_t *iters_dev, double *berr_dev,
                      int32_t *info_dev, void *work, size_t work_bytes, void *stream);
+
+/* Refinement schemes of rbt_solve_mixed. */
+#define RBT_IR_CLASSIC 0 /* X += V (LU)^-1 U^T (B - A X)                         */
+#define RBT_IR_GMRES 1   /* correction by GMRES on A, preconditioned by V (LU)^-1 U^T */
+
+/* Device. Mixed-precision form of rbt_solve_refine (the refinement of Sec. 5
+ * with a factorization in lower precision, the mixed-precision refinement
+ * the paper points to in its discussion of accuracy): A (n x n FP64, lda) is
+ * read only and kept for the residuals; A~ = U^T A V is formed from it in
+ * FP64 arithmetic and stored in FP32 into LU (n x n FP32, ldlu), which is
+ * then eliminated without pivoting in place:
+ *   prec = RBT_FP32: FP32 storage, FP32 matrix-core updates;
+ *   prec = RBT_BF16: FP32 storage, updates with operands rounded to BF16
+ *                    (nearest even) and FP32 accumulation.
+ * Diagonal blocks and triangular solves of the elimination are computed in
+ * FP64 and rounded to FP32 on store. Solves with the FP32 factors widen them
+ * and run in FP64. Refinement is in FP64 with the original A:
+ *   solver = RBT_IR_CLASSIC: X += V (LU)^-1 U^T (B - A X);
+ *   solver = RBT_IR_GMRES:   the correction solves A D = B - A X by restarted
+ *                            GMRES in FP64, preconditioned on the left by
+ *                            V (LU)^-1 U^T.
+ * Stops when the Eq. 7 backward error is <= tol or after max_iter
+ * corrections (GMRES: iterations of the Krylov method). iters_dev, berr_dev,
+ * info_dev: as rbt_solve_refine. depth <= 3 (RBT_ERR_UNSUPPORTED otherwise).
+ * work: >= rbt_workspace_size(n, nrhs, depth, prec) bytes. Synchronizes
+ * `stream` once per refinement step. */
+int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, float *LU,
+                    int64_t ldlu, const double *B, int64_t ldb, double *X, int64_t ldx, int depth,
+                    uint64_t seed, int prec, int solver, double tol, int max_iter,
+                    int32_t *iters_dev, double *berr_dev, int32_t *info_dev, void *work,
+                    size_t work_bytes, void *stream);
 
 /* Device. Backward error of Eq. 7 for n x nrhs X against A (n x n) and B:
  * max over columns of ||B - A X||_inf / (||A||_inf ||X||_inf + ||B||_inf),

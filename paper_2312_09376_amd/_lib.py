@@ -15,6 +15,7 @@ RBT_ERR_UNSUPPORTED = -102
 RBT_MAX_DEPTH = 16
 RBT_FP64, RBT_FP32, RBT_BF16 = 0, 1, 2
 RBT_OP_T, RBT_OP_N = 0, 1
+RBT_IR_CLASSIC, RBT_IR_GMRES = 0, 1
 
 i64, i32, u64, dbl, sz = ctypes.c_int64, ctypes.c_int, ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t
 vp = ctypes.c_void_p
@@ -34,6 +35,8 @@ SIGNATURES = {
     "rbt_solve": (i32, [i64, i64, vp, i64, vp, i64, i32, u64, vp]),
     "rbt_solve_refine": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, u64, dbl, i32,
                                vp, vp, vp, vp, sz, vp]),
+    "rbt_solve_mixed": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, u64, i32, i32,
+                              dbl, i32, vp, vp, vp, vp, sz, vp]),
     "rbt_backward_error": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, vp, sz, vp]),
     "rbt_solve_backward": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, u64,
                                  vp, sz, vp]),

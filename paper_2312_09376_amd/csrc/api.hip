@@ -66,19 +66,21 @@ inline int64_t nblocks(int64_t n) { return (n + kNB - 1) / kNB; }
 // diagonal blocks (for the few-right-hand-side solves) come first, so that
 // rbt_getrs and the composite entry points agree on where they live.
 struct Layout {
-  size_t winv, coef, resid, partial, small, total;
-  size_t o_winv, o_coef, o_resid, o_partial, o_small;
+  size_t winv, sync, coef, resid, partial, small, total;
+  size_t o_winv, o_sync, o_coef, o_resid, o_partial, o_small;
 };
 
 Layout layout(int64_t n, int64_t nrhs, int d) {
   Layout L{};
   L.winv = align256(size_t(diag_inv_doubles(n)) * sizeof(double));
+  L.sync = align256(size_t(sweep_sync_ints(n)) * sizeof(int32_t));
   L.coef = align256(size_t(2) * n * d * sizeof(double));
   L.resid = align256(size_t(n) * nrhs * sizeof(double));
   L.partial = align256(resid_scratch_doubles(n, nrhs) * sizeof(double));
   L.small = 512;
   L.o_winv = 0;
-  L.o_coef = L.o_winv + L.winv;
+  L.o_sync = L.o_winv + L.winv;
+  L.o_coef = L.o_sync + L.sync;
   L.o_resid = L.o_coef + L.coef;
   L.o_partial = L.o_resid + L.resid;
   L.o_small = L.o_partial + L.partial;
@@ -102,6 +104,19 @@ Options &options() {
   return o;
 }
 
+// GEMM C -= A B of the elimination: FP64 on the FP64 matrix cores, or FP32
+// storage with FP32 or BF16 operands (FP32 accumulation).
+hipError_t gemm_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                    const double *B, int64_t ldb, double *C, int64_t ldc, int /*prec*/,
+                    bool trailing, hipStream_t s) {
+  return launch_dgemm(M, N, K, A, lda, OpA::General, B, ldb, OpB::General, C, ldc,
+                      trailing ? Acc::SubtractTrailing : Acc::Subtract, s);
+}
+hipError_t gemm_sub(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda, const float *B,
+                    int64_t ldb, float *C, int64_t ldc, int prec, bool trailing, hipStream_t s) {
+  return launch_sgemm_sub(M, N, K, A, lda, B, ldb, C, ldc, prec == RBT_BF16, trailing, s);
+}
+
 // Blocked right-looking elimination without pivoting, two levels:
 // the matrix is processed in panels of width W (a multiple of kNB); inside a
 // panel, kNB-wide steps factor the diagonal block, solve the rows below it
@@ -109,7 +124,11 @@ Options &options() {
 // U12 = L11^-1 A12 is solved (kNB rows at a time) and the trailing matrix is
 // updated by one GEMM of depth W, which keeps the GEMM's read-modify-write of
 // A22 well under the HBM bandwidth at matrix-core rate.
-int genp_fp64(int64_t n, double *A, int64_t lda, int32_t *info, hipStream_t s) {
+// T = double: FP64 throughout. T = float (mixed precision): FP32 storage;
+// diagonal blocks and triangular solves computed in FP64 and rounded on
+// store; GEMM updates with FP32 (prec RBT_FP32) or BF16 (RBT_BF16) operands.
+template <typename T>
+int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t s) {
   if (info) RBT_HIP_CHECK(launch_fill_i32(info, 0, s));
   const int64_t W = options().outer_nb;
   for (int64_t k0 = 0; k0 < n; k0 += W) {
@@ -117,7 +136,7 @@ int genp_fp64(int64_t n, double *A, int64_t lda, int32_t *info, hipStream_t s) {
     // ---- panel A[k0:n, k0:k0+w] ----
     for (int64_t k = k0; k < k0 + w; k += kNB) {
       const int kb = int(k0 + w - k < kNB ? k0 + w - k : kNB);
-      double *A11 = A + k + k * lda;
+      T *A11 = A + k + k * lda;
       {
         StageScope t(kStageDiag, s, 2.0 / 3.0 * double(kb) * kb * kb);
         RBT_HIP_CHECK(launch_diag_lu(kb, A11, lda, k, info, s));
@@ -133,9 +152,8 @@ int genp_fp64(int64_t n, double *A, int64_t lda, int32_t *info, hipStream_t s) {
       }
       if (pc > 0 && rows > 0) {
         StageScope t(kStagePanel, s, 2.0 * double(rows) * pc * kb);
-        RBT_HIP_CHECK(launch_dgemm(rows, pc, kb, A + (k + kb) + k * lda, lda, OpA::General,
-                                   A + k + (k + kb) * lda, lda, OpB::General,
-                                   A + (k + kb) + (k + kb) * lda, lda, Acc::Subtract, s));
+        RBT_HIP_CHECK(gemm_sub(rows, pc, kb, A + (k + kb) + k * lda, lda, A + k + (k + kb) * lda,
+                               lda, A + (k + kb) + (k + kb) * lda, lda, prec, false, s));
       }
     }
     const int64_t rc = n - k0 - w;  // columns right of the panel
@@ -151,34 +169,36 @@ int genp_fp64(int64_t n, double *A, int64_t lda, int32_t *info, hipStream_t s) {
       }
       if (below > 0) {
         StageScope t(kStagePanel, s, 2.0 * double(below) * rc * kb);
-        RBT_HIP_CHECK(launch_dgemm(below, rc, kb, A + (k + kb) + k * lda, lda, OpA::General,
-                                   A + k + (k0 + w) * lda, lda, OpB::General,
-                                   A + (k + kb) + (k0 + w) * lda, lda, Acc::Subtract, s));
+        RBT_HIP_CHECK(gemm_sub(below, rc, kb, A + (k + kb) + k * lda, lda, A + k + (k0 + w) * lda,
+                               lda, A + (k + kb) + (k0 + w) * lda, lda, prec, false, s));
       }
     }
     // ---- trailing update A22 -= L21 U12, depth w ----
     {
       StageScope t(kStageTrailing, s, 2.0 * double(rc) * rc * w);
-      RBT_HIP_CHECK(launch_dgemm(rc, rc, w, A + (k0 + w) + k0 * lda, lda, OpA::General,
-                                 A + k0 + (k0 + w) * lda, lda, OpB::General,
-                                 A + (k0 + w) + (k0 + w) * lda, lda, Acc::SubtractTrailing, s));
+      RBT_HIP_CHECK(gemm_sub(rc, rc, w, A + (k0 + w) + k0 * lda, lda, A + k0 + (k0 + w) * lda, lda,
+                             A + (k0 + w) + (k0 + w) * lda, lda, prec, true, s));
     }
   }
   return 0;
+}
+
+int genp_fp64(int64_t n, double *A, int64_t lda, int32_t *info, hipStream_t s) {
+  return genp_impl(n, A, lda, info, RBT_FP64, s);
 }
 
 // B <- (LU)^-1 B (trans = 0) or (LU)^-T B (trans = 1): block solves with the
 // diagonal blocks (k_trsm.hip) and updates of the remaining rows, by the
 // FMA kernel for few right-hand sides and the matrix-core GEMM otherwise.
 int getrs_fp64(int64_t n, int64_t nrhs, const double *LU, int64_t ld, double *B, int64_t ldb,
-               int trans, const double *winv, hipStream_t s) {
+               int trans, const double *winv, int32_t *sync, hipStream_t s) {
   if (n == 0 || nrhs == 0) return 0;
   if (nrhs <= kSkinnyMax) {
-    // one fused launch per diagonal block: inverse + one refinement step
-    RBT_HIP_CHECK(launch_trsv_sweep(trans ? TriMode::UT : TriMode::LN, n, nrhs, LU, ld, winv, B,
-                                    ldb, s));
-    RBT_HIP_CHECK(launch_trsv_sweep(trans ? TriMode::LT : TriMode::UN, n, nrhs, LU, ld, winv, B,
-                                    ldb, s));
+    // one persistent launch per sweep: inverse + one refinement step per block
+    RBT_HIP_CHECK(launch_sweep(trans ? TriMode::UT : TriMode::LN, n, nrhs, LU, ld, winv, B, ldb,
+                               sync, s));
+    RBT_HIP_CHECK(launch_sweep(trans ? TriMode::LT : TriMode::UN, n, nrhs, LU, ld, winv, B, ldb,
+                               sync, s));
     return 0;
   }
   const int64_t nb = nblocks(n);
@@ -241,9 +261,9 @@ hipError_t transform_vec_t(const Geometry &g, int64_t nrhs, double *B, int64_t l
   return launch_transform_vec(g, nrhs, B, ldb, C, op, s);
 }
 int getrs_t(int64_t n, int64_t nrhs, const double *LU, int64_t ld, double *B, int64_t ldb,
-            int trans, const double *winv, hipStream_t s) {
+            int trans, const double *winv, int32_t *sync, hipStream_t s) {
   StageScope t(kStageSolve, s, 2.0 * double(n) * n * nrhs);
-  return getrs_fp64(n, nrhs, LU, ld, B, ldb, trans, winv, s);
+  return getrs_fp64(n, nrhs, LU, ld, B, ldb, trans, winv, sync, s);
 }
 // Inverses of the diagonal blocks, needed by the few-right-hand-side solves.
 int diag_inverses_t(int64_t n, int64_t nrhs, const double *LU, int64_t ld, double *winv,
@@ -251,6 +271,74 @@ int diag_inverses_t(int64_t n, int64_t nrhs, const double *LU, int64_t ld, doubl
   if (nrhs > kSkinnyMax || n == 0) return 0;
   StageScope t(kStageSolve, s, 2.0 / 3.0 * double(n) * kNB * kNB);
   RBT_HIP_CHECK(launch_diag_inverses(n, LU, ld, winv, s));
+  return 0;
+}
+
+// Mixed precision: inverses of the diagonal blocks of the FP32 factors (in
+// FP64), always formed, since every solve with FP32 factors runs as sweeps.
+int diag_inverses_t(int64_t n, const float *LU, int64_t ld, double *winv, hipStream_t s) {
+  if (n == 0) return 0;
+  StageScope t(kStageSolve, s, 2.0 / 3.0 * double(n) * kNB * kNB);
+  RBT_HIP_CHECK(launch_diag_inverses(n, LU, ld, winv, s));
+  return 0;
+}
+// B <- (LU)^-1 B or (LU)^-T B with FP32 factors, FP64 right-hand sides and
+// arithmetic: sweeps over groups of at most kSkinnyMax columns.
+int getrs_t(int64_t n, int64_t nrhs, const float *LU, int64_t ld, double *B, int64_t ldb,
+            int trans, const double *winv, int32_t *sync, hipStream_t s) {
+  StageScope t(kStageSolve, s, 2.0 * double(n) * n * nrhs);
+  for (int64_t c0 = 0; c0 < nrhs; c0 += kSkinnyMax) {
+    const int64_t nc = nrhs - c0 < kSkinnyMax ? nrhs - c0 : kSkinnyMax;
+    double *Bc = B + c0 * ldb;
+    RBT_HIP_CHECK(launch_sweep(trans ? TriMode::UT : TriMode::LN, n, nc, LU, ld, winv, Bc, ldb,
+                               sync, s));
+    RBT_HIP_CHECK(launch_sweep(trans ? TriMode::LT : TriMode::UN, n, nc, LU, ld, winv, Bc, ldb,
+                               sync, s));
+  }
+  return 0;
+}
+
+// R <- V (L U)^-1 U^T R: the solve of Eq. 1 with the factors of A~.
+template <typename TF>
+int apply_solve(const Geometry &g, int64_t nrhs, const TF *LU, int64_t ld, double *R, int64_t ldr,
+                const double *U, const double *V, const double *winv, int32_t *sync,
+                hipStream_t s) {
+  RBT_HIP_CHECK(transform_vec_t(g, nrhs, R, ldr, U, RBT_OP_T, s));
+  const int rc = getrs_t(g.n, nrhs, LU, ld, R, ldr, 0, winv, sync, s);
+  if (rc) return rc;
+  RBT_HIP_CHECK(transform_vec_t(g, nrhs, R, ldr, V, RBT_OP_N, s));
+  return 0;
+}
+
+// Classical iterative refinement (Sec. 5): R = B - A X in FP64 with the
+// original A, Eq. 7 backward error, X += V (LU)^-1 U^T R, until the backward
+// error is <= tol or max_iter corrections have been applied. X holds the
+// first solution on entry. The host reads the backward error once per
+// iteration (one stream synchronization).
+template <typename TF>
+int refine_classic(int64_t n, int64_t nrhs, const double *A, int64_t lda, const TF *LU,
+                   int64_t ldlu, const double *B, int64_t ldb, double *X, int64_t ldx,
+                   const Geometry &g, const double *U, const double *V, const double *winv,
+                   int32_t *sync, double *R, double *scratch, double *anorm, double *berr, double tol,
+                   int max_iter, int *it_out, hipStream_t s) {
+  int it = 0;
+  for (;;) {
+    {
+      StageScope t(kStageResidual, s, 8.0 * double(n) * n);
+      RBT_HIP_CHECK(launch_residual_berr(n, nrhs, A, lda, X, ldx, B, ldb, R, n, it == 0, scratch,
+                                         anorm, berr, s));
+    }
+    if (it >= max_iter) break;
+    double be_host = 0.0;
+    RBT_HIP_CHECK(hipMemcpyAsync(&be_host, berr, sizeof(double), hipMemcpyDeviceToHost, s));
+    RBT_HIP_CHECK(hipStreamSynchronize(s));
+    if (be_host <= tol) break;
+    const int rc = apply_solve(g, nrhs, LU, ldlu, R, n, U, V, winv, sync, s);
+    if (rc) return rc;
+    RBT_HIP_CHECK(launch_axpy_cols(n, nrhs, R, n, X, ldx, s));
+    ++it;
+  }
+  *it_out = it;
   return 0;
 }
 
@@ -262,7 +350,8 @@ bool bad_depth(int d) { return d < 0 || d > RBT_MAX_DEPTH; }
 using namespace rbt;
 
 extern "C" size_t rbt_workspace_size(int64_t n, int64_t nrhs, int depth, int precision) {
-  if (n < 0 || nrhs < 0 || bad_depth(depth) || precision != RBT_FP64) return 0;
+  if (n < 0 || nrhs < 0 || bad_depth(depth)) return 0;
+  if (precision != RBT_FP64 && precision != RBT_FP32 && precision != RBT_BF16) return 0;
   return layout(n, nrhs, depth).total;
 }
 
@@ -325,12 +414,13 @@ extern "C" int rbt_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu
   if (trans != 0 && trans != 1) return -7;
   const Layout L = layout(n, nrhs, 0);
   if (n > 0 && work == nullptr) return -8;
-  if (work_bytes < L.winv) return RBT_ERR_WORKSPACE;
+  if (work_bytes < L.o_sync + L.sync) return RBT_ERR_WORKSPACE;
   hipStream_t s = S(stream);
   double *winv = at<double>(work, L.o_winv);
+  int32_t *sync = at<int32_t>(work, L.o_sync);
   int rc = diag_inverses_t(n, nrhs, LU, ldlu, winv, s);
   if (rc) return rc;
-  return getrs_fp64(n, nrhs, LU, ldlu, B, ldb, trans, winv, s);
+  return getrs_fp64(n, nrhs, LU, ldlu, B, ldb, trans, winv, sync, s);
 }
 
 extern "C" int rbt_solve_ex(int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_t ldb,
@@ -359,7 +449,7 @@ extern "C" int rbt_solve_ex(int64_t n, int64_t nrhs, double *A, int64_t lda, dou
   if (rc) return rc;
   rc = diag_inverses_t(n, nrhs, A, lda, winv, s);
   if (rc) return rc;
-  rc = getrs_t(n, nrhs, A, lda, B, ldb, 0, winv, s);
+  rc = getrs_t(n, nrhs, A, lda, B, ldb, 0, winv, at<int32_t>(work, L.o_sync), s);
   if (rc) return rc;
   RBT_HIP_CHECK(transform_vec_t(g, nrhs, B, ldb, V, RBT_OP_N, s));
   return 0;
@@ -445,30 +535,82 @@ extern "C" int rbt_solve_refine(int64_t n, int64_t nrhs, const double *A, int64_
   rc = diag_inverses_t(n, nrhs, LU, ldlu, winv, s);
   if (rc) return rc;
   RBT_HIP_CHECK(launch_copy_cols(n, nrhs, B, ldb, X, ldx, s));
-  RBT_HIP_CHECK(transform_vec_t(g, nrhs, X, ldx, U, RBT_OP_T, s));
-  rc = getrs_t(n, nrhs, LU, ldlu, X, ldx, 0, winv, s);
+  int32_t *sync = at<int32_t>(work, L.o_sync);
+  rc = apply_solve(g, nrhs, (const double *)LU, ldlu, X, ldx, U, V, winv, sync, s);
   if (rc) return rc;
-  RBT_HIP_CHECK(transform_vec_t(g, nrhs, X, ldx, V, RBT_OP_N, s));
-
   int it = 0;
-  for (;;) {
-    {
-      StageScope t(kStageResidual, s, 8.0 * double(n) * n);
-      RBT_HIP_CHECK(launch_residual_berr(n, nrhs, A, lda, X, ldx, B, ldb, R, n, it == 0, scratch,
-                                         anorm, berr, s));
-    }
-    if (it >= max_iter) break;
-    double be_host = 0.0;
-    RBT_HIP_CHECK(hipMemcpyAsync(&be_host, berr, sizeof(double), hipMemcpyDeviceToHost, s));
+  rc = refine_classic(n, nrhs, A, lda, (const double *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv, sync, R,
+                      scratch, anorm, berr, tol, max_iter, &it, s);
+  if (rc) return rc;
+  if (iters_dev) {
+    RBT_HIP_CHECK(hipMemcpyAsync(iters_dev, &it, sizeof(int32_t), hipMemcpyHostToDevice, s));
     RBT_HIP_CHECK(hipStreamSynchronize(s));
-    if (be_host <= tol) break;
-    RBT_HIP_CHECK(transform_vec_t(g, nrhs, R, n, U, RBT_OP_T, s));
-    rc = getrs_t(n, nrhs, LU, ldlu, R, n, 0, winv, s);
-    if (rc) return rc;
-    RBT_HIP_CHECK(transform_vec_t(g, nrhs, R, n, V, RBT_OP_N, s));
-    RBT_HIP_CHECK(launch_axpy_cols(n, nrhs, R, n, X, ldx, s));
-    ++it;
   }
+  return 0;
+}
+
+extern "C" int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, float *LU,
+                               int64_t ldlu, const double *B, int64_t ldb, double *X, int64_t ldx,
+                               int depth, uint64_t seed, int prec, int solver, double tol,
+                               int max_iter, int32_t *iters_dev, double *berr_dev,
+                               int32_t *info_dev, void *work, size_t work_bytes, void *stream) {
+  if (n < 0) return -1;
+  if (nrhs < 0) return -2;
+  if (n > 0 && A == nullptr) return -3;
+  if (lda < (n > 1 ? n : 1)) return -4;
+  if (n > 0 && LU == nullptr) return -5;
+  if (ldlu < (n > 1 ? n : 1)) return -6;
+  if (n > 0 && nrhs > 0 && B == nullptr) return -7;
+  if (ldb < (n > 1 ? n : 1)) return -8;
+  if (n > 0 && nrhs > 0 && X == nullptr) return -9;
+  if (ldx < (n > 1 ? n : 1)) return -10;
+  if (bad_depth(depth)) return -11;
+  if (prec != RBT_FP32 && prec != RBT_BF16) return -13;
+  if (solver != RBT_IR_CLASSIC && solver != RBT_IR_GMRES) return -14;
+  if (!(tol >= 0.0)) return -15;
+  if (max_iter < 0) return -16;
+  if (depth > 3) return RBT_ERR_UNSUPPORTED;  // the FP32-output transform is one pass
+  if (solver == RBT_IR_GMRES) return RBT_ERR_UNSUPPORTED;
+  const Layout L = layout(n, nrhs, depth);
+  if (n > 0 && work == nullptr) return -20;
+  if (work_bytes < L.total) return RBT_ERR_WORKSPACE;
+  hipStream_t s = S(stream);
+  double *small = at<double>(work, L.o_small);
+  double *berr = berr_dev ? berr_dev : small + 1;
+  if (n == 0 || nrhs == 0) {
+    RBT_HIP_CHECK(launch_fill_f64(berr, 0.0, s));
+    if (iters_dev) RBT_HIP_CHECK(launch_fill_i32(iters_dev, 0, s));
+    if (n > 0) {  // still factor, as the square case of rbt_genp
+      const Geometry g = geometry(n, depth);
+      double *U = at<double>(work, L.o_coef);
+      RBT_HIP_CHECK(generate_t(n, depth, seed, U, U + n * depth, s));
+      RBT_HIP_CHECK(transform2_t(g, A, lda, LU, ldlu, RBT_FP32, U, U + n * depth, s));
+      return genp_impl(n, LU, ldlu, info_dev, prec, s);
+    }
+    return 0;
+  }
+  const Geometry g = geometry(n, depth);
+  double *U = at<double>(work, L.o_coef);
+  double *V = U + n * depth;
+  double *R = at<double>(work, L.o_resid);
+  double *scratch = at<double>(work, L.o_partial);
+  double *winv = at<double>(work, L.o_winv);
+  double *anorm = small;
+
+  RBT_HIP_CHECK(generate_t(n, depth, seed, U, V, s));
+  RBT_HIP_CHECK(transform2_t(g, A, lda, LU, ldlu, RBT_FP32, U, V, s));
+  int rc = genp_impl(n, LU, ldlu, info_dev, prec, s);
+  if (rc) return rc;
+  rc = diag_inverses_t(n, LU, ldlu, winv, s);
+  if (rc) return rc;
+  RBT_HIP_CHECK(launch_copy_cols(n, nrhs, B, ldb, X, ldx, s));
+  int32_t *sync = at<int32_t>(work, L.o_sync);
+  rc = apply_solve(g, nrhs, (const float *)LU, ldlu, X, ldx, U, V, winv, sync, s);
+  if (rc) return rc;
+  int it = 0;
+  rc = refine_classic(n, nrhs, A, lda, (const float *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv, sync, R,
+                      scratch, anorm, berr, tol, max_iter, &it, s);
+  if (rc) return rc;
   if (iters_dev) {
     RBT_HIP_CHECK(hipMemcpyAsync(iters_dev, &it, sizeof(int32_t), hipMemcpyHostToDevice, s));
     RBT_HIP_CHECK(hipStreamSynchronize(s));
@@ -555,7 +697,7 @@ extern "C" int rbt_solve_backward(int64_t n, int64_t nrhs, const double *LU, int
   RBT_HIP_CHECK(transform_vec_t(g, nrhs, dB, lddb, V, RBT_OP_T, s));
   int rc = diag_inverses_t(n, nrhs, LU, ldlu, winv, s);
   if (rc) return rc;
-  rc = getrs_t(n, nrhs, LU, ldlu, dB, lddb, 1, winv, s);
+  rc = getrs_t(n, nrhs, LU, ldlu, dB, lddb, 1, winv, at<int32_t>(work, L.o_sync), s);
   if (rc) return rc;
   RBT_HIP_CHECK(transform_vec_t(g, nrhs, dB, lddb, U, RBT_OP_N, s));
   if (dA != nullptr) RBT_HIP_CHECK(launch_neg_outer(n, nrhs, dB, lddb, X, ldx, dA, ldda, s));

@@ -90,10 +90,19 @@ enum class Acc { Overwrite, Subtract, SubtractTrailing };
 hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, OpA opa,
                         const double *B, int64_t ldb, OpB opb, double *C, int64_t ldc, Acc acc,
                         hipStream_t s);
+// k_sgemm.hip : C -= A B with FP32 storage; bf16: BF16 operands on the matrix
+// cores (FP32 accumulation), else FP32 operands. trailing: separate kernel
+// instance for the trailing update (same arithmetic).
+hipError_t launch_sgemm_sub(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda,
+                            const float *B, int64_t ldb, float *C, int64_t ldc, bool bf16,
+                            bool trailing, hipStream_t s);
 
 // k_getrf.hip : factor the kb x kb diagonal block in place (kb <= kNB);
-// first exact zero pivot -> *info = gofs + c + 1.
+// first exact zero pivot -> *info = gofs + c + 1. FP32 blocks are eliminated
+// in FP64 and rounded on store.
 hipError_t launch_diag_lu(int kb, double *A, int64_t lda, int64_t gofs, int32_t *info,
+                          hipStream_t s);
+hipError_t launch_diag_lu(int kb, float *A, int64_t lda, int64_t gofs, int32_t *info,
                           hipStream_t s);
 
 // k_trsm.hip : triangular solves with a factored diagonal block T (kb <= kNB).
@@ -105,14 +114,19 @@ enum class TriMode {
 };
 hipError_t launch_trsm_left(TriMode mode, int kb, int64_t N, const double *T, int64_t ldt,
                             double *B, int64_t ldb, hipStream_t s);
+hipError_t launch_trsm_left(TriMode mode, int kb, int64_t N, const float *T, int64_t ldt, float *B,
+                            int64_t ldb, hipStream_t s);
 // X U = B in place, B: M x kb
 hipError_t launch_trsm_right_upper(int kb, int64_t M, const double *T, int64_t ldt, double *B,
+                                   int64_t ldb, hipStream_t s);
+hipError_t launch_trsm_right_upper(int kb, int64_t M, const float *T, int64_t ldt, float *B,
                                    int64_t ldb, hipStream_t s);
 // Inverses of all kNB x kNB diagonal blocks of the factors of an n x n
 // elimination: block b's L^-1 at W + b * 2 kNB^2 and U^-1 at
 // W + b * 2 kNB^2 + kNB^2 (ld kNB). Needs diag_inv_doubles(n) doubles.
 hipError_t launch_diag_inverses(int64_t n, const double *LU, int64_t ld, double *W,
                                 hipStream_t s);
+hipError_t launch_diag_inverses(int64_t n, const float *LU, int64_t ld, double *W, hipStream_t s);
 inline int64_t diag_inv_doubles(int64_t n) { return ((n + kNB - 1) / kNB) * 2 * kNB * kNB; }
 
 // k_solve.hip
@@ -125,6 +139,17 @@ hipError_t launch_skinny_update(int64_t M, int64_t N, int K, const double *A, in
 // the diagonal-block inverses of launch_diag_inverses (one launch per block).
 hipError_t launch_trsv_sweep(TriMode mode, int64_t n, int64_t nrhs, const double *LU, int64_t ld,
                              const double *Winv, double *B, int64_t ldb, hipStream_t s);
+hipError_t launch_trsv_sweep(TriMode mode, int64_t n, int64_t nrhs, const float *LU, int64_t ld,
+                             const double *Winv, double *B, int64_t ldb, hipStream_t s);
+// k_sweep.hip : the same sweeps as ONE persistent launch (ticket-ordered
+// block rows, a published-blocks counter). sync: sweep_sync_ints(n) int32
+// of device scratch (cleared by the launch itself); FP64 factors take one
+// refinement step per diagonal block, FP32 factors the inverse alone.
+inline int64_t sweep_sync_ints(int64_t /*n*/) { return 4; }
+hipError_t launch_sweep(TriMode mode, int64_t n, int64_t nrhs, const double *LU, int64_t ld,
+                        const double *Winv, double *B, int64_t ldb, int32_t *sync, hipStream_t s);
+hipError_t launch_sweep(TriMode mode, int64_t n, int64_t nrhs, const float *LU, int64_t ld,
+                        const double *Winv, double *B, int64_t ldb, int32_t *sync, hipStream_t s);
 // doubles of scratch needed by launch_residual_berr
 size_t resid_scratch_doubles(int64_t n, int64_t nrhs);
 // R = B - A X; berr = Eq. 7 (max over columns); with_anorm: also ||A||_inf -> *anorm

@@ -15,7 +15,8 @@
 //      16 x 16 tiles shared out over the four wavefronts; each tile's
 //      accumulator starts from the LDS values and the L operand is negated.
 // Rows and columns beyond kb hold the identity, so they never disturb the
-// active part. A zero pivot is recorded in *info (first one, 1-based, offset
+// active part. The block may be stored in FP32 (mixed-precision elimination):
+// it is then widened on load, eliminated in FP64 and rounded once on store. A zero pivot is recorded in *info (first one, 1-based, offset
 // gofs) and the arithmetic continues with IEEE Inf/NaN.
 #include "internal.h"
 
@@ -35,7 +36,8 @@ __device__ __forceinline__ double wave_bcast(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
-__global__ void __launch_bounds__(256) k_diag_lu(int kb, double *__restrict__ A, int64_t lda,
+template <typename T>
+__global__ void __launch_bounds__(256) k_diag_lu(int kb, T *__restrict__ A, int64_t lda,
                                                  int64_t gofs, int32_t *__restrict__ info) {
   __shared__ double S[NB * LD];
 
@@ -49,14 +51,19 @@ __global__ void __launch_bounds__(256) k_diag_lu(int kb, double *__restrict__ A,
     const int r = tid & (NB - 1), c0 = tid >> 7;  // row, first column (0/1)
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-      double v[32];
+      // unconditional loads at clamped valid indices, masked afterwards
+      T v[32];
+      const int rr = r < kb ? r : kb - 1;
 #pragma unroll
       for (int i = 0; i < 32; ++i) {
         const int c = c0 + 2 * (32 * half + i);
-        v[i] = (r < kb && c < kb) ? A[r + int64_t(c) * lda] : ((r == c) ? 1.0 : 0.0);
+        v[i] = A[rr + int64_t(c < kb ? c : kb - 1) * lda];
       }
 #pragma unroll
-      for (int i = 0; i < 32; ++i) S[(c0 + 2 * (32 * half + i)) * LD + r] = v[i];
+      for (int i = 0; i < 32; ++i) {
+        const int c = c0 + 2 * (32 * half + i);
+        S[c * LD + r] = (r < kb && c < kb) ? double(v[i]) : ((r == c) ? 1.0 : 0.0);
+      }
     }
   }
   __syncthreads();
@@ -142,19 +149,28 @@ __global__ void __launch_bounds__(256) k_diag_lu(int kb, double *__restrict__ A,
 #pragma unroll 16
     for (int i = 0; i < 64; ++i) {
       const int c = c0 + 2 * i;
-      if (rr < kb && c < kb) A[rr + int64_t(c) * lda] = S[c * LD + rr];
+      if (rr < kb && c < kb) A[rr + int64_t(c) * lda] = T(S[c * LD + rr]);
     }
   }
 }
 
 }  // namespace
 
-hipError_t launch_diag_lu(int kb, double *A, int64_t lda, int64_t gofs, int32_t *info,
-                          hipStream_t s) {
+template <typename T>
+hipError_t diag_lu_t(int kb, T *A, int64_t lda, int64_t gofs, int32_t *info, hipStream_t s) {
   if (kb <= 0) return hipSuccess;
   if (kb > kNB) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_diag_lu, dim3(1), dim3(256), 0, s, kb, A, lda, gofs, info);
+  hipLaunchKernelGGL(k_diag_lu<T>, dim3(1), dim3(256), 0, s, kb, A, lda, gofs, info);
   return hipGetLastError();
+}
+
+hipError_t launch_diag_lu(int kb, double *A, int64_t lda, int64_t gofs, int32_t *info,
+                          hipStream_t s) {
+  return diag_lu_t(kb, A, lda, gofs, info, s);
+}
+hipError_t launch_diag_lu(int kb, float *A, int64_t lda, int64_t gofs, int32_t *info,
+                          hipStream_t s) {
+  return diag_lu_t(kb, A, lda, gofs, info, s);
 }
 
 }  // namespace rbt

@@ -58,16 +58,21 @@ __global__ void __launch_bounds__(kRows) k_skinny_update(int64_t M, int N, int K
 // op(A)(m, k) of the four sweeps, A = the L\U factors (ld):
 //   LN L (forward), UN U (backward), UT U^T (forward), LT L^T (backward).
 // Dinv: LN L^-1, UN U^-1 (stored), UT (U^-1)^T, LT (L^-1)^T (read transposed).
-template <TriMode MODE>
-__device__ __forceinline__ double op_a(const double *A, int64_t ld, int64_t m, int64_t k) {
+// The factors may be stored in FP32 (mixed precision): they are widened on
+// load and every sum is FP64.
+// Loads return the stored type; callers batch a chunk of loads before
+// widening any of them (a widening right after each load makes the compiler
+// wait for every load in turn).
+template <TriMode MODE, typename TF>
+__device__ __forceinline__ TF op_a(const TF *A, int64_t ld, int64_t m, int64_t k) {
   if constexpr (MODE == TriMode::LN || MODE == TriMode::UN)
     return A[m + k * ld];
   else
     return A[k + m * ld];
 }
 
-template <int NMAX, TriMode MODE>
-__global__ void __launch_bounds__(kRows) k_trsv_step(int64_t n, int N, const double *A,
+template <int NMAX, TriMode MODE, typename TF>
+__global__ void __launch_bounds__(kRows) k_trsv_step(int64_t n, int N, const TF *A,
                                                      int64_t ld, const double *Winv, double *B,
                                                      int64_t ldb, int64_t cur, int64_t nxt) {
   constexpr bool FWD = (MODE == TriMode::LN || MODE == TriMode::UT);
@@ -98,11 +103,23 @@ __global__ void __launch_bounds__(kRows) k_trsv_step(int64_t n, int N, const dou
     double acc[NMAX];
 #pragma unroll
     for (int c = 0; c < NMAX; ++c) acc[c] = 0.0;
-#pragma unroll 16
-    for (int k = 0; k < kNB; ++k) {
-      const double a = (k < cb) ? op_a<MODE>(A, ld, m, c0 + k) : 0.0;
+    // cur >= 0 here, so cb >= 1: loads use clamped (valid) columns and the
+    // mask is applied after the load, which keeps each chunk's 16 loads in
+    // flight together
+    for (int k0 = 0; k0 < kNB; k0 += 16) {
+      TF raw[16];
 #pragma unroll
-      for (int c = 0; c < NMAX; ++c) acc[c] += a * xs[k][c];
+      for (int jj = 0; jj < 16; ++jj) {
+        const int kc = k0 + jj < cb ? k0 + jj : cb - 1;
+        const TF v = op_a<MODE>(A, ld, m, c0 + kc);
+        raw[jj] = (k0 + jj < cb) ? v : TF(0);
+      }
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        const double a = double(raw[jj]);
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c) acc[c] += a * xs[k0 + jj][c];
+      }
     }
 #pragma unroll
     for (int c = 0; c < NMAX; ++c)
@@ -123,13 +140,13 @@ __global__ void __launch_bounds__(kRows) k_trsv_step(int64_t n, int N, const dou
 #pragma unroll
     for (int c = 0; c < NMAX; ++c) acc[c] = 0.0;
     auto chunk = [&](int q) {  // a batch of 16 independent loads
-      double e[16];
+      decltype(entry(0, 0)) e[16];
 #pragma unroll
       for (int jj = 0; jj < 16; ++jj) e[jj] = entry(i, H * h + q + jj);
 #pragma unroll
       for (int jj = 0; jj < 16; ++jj)
 #pragma unroll
-        for (int c = 0; c < NMAX; ++c) acc[c] += e[jj] * vec[H * h + q + jj][c];
+        for (int c = 0; c < NMAX; ++c) acc[c] += double(e[jj]) * vec[H * h + q + jj][c];
     };
     if constexpr (NMAX == 1) {
 #pragma unroll
@@ -141,23 +158,35 @@ __global__ void __launch_bounds__(kRows) k_trsv_step(int64_t n, int N, const dou
 #pragma unroll
     for (int c = 0; c < NMAX; ++c) part[h][i][c] = acc[c];
   };
-  // product entries (zero outside the valid block / triangle)
-  auto e_cross = [&](int ii, int jj) -> double {
-    return (ii < kb && jj < cb) ? op_a<MODE>(A, ld, r0 + ii, c0 + jj) : 0.0;
+  // product entries (zero outside the valid block / triangle); every load
+  // is unconditional at a clamped valid address and masked afterwards
+  // (kb >= 1; e_cross is only used when cb >= 1; Di blocks are full
+  // kNB x kNB allocations whose entries beyond kb are never used)
+  const int kl = kb - 1;
+  auto e_cross = [&](int ii, int jj) -> TF {
+    const TF v = op_a<MODE>(A, ld, r0 + (ii < kb ? ii : kl), c0 + (jj < cb ? jj : cb - 1));
+    return (ii < kb && jj < cb) ? v : TF(0);
   };
   auto e_dinv = [&](int ii, int jj) -> double {
-    if (ii >= kb || jj >= kb) return 0.0;
-    return (MODE == TriMode::LN || MODE == TriMode::UN) ? Di[ii + jj * kNB] : Di[jj + ii * kNB];
+    const double v =
+        (MODE == TriMode::LN || MODE == TriMode::UN) ? Di[ii + jj * kNB] : Di[jj + ii * kNB];
+    return (ii < kb && jj < kb) ? v : 0.0;
   };
-  auto e_tdiag = [&](int ii, int jj) -> double {
-    if (ii >= kb || jj >= kb) return 0.0;
-    if (ii == jj) return UNIT ? 1.0 : op_a<MODE>(A, ld, r0 + ii, r0 + jj);
-    if (FWD ? (jj > ii) : (jj < ii)) return 0.0;
-    return op_a<MODE>(A, ld, r0 + ii, r0 + jj);
+  auto e_tdiag = [&](int ii, int jj) -> TF {
+    const TF v = op_a<MODE>(A, ld, r0 + (ii < kb ? ii : kl), r0 + (jj < kb ? jj : kl));
+    if (ii >= kb || jj >= kb) return TF(0);
+    if (ii == jj) return UNIT ? TF(1) : v;
+    if (FWD ? (jj > ii) : (jj < ii)) return TF(0);
+    return v;
   };
 
   // r = b - op(A)[nxt, cur] x_cur  -> vs
-  half_product(e_cross, xs);
+  if (cb > 0) {
+    half_product(e_cross, xs);
+  } else {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) part[h][i][c] = 0.0;
+  }
   __syncthreads();
   double r[NMAX];
   if (h == 0) {
@@ -518,8 +547,8 @@ hipError_t resid_t(int64_t n, int N, const double *A, int64_t lda, const double 
   return hipGetLastError();
 }
 
-template <int NMAX, TriMode MODE>
-hipError_t trsv_sweep_t(int64_t n, int N, const double *LU, int64_t ld, const double *Winv,
+template <int NMAX, TriMode MODE, typename TF>
+hipError_t trsv_sweep_t(int64_t n, int N, const TF *LU, int64_t ld, const double *Winv,
                         double *B, int64_t ldb, hipStream_t s) {
   constexpr bool FWD = (MODE == TriMode::LN || MODE == TriMode::UT);
   const int64_t nb = (n + kNB - 1) / kNB;
@@ -528,14 +557,14 @@ hipError_t trsv_sweep_t(int64_t n, int N, const double *LU, int64_t ld, const do
     const int64_t cur = i == 0 ? -1 : (FWD ? nxt - 1 : nxt + 1);
     const int64_t rest = FWD ? (n - (nxt + 1) * kNB) : nxt * kNB;  // rows beyond block nxt
     const int64_t extra = (cur < 0 || rest <= 0) ? 0 : (rest + kRows - 1) / kRows;
-    hipLaunchKernelGGL((k_trsv_step<NMAX, MODE>), dim3(unsigned(1 + extra)), dim3(kRows), 0, s, n,
+    hipLaunchKernelGGL((k_trsv_step<NMAX, MODE, TF>), dim3(unsigned(1 + extra)), dim3(kRows), 0, s, n,
                        N, LU, ld, Winv, B, ldb, cur, nxt);
   }
   return hipGetLastError();
 }
 
-template <int NMAX>
-hipError_t trsv_sweep_n(TriMode mode, int64_t n, int N, const double *LU, int64_t ld,
+template <int NMAX, typename TF>
+hipError_t trsv_sweep_n(TriMode mode, int64_t n, int N, const TF *LU, int64_t ld,
                         const double *Winv, double *B, int64_t ldb, hipStream_t s) {
   switch (mode) {
     case TriMode::LN: return trsv_sweep_t<NMAX, TriMode::LN>(n, N, LU, ld, Winv, B, ldb, s);
@@ -547,8 +576,9 @@ hipError_t trsv_sweep_n(TriMode mode, int64_t n, int N, const double *LU, int64_
 
 }  // namespace
 
-hipError_t launch_trsv_sweep(TriMode mode, int64_t n, int64_t nrhs, const double *LU, int64_t ld,
-                             const double *Winv, double *B, int64_t ldb, hipStream_t s) {
+template <typename TF>
+hipError_t trsv_sweep_any(TriMode mode, int64_t n, int64_t nrhs, const TF *LU, int64_t ld,
+                          const double *Winv, double *B, int64_t ldb, hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return hipSuccess;
   if (nrhs > kSkinnyMax) return hipErrorInvalidValue;
   const int N = int(nrhs);
@@ -556,6 +586,15 @@ hipError_t launch_trsv_sweep(TriMode mode, int64_t n, int64_t nrhs, const double
   if (N <= 4) return trsv_sweep_n<4>(mode, n, N, LU, ld, Winv, B, ldb, s);
   if (N <= 8) return trsv_sweep_n<8>(mode, n, N, LU, ld, Winv, B, ldb, s);
   return trsv_sweep_n<16>(mode, n, N, LU, ld, Winv, B, ldb, s);
+}
+
+hipError_t launch_trsv_sweep(TriMode mode, int64_t n, int64_t nrhs, const double *LU, int64_t ld,
+                             const double *Winv, double *B, int64_t ldb, hipStream_t s) {
+  return trsv_sweep_any(mode, n, nrhs, LU, ld, Winv, B, ldb, s);
+}
+hipError_t launch_trsv_sweep(TriMode mode, int64_t n, int64_t nrhs, const float *LU, int64_t ld,
+                             const double *Winv, double *B, int64_t ldb, hipStream_t s) {
+  return trsv_sweep_any(mode, n, nrhs, LU, ld, Winv, B, ldb, s);
 }
 
 size_t resid_scratch_doubles(int64_t n, int64_t nrhs) {

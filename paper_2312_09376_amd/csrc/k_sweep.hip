@@ -1,0 +1,317 @@
+// Triangular sweeps for few right-hand sides (nrhs <= 16) as ONE persistent
+// launch per sweep, for the solves after the elimination (Sec. 1, step 3:
+// L y = b~, U x~ = y) and the adjoint solves.
+//
+// Each workgroup takes a ticket (atomic counter) and handles the block row
+// of that rank in sweep order: it accumulates op(A)[b, j] x_j over the
+// blocks j solved before it, then solves its diagonal block with the
+// precomputed inverse (x = Di r; for FP64 factors one more step,
+// x += Di (r - T x), keeps the backward error of substitution) and
+// publishes x_b. Blocks are published strictly in ticket order, so one
+// counter `done` (= number of published blocks) replaces per-block flags: a
+// workgroup that needs block s waits until done > s, then consumes every
+// block published so far without waiting again. The matrix entries of the
+// next block are loaded before each wait, so the loads overlap it.
+//
+// Progress: a workgroup only waits for blocks of smaller tickets, which were
+// taken by workgroups already running, so every wait ends. The spin is also
+// bounded (kSpinLimit sleeps); a workgroup that reaches the bound records it
+// in the error word and goes on, so the grid always drains.
+//
+// Coherence across XCDs: x_b is stored with agent-scope atomic stores, then
+// a device fence and a release store of `done`; waiters poll `done` with
+// relaxed agent-scope loads (no cache invalidation per poll), take one
+// acquire fence when it has advanced, and read x_j with agent-scope atomic
+// loads.
+//
+// Layout: 512 threads = 128 rows x 4 column segments of 32; products of a
+// 128 x 128 block with the x block are reduced over the segments in LDS.
+#include <type_traits>
+
+#include "internal.h"
+
+namespace rbt {
+
+namespace {
+
+constexpr int TPB = 512;
+constexpr int SEG = 4;
+constexpr int SEGW = kNB / SEG;  // 32 columns per segment
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+template <TriMode MODE, typename TF>
+__device__ __forceinline__ TF op_e(const TF *A, int64_t ld, int64_t m, int64_t k) {
+  if constexpr (MODE == TriMode::LN || MODE == TriMode::UN)
+    return A[m + k * ld];
+  else
+    return A[k + m * ld];
+}
+
+__device__ __forceinline__ double coherent_load(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void coherent_store(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int NMAX, TriMode MODE, typename TF, bool REFINE>
+__global__ void __launch_bounds__(TPB)
+    k_sweep(int64_t n, int N, const TF *__restrict__ A, int64_t ld,
+            const double *__restrict__ Winv, double *B, int64_t ldb, int32_t *sync, int64_t nb) {
+  constexpr bool FWD = (MODE == TriMode::LN || MODE == TriMode::UT);
+  constexpr bool UNIT = (MODE == TriMode::LN || MODE == TriMode::LT);
+  __shared__ double xs[kNB][NMAX];
+  __shared__ double part[SEG][kNB][NMAX];
+  __shared__ int64_t tk;
+
+  const int tid = threadIdx.x;
+  const int i = tid & (kNB - 1), sg = tid >> 7;
+  if (tid == 0) tk = atomicAdd(&sync[0], 1);
+  __syncthreads();
+  const int64_t t = tk;
+  if (t >= nb) return;
+  int32_t *done = sync + 1;
+  int32_t *err = sync + 2;
+  __shared__ int64_t avail_sh;
+  const int64_t b = FWD ? t : nb - 1 - t;
+  const int64_t r0 = b * kNB;
+  const int kb = int(n - r0 < kNB ? n - r0 : kNB);
+  const int ir = i < kb ? i : kb - 1;  // clamped row for loads
+
+  // sum over segments of part -> out (threads of segment 0)
+  auto reduce = [&](const double (&a)[NMAX], double (&out)[NMAX]) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) part[sg][i][c] = a[c];
+    __syncthreads();
+    if (sg == 0) {
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c)
+        out[c] = (part[0][i][c] + part[1][i][c]) + (part[2][i][c] + part[3][i][c]);
+    }
+    __syncthreads();
+  };
+
+  // Single right-hand side: the diagonal block's inverse and the
+  // right-hand side do not depend on other blocks, so they are loaded into
+  // registers before any wait and leave the critical path of the sweep.
+  constexpr bool PRE = (NMAX == 1);
+  const double *Di = Winv + b * 2 * kNB * kNB +
+                     ((MODE == TriMode::LN || MODE == TriMode::LT) ? 0 : kNB * kNB);
+  auto load_dinv = [&](double (&ev)[SEGW]) {
+#pragma unroll
+    for (int q = 0; q < SEGW; ++q) {
+      const int jj = sg * SEGW + q;
+      // Di is a full kNB x kNB allocation; entries beyond kb are masked
+      const double v = (MODE == TriMode::LN || MODE == TriMode::UN) ? Di[i + jj * kNB]
+                                                                    : Di[jj + i * kNB];
+      ev[q] = (i < kb && jj < kb) ? v : 0.0;
+    }
+  };
+  auto load_tdiag = [&](TF (&e)[SEGW]) {
+#pragma unroll
+    for (int q = 0; q < SEGW; ++q) {
+      const int jj = sg * SEGW + q;
+      e[q] = op_e<MODE>(A, ld, r0 + ir, r0 + (jj < kb ? jj : kb - 1));
+    }
+  };
+  double dpre[PRE ? SEGW : 1];
+  double bpre = 0.0;
+  if constexpr (PRE) {
+    load_dinv(dpre);
+    if (sg == 0 && i < kb && N > 0) bpre = B[r0 + i];
+  }
+
+  // ---- accumulate op(A)[b, j] x_j over the blocks solved before b ----
+  double acc[NMAX];
+#pragma unroll
+  for (int c = 0; c < NMAX; ++c) acc[c] = 0.0;
+  int64_t avail = 0;  // blocks known to be published (uniform)
+  for (int64_t s = 0; s < t; ++s) {
+    const int64_t j = FWD ? s : nb - 1 - s;
+    const int64_t c0 = j * kNB;
+    const int cb = int(n - c0 < kNB ? n - c0 : kNB);
+    TF e[SEGW];
+#pragma unroll
+    for (int q = 0; q < SEGW; ++q) {
+      const int col = sg * SEGW + q;
+      e[q] = op_e<MODE>(A, ld, r0 + ir, c0 + (col < cb ? col : cb - 1));
+    }
+    if (s >= avail) {
+      if (tid == 0) {
+        uint32_t spins = 0;
+        int32_t d;
+        while ((d = __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) <= s) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > kSpinLimit) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            d = int32_t(s + 1);
+            break;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        avail_sh = d;
+      }
+      __syncthreads();
+      avail = avail_sh;
+    }
+    for (int idx = tid; idx < kNB * NMAX; idx += TPB) {
+      const int k = idx / NMAX, c = idx % NMAX;
+      xs[k][c] = (k < cb && c < N) ? coherent_load(&B[(c0 + k) + int64_t(c) * ldb]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SEGW; ++q) {
+      const int col = sg * SEGW + q;
+      const double a = col < cb ? double(e[q]) : 0.0;
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) acc[c] += a * xs[col][c];
+    }
+    __syncthreads();
+  }
+
+  // ---- r = b_b - acc ----
+  double r[NMAX];
+  reduce(acc, r);
+  if (sg == 0) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) {
+      // rows beyond kb summed clamped loads: zero them
+      double bv;
+      if constexpr (PRE)
+        bv = bpre;
+      else
+        bv = (i < kb && c < N) ? B[(r0 + i) + int64_t(c) * ldb] : 0.0;
+      r[c] = (i < kb && c < N) ? bv - r[c] : 0.0;
+      xs[i][c] = r[c];
+    }
+  }
+  __syncthreads();
+
+  // product of the diagonal block's inverse with xs
+  auto prod_dinv = [&](double (&out)[NMAX]) {
+    double ev[SEGW];
+    if constexpr (PRE) {
+#pragma unroll
+      for (int q = 0; q < SEGW; ++q) ev[q] = dpre[q];
+    } else {
+      load_dinv(ev);
+    }
+    double a[NMAX];
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) a[c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < SEGW; ++q)
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) a[c] += ev[q] * xs[sg * SEGW + q][c];
+    reduce(a, out);
+  };
+
+  // ---- x = Di r ----
+  double x[NMAX];
+  prod_dinv(x);
+  if constexpr (REFINE) {
+    // res = r - T x ; x += Di res
+    if (sg == 0) {
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) xs[i][c] = x[c];
+    }
+    __syncthreads();
+    TF e[SEGW];
+    load_tdiag(e);
+    double a[NMAX];
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) a[c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < SEGW; ++q) {
+      const int jj = sg * SEGW + q;
+      double v = double(e[q]);
+      if (jj >= kb || i >= kb) v = 0.0;
+      else if (jj == i) v = UNIT ? 1.0 : v;
+      else if (FWD ? (jj > i) : (jj < i)) v = 0.0;
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) a[c] += v * xs[jj][c];
+    }
+    double tx[NMAX];
+    reduce(a, tx);
+    if (sg == 0) {
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) xs[i][c] = r[c] - tx[c];
+    }
+    __syncthreads();
+    double dx[NMAX];
+    prod_dinv(dx);
+    if (sg == 0) {
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) x[c] += dx[c];
+    }
+  }
+
+  // ---- publish x_b ----
+  if (sg == 0 && i < kb) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c)
+      if (c < N) coherent_store(&B[(r0 + i) + int64_t(c) * ldb], x[c]);
+  }
+  __threadfence();
+  __syncthreads();
+  // every block of a smaller ticket is published (this one consumed them
+  // all) and none of a larger ticket is, so done == t here
+  if (tid == 0)
+    __hip_atomic_store(done, int32_t(t + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_zero_i32(int32_t *p, int64_t count) {
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < count;
+       k += int64_t(gridDim.x) * blockDim.x)
+    p[k] = 0;
+}
+
+template <int NMAX, TriMode MODE, typename TF>
+hipError_t sweep_t(int64_t n, int N, const TF *LU, int64_t ld, const double *Winv, double *B,
+                   int64_t ldb, int32_t *sync, hipStream_t s) {
+  constexpr bool REFINE = std::is_same<TF, double>::value;
+  const int64_t nb = (n + kNB - 1) / kNB;
+  if (nb > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, sync, sweep_sync_ints(n));
+  hipLaunchKernelGGL((k_sweep<NMAX, MODE, TF, REFINE>), dim3(unsigned(nb)), dim3(TPB), 0, s, n, N,
+                     LU, ld, Winv, B, ldb, sync, nb);
+  return hipGetLastError();
+}
+
+template <int NMAX, typename TF>
+hipError_t sweep_n(TriMode mode, int64_t n, int N, const TF *LU, int64_t ld, const double *Winv,
+                   double *B, int64_t ldb, int32_t *sync, hipStream_t s) {
+  switch (mode) {
+    case TriMode::LN: return sweep_t<NMAX, TriMode::LN>(n, N, LU, ld, Winv, B, ldb, sync, s);
+    case TriMode::UN: return sweep_t<NMAX, TriMode::UN>(n, N, LU, ld, Winv, B, ldb, sync, s);
+    case TriMode::UT: return sweep_t<NMAX, TriMode::UT>(n, N, LU, ld, Winv, B, ldb, sync, s);
+    default: return sweep_t<NMAX, TriMode::LT>(n, N, LU, ld, Winv, B, ldb, sync, s);
+  }
+}
+
+template <typename TF>
+hipError_t sweep_any(TriMode mode, int64_t n, int64_t nrhs, const TF *LU, int64_t ld,
+                     const double *Winv, double *B, int64_t ldb, int32_t *sync, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return hipSuccess;
+  if (nrhs > kSkinnyMax || sync == nullptr) return hipErrorInvalidValue;
+  const int N = int(nrhs);
+  if (N <= 1) return sweep_n<1>(mode, n, N, LU, ld, Winv, B, ldb, sync, s);
+  if (N <= 4) return sweep_n<4>(mode, n, N, LU, ld, Winv, B, ldb, sync, s);
+  if (N <= 8) return sweep_n<8>(mode, n, N, LU, ld, Winv, B, ldb, sync, s);
+  return sweep_n<16>(mode, n, N, LU, ld, Winv, B, ldb, sync, s);
+}
+
+}  // namespace
+
+hipError_t launch_sweep(TriMode mode, int64_t n, int64_t nrhs, const double *LU, int64_t ld,
+                        const double *Winv, double *B, int64_t ldb, int32_t *sync,
+                        hipStream_t s) {
+  return sweep_any(mode, n, nrhs, LU, ld, Winv, B, ldb, sync, s);
+}
+hipError_t launch_sweep(TriMode mode, int64_t n, int64_t nrhs, const float *LU, int64_t ld,
+                        const double *Winv, double *B, int64_t ldb, int32_t *sync,
+                        hipStream_t s) {
+  return sweep_any(mode, n, nrhs, LU, ld, Winv, B, ldb, sync, s);
+}
+
+}  // namespace rbt

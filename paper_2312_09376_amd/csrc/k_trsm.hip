@@ -26,6 +26,10 @@
 //
 // MFMA: v_mfma_f64_16x16x4_f64 with the standard operand order; its output
 // element (lane l, v) is row l/16 + 4v, column l % 16.
+//
+// The triangle (TT) and the right-hand sides (TB) may be stored in FP32
+// (mixed-precision elimination); values are widened on load and all
+// arithmetic is FP64, rounded once on store.
 #include "internal.h"
 
 namespace rbt {
@@ -47,22 +51,26 @@ constexpr bool unit_diag() {
   return MODE == TriMode::LN || MODE == TriMode::LT;
 }
 
-// op(T)(i, j) read from global memory (i, j < kb).
-template <TriMode MODE>
-__device__ __forceinline__ double op_t(const double *T, int64_t ldt, int i, int j) {
+// op(T)(i, j) read from global memory (i, j < kb), in the stored type.
+// Loads are issued unconditionally at clamped valid indices and masked
+// afterwards, so that a batch of them is in flight together (a conditional
+// load per element, or a widening right after it, serializes them).
+template <TriMode MODE, typename TT>
+__device__ __forceinline__ TT op_t(const TT *T, int64_t ldt, int i, int j) {
   if constexpr (MODE == TriMode::LN || MODE == TriMode::UN)
     return T[i + int64_t(j) * ldt];
   else
     return T[j + int64_t(i) * ldt];
 }
+__device__ __forceinline__ int clampi(int v, int hi) { return v < hi ? v : hi; }
 
 // BATCH: blockIdx.y selects diagonal block b of an n x n factor (T and B
 // offset by b * kNB (1 + ldt) and b * bstride, kb = min(kNB, n - b kNB)), and
 // the right-hand side is the identity (X = op(T_bb)^-1): used to form the
 // inverses of the diagonal blocks once per factorization.
-template <TriMode MODE, bool BATCH>
-__global__ void __launch_bounds__(256, 2) k_trsm_left(int kb, int64_t N, const double *T,
-                                                      int64_t ldt, double *B, int64_t ldb,
+template <TriMode MODE, bool BATCH, typename TT, typename TB>
+__global__ void __launch_bounds__(256, 2) k_trsm_left(int kb, int64_t N, const TT *T,
+                                                      int64_t ldt, TB *B, int64_t ldb,
                                                       int64_t n, int64_t bstride) {
   if constexpr (BATCH) {
     const int64_t b = blockIdx.y;
@@ -82,32 +90,39 @@ __global__ void __launch_bounds__(256, 2) k_trsm_left(int kb, int64_t N, const d
 
   {  // stage the diagonal blocks (reciprocal on the diagonal of non-unit modes)
     const int i = threadIdx.x % IB, j = threadIdx.x / IB;
-    double v[NBK];
+    TT raw[NBK];
+#pragma unroll
+    for (int b = 0; b < NBK; ++b)
+      raw[b] = op_t<MODE>(T, ldt, clampi(IB * b + i, kb - 1), clampi(IB * b + j, kb - 1));
 #pragma unroll
     for (int b = 0; b < NBK; ++b) {
       const int gi = IB * b + i, gj = IB * b + j;
-      v[b] = (gi < kb && gj < kb) ? op_t<MODE>(T, ldt, gi, gj) : (i == j ? 1.0 : 0.0);
-    }
-#pragma unroll
-    for (int b = 0; b < NBK; ++b) {
-      if (!unit_diag<MODE>() && i == j) v[b] = 1.0 / v[b];
-      dblk[b * BLK + j * IB + i] = v[b];
+      double v = (gi < kb && gj < kb) ? double(raw[b]) : (i == j ? 1.0 : 0.0);
+      if (!unit_diag<MODE>() && i == j) v = 1.0 / v;
+      dblk[b * BLK + j * IB + i] = v;
     }
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {  // strip: lane = row (two halves), 16 columns
     const int row = lane + 64 * h;
-    double v[IB];
+    if constexpr (BATCH) {
 #pragma unroll
-    for (int c = 0; c < IB; ++c) {
-      const int64_t col = col0 + c;
-      if constexpr (BATCH)
-        v[c] = (row < kb && col < N && row == col) ? 1.0 : 0.0;
-      else
-        v[c] = (row < kb && col < N) ? B[row + col * ldb] : 0.0;
+      for (int c = 0; c < IB; ++c) {
+        const int64_t col = col0 + c;
+        strip[row * IB + c] = (row < kb && col < N && row == col) ? 1.0 : 0.0;
+      }
+    } else {
+      TB raw[IB];
+      const int64_t rr = clampi(row, kb - 1);
+#pragma unroll
+      for (int c = 0; c < IB; ++c) {
+        const int64_t col = col0 + c < N ? col0 + c : N - 1;
+        raw[c] = B[rr + col * ldb];
+      }
+#pragma unroll
+      for (int c = 0; c < IB; ++c)
+        strip[row * IB + c] = (row < kb && col0 + c < N) ? double(raw[c]) : 0.0;
     }
-#pragma unroll
-    for (int c = 0; c < IB; ++c) strip[row * IB + c] = v[c];
   }
   __syncthreads();
 
@@ -116,6 +131,16 @@ __global__ void __launch_bounds__(256, 2) k_trsm_left(int kb, int64_t N, const d
     const int I = FWD ? step : nbk - 1 - step;
     const int ia = IB * I + l16;
     // prefetch this step's off-diagonal operands: op(T)[ia][16 J + 4 kk + lk]
+    TT araw[NBK - 1][4];
+#pragma unroll
+    for (int s2 = 0; s2 < NBK - 1; ++s2) {
+      const int J = FWD ? s2 : nbk - 1 - s2;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int kx = IB * J + 4 * kk + lk;
+        araw[s2][kk] = op_t<MODE>(T, ldt, clampi(ia, kb - 1), clampi(kx < 0 ? 0 : kx, kb - 1));
+      }
+    }
     double a[NBK - 1][4];
 #pragma unroll
     for (int s2 = 0; s2 < NBK - 1; ++s2) {
@@ -123,7 +148,7 @@ __global__ void __launch_bounds__(256, 2) k_trsm_left(int kb, int64_t N, const d
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int kx = IB * J + 4 * kk + lk;
-        a[s2][kk] = (s2 < step && ia < kb && kx < kb) ? op_t<MODE>(T, ldt, ia, kx) : 0.0;
+        a[s2][kk] = (s2 < step && ia < kb && kx >= 0 && kx < kb) ? double(araw[s2][kk]) : 0.0;
       }
     }
     d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
@@ -180,13 +205,14 @@ __global__ void __launch_bounds__(256, 2) k_trsm_left(int kb, int64_t N, const d
 #pragma unroll
     for (int c = 0; c < IB; ++c) {
       const int64_t col = col0 + c;
-      if (row < kb && col < N) B[row + col * ldb] = strip[row * IB + c];
+      if (row < kb && col < N) B[row + col * ldb] = TB(strip[row * IB + c]);
     }
   }
 }
 
-__global__ void __launch_bounds__(256, 2) k_trsm_right_upper(int kb, int64_t M, const double *T,
-                                                             int64_t ldt, double *B,
+template <typename TT>
+__global__ void __launch_bounds__(256, 2) k_trsm_right_upper(int kb, int64_t M, const TT *T,
+                                                             int64_t ldt, TT *B,
                                                              int64_t ldb) {
   __shared__ double dblk[NBK * BLK];        // diagonal blocks of U, element (r,c) at r*16+c
   __shared__ double strip_all[4][NB * IB];  // per wavefront: column-major 16 x 128
@@ -197,32 +223,34 @@ __global__ void __launch_bounds__(256, 2) k_trsm_right_upper(int kb, int64_t M, 
 
   {
     const int r = threadIdx.x % IB, c = threadIdx.x / IB;
-    double v[NBK];
+    TT raw[NBK];
+#pragma unroll
+    for (int b = 0; b < NBK; ++b)
+      raw[b] = T[clampi(IB * b + r, kb - 1) + int64_t(clampi(IB * b + c, kb - 1)) * ldt];
 #pragma unroll
     for (int b = 0; b < NBK; ++b) {
       const int gi = IB * b + r, gj = IB * b + c;
-      v[b] = (gi < kb && gj < kb) ? T[gi + int64_t(gj) * ldt] : (r == c ? 1.0 : 0.0);
-    }
-#pragma unroll
-    for (int b = 0; b < NBK; ++b) {
-      if (r == c) v[b] = 1.0 / v[b];
-      dblk[b * BLK + r * IB + c] = v[b];
+      double v = (gi < kb && gj < kb) ? double(raw[b]) : (r == c ? 1.0 : 0.0);
+      if (r == c) v = 1.0 / v;
+      dblk[b * BLK + r * IB + c] = v;
     }
   }
   {
     // lane = (row r = lane % 16, column group lane / 16): columns cg + 4u
     const int r = lane % IB, cg = lane / IB;
     const int64_t row = row0 + r;
+    const int64_t rr = row < M ? row : M - 1;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      double v[16];
+      TT raw[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        raw[u] = B[rr + int64_t(clampi(cg + 4 * (16 * h + u), kb - 1)) * ldb];
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int c = cg + 4 * (16 * h + u);
-        v[u] = (row < M && c < kb) ? B[row + int64_t(c) * ldb] : 0.0;
+        strip[c * IB + r] = (row < M && c < kb) ? double(raw[u]) : 0.0;
       }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) strip[(cg + 4 * (16 * h + u)) * IB + r] = v[u];
     }
   }
   __syncthreads();
@@ -230,13 +258,20 @@ __global__ void __launch_bounds__(256, 2) k_trsm_right_upper(int kb, int64_t M, 
   const int nbk = (kb + IB - 1) / IB;
   for (int J = 0; J < nbk; ++J) {
     const int jc = IB * J + l16;  // column of U this lane feeds
+    TT braw[NBK - 1][4];
+#pragma unroll
+    for (int I = 0; I < NBK - 1; ++I) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        braw[I][kk] = T[clampi(IB * I + 4 * kk + lk, kb - 1) + int64_t(clampi(jc, kb - 1)) * ldt];
+    }
     double b[NBK - 1][4];
 #pragma unroll
     for (int I = 0; I < NBK - 1; ++I) {
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int kx = IB * I + 4 * kk + lk;
-        b[I][kk] = (I < J && kx < kb && jc < kb) ? T[kx + int64_t(jc) * ldt] : 0.0;
+        b[I][kk] = (I < J && kx < kb && jc < kb) ? double(braw[I][kk]) : 0.0;
       }
     }
     d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
@@ -281,48 +316,75 @@ __global__ void __launch_bounds__(256, 2) k_trsm_right_upper(int kb, int64_t M, 
 #pragma unroll
     for (int u = 0; u < 32; ++u) {
       const int c = cg + 4 * u;
-      if (row < M && c < kb) B[row + int64_t(c) * ldb] = strip[c * IB + r];
+      if (row < M && c < kb) B[row + int64_t(c) * ldb] = TT(strip[c * IB + r]);
     }
   }
+}
+
+template <typename TT, typename TB>
+hipError_t trsm_left_t(TriMode mode, int kb, int64_t N, const TT *T, int64_t ldt, TB *B,
+                       int64_t ldb, hipStream_t s) {
+  if (kb <= 0 || N <= 0) return hipSuccess;
+  if (kb > kNB) return hipErrorInvalidValue;
+  const dim3 grid(unsigned((N + 63) / 64));
+  const int64_t z = 0;
+  switch (mode) {
+    case TriMode::LN: hipLaunchKernelGGL((k_trsm_left<TriMode::LN, false, TT, TB>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, z, z); break;
+    case TriMode::UN: hipLaunchKernelGGL((k_trsm_left<TriMode::UN, false, TT, TB>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, z, z); break;
+    case TriMode::UT: hipLaunchKernelGGL((k_trsm_left<TriMode::UT, false, TT, TB>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, z, z); break;
+    case TriMode::LT: hipLaunchKernelGGL((k_trsm_left<TriMode::LT, false, TT, TB>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, z, z); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename TT>
+hipError_t diag_inverses_t(int64_t n, const TT *LU, int64_t ld, double *W, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = (n + NB - 1) / NB;
+  if (nb > 65535) return hipErrorInvalidValue;
+  const dim3 grid(2, unsigned(nb));  // 2 x 64 columns of each 128 x 128 block
+  // L^-1 at W + b * 2 kNB^2, U^-1 at W + b * 2 kNB^2 + kNB^2, each ld kNB
+  hipLaunchKernelGGL((k_trsm_left<TriMode::LN, true, TT, double>), grid, dim3(256), 0, s, NB,
+                     int64_t(NB), LU, ld, W, int64_t(NB), n, int64_t(2 * NB * NB));
+  hipLaunchKernelGGL((k_trsm_left<TriMode::UN, true, TT, double>), grid, dim3(256), 0, s, NB,
+                     int64_t(NB), LU, ld, W + NB * NB, int64_t(NB), n, int64_t(2 * NB * NB));
+  return hipGetLastError();
+}
+
+template <typename TT>
+hipError_t trsm_right_upper_t(int kb, int64_t M, const TT *T, int64_t ldt, TT *B, int64_t ldb,
+                              hipStream_t s) {
+  if (kb <= 0 || M <= 0) return hipSuccess;
+  if (kb > kNB) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_trsm_right_upper<TT>, dim3(unsigned((M + 63) / 64)), dim3(256), 0, s, kb,
+                     M, T, ldt, B, ldb);
+  return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_trsm_left(TriMode mode, int kb, int64_t N, const double *T, int64_t ldt,
                             double *B, int64_t ldb, hipStream_t s) {
-  if (kb <= 0 || N <= 0) return hipSuccess;
-  if (kb > kNB) return hipErrorInvalidValue;
-  const dim3 grid(unsigned((N + 63) / 64));
-  switch (mode) {
-    case TriMode::LN: hipLaunchKernelGGL((k_trsm_left<TriMode::LN, false>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, int64_t(0), int64_t(0)); break;
-    case TriMode::UN: hipLaunchKernelGGL((k_trsm_left<TriMode::UN, false>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, int64_t(0), int64_t(0)); break;
-    case TriMode::UT: hipLaunchKernelGGL((k_trsm_left<TriMode::UT, false>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, int64_t(0), int64_t(0)); break;
-    case TriMode::LT: hipLaunchKernelGGL((k_trsm_left<TriMode::LT, false>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, int64_t(0), int64_t(0)); break;
-  }
-  return hipGetLastError();
+  return trsm_left_t(mode, kb, N, T, ldt, B, ldb, s);
 }
-
+hipError_t launch_trsm_left(TriMode mode, int kb, int64_t N, const float *T, int64_t ldt, float *B,
+                            int64_t ldb, hipStream_t s) {
+  return trsm_left_t(mode, kb, N, T, ldt, B, ldb, s);
+}
 hipError_t launch_diag_inverses(int64_t n, const double *LU, int64_t ld, double *W,
                                 hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const int64_t nb = (n + NB - 1) / NB;
-  if (nb > 65535) return hipErrorInvalidValue;
-  const dim3 grid(2, unsigned(nb));  // 2 x 64 columns of each 128 x 128 block
-  // L^-1 at W + b * 2 kNB^2, U^-1 at W + b * 2 kNB^2 + kNB^2, each ld kNB
-  hipLaunchKernelGGL((k_trsm_left<TriMode::LN, true>), grid, dim3(256), 0, s, NB, int64_t(NB), LU,
-                     ld, W, int64_t(NB), n, int64_t(2 * NB * NB));
-  hipLaunchKernelGGL((k_trsm_left<TriMode::UN, true>), grid, dim3(256), 0, s, NB, int64_t(NB), LU,
-                     ld, W + NB * NB, int64_t(NB), n, int64_t(2 * NB * NB));
-  return hipGetLastError();
+  return diag_inverses_t(n, LU, ld, W, s);
 }
-
+hipError_t launch_diag_inverses(int64_t n, const float *LU, int64_t ld, double *W, hipStream_t s) {
+  return diag_inverses_t(n, LU, ld, W, s);
+}
 hipError_t launch_trsm_right_upper(int kb, int64_t M, const double *T, int64_t ldt, double *B,
                                    int64_t ldb, hipStream_t s) {
-  if (kb <= 0 || M <= 0) return hipSuccess;
-  if (kb > kNB) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_trsm_right_upper, dim3(unsigned((M + 63) / 64)), dim3(256), 0, s, kb, M,
-                     T, ldt, B, ldb);
-  return hipGetLastError();
+  return trsm_right_upper_t(kb, M, T, ldt, B, ldb, s);
+}
+hipError_t launch_trsm_right_upper(int kb, int64_t M, const float *T, int64_t ldt, float *B,
+                                   int64_t ldb, hipStream_t s) {
+  return trsm_right_upper_t(kb, M, T, ldt, B, ldb, s);
 }
 
 }  // namespace rbt

@@ -11,7 +11,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import RBT_FP32, RBT_FP64, RBT_OP_N, RBT_OP_T, check  # noqa: F401
+from ._lib import (RBT_BF16, RBT_FP32, RBT_FP64, RBT_IR_CLASSIC, RBT_IR_GMRES, RBT_OP_N,  # noqa: F401
+                   RBT_OP_T, check)
 
 
 def _colmajor_ld(t):
@@ -176,6 +177,33 @@ def solve_refine(A, B, depth=2, seed=2023, tol=None, max_iter=10, LU=None, X=Non
     check(lib().rbt_solve_refine(n, k, _p(A), _ld(A), _p(LU), _ld(LU), _p(B), _ld(B), _p(X), _ld(X),
                                  depth, seed, float(tol), int(max_iter), _p(iters), _p(berr),
                                  _p(info), _p(work), work.numel(), _stream(dev)), "rbt_solve_refine")
+    return X, LU, iters, berr, info, work
+
+
+def solve_mixed(A, B, depth=2, seed=2023, prec=RBT_FP32, solver=RBT_IR_CLASSIC, tol=None,
+                max_iter=30, LU=None, X=None, work=None):
+    """FP32 or BF16-update elimination of A~ with FP64 refinement.
+    A, B: FP64 (read only). Returns (X, LU (FP32 factors of A~), iters, berr, info, work)."""
+    A = colmajor(A)
+    B = colmajor(B)
+    _dev_f64(A, "A")
+    _dev_f64(B, "B")
+    n, k = A.shape[0], B.shape[1]
+    if tol is None:
+        tol = 10.0 * n * 2.0 ** -52
+    dev = A.device
+    LU = LU if LU is not None else torch.empty_strided((n, n), (1, max(1, n)), dtype=torch.float32, device=dev)
+    if LU.dtype != torch.float32:
+        raise TypeError("LU must be float32")
+    X = X if X is not None else torch.empty_strided((n, k), (1, max(1, n)), dtype=torch.float64, device=dev)
+    work = work if work is not None else _workspace(n, k, depth, dev, prec)
+    iters = torch.zeros(1, dtype=torch.int32, device=dev)
+    berr = torch.zeros(1, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    check(lib().rbt_solve_mixed(n, k, _p(A), _ld(A), _p(LU), _ld(LU), _p(B), _ld(B), _p(X), _ld(X),
+                                depth, seed, int(prec), int(solver), float(tol), int(max_iter),
+                                _p(iters), _p(berr), _p(info), _p(work), work.numel(),
+                                _stream(dev)), "rbt_solve_mixed")
     return X, LU, iters, berr, info, work
 
 

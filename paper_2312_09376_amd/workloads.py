@@ -47,6 +47,15 @@ def shifted(n, seed=MATRIX_SEED):
     return A
 
 
+def dominant(n, seed=MATRIX_SEED, scale=0.3):
+    """I + scale * N(0,1)/sqrt(n): eigenvalues within about `scale` of 1, so
+    the condition number stays O(1) at any n (a matrix every precision of the
+    mixed-precision path must refine to full FP64 accuracy)."""
+    A = scale * randn_matrix(n, seed) / math.sqrt(n)
+    A[np.diag_indices(n)] += 1.0
+    return A
+
+
 def orthog(n):
     i = np.arange(1, n + 1, dtype=np.float64)
     return np.asfortranarray(math.sqrt(2.0 / (n + 1)) * np.sin(np.outer(i, i) * math.pi / (n + 1)))
@@ -93,6 +102,26 @@ def device_hostile(n, seed=MATRIX_SEED, block=8, scale=1e-12, device="cuda"):
     A = device_randn(n, n, seed, device)
     b = min(block, n)
     A[:b, :b] *= scale
+    return A
+
+
+def device_logcond(n, seed=MATRIX_SEED, cond=1e6, reflectors=8, device="cuda"):
+    """Column-major Q1 diag(sigma) Q2^T on the device, sigma log-spaced from 1
+    to 1/cond, Q1, Q2 products of random Householder reflectors (as
+    `logcond`, with reflector vectors drawn on the device)."""
+    import torch
+    sigma = torch.logspace(0.0, -math.log10(cond), n, dtype=torch.float64, device=device)
+    A = torch.diag(sigma).t()          # column-major n x n
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    for side in range(2):
+        for _ in range(reflectors):
+            v = torch.randn(n, generator=g, device=device, dtype=torch.float64)
+            w = (2.0 / torch.dot(v, v)) * v
+            if side == 0:   # A <- (I - w v^T) A
+                A -= torch.outer(w, v @ A)
+            else:           # A <- A (I - v w^T)
+                A -= torch.outer(A @ v, w)
     return A
 
 

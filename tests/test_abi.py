@@ -78,6 +78,17 @@ def test_argument_errors(lib):
     assert lib.rbt_solve_refine(5, 1, dummy, 5, dummy, 5, dummy, 5, dummy, 5, 2, 0, -1.0, 3,
                                 None, None, None, dummy, 1 << 30, None) == -13
 
+    def mixed(prec=_lib.RBT_FP32, solver=_lib.RBT_IR_CLASSIC, tol=1e-10, depth=2, ldlu=5):
+        return lib.rbt_solve_mixed(5, 1, dummy, 5, dummy, ldlu, dummy, 5, dummy, 5, depth, 0, prec,
+                                   solver, tol, 3, None, None, None, dummy, 1 << 30, None)
+    assert mixed(prec=_lib.RBT_FP64) == -13
+    assert mixed(solver=7) == -14
+    assert mixed(tol=-1.0) == -15
+    assert mixed(ldlu=4) == -6
+    assert mixed(depth=4) == _lib.RBT_ERR_UNSUPPORTED
+    assert lib.rbt_workspace_size(1000, 1, 2, _lib.RBT_BF16) > 0
+    assert lib.rbt_workspace_size(1000, 1, 2, 9) == 0
+
 
 def test_workspace_size_monotone(lib):
     a = lib.rbt_workspace_size(1000, 1, 2, 0)

@@ -1,0 +1,133 @@
+"""GPU parity of the mixed-precision path (FP32 or BF16-update elimination of
+A~ = U^T A V, FP64 refinement with the original A) against the FP64 oracle.
+
+The low-precision factors are compared with the oracle's emulation
+(oracle/lowprec.py) only up to rounding-order tolerances; the final FP64
+solution is compared with the FP64 oracle solution, and the backward error
+with the refinement tolerance."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import coeffs, lowprec, solve as osolve, transform as otr
+from paper_2312_09376_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+EPS = 2.0 ** -52
+
+
+@pytest.fixture(scope="module")
+def rbt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_09376_amd import rbt as r
+    r.lib()
+    return r
+
+
+def dev(a):
+    a = np.asarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a[:, None]
+    return torch.from_numpy(np.ascontiguousarray(a.T)).cuda().t()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def relfro(a, b):
+    den = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,k,d", [(1, 1, 2), (5, 2, 2), (129, 1, 2), (300, 3, 1), (1003, 2, 2),
+                                   (777, 20, 3), (513, 1, 0)])
+def test_mixed_converges_to_oracle_solution(rbt, prec, n, k, d):
+    A = workloads.dominant(n, seed=n + 1)
+    B = workloads.randn(n, k, seed=3)
+    p = rbt.RBT_FP32 if prec == "fp32" else rbt.RBT_BF16
+    tol = 10 * n * EPS
+    X, LU, iters, berr, info, _ = rbt.solve_mixed(dev(A), dev(B), d, 2023, prec=p, tol=tol,
+                                                  max_iter=40)
+    assert int(info.item()) == 0
+    be = float(berr.item())
+    assert be <= tol, (be, int(iters.item()))
+    Uo, Vo = coeffs.generate(n, d, 2023)
+    Xo, _, _ = osolve.rbt_solve(A, B, Uo, Vo, d)
+    # both solutions are within kappa * (backward error) of A^-1 B
+    kappa = np.linalg.cond(A, np.inf)
+    assert relfro(host(X), Xo) <= 10 * kappa * tol
+    it = int(iters.item())
+    assert it <= (4 if prec == "fp32" else 12), it
+
+
+def test_mixed_fp32_factors_match_emulation(rbt):
+    n, d = 300, 2
+    A = workloads.dominant(n, seed=5)
+    B = workloads.randn(n, 1, seed=6)
+    _, LU, _, _, info, _ = rbt.solve_mixed(dev(A), dev(B), d, 2023, prec=rbt.RBT_FP32)
+    Uo, Vo = coeffs.generate(n, d, 2023)
+    At = otr.two_sided(A, Uo, Vo, d)
+    LUo, info_o = lowprec.genp_f32(At)
+    assert int(info.item()) == info_o == 0
+    LUg = host(LU).astype(np.float64)
+    assert relfro(LUg, LUo.astype(np.float64)) <= 2e-6
+    # reconstruction property at any size: || A~ - L U || / || A~ || ~ n u32
+    L = np.tril(LUg, -1) + np.eye(n)
+    Uf = np.triu(LUg)
+    assert relfro(L @ Uf, At) <= 1e-5
+
+
+def test_mixed_bf16_uses_bf16_operands(rbt):
+    """BF16 factors differ from the FP32 ones by about the BF16 unit roundoff
+    (and agree with the BF16 emulation to that order)."""
+    n, d = 600, 2
+    A = workloads.dominant(n, seed=8)
+    B = workloads.randn(n, 1, seed=9)
+    _, LU32, _, _, _, _ = rbt.solve_mixed(dev(A), dev(B), d, 2023, prec=rbt.RBT_FP32)
+    _, LU16, _, _, _, _ = rbt.solve_mixed(dev(A), dev(B), d, 2023, prec=rbt.RBT_BF16)
+    a32 = host(LU32).astype(np.float64)
+    a16 = host(LU16).astype(np.float64)
+    diff = relfro(a16, a32)
+    assert 1e-5 <= diff <= 2e-2, diff
+    Uo, Vo = coeffs.generate(n, d, 2023)
+    At = otr.two_sided(A, Uo, Vo, d)
+    LUe, _ = lowprec.genp_f32(At, bf16_update=True)
+    assert relfro(a16, LUe.astype(np.float64)) <= 1e-3
+
+
+def test_mixed_fp32_randn_refines_to_tolerance(rbt):
+    n = 512
+    A = workloads.randn_matrix(n, seed=42)
+    B = workloads.randn(n, 1, seed=64)
+    tol = 10 * n * EPS
+    X, _, iters, berr, info, _ = rbt.solve_mixed(dev(A), dev(B), 2, 2023, prec=rbt.RBT_FP32,
+                                                 tol=tol, max_iter=40)
+    assert int(info.item()) == 0
+    assert float(berr.item()) <= tol
+    Xe = np.linalg.solve(A, B)
+    kappa = np.linalg.cond(A, np.inf)
+    assert relfro(host(X), Xe) <= 20 * kappa * tol
+
+
+def test_mixed_zero_pivot_reports_info(rbt):
+    A = np.eye(200)
+    A[130, 130] = 0.0
+    A[130, 131] = 1.0
+    A[131, 130] = 1.0
+    B = np.ones((200, 1))
+    _, _, iters, berr, info, _ = rbt.solve_mixed(dev(A), dev(B), 0, 1, prec=rbt.RBT_FP32,
+                                                 max_iter=3)
+    assert int(info.item()) == 131
+    assert not (float(berr.item()) <= 1.0)  # NaN/Inf never looks converged
+    assert int(iters.item()) == 3
+
+
+def test_mixed_empty(rbt):
+    A = torch.empty_strided((0, 0), (1, 1), dtype=torch.float64, device="cuda")
+    B = torch.empty_strided((0, 1), (1, 1), dtype=torch.float64, device="cuda")
+    X, _, iters, berr, info, _ = rbt.solve_mixed(A, B, 2, 1)
+    assert int(iters.item()) == 0 and float(berr.item()) == 0.0
