@@ -1,5 +1,6 @@
 // C ABI entry points (include/rbt.h): argument checks, workspace carving and
 // the launch sequence of the method (Eq. 1 and the three steps under it).
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -66,24 +67,46 @@ inline int64_t nblocks(int64_t n) { return (n + kNB - 1) / kNB; }
 // diagonal blocks (for the few-right-hand-side solves) come first, so that
 // rbt_getrs and the composite entry points agree on where they live.
 struct Layout {
-  size_t winv, sync, coef, resid, partial, small, total;
-  size_t o_winv, o_sync, o_coef, o_resid, o_partial, o_small;
+  size_t winv, sync, coef, resid, partial, krylov, small, total;
+  size_t o_winv, o_sync, o_coef, o_resid, o_partial, o_krylov, o_small;
 };
 
-Layout layout(int64_t n, int64_t nrhs, int d) {
+// GMRES-IR: Krylov basis per restart cycle and the reduction of the
+// preconditioned residual that ends a cycle.
+constexpr int kGmresRestart = 50;
+constexpr double kGmresTau = 1e-10;
+
+int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
+
+// doubles of the GMRES work area: basis (restart + 1 blocks of n x 16), W,
+// and small per-column arrays (dots, second dots, norms, coefficients)
+size_t krylov_doubles(int64_t n) {
+  return size_t(kGmresRestart + 2) * n * kSkinnyMax + size_t(4 * (kGmresRestart + 2)) * kSkinnyMax;
+}
+
+// mixed: the mixed-precision entry point (GMRES work area; residual scratch
+// also for one group of <= 16 columns).
+Layout layout(int64_t n, int64_t nrhs, int d, bool mixed = false) {
   Layout L{};
   L.winv = align256(size_t(diag_inv_doubles(n)) * sizeof(double));
   L.sync = align256(size_t(sweep_sync_ints(n)) * sizeof(int32_t));
   L.coef = align256(size_t(2) * n * d * sizeof(double));
   L.resid = align256(size_t(n) * nrhs * sizeof(double));
-  L.partial = align256(resid_scratch_doubles(n, nrhs) * sizeof(double));
+  size_t part = resid_scratch_doubles(n, nrhs);
+  if (mixed) {
+    const size_t p16 = resid_scratch_doubles(n, min64(nrhs, kSkinnyMax));
+    part = part > p16 ? part : p16;
+  }
+  L.partial = align256(part * sizeof(double));
+  L.krylov = mixed ? align256(krylov_doubles(n) * sizeof(double)) : 0;
   L.small = 512;
   L.o_winv = 0;
   L.o_sync = L.o_winv + L.winv;
   L.o_coef = L.o_sync + L.sync;
   L.o_resid = L.o_coef + L.coef;
   L.o_partial = L.o_resid + L.resid;
-  L.o_small = L.o_partial + L.partial;
+  L.o_krylov = L.o_partial + L.partial;
+  L.o_small = L.o_krylov + L.krylov;
   L.total = L.o_small + L.small;
   return L;
 }
@@ -342,6 +365,160 @@ int refine_classic(int64_t n, int64_t nrhs, const double *A, int64_t lda, const 
   return 0;
 }
 
+// GMRES-IR: each refinement step solves A D = R (R = B - A X in FP64 with
+// the original A) by restarted GMRES in FP64, left-preconditioned by
+// M^-1 = V (LU)^-1 U^T (the solve of Eq. 1 with the low-precision factors),
+// and adds D to X. A cycle ends when the preconditioned residual estimate
+// of every column has dropped by kGmresTau, or after kGmresRestart
+// iterations; the refinement ends when the Eq. 7 backward error is <= tol
+// or max_iter Krylov iterations are spent. Columns are processed in groups
+// of <= kSkinnyMax with independent Krylov spaces; classical Gram-Schmidt
+// with one reorthogonalization; the small Hessenberg least-squares problems
+// (Givens rotations) are solved on the host, one synchronization per
+// iteration. *it_out = Krylov iterations of the group that needed most.
+template <typename TF>
+int refine_gmres(int64_t n, int64_t nrhs, const double *A, int64_t lda, const TF *LU,
+                 int64_t ldlu, const double *B, int64_t ldb, double *X, int64_t ldx,
+                 const Geometry &g, const double *U, const double *V, const double *winv,
+                 int32_t *sync, double *R, double *scratch, double *kry, double *anorm,
+                 double *berr, double tol, int max_iter, int *it_out, hipStream_t s) {
+  const int m = kGmresRestart;
+  const int64_t vs = n * kSkinnyMax;  // stride of basis blocks
+  double *Vb = kry;
+  double *W = Vb + (m + 1) * vs;
+  double *dots = W + vs;
+  double *dots2 = dots + (m + 2) * kSkinnyMax;
+  double *nrm = dots2 + (m + 2) * kSkinnyMax;
+  double *coef = nrm + (m + 2) * kSkinnyMax;
+  std::vector<double> hd((m + 2) * kSkinnyMax), hd2((m + 2) * kSkinnyMax), hn(kSkinnyMax);
+  std::vector<double> H, cs, sn, gv, beta, y;
+  std::vector<int> kc;
+  std::vector<char> active;
+  int worst = 0;
+  bool first = true;
+  auto residual = [&](int64_t nc, double *Xc, const double *Bc) -> int {
+    StageScope t(kStageResidual, s, 8.0 * double(n) * n);
+    RBT_HIP_CHECK(launch_residual_berr(n, nc, A, lda, Xc, ldx, Bc, ldb, R, n, first, scratch,
+                                       anorm, berr, s));
+    first = false;
+    return 0;
+  };
+  for (int64_t c0 = 0; c0 < nrhs; c0 += kSkinnyMax) {
+    const int nc = int(min64(kSkinnyMax, nrhs - c0));
+    double *Xc = X + c0 * ldx;
+    const double *Bc = B + c0 * ldb;
+    int total = 0;
+    for (;;) {
+      int rc = residual(nc, Xc, Bc);
+      if (rc) return rc;
+      double be = 0.0;
+      RBT_HIP_CHECK(hipMemcpyAsync(&be, berr, sizeof(double), hipMemcpyDeviceToHost, s));
+      RBT_HIP_CHECK(hipStreamSynchronize(s));
+      if (be <= tol || total >= max_iter) break;
+      // z = M^-1 r, v_0 = z / ||z||
+      rc = apply_solve(g, nc, LU, ldlu, R, n, U, V, winv, sync, s);
+      if (rc) return rc;
+      RBT_HIP_CHECK(launch_coldots(n, nc, 1, R, 0, R, n, nrm, s));
+      RBT_HIP_CHECK(launch_colscale(n, nc, R, n, nrm, Vb, s));
+      RBT_HIP_CHECK(hipMemcpyAsync(hn.data(), nrm, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+      RBT_HIP_CHECK(hipStreamSynchronize(s));
+      H.assign(size_t(nc) * (m + 1) * m, 0.0);
+      cs.assign(size_t(nc) * m, 0.0);
+      sn.assign(size_t(nc) * m, 0.0);
+      gv.assign(size_t(nc) * (m + 1), 0.0);
+      beta.assign(nc, 0.0);
+      kc.assign(nc, 0);
+      active.assign(nc, 0);
+      for (int c = 0; c < nc; ++c) {
+        beta[c] = hn[c] > 0.0 ? std::sqrt(hn[c]) : 0.0;
+        gv[size_t(c) * (m + 1)] = beta[c];
+        active[c] = beta[c] > 0.0;
+      }
+      for (int j = 0; j < m && total < max_iter; ++j) {
+        double *Vj = Vb + j * vs;
+        {
+          StageScope t(kStageResidual, s, 8.0 * double(n) * n);
+          RBT_HIP_CHECK(launch_matvec(n, nc, A, lda, Vj, n, W, n, scratch, s));
+        }
+        rc = apply_solve(g, nc, LU, ldlu, W, n, U, V, winv, sync, s);
+        if (rc) return rc;
+        RBT_HIP_CHECK(launch_coldots(n, nc, j + 1, Vb, vs, W, n, dots, s));
+        RBT_HIP_CHECK(launch_colcombo(n, nc, j + 1, Vb, vs, dots, -1.0, W, n, s));
+        RBT_HIP_CHECK(launch_coldots(n, nc, j + 1, Vb, vs, W, n, dots2, s));
+        RBT_HIP_CHECK(launch_colcombo(n, nc, j + 1, Vb, vs, dots2, -1.0, W, n, s));
+        RBT_HIP_CHECK(launch_coldots(n, nc, 1, W, 0, W, n, nrm, s));
+        RBT_HIP_CHECK(launch_colscale(n, nc, W, n, nrm, Vb + (j + 1) * vs, s));
+        RBT_HIP_CHECK(hipMemcpyAsync(hd.data(), dots, (j + 1) * nc * sizeof(double),
+                                     hipMemcpyDeviceToHost, s));
+        RBT_HIP_CHECK(hipMemcpyAsync(hd2.data(), dots2, (j + 1) * nc * sizeof(double),
+                                     hipMemcpyDeviceToHost, s));
+        RBT_HIP_CHECK(hipMemcpyAsync(hn.data(), nrm, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+        RBT_HIP_CHECK(hipStreamSynchronize(s));
+        ++total;
+        bool all_done = true;
+        for (int c = 0; c < nc; ++c) {
+          if (!active[c]) continue;
+          double *h = &H[(size_t(c) * m + j) * (m + 1)];  // column j of column c's Hessenberg
+          for (int i = 0; i <= j; ++i) h[i] = hd[i * nc + c] + hd2[i * nc + c];
+          h[j + 1] = hn[c] > 0.0 ? std::sqrt(hn[c]) : 0.0;
+          double *csc = &cs[size_t(c) * m], *snc = &sn[size_t(c) * m];
+          double *gc = &gv[size_t(c) * (m + 1)];
+          for (int i = 0; i < j; ++i) {
+            const double t0 = csc[i] * h[i] + snc[i] * h[i + 1];
+            h[i + 1] = -snc[i] * h[i] + csc[i] * h[i + 1];
+            h[i] = t0;
+          }
+          const double den = std::hypot(h[j], h[j + 1]);
+          csc[j] = den > 0.0 ? h[j] / den : 1.0;
+          snc[j] = den > 0.0 ? h[j + 1] / den : 0.0;
+          const double sub = h[j + 1];
+          h[j] = den;
+          h[j + 1] = 0.0;
+          gc[j + 1] = -snc[j] * gc[j];
+          gc[j] = csc[j] * gc[j];
+          kc[c] = j + 1;
+          if (!(std::fabs(gc[j + 1]) > kGmresTau * beta[c]) || sub == 0.0 || den == 0.0)
+            active[c] = 0;
+          else
+            all_done = false;
+        }
+        if (all_done) break;
+      }
+      // y = R^-1 g per column (upper triangular, size kc[c]); X += V y
+      int kmax = 0;
+      y.assign(size_t(m + 1) * nc, 0.0);
+      for (int c = 0; c < nc; ++c) {
+        const int k = kc[c];
+        kmax = k > kmax ? k : kmax;
+        const double *gc = &gv[size_t(c) * (m + 1)];
+        for (int i = k - 1; i >= 0; --i) {
+          double acc = gc[i];
+          for (int l = i + 1; l < k; ++l)
+            acc -= H[(size_t(c) * m + l) * (m + 1) + i] * y[size_t(l) * nc + c];
+          const double d = H[(size_t(c) * m + i) * (m + 1) + i];
+          y[size_t(i) * nc + c] = d != 0.0 ? acc / d : 0.0;
+        }
+      }
+      if (kmax > 0) {
+        RBT_HIP_CHECK(hipMemcpyAsync(coef, y.data(), size_t(kmax) * nc * sizeof(double),
+                                     hipMemcpyHostToDevice, s));
+        RBT_HIP_CHECK(launch_colcombo(n, nc, kmax, Vb, vs, coef, 1.0, Xc, ldx, s));
+        // y must stay valid until the copy has run: the residual that starts
+        // the next step synchronizes the stream
+      } else {
+        break;  // no progress possible (zero preconditioned residual)
+      }
+    }
+    worst = total > worst ? total : worst;
+  }
+  if (nrhs > kSkinnyMax) {  // backward error over all columns
+    const int rc = residual(nrhs, X, B);
+    if (rc) return rc;
+  }
+  *it_out = worst;
+  return 0;
+}
+
 bool bad_depth(int d) { return d < 0 || d > RBT_MAX_DEPTH; }
 
 }  // namespace
@@ -352,7 +529,7 @@ using namespace rbt;
 extern "C" size_t rbt_workspace_size(int64_t n, int64_t nrhs, int depth, int precision) {
   if (n < 0 || nrhs < 0 || bad_depth(depth)) return 0;
   if (precision != RBT_FP64 && precision != RBT_FP32 && precision != RBT_BF16) return 0;
-  return layout(n, nrhs, depth).total;
+  return layout(n, nrhs, depth, precision != RBT_FP64).total;
 }
 
 extern "C" int rbt_generate_device(int64_t n, int depth, uint64_t seed, double *dU, double *dV,
@@ -570,8 +747,7 @@ extern "C" int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t
   if (!(tol >= 0.0)) return -15;
   if (max_iter < 0) return -16;
   if (depth > 3) return RBT_ERR_UNSUPPORTED;  // the FP32-output transform is one pass
-  if (solver == RBT_IR_GMRES) return RBT_ERR_UNSUPPORTED;
-  const Layout L = layout(n, nrhs, depth);
+  const Layout L = layout(n, nrhs, depth, true);
   if (n > 0 && work == nullptr) return -20;
   if (work_bytes < L.total) return RBT_ERR_WORKSPACE;
   hipStream_t s = S(stream);
@@ -608,8 +784,13 @@ extern "C" int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t
   rc = apply_solve(g, nrhs, (const float *)LU, ldlu, X, ldx, U, V, winv, sync, s);
   if (rc) return rc;
   int it = 0;
-  rc = refine_classic(n, nrhs, A, lda, (const float *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv, sync, R,
-                      scratch, anorm, berr, tol, max_iter, &it, s);
+  if (solver == RBT_IR_GMRES)
+    rc = refine_gmres(n, nrhs, A, lda, (const float *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv,
+                      sync, R, scratch, at<double>(work, L.o_krylov), anorm, berr, tol, max_iter,
+                      &it, s);
+  else
+    rc = refine_classic(n, nrhs, A, lda, (const float *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv,
+                        sync, R, scratch, anorm, berr, tol, max_iter, &it, s);
   if (rc) return rc;
   if (iters_dev) {
     RBT_HIP_CHECK(hipMemcpyAsync(iters_dev, &it, sizeof(int32_t), hipMemcpyHostToDevice, s));

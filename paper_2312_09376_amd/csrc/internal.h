@@ -130,19 +130,11 @@ hipError_t launch_diag_inverses(int64_t n, const float *LU, int64_t ld, double *
 inline int64_t diag_inv_doubles(int64_t n) { return ((n + kNB - 1) / kNB) * 2 * kNB * kNB; }
 
 // k_solve.hip
-constexpr int64_t kSkinnyMax = 16;  // right-hand sides handled by the FMA kernels
-// Y (M x N) -= op(A) (M x K) X (K x N), N <= kSkinnyMax, K <= kNB
-hipError_t launch_skinny_update(int64_t M, int64_t N, int K, const double *A, int64_t lda,
-                                bool trans, const double *X, int64_t ldx, double *Y, int64_t ldy,
-                                hipStream_t s);
-// Triangular sweep with op(A) of the factors for nrhs <= kSkinnyMax, using
-// the diagonal-block inverses of launch_diag_inverses (one launch per block).
-hipError_t launch_trsv_sweep(TriMode mode, int64_t n, int64_t nrhs, const double *LU, int64_t ld,
-                             const double *Winv, double *B, int64_t ldb, hipStream_t s);
-hipError_t launch_trsv_sweep(TriMode mode, int64_t n, int64_t nrhs, const float *LU, int64_t ld,
-                             const double *Winv, double *B, int64_t ldb, hipStream_t s);
-// k_sweep.hip : the same sweeps as ONE persistent launch (ticket-ordered
-// block rows, a published-blocks counter). sync: sweep_sync_ints(n) int32
+constexpr int64_t kSkinnyMax = 16;  // right-hand sides handled by the sweeps and FMA kernels
+// k_sweep.hip : triangular sweep with op(A) of the factors for
+// nrhs <= kSkinnyMax, using the diagonal-block inverses of
+// launch_diag_inverses, as ONE persistent launch (ticket-ordered block rows,
+// a published-blocks counter). sync: sweep_sync_ints(n) int32
 // of device scratch (cleared by the launch itself); FP64 factors take one
 // refinement step per diagonal block, FP32 factors the inverse alone.
 inline int64_t sweep_sync_ints(int64_t /*n*/) { return 4; }
@@ -158,6 +150,20 @@ hipError_t launch_residual_berr(int64_t n, int64_t nrhs, const double *A, int64_
                                 const double *X, int64_t ldx, const double *B, int64_t ldb,
                                 double *R, int64_t ldr, bool with_anorm, double *scratch,
                                 double *anorm, double *berr, hipStream_t s);
+// Y = A X (n x nrhs, nrhs <= kSkinnyMax); scratch as launch_residual_berr.
+hipError_t launch_matvec(int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *X,
+                         int64_t ldx, double *Y, int64_t ldy, double *scratch, hipStream_t s);
+// Krylov vector operations on N <= kSkinnyMax independent columns; basis
+// vector i, column c at V[i * vs + c * n + m].
+// out[i * N + c] = <V_i[:, c], W[:, c]> for i < J
+hipError_t launch_coldots(int64_t n, int N, int J, const double *V, int64_t vs, const double *W,
+                          int64_t ldw, double *out, hipStream_t s);
+// W[:, c] += sign * sum_{i < J} coef[i * N + c] V_i[:, c]
+hipError_t launch_colcombo(int64_t n, int N, int J, const double *V, int64_t vs,
+                           const double *coef, double sign, double *W, int64_t ldw, hipStream_t s);
+// O[:, c] (ld n) = W[:, c] / sqrt(nrm2[c]), or 0 when nrm2[c] <= 0
+hipError_t launch_colscale(int64_t n, int N, const double *W, int64_t ldw, const double *nrm2,
+                           double *O, hipStream_t s);
 hipError_t launch_axpy_cols(int64_t n, int64_t nrhs, const double *D, int64_t ldd, double *X,
                             int64_t ldx, hipStream_t s);
 hipError_t launch_copy_cols(int64_t n, int64_t nrhs, const double *S, int64_t lds, double *D,

@@ -1,7 +1,7 @@
-// Kernels around the solve for few right-hand sides: block updates of the
-// triangular solves, the residual B - A X with the row sums of |A| for
-// ||A||_inf fused into the same pass over A, the backward error of Eq. 7,
-// and the column updates of iterative refinement (Sec. 5).
+// Kernels around the solve: the residual B - A X with the row sums of |A|
+// for ||A||_inf fused into the same pass over A, the backward error of
+// Eq. 7, the column updates of iterative refinement (Sec. 5) and the
+// outer product of the adjoint.
 //
 // These are HBM-bound (one read of the matrix, a few columns of output), so
 // they run as plain FMA kernels with lanes along rows (coalesced column
@@ -15,225 +15,6 @@ namespace {
 
 constexpr int kRows = 256;       // rows per workgroup
 constexpr int64_t kChunk = 256;  // columns per split-K chunk of the residual
-
-// Y (M x N) -= op(A) (M x K) X (K x N), N <= NMAX <= 16, K <= kNB.
-// TRANS: op(A)(m, k) = A[k + m lda] (transposed storage).
-template <int NMAX, bool TRANS>
-__global__ void __launch_bounds__(kRows) k_skinny_update(int64_t M, int N, int K,
-                                                         const double *__restrict__ A,
-                                                         int64_t lda,
-                                                         const double *__restrict__ X,
-                                                         int64_t ldx, double *Y, int64_t ldy) {
-  __shared__ double xs[kNB][NMAX];
-  for (int idx = threadIdx.x; idx < K * NMAX; idx += kRows) {
-    const int k = idx / NMAX, n = idx % NMAX;
-    xs[k][n] = n < N ? X[k + int64_t(n) * ldx] : 0.0;
-  }
-  __syncthreads();
-  const int64_t m = int64_t(blockIdx.x) * kRows + threadIdx.x;
-  if (m >= M) return;
-  double acc[NMAX];
-#pragma unroll
-  for (int n = 0; n < NMAX; ++n) acc[n] = 0.0;
-#pragma unroll 8
-  for (int k = 0; k < K; ++k) {
-    const double a = TRANS ? A[k + m * lda] : A[m + int64_t(k) * lda];
-#pragma unroll
-    for (int n = 0; n < NMAX; ++n) acc[n] += a * xs[k][n];
-  }
-#pragma unroll
-  for (int n = 0; n < NMAX; ++n)
-    if (n < N) Y[m + int64_t(n) * ldy] -= acc[n];
-}
-
-// One step of a blocked triangular sweep for few right-hand sides
-// (N <= NMAX), used by the solves after the elimination. Block `cur` of the
-// solution is final (cur < 0: none yet); this launch
-//   - workgroup 0: subtracts block cur's contribution from block `nxt` and
-//     solves block nxt with the precomputed inverse of its diagonal block and
-//     one step of refinement, x = Di r, x += Di (r - T x), which keeps the
-//     backward error of substitution (the inverse alone does not);
-//   - workgroups 1..: subtract block cur's contribution from the rows beyond
-//     block nxt (below it for forward sweeps, above it for backward ones).
-// op(A)(m, k) of the four sweeps, A = the L\U factors (ld):
-//   LN L (forward), UN U (backward), UT U^T (forward), LT L^T (backward).
-// Dinv: LN L^-1, UN U^-1 (stored), UT (U^-1)^T, LT (L^-1)^T (read transposed).
-// The factors may be stored in FP32 (mixed precision): they are widened on
-// load and every sum is FP64.
-// Loads return the stored type; callers batch a chunk of loads before
-// widening any of them (a widening right after each load makes the compiler
-// wait for every load in turn).
-template <TriMode MODE, typename TF>
-__device__ __forceinline__ TF op_a(const TF *A, int64_t ld, int64_t m, int64_t k) {
-  if constexpr (MODE == TriMode::LN || MODE == TriMode::UN)
-    return A[m + k * ld];
-  else
-    return A[k + m * ld];
-}
-
-template <int NMAX, TriMode MODE, typename TF>
-__global__ void __launch_bounds__(kRows) k_trsv_step(int64_t n, int N, const TF *A,
-                                                     int64_t ld, const double *Winv, double *B,
-                                                     int64_t ldb, int64_t cur, int64_t nxt) {
-  constexpr bool FWD = (MODE == TriMode::LN || MODE == TriMode::UT);
-  constexpr bool UNIT = (MODE == TriMode::LN || MODE == TriMode::LT);
-  constexpr int H = kNB / 2;  // each half-workgroup covers 64 of the 128 columns
-  __shared__ double xs[kNB][NMAX];        // block cur of the solution
-  __shared__ double vs[kNB][NMAX];        // operand vector of the current product
-  __shared__ double part[2][kNB][NMAX];   // half sums
-  const int t = threadIdx.x;
-  const int64_t c0 = cur * kNB;
-  const int cb = cur < 0 ? 0 : int(n - c0 < kNB ? n - c0 : kNB);
-  for (int idx = t; idx < kNB * NMAX; idx += kRows) {
-    const int k = idx / NMAX, c = idx % NMAX;
-    xs[k][c] = (k < cb && c < N) ? B[(c0 + k) + int64_t(c) * ldb] : 0.0;
-  }
-  __syncthreads();
-
-  if (blockIdx.x > 0) {
-    // rows beyond block nxt: B[m] -= op(A)[m, block cur] x_cur
-    int64_t m;
-    if (FWD) {
-      m = (nxt + 1) * kNB + int64_t(blockIdx.x - 1) * kRows + t;
-      if (m >= n) return;
-    } else {
-      m = int64_t(blockIdx.x - 1) * kRows + t;
-      if (m >= nxt * kNB) return;
-    }
-    double acc[NMAX];
-#pragma unroll
-    for (int c = 0; c < NMAX; ++c) acc[c] = 0.0;
-    // cur >= 0 here, so cb >= 1: loads use clamped (valid) columns and the
-    // mask is applied after the load, which keeps each chunk's 16 loads in
-    // flight together
-    for (int k0 = 0; k0 < kNB; k0 += 16) {
-      TF raw[16];
-#pragma unroll
-      for (int jj = 0; jj < 16; ++jj) {
-        const int kc = k0 + jj < cb ? k0 + jj : cb - 1;
-        const TF v = op_a<MODE>(A, ld, m, c0 + kc);
-        raw[jj] = (k0 + jj < cb) ? v : TF(0);
-      }
-#pragma unroll
-      for (int jj = 0; jj < 16; ++jj) {
-        const double a = double(raw[jj]);
-#pragma unroll
-        for (int c = 0; c < NMAX; ++c) acc[c] += a * xs[k0 + jj][c];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < NMAX; ++c)
-      if (c < N) B[m + int64_t(c) * ldb] -= acc[c];
-    return;
-  }
-
-  // ---- workgroup 0: block nxt ----
-  const int64_t r0 = nxt * kNB;
-  const int kb = int(n - r0 < kNB ? n - r0 : kNB);
-  const double *Di = Winv + nxt * 2 * kNB * kNB +
-                     ((MODE == TriMode::LN || MODE == TriMode::LT) ? 0 : kNB * kNB);
-  const int i = t & (kNB - 1), h = t >> 7;  // row, column half
-  const bool row = i < kb;
-  // Half-sum of a 128 x 128 product with vector vec (LDS), entry(i, j) given.
-  auto half_product = [&](auto entry, const double (*vec)[NMAX]) {
-    double acc[NMAX];
-#pragma unroll
-    for (int c = 0; c < NMAX; ++c) acc[c] = 0.0;
-    auto chunk = [&](int q) {  // a batch of 16 independent loads
-      decltype(entry(0, 0)) e[16];
-#pragma unroll
-      for (int jj = 0; jj < 16; ++jj) e[jj] = entry(i, H * h + q + jj);
-#pragma unroll
-      for (int jj = 0; jj < 16; ++jj)
-#pragma unroll
-        for (int c = 0; c < NMAX; ++c) acc[c] += double(e[jj]) * vec[H * h + q + jj][c];
-    };
-    if constexpr (NMAX == 1) {
-#pragma unroll
-      for (int q = 0; q < H; q += 16) chunk(q);
-    } else {
-#pragma nounroll
-      for (int q = 0; q < H; q += 16) chunk(q);
-    }
-#pragma unroll
-    for (int c = 0; c < NMAX; ++c) part[h][i][c] = acc[c];
-  };
-  // product entries (zero outside the valid block / triangle); every load
-  // is unconditional at a clamped valid address and masked afterwards
-  // (kb >= 1; e_cross is only used when cb >= 1; Di blocks are full
-  // kNB x kNB allocations whose entries beyond kb are never used)
-  const int kl = kb - 1;
-  auto e_cross = [&](int ii, int jj) -> TF {
-    const TF v = op_a<MODE>(A, ld, r0 + (ii < kb ? ii : kl), c0 + (jj < cb ? jj : cb - 1));
-    return (ii < kb && jj < cb) ? v : TF(0);
-  };
-  auto e_dinv = [&](int ii, int jj) -> double {
-    const double v =
-        (MODE == TriMode::LN || MODE == TriMode::UN) ? Di[ii + jj * kNB] : Di[jj + ii * kNB];
-    return (ii < kb && jj < kb) ? v : 0.0;
-  };
-  auto e_tdiag = [&](int ii, int jj) -> TF {
-    const TF v = op_a<MODE>(A, ld, r0 + (ii < kb ? ii : kl), r0 + (jj < kb ? jj : kl));
-    if (ii >= kb || jj >= kb) return TF(0);
-    if (ii == jj) return UNIT ? TF(1) : v;
-    if (FWD ? (jj > ii) : (jj < ii)) return TF(0);
-    return v;
-  };
-
-  // r = b - op(A)[nxt, cur] x_cur  -> vs
-  if (cb > 0) {
-    half_product(e_cross, xs);
-  } else {
-#pragma unroll
-    for (int c = 0; c < NMAX; ++c) part[h][i][c] = 0.0;
-  }
-  __syncthreads();
-  double r[NMAX];
-  if (h == 0) {
-#pragma unroll
-    for (int c = 0; c < NMAX; ++c) {
-      const double bv = (row && c < N) ? B[(r0 + i) + int64_t(c) * ldb] : 0.0;
-      r[c] = bv - (part[0][i][c] + part[1][i][c]);
-      vs[i][c] = r[c];
-    }
-  }
-  __syncthreads();
-  // x = Di r
-  half_product(e_dinv, vs);
-  __syncthreads();
-  double x[NMAX];
-  if (h == 0) {
-#pragma unroll
-    for (int c = 0; c < NMAX; ++c) x[c] = part[0][i][c] + part[1][i][c];
-  }
-  __syncthreads();
-  if (h == 0) {
-#pragma unroll
-    for (int c = 0; c < NMAX; ++c) vs[i][c] = x[c];
-  }
-  __syncthreads();
-  // res = r - T x
-  half_product(e_tdiag, vs);
-  __syncthreads();
-  if (h == 0) {
-#pragma unroll
-    for (int c = 0; c < NMAX; ++c) r[c] -= part[0][i][c] + part[1][i][c];
-  }
-  __syncthreads();
-  if (h == 0) {
-#pragma unroll
-    for (int c = 0; c < NMAX; ++c) vs[i][c] = r[c];
-  }
-  __syncthreads();
-  // x += Di res
-  half_product(e_dinv, vs);
-  __syncthreads();
-  if (h == 0 && row) {
-#pragma unroll
-    for (int c = 0; c < NMAX; ++c)
-      if (c < N) B[(r0 + i) + int64_t(c) * ldb] = x[c] + (part[0][i][c] + part[1][i][c]);
-  }
-}
 
 // partial[(c N + n) M + m] = sum_{k in chunk c} A[m, k] X[k, n];
 // ABS: abspart[c M + m] = sum_{k in chunk c} |A[m, k]|.
@@ -512,19 +293,69 @@ __global__ void k_fill_f64(double *p, double v) {
   if (threadIdx.x == 0) p[0] = v;
 }
 
-dim3 col_grid(int64_t n, int64_t nrhs) {
-  return dim3(unsigned((n + kRows - 1) / kRows), unsigned(nrhs < 65535 ? nrhs : 65535));
+// Y[m, n] = sum over split-K chunks of partial (the product A X of
+// k_gemv_partial without the residual).
+template <int NMAX>
+__global__ void __launch_bounds__(kRows) k_gemv_sum(int64_t M, int N, int64_t chunks,
+                                                    const double *__restrict__ partial,
+                                                    double *__restrict__ Y, int64_t ldy) {
+  const int64_t m = int64_t(blockIdx.x) * kRows + threadIdx.x;
+  if (m >= M) return;
+  for (int n = 0; n < N; ++n) {
+    double s = 0.0;
+    for (int64_t c = 0; c < chunks; ++c) s += partial[(c * N + n) * M + m];
+    Y[m + int64_t(n) * ldy] = s;
+  }
 }
 
-template <int NMAX>
-hipError_t skinny_t(int64_t M, int N, int K, const double *A, int64_t lda, bool trans,
-                    const double *X, int64_t ldx, double *Y, int64_t ldy, hipStream_t s) {
-  const dim3 grid(unsigned((M + kRows - 1) / kRows));
-  if (trans)
-    hipLaunchKernelGGL((k_skinny_update<NMAX, true>), grid, dim3(kRows), 0, s, M, N, K, A, lda, X, ldx, Y, ldy);
-  else
-    hipLaunchKernelGGL((k_skinny_update<NMAX, false>), grid, dim3(kRows), 0, s, M, N, K, A, lda, X, ldx, Y, ldy);
-  return hipGetLastError();
+// Krylov vector kernels (GMRES in FP64 on column blocks of <= kSkinnyMax
+// independent columns; basis vector i of column c at V[i * vs + c * n + m]).
+// out[i * N + c] = <V_i[:, c], W[:, c]>, one workgroup per (i, c).
+__global__ void __launch_bounds__(kRows) k_coldots(int64_t n, int N, const double *__restrict__ V,
+                                                   int64_t vs, const double *__restrict__ W,
+                                                   int64_t ldw, double *__restrict__ out) {
+  __shared__ double sh[kRows];
+  const int i = blockIdx.x, c = blockIdx.y;
+  const double *v = V + int64_t(i) * vs + int64_t(c) * n;
+  const double *w = W + int64_t(c) * ldw;
+  double acc = 0.0;
+  for (int64_t m = threadIdx.x; m < n; m += kRows) acc += v[m] * w[m];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = kRows / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i * N + c] = sh[0];
+}
+
+// W[:, c] += sign * sum_{i < J} coef[i * N + c] V_i[:, c]
+__global__ void __launch_bounds__(kRows) k_colcombo(int64_t n, int N, int J,
+                                                    const double *__restrict__ V, int64_t vs,
+                                                    const double *__restrict__ coef, double sign,
+                                                    double *__restrict__ W, int64_t ldw) {
+  const int64_t m = int64_t(blockIdx.x) * kRows + threadIdx.x;
+  const int c = blockIdx.y;
+  if (m >= n) return;
+  double acc = 0.0;
+  for (int i = 0; i < J; ++i) acc += coef[i * N + c] * V[int64_t(i) * vs + int64_t(c) * n + m];
+  W[m + int64_t(c) * ldw] += sign * acc;
+}
+
+// O[:, c] = W[:, c] / sqrt(nrm2[c]) (zero when nrm2[c] is not positive:
+// a column whose Krylov space is exhausted contributes nothing more).
+__global__ void __launch_bounds__(kRows) k_colscale(int64_t n, const double *__restrict__ W,
+                                                    int64_t ldw, const double *__restrict__ nrm2,
+                                                    double *__restrict__ O) {
+  const int64_t m = int64_t(blockIdx.x) * kRows + threadIdx.x;
+  const int c = blockIdx.y;
+  if (m >= n) return;
+  const double q = nrm2[c];
+  O[m + int64_t(c) * n] = q > 0.0 ? W[m + int64_t(c) * ldw] / sqrt(q) : 0.0;
+}
+
+dim3 col_grid(int64_t n, int64_t nrhs) {
+  return dim3(unsigned((n + kRows - 1) / kRows), unsigned(nrhs < 65535 ? nrhs : 65535));
 }
 
 template <int NMAX>
@@ -547,55 +378,7 @@ hipError_t resid_t(int64_t n, int N, const double *A, int64_t lda, const double 
   return hipGetLastError();
 }
 
-template <int NMAX, TriMode MODE, typename TF>
-hipError_t trsv_sweep_t(int64_t n, int N, const TF *LU, int64_t ld, const double *Winv,
-                        double *B, int64_t ldb, hipStream_t s) {
-  constexpr bool FWD = (MODE == TriMode::LN || MODE == TriMode::UT);
-  const int64_t nb = (n + kNB - 1) / kNB;
-  for (int64_t i = 0; i < nb; ++i) {
-    const int64_t nxt = FWD ? i : nb - 1 - i;
-    const int64_t cur = i == 0 ? -1 : (FWD ? nxt - 1 : nxt + 1);
-    const int64_t rest = FWD ? (n - (nxt + 1) * kNB) : nxt * kNB;  // rows beyond block nxt
-    const int64_t extra = (cur < 0 || rest <= 0) ? 0 : (rest + kRows - 1) / kRows;
-    hipLaunchKernelGGL((k_trsv_step<NMAX, MODE, TF>), dim3(unsigned(1 + extra)), dim3(kRows), 0, s, n,
-                       N, LU, ld, Winv, B, ldb, cur, nxt);
-  }
-  return hipGetLastError();
-}
-
-template <int NMAX, typename TF>
-hipError_t trsv_sweep_n(TriMode mode, int64_t n, int N, const TF *LU, int64_t ld,
-                        const double *Winv, double *B, int64_t ldb, hipStream_t s) {
-  switch (mode) {
-    case TriMode::LN: return trsv_sweep_t<NMAX, TriMode::LN>(n, N, LU, ld, Winv, B, ldb, s);
-    case TriMode::UN: return trsv_sweep_t<NMAX, TriMode::UN>(n, N, LU, ld, Winv, B, ldb, s);
-    case TriMode::UT: return trsv_sweep_t<NMAX, TriMode::UT>(n, N, LU, ld, Winv, B, ldb, s);
-    default: return trsv_sweep_t<NMAX, TriMode::LT>(n, N, LU, ld, Winv, B, ldb, s);
-  }
-}
-
 }  // namespace
-
-template <typename TF>
-hipError_t trsv_sweep_any(TriMode mode, int64_t n, int64_t nrhs, const TF *LU, int64_t ld,
-                          const double *Winv, double *B, int64_t ldb, hipStream_t s) {
-  if (n <= 0 || nrhs <= 0) return hipSuccess;
-  if (nrhs > kSkinnyMax) return hipErrorInvalidValue;
-  const int N = int(nrhs);
-  if (N <= 1) return trsv_sweep_n<1>(mode, n, N, LU, ld, Winv, B, ldb, s);
-  if (N <= 4) return trsv_sweep_n<4>(mode, n, N, LU, ld, Winv, B, ldb, s);
-  if (N <= 8) return trsv_sweep_n<8>(mode, n, N, LU, ld, Winv, B, ldb, s);
-  return trsv_sweep_n<16>(mode, n, N, LU, ld, Winv, B, ldb, s);
-}
-
-hipError_t launch_trsv_sweep(TriMode mode, int64_t n, int64_t nrhs, const double *LU, int64_t ld,
-                             const double *Winv, double *B, int64_t ldb, hipStream_t s) {
-  return trsv_sweep_any(mode, n, nrhs, LU, ld, Winv, B, ldb, s);
-}
-hipError_t launch_trsv_sweep(TriMode mode, int64_t n, int64_t nrhs, const float *LU, int64_t ld,
-                             const double *Winv, double *B, int64_t ldb, hipStream_t s) {
-  return trsv_sweep_any(mode, n, nrhs, LU, ld, Winv, B, ldb, s);
-}
 
 size_t resid_scratch_doubles(int64_t n, int64_t nrhs) {
   const int64_t chunks = (n + kChunk - 1) / kChunk;
@@ -604,17 +387,6 @@ size_t resid_scratch_doubles(int64_t n, int64_t nrhs) {
   // partial (chunks * max(nrhs,16) * n) + abspart (chunks * n) + blockstat + colstat
   const int64_t w = nn > kSkinnyMax ? 0 : nn;
   return size_t(chunks) * n * (w + 1) + size_t(nblk) * (3 * kSkinnyMax + 1) + 3 * size_t(nn) + 64;
-}
-
-hipError_t launch_skinny_update(int64_t M, int64_t N, int K, const double *A, int64_t lda,
-                                bool trans, const double *X, int64_t ldx, double *Y, int64_t ldy,
-                                hipStream_t s) {
-  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
-  if (K > kNB || N > kSkinnyMax) return hipErrorInvalidValue;
-  if (N <= 1) return skinny_t<1>(M, int(N), K, A, lda, trans, X, ldx, Y, ldy, s);
-  if (N <= 4) return skinny_t<4>(M, int(N), K, A, lda, trans, X, ldx, Y, ldy, s);
-  if (N <= 8) return skinny_t<8>(M, int(N), K, A, lda, trans, X, ldx, Y, ldy, s);
-  return skinny_t<16>(M, int(N), K, A, lda, trans, X, ldx, Y, ldy, s);
 }
 
 hipError_t launch_residual_berr(int64_t n, int64_t nrhs, const double *A, int64_t lda,
@@ -686,6 +458,58 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, hipStream_t s) {
 
 hipError_t launch_fill_f64(double *p, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_matvec(int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *X,
+                         int64_t ldx, double *Y, int64_t ldy, double *scratch, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return hipSuccess;
+  if (nrhs > kSkinnyMax) return hipErrorInvalidValue;
+  const int64_t chunks = (n + kChunk - 1) / kChunk;
+  const int64_t nblk = (n + kRows - 1) / kRows;
+  const dim3 g2 = dim3(unsigned(nblk), unsigned(chunks));
+  const int N = int(nrhs);
+  double *partial = scratch;
+#define RBT_MATVEC(NM)                                                                          \
+  hipLaunchKernelGGL((k_gemv_partial<NM, false>), g2, dim3(kRows), 0, s, n, N, n, A, lda, X,   \
+                     ldx, partial, (double *)nullptr);                                          \
+  hipLaunchKernelGGL((k_gemv_sum<NM>), dim3(unsigned(nblk)), dim3(kRows), 0, s, n, N, chunks,   \
+                     partial, Y, ldy);
+  if (N <= 1) {
+    RBT_MATVEC(1)
+  } else if (N <= 4) {
+    RBT_MATVEC(4)
+  } else if (N <= 8) {
+    RBT_MATVEC(8)
+  } else {
+    RBT_MATVEC(16)
+  }
+#undef RBT_MATVEC
+  return hipGetLastError();
+}
+
+hipError_t launch_coldots(int64_t n, int N, int J, const double *V, int64_t vs, const double *W,
+                          int64_t ldw, double *out, hipStream_t s) {
+  if (J <= 0 || N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_coldots, dim3(unsigned(J), unsigned(N)), dim3(kRows), 0, s, n, N, V, vs, W,
+                     ldw, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_colcombo(int64_t n, int N, int J, const double *V, int64_t vs,
+                           const double *coef, double sign, double *W, int64_t ldw,
+                           hipStream_t s) {
+  if (J <= 0 || N <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_colcombo, dim3(unsigned((n + kRows - 1) / kRows), unsigned(N)), dim3(kRows),
+                     0, s, n, N, J, V, vs, coef, sign, W, ldw);
+  return hipGetLastError();
+}
+
+hipError_t launch_colscale(int64_t n, int N, const double *W, int64_t ldw, const double *nrm2,
+                           double *O, hipStream_t s) {
+  if (N <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_colscale, dim3(unsigned((n + kRows - 1) / kRows), unsigned(N)), dim3(kRows),
+                     0, s, n, W, ldw, nrm2, O);
   return hipGetLastError();
 }
 

@@ -131,3 +131,49 @@ def test_mixed_empty(rbt):
     B = torch.empty_strided((0, 1), (1, 1), dtype=torch.float64, device="cuda")
     X, _, iters, berr, info, _ = rbt.solve_mixed(A, B, 2, 1)
     assert int(iters.item()) == 0 and float(berr.item()) == 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,k,d", [(1, 1, 2), (300, 3, 1), (1003, 2, 2), (700, 20, 2)])
+def test_gmres_ir_converges_to_oracle_solution(rbt, prec, n, k, d):
+    A = workloads.dominant(n, seed=n + 7)
+    B = workloads.randn(n, k, seed=4)
+    p = rbt.RBT_FP32 if prec == "fp32" else rbt.RBT_BF16
+    tol = 10 * n * EPS
+    X, _, iters, berr, info, _ = rbt.solve_mixed(dev(A), dev(B), d, 2023, prec=p,
+                                                 solver=rbt.RBT_IR_GMRES, tol=tol, max_iter=60)
+    assert int(info.item()) == 0
+    assert float(berr.item()) <= tol
+    Uo, Vo = coeffs.generate(n, d, 2023)
+    Xo, _, _ = osolve.rbt_solve(A, B, Uo, Vo, d)
+    kappa = np.linalg.cond(A, np.inf)
+    assert relfro(host(X), Xo) <= 10 * kappa * tol
+    assert int(iters.item()) <= (8 if prec == "fp32" else 20)
+
+
+def test_gmres_ir_fp32_randn_beats_classical(rbt):
+    """N(0,1) at n = 1536: GMRES-IR reaches the tolerance in fewer Krylov
+    iterations than classical refinement needs corrections."""
+    n = 1536
+    A = workloads.randn_matrix(n, seed=42)
+    B = workloads.randn(n, 1, seed=64)
+    tol = 10 * n * EPS
+    Xg, _, itg, beg, _, _ = rbt.solve_mixed(dev(A), dev(B), 2, 2023, prec=rbt.RBT_FP32,
+                                            solver=rbt.RBT_IR_GMRES, tol=tol, max_iter=100)
+    Xc, _, itc, bec, _, _ = rbt.solve_mixed(dev(A), dev(B), 2, 2023, prec=rbt.RBT_FP32,
+                                            solver=rbt.RBT_IR_CLASSIC, tol=tol, max_iter=100)
+    assert float(beg.item()) <= tol
+    assert int(itg.item()) < int(itc.item()) or float(bec.item()) > tol
+    Xe = np.linalg.solve(A, B)
+    kappa = np.linalg.cond(A, np.inf)
+    assert relfro(host(Xg), Xe) <= 20 * kappa * tol
+
+
+def test_gmres_ir_respects_iteration_cap(rbt):
+    n = 512
+    A = workloads.randn_matrix(n, seed=42)
+    B = workloads.randn(n, 2, seed=64)
+    _, _, iters, berr, _, _ = rbt.solve_mixed(dev(A), dev(B), 2, 2023, prec=rbt.RBT_BF16,
+                                              solver=rbt.RBT_IR_GMRES, tol=0.0, max_iter=7)
+    assert int(iters.item()) == 7
+    assert np.isfinite(float(berr.item()))
