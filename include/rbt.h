@@ -178,6 +178,49 @@ int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, float
                     int32_t *iters_dev, double *berr_dev, int32_t *info_dev, void *work,
                     size_t work_bytes, void *stream);
 
+/* Batched solves: many independent systems A_s X_s = B_s of different
+ * orders (the method of Eq. 1 per system, with mixed precision as in
+ * rbt_solve_mixed: FP32 elimination of A~_s, or BF16 trailing-update
+ * operands, and classical FP64 refinement with the original A_s), all in ONE
+ * persistent launch: each workgroup takes systems from a queue, largest
+ * first, and runs every step of the method on each.
+ *
+ * Host. Workspace bytes for a batch of `batch` systems with orders n[s] and
+ * right-hand-side counts nrhs[s] (host arrays; 0 <= nrhs[s] <= 16), depth
+ * <= 3, prec RBT_FP32 or RBT_BF16; 0 for invalid arguments. About
+ * 4 n^2 + 8 (2 n d + 64^2 ceil(n/64) + n nrhs) bytes per system. */
+size_t rbt_batched_workspace_size(int64_t batch, const int64_t *n, const int64_t *nrhs, int depth,
+                                  int prec);
+
+/* Host. Write the plan (header and queue of systems, largest first) for
+ * these sizes into the device workspace `work` (>= rbt_batched_workspace_size
+ * bytes); synchronizes `stream`. Call once per set of sizes; the plan stays
+ * valid for any number of rbt_solve_batched calls with the same batch,
+ * depth and prec. nrhs[s] > 16 or depth > 3: RBT_ERR_UNSUPPORTED. */
+int rbt_batched_plan(int64_t batch, const int64_t *n, const int64_t *nrhs, int depth, int prec,
+                     void *work, size_t work_bytes, void *stream);
+
+/* Device. Solve the planned batch. A, lda, B, ldb, X, ldx: device arrays of
+ * `batch` entries (pointers to column-major FP64 matrices in device memory
+ * and their leading dimensions): A[s] n x n (read only, kept for the
+ * residuals), B[s] n x nrhs (read only), X[s] n x nrhs (output). System s
+ * draws its coefficients from seed_s = SplitMix64 output number s of `seed`
+ * (the draw of the header's conventions, per system). Refinement stops per
+ * system at the Eq. 7 backward error <= tol or after max_iter corrections;
+ * tol < 0 means |tol| n_s 2^-52 for system s of order n_s (NaN: -11).
+ * iters_dev, berr_dev, info_dev: device arrays of `batch` entries
+ * (nullable) for the correction count, the final backward error and the
+ * first zero pivot (as rbt_genp) of each system. Enqueues a reset kernel and
+ * the persistent kernel on `stream`, allocates nothing and synchronizes
+ * nothing, so it can be captured in a HIP graph. A plan that does not match
+ * (batch, depth, prec) or a workspace smaller than the plan's makes the
+ * launch do nothing. Concurrent calls with the same workspace race. */
+int rbt_solve_batched(int64_t batch, const double *const *A, const int64_t *lda,
+                      const double *const *B, const int64_t *ldb, double *const *X,
+                      const int64_t *ldx, int depth, uint64_t seed, int prec, double tol,
+                      int max_iter, int32_t *iters_dev, double *berr_dev, int32_t *info_dev,
+                      void *work, size_t work_bytes, void *stream);
+
 /* Device. Backward error of Eq. 7 for n x nrhs X against A (n x n) and B:
  * max over columns of ||B - A X||_inf / (||A||_inf ||X||_inf + ||B||_inf),
  * written to berr_dev (device double). work: >= rbt_workspace_size(n, nrhs,

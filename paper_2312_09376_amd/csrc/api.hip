@@ -1,7 +1,9 @@
 // C ABI entry points (include/rbt.h): argument checks, workspace carving and
 // the launch sequence of the method (Eq. 1 and the three steps under it).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <cstdlib>
 #include <vector>
 
@@ -796,6 +798,132 @@ extern "C" int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t
     RBT_HIP_CHECK(hipMemcpyAsync(iters_dev, &it, sizeof(int32_t), hipMemcpyHostToDevice, s));
     RBT_HIP_CHECK(hipStreamSynchronize(s));
   }
+  return 0;
+}
+
+// ---- batched solves ----
+namespace rbt {
+namespace {
+
+struct BatchPlanSizes {
+  size_t f_off, d_off, total;
+};
+
+// Workspace: header | descriptor table | FP32 factors | FP64 areas; each
+// system's factor and FP64 area start on 256-byte boundaries.
+BatchPlanSizes batch_sizes(int64_t batch, const int64_t *n, const int64_t *nrhs, int depth,
+                           std::vector<BatchDesc> *desc) {
+  BatchPlanSizes z{};
+  z.f_off = align256(kBatchTableOffset + size_t(batch) * sizeof(BatchDesc));
+  size_t f = 0, d = 0;  // floats, doubles
+  std::vector<int64_t> order(batch);
+  for (int64_t i = 0; i < batch; ++i) order[i] = i;
+  // largest systems first (longest-processing-time order for the queue)
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t b) { return n[a] > n[b]; });
+  if (desc) desc->resize(batch);
+  for (int64_t t = 0; t < batch; ++t) {
+    const int64_t i = order[t];
+    if (desc) {
+      BatchDesc &D = (*desc)[t];
+      D = BatchDesc{};
+      D.sys = i;
+      D.n = n[i];
+      D.nrhs = nrhs[i];
+      D.f_off = int64_t(f);
+      D.d_off = int64_t(d);
+    }
+    f += align256(size_t(n[i]) * n[i] * sizeof(float)) / sizeof(float);
+    d += align256(size_t(batched_sys_doubles(n[i], nrhs[i], depth)) * sizeof(double)) /
+         sizeof(double);
+  }
+  z.d_off = align256(z.f_off + f * sizeof(float));
+  z.total = z.d_off + d * sizeof(double);
+  return z;
+}
+
+int check_batch_sizes(int64_t batch, const int64_t *n, const int64_t *nrhs) {
+  if (batch < 0) return -1;
+  if (batch > 0 && n == nullptr) return -2;
+  if (batch > 0 && nrhs == nullptr) return -3;
+  for (int64_t i = 0; i < batch; ++i) {
+    if (n[i] < 0) return -2;
+    if (nrhs[i] < 0) return -3;
+    if (nrhs[i] > kSkinnyMax) return RBT_ERR_UNSUPPORTED;
+  }
+  return 0;
+}
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    return 256;
+  return cus;
+}
+
+}  // namespace
+}  // namespace rbt
+
+extern "C" size_t rbt_batched_workspace_size(int64_t batch, const int64_t *n,
+                                             const int64_t *nrhs, int depth, int prec) {
+  if (check_batch_sizes(batch, n, nrhs) != 0 || depth < 0 || depth > 3) return 0;
+  if (prec != RBT_FP32 && prec != RBT_BF16) return 0;
+  return batch_sizes(batch, n, nrhs, depth, nullptr).total;
+}
+
+extern "C" int rbt_batched_plan(int64_t batch, const int64_t *n, const int64_t *nrhs, int depth,
+                                int prec, void *work, size_t work_bytes, void *stream) {
+  const int rc = check_batch_sizes(batch, n, nrhs);
+  if (rc) return rc;
+  if (depth < 0) return -4;
+  if (depth > 3) return RBT_ERR_UNSUPPORTED;
+  if (prec != RBT_FP32 && prec != RBT_BF16) return -5;
+  if (work == nullptr) return -6;
+  std::vector<BatchDesc> desc;
+  const BatchPlanSizes z = batch_sizes(batch, n, nrhs, depth, &desc);
+  if (work_bytes < z.total) return RBT_ERR_WORKSPACE;
+  std::vector<char> host(kBatchTableOffset + desc.size() * sizeof(BatchDesc), 0);
+  BatchHeader h{};
+  h.ticket = 0;
+  h.batch = batch;
+  h.depth = depth;
+  h.prec = prec;
+  h.f_off_bytes = int64_t(z.f_off);
+  h.d_off_bytes = int64_t(z.d_off);
+  h.total_bytes = int64_t(z.total);
+  std::memcpy(host.data(), &h, sizeof(h));
+  if (!desc.empty())
+    std::memcpy(host.data() + kBatchTableOffset, desc.data(), desc.size() * sizeof(BatchDesc));
+  hipStream_t s = S(stream);
+  RBT_HIP_CHECK(hipMemcpyAsync(work, host.data(), host.size(), hipMemcpyHostToDevice, s));
+  RBT_HIP_CHECK(hipStreamSynchronize(s));
+  return 0;
+}
+
+extern "C" int rbt_solve_batched(int64_t batch, const double *const *A, const int64_t *lda,
+                                 const double *const *B, const int64_t *ldb, double *const *X,
+                                 const int64_t *ldx, int depth, uint64_t seed, int prec,
+                                 double tol, int max_iter, int32_t *iters_dev, double *berr_dev,
+                                 int32_t *info_dev, void *work, size_t work_bytes,
+                                 void *stream) {
+  if (batch < 0) return -1;
+  if (batch > 0 && (A == nullptr || lda == nullptr)) return A == nullptr ? -2 : -3;
+  if (batch > 0 && (B == nullptr || ldb == nullptr)) return B == nullptr ? -4 : -5;
+  if (batch > 0 && (X == nullptr || ldx == nullptr)) return X == nullptr ? -6 : -7;
+  if (depth < 0) return -8;
+  if (depth > 3) return RBT_ERR_UNSUPPORTED;
+  if (prec != RBT_FP32 && prec != RBT_BF16) return -10;
+  if (tol != tol) return -11;
+  if (max_iter < 0) return -12;
+  if (batch == 0) return 0;
+  if (work == nullptr) return -16;
+  if (work_bytes < kBatchTableOffset + size_t(batch) * sizeof(BatchDesc)) return RBT_ERR_WORKSPACE;
+  const int64_t cap = 2 * int64_t(device_cus());  // two workgroups per CU
+  const int grid = int(batch < cap ? batch : cap);
+  RBT_HIP_CHECK(launch_batched(batch, work, work_bytes, A, lda, B, ldb, X, ldx, depth, seed, prec,
+                               tol, max_iter, iters_dev, berr_dev, info_dev, grid, S(stream)));
   return 0;
 }
 

@@ -172,6 +172,34 @@ hipError_t launch_copy_cols(int64_t n, int64_t nrhs, const double *S, int64_t ld
 hipError_t launch_neg_outer(int64_t n, int64_t nrhs, const double *Lm, int64_t ldl,
                             const double *X, int64_t ldx, double *dA, int64_t ldda,
                             hipStream_t s);
+// k_batched.hip : batched solves in one persistent launch. The host plan
+// writes a BatchHeader and `batch` BatchDesc entries (largest systems first)
+// into the workspace; the kernel takes entries from the queue in that order.
+struct BatchHeader {
+  int32_t ticket;  // queue position (reset by each launch)
+  int32_t pad0;
+  int64_t batch;   // entries in the table
+  int32_t depth, prec;
+  int64_t f_off_bytes, d_off_bytes, total_bytes;  // FP32 area, FP64 area, workspace used
+};
+struct BatchDesc {
+  int64_t sys;      // index into the caller's arrays
+  int64_t n, nrhs;
+  int64_t f_off;    // FP32 factor n x n (ld n), in floats from the FP32 area
+  int64_t d_off;    // U, V (n x d each), inverse blocks, residual (n x nrhs), in doubles
+  int64_t pad[3];
+};
+constexpr size_t kBatchTableOffset = 256;  // descriptors follow the header
+hipError_t launch_batched(int64_t batch, void *work, size_t work_bytes, const double *const *A,
+                          const int64_t *lda, const double *const *B, const int64_t *ldb,
+                          double *const *X, const int64_t *ldx, int depth, uint64_t seed,
+                          int prec, double tol, int max_iter, int32_t *iters, double *berr,
+                          int32_t *info, int grid, hipStream_t s);
+// FP64 doubles of one batched system's area (U, V, inverse blocks of 64, residual)
+inline int64_t batched_sys_doubles(int64_t n, int64_t nrhs, int d) {
+  return 2 * n * d + ((n + 63) / 64) * 64 * 64 + n * nrhs;
+}
+
 hipError_t launch_fill_i32(int32_t *p, int32_t v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, hipStream_t s);
 

@@ -1,0 +1,818 @@
+// Batched solves of many independent systems of different sizes in ONE
+// persistent launch: each workgroup takes systems from a queue (largest
+// first, as ordered by the host plan) and runs the whole method on each:
+// coefficients (Sec. 6 law), the two-sided transform A~ = U^T A V stored in
+// FP32 (Eq. 1), elimination without pivoting in FP32 (or with BF16 trailing
+// update operands), the solve of Eq. 1 with the low-precision factors, and
+// FP64 refinement with the original A until the Eq. 7 backward error is
+// <= tol (Sec. 5).
+//
+// Per system, in the workspace: F (n x n FP32, ld n) holds A~ and then its
+// L\U factors; the FP64 area holds U, V (n x d each), the FP64 inverses of
+// the 64 x 64 diagonal blocks (strictly lower part: L^-1, upper part with
+// the diagonal: U^-1, one 64 x 64 array per block) and the residual
+// (n x nrhs).
+//
+// Elimination, per 64-column step k (right-looking):
+//   diagonal block in LDS (FP64): 16-column panels factored by wavefront 0
+//   with readlane broadcasts, U rows by substitution, rank-16 updates;
+//   its inverses L^-1 and U^-1 by substitution (one column per lane:
+//   wavefront 0 the columns of L^-1, wavefront 1 those of U^-1);
+//   L21 = A21 U11^-1 and U12 = L11^-1 A12 as FP64 products with the
+//   inverses (v_mfma_f64_16x16x4f64; rounded to FP32 once), and
+//   A22 -= L21 U12 in FP32 (v_mfma_f32_16x16x4f32; BF16 mode:
+//   v_mfma_f32_16x16x32_bf16), all on the matrix cores in 64 x 64 tiles.
+// Solves: block sweeps over the factors (widened to FP64) with the FP64
+// inverses of the diagonal blocks.
+//
+// The host plan (rbt_batched_plan) writes the header and the descriptor
+// table; the kernel checks the header against its arguments and does
+// nothing for a plan that does not match.
+#include "butterfly_dev.h"
+
+namespace rbt {
+
+namespace {
+
+constexpr int BT = 256;      // threads per workgroup
+constexpr int BB = 64;       // block size of the per-system elimination
+constexpr int LDS_ = BB + 1; // LDS leading dimension of FP64 64 x 64 blocks
+constexpr int LDF = BB + 1;  // FP32 tiles
+constexpr int LDH = BB + 8;  // BF16 tiles (rows of 144 bytes)
+constexpr int NR = kSkinnyMax;  // right-hand sides per system, at most
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// LDS: region 0 (the diagonal block S, or the GEMM tiles, or the residual
+// buffers) and region 1 (the inverses T, kept through the panel products of
+// a step); the sweeps use both regions.
+constexpr int kR0Doubles = BB * LDS_;       // 4160 doubles
+constexpr int kR1Doubles = BB * LDS_;
+static_assert(6 * BB * NR <= kR0Doubles + kR1Doubles, "sweep buffers exceed LDS");
+static_assert(256 * NR + BT / 64 <= kR0Doubles, "residual buffers exceed region 0");
+
+struct Args {
+  int64_t batch;
+  char *work;
+  size_t work_bytes;
+  const double *const *A;
+  const int64_t *lda;
+  const double *const *B;
+  const int64_t *ldb;
+  double *const *X;
+  const int64_t *ldx;
+  int32_t *iters;
+  double *berr;
+  int32_t *info;
+  uint64_t seed;
+  double tol;
+  int depth, prec, max_iter;
+};
+
+__device__ __forceinline__ double wave_bcast(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double nanmax(double a, double b) {
+  return (b > a || b != b) ? b : a;
+}
+
+// NaN-propagating maximum over the workgroup (red: BT/64 doubles of LDS).
+__device__ double wg_nanmax(double v, double *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = nanmax(v, __shfl_xor(v, o));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int w = 1; w < BT / 64; ++w) r = nanmax(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------- tiles
+
+// acc (per wavefront 32 x 32 of a 64 x 64 tile) = A (64 x K) B (K x 64),
+// K = 64, operands staged in LDS: FP32 As[m][k], Bs[n][k] (ld LDF) or BF16
+// Ah[m][k], Bh[n][k] (ld LDH).
+template <bool BF16>
+__device__ __forceinline__ void tile_mma(const void *sa, const void *sb, f4 (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  if constexpr (!BF16) {
+    const float(*As)[LDF] = reinterpret_cast<const float(*)[LDF]>(sa);
+    const float(*Bs)[LDF] = reinterpret_cast<const float(*)[LDF]>(sb);
+#pragma unroll
+    for (int kk = 0; kk < BB / 4; ++kk) {
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[wm * 32 + 16 * i + l16][4 * kk + lk];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[wn * 32 + 16 * j + l16][4 * kk + lk];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  } else {
+    const __bf16(*Ah)[LDH] = reinterpret_cast<const __bf16(*)[LDH]>(sa);
+    const __bf16(*Bh)[LDH] = reinterpret_cast<const __bf16(*)[LDH]>(sb);
+#pragma unroll
+    for (int kk = 0; kk < BB / 32; ++kk) {
+      bf8 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const bf8 *>(&Ah[wm * 32 + 16 * i + l16][32 * kk + 8 * lk]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        b[j] = *reinterpret_cast<const bf8 *>(&Bh[wn * 32 + 16 * j + l16][32 * kk + 8 * lk]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+}
+
+// Stage a 64 x 64 operand in LDS as dst[r][k] from a column-major FP32
+// source whose element (r, k) is src[r + k * ld] (rmode: r runs down a
+// column) or src[k + r * ld] (kmode: k runs down a column). Entries with
+// r >= rv or k >= kv are zero.
+template <bool BF16, bool KMODE>
+__device__ __forceinline__ void stage(void *dst, const float *src, int64_t ld, int rv, int kv) {
+  const int tid = threadIdx.x;
+  // thread: column c = tid / 4 of the source, 16 consecutive entries
+  const int col = tid >> 2, seg = (tid & 3) * 16;
+  float v[16];
+  if (KMODE) {
+    // source column = operand row r = col; entries k = seg..seg+15
+    const bool full = col < rv && seg + 16 <= kv;
+    const float *p = src + seg + int64_t(col) * ld;
+    if (full) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f4u t = *reinterpret_cast<const f4u *>(p + 4 * q);
+        v[4 * q] = t[0]; v[4 * q + 1] = t[1]; v[4 * q + 2] = t[2]; v[4 * q + 3] = t[3];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = (col < rv && seg + e < kv) ? p[e] : 0.0f;
+    }
+    if constexpr (BF16) {
+      __bf16(*D)[LDH] = reinterpret_cast<__bf16(*)[LDH]>(dst);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) D[col][seg + e] = (__bf16)v[e];
+    } else {
+      float(*D)[LDF] = reinterpret_cast<float(*)[LDF]>(dst);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) D[col][seg + e] = v[e];
+    }
+  } else {
+    // source column = operand k = col; entries r = seg..seg+15
+    const bool full = col < kv && seg + 16 <= rv;
+    const float *p = src + seg + int64_t(col) * ld;
+    if (full) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f4u t = *reinterpret_cast<const f4u *>(p + 4 * q);
+        v[4 * q] = t[0]; v[4 * q + 1] = t[1]; v[4 * q + 2] = t[2]; v[4 * q + 3] = t[3];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = (col < kv && seg + e < rv) ? p[e] : 0.0f;
+    }
+    if constexpr (BF16) {
+      __bf16(*D)[LDH] = reinterpret_cast<__bf16(*)[LDH]>(dst);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) D[seg + e][col] = (__bf16)v[e];
+    } else {
+      float(*D)[LDF] = reinterpret_cast<float(*)[LDF]>(dst);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) D[seg + e][col] = v[e];
+    }
+  }
+}
+
+// Apply a tile result to C (column-major FP32, ld): rows r0.., cols c0..,
+// valid rv x cv; SUB: C -= acc, else C = acc.
+template <bool SUB>
+__device__ __forceinline__ void tile_store(const f4 (&acc)[2][2], float *C, int64_t ld, int rv,
+                                           int cv) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = wn * 32 + 16 * j + l16;
+      if (col >= cv) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wm * 32 + 16 * i + 4 * lk + v;
+        if (row < rv) {
+          float *p = C + row + int64_t(col) * ld;
+          if (SUB)
+            *p -= acc[i][j][v];
+          else
+            *p = acc[i][j][v];
+        }
+      }
+    }
+}
+
+// FP64 panel products (the solves with the diagonal block's inverses): an
+// explicit inverse applied in FP32 loses accuracy on blocks with growth, so
+// these products stay in FP64 (v_mfma_f64_16x16x4f64, output element
+// (lane l, v) at row l/16 + 4v, column l % 16) and only the result is
+// rounded to FP32. Operands come from accessors a(m, k), b(k, n).
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <typename FA, typename FB>
+__device__ __forceinline__ void tile_mma64(FA a_at, FB b_at, d4 (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int kk = 0; kk < BB / 4; ++kk) {
+    double a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = a_at(wm * 32 + 16 * i + l16, 4 * kk + lk);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = b_at(4 * kk + lk, wn * 32 + 16 * j + l16);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+}
+
+// C (FP32, ld) = acc rounded, rows < rv, cols < cv.
+__device__ __forceinline__ void tile_store64(const d4 (&acc)[2][2], float *C, int64_t ld, int rv,
+                                             int cv) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = wn * 32 + 16 * j + l16;
+      if (col >= cv) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wm * 32 + 16 * i + lk + 4 * v;
+        if (row < rv) C[row + int64_t(col) * ld] = float(acc[i][j][v]);
+      }
+    }
+}
+
+// Stage a 64 x 64 block of F (FP32, column-major, rows r0.., cols c0..;
+// rv x cv valid) in LDS as FP64 D[c * LDS_ + r] (zero outside).
+__device__ __forceinline__ void stage64(double *D, const float *src, int64_t ld, int rv, int cv) {
+  const int tid = threadIdx.x;
+  const int col = tid >> 2, seg = (tid & 3) * 16;
+  float v[16];
+  if (col < cv && seg + 16 <= rv) {
+    const float *p = src + seg + int64_t(col) * ld;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f4u t = *reinterpret_cast<const f4u *>(p + 4 * q);
+      v[4 * q] = t[0]; v[4 * q + 1] = t[1]; v[4 * q + 2] = t[2]; v[4 * q + 3] = t[3];
+    }
+  } else {
+    const float *p = src + int64_t(col < cv ? col : 0) * ld;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = (col < cv && seg + e < rv) ? p[seg + e] : 0.0f;
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) D[col * LDS_ + seg + e] = double(v[e]);
+}
+
+// ------------------------------------------------------- one system
+
+struct Sys {
+  int64_t n, nrhs;
+  float *F;          // n x n, ld n
+  double *U, *V;     // n x d each
+  double *Inv;       // nblk x 64 x 64
+  double *R;         // n x nrhs
+  const double *A;
+  int64_t lda;
+  const double *Bm;
+  int64_t ldb;
+  double *Xm;
+  int64_t ldx;
+};
+
+// Factor the kb x kb diagonal block at (k, k) of F: S (LDS, FP64) <- L\U,
+// T (LDS, FP64) <- L^-1 below the diagonal, U^-1 on and above; inverses
+// also to Inv (64 x 64, full, identity beyond kb); factors back to F.
+__device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double *S, double *T, double *Invb,
+                           int *info_sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  {
+    const int r = tid & 63, cg = tid >> 6;
+    const int rr = r < kb ? r : kb - 1;
+    float v[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int c = cg + 4 * t;
+      v[t] = s.F[(k + rr) + (k + (c < kb ? c : kb - 1)) * s.n];
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int c = cg + 4 * t;
+      S[c * LDS_ + r] = (r < kb && c < kb) ? double(v[t]) : (r == c ? 1.0 : 0.0);
+    }
+  }
+  __syncthreads();
+  for (int c0 = 0; c0 < BB; c0 += 16) {
+    if (wave == 0) {
+      double xa[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) xa[j] = S[(c0 + j) * LDS_ + lane];
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) {
+        const int c = c0 + cc;
+        double prow[16];
+#pragma unroll
+        for (int j = cc; j < 16; ++j) prow[j] = wave_bcast(xa[j], c);
+        const double p = prow[cc];
+        if (lane == 0 && c < kb && p == 0.0 && *info_sh == 0) *info_sh = int(k + c + 1);
+        const bool act = lane > c;
+        const double la = xa[cc] / p;
+        xa[cc] = act ? la : xa[cc];
+#pragma unroll
+        for (int j = cc + 1; j < 16; ++j) {
+          const double u = xa[j] - la * prow[j];
+          xa[j] = act ? u : xa[j];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (lane >= c0) S[(c0 + j) * LDS_ + lane] = xa[j];
+    }
+    __syncthreads();
+    const int c1 = c0 + 16;
+    if (c1 >= BB) break;
+    if (tid < BB - c1) {  // U rows c0..c0+15, columns c1..63
+      const int col = c1 + tid;
+      double y[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) y[i] = S[col * LDS_ + c0 + i];
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+#pragma unroll
+        for (int i2 = i + 1; i2 < 16; ++i2) y[i2] -= S[(c0 + i) * LDS_ + c0 + i2] * y[i];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) S[col * LDS_ + c0 + i] = y[i];
+    }
+    __syncthreads();
+    const int w = BB - c1;
+    for (int e = tid; e < w * w; e += BT) {
+      const int i = c1 + e % w, j = c1 + e / w;
+      double a = S[j * LDS_ + i];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) a -= S[(c0 + t) * LDS_ + i] * S[j * LDS_ + c0 + t];
+      S[j * LDS_ + i] = a;
+    }
+    __syncthreads();
+  }
+  // inverses: wave 0 column j of L^-1 (rows > j), wave 1 column j of U^-1
+  if (wave == 0) {
+    const int j = lane;
+    for (int i = j + 1; i < BB; ++i) {
+      double a = -S[j * LDS_ + i];
+      for (int t = j + 1; t < i; ++t) a -= S[t * LDS_ + i] * T[j * LDS_ + t];
+      T[j * LDS_ + i] = a;
+    }
+  } else if (wave == 1) {
+    const int j = lane;
+    const double xj = 1.0 / S[j * LDS_ + j];
+    T[j * LDS_ + j] = xj;
+    for (int i = j - 1; i >= 0; --i) {
+      double a = 0.0;
+      for (int t = i + 1; t <= j; ++t) a += S[t * LDS_ + i] * T[j * LDS_ + t];
+      T[j * LDS_ + i] = -a / S[i * LDS_ + i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < BB * BB; e += BT) {
+    const int r = e & 63, c = e >> 6;
+    Invb[r + c * BB] = T[c * LDS_ + r];
+    if (r < kb && c < kb) s.F[(k + r) + (k + c) * s.n] = float(S[c * LDS_ + r]);
+  }
+  __syncthreads();
+}
+
+template <bool BF16U>
+__device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int *info_sh) {
+  const int64_t n = s.n;
+  float(*As)[LDF] = reinterpret_cast<float(*)[LDF]>(L0);
+  float(*Bs)[LDF] = reinterpret_cast<float(*)[LDF]>(L0 + (BB * LDF + 1) / 2);
+  __bf16(*Ah)[LDH] = reinterpret_cast<__bf16(*)[LDH]>(L0);
+  __bf16(*Bh)[LDH] = reinterpret_cast<__bf16(*)[LDH]>(L0 + (BB * LDH) / 4);
+  for (int64_t k = 0; k < n; k += BB) {
+    const int kb = int(n - k < BB ? n - k : BB);
+    double *Invb = s.Inv + (k / BB) * BB * BB;
+    diag_block(s, k, kb, L0, L1, Invb, info_sh);
+    const int64_t rest = n - k - kb;
+    if (rest <= 0) break;
+    f4 acc[2][2];
+    d4 acc64[2][2];
+    const double *T = L1;  // L^-1 below the diagonal, U^-1 on and above (ld LDS_)
+    // L21 = A21 U11^-1 (rows k+kb.., 64-row tiles), FP64 products
+    for (int64_t r0 = k + kb; r0 < n; r0 += BB) {
+      const int rv = int(n - r0 < BB ? n - r0 : BB);
+      // stage A21 tile as [k][r]: element (r, kx) at L0[kx * LDS_ + r]
+      stage64(L0, s.F + r0 + k * n, n, rv, kb);
+      __syncthreads();
+      tile_mma64([&](int m, int kx) { return L0[kx * LDS_ + m]; },
+                 [&](int kx, int nx) { return kx <= nx ? T[nx * LDS_ + kx] : 0.0; }, acc64);
+      __syncthreads();
+      tile_store64(acc64, s.F + r0 + k * n, n, rv, kb);
+    }
+    __syncthreads();
+    // U12 = L11^-1 A12 (64-column tiles), FP64 products
+    for (int64_t c0 = k + kb; c0 < n; c0 += BB) {
+      const int cv = int(n - c0 < BB ? n - c0 : BB);
+      // stage A12 tile: element (kx, nx) at L0[nx * LDS_ + kx]
+      stage64(L0, s.F + k + c0 * n, n, kb, cv);
+      __syncthreads();
+      tile_mma64([&](int m, int kx) { return m > kx ? T[kx * LDS_ + m] : (m == kx ? 1.0 : 0.0); },
+                 [&](int kx, int nx) { return L0[nx * LDS_ + kx]; }, acc64);
+      __syncthreads();
+      tile_store64(acc64, s.F + k + c0 * n, n, kb, cv);
+    }
+    __syncthreads();
+    // A22 -= L21 U12 (64 x 64 tiles; the L21 row tile stays in LDS)
+    for (int64_t r0 = k + kb; r0 < n; r0 += BB) {
+      const int rv = int(n - r0 < BB ? n - r0 : BB);
+      if constexpr (BF16U)
+        stage<true, false>(Ah, s.F + r0 + k * n, n, rv, kb);
+      else
+        stage<false, false>(As, s.F + r0 + k * n, n, rv, kb);
+      for (int64_t c0 = k + kb; c0 < n; c0 += BB) {
+        const int cv = int(n - c0 < BB ? n - c0 : BB);
+        if constexpr (BF16U)
+          stage<true, true>(Bh, s.F + k + c0 * n, n, cv, kb);
+        else
+          stage<false, true>(Bs, s.F + k + c0 * n, n, cv, kb);
+        __syncthreads();
+        if constexpr (BF16U)
+          tile_mma<true>(Ah, Bh, acc);
+        else
+          tile_mma<false>(As, Bs, acc);
+        __syncthreads();
+        tile_store<true>(acc, s.F + r0 + c0 * n, n, rv, cv);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// One-sided transform of the n x nrhs block Y (ld ldy) with coefficients C.
+template <int OP>
+__device__ __noinline__ void transform_vec_sys(const Sys &s, int d, double *Y, int64_t ldy, const double *C) {
+  if (d == 0) return;
+  const int64_t m = (((s.n - 1) >> d) + 1) << d;
+  const int64_t q = m >> d;
+  const dev::Pass ps = dev::make_pass(s.n, q, d, 1, d);
+  const int ng = int(ps.ngroups);
+  for (int e = threadIdx.x; e < ng * int(s.nrhs); e += BT) {
+    const int gr = e % ng, j = e / ng;
+    const int64_t rb = dev::group_base(ps, gr);
+    if (rb >= s.n) continue;
+    switch (d) {
+      case 1: dev::transform_vec_block<1, OP>(Y, ldy, j, C, ps, rb); break;
+      case 2: dev::transform_vec_block<2, OP>(Y, ldy, j, C, ps, rb); break;
+      default: dev::transform_vec_block<3, OP>(Y, ldy, j, C, ps, rb); break;
+    }
+  }
+  __syncthreads();
+}
+
+// Y (n x nrhs FP64, ld ldy) <- (L U)^-1 Y with the FP32 factors widened to
+// FP64 and the FP64 inverses of the diagonal blocks: for each block, the
+// contributions of the solved blocks (threads: 64 rows x 4 segments of 16
+// columns of each 64-column chunk of the solved range, the chunk of Y
+// staged in LDS), then x_b = Dinv_b r_b.
+template <bool LOWER>
+__device__ __noinline__ void sweep(const Sys &s, double *Y, int64_t ldy, double *L0) {
+  const int64_t n = s.n;
+  const int N = int(s.nrhs);
+  const int tid = threadIdx.x, i = tid & 63, sg = tid >> 6;
+  double(*part)[BB][NR] = reinterpret_cast<double(*)[BB][NR]>(L0);  // [4][64][16]
+  double(*xs)[NR] = reinterpret_cast<double(*)[NR]>(L0 + 4 * BB * NR);
+  double(*yc)[NR] = reinterpret_cast<double(*)[NR]>(L0 + 5 * BB * NR);
+  const int64_t nblk = (n + BB - 1) / BB;
+  for (int64_t t = 0; t < nblk; ++t) {
+    const int64_t b = LOWER ? t : nblk - 1 - t;
+    const int64_t r0 = b * BB;
+    const int kb = int(n - r0 < BB ? n - r0 : BB);
+    // solved range: [0, r0) for L, [r0 + kb, n) for U
+    const int64_t lo = LOWER ? 0 : r0 + kb, hi = LOWER ? r0 : n;
+    double acc[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+    const float *Frow = s.F + (r0 + (i < kb ? i : kb - 1));
+    for (int64_t c0 = lo; c0 < hi; c0 += BB) {
+      const int cw = int(hi - c0 < BB ? hi - c0 : BB);
+      float fv[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int kx = sg * 16 + q;
+        fv[q] = Frow[(c0 + (kx < cw ? kx : cw - 1)) * n];
+      }
+      __syncthreads();
+      for (int e = tid; e < BB * NR; e += BT) {
+        const int kx = e / NR, c = e % NR;
+        yc[kx][c] = (kx < cw && c < N) ? Y[(c0 + kx) + int64_t(c) * ldy] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll 2
+      for (int q = 0; q < 16; ++q) {
+        const int kx = sg * 16 + q;
+        const double a = (i < kb && kx < cw) ? double(fv[q]) : 0.0;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] += a * yc[kx][c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NR; ++c) part[sg][i][c] = acc[c];
+    __syncthreads();
+    if (sg == 0) {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        const double sum = (part[0][i][c] + part[1][i][c]) + (part[2][i][c] + part[3][i][c]);
+        xs[i][c] = (i < kb && c < N) ? Y[(r0 + i) + int64_t(c) * ldy] - sum : 0.0;
+      }
+    }
+    __syncthreads();
+    // x_b = Dinv r: thread (i, sg) sums over k in segment sg
+    const double *Db = s.Inv + b * BB * BB;
+    double dv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) dv[q] = Db[i + (sg * 16 + q) * BB];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+#pragma unroll 2
+    for (int q = 0; q < 16; ++q) {
+      const int kx = sg * 16 + q;
+      const double v = LOWER ? (i > kx ? dv[q] : (i == kx ? 1.0 : 0.0)) : (i <= kx ? dv[q] : 0.0);
+#pragma unroll
+      for (int c = 0; c < NR; ++c) acc[c] += v * xs[kx][c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NR; ++c) part[sg][i][c] = acc[c];
+    __syncthreads();
+    if (sg == 0 && i < kb) {
+#pragma unroll
+      for (int c = 0; c < NR; ++c)
+        if (c < N)
+          Y[(r0 + i) + int64_t(c) * ldy] =
+              (part[0][i][c] + part[1][i][c]) + (part[2][i][c] + part[3][i][c]);
+    }
+    __syncthreads();
+  }
+}
+
+// R = B - A X (FP64, original A), Eq. 7 backward error (max over columns);
+// with_anorm: also ||A||_inf into *anorm. One pass over A (rows on
+// threads, X staged in LDS by chunks of columns), then the column maxima of
+// |R|, |X|, |B| in a second, small pass.
+__device__ __noinline__ double residual(const Sys &s, double *L0, bool with_anorm, double *anorm) {
+  const int64_t n = s.n;
+  const int N = int(s.nrhs);
+  const int tid = threadIdx.x;
+  constexpr int KC = 256;  // columns of A per staged chunk of X
+  double(*xs)[NR] = reinterpret_cast<double(*)[NR]>(L0);  // [KC][16]
+  double *red = L0 + KC * NR;
+  double amax = 0.0;
+  for (int64_t m0 = 0; m0 < n; m0 += BT) {
+    const int64_t m = m0 + tid;
+    double acc[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+    double asum = 0.0;
+    for (int64_t k0 = 0; k0 < n; k0 += KC) {
+      const int kc = int(n - k0 < KC ? n - k0 : KC);
+      __syncthreads();
+      for (int e = tid; e < KC * NR; e += BT) {
+        const int kx = e / NR, c = e % NR;
+        xs[kx][c] = (kx < kc && c < N) ? s.Xm[(k0 + kx) + int64_t(c) * s.ldx] : 0.0;
+      }
+      __syncthreads();
+      if (m < n) {
+        const double *Ap = s.A + m + k0 * s.lda;
+        for (int kx = 0; kx < kc; ++kx) {
+          const double a = Ap[int64_t(kx) * s.lda];
+          if (with_anorm) asum += fabs(a);
+#pragma unroll
+          for (int c = 0; c < NR; ++c) acc[c] += a * xs[kx][c];
+        }
+      }
+    }
+    if (m < n) {
+      amax = nanmax(amax, asum);
+#pragma unroll
+      for (int c = 0; c < NR; ++c)
+        if (c < N) s.R[m + int64_t(c) * n] = s.Bm[m + int64_t(c) * s.ldb] - acc[c];
+    }
+  }
+  __syncthreads();
+  if (with_anorm) {
+    const double an = wg_nanmax(amax, red);
+    if (tid == 0) *anorm = an;
+    __syncthreads();
+  }
+  const double an = *anorm;
+  double be = 0.0;
+  for (int c = 0; c < N; ++c) {
+    double rm = 0.0, xm = 0.0, bm = 0.0;
+    for (int64_t m = tid; m < n; m += BT) {
+      rm = nanmax(rm, fabs(s.R[m + int64_t(c) * n]));
+      xm = nanmax(xm, fabs(s.Xm[m + int64_t(c) * s.ldx]));
+      bm = nanmax(bm, fabs(s.Bm[m + int64_t(c) * s.ldb]));
+    }
+    const double r = wg_nanmax(rm, red);
+    const double x = wg_nanmax(xm, red);
+    const double b = wg_nanmax(bm, red);
+    const double den = an * x + b;
+    const double e = den > 0.0 ? r / den : (r > 0.0 ? INFINITY : (r != r ? r : 0.0));
+    be = nanmax(be, e);
+  }
+  return be;
+}
+
+template <bool BF16U>
+__device__ void solve_system(const Args &a, const BatchDesc &D, float *fbase, double *dbase,
+                             double *L0, double *L1, int *info_sh, double *anorm_sh) {
+  const int tid = threadIdx.x;
+  const int d = a.depth;
+  Sys s;
+  s.n = D.n;
+  s.nrhs = D.nrhs;
+  s.F = fbase + D.f_off;
+  s.U = dbase + D.d_off;
+  s.V = s.U + s.n * d;
+  s.Inv = s.V + s.n * d;
+  s.R = s.Inv + ((s.n + BB - 1) / BB) * BB * BB;
+  s.A = a.A[D.sys];
+  s.lda = a.lda[D.sys];
+  s.Bm = a.B[D.sys];
+  s.ldb = a.ldb[D.sys];
+  s.Xm = a.X[D.sys];
+  s.ldx = a.ldx[D.sys];
+  const int64_t n = s.n;
+  const uint64_t seed = dev::splitmix_at(a.seed, uint64_t(D.sys));
+  if (tid == 0) *info_sh = 0;
+  // coefficients
+  for (int64_t e = tid; e < 2 * n * d; e += BT) {
+    const int side = e >= n * d ? 1 : 0;
+    const int64_t rem = e - side * n * d;
+    s.U[e] = dev::coefficient(seed, rem % n, side, int(rem / n) + 1);
+  }
+  __syncthreads();
+  // A~ = U^T A V into F (FP32)
+  {
+    const int64_t m = d > 0 ? ((((n - 1) >> d) + 1) << d) : n;
+    const int64_t q = m >> d;
+    const dev::Pass ps = d > 0 ? dev::make_pass(n, q, d, 1, d) : dev::identity_pass(n);
+    for (int64_t e = tid; e < ps.ngroups * ps.ngroups; e += BT) {
+      const int64_t gr = e % ps.ngroups, gc = e / ps.ngroups;
+      const int64_t rb = dev::group_base(ps, gr), cb = dev::group_base(ps, gc);
+      if (rb >= n || cb >= n) continue;
+      switch (d) {
+        case 0: dev::transform2_block<0, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
+        case 1: dev::transform2_block<1, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
+        case 2: dev::transform2_block<2, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
+        default: dev::transform2_block<3, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
+      }
+    }
+  }
+  __syncthreads();
+  eliminate<BF16U>(s, L0, L1, info_sh);
+  // X = V (LU)^-1 U^T B
+  for (int64_t e = tid; e < n * s.nrhs; e += BT)
+    s.Xm[(e % n) + (e / n) * s.ldx] = s.Bm[(e % n) + (e / n) * s.ldb];
+  __syncthreads();
+  transform_vec_sys<RBT_OP_T>(s, d, s.Xm, s.ldx, s.U);
+  sweep<true>(s, s.Xm, s.ldx, L0);
+  sweep<false>(s, s.Xm, s.ldx, L0);
+  transform_vec_sys<RBT_OP_N>(s, d, s.Xm, s.ldx, s.V);
+  // refinement (tol < 0: |tol| n eps64 for this system)
+  const double tol = a.tol < 0.0 ? -a.tol * double(n) * 0x1.0p-52 : a.tol;
+  int it = 0;
+  double be = 0.0;
+  for (;;) {
+    be = residual(s, L0, it == 0, anorm_sh);
+    if (be <= tol || it >= a.max_iter) break;  // a NaN error never looks converged
+    transform_vec_sys<RBT_OP_T>(s, d, s.R, n, s.U);
+    sweep<true>(s, s.R, n, L0);
+    sweep<false>(s, s.R, n, L0);
+    transform_vec_sys<RBT_OP_N>(s, d, s.R, n, s.V);
+    for (int64_t e = tid; e < n * s.nrhs; e += BT)
+      s.Xm[(e % n) + (e / n) * s.ldx] += s.R[e];
+    __syncthreads();
+    ++it;
+  }
+  if (tid == 0) {
+    if (a.iters) a.iters[D.sys] = it;
+    if (a.berr) a.berr[D.sys] = be;
+    if (a.info) a.info[D.sys] = *info_sh;
+  }
+  __syncthreads();
+}
+
+template <bool BF16U>
+__global__ void __launch_bounds__(BT, 2) k_batched(Args a) {
+  __shared__ __attribute__((aligned(16))) double lds[kR0Doubles + kR1Doubles];
+  double *L0 = lds, *L1 = lds + kR0Doubles;
+  __shared__ int64_t tk_sh;
+  __shared__ int info_sh;
+  __shared__ double anorm_sh;
+  BatchHeader *hdr = reinterpret_cast<BatchHeader *>(a.work);
+  // a plan for other sizes, depth or precision, or a workspace too small for
+  // it: do nothing
+  if (hdr->batch != a.batch || hdr->depth != a.depth || hdr->prec != a.prec ||
+      hdr->total_bytes < 0 || size_t(hdr->total_bytes) > a.work_bytes)
+    return;
+  const BatchDesc *desc = reinterpret_cast<const BatchDesc *>(a.work + kBatchTableOffset);
+  float *fbase = reinterpret_cast<float *>(a.work + hdr->f_off_bytes);
+  double *dbase = reinterpret_cast<double *>(a.work + hdr->d_off_bytes);
+  for (;;) {
+    if (threadIdx.x == 0) tk_sh = atomicAdd(&hdr->ticket, 1);
+    __syncthreads();
+    const int64_t t = tk_sh;
+    __syncthreads();
+    if (t >= a.batch) break;
+    const BatchDesc D = desc[t];
+    if (D.n > 0) {
+      solve_system<BF16U>(a, D, fbase, dbase, L0, L1, &info_sh, &anorm_sh);
+    } else if (threadIdx.x == 0) {
+      if (a.iters) a.iters[D.sys] = 0;
+      if (a.berr) a.berr[D.sys] = 0.0;
+      if (a.info) a.info[D.sys] = 0;
+    }
+  }
+}
+
+__global__ void k_reset_ticket(void *work) {
+  if (threadIdx.x == 0) reinterpret_cast<BatchHeader *>(work)->ticket = 0;
+}
+
+}  // namespace
+
+hipError_t launch_batched(int64_t batch, void *work, size_t work_bytes, const double *const *A,
+                          const int64_t *lda, const double *const *B, const int64_t *ldb,
+                          double *const *X, const int64_t *ldx, int depth, uint64_t seed,
+                          int prec, double tol, int max_iter, int32_t *iters, double *berr,
+                          int32_t *info, int grid, hipStream_t s) {
+  Args a;
+  a.batch = batch;
+  a.work = static_cast<char *>(work);
+  a.work_bytes = work_bytes;
+  a.A = A;
+  a.lda = lda;
+  a.B = B;
+  a.ldb = ldb;
+  a.X = X;
+  a.ldx = ldx;
+  a.iters = iters;
+  a.berr = berr;
+  a.info = info;
+  a.seed = seed;
+  a.tol = tol;
+  a.depth = depth;
+  a.prec = prec;
+  a.max_iter = max_iter;
+  hipLaunchKernelGGL(k_reset_ticket, dim3(1), dim3(64), 0, s, work);
+  if (prec == RBT_BF16)
+    hipLaunchKernelGGL(k_batched<true>, dim3(unsigned(grid)), dim3(BT), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_batched<false>, dim3(unsigned(grid)), dim3(BT), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace rbt

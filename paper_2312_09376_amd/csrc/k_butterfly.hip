@@ -24,20 +24,14 @@
 // 4dn^2 flop count).
 #include <cmath>
 
-#include "internal.h"
+#include "butterfly_dev.h"
 
 namespace rbt {
 
 namespace {
 
-constexpr double kInvSqrt2 = 0.70710678118654752440;
-
-__device__ __forceinline__ uint64_t splitmix_at(uint64_t seed, uint64_t c) {
-  uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
+using dev::Pass;
+using dev::group_base;
 
 __global__ void __launch_bounds__(256) k_generate(int64_t n, int d, uint64_t seed,
                                                   double *__restrict__ U,
@@ -49,36 +43,8 @@ __global__ void __launch_bounds__(256) k_generate(int64_t n, int d, uint64_t see
   const int64_t rem = idx - side * n * d;
   const int layer = int(rem / n) + 1;
   const int64_t i = rem % n;
-  const uint64_t c = 128ull * uint64_t(i) + 64ull * uint64_t(side) + uint64_t(layer - 1);
-  const double u = double(splitmix_at(seed, c) >> 11) * 0x1.0p-53;
-  const double r = 2.0 * u - 1.0;
-  const double v = exp(r / 20.0);
-  (side ? V : U)[rem] = v;
+  (side ? V : U)[rem] = dev::coefficient(seed, i, side, layer);
 }
-
-// Geometry of one pass over layers lo..hi (P = hi - lo + 1 <= 3).
-struct Pass {
-  int64_t n, q;
-  int d, lo, hi;
-  int64_t stride;   // 2^(d-hi) q : partner distance of layer hi
-  int64_t ngroups;  // m / 2^P
-};
-
-__device__ __forceinline__ int64_t group_base(const Pass &ps, int64_t g) {
-  const int64_t r = g % ps.q;
-  const int64_t rest = g / ps.q;
-  const int lowbits = ps.d - ps.hi;
-  const int64_t tl = rest & ((int64_t(1) << lowbits) - 1);
-  const int64_t th = rest >> lowbits;
-  return r + ps.q * (tl + (th << (ps.d - ps.lo + 1)));
-}
-
-template <typename T>
-__device__ __forceinline__ T convert_out(double x);
-template <>
-__device__ __forceinline__ double convert_out<double>(double x) { return x; }
-template <>
-__device__ __forceinline__ float convert_out<float>(double x) { return float(x); }
 
 // Two-sided pass. Thread (gx, gy) owns row group gx and column group gy.
 template <int P, typename TO>
@@ -86,162 +52,31 @@ __global__ void __launch_bounds__(256) k_transform2(const double *__restrict__ A
                                                     TO *__restrict__ Out, int64_t ldo,
                                                     const double *__restrict__ U,
                                                     const double *__restrict__ V, Pass ps) {
-  constexpr int G = 1 << P;
   const int64_t gr = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (gr >= ps.ngroups) return;
   const int64_t rb = group_base(ps, gr);
   if (rb >= ps.n) return;
-  int64_t ri[G];
-  bool rv[G];
-#pragma unroll
-  for (int p = 0; p < G; ++p) {
-    ri[p] = rb + p * ps.stride;
-    rv[p] = ri[p] < ps.n;
-  }
   for (int64_t gc = blockIdx.y; gc < ps.ngroups; gc += gridDim.y) {
     const int64_t cb = group_base(ps, gc);
     if (cb >= ps.n) continue;
-    int64_t ci[G];
-    bool cv[G];
-#pragma unroll
-    for (int p = 0; p < G; ++p) {
-      ci[p] = cb + p * ps.stride;
-      cv[p] = ci[p] < ps.n;
-    }
-    double x[G][G];
-#pragma unroll
-    for (int c = 0; c < G; ++c) {
-#pragma unroll
-      for (int r = 0; r < G; ++r) {
-        x[r][c] = (rv[r] && cv[c]) ? A[ri[r] + ci[c] * lda] : 0.0;
-      }
-    }
-#pragma unroll
-    for (int bit = 0; bit < P; ++bit) {
-      // layer l = hi - bit pairs block members p and p ^ (1 << bit)
-      const int l = ps.hi - bit;
-      const int64_t off = int64_t(l - 1) * ps.n;
-      double fr[G], fc[G];
-#pragma unroll
-      for (int p = 0; p < G; ++p) {
-        const int p2 = p ^ (1 << bit);
-        const double sr = (rv[p] && rv[p2]) ? kInvSqrt2 : 1.0;
-        const double sc = (cv[p] && cv[p2]) ? kInvSqrt2 : 1.0;
-        fr[p] = rv[p] ? U[off + ri[p]] * sr : 0.0;
-        fc[p] = cv[p] ? V[off + ci[p]] * sc : 0.0;
-      }
-      // rows
-#pragma unroll
-      for (int p = 0; p < G; ++p) {
-        if (p & (1 << bit)) continue;
-        const int p2 = p | (1 << bit);
-        if (!rv[p2]) continue;
-#pragma unroll
-        for (int c = 0; c < G; ++c) {
-          const double a = x[p][c], b = x[p2][c];
-          x[p][c] = a + b;
-          x[p2][c] = a - b;
-        }
-      }
-      // columns
-#pragma unroll
-      for (int p = 0; p < G; ++p) {
-        if (p & (1 << bit)) continue;
-        const int p2 = p | (1 << bit);
-        if (!cv[p2]) continue;
-#pragma unroll
-        for (int r = 0; r < G; ++r) {
-          const double a = x[r][p], b = x[r][p2];
-          x[r][p] = a + b;
-          x[r][p2] = a - b;
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < G; ++r)
-#pragma unroll
-        for (int c = 0; c < G; ++c) x[r][c] *= fr[r] * fc[c];
-    }
-#pragma unroll
-    for (int c = 0; c < G; ++c) {
-#pragma unroll
-      for (int r = 0; r < G; ++r) {
-        if (rv[r] && cv[c]) Out[ri[r] + ci[c] * ldo] = convert_out<TO>(x[r][c]);
-      }
-    }
+    dev::transform2_block<P, TO>(A, lda, Out, ldo, U, V, ps, rb, cb);
   }
 }
 
-// One-sided pass on an n x nrhs block. op T: layers hi..lo, mix then scale;
-// op N: layers lo..hi, scale then mix.
+// One-sided pass on an n x nrhs block.
 template <int P, int OP>
 __global__ void __launch_bounds__(256) k_transform_vec(double *__restrict__ B, int64_t ldb,
                                                        int64_t nrhs,
                                                        const double *__restrict__ C, Pass ps) {
-  constexpr int G = 1 << P;
   const int64_t gr = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (gr >= ps.ngroups) return;
   const int64_t rb = group_base(ps, gr);
   if (rb >= ps.n) return;
-  int64_t ri[G];
-  bool rv[G];
-#pragma unroll
-  for (int p = 0; p < G; ++p) {
-    ri[p] = rb + p * ps.stride;
-    rv[p] = ri[p] < ps.n;
-  }
-  for (int64_t j = blockIdx.y; j < nrhs; j += gridDim.y) {
-    double x[G];
-#pragma unroll
-    for (int p = 0; p < G; ++p) x[p] = rv[p] ? B[ri[p] + j * ldb] : 0.0;
-#pragma unroll
-    for (int s = 0; s < P; ++s) {
-      const int bit = (OP == RBT_OP_T) ? s : P - 1 - s;
-      const int l = ps.hi - bit;
-      const int64_t off = int64_t(l - 1) * ps.n;
-      double f[G];
-#pragma unroll
-      for (int p = 0; p < G; ++p) {
-        const int p2 = p ^ (1 << bit);
-        f[p] = rv[p] ? C[off + ri[p]] * ((rv[p2]) ? kInvSqrt2 : 1.0) : 0.0;
-      }
-      if (OP == RBT_OP_N) {
-        // scale by the coefficient of the input index (R_l before O_l);
-        // the 1/sqrt(2) of a pair is common to both members, so it can be
-        // applied before the mix as well
-#pragma unroll
-        for (int p = 0; p < G; ++p) x[p] *= f[p];
-      }
-#pragma unroll
-      for (int p = 0; p < G; ++p) {
-        if (p & (1 << bit)) continue;
-        const int p2 = p | (1 << bit);
-        if (!rv[p2]) continue;
-        const double a = x[p], b = x[p2];
-        x[p] = a + b;
-        x[p2] = a - b;
-      }
-      if (OP == RBT_OP_T) {
-#pragma unroll
-        for (int p = 0; p < G; ++p) x[p] *= f[p];
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < G; ++p)
-      if (rv[p]) B[ri[p] + j * ldb] = x[p];
-  }
+  for (int64_t j = blockIdx.y; j < nrhs; j += gridDim.y)
+    dev::transform_vec_block<P, OP>(B, ldb, j, C, ps, rb);
 }
 
-Pass make_pass(const Geometry &g, int lo, int hi) {
-  Pass ps;
-  ps.n = g.n;
-  ps.q = g.q;
-  ps.d = g.d;
-  ps.lo = lo;
-  ps.hi = hi;
-  ps.stride = g.q << (g.d - hi);
-  ps.ngroups = g.m >> (hi - lo + 1);
-  return ps;
-}
+Pass make_pass(const Geometry &g, int lo, int hi) { return dev::make_pass(g.n, g.q, g.d, lo, hi); }
 
 template <typename TO>
 hipError_t launch_pass2(const Pass &ps, const double *A, int64_t lda, TO *out, int64_t ldo,
@@ -290,8 +125,7 @@ hipError_t launch_transform2(const Geometry &g, const double *A, int64_t lda, vo
   if (g.n == 0) return hipSuccess;
   if (g.d == 0) {
     if (out_prec == RBT_FP64 && (const void *)A == out) return hipSuccess;
-    Pass ps;
-    ps.n = g.n; ps.q = g.n; ps.d = 0; ps.lo = 1; ps.hi = 0; ps.stride = g.n; ps.ngroups = g.n;
+    const Pass ps = dev::identity_pass(g.n);
     if (out_prec == RBT_FP32) return launch_pass2<float>(ps, A, lda, (float *)out, ldo, U, V, s);
     return launch_pass2<double>(ps, A, lda, (double *)out, ldo, U, V, s);
   }

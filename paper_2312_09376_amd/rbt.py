@@ -21,6 +21,8 @@ def _colmajor_ld(t):
     if t.dim() != 2:
         return None
     rows, cols = t.shape
+    if rows == 0 or cols == 0:
+        return max(1, rows)  # an empty matrix: any leading dimension will do
     if rows > 1 and t.stride(0) != 1:
         return None
     ld = t.stride(1) if cols > 1 else max(1, rows)
@@ -205,6 +207,91 @@ def solve_mixed(A, B, depth=2, seed=2023, prec=RBT_FP32, solver=RBT_IR_CLASSIC, 
                                 _p(iters), _p(berr), _p(info), _p(work), work.numel(),
                                 _stream(dev)), "rbt_solve_mixed")
     return X, LU, iters, berr, info, work
+
+
+class BatchPlan:
+    """Sizes, workspace and device descriptor arrays of a planned batch."""
+
+    def __init__(self, ns, ks, depth, prec, device="cuda"):
+        ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int64))
+        ks = np.ascontiguousarray(np.asarray(ks, dtype=np.int64))
+        if ns.shape != ks.shape or ns.ndim != 1:
+            raise ValueError("ns and ks must be 1-D arrays of the same length")
+        self.ns, self.ks, self.depth, self.prec = ns, ks, int(depth), int(prec)
+        self.batch = int(ns.size)
+        vp = ctypes.c_void_p
+        nbytes = lib().rbt_batched_workspace_size(self.batch, ns.ctypes.data_as(vp),
+                                                  ks.ctypes.data_as(vp), self.depth, self.prec)
+        if nbytes == 0 and self.batch > 0:
+            raise _lib.RBTError("rbt_batched_workspace_size rejected the sizes")
+        self.work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        check(lib().rbt_batched_plan(self.batch, ns.ctypes.data_as(vp), ks.ctypes.data_as(vp),
+                                     self.depth, self.prec, _p(self.work), self.work.numel(),
+                                     _stream(self.work.device)), "rbt_batched_plan")
+
+
+def batched_plan(ns, ks, depth=2, prec=RBT_FP32, device="cuda"):
+    return BatchPlan(ns, ks, depth, prec, device)
+
+
+class BatchArgs:
+    """Device descriptor arrays (pointers and leading dimensions of A, B, X)
+    and per-system outputs of a batched solve; building them copies to the
+    device, launching with them does not."""
+
+    def __init__(self, plan, As, Bs, Xs=None):
+        if len(As) != plan.batch or len(Bs) != plan.batch:
+            raise ValueError("batch size does not match the plan")
+        dev = plan.work.device
+        As = [colmajor(a) for a in As]
+        Bs = [colmajor(b) for b in Bs]
+        for s, (a, b) in enumerate(zip(As, Bs)):
+            _dev_f64(a, f"As[{s}]")
+            _dev_f64(b, f"Bs[{s}]")
+            if a.shape != (plan.ns[s], plan.ns[s]) or b.shape != (plan.ns[s], plan.ks[s]):
+                raise ValueError(f"system {s}: shapes {tuple(a.shape)}, {tuple(b.shape)} do not "
+                                 f"match the plan ({plan.ns[s]}, {plan.ks[s]})")
+        if Xs is None:
+            Xs = [torch.empty_strided((int(n), int(k)), (1, max(1, int(n))), dtype=torch.float64,
+                                      device=dev) for n, k in zip(plan.ns, plan.ks)]
+        for s, x in enumerate(Xs):
+            _dev_f64(x, f"Xs[{s}]")
+            _ld(x)
+
+        def ptrs(ts):
+            return torch.tensor([t.data_ptr() for t in ts], dtype=torch.int64, device=dev)
+
+        def lds(ts):
+            return torch.tensor([_ld(t) for t in ts], dtype=torch.int64, device=dev)
+
+        self.As, self.Bs, self.Xs = As, Bs, Xs
+        self.pA, self.lA, self.pB, self.lB = ptrs(As), lds(As), ptrs(Bs), lds(Bs)
+        self.pX, self.lX = ptrs(Xs), lds(Xs)
+        nb = max(1, plan.batch)
+        self.iters = torch.zeros(nb, dtype=torch.int32, device=dev)
+        self.berr = torch.zeros(nb, dtype=torch.float64, device=dev)
+        self.info = torch.zeros(nb, dtype=torch.int32, device=dev)
+
+
+def solve_batched_launch(plan, args, seed=2023, tol=-10.0, max_iter=30):
+    """Enqueue the batched solve on the current stream (no allocation, no
+    copy, no synchronization: capturable in a HIP graph). tol < 0 means
+    |tol| n_s eps64 for system s."""
+    check(lib().rbt_solve_batched(plan.batch, _p(args.pA), _p(args.lA), _p(args.pB), _p(args.lB),
+                                  _p(args.pX), _p(args.lX), plan.depth, seed, plan.prec,
+                                  float(tol), int(max_iter), _p(args.iters), _p(args.berr),
+                                  _p(args.info), _p(plan.work), plan.work.numel(),
+                                  _stream(plan.work.device)), "rbt_solve_batched")
+
+
+def solve_batched(plan, As, Bs, seed=2023, tol=None, max_iter=30, Xs=None):
+    """Solve the planned batch: As[s] (n x n), Bs[s] (n x nrhs) column-major
+    FP64 device tensors. tol < 0 means |tol| n_s eps64 for system s (default
+    10 n_s eps64). Returns (Xs, iters, berr, info); iters/berr/info are
+    device tensors with one entry per system."""
+    args = BatchArgs(plan, As, Bs, Xs)
+    solve_batched_launch(plan, args, seed, -10.0 if tol is None else tol, max_iter)
+    return args.Xs, args.iters, args.berr, args.info
 
 
 def backward_error(A, X, B, work=None):
