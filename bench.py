@@ -52,12 +52,19 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=4096, help="oracle sample size")
     ap.add_argument("--outer-nb", type=int, default=0,
                     help="panel width of the elimination (multiple of 128; 0 = library default)")
-    ap.add_argument("--mode", choices=["solve", "mixed", "copy"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "mixed", "batched", "copy"], default="solve",
                     help="solve: the FP64 step (default); mixed: FP32/BF16 elimination with FP64 "
                          "refinement; copy: a plain FP64 matrix copy through the transform kernel "
                          "at depth 0 (reference point for HBM byte counters)")
     ap.add_argument("--prec", choices=["fp32", "bf16"], default="fp32", help="mixed mode")
     ap.add_argument("--solver", choices=["classic", "gmres"], default="classic", help="mixed mode")
+    ap.add_argument("--batch", type=int, default=2048, help="batched mode: number of systems")
+    ap.add_argument("--batch-n", type=int, default=0,
+                    help="batched mode: all systems of this order (0: n ~ U{37..1500})")
+    ap.add_argument("--batch-nrhs", type=int, default=0,
+                    help="batched mode: all systems with this many right-hand sides (0: U{1..16})")
+    ap.add_argument("--tol-scale", type=float, default=10.0,
+                    help="batched mode: refine to tol-scale * n * eps per system (0: max_iter steps)")
     ap.add_argument("--matrix", choices=["randn", "logcond", "dominant"], default="randn",
                     help="mixed mode: N(0,1), Q1 diag(10^-6 .. 1) Q2^T, or I + 0.3 N(0,1)/sqrt(n)")
     return ap.parse_args()
@@ -188,6 +195,90 @@ def mixed_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def batched_mode(args):
+    """One step = one graph replay of rbt_solve_batched over the whole batch:
+    `batch` systems with n ~ U{37..1500}, nrhs ~ U{1..16} (size seed 7),
+    A_s ~ N(0,1) (seed 42 + s), B_s ~ N(0,1) (seed 64 + s); FP32 (or BF16
+    update) elimination and FP64 refinement to 10 n_s eps per system."""
+    import numpy as np
+    import torch
+    from paper_2312_09376_amd import rbt, workloads
+    ns, ks = workloads.batch_sizes(count=args.batch)
+    if args.batch_n:
+        ns = np.full(args.batch, args.batch_n, dtype=np.int64)
+    if args.batch_nrhs:
+        ks = np.full(args.batch, args.batch_nrhs, dtype=np.int64)
+    tol = -args.tol_scale
+    prec = rbt.RBT_FP32 if args.prec == "fp32" else rbt.RBT_BF16
+    d = args.depth
+    As, Bs = [], []
+    for s_, (n, k) in enumerate(zip(ns, ks)):
+        if args.matrix == "dominant":
+            A = workloads.device_randn(int(n), int(n), workloads.MATRIX_SEED + s_) * (0.3 / math.sqrt(n))
+            A.diagonal().add_(1.0)
+        else:
+            A = workloads.device_randn(int(n), int(n), workloads.MATRIX_SEED + s_)
+        As.append(A)
+        Bs.append(workloads.device_randn(int(n), int(k), workloads.RHS_SEED + s_))
+    plan = rbt.batched_plan(ns, ks, d, prec)
+    bargs = rbt.BatchArgs(plan, As, Bs)
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        rbt.solve_batched_launch(plan, bargs, seed=args.seed, tol=tol, max_iter=args.max_iter)
+    torch.cuda.current_stream().wait_stream(stream)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        rbt.solve_batched_launch(plan, bargs, seed=args.seed, tol=tol, max_iter=args.max_iter)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        graph.replay()
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_gpu = ev0.elapsed_time(ev1) / args.steps
+    flops = float(np.sum((2.0 / 3.0) * ns.astype(np.float64) ** 3))
+    iters = bargs.iters.cpu().numpy()
+    berr = bargs.berr.cpu().numpy()
+    info = bargs.info.cpu().numpy()
+    tols = max(args.tol_scale, 10.0) * ns * 2.0 ** -52
+    converged = int(np.sum(berr <= tols))
+    peak = PEAK_FP32_MFMA_TFLOPS if args.prec == "fp32" else PEAK_BF16_MFMA_TFLOPS
+    achieved = flops / (ms_gpu * 1e-3) / 1e12
+    out = {
+        "metric": "batched solve TFLOP/s (sum of 2/3 n^3 over the batch) and systems/s",
+        "value": round(flops / (ms_step * 1e-3) / 1e12, 4), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": f"{args.batch} systems, "
+                               + (f"n={args.batch_n}, " if args.batch_n else "n~U{37..1500}, ")
+                               + (f"nrhs={args.batch_nrhs}, " if args.batch_nrhs else "nrhs~U{1..16} (seed 7), ")
+                               + f"A={args.matrix} (seed 42+s), depth {d}, {args.prec.upper()} "
+                               f"elimination + FP64 refinement to 10 n eps, one persistent "
+                               f"launch replayed from a HIP graph",
+                   "batch": args.batch, "depth": d, "matrix": args.matrix,
+                   "sum_n2": int(np.sum(ns.astype(np.int64) ** 2)), "flops": flops},
+        "systems_per_s": round(args.batch / (ms_step * 1e-3), 1),
+        "roofline": {"bound": "mfma", "kernel": "k_batched (persistent, whole method per system)",
+                     "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "avg_launch_ms": round(ms_gpu, 4), "flops_per_launch": flops},
+        "converged": converged, "max_iters": int(iters.max()), "mean_iters": float(iters.mean()),
+        "max_berr_over_tol": float(np.max(berr / tols)), "zero_pivots": int(np.sum(info != 0)),
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(n, nrhs, depth, seed):
     """The oracle, as it stands, on the host cores: one full solve (coefficients,
     transform, elimination, solves, refinement to the same tolerance)."""
@@ -234,6 +325,9 @@ def main():
         return
     if args.mode == "mixed":
         mixed_mode(args)
+        return
+    if args.mode == "batched":
+        batched_mode(args)
         return
     if args.outer_nb:
         rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, args.outer_nb)

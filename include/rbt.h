@@ -208,6 +208,9 @@ int rbt_batched_plan(int64_t batch, const int64_t *n, const int64_t *nrhs, int d
  * (the draw of the header's conventions, per system). Refinement stops per
  * system at the Eq. 7 backward error <= tol or after max_iter corrections;
  * tol < 0 means |tol| n_s 2^-52 for system s of order n_s (NaN: -11).
+ * A system also stops when two corrections in a row fail to reduce its best
+ * backward error by 10 % (stagnation), or when the error is NaN; its
+ * berr_dev entry then stays above tol.
  * iters_dev, berr_dev, info_dev: device arrays of `batch` entries
  * (nullable) for the correction count, the final backward error and the
  * first zero pivot (as rbt_genp) of each system. Enqueues a reset kernel and

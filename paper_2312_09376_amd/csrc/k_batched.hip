@@ -50,7 +50,7 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 // a step); the sweeps use both regions.
 constexpr int kR0Doubles = BB * LDS_;       // 4160 doubles
 constexpr int kR1Doubles = BB * LDS_;
-static_assert(6 * BB * NR <= kR0Doubles + kR1Doubles, "sweep buffers exceed LDS");
+static_assert(5 * BB * NR <= kR0Doubles + kR1Doubles, "sweep buffers exceed LDS");  // part + xs
 static_assert(256 * NR + BT / 64 <= kR0Doubles, "residual buffers exceed region 0");
 
 struct Args {
@@ -511,87 +511,103 @@ __device__ __noinline__ void transform_vec_sys(const Sys &s, int d, double *Y, i
   __syncthreads();
 }
 
-// Y (n x nrhs FP64, ld ldy) <- (L U)^-1 Y with the FP32 factors widened to
-// FP64 and the FP64 inverses of the diagonal blocks: for each block, the
-// contributions of the solved blocks (threads: 64 rows x 4 segments of 16
-// columns of each 64-column chunk of the solved range, the chunk of Y
-// staged in LDS), then x_b = Dinv_b r_b.
-template <bool LOWER>
+// Y (n x nrhs FP64, ld ldy) <- (L U)^-1 Y (LOWER: L, else U) with the FP32
+// factors widened to FP64 and the FP64 inverses of the diagonal blocks,
+// right-looking: for each diagonal block b in sweep order, x_b = Dinv_b y_b
+// (threads: 64 rows x 4 segments of 16, reduced in LDS), then every row
+// still to be solved takes y_m -= F[m, block b] x_b as an FP64 matrix-core
+// product of 16-row tiles of the factor (16 loads per lane, issued one tile
+// ahead) with x_b (16 values per lane, held in registers for the step).
+// v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; output element (l, v) is row l / 16 + 4 v, column
+// l % 16. NRT: right-hand sides of the inverse product (>= N).
+template <bool LOWER, int NRT>
 __device__ __noinline__ void sweep(const Sys &s, double *Y, int64_t ldy, double *L0) {
   const int64_t n = s.n;
   const int N = int(s.nrhs);
   const int tid = threadIdx.x, i = tid & 63, sg = tid >> 6;
-  double(*part)[BB][NR] = reinterpret_cast<double(*)[BB][NR]>(L0);  // [4][64][16]
-  double(*xs)[NR] = reinterpret_cast<double(*)[NR]>(L0 + 4 * BB * NR);
-  double(*yc)[NR] = reinterpret_cast<double(*)[NR]>(L0 + 5 * BB * NR);
+  const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, lk = lane >> 4;
+  double(*part)[BB][NRT] = reinterpret_cast<double(*)[BB][NRT]>(L0);  // [4][64][NRT]
+  double(*xs)[NR] = reinterpret_cast<double(*)[NR]>(L0 + 4 * BB * NRT);  // [64][16]
   const int64_t nblk = (n + BB - 1) / BB;
   for (int64_t t = 0; t < nblk; ++t) {
     const int64_t b = LOWER ? t : nblk - 1 - t;
     const int64_t r0 = b * BB;
     const int kb = int(n - r0 < BB ? n - r0 : BB);
-    // solved range: [0, r0) for L, [r0 + kb, n) for U
-    const int64_t lo = LOWER ? 0 : r0 + kb, hi = LOWER ? r0 : n;
-    double acc[NR];
-#pragma unroll
-    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
-    const float *Frow = s.F + (r0 + (i < kb ? i : kb - 1));
-    for (int64_t c0 = lo; c0 < hi; c0 += BB) {
-      const int cw = int(hi - c0 < BB ? hi - c0 : BB);
-      float fv[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int kx = sg * 16 + q;
-        fv[q] = Frow[(c0 + (kx < cw ? kx : cw - 1)) * n];
-      }
-      __syncthreads();
-      for (int e = tid; e < BB * NR; e += BT) {
-        const int kx = e / NR, c = e % NR;
-        yc[kx][c] = (kx < cw && c < N) ? Y[(c0 + kx) + int64_t(c) * ldy] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll 2
-      for (int q = 0; q < 16; ++q) {
-        const int kx = sg * 16 + q;
-        const double a = (i < kb && kx < cw) ? double(fv[q]) : 0.0;
-#pragma unroll
-        for (int c = 0; c < NR; ++c) acc[c] += a * yc[kx][c];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < NR; ++c) part[sg][i][c] = acc[c];
-    __syncthreads();
+    // y_b -> LDS
     if (sg == 0) {
 #pragma unroll
-      for (int c = 0; c < NR; ++c) {
-        const double sum = (part[0][i][c] + part[1][i][c]) + (part[2][i][c] + part[3][i][c]);
-        xs[i][c] = (i < kb && c < N) ? Y[(r0 + i) + int64_t(c) * ldy] - sum : 0.0;
-      }
+      for (int c = 0; c < NR; ++c)
+        xs[i][c] = (i < kb && c < N) ? Y[(r0 + i) + int64_t(c) * ldy] : 0.0;
     }
     __syncthreads();
-    // x_b = Dinv r: thread (i, sg) sums over k in segment sg
+    // x_b = Dinv y_b
     const double *Db = s.Inv + b * BB * BB;
     double dv[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) dv[q] = Db[i + (sg * 16 + q) * BB];
+    double acc[NRT];
 #pragma unroll
-    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
-#pragma unroll 2
+    for (int c = 0; c < NRT; ++c) acc[c] = 0.0;
+#pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int kx = sg * 16 + q;
       const double v = LOWER ? (i > kx ? dv[q] : (i == kx ? 1.0 : 0.0)) : (i <= kx ? dv[q] : 0.0);
 #pragma unroll
-      for (int c = 0; c < NR; ++c) acc[c] += v * xs[kx][c];
+      for (int c = 0; c < NRT; ++c) acc[c] += v * xs[kx][c];
+    }
+#pragma unroll
+    for (int c = 0; c < NRT; ++c) part[sg][i][c] = acc[c];
+    __syncthreads();
+    if (sg == 0) {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        double x = 0.0;
+        if (c < NRT && i < kb && c < N)
+          x = (part[0][i][c] + part[1][i][c]) + (part[2][i][c] + part[3][i][c]);
+        xs[i][c] = x;
+        if (i < kb && c < N) Y[(r0 + i) + int64_t(c) * ldy] = x;
+      }
     }
     __syncthreads();
+    // rows still to be solved: after the block (L) or before it (U)
+    const int64_t lo = LOWER ? r0 + kb : 0, hi = LOWER ? n : r0;
+    if (hi > lo) {
+      double xb[16];
 #pragma unroll
-    for (int c = 0; c < NR; ++c) part[sg][i][c] = acc[c];
-    __syncthreads();
-    if (sg == 0 && i < kb) {
+      for (int kk = 0; kk < 16; ++kk) xb[kk] = xs[lk + 4 * kk][l16];
+      const int64_t ntile = (hi - lo + 15) / 16;
+      auto load_tile = [&](int64_t tt, float (&av)[16]) {
+        const int64_t m = lo + 16 * tt + l16;
+        const int64_t mc = m < hi ? m : hi - 1;
 #pragma unroll
-      for (int c = 0; c < NR; ++c)
-        if (c < N)
-          Y[(r0 + i) + int64_t(c) * ldy] =
-              (part[0][i][c] + part[1][i][c]) + (part[2][i][c] + part[3][i][c]);
+        for (int kk = 0; kk < 16; ++kk) {
+          const int kx = lk + 4 * kk;
+          av[kk] = s.F[mc + (r0 + (kx < kb ? kx : kb - 1)) * n];
+        }
+      };
+      float av[16], an[16];
+      int64_t tt = wave;
+      if (tt < ntile) load_tile(tt, av);
+      for (; tt < ntile; tt += 4) {
+        if (tt + 4 < ntile) load_tile(tt + 4, an);
+        typedef double d4v __attribute__((ext_vector_type(4)));
+        d4v o = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+          const double a = (lk + 4 * kk < kb && lo + 16 * tt + l16 < hi) ? double(av[kk]) : 0.0;
+          o = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb[kk], o, 0, 0, 0);
+        }
+        if (l16 < N) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t m = lo + 16 * tt + lk + 4 * v;
+            if (m < hi) Y[m + int64_t(l16) * ldy] -= o[v];
+          }
+        }
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) av[kk] = an[kk];
+      }
     }
     __syncthreads();
   }
@@ -601,42 +617,58 @@ __device__ __noinline__ void sweep(const Sys &s, double *Y, int64_t ldy, double 
 // with_anorm: also ||A||_inf into *anorm. One pass over A (rows on
 // threads, X staged in LDS by chunks of columns), then the column maxima of
 // |R|, |X|, |B| in a second, small pass.
+template <int NRT>
 __device__ __noinline__ double residual(const Sys &s, double *L0, bool with_anorm, double *anorm) {
   const int64_t n = s.n;
   const int N = int(s.nrhs);
   const int tid = threadIdx.x;
   constexpr int KC = 256;  // columns of A per staged chunk of X
-  double(*xs)[NR] = reinterpret_cast<double(*)[NR]>(L0);  // [KC][16]
+  double(*xs)[NRT] = reinterpret_cast<double(*)[NRT]>(L0);  // [KC][NRT]
   double *red = L0 + KC * NR;
   double amax = 0.0;
   for (int64_t m0 = 0; m0 < n; m0 += BT) {
     const int64_t m = m0 + tid;
-    double acc[NR];
+    double acc[NRT];
 #pragma unroll
-    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NRT; ++c) acc[c] = 0.0;
     double asum = 0.0;
     for (int64_t k0 = 0; k0 < n; k0 += KC) {
       const int kc = int(n - k0 < KC ? n - k0 : KC);
       __syncthreads();
-      for (int e = tid; e < KC * NR; e += BT) {
-        const int kx = e / NR, c = e % NR;
+      for (int e = tid; e < KC * NRT; e += BT) {
+        const int kx = e % KC, c = e / KC;  // consecutive threads: consecutive rows of X
         xs[kx][c] = (kx < kc && c < N) ? s.Xm[(k0 + kx) + int64_t(c) * s.ldx] : 0.0;
       }
       __syncthreads();
       if (m < n) {
         const double *Ap = s.A + m + k0 * s.lda;
-        for (int kx = 0; kx < kc; ++kx) {
+        // batches of 32 loads in flight (kc is a multiple of 32 except at the end)
+        int kx = 0;
+#pragma unroll 1
+        for (; kx + 32 <= kc; kx += 32) {
+          double av[32];
+#pragma unroll
+          for (int q = 0; q < 32; ++q) av[q] = Ap[int64_t(kx + q) * s.lda];
+#pragma unroll
+          for (int q = 0; q < 32; ++q) {
+            if (with_anorm) asum += fabs(av[q]);
+#pragma unroll
+            for (int c = 0; c < NRT; ++c) acc[c] += av[q] * xs[kx + q][c];
+          }
+        }
+#pragma unroll 1
+        for (; kx < kc; ++kx) {
           const double a = Ap[int64_t(kx) * s.lda];
           if (with_anorm) asum += fabs(a);
 #pragma unroll
-          for (int c = 0; c < NR; ++c) acc[c] += a * xs[kx][c];
+          for (int c = 0; c < NRT; ++c) acc[c] += a * xs[kx][c];
         }
       }
     }
     if (m < n) {
       amax = nanmax(amax, asum);
 #pragma unroll
-      for (int c = 0; c < NR; ++c)
+      for (int c = 0; c < NRT; ++c)
         if (c < N) s.R[m + int64_t(c) * n] = s.Bm[m + int64_t(c) * s.ldb] - acc[c];
     }
   }
@@ -663,6 +695,39 @@ __device__ __noinline__ double residual(const Sys &s, double *L0, bool with_anor
     be = nanmax(be, e);
   }
   return be;
+}
+
+// X <- V (LU)^-1 U^T X (X holds B on entry), then classical refinement in
+// FP64 until the Eq. 7 backward error is <= tol or max_iter corrections.
+template <int NRT>
+__device__ void refine_system(const Sys &s, int d, double tol, int max_iter, double *L0,
+                              double *anorm_sh, int *it_out, double *be_out) {
+  const int64_t n = s.n;
+  transform_vec_sys<RBT_OP_T>(s, d, s.Xm, s.ldx, s.U);
+  sweep<true, NRT>(s, s.Xm, s.ldx, L0);
+  sweep<false, NRT>(s, s.Xm, s.ldx, L0);
+  transform_vec_sys<RBT_OP_N>(s, d, s.Xm, s.ldx, s.V);
+  int it = 0, stalled = 0;
+  double be = 0.0, best = INFINITY;
+  for (;;) {
+    be = residual<NRT>(s, L0, it == 0, anorm_sh);
+    if (be <= tol || it >= max_iter) break;  // a NaN error never looks converged
+    // stagnation: two corrections in a row that do not improve the best
+    // backward error by 10 % end the refinement (reported not converged)
+    stalled = (be < 0.9 * best) ? 0 : stalled + 1;
+    if (be < best) best = be;
+    if (stalled >= 2 || be != be) break;
+    transform_vec_sys<RBT_OP_T>(s, d, s.R, n, s.U);
+    sweep<true, NRT>(s, s.R, n, L0);
+    sweep<false, NRT>(s, s.R, n, L0);
+    transform_vec_sys<RBT_OP_N>(s, d, s.R, n, s.V);
+    for (int64_t e = threadIdx.x; e < n * s.nrhs; e += BT)
+      s.Xm[(e % n) + (e / n) * s.ldx] += s.R[e];
+    __syncthreads();
+    ++it;
+  }
+  *it_out = it;
+  *be_out = be;
 }
 
 template <bool BF16U>
@@ -713,30 +778,19 @@ __device__ void solve_system(const Args &a, const BatchDesc &D, float *fbase, do
   }
   __syncthreads();
   eliminate<BF16U>(s, L0, L1, info_sh);
-  // X = V (LU)^-1 U^T B
+  // X = V (LU)^-1 U^T B, then refinement (tol < 0: |tol| n eps64)
   for (int64_t e = tid; e < n * s.nrhs; e += BT)
     s.Xm[(e % n) + (e / n) * s.ldx] = s.Bm[(e % n) + (e / n) * s.ldb];
   __syncthreads();
-  transform_vec_sys<RBT_OP_T>(s, d, s.Xm, s.ldx, s.U);
-  sweep<true>(s, s.Xm, s.ldx, L0);
-  sweep<false>(s, s.Xm, s.ldx, L0);
-  transform_vec_sys<RBT_OP_N>(s, d, s.Xm, s.ldx, s.V);
-  // refinement (tol < 0: |tol| n eps64 for this system)
   const double tol = a.tol < 0.0 ? -a.tol * double(n) * 0x1.0p-52 : a.tol;
   int it = 0;
   double be = 0.0;
-  for (;;) {
-    be = residual(s, L0, it == 0, anorm_sh);
-    if (be <= tol || it >= a.max_iter) break;  // a NaN error never looks converged
-    transform_vec_sys<RBT_OP_T>(s, d, s.R, n, s.U);
-    sweep<true>(s, s.R, n, L0);
-    sweep<false>(s, s.R, n, L0);
-    transform_vec_sys<RBT_OP_N>(s, d, s.R, n, s.V);
-    for (int64_t e = tid; e < n * s.nrhs; e += BT)
-      s.Xm[(e % n) + (e / n) * s.ldx] += s.R[e];
-    __syncthreads();
-    ++it;
-  }
+  if (s.nrhs <= 1)
+    refine_system<1>(s, d, tol, a.max_iter, L0, anorm_sh, &it, &be);
+  else if (s.nrhs <= 4)
+    refine_system<4>(s, d, tol, a.max_iter, L0, anorm_sh, &it, &be);
+  else
+    refine_system<NR>(s, d, tol, a.max_iter, L0, anorm_sh, &it, &be);
   if (tid == 0) {
     if (a.iters) a.iters[D.sys] = it;
     if (a.berr) a.berr[D.sys] = be;
