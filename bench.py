@@ -249,6 +249,7 @@ def batched_mode(args):
     iters = bargs.iters.cpu().numpy()
     berr = bargs.berr.cpu().numpy()
     info = bargs.info.cpu().numpy()
+    path = bargs.path.cpu().numpy()
     tols = max(args.tol_scale, 10.0) * ns * 2.0 ** -52
     converged = int(np.sum(berr <= tols))
     peak = PEAK_FP32_MFMA_TFLOPS if args.prec == "fp32" else PEAK_BF16_MFMA_TFLOPS
@@ -274,6 +275,7 @@ def batched_mode(args):
                      "avg_launch_ms": round(ms_gpu, 4), "flops_per_launch": flops},
         "converged": converged, "max_iters": int(iters.max()), "mean_iters": float(iters.mean()),
         "max_berr_over_tol": float(np.max(berr / tols)), "zero_pivots": int(np.sum(info != 0)),
+        "fp64_fallbacks": int(np.sum(path != 0)),
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)

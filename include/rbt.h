@@ -183,12 +183,16 @@ int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, float
  * rbt_solve_mixed: FP32 elimination of A~_s, or BF16 trailing-update
  * operands, and classical FP64 refinement with the original A_s), all in ONE
  * persistent launch: each workgroup takes systems from a queue, largest
- * first, and runs every step of the method on each.
+ * first, and runs every step of the method on each. A system whose
+ * low-precision refinement does not reach tol is factored again with FP64
+ * storage and arithmetic (same coefficients) and refined again.
  *
  * Host. Workspace bytes for a batch of `batch` systems with orders n[s] and
  * right-hand-side counts nrhs[s] (host arrays; 0 <= nrhs[s] <= 16), depth
  * <= 3, prec RBT_FP32 or RBT_BF16; 0 for invalid arguments. About
- * 4 n^2 + 8 (2 n d + 64^2 ceil(n/64) + n nrhs) bytes per system. */
+ * 12 n^2 + 8 (2 n d + 64^2 ceil(n/64) + n nrhs) bytes per system (FP32
+ * factors, FP64 factors of the fallback, coefficients, inverse blocks,
+ * residual). */
 size_t rbt_batched_workspace_size(int64_t batch, const int64_t *n, const int64_t *nrhs, int depth,
                                   int prec);
 
@@ -211,9 +215,10 @@ int rbt_batched_plan(int64_t batch, const int64_t *n, const int64_t *nrhs, int d
  * A system also stops when two corrections in a row fail to reduce its best
  * backward error by 10 % (stagnation), or when the error is NaN; its
  * berr_dev entry then stays above tol.
- * iters_dev, berr_dev, info_dev: device arrays of `batch` entries
- * (nullable) for the correction count, the final backward error and the
- * first zero pivot (as rbt_genp) of each system. Enqueues a reset kernel and
+ * iters_dev, berr_dev, info_dev, path_dev: device arrays of `batch`
+ * entries (nullable) for the correction count (both passes), the final
+ * backward error, the first zero pivot (as rbt_genp) of the last pass, and
+ * the pass that produced X (0: low precision, 1: FP64 fallback). Enqueues a reset kernel and
  * the persistent kernel on `stream`, allocates nothing and synchronizes
  * nothing, so it can be captured in a HIP graph. A plan that does not match
  * (batch, depth, prec) or a workspace smaller than the plan's makes the
@@ -222,7 +227,7 @@ int rbt_solve_batched(int64_t batch, const double *const *A, const int64_t *lda,
                       const double *const *B, const int64_t *ldb, double *const *X,
                       const int64_t *ldx, int depth, uint64_t seed, int prec, double tol,
                       int max_iter, int32_t *iters_dev, double *berr_dev, int32_t *info_dev,
-                      void *work, size_t work_bytes, void *stream);
+                      int32_t *path_dev, void *work, size_t work_bytes, void *stream);
 
 /* Device. Backward error of Eq. 7 for n x nrhs X against A (n x n) and B:
  * max over columns of ||B - A X||_inf / (||A||_inf ||X||_inf + ||B||_inf),

@@ -806,7 +806,7 @@ namespace rbt {
 namespace {
 
 struct BatchPlanSizes {
-  size_t f_off, d_off, total;
+  size_t f_off, d_off, f64_off, total;
 };
 
 // Workspace: header | descriptor table | FP32 factors | FP64 areas; each
@@ -815,7 +815,7 @@ BatchPlanSizes batch_sizes(int64_t batch, const int64_t *n, const int64_t *nrhs,
                            std::vector<BatchDesc> *desc) {
   BatchPlanSizes z{};
   z.f_off = align256(kBatchTableOffset + size_t(batch) * sizeof(BatchDesc));
-  size_t f = 0, d = 0;  // floats, doubles
+  size_t f = 0, d = 0, f64 = 0;  // floats, doubles, fallback doubles
   std::vector<int64_t> order(batch);
   for (int64_t i = 0; i < batch; ++i) order[i] = i;
   // largest systems first (longest-processing-time order for the queue)
@@ -832,13 +832,16 @@ BatchPlanSizes batch_sizes(int64_t batch, const int64_t *n, const int64_t *nrhs,
       D.nrhs = nrhs[i];
       D.f_off = int64_t(f);
       D.d_off = int64_t(d);
+      D.f64_off = int64_t(f64);
     }
+    f64 += align256(size_t(n[i]) * n[i] * sizeof(double)) / sizeof(double);
     f += align256(size_t(n[i]) * n[i] * sizeof(float)) / sizeof(float);
     d += align256(size_t(batched_sys_doubles(n[i], nrhs[i], depth)) * sizeof(double)) /
          sizeof(double);
   }
   z.d_off = align256(z.f_off + f * sizeof(float));
-  z.total = z.d_off + d * sizeof(double);
+  z.f64_off = align256(z.d_off + d * sizeof(double));
+  z.total = z.f64_off + f64 * sizeof(double);
   return z;
 }
 
@@ -893,6 +896,7 @@ extern "C" int rbt_batched_plan(int64_t batch, const int64_t *n, const int64_t *
   h.f_off_bytes = int64_t(z.f_off);
   h.d_off_bytes = int64_t(z.d_off);
   h.total_bytes = int64_t(z.total);
+  h.f64_off_bytes = int64_t(z.f64_off);
   std::memcpy(host.data(), &h, sizeof(h));
   if (!desc.empty())
     std::memcpy(host.data() + kBatchTableOffset, desc.data(), desc.size() * sizeof(BatchDesc));
@@ -906,8 +910,8 @@ extern "C" int rbt_solve_batched(int64_t batch, const double *const *A, const in
                                  const double *const *B, const int64_t *ldb, double *const *X,
                                  const int64_t *ldx, int depth, uint64_t seed, int prec,
                                  double tol, int max_iter, int32_t *iters_dev, double *berr_dev,
-                                 int32_t *info_dev, void *work, size_t work_bytes,
-                                 void *stream) {
+                                 int32_t *info_dev, int32_t *path_dev, void *work,
+                                 size_t work_bytes, void *stream) {
   if (batch < 0) return -1;
   if (batch > 0 && (A == nullptr || lda == nullptr)) return A == nullptr ? -2 : -3;
   if (batch > 0 && (B == nullptr || ldb == nullptr)) return B == nullptr ? -4 : -5;
@@ -918,12 +922,13 @@ extern "C" int rbt_solve_batched(int64_t batch, const double *const *A, const in
   if (tol != tol) return -11;
   if (max_iter < 0) return -12;
   if (batch == 0) return 0;
-  if (work == nullptr) return -16;
+  if (work == nullptr) return -17;
   if (work_bytes < kBatchTableOffset + size_t(batch) * sizeof(BatchDesc)) return RBT_ERR_WORKSPACE;
   const int64_t cap = 2 * int64_t(device_cus());  // two workgroups per CU
   const int grid = int(batch < cap ? batch : cap);
   RBT_HIP_CHECK(launch_batched(batch, work, work_bytes, A, lda, B, ldb, X, ldx, depth, seed, prec,
-                               tol, max_iter, iters_dev, berr_dev, info_dev, grid, S(stream)));
+                               tol, max_iter, iters_dev, berr_dev, info_dev, path_dev, grid,
+                               S(stream)));
   return 0;
 }
 

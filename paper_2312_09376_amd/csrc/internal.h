@@ -181,20 +181,22 @@ struct BatchHeader {
   int64_t batch;   // entries in the table
   int32_t depth, prec;
   int64_t f_off_bytes, d_off_bytes, total_bytes;  // FP32 area, FP64 area, workspace used
+  int64_t f64_off_bytes;  // FP64 factor area of the fallback (0: none)
 };
 struct BatchDesc {
   int64_t sys;      // index into the caller's arrays
   int64_t n, nrhs;
   int64_t f_off;    // FP32 factor n x n (ld n), in floats from the FP32 area
   int64_t d_off;    // U, V (n x d each), inverse blocks, residual (n x nrhs), in doubles
-  int64_t pad[3];
+  int64_t f64_off;  // FP64 factor n x n (fallback), in doubles from the FP64 factor area
+  int64_t pad[2];
 };
 constexpr size_t kBatchTableOffset = 256;  // descriptors follow the header
 hipError_t launch_batched(int64_t batch, void *work, size_t work_bytes, const double *const *A,
                           const int64_t *lda, const double *const *B, const int64_t *ldb,
                           double *const *X, const int64_t *ldx, int depth, uint64_t seed,
                           int prec, double tol, int max_iter, int32_t *iters, double *berr,
-                          int32_t *info, int grid, hipStream_t s);
+                          int32_t *info, int32_t *path, int grid, hipStream_t s);
 // FP64 doubles of one batched system's area (U, V, inverse blocks of 64, residual)
 inline int64_t batched_sys_doubles(int64_t n, int64_t nrhs, int d) {
   return 2 * n * d + ((n + 63) / 64) * 64 * 64 + n * nrhs;

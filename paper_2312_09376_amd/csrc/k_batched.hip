@@ -66,6 +66,7 @@ struct Args {
   int32_t *iters;
   double *berr;
   int32_t *info;
+  int32_t *path;
   uint64_t seed;
   double tol;
   int depth, prec, max_iter;
@@ -265,8 +266,10 @@ __device__ __forceinline__ void tile_mma64(FA a_at, FB b_at, d4 (&acc)[2][2]) {
   }
 }
 
-// C (FP32, ld) = acc rounded, rows < rv, cols < cv.
-__device__ __forceinline__ void tile_store64(const d4 (&acc)[2][2], float *C, int64_t ld, int rv,
+// C (FP32 or FP64, ld) = acc (rounded), or C -= acc (SUB); rows < rv,
+// cols < cv.
+template <bool SUB = false, typename T>
+__device__ __forceinline__ void tile_store64(const d4 (&acc)[2][2], T *C, int64_t ld, int rv,
                                              int cv) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -280,28 +283,45 @@ __device__ __forceinline__ void tile_store64(const d4 (&acc)[2][2], float *C, in
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = wm * 32 + 16 * i + lk + 4 * v;
-        if (row < rv) C[row + int64_t(col) * ld] = float(acc[i][j][v]);
+        if (row < rv) {
+          T *p = C + row + int64_t(col) * ld;
+          if (SUB)
+            *p = T(double(*p) - acc[i][j][v]);
+          else
+            *p = T(acc[i][j][v]);
+        }
       }
     }
 }
 
-// Stage a 64 x 64 block of F (FP32, column-major, rows r0.., cols c0..;
-// rv x cv valid) in LDS as FP64 D[c * LDS_ + r] (zero outside).
-__device__ __forceinline__ void stage64(double *D, const float *src, int64_t ld, int rv, int cv) {
+// Stage a 64 x 64 block of F (FP32 or FP64, column-major, rows r0..,
+// cols c0..; rv x cv valid) in LDS as FP64 D[c * LDS_ + r] (zero outside).
+template <typename T>
+__device__ __forceinline__ void stage64(double *D, const T *src, int64_t ld, int rv, int cv) {
   const int tid = threadIdx.x;
   const int col = tid >> 2, seg = (tid & 3) * 16;
-  float v[16];
-  if (col < cv && seg + 16 <= rv) {
-    const float *p = src + seg + int64_t(col) * ld;
+  T v[16];
+  if constexpr (sizeof(T) == 4) {
+    if (col < cv && seg + 16 <= rv) {
+      const float *p = src + seg + int64_t(col) * ld;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const f4u t = *reinterpret_cast<const f4u *>(p + 4 * q);
-      v[4 * q] = t[0]; v[4 * q + 1] = t[1]; v[4 * q + 2] = t[2]; v[4 * q + 3] = t[3];
+      for (int q = 0; q < 4; ++q) {
+        const f4u t = *reinterpret_cast<const f4u *>(p + 4 * q);
+        v[4 * q] = t[0]; v[4 * q + 1] = t[1]; v[4 * q + 2] = t[2]; v[4 * q + 3] = t[3];
+      }
+    } else {
+      const T *p = src + int64_t(col < cv ? col : 0) * ld;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = (col < cv && seg + e < rv) ? p[seg + e] : T(0);
     }
   } else {
-    const float *p = src + int64_t(col < cv ? col : 0) * ld;
+    const T *p = src + int64_t(col < cv ? col : 0) * ld;
+    const int rl = rv - 1;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = (col < cv && seg + e < rv) ? p[seg + e] : 0.0f;
+    for (int e = 0; e < 16; ++e) {
+      const T x = p[seg + e < rv ? seg + e : (rl > 0 ? rl : 0)];
+      v[e] = (col < cv && seg + e < rv) ? x : T(0);
+    }
   }
 #pragma unroll
   for (int e = 0; e < 16; ++e) D[col * LDS_ + seg + e] = double(v[e]);
@@ -312,6 +332,7 @@ __device__ __forceinline__ void stage64(double *D, const float *src, int64_t ld,
 struct Sys {
   int64_t n, nrhs;
   float *F;          // n x n, ld n
+  double *F64;       // n x n, ld n: FP64 factors of the fallback (nullable)
   double *U, *V;     // n x d each
   double *Inv;       // nblk x 64 x 64
   double *R;         // n x nrhs
@@ -323,20 +344,30 @@ struct Sys {
   int64_t ldx;
 };
 
+template <typename T>
+__device__ __forceinline__ T *fmat(const Sys &s) {
+  if constexpr (sizeof(T) == 4)
+    return s.F;
+  else
+    return s.F64;
+}
+
 // Factor the kb x kb diagonal block at (k, k) of F: S (LDS, FP64) <- L\U,
 // T (LDS, FP64) <- L^-1 below the diagonal, U^-1 on and above; inverses
 // also to Inv (64 x 64, full, identity beyond kb); factors back to F.
-__device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double *S, double *T, double *Invb,
-                           int *info_sh) {
+template <typename TF>
+__device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double *S, double *T,
+                                        double *Invb, int *info_sh) {
+  TF *F = fmat<TF>(s);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   {
     const int r = tid & 63, cg = tid >> 6;
     const int rr = r < kb ? r : kb - 1;
-    float v[16];
+    TF v[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
       const int c = cg + 4 * t;
-      v[t] = s.F[(k + rr) + (k + (c < kb ? c : kb - 1)) * s.n];
+      v[t] = F[(k + rr) + (k + (c < kb ? c : kb - 1)) * s.n];
     }
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
@@ -419,14 +450,17 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
   for (int e = tid; e < BB * BB; e += BT) {
     const int r = e & 63, c = e >> 6;
     Invb[r + c * BB] = T[c * LDS_ + r];
-    if (r < kb && c < kb) s.F[(k + r) + (k + c) * s.n] = float(S[c * LDS_ + r]);
+    if (r < kb && c < kb) F[(k + r) + (k + c) * s.n] = TF(S[c * LDS_ + r]);
   }
   __syncthreads();
 }
 
-template <bool BF16U>
+// TF = float: FP32 factors (trailing update in FP32 or, BF16U, with BF16
+// operands); TF = double: FP64 factors (the fallback; FP64 trailing update).
+template <typename TF, bool BF16U>
 __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int *info_sh) {
   const int64_t n = s.n;
+  TF *F = fmat<TF>(s);
   float(*As)[LDF] = reinterpret_cast<float(*)[LDF]>(L0);
   float(*Bs)[LDF] = reinterpret_cast<float(*)[LDF]>(L0 + (BB * LDF + 1) / 2);
   __bf16(*Ah)[LDH] = reinterpret_cast<__bf16(*)[LDH]>(L0);
@@ -434,7 +468,7 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
   for (int64_t k = 0; k < n; k += BB) {
     const int kb = int(n - k < BB ? n - k : BB);
     double *Invb = s.Inv + (k / BB) * BB * BB;
-    diag_block(s, k, kb, L0, L1, Invb, info_sh);
+    diag_block<TF>(s, k, kb, L0, L1, Invb, info_sh);
     const int64_t rest = n - k - kb;
     if (rest <= 0) break;
     f4 acc[2][2];
@@ -444,46 +478,56 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
     for (int64_t r0 = k + kb; r0 < n; r0 += BB) {
       const int rv = int(n - r0 < BB ? n - r0 : BB);
       // stage A21 tile as [k][r]: element (r, kx) at L0[kx * LDS_ + r]
-      stage64(L0, s.F + r0 + k * n, n, rv, kb);
+      stage64(L0, F + r0 + k * n, n, rv, kb);
       __syncthreads();
       tile_mma64([&](int m, int kx) { return L0[kx * LDS_ + m]; },
                  [&](int kx, int nx) { return kx <= nx ? T[nx * LDS_ + kx] : 0.0; }, acc64);
       __syncthreads();
-      tile_store64(acc64, s.F + r0 + k * n, n, rv, kb);
+      tile_store64(acc64, F + r0 + k * n, n, rv, kb);
     }
     __syncthreads();
     // U12 = L11^-1 A12 (64-column tiles), FP64 products
     for (int64_t c0 = k + kb; c0 < n; c0 += BB) {
       const int cv = int(n - c0 < BB ? n - c0 : BB);
       // stage A12 tile: element (kx, nx) at L0[nx * LDS_ + kx]
-      stage64(L0, s.F + k + c0 * n, n, kb, cv);
+      stage64(L0, F + k + c0 * n, n, kb, cv);
       __syncthreads();
       tile_mma64([&](int m, int kx) { return m > kx ? T[kx * LDS_ + m] : (m == kx ? 1.0 : 0.0); },
                  [&](int kx, int nx) { return L0[nx * LDS_ + kx]; }, acc64);
       __syncthreads();
-      tile_store64(acc64, s.F + k + c0 * n, n, kb, cv);
+      tile_store64(acc64, F + k + c0 * n, n, kb, cv);
     }
     __syncthreads();
     // A22 -= L21 U12 (64 x 64 tiles; the L21 row tile stays in LDS)
     for (int64_t r0 = k + kb; r0 < n; r0 += BB) {
       const int rv = int(n - r0 < BB ? n - r0 : BB);
-      if constexpr (BF16U)
-        stage<true, false>(Ah, s.F + r0 + k * n, n, rv, kb);
+      if constexpr (sizeof(TF) == 8)
+        stage64(L0, F + r0 + k * n, n, rv, kb);   // (r, kx) at L0[kx * LDS_ + r]
+      else if constexpr (BF16U)
+        stage<true, false>(Ah, F + r0 + k * n, n, rv, kb);
       else
-        stage<false, false>(As, s.F + r0 + k * n, n, rv, kb);
+        stage<false, false>(As, F + r0 + k * n, n, rv, kb);
       for (int64_t c0 = k + kb; c0 < n; c0 += BB) {
         const int cv = int(n - c0 < BB ? n - c0 : BB);
-        if constexpr (BF16U)
-          stage<true, true>(Bh, s.F + k + c0 * n, n, cv, kb);
+        if constexpr (sizeof(TF) == 8)
+          stage64(L1, F + k + c0 * n, n, kb, cv);  // (kx, nx) at L1[nx * LDS_ + kx]
+        else if constexpr (BF16U)
+          stage<true, true>(Bh, F + k + c0 * n, n, cv, kb);
         else
-          stage<false, true>(Bs, s.F + k + c0 * n, n, cv, kb);
+          stage<false, true>(Bs, F + k + c0 * n, n, cv, kb);
         __syncthreads();
-        if constexpr (BF16U)
+        if constexpr (sizeof(TF) == 8)
+          tile_mma64([&](int m, int kx) { return L0[kx * LDS_ + m]; },
+                     [&](int kx, int nx) { return L1[nx * LDS_ + kx]; }, acc64);
+        else if constexpr (BF16U)
           tile_mma<true>(Ah, Bh, acc);
         else
           tile_mma<false>(As, Bs, acc);
         __syncthreads();
-        tile_store<true>(acc, s.F + r0 + c0 * n, n, rv, cv);
+        if constexpr (sizeof(TF) == 8)
+          tile_store64<true>(acc64, F + r0 + c0 * n, n, rv, cv);
+        else
+          tile_store<true>(acc, F + r0 + c0 * n, n, rv, cv);
       }
     }
     __syncthreads();
@@ -521,8 +565,9 @@ __device__ __noinline__ void transform_vec_sys(const Sys &s, int d, double *Y, i
 // v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; output element (l, v) is row l / 16 + 4 v, column
 // l % 16. NRT: right-hand sides of the inverse product (>= N).
-template <bool LOWER, int NRT>
+template <bool LOWER, int NRT, typename TF>
 __device__ __noinline__ void sweep(const Sys &s, double *Y, int64_t ldy, double *L0) {
+  const TF *F = fmat<TF>(s);
   const int64_t n = s.n;
   const int N = int(s.nrhs);
   const int tid = threadIdx.x, i = tid & 63, sg = tid >> 6;
@@ -577,16 +622,16 @@ __device__ __noinline__ void sweep(const Sys &s, double *Y, int64_t ldy, double 
 #pragma unroll
       for (int kk = 0; kk < 16; ++kk) xb[kk] = xs[lk + 4 * kk][l16];
       const int64_t ntile = (hi - lo + 15) / 16;
-      auto load_tile = [&](int64_t tt, float (&av)[16]) {
+      auto load_tile = [&](int64_t tt, TF (&av)[16]) {
         const int64_t m = lo + 16 * tt + l16;
         const int64_t mc = m < hi ? m : hi - 1;
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
           const int kx = lk + 4 * kk;
-          av[kk] = s.F[mc + (r0 + (kx < kb ? kx : kb - 1)) * n];
+          av[kk] = F[mc + (r0 + (kx < kb ? kx : kb - 1)) * n];
         }
       };
-      float av[16], an[16];
+      TF av[16], an[16];
       int64_t tt = wave;
       if (tt < ntile) load_tile(tt, av);
       for (; tt < ntile; tt += 4) {
@@ -697,15 +742,19 @@ __device__ __noinline__ double residual(const Sys &s, double *L0, bool with_anor
   return be;
 }
 
-// X <- V (LU)^-1 U^T X (X holds B on entry), then classical refinement in
-// FP64 until the Eq. 7 backward error is <= tol or max_iter corrections.
-template <int NRT>
+// X = V (LU)^-1 U^T B with the factors of storage type TF, then classical
+// refinement in FP64 until the Eq. 7 backward error is <= tol, max_iter
+// corrections, stagnation or NaN.
+template <int NRT, typename TF>
 __device__ void refine_system(const Sys &s, int d, double tol, int max_iter, double *L0,
                               double *anorm_sh, int *it_out, double *be_out) {
   const int64_t n = s.n;
+  for (int64_t e = threadIdx.x; e < n * s.nrhs; e += BT)
+    s.Xm[(e % n) + (e / n) * s.ldx] = s.Bm[(e % n) + (e / n) * s.ldb];
+  __syncthreads();
   transform_vec_sys<RBT_OP_T>(s, d, s.Xm, s.ldx, s.U);
-  sweep<true, NRT>(s, s.Xm, s.ldx, L0);
-  sweep<false, NRT>(s, s.Xm, s.ldx, L0);
+  sweep<true, NRT, TF>(s, s.Xm, s.ldx, L0);
+  sweep<false, NRT, TF>(s, s.Xm, s.ldx, L0);
   transform_vec_sys<RBT_OP_N>(s, d, s.Xm, s.ldx, s.V);
   int it = 0, stalled = 0;
   double be = 0.0, best = INFINITY;
@@ -718,8 +767,8 @@ __device__ void refine_system(const Sys &s, int d, double tol, int max_iter, dou
     if (be < best) best = be;
     if (stalled >= 2 || be != be) break;
     transform_vec_sys<RBT_OP_T>(s, d, s.R, n, s.U);
-    sweep<true, NRT>(s, s.R, n, L0);
-    sweep<false, NRT>(s, s.R, n, L0);
+    sweep<true, NRT, TF>(s, s.R, n, L0);
+    sweep<false, NRT, TF>(s, s.R, n, L0);
     transform_vec_sys<RBT_OP_N>(s, d, s.R, n, s.V);
     for (int64_t e = threadIdx.x; e < n * s.nrhs; e += BT)
       s.Xm[(e % n) + (e / n) * s.ldx] += s.R[e];
@@ -730,15 +779,46 @@ __device__ void refine_system(const Sys &s, int d, double tol, int max_iter, dou
   *be_out = be;
 }
 
+// A~ = U^T A V into the FP32 (lowp) or FP64 factor storage.
+__device__ __noinline__ void transform_into(const Sys &s, int d, bool lowp) {
+  const int64_t n = s.n;
+  const int64_t m = d > 0 ? ((((n - 1) >> d) + 1) << d) : n;
+  const int64_t q = m >> d;
+  const dev::Pass ps = d > 0 ? dev::make_pass(n, q, d, 1, d) : dev::identity_pass(n);
+  for (int64_t e = threadIdx.x; e < ps.ngroups * ps.ngroups; e += BT) {
+    const int64_t gr = e % ps.ngroups, gc = e / ps.ngroups;
+    const int64_t rb = dev::group_base(ps, gr), cb = dev::group_base(ps, gc);
+    if (rb >= n || cb >= n) continue;
+    if (lowp) {
+      switch (d) {
+        case 0: dev::transform2_block<0, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
+        case 1: dev::transform2_block<1, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
+        case 2: dev::transform2_block<2, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
+        default: dev::transform2_block<3, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
+      }
+    } else {
+      switch (d) {
+        case 0: dev::transform2_block<0, double>(s.A, s.lda, s.F64, n, s.U, s.V, ps, rb, cb); break;
+        case 1: dev::transform2_block<1, double>(s.A, s.lda, s.F64, n, s.U, s.V, ps, rb, cb); break;
+        case 2: dev::transform2_block<2, double>(s.A, s.lda, s.F64, n, s.U, s.V, ps, rb, cb); break;
+        default: dev::transform2_block<3, double>(s.A, s.lda, s.F64, n, s.U, s.V, ps, rb, cb); break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
 template <bool BF16U>
 __device__ void solve_system(const Args &a, const BatchDesc &D, float *fbase, double *dbase,
-                             double *L0, double *L1, int *info_sh, double *anorm_sh) {
+                             double *f64base, double *L0, double *L1, int *info_sh,
+                             double *anorm_sh) {
   const int tid = threadIdx.x;
   const int d = a.depth;
   Sys s;
   s.n = D.n;
   s.nrhs = D.nrhs;
   s.F = fbase + D.f_off;
+  s.F64 = f64base ? f64base + D.f64_off : nullptr;
   s.U = dbase + D.d_off;
   s.V = s.U + s.n * d;
   s.Inv = s.V + s.n * d;
@@ -759,38 +839,41 @@ __device__ void solve_system(const Args &a, const BatchDesc &D, float *fbase, do
     s.U[e] = dev::coefficient(seed, rem % n, side, int(rem / n) + 1);
   }
   __syncthreads();
-  // A~ = U^T A V into F (FP32)
-  {
-    const int64_t m = d > 0 ? ((((n - 1) >> d) + 1) << d) : n;
-    const int64_t q = m >> d;
-    const dev::Pass ps = d > 0 ? dev::make_pass(n, q, d, 1, d) : dev::identity_pass(n);
-    for (int64_t e = tid; e < ps.ngroups * ps.ngroups; e += BT) {
-      const int64_t gr = e % ps.ngroups, gc = e / ps.ngroups;
-      const int64_t rb = dev::group_base(ps, gr), cb = dev::group_base(ps, gc);
-      if (rb >= n || cb >= n) continue;
-      switch (d) {
-        case 0: dev::transform2_block<0, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
-        case 1: dev::transform2_block<1, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
-        case 2: dev::transform2_block<2, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
-        default: dev::transform2_block<3, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
-      }
-    }
-  }
-  __syncthreads();
-  eliminate<BF16U>(s, L0, L1, info_sh);
-  // X = V (LU)^-1 U^T B, then refinement (tol < 0: |tol| n eps64)
-  for (int64_t e = tid; e < n * s.nrhs; e += BT)
-    s.Xm[(e % n) + (e / n) * s.ldx] = s.Bm[(e % n) + (e / n) * s.ldb];
-  __syncthreads();
   const double tol = a.tol < 0.0 ? -a.tol * double(n) * 0x1.0p-52 : a.tol;
-  int it = 0;
+  int it = 0, path = 0;
   double be = 0.0;
-  if (s.nrhs <= 1)
-    refine_system<1>(s, d, tol, a.max_iter, L0, anorm_sh, &it, &be);
-  else if (s.nrhs <= 4)
-    refine_system<4>(s, d, tol, a.max_iter, L0, anorm_sh, &it, &be);
-  else
-    refine_system<NR>(s, d, tol, a.max_iter, L0, anorm_sh, &it, &be);
+  // low precision first; if its refinement fails, FP64 factors (fallback)
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      if (be <= tol || s.F64 == nullptr) break;
+      path = 1;
+      if (tid == 0) *info_sh = 0;
+      __syncthreads();
+    }
+    transform_into(s, d, pass == 0);
+    if (pass == 0)
+      eliminate<float, BF16U>(s, L0, L1, info_sh);
+    else
+      eliminate<double, false>(s, L0, L1, info_sh);
+    int it_p = 0;
+    if (pass == 0) {
+      if (s.nrhs <= 1)
+        refine_system<1, float>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be);
+      else if (s.nrhs <= 4)
+        refine_system<4, float>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be);
+      else
+        refine_system<NR, float>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be);
+    } else {
+      if (s.nrhs <= 1)
+        refine_system<1, double>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be);
+      else if (s.nrhs <= 4)
+        refine_system<4, double>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be);
+      else
+        refine_system<NR, double>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be);
+    }
+    it += it_p;
+  }
+  if (tid == 0 && a.path) a.path[D.sys] = path;
   if (tid == 0) {
     if (a.iters) a.iters[D.sys] = it;
     if (a.berr) a.berr[D.sys] = be;
@@ -815,6 +898,8 @@ __global__ void __launch_bounds__(BT, 2) k_batched(Args a) {
   const BatchDesc *desc = reinterpret_cast<const BatchDesc *>(a.work + kBatchTableOffset);
   float *fbase = reinterpret_cast<float *>(a.work + hdr->f_off_bytes);
   double *dbase = reinterpret_cast<double *>(a.work + hdr->d_off_bytes);
+  double *f64base =
+      hdr->f64_off_bytes > 0 ? reinterpret_cast<double *>(a.work + hdr->f64_off_bytes) : nullptr;
   for (;;) {
     if (threadIdx.x == 0) tk_sh = atomicAdd(&hdr->ticket, 1);
     __syncthreads();
@@ -823,8 +908,9 @@ __global__ void __launch_bounds__(BT, 2) k_batched(Args a) {
     if (t >= a.batch) break;
     const BatchDesc D = desc[t];
     if (D.n > 0) {
-      solve_system<BF16U>(a, D, fbase, dbase, L0, L1, &info_sh, &anorm_sh);
+      solve_system<BF16U>(a, D, fbase, dbase, f64base, L0, L1, &info_sh, &anorm_sh);
     } else if (threadIdx.x == 0) {
+      if (a.path) a.path[D.sys] = 0;
       if (a.iters) a.iters[D.sys] = 0;
       if (a.berr) a.berr[D.sys] = 0.0;
       if (a.info) a.info[D.sys] = 0;
@@ -842,7 +928,7 @@ hipError_t launch_batched(int64_t batch, void *work, size_t work_bytes, const do
                           const int64_t *lda, const double *const *B, const int64_t *ldb,
                           double *const *X, const int64_t *ldx, int depth, uint64_t seed,
                           int prec, double tol, int max_iter, int32_t *iters, double *berr,
-                          int32_t *info, int grid, hipStream_t s) {
+                          int32_t *info, int32_t *path, int grid, hipStream_t s) {
   Args a;
   a.batch = batch;
   a.work = static_cast<char *>(work);
@@ -856,6 +942,7 @@ hipError_t launch_batched(int64_t batch, void *work, size_t work_bytes, const do
   a.iters = iters;
   a.berr = berr;
   a.info = info;
+  a.path = path;
   a.seed = seed;
   a.tol = tol;
   a.depth = depth;

@@ -271,6 +271,7 @@ class BatchArgs:
         self.iters = torch.zeros(nb, dtype=torch.int32, device=dev)
         self.berr = torch.zeros(nb, dtype=torch.float64, device=dev)
         self.info = torch.zeros(nb, dtype=torch.int32, device=dev)
+        self.path = torch.zeros(nb, dtype=torch.int32, device=dev)
 
 
 def solve_batched_launch(plan, args, seed=2023, tol=-10.0, max_iter=30):
@@ -280,7 +281,7 @@ def solve_batched_launch(plan, args, seed=2023, tol=-10.0, max_iter=30):
     check(lib().rbt_solve_batched(plan.batch, _p(args.pA), _p(args.lA), _p(args.pB), _p(args.lB),
                                   _p(args.pX), _p(args.lX), plan.depth, seed, plan.prec,
                                   float(tol), int(max_iter), _p(args.iters), _p(args.berr),
-                                  _p(args.info), _p(plan.work), plan.work.numel(),
+                                  _p(args.info), _p(args.path), _p(plan.work), plan.work.numel(),
                                   _stream(plan.work.device)), "rbt_solve_batched")
 
 

@@ -92,6 +92,29 @@ def test_batched_randn_refines(rbt):
         assert relfro(host(X), Xe) <= 20 * np.linalg.cond(A, np.inf) * tol
 
 
+def test_batched_fp64_fallback(rbt):
+    """BF16-update factors of N(0,1) systems are too inaccurate for classical
+    refinement; those systems are factored again in FP64 and still reach
+    10 n eps, matching the FP64 oracle solution."""
+    ns = np.array([300, 600, 900, 45])
+    ks = np.array([1, 4, 2, 3])
+    As = [workloads.randn_matrix(int(n), seed=s + 300) for s, n in enumerate(ns)]
+    Bs = [workloads.randn(int(n), int(k), seed=2000 + s) for s, (n, k) in enumerate(zip(ns, ks))]
+    plan = rbt.batched_plan(ns, ks, 2, rbt.RBT_BF16)
+    args = rbt.BatchArgs(plan, [dev(a) for a in As], [dev(b) for b in Bs])
+    rbt.solve_batched_launch(plan, args, seed=77, max_iter=30)
+    torch.cuda.synchronize()
+    berr, path, info = host(args.berr), host(args.path), host(args.info)
+    assert path[:3].sum() >= 1  # at least one system needed the fallback
+    for s, (A, B, X) in enumerate(zip(As, Bs, args.Xs)):
+        n = A.shape[0]
+        tol = 10 * n * EPS
+        assert info[s] == 0 and berr[s] <= tol, (s, berr[s], path[s])
+        U, V = coeffs.generate(n, 2, system_seed(77, s))
+        Xo, _, _ = osolve.rbt_solve(A, B, U, V, 2)
+        assert relfro(host(X), Xo) <= 20 * np.linalg.cond(A, np.inf) * tol
+
+
 @pytest.mark.parametrize("depth", [0, 1, 3])
 def test_batched_depths(rbt, depth):
     ns = np.array([5, 64, 200, 131])
