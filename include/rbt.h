@@ -252,6 +252,23 @@ int rbt_solve_backward(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu, 
                        double *dB, int64_t lddb, int depth, uint64_t seed, void *work,
                        size_t work_bytes, void *stream);
 
+/* Device. Adjoint of the mixed-precision solve (rbt_solve_mixed): LU = the
+ * FP32 L\U factors of A~ left by rbt_solve_mixed for the same (depth,
+ * seed); A = the original FP64 matrix (n x n, lda), used to refine
+ * Lambda = A^-T G in FP64: Lambda_0 = U (LU)^-T V^T G with the FP32 factors
+ * (widened to FP64 in the solves), then Lambda += U (LU)^-T V^T (G - A^T
+ * Lambda) until the Eq. 7 backward error of A^T Lambda = G (with
+ * ||A^T||_inf = ||A||_1) is <= tol or max_iter corrections are done.
+ * dB = Lambda, dA = -Lambda X^T (nullable: skipped). iters_dev, berr_dev:
+ * as rbt_solve_refine. work: >= rbt_workspace_size(n, nrhs, depth,
+ * RBT_FP32) bytes. Synchronizes `stream` once per correction. */
+int rbt_solve_backward_mixed(int64_t n, int64_t nrhs, const float *LU, int64_t ldlu,
+                             const double *A, int64_t lda, const double *X, int64_t ldx,
+                             const double *G, int64_t ldg, double *dA, int64_t ldda, double *dB,
+                             int64_t lddb, int depth, uint64_t seed, double tol, int max_iter,
+                             int32_t *iters_dev, double *berr_dev, void *work, size_t work_bytes,
+                             void *stream);
+
 /* Tuning options (process-wide; not thread safe).
  * RBT_OPT_OUTER_NB: width of the panels of the elimination whose trailing
  *   update is a single GEMM (multiple of 128, 128..2048; default 1024). The

@@ -44,6 +44,8 @@ SIGNATURES = {
     "rbt_backward_error": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, vp, sz, vp]),
     "rbt_solve_backward": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, u64,
                                  vp, sz, vp]),
+    "rbt_solve_backward_mixed": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp,
+                                       i64, i32, u64, dbl, i32, vp, vp, vp, sz, vp]),
     "rbt_set_option": (i32, [i32, i64]),
     "rbt_get_option": (i64, [i32]),
     "rbt_timing_enable": (i32, [i32]),

@@ -962,6 +962,88 @@ extern "C" int rbt_timing_read(int nstages, double *ms, int64_t *launches, doubl
   return rc;
 }
 
+extern "C" int rbt_solve_backward_mixed(int64_t n, int64_t nrhs, const float *LU, int64_t ldlu,
+                                        const double *A, int64_t lda, const double *X,
+                                        int64_t ldx, const double *G, int64_t ldg, double *dA,
+                                        int64_t ldda, double *dB, int64_t lddb, int depth,
+                                        uint64_t seed, double tol, int max_iter,
+                                        int32_t *iters_dev, double *berr_dev, void *work,
+                                        size_t work_bytes, void *stream) {
+  if (n < 0) return -1;
+  if (nrhs < 0) return -2;
+  if (n > 0 && LU == nullptr) return -3;
+  if (ldlu < (n > 1 ? n : 1)) return -4;
+  if (n > 0 && nrhs > 0 && A == nullptr) return -5;
+  if (lda < (n > 1 ? n : 1)) return -6;
+  if (n > 0 && nrhs > 0 && dA != nullptr && X == nullptr) return -7;
+  if (ldx < (n > 1 ? n : 1)) return -8;
+  if (n > 0 && nrhs > 0 && G == nullptr) return -9;
+  if (ldg < (n > 1 ? n : 1)) return -10;
+  if (dA != nullptr && ldda < (n > 1 ? n : 1)) return -12;
+  if (n > 0 && nrhs > 0 && dB == nullptr) return -13;
+  if (lddb < (n > 1 ? n : 1)) return -14;
+  if (bad_depth(depth)) return -15;
+  if (!(tol >= 0.0)) return -17;
+  if (max_iter < 0) return -18;
+  const Layout L = layout(n, nrhs, depth, true);
+  if (n > 0 && work == nullptr) return -21;
+  if (work_bytes < L.total) return RBT_ERR_WORKSPACE;
+  hipStream_t s = S(stream);
+  double *small = at<double>(work, L.o_small);
+  double *berr = berr_dev ? berr_dev : small + 1;
+  if (n == 0 || nrhs == 0) {
+    RBT_HIP_CHECK(launch_fill_f64(berr, 0.0, s));
+    if (iters_dev) RBT_HIP_CHECK(launch_fill_i32(iters_dev, 0, s));
+    return 0;
+  }
+  const Geometry g = geometry(n, depth);
+  double *U = at<double>(work, L.o_coef);
+  double *V = U + n * depth;
+  double *winv = at<double>(work, L.o_winv);
+  int32_t *sync = at<int32_t>(work, L.o_sync);
+  double *R = at<double>(work, L.o_resid);
+  double *scratch = at<double>(work, L.o_partial);
+  double *anorm = small;
+  // Lambda = A^-T G = U (A~^-T (V^T G)) with the FP32 factors of A~, then
+  // refinement on A^T Lambda = G in FP64
+  RBT_HIP_CHECK(generate_t(n, depth, seed, U, V, s));
+  int rc = diag_inverses_t(n, LU, ldlu, winv, s);
+  if (rc) return rc;
+  auto adjoint_solve = [&](double *Y, int64_t ldy) -> int {
+    RBT_HIP_CHECK(transform_vec_t(g, nrhs, Y, ldy, V, RBT_OP_T, s));
+    const int r = getrs_t(n, nrhs, LU, ldlu, Y, ldy, 1, winv, sync, s);
+    if (r) return r;
+    RBT_HIP_CHECK(transform_vec_t(g, nrhs, Y, ldy, U, RBT_OP_N, s));
+    return 0;
+  };
+  RBT_HIP_CHECK(launch_copy_cols(n, nrhs, G, ldg, dB, lddb, s));
+  rc = adjoint_solve(dB, lddb);
+  if (rc) return rc;
+  int it = 0;
+  for (;;) {
+    {
+      StageScope t(kStageResidual, s, 8.0 * double(n) * n);
+      RBT_HIP_CHECK(launch_residual_berr_T(n, nrhs, A, lda, dB, lddb, G, ldg, R, n, it == 0,
+                                           scratch, anorm, berr, s));
+    }
+    if (it >= max_iter) break;
+    double be_host = 0.0;
+    RBT_HIP_CHECK(hipMemcpyAsync(&be_host, berr, sizeof(double), hipMemcpyDeviceToHost, s));
+    RBT_HIP_CHECK(hipStreamSynchronize(s));
+    if (be_host <= tol) break;
+    rc = adjoint_solve(R, n);
+    if (rc) return rc;
+    RBT_HIP_CHECK(launch_axpy_cols(n, nrhs, R, n, dB, lddb, s));
+    ++it;
+  }
+  if (dA != nullptr) RBT_HIP_CHECK(launch_neg_outer(n, nrhs, dB, lddb, X, ldx, dA, ldda, s));
+  if (iters_dev) {
+    RBT_HIP_CHECK(hipMemcpyAsync(iters_dev, &it, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    RBT_HIP_CHECK(hipStreamSynchronize(s));
+  }
+  return 0;
+}
+
 extern "C" int rbt_set_option(int option, int64_t value) {
   switch (option) {
     case RBT_OPT_OUTER_NB:

@@ -164,6 +164,12 @@ hipError_t launch_colcombo(int64_t n, int N, int J, const double *V, int64_t vs,
 // O[:, c] (ld n) = W[:, c] / sqrt(nrm2[c]), or 0 when nrm2[c] <= 0
 hipError_t launch_colscale(int64_t n, int N, const double *W, int64_t ldw, const double *nrm2,
                            double *O, hipStream_t s);
+// R = G - A^T L and the Eq. 7 backward error of the adjoint system
+// (||A^T||_inf = ||A||_1); scratch: n + 3 nrhs doubles.
+hipError_t launch_residual_berr_T(int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                                  const double *L, int64_t ldl, const double *G, int64_t ldg,
+                                  double *R, int64_t ldr, bool with_anorm, double *scratch,
+                                  double *anorm, double *berr, hipStream_t s);
 hipError_t launch_axpy_cols(int64_t n, int64_t nrhs, const double *D, int64_t ldd, double *X,
                             int64_t ldx, hipStream_t s);
 hipError_t launch_copy_cols(int64_t n, int64_t nrhs, const double *S, int64_t lds, double *D,

@@ -285,6 +285,23 @@ __global__ void __launch_bounds__(kRows) k_neg_outer(int64_t n, int64_t nrhs,
   }
 }
 
+// out[i] = sum_k |A[k, i]| (column sums: ||A||_1 = ||A^T||_inf), one
+// workgroup per column.
+__global__ void __launch_bounds__(kRows) k_colabs(int64_t n, const double *__restrict__ A,
+                                                 int64_t lda, double *__restrict__ out) {
+  __shared__ double sh[kRows];
+  const int64_t i = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += kRows) acc += fabs(A[k + i * lda]);
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = kRows / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = sh[0];
+}
+
 __global__ void k_fill_i32(int32_t *p, int32_t v) {
   if (threadIdx.x == 0) p[0] = v;
 }
@@ -510,6 +527,33 @@ hipError_t launch_colscale(int64_t n, int N, const double *W, int64_t ldw, const
   if (N <= 0 || n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_colscale, dim3(unsigned((n + kRows - 1) / kRows), unsigned(N)), dim3(kRows),
                      0, s, n, W, ldw, nrm2, O);
+  return hipGetLastError();
+}
+
+// R = G - A^T L (the residual of the adjoint system A^T L = G) and its Eq. 7
+// backward error with ||A^T||_inf = ||A||_1 (with_anorm: computed here into
+// *anorm, else read). scratch: n + 3 nrhs doubles.
+hipError_t launch_residual_berr_T(int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                                  const double *L, int64_t ldl, const double *G, int64_t ldg,
+                                  double *R, int64_t ldr, bool with_anorm, double *scratch,
+                                  double *anorm, double *berr, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) {
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, berr, 0.0);
+    return hipGetLastError();
+  }
+  double *colabs = scratch;
+  double *colstat = scratch + n;
+  if (with_anorm) {
+    hipLaunchKernelGGL(k_colabs, dim3(unsigned(n)), dim3(kRows), 0, s, n, A, lda, colabs);
+    hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(kRows), 0, s, n, colabs, anorm);
+  }
+  hipLaunchKernelGGL(k_copy_cols, col_grid(n, nrhs), dim3(kRows), 0, s, n, nrhs, G, ldg, R, ldr);
+  hipError_t e = launch_dgemm(n, nrhs, n, A, lda, OpA::GeneralT, L, ldl, OpB::General, R, ldr,
+                              Acc::Subtract, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colmax, dim3(unsigned(nrhs)), dim3(kRows), 0, s, n, R, ldr, L, ldl, G, ldg,
+                     colstat);
+  hipLaunchKernelGGL(k_berr_final, dim3(1), dim3(64), 0, s, nrhs, colstat, anorm, berr);
   return hipGetLastError();
 }
 

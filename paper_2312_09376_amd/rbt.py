@@ -352,6 +352,34 @@ def solve_backward(LU, X, G, depth=2, seed=2023, need_dA=True, work=None):
     return dA, dB
 
 
+def solve_backward_mixed(LU, A, X, G, depth=2, seed=2023, tol=None, max_iter=30, need_dA=True,
+                         work=None):
+    """Adjoint of the mixed-precision solve: LU (FP32 factors of U^T A V from
+    solve_mixed), A the original FP64 matrix (for the FP64 refinement of
+    A^-T G). Returns (dA, dB, iters, berr)."""
+    LU, A, X, G = colmajor(LU), colmajor(A), colmajor(X), colmajor(G)
+    if not (LU.is_cuda and LU.dtype == torch.float32):
+        raise TypeError("LU must be a float32 tensor on a HIP device")
+    _dev_f64(A, "A")
+    _dev_f64(G, "G")
+    n, k = LU.shape[0], G.shape[1]
+    if tol is None:
+        tol = 10.0 * n * 2.0 ** -52
+    dev = LU.device
+    dB = torch.empty_strided((n, k), (1, max(1, n)), dtype=torch.float64, device=dev)
+    dA = torch.empty_strided((n, n), (1, max(1, n)), dtype=torch.float64, device=dev) if need_dA else None
+    work = work if work is not None else _workspace(n, k, depth, dev, RBT_FP32)
+    iters = torch.zeros(1, dtype=torch.int32, device=dev)
+    berr = torch.zeros(1, dtype=torch.float64, device=dev)
+    check(lib().rbt_solve_backward_mixed(n, k, _p(LU), _ld(LU), _p(A), _ld(A), _p(X), _ld(X),
+                                         _p(G), _ld(G), _p(dA),
+                                         _ld(dA) if dA is not None else max(1, n), _p(dB),
+                                         _ld(dB), depth, seed, float(tol), int(max_iter),
+                                         _p(iters), _p(berr), _p(work), work.numel(),
+                                         _stream(dev)), "rbt_solve_backward_mixed")
+    return dA, dB, iters, berr
+
+
 class RBTSolve(torch.autograd.Function):
     """X = A^-1 B by the RBT method, differentiable in A and B.
 
@@ -380,6 +408,39 @@ class RBTSolve(torch.autograd.Function):
         return dA, dB, None, None, None
 
 
-def rbt_solve(A, B, depth=2, seed=2023, max_iter=10):
-    """Differentiable X = A^-1 B (FP64 tensors on the device)."""
+class RBTSolveMixed(torch.autograd.Function):
+    """X = A^-1 B with the FP32 (or BF16-update) factors and FP64 GMRES or
+    classical refinement, differentiable in A and B; the backward solve
+    reuses the FP32 factors and refines A^-T G in FP64 against A."""
+
+    @staticmethod
+    def forward(ctx, A, B, depth=2, seed=2023, max_iter=30, prec=RBT_FP32, solver=RBT_IR_GMRES):
+        vec = B.dim() == 1
+        B2 = B.reshape(-1, 1) if vec else B
+        Ad = colmajor(A.detach())
+        X, LU, _, _, _, _ = solve_mixed(Ad, B2.detach(), depth, seed, prec=prec, solver=solver,
+                                        max_iter=max_iter)
+        ctx.save_for_backward(LU, Ad, X)
+        ctx.depth, ctx.seed, ctx.vec, ctx.max_iter = depth, seed, vec, max_iter
+        out = X.reshape(-1) if vec else X
+        return out.clone(memory_format=torch.contiguous_format)
+
+    @staticmethod
+    def backward(ctx, G):
+        LU, Ad, X = ctx.saved_tensors
+        G2 = G.reshape(-1, 1) if ctx.vec else G
+        dA, dB, _, _ = solve_backward_mixed(LU, Ad, X, G2.contiguous(), ctx.depth, ctx.seed,
+                                            max_iter=ctx.max_iter,
+                                            need_dA=ctx.needs_input_grad[0])
+        if ctx.vec:
+            dB = dB.reshape(-1)
+        return dA, dB, None, None, None, None, None
+
+
+def rbt_solve(A, B, depth=2, seed=2023, max_iter=10, prec=RBT_FP64):
+    """Differentiable X = A^-1 B (FP64 tensors on the device). prec RBT_FP32
+    or RBT_BF16: low-precision factors with FP64 GMRES refinement (forward)
+    and FP64 refinement of the adjoint solve (backward)."""
+    if prec != RBT_FP64:
+        return RBTSolveMixed.apply(A, B, depth, seed, max(max_iter, 30), prec, RBT_IR_GMRES)
     return RBTSolve.apply(A, B, depth, seed, max_iter)

@@ -88,6 +88,48 @@ def test_argument_errors(lib):
     assert mixed(depth=4) == _lib.RBT_ERR_UNSUPPORTED
     assert lib.rbt_workspace_size(1000, 1, 2, _lib.RBT_BF16) > 0
     assert lib.rbt_workspace_size(1000, 1, 2, 9) == 0
+    # adjoint of the mixed solve
+    assert lib.rbt_solve_backward_mixed(5, 1, dummy, 5, dummy, 4, dummy, 5, dummy, 5, None, 5,
+                                        dummy, 5, 2, 0, 1e-10, 3, None, None, dummy, 1 << 30,
+                                        None) == -6
+    assert lib.rbt_solve_backward_mixed(5, 1, dummy, 5, dummy, 5, dummy, 5, dummy, 5, None, 5,
+                                        dummy, 5, 2, 0, -1.0, 3, None, None, dummy, 1 << 30,
+                                        None) == -17
+
+
+def test_batched_argument_errors(lib):
+    vp = ctypes.c_void_p
+    ns = np.array([10, 20], dtype=np.int64)
+    ks = np.array([1, 17], dtype=np.int64)
+    assert lib.rbt_batched_workspace_size(2, ns.ctypes.data_as(vp), ks.ctypes.data_as(vp), 2,
+                                          _lib.RBT_FP32) == 0  # nrhs > 16
+    ks[1] = 16
+    a = lib.rbt_batched_workspace_size(2, ns.ctypes.data_as(vp), ks.ctypes.data_as(vp), 2,
+                                       _lib.RBT_FP32)
+    b = lib.rbt_batched_workspace_size(2, ns.ctypes.data_as(vp), ks.ctypes.data_as(vp), 3,
+                                       _lib.RBT_FP32)
+    assert 0 < a <= b
+    assert lib.rbt_batched_workspace_size(2, ns.ctypes.data_as(vp), ks.ctypes.data_as(vp), 4,
+                                          _lib.RBT_FP32) == 0
+    ks[1] = 17
+    assert lib.rbt_batched_plan(2, ns.ctypes.data_as(vp), ks.ctypes.data_as(vp), 2, _lib.RBT_FP32,
+                                vp(0x1000), 1 << 20, None) == _lib.RBT_ERR_UNSUPPORTED
+    ks[1] = 2
+    assert lib.rbt_batched_plan(2, ns.ctypes.data_as(vp), ks.ctypes.data_as(vp), 2, 7,
+                                vp(0x1000), 1 << 20, None) == -5
+    assert lib.rbt_batched_plan(2, ns.ctypes.data_as(vp), ks.ctypes.data_as(vp), 2, _lib.RBT_FP32,
+                                vp(0x1000), 16, None) == _lib.RBT_ERR_WORKSPACE
+    d = vp(0x1000)
+    assert lib.rbt_solve_batched(-1, d, d, d, d, d, d, 2, 0, _lib.RBT_FP32, 1e-10, 3, None,
+                                 None, None, None, d, 1 << 20, None) == -1
+    assert lib.rbt_solve_batched(2, d, d, d, d, d, d, 2, 0, 5, 1e-10, 3, None, None, None, None,
+                                 d, 1 << 20, None) == -10
+    assert lib.rbt_solve_batched(2, d, d, d, d, d, d, 2, 0, _lib.RBT_FP32, float("nan"), 3, None,
+                                 None, None, None, d, 1 << 20, None) == -11
+    assert lib.rbt_solve_batched(2, d, d, d, d, d, d, 2, 0, _lib.RBT_FP32, 1e-10, 3, None,
+                                 None, None, None, d, 100, None) == _lib.RBT_ERR_WORKSPACE
+    assert lib.rbt_solve_batched(0, None, None, None, None, None, None, 2, 0, _lib.RBT_FP32,
+                                 1e-10, 3, None, None, None, None, None, 0, None) == 0
 
 
 def test_workspace_size_monotone(lib):

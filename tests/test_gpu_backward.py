@@ -111,3 +111,42 @@ def test_autograd_finite_differences(rbt):
         Bm[i, c] -= h
         fd = (loss(A, Bp) - loss(A, Bm)) / (2 * h)
         assert abs(gB[i, c] - fd) <= 1e-6 * max(1.0, abs(fd))
+
+
+@pytest.mark.parametrize("n,k,d", [(1, 1, 2), (300, 3, 2), (1003, 8, 2), (513, 20, 1)])
+def test_backward_mixed_matches_oracle(rbt, n, k, d):
+    """FP32 factors + FP64 refinement of the adjoint solve reach the FP64
+    oracle's adjoint to within kappa * 10 n eps."""
+    A = workloads.dominant(n, seed=n + 3)
+    B = workloads.randn(n, k, seed=1)
+    G = workloads.randn(n, k, seed=2)
+    X, LU32, _, _, info, _ = rbt.solve_mixed(dev(A), dev(B), d, 2023, prec=rbt.RBT_FP32,
+                                             solver=rbt.RBT_IR_GMRES)
+    assert int(info.item()) == 0
+    dA, dB, iters, berr = rbt.solve_backward_mixed(LU32, dev(A), X, dev(G), d, 2023)
+    tol = 10 * n * 2.0 ** -52
+    assert float(berr.item()) <= tol
+    Uo, Vo = coeffs.generate(n, d, 2023)
+    Xo, LUo, _ = osolve.rbt_solve(A, B, Uo, Vo, d)
+    dAo, dBo = osolve.adjoint(LUo, Xo, G, Uo, Vo, d)
+    kappa = np.linalg.cond(A, np.inf)
+    assert relmax(host(dB), dBo.reshape(n, k)) <= 10 * kappa * tol
+    assert relmax(host(dA), dAo) <= 10 * kappa * tol
+    assert int(iters.item()) <= 6
+
+
+def test_autograd_mixed_finite_differences(rbt):
+    n, k = 512, 4
+    A = workloads.shifted(n, seed=31)
+    B = workloads.randn(n, k, seed=32)
+    C = workloads.randn(n, k, seed=33)
+    At = torch.from_numpy(A).cuda().requires_grad_(True)
+    Bt = torch.from_numpy(B).cuda().requires_grad_(True)
+    X = rbt.rbt_solve(At, Bt, 2, 2023, prec=rbt.RBT_FP32)
+    (X * torch.from_numpy(C).cuda()).sum().backward()
+    gA, gB = host(At.grad), host(Bt.grad)
+    # dense FP64 reference of the same gradient
+    lam = np.linalg.solve(A.T, C)
+    Xe = np.linalg.solve(A, B)
+    assert relmax(gB, lam) <= 1e-9
+    assert relmax(gA, -lam @ Xe.T) <= 1e-9
