@@ -52,11 +52,13 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=4096, help="oracle sample size")
     ap.add_argument("--outer-nb", type=int, default=0,
                     help="panel width of the elimination (multiple of 128; 0 = library default)")
-    ap.add_argument("--mode", choices=["solve", "mixed", "batched", "copy"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "mixed", "batched", "backward", "copy"],
+                    default="solve",
                     help="solve: the FP64 step (default); mixed: FP32/BF16 elimination with FP64 "
                          "refinement; copy: a plain FP64 matrix copy through the transform kernel "
                          "at depth 0 (reference point for HBM byte counters)")
-    ap.add_argument("--prec", choices=["fp32", "bf16"], default="fp32", help="mixed mode")
+    ap.add_argument("--prec", choices=["fp32", "bf16", "fp64"], default="fp32",
+                    help="mixed / batched / backward modes (fp64: backward mode only)")
     ap.add_argument("--solver", choices=["classic", "gmres"], default="classic", help="mixed mode")
     ap.add_argument("--batch", type=int, default=2048, help="batched mode: number of systems")
     ap.add_argument("--batch-n", type=int, default=0,
@@ -281,6 +283,75 @@ def batched_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def backward_mode(args):
+    """One step = forward solve + adjoint (dA and dB for dL/dX = G) of each of
+    `batch` systems: A_s = N(0,1)/sqrt(n) + I (seed 42 + s), B_s, G_s ~ N(0,1)
+    (n x nrhs). fp64: FP64 solve with refinement and the FP64 adjoint;
+    fp32/bf16: low-precision factors with FP64 GMRES refinement forward and
+    FP64 refinement of the adjoint solve."""
+    import torch
+    from paper_2312_09376_amd import rbt, workloads
+    n, k, d = args.n, args.nrhs, args.depth
+    nb = args.batch
+    tol = 10.0 * n * 2.0 ** -52
+    As = []
+    for s_ in range(nb):
+        A = workloads.device_randn(n, n, workloads.MATRIX_SEED + s_) / math.sqrt(n)
+        A.diagonal().add_(1.0)
+        As.append(A)
+    Bs = [workloads.device_randn(n, k, workloads.RHS_SEED + s_) for s_ in range(nb)]
+    Gs = [workloads.device_randn(n, k, 1000 + s_) for s_ in range(nb)]
+    fp64 = args.prec == "fp64"
+    prec = {"fp32": rbt.RBT_FP32, "bf16": rbt.RBT_BF16, "fp64": rbt.RBT_FP64}[args.prec]
+    LU = torch.empty_strided((n, n), (1, n), dtype=torch.float64 if fp64 else torch.float32,
+                             device="cuda")
+    X = torch.empty_strided((n, k), (1, n), dtype=torch.float64, device="cuda")
+    work = rbt._workspace(n, k, d, As[0].device, prec)
+    torch.cuda.synchronize()
+    worst = {"fwd": 0.0, "bwd": 0.0}
+
+    def step():
+        for A, B, G in zip(As, Bs, Gs):
+            if fp64:
+                _, _, _, be, _, _ = rbt.solve_refine(A, B, d, args.seed, tol=tol,
+                                                     max_iter=args.max_iter, LU=LU, X=X, work=work)
+                dA, dB = rbt.solve_backward(LU, X, G, d, args.seed, work=work)
+                bb = None
+            else:
+                _, _, _, be, _, _ = rbt.solve_mixed(A, B, d, args.seed, prec=prec,
+                                                    solver=rbt.RBT_IR_GMRES, tol=tol,
+                                                    max_iter=args.max_iter, LU=LU, X=X, work=work)
+                dA, dB, _, bb = rbt.solve_backward_mixed(LU, A, X, G, d, args.seed, tol=tol,
+                                                         max_iter=args.max_iter, work=work)
+            worst["fwd"] = max(worst["fwd"], float(be.item()))
+            if bb is not None:
+                worst["bwd"] = max(worst["bwd"], float(bb.item()))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    flops = nb * (2.0 / 3.0) * n ** 3
+    out = {
+        "metric": "solve + adjoint (dA, dB) throughput, TFLOP/s of the forward eliminations",
+        "value": round(flops / (ms_step * 1e-3) / 1e12, 4), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": f"{nb} systems, n={n}, nrhs={k}, depth {d}, A=N(0,1)/sqrt(n)+I "
+                               f"(seed 42+s), forward {args.prec.upper()} solve to 10 n eps + "
+                               f"adjoint with dA", "batch": nb, "n": n, "nrhs": k, "depth": d},
+        "systems_per_s": round(nb / (ms_step * 1e-3), 2),
+        "max_forward_berr": worst["fwd"], "max_adjoint_berr": worst["bwd"] if not fp64 else None,
+        "berr_tol": tol, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(n, nrhs, depth, seed):
     """The oracle, as it stands, on the host cores: one full solve (coefficients,
     transform, elimination, solves, refinement to the same tolerance)."""
@@ -330,6 +401,9 @@ def main():
         return
     if args.mode == "batched":
         batched_mode(args)
+        return
+    if args.mode == "backward":
+        backward_mode(args)
         return
     if args.outer_nb:
         rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, args.outer_nb)
