@@ -60,6 +60,10 @@ def parse():
     ap.add_argument("--prec", choices=["fp32", "bf16", "fp64"], default="fp32",
                     help="mixed / batched / backward modes (fp64: backward mode only)")
     ap.add_argument("--solver", choices=["classic", "gmres"], default="classic", help="mixed mode")
+    ap.add_argument("--guarded", action="store_true",
+                    help="mixed mode: fall back to FP64 factors when the low-precision "
+                         "refinement cannot reach tol (max-iter is then its budget)")
+    ap.add_argument("--max-iter64", type=int, default=10, help="guarded mixed mode: FP64 budget")
     ap.add_argument("--batch", type=int, default=2048, help="batched mode: number of systems")
     ap.add_argument("--batch-n", type=int, default=0,
                     help="batched mode: all systems of this order (0: n ~ U{37..1500})")
@@ -140,11 +144,18 @@ def mixed_mode(args):
         A.diagonal().add_(1.0)
     B = workloads.device_randn(n, k, workloads.RHS_SEED)
     LU = torch.empty_strided((n, n), (1, n), dtype=torch.float32, device="cuda")
+    LU64 = (torch.empty_strided((n, n), (1, n), dtype=torch.float64, device="cuda")
+            if args.guarded else None)
     X = torch.empty_strided((n, k), (1, n), dtype=torch.float64, device="cuda")
     work = rbt._workspace(n, k, d, A.device, prec)
     torch.cuda.synchronize()
 
     def step():
+        if args.guarded:
+            X_, _, _, it_, be_, info_, path_, _ = rbt.solve_mixed_guarded(
+                A, B, d, args.seed, prec=prec, solver=solver, tol=tol, max_iter=args.max_iter,
+                max_iter64=args.max_iter64, LU=LU, LU64=LU64, X=X, work=work)
+            return X_, None, (it_, path_), be_, info_, None
         return rbt.solve_mixed(A, B, d, args.seed, prec=prec, solver=solver, tol=tol,
                                max_iter=args.max_iter, LU=LU, X=X, work=work)
 
@@ -190,10 +201,17 @@ def mixed_mode(args):
                      "launches": tr_cnt, "avg_launch_ms": round(tr_ms / max(tr_cnt, 1), 4),
                      "flops_per_launch": tr_work / max(tr_cnt, 1)},
         "berr": berr, "berr_tol": tol, "converged": berr <= tol,
-        "ir_steps": [int(i.item()) for i in iters], "info": int(info.item()),
         "stages_ms_per_step": {s_: round(v[0] / args.steps, 3) for s_, v in stages.items()},
         "cpu_baseline": None,
     }
+    if args.guarded:
+        out["config"]["guarded"] = True
+        out["ir_steps"] = [[int(v) for v in i[0].cpu()] for i in iters]  # [low prec, FP64]
+        out["fp64_fallback"] = [int(i[1].item()) for i in iters]
+        out["info"] = [int(v) for v in info.cpu()]
+    else:
+        out["ir_steps"] = [int(i.item()) for i in iters]
+        out["info"] = int(info.item())
     print(json.dumps(out), flush=True)
 
 

@@ -178,6 +178,42 @@ int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, float
                     int32_t *iters_dev, double *berr_dev, int32_t *info_dev, void *work,
                     size_t work_bytes, void *stream);
 
+/* Device. rbt_solve_mixed with a fallback to FP64 factors: try the
+ * low-precision factors first and, only if their refinement cannot reach
+ * tol, factor A~ again in FP64 and refine with those. Sec. 5 pairs the
+ * fast unpivoted solve with a check of its result and re-solves with a more
+ * robust solver only when refinement fails; here the more robust solve is
+ * the same method in FP64 (same butterflies, FP64 GENP, classical FP64
+ * refinement): this library has no pivoted factorization.
+ *
+ * The low-precision phase is rbt_solve_mixed with max_iter as its budget,
+ * except that it also stops early when tol is out of reach: a non-finite
+ * backward error; classical: a correction that does not halve the backward
+ * error; GMRES: from the 8th iteration of a cycle on, when the residual
+ * estimate, extrapolated at the geometric rate of its last 4 iterations
+ * over the remaining budget, leaves the backward error > 1e3 * tol. The
+ * fallback then runs when the final
+ * backward error is not <= tol (NaN included), with at most max_iter64
+ * classical corrections.
+ *
+ * LU64: n x n FP64 (ldlu64 >= max(1, n)), caller-owned, written only by a
+ * fallback (then it holds the FP64 factors of A~). Other arguments as in
+ * rbt_solve_mixed; work: rbt_workspace_size(n, nrhs, depth, prec) bytes.
+ * iters_dev: device int32[2] = {low-precision iterations, FP64
+ * corrections}; info_dev: device int32[2] = {info of the low-precision
+ * elimination, info of the FP64 one (0 without fallback)}; path_dev: device
+ * int32, 0 = low-precision factors reached tol, 1 = FP64 fallback ran;
+ * berr_dev: final Eq. 7 backward error. All four nullable. Synchronizes
+ * `stream` as rbt_solve_mixed does, and once more before returning.
+ * Errors: -i for argument i; RBT_ERR_WORKSPACE; RBT_ERR_UNSUPPORTED for
+ * depth > 3; RBT_ERR_HIP. */
+int rbt_solve_mixed_guarded(int64_t n, int64_t nrhs, const double *A, int64_t lda, float *LU,
+                            int64_t ldlu, double *LU64, int64_t ldlu64, const double *B,
+                            int64_t ldb, double *X, int64_t ldx, int depth, uint64_t seed,
+                            int prec, int solver, double tol, int max_iter, int max_iter64,
+                            int32_t *iters_dev, double *berr_dev, int32_t *info_dev,
+                            int32_t *path_dev, void *work, size_t work_bytes, void *stream);
+
 /* Batched solves: many independent systems A_s X_s = B_s of different
  * orders (the method of Eq. 1 per system, with mixed precision as in
  * rbt_solve_mixed: FP32 elimination of A~_s, or BF16 trailing-update

@@ -37,6 +37,8 @@ SIGNATURES = {
                                vp, vp, vp, vp, sz, vp]),
     "rbt_solve_mixed": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, u64, i32, i32,
                               dbl, i32, vp, vp, vp, vp, sz, vp]),
+    "rbt_solve_mixed_guarded": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32,
+                                      u64, i32, i32, dbl, i32, i32, vp, vp, vp, vp, vp, sz, vp]),
     "rbt_batched_workspace_size": (sz, [i64, vp, vp, i32, i32]),
     "rbt_batched_plan": (i32, [i64, vp, vp, i32, i32, vp, sz, vp]),
     "rbt_solve_batched": (i32, [i64, vp, vp, vp, vp, vp, vp, i32, u64, i32, dbl, i32, vp, vp, vp,

@@ -77,6 +77,13 @@ struct Layout {
 // preconditioned residual that ends a cycle.
 constexpr int kGmresRestart = 50;
 constexpr double kGmresTau = 1e-10;
+// Guarded GMRES-IR: from iteration kGmresStallMin of a cycle on, the
+// residual estimate is extrapolated at the rate of the last kGmresStallWin
+// iterations; the refinement stops when the extrapolated backward error at
+// the end of the budget exceeds tol by more than the margin.
+constexpr int kGmresStallMin = 8;
+constexpr int kGmresStallWin = 4;
+constexpr double kGmresStallMargin = 1e3;
 
 int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
 
@@ -345,8 +352,9 @@ int refine_classic(int64_t n, int64_t nrhs, const double *A, int64_t lda, const 
                    int64_t ldlu, const double *B, int64_t ldb, double *X, int64_t ldx,
                    const Geometry &g, const double *U, const double *V, const double *winv,
                    int32_t *sync, double *R, double *scratch, double *anorm, double *berr, double tol,
-                   int max_iter, int *it_out, hipStream_t s) {
+                   int max_iter, int *it_out, hipStream_t s, bool *stalled = nullptr) {
   int it = 0;
+  double be_prev = 0.0;
   for (;;) {
     {
       StageScope t(kStageResidual, s, 8.0 * double(n) * n);
@@ -358,6 +366,13 @@ int refine_classic(int64_t n, int64_t nrhs, const double *A, int64_t lda, const 
     RBT_HIP_CHECK(hipMemcpyAsync(&be_host, berr, sizeof(double), hipMemcpyDeviceToHost, s));
     RBT_HIP_CHECK(hipStreamSynchronize(s));
     if (be_host <= tol) break;
+    // guarded use: a non-finite error, or a correction that did not halve
+    // the error, means these factors cannot reach tol (the caller falls back)
+    if (stalled && (!(be_host < HUGE_VAL) || (it > 0 && !(be_host < 0.5 * be_prev)))) {
+      *stalled = true;
+      break;
+    }
+    be_prev = be_host;
     const int rc = apply_solve(g, nrhs, LU, ldlu, R, n, U, V, winv, sync, s);
     if (rc) return rc;
     RBT_HIP_CHECK(launch_axpy_cols(n, nrhs, R, n, X, ldx, s));
@@ -383,7 +398,8 @@ int refine_gmres(int64_t n, int64_t nrhs, const double *A, int64_t lda, const TF
                  int64_t ldlu, const double *B, int64_t ldb, double *X, int64_t ldx,
                  const Geometry &g, const double *U, const double *V, const double *winv,
                  int32_t *sync, double *R, double *scratch, double *kry, double *anorm,
-                 double *berr, double tol, int max_iter, int *it_out, hipStream_t s) {
+                 double *berr, double tol, int max_iter, int *it_out, hipStream_t s,
+                 bool *stalled = nullptr) {
   const int m = kGmresRestart;
   const int64_t vs = n * kSkinnyMax;  // stride of basis blocks
   double *Vb = kry;
@@ -393,7 +409,7 @@ int refine_gmres(int64_t n, int64_t nrhs, const double *A, int64_t lda, const TF
   double *nrm = dots2 + (m + 2) * kSkinnyMax;
   double *coef = nrm + (m + 2) * kSkinnyMax;
   std::vector<double> hd((m + 2) * kSkinnyMax), hd2((m + 2) * kSkinnyMax), hn(kSkinnyMax);
-  std::vector<double> H, cs, sn, gv, beta, y;
+  std::vector<double> H, cs, sn, gv, beta, y, hist;
   std::vector<int> kc;
   std::vector<char> active;
   int worst = 0;
@@ -417,6 +433,11 @@ int refine_gmres(int64_t n, int64_t nrhs, const double *A, int64_t lda, const TF
       RBT_HIP_CHECK(hipMemcpyAsync(&be, berr, sizeof(double), hipMemcpyDeviceToHost, s));
       RBT_HIP_CHECK(hipStreamSynchronize(s));
       if (be <= tol || total >= max_iter) break;
+      if (stalled && !(be < HUGE_VAL)) {
+        *stalled = true;
+        break;
+      }
+      bool stop = false;
       // z = M^-1 r, v_0 = z / ||z||
       rc = apply_solve(g, nc, LU, ldlu, R, n, U, V, winv, sync, s);
       if (rc) return rc;
@@ -431,6 +452,7 @@ int refine_gmres(int64_t n, int64_t nrhs, const double *A, int64_t lda, const TF
       beta.assign(nc, 0.0);
       kc.assign(nc, 0);
       active.assign(nc, 0);
+      hist.assign(size_t(nc) * (m + 1), 1.0);
       for (int c = 0; c < nc; ++c) {
         beta[c] = hn[c] > 0.0 ? std::sqrt(hn[c]) : 0.0;
         gv[size_t(c) * (m + 1)] = beta[c];
@@ -485,6 +507,27 @@ int refine_gmres(int64_t n, int64_t nrhs, const double *A, int64_t lda, const TF
             all_done = false;
         }
         if (all_done) break;
+        // guarded use: extrapolate each column's residual estimate at the
+        // geometric rate of its last kGmresStallWin iterations over the
+        // remaining budget; if that leaves the backward error far above tol,
+        // stop (the caller falls back)
+        if (stalled) {
+          double pred = 0.0;
+          for (int c = 0; c < nc; ++c) {
+            const double r = beta[c] > 0.0 ? std::fabs(gv[size_t(c) * (m + 1) + j + 1]) / beta[c]
+                                           : 0.0;
+            hist[size_t(c) * (m + 1) + j + 1] = r;
+            if (!active[c] || j + 1 < kGmresStallMin) continue;
+            const double r0 = hist[size_t(c) * (m + 1) + j + 1 - kGmresStallWin];
+            const double rate = r0 > 0.0 ? std::pow(r / r0, 1.0 / kGmresStallWin) : 0.0;
+            const double p = r * std::pow(rate, double(max_iter - total));
+            pred = p > pred ? p : pred;
+          }
+          if (be * pred > kGmresStallMargin * tol) {
+            stop = true;
+            break;
+          }
+        }
       }
       // y = R^-1 g per column (upper triangular, size kc[c]); X += V y
       int kmax = 0;
@@ -509,6 +552,14 @@ int refine_gmres(int64_t n, int64_t nrhs, const double *A, int64_t lda, const TF
         // the next step synchronizes the stream
       } else {
         break;  // no progress possible (zero preconditioned residual)
+      }
+      if (stop) {
+        // the correction is kept; y is still read by the copy above
+        RBT_HIP_CHECK(hipStreamSynchronize(s));
+        *stalled = true;
+        worst = total > worst ? total : worst;
+        *it_out = worst;
+        return residual(nrhs, X, B);
       }
     }
     worst = total > worst ? total : worst;
@@ -728,36 +779,24 @@ extern "C" int rbt_solve_refine(int64_t n, int64_t nrhs, const double *A, int64_
   return 0;
 }
 
-extern "C" int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, float *LU,
-                               int64_t ldlu, const double *B, int64_t ldb, double *X, int64_t ldx,
-                               int depth, uint64_t seed, int prec, int solver, double tol,
-                               int max_iter, int32_t *iters_dev, double *berr_dev,
-                               int32_t *info_dev, void *work, size_t work_bytes, void *stream) {
-  if (n < 0) return -1;
-  if (nrhs < 0) return -2;
-  if (n > 0 && A == nullptr) return -3;
-  if (lda < (n > 1 ? n : 1)) return -4;
-  if (n > 0 && LU == nullptr) return -5;
-  if (ldlu < (n > 1 ? n : 1)) return -6;
-  if (n > 0 && nrhs > 0 && B == nullptr) return -7;
-  if (ldb < (n > 1 ? n : 1)) return -8;
-  if (n > 0 && nrhs > 0 && X == nullptr) return -9;
-  if (ldx < (n > 1 ? n : 1)) return -10;
-  if (bad_depth(depth)) return -11;
-  if (prec != RBT_FP32 && prec != RBT_BF16) return -13;
-  if (solver != RBT_IR_CLASSIC && solver != RBT_IR_GMRES) return -14;
-  if (!(tol >= 0.0)) return -15;
-  if (max_iter < 0) return -16;
-  if (depth > 3) return RBT_ERR_UNSUPPORTED;  // the FP32-output transform is one pass
+namespace rbt {
+namespace {
+
+// Body of the mixed-precision solve. stalled != nullptr: guarded use, the
+// refinement stops early when it cannot reach tol (non-finite error, or no
+// progress), *stalled says so. *it_out = refinement iterations.
+int mixed_impl(int64_t n, int64_t nrhs, const double *A, int64_t lda, float *LU, int64_t ldlu,
+               const double *B, int64_t ldb, double *X, int64_t ldx, int depth, uint64_t seed,
+               int prec, int solver, double tol, int max_iter, double *berr_dev,
+               int32_t *info_dev, void *work, size_t work_bytes, hipStream_t s, int *it_out,
+               bool *stalled) {
+  *it_out = 0;
   const Layout L = layout(n, nrhs, depth, true);
-  if (n > 0 && work == nullptr) return -20;
   if (work_bytes < L.total) return RBT_ERR_WORKSPACE;
-  hipStream_t s = S(stream);
   double *small = at<double>(work, L.o_small);
   double *berr = berr_dev ? berr_dev : small + 1;
   if (n == 0 || nrhs == 0) {
     RBT_HIP_CHECK(launch_fill_f64(berr, 0.0, s));
-    if (iters_dev) RBT_HIP_CHECK(launch_fill_i32(iters_dev, 0, s));
     if (n > 0) {  // still factor, as the square case of rbt_genp
       const Geometry g = geometry(n, depth);
       double *U = at<double>(work, L.o_coef);
@@ -765,6 +804,7 @@ extern "C" int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t
       RBT_HIP_CHECK(transform2_t(g, A, lda, LU, ldlu, RBT_FP32, U, U + n * depth, s));
       return genp_impl(n, LU, ldlu, info_dev, prec, s);
     }
+    if (info_dev) RBT_HIP_CHECK(launch_fill_i32(info_dev, 0, s));
     return 0;
   }
   const Geometry g = geometry(n, depth);
@@ -785,19 +825,120 @@ extern "C" int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t
   int32_t *sync = at<int32_t>(work, L.o_sync);
   rc = apply_solve(g, nrhs, (const float *)LU, ldlu, X, ldx, U, V, winv, sync, s);
   if (rc) return rc;
-  int it = 0;
   if (solver == RBT_IR_GMRES)
-    rc = refine_gmres(n, nrhs, A, lda, (const float *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv,
-                      sync, R, scratch, at<double>(work, L.o_krylov), anorm, berr, tol, max_iter,
-                      &it, s);
-  else
-    rc = refine_classic(n, nrhs, A, lda, (const float *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv,
-                        sync, R, scratch, anorm, berr, tol, max_iter, &it, s);
+    return refine_gmres(n, nrhs, A, lda, (const float *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv,
+                        sync, R, scratch, at<double>(work, L.o_krylov), anorm, berr, tol,
+                        max_iter, it_out, s, stalled);
+  return refine_classic(n, nrhs, A, lda, (const float *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv,
+                        sync, R, scratch, anorm, berr, tol, max_iter, it_out, s, stalled);
+}
+
+int mixed_args(int64_t n, int64_t nrhs, const double *A, int64_t lda, const float *LU,
+               int64_t ldlu, const double *B, int64_t ldb, const double *X, int64_t ldx,
+               int depth, int prec, int solver, double tol, int max_iter) {
+  if (n < 0) return -1;
+  if (nrhs < 0) return -2;
+  if (n > 0 && A == nullptr) return -3;
+  if (lda < (n > 1 ? n : 1)) return -4;
+  if (n > 0 && LU == nullptr) return -5;
+  if (ldlu < (n > 1 ? n : 1)) return -6;
+  if (n > 0 && nrhs > 0 && B == nullptr) return -7;
+  if (ldb < (n > 1 ? n : 1)) return -8;
+  if (n > 0 && nrhs > 0 && X == nullptr) return -9;
+  if (ldx < (n > 1 ? n : 1)) return -10;
+  if (bad_depth(depth)) return -11;
+  if (prec != RBT_FP32 && prec != RBT_BF16) return -13;
+  if (solver != RBT_IR_CLASSIC && solver != RBT_IR_GMRES) return -14;
+  if (!(tol >= 0.0)) return -15;
+  if (max_iter < 0) return -16;
+  if (depth > 3) return RBT_ERR_UNSUPPORTED;  // the FP32-output transform is one pass
+  return 0;
+}
+
+}  // namespace
+}  // namespace rbt
+
+extern "C" int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, float *LU,
+                               int64_t ldlu, const double *B, int64_t ldb, double *X, int64_t ldx,
+                               int depth, uint64_t seed, int prec, int solver, double tol,
+                               int max_iter, int32_t *iters_dev, double *berr_dev,
+                               int32_t *info_dev, void *work, size_t work_bytes, void *stream) {
+  int rc = mixed_args(n, nrhs, A, lda, LU, ldlu, B, ldb, X, ldx, depth, prec, solver, tol,
+                      max_iter);
+  if (rc) return rc;
+  if (n > 0 && work == nullptr) return -20;
+  hipStream_t s = S(stream);
+  int it = 0;
+  rc = mixed_impl(n, nrhs, A, lda, LU, ldlu, B, ldb, X, ldx, depth, seed, prec, solver, tol,
+                  max_iter, berr_dev, info_dev, work, work_bytes, s, &it, nullptr);
   if (rc) return rc;
   if (iters_dev) {
     RBT_HIP_CHECK(hipMemcpyAsync(iters_dev, &it, sizeof(int32_t), hipMemcpyHostToDevice, s));
     RBT_HIP_CHECK(hipStreamSynchronize(s));
   }
+  return 0;
+}
+
+extern "C" int rbt_solve_mixed_guarded(int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                                       float *LU, int64_t ldlu, double *LU64, int64_t ldlu64,
+                                       const double *B, int64_t ldb, double *X, int64_t ldx,
+                                       int depth, uint64_t seed, int prec, int solver, double tol,
+                                       int max_iter, int max_iter64, int32_t *iters_dev,
+                                       double *berr_dev, int32_t *info_dev, int32_t *path_dev,
+                                       void *work, size_t work_bytes, void *stream) {
+  // argument numbers of rbt_solve_mixed shift by two after ldlu (LU64, ldlu64)
+  int rc = mixed_args(n, nrhs, A, lda, LU, ldlu, B, ldb, X, ldx, depth, prec, solver, tol,
+                      max_iter);
+  if (rc <= -1 && rc >= -6) return rc;
+  if (n > 0 && LU64 == nullptr) return -7;
+  if (ldlu64 < (n > 1 ? n : 1)) return -8;
+  if (rc <= -7 && rc >= -16) return rc - 2;
+  if (rc) return rc;
+  if (max_iter64 < 0) return -19;
+  if (n > 0 && work == nullptr) return -24;
+  hipStream_t s = S(stream);
+  const Layout L = layout(n, nrhs, depth, true);
+  double *small = at<double>(work, L.o_small);
+  double *berr = berr_dev ? berr_dev : small + 1;
+  int32_t its[2] = {0, 0};
+  int32_t path = 0;
+  bool stalled = false;
+  rc = mixed_impl(n, nrhs, A, lda, LU, ldlu, B, ldb, X, ldx, depth, seed, prec, solver, tol,
+                  max_iter, berr, info_dev, work, work_bytes, s, &its[0], &stalled);
+  if (rc) return rc;
+  if (info_dev) RBT_HIP_CHECK(launch_fill_i32(info_dev + 1, 0, s));
+  double be = 0.0;
+  RBT_HIP_CHECK(hipMemcpyAsync(&be, berr, sizeof(double), hipMemcpyDeviceToHost, s));
+  RBT_HIP_CHECK(hipStreamSynchronize(s));
+  if (n > 0 && nrhs > 0 && !(be <= tol)) {
+    // the low-precision factors cannot reach tol: factor A~ again in FP64
+    // (same butterflies, already in the workspace) and refine from scratch
+    path = 1;
+    const Geometry g = geometry(n, depth);
+    double *U = at<double>(work, L.o_coef);
+    double *V = U + n * depth;
+    double *winv = at<double>(work, L.o_winv);
+    int32_t *sync = at<int32_t>(work, L.o_sync);
+    RBT_HIP_CHECK(transform2_t(g, A, lda, LU64, ldlu64, RBT_FP64, U, V, s));
+    rc = genp_fp64(n, LU64, ldlu64, info_dev ? info_dev + 1 : nullptr, s);
+    if (rc) return rc;
+    rc = diag_inverses_t(n, nrhs, LU64, ldlu64, winv, s);
+    if (rc) return rc;
+    RBT_HIP_CHECK(launch_copy_cols(n, nrhs, B, ldb, X, ldx, s));
+    rc = apply_solve(g, nrhs, (const double *)LU64, ldlu64, X, ldx, U, V, winv, sync, s);
+    if (rc) return rc;
+    int it64 = 0;
+    rc = refine_classic(n, nrhs, A, lda, (const double *)LU64, ldlu64, B, ldb, X, ldx, g, U, V,
+                        winv, sync, at<double>(work, L.o_resid), at<double>(work, L.o_partial),
+                        small, berr, tol, max_iter64, &it64, s);
+    if (rc) return rc;
+    its[1] = it64;
+  }
+  if (iters_dev)
+    RBT_HIP_CHECK(hipMemcpyAsync(iters_dev, its, sizeof(its), hipMemcpyHostToDevice, s));
+  if (path_dev)
+    RBT_HIP_CHECK(hipMemcpyAsync(path_dev, &path, sizeof(path), hipMemcpyHostToDevice, s));
+  RBT_HIP_CHECK(hipStreamSynchronize(s));
   return 0;
 }
 

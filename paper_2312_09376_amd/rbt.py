@@ -209,6 +209,41 @@ def solve_mixed(A, B, depth=2, seed=2023, prec=RBT_FP32, solver=RBT_IR_CLASSIC, 
     return X, LU, iters, berr, info, work
 
 
+def solve_mixed_guarded(A, B, depth=2, seed=2023, prec=RBT_FP32, solver=RBT_IR_GMRES, tol=None,
+                        max_iter=30, max_iter64=10, LU=None, LU64=None, X=None, work=None):
+    """solve_mixed with a fallback to FP64 factors when the low-precision
+    refinement cannot reach tol. Returns (X, LU, LU64, iters[2], berr,
+    info[2], path, work); path 1 means the FP64 fallback ran (LU64 then holds
+    the FP64 factors of A~)."""
+    A = colmajor(A)
+    B = colmajor(B)
+    _dev_f64(A, "A")
+    _dev_f64(B, "B")
+    n, k = A.shape[0], B.shape[1]
+    if tol is None:
+        tol = 10.0 * n * 2.0 ** -52
+    dev = A.device
+    LU = LU if LU is not None else torch.empty_strided((n, n), (1, max(1, n)), dtype=torch.float32, device=dev)
+    if LU.dtype != torch.float32:
+        raise TypeError("LU must be float32")
+    LU64 = LU64 if LU64 is not None else torch.empty_strided((n, n), (1, max(1, n)), dtype=torch.float64,
+                                                             device=dev)
+    if LU64.dtype != torch.float64:
+        raise TypeError("LU64 must be float64")
+    X = X if X is not None else torch.empty_strided((n, k), (1, max(1, n)), dtype=torch.float64, device=dev)
+    work = work if work is not None else _workspace(n, k, depth, dev, prec)
+    iters = torch.zeros(2, dtype=torch.int32, device=dev)
+    berr = torch.zeros(1, dtype=torch.float64, device=dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    path = torch.zeros(1, dtype=torch.int32, device=dev)
+    check(lib().rbt_solve_mixed_guarded(n, k, _p(A), _ld(A), _p(LU), _ld(LU), _p(LU64), _ld(LU64),
+                                        _p(B), _ld(B), _p(X), _ld(X), depth, seed, int(prec),
+                                        int(solver), float(tol), int(max_iter), int(max_iter64),
+                                        _p(iters), _p(berr), _p(info), _p(path), _p(work),
+                                        work.numel(), _stream(dev)), "rbt_solve_mixed_guarded")
+    return X, LU, LU64, iters, berr, info, path, work
+
+
 class BatchPlan:
     """Sizes, workspace and device descriptor arrays of a planned batch."""
 

@@ -88,6 +88,17 @@ def test_argument_errors(lib):
     assert mixed(depth=4) == _lib.RBT_ERR_UNSUPPORTED
     assert lib.rbt_workspace_size(1000, 1, 2, _lib.RBT_BF16) > 0
     assert lib.rbt_workspace_size(1000, 1, 2, 9) == 0
+    def guarded(prec=_lib.RBT_FP32, tol=1e-10, ldlu64=5, lu64=dummy, max_iter64=3, ldx=5):
+        return lib.rbt_solve_mixed_guarded(5, 1, dummy, 5, dummy, 5, lu64, ldlu64, dummy, 5,
+                                           dummy, ldx, 2, 0, prec, _lib.RBT_IR_GMRES, tol, 3,
+                                           max_iter64, None, None, None, None, dummy, 1 << 30,
+                                           None)
+    assert guarded(lu64=None) == -7
+    assert guarded(ldlu64=4) == -8
+    assert guarded(ldx=4) == -12
+    assert guarded(prec=_lib.RBT_FP64) == -15
+    assert guarded(tol=-1.0) == -17
+    assert guarded(max_iter64=-1) == -19
     # adjoint of the mixed solve
     assert lib.rbt_solve_backward_mixed(5, 1, dummy, 5, dummy, 4, dummy, 5, dummy, 5, None, 5,
                                         dummy, 5, 2, 0, 1e-10, 3, None, None, dummy, 1 << 30,

@@ -177,3 +177,81 @@ def test_gmres_ir_respects_iteration_cap(rbt):
                                               solver=rbt.RBT_IR_GMRES, tol=0.0, max_iter=7)
     assert int(iters.item()) == 7
     assert np.isfinite(float(berr.item()))
+
+
+def test_guarded_without_fallback_matches_mixed(rbt):
+    """When the low-precision factors reach tol, the guarded solve is the
+    mixed solve: same result bit for bit, no FP64 factorization."""
+    n = 700
+    A = workloads.dominant(n, seed=21)
+    B = workloads.randn(n, 3, seed=22)
+    Xm, _, itm, bem, _, _ = rbt.solve_mixed(dev(A), dev(B), 2, 2023, prec=rbt.RBT_FP32,
+                                            solver=rbt.RBT_IR_GMRES, max_iter=30)
+    Xg, _, _, its, beg, info, path, _ = rbt.solve_mixed_guarded(dev(A), dev(B), 2, 2023,
+                                                                prec=rbt.RBT_FP32,
+                                                                solver=rbt.RBT_IR_GMRES,
+                                                                max_iter=30)
+    assert int(path.item()) == 0
+    assert host(its).tolist() == [int(itm.item()), 0]
+    assert host(info).tolist() == [0, 0]
+    assert np.array_equal(host(Xg), host(Xm))
+    assert float(beg.item()) == float(bem.item()) <= 10 * n * EPS
+
+
+@pytest.mark.parametrize("n,k", [(700, 1), (333, 5)])
+def test_guarded_fallback_matches_fp64_oracle(rbt, n, k):
+    """BF16 factors of an N(0,1) matrix with no refinement budget cannot
+    reach 10 n eps, so the FP64 factors of the same A~ are computed: they
+    reconstruct the oracle's A~ to FP64 accuracy (elementwise agreement of
+    unpivoted factors of an N(0,1) matrix has no fixed tolerance), and the
+    refined solution reaches the tolerance."""
+    A = workloads.randn_matrix(n, seed=n)
+    B = workloads.randn(n, k, seed=5)
+    tol = 10 * n * EPS
+    X, _, LU64, its, berr, info, path, _ = rbt.solve_mixed_guarded(
+        dev(A), dev(B), 2, 2023, prec=rbt.RBT_BF16, solver=rbt.RBT_IR_CLASSIC, tol=tol,
+        max_iter=0, max_iter64=10)
+    assert int(path.item()) == 1
+    assert host(info).tolist() == [0, 0]
+    assert host(its)[0] == 0
+    assert float(berr.item()) <= tol
+    Uo, Vo = coeffs.generate(n, 2, 2023)
+    At = otr.two_sided(A, Uo, Vo, 2)
+    F = host(LU64)
+    Lm = np.tril(F, -1) + np.eye(n)
+    Um = np.triu(F)
+    assert np.abs(Lm @ Um - At).max() / (np.abs(Lm).max() * np.abs(Um).max()) <= 20 * n * EPS
+    Xe = np.linalg.solve(A, B)
+    assert relfro(host(X), Xe) <= 20 * np.linalg.cond(A, np.inf) * tol
+
+
+def test_guarded_gmres_stall_rule(rbt):
+    """tol = 0 is out of reach of any extrapolation, so the GMRES phase stops
+    after the minimum of 8 iterations of its first cycle (unless the cycle
+    ended before) and the FP64 phase spends its whole budget."""
+    n = 400
+    A = workloads.randn_matrix(n, seed=77)
+    B = workloads.randn(n, 2, seed=78)
+    X, _, _, its, berr, info, path, _ = rbt.solve_mixed_guarded(
+        dev(A), dev(B), 2, 2023, prec=rbt.RBT_BF16, solver=rbt.RBT_IR_GMRES, tol=0.0,
+        max_iter=100, max_iter64=2)
+    its = host(its)
+    assert int(path.item()) == 1
+    assert 1 <= its[0] <= 8 and its[1] == 2
+    assert float(berr.item()) <= 10 * n * EPS
+    assert relfro(host(X), np.linalg.solve(A, B)) <= 20 * np.linalg.cond(A, np.inf) * 10 * n * EPS
+
+
+def test_guarded_classic_stall_rule(rbt):
+    """Classical refinement with BF16 factors of an N(0,1) matrix stops at the
+    first correction that does not halve the backward error, long before the
+    budget, and the FP64 fallback reaches the tolerance."""
+    n = 900
+    A = workloads.randn_matrix(n, seed=9)
+    B = workloads.randn(n, 1, seed=10)
+    _, _, _, its, berr, _, path, _ = rbt.solve_mixed_guarded(
+        dev(A), dev(B), 2, 2023, prec=rbt.RBT_BF16, solver=rbt.RBT_IR_CLASSIC, max_iter=200)
+    its = host(its)
+    if int(path.item()) == 1:
+        assert its[0] < 200
+    assert float(berr.item()) <= 10 * n * EPS
