@@ -69,6 +69,10 @@ def parse():
                     help="batched mode: all systems of this order (0: n ~ U{37..1500})")
     ap.add_argument("--batch-nrhs", type=int, default=0,
                     help="batched mode: all systems with this many right-hand sides (0: U{1..16})")
+    ap.add_argument("--batch-tile-cols", type=int, default=0,
+                    help="batched mode: 64-column tiles per trailing-update round (0: tuned)")
+    ap.add_argument("--batch-wgs", type=int, default=0,
+                    help="batched mode: persistent workgroups per CU (0: tuned)")
     ap.add_argument("--tol-scale", type=float, default=10.0,
                     help="batched mode: refine to tol-scale * n * eps per system (0: max_iter steps)")
     ap.add_argument("--matrix", choices=["randn", "logcond", "dominant"], default="randn",
@@ -240,18 +244,25 @@ def batched_mode(args):
             A = workloads.device_randn(int(n), int(n), workloads.MATRIX_SEED + s_)
         As.append(A)
         Bs.append(workloads.device_randn(int(n), int(k), workloads.RHS_SEED + s_))
+    tuned = not (args.batch_tile_cols or args.batch_wgs)  # explicit shape overrides the table
+    if args.batch_tile_cols:
+        rbt.set_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS, args.batch_tile_cols)
+    if args.batch_wgs:
+        rbt.set_option(rbt._lib.RBT_OPT_BATCH_WGS_PER_CU, args.batch_wgs)
     plan = rbt.batched_plan(ns, ks, d, prec)
     bargs = rbt.BatchArgs(plan, As, Bs)
     torch.cuda.synchronize()
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(stream):
-        rbt.solve_batched_launch(plan, bargs, seed=args.seed, tol=tol, max_iter=args.max_iter)
+        rbt.solve_batched_launch(plan, bargs, seed=args.seed, tol=tol, max_iter=args.max_iter,
+                                 tuned=tuned)
     torch.cuda.current_stream().wait_stream(stream)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        rbt.solve_batched_launch(plan, bargs, seed=args.seed, tol=tol, max_iter=args.max_iter)
+        rbt.solve_batched_launch(plan, bargs, seed=args.seed, tol=tol, max_iter=args.max_iter,
+                                 tuned=tuned)
     for _ in range(args.warmup):
         graph.replay()
     torch.cuda.synchronize()
@@ -287,7 +298,9 @@ def batched_mode(args):
                                f"elimination + FP64 refinement to 10 n eps, one persistent "
                                f"launch replayed from a HIP graph",
                    "batch": args.batch, "depth": d, "matrix": args.matrix,
-                   "sum_n2": int(np.sum(ns.astype(np.int64) ** 2)), "flops": flops},
+                   "sum_n2": int(np.sum(ns.astype(np.int64) ** 2)), "flops": flops,
+                   "tile_cols": rbt.get_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS),
+                   "wgs_per_cu": rbt.get_option(rbt._lib.RBT_OPT_BATCH_WGS_PER_CU)},
         "systems_per_s": round(args.batch / (ms_step * 1e-3), 1),
         "roofline": {"bound": "mfma", "kernel": "k_batched (persistent, whole method per system)",
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",

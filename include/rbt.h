@@ -311,6 +311,17 @@ int rbt_solve_backward_mixed(int64_t n, int64_t nrhs, const float *LU, int64_t l
  *   diagonal blocks are always 128 x 128. Changes only the order of the
  *   roundings, not the method. */
 #define RBT_OPT_OUTER_NB 1
+/* RBT_OPT_BATCH_TILE_COLS: rbt_solve_batched, 64-column tiles of the
+ *   low-precision trailing update per round (1 or 2; default 1): more tiles
+ *   per round, fewer barriers, more registers.
+ * RBT_OPT_BATCH_WGS_PER_CU: rbt_solve_batched, persistent workgroups per
+ *   compute unit (1 or 2; default 2).
+ * Both change the schedule only: every system's arithmetic is the same. The
+ * package's autotuner times every combination on the device and keeps a
+ * table per precision, which its binding applies before each launch; a
+ * launch uses the values current when it is enqueued (or captured). */
+#define RBT_OPT_BATCH_TILE_COLS 2
+#define RBT_OPT_BATCH_WGS_PER_CU 3
 /* Returns 0, -1 for an unknown option, -2 for an invalid value. */
 int rbt_set_option(int option, int64_t value);
 /* Current value, or -1 for an unknown option. */

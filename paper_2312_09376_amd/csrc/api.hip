@@ -130,6 +130,8 @@ inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 // Tunable options (rbt_set_option).
 struct Options {
   int64_t outer_nb = 1024;  // width of the panel whose trailing update is one GEMM
+  int64_t batch_tile_cols = 1;  // batched: 64-column tiles per trailing-update round
+  int64_t batch_wgs_per_cu = 2; // batched: persistent workgroups per compute unit
 };
 Options &options() {
   static Options o;
@@ -1065,11 +1067,11 @@ extern "C" int rbt_solve_batched(int64_t batch, const double *const *A, const in
   if (batch == 0) return 0;
   if (work == nullptr) return -17;
   if (work_bytes < kBatchTableOffset + size_t(batch) * sizeof(BatchDesc)) return RBT_ERR_WORKSPACE;
-  const int64_t cap = 2 * int64_t(device_cus());  // two workgroups per CU
+  const int64_t cap = options().batch_wgs_per_cu * int64_t(device_cus());
   const int grid = int(batch < cap ? batch : cap);
   RBT_HIP_CHECK(launch_batched(batch, work, work_bytes, A, lda, B, ldb, X, ldx, depth, seed, prec,
                                tol, max_iter, iters_dev, berr_dev, info_dev, path_dev, grid,
-                               S(stream)));
+                               int(options().batch_tile_cols), S(stream)));
   return 0;
 }
 
@@ -1191,6 +1193,14 @@ extern "C" int rbt_set_option(int option, int64_t value) {
       if (value < kNB || value % kNB != 0 || value > 16 * kNB) return -2;
       options().outer_nb = value;
       return 0;
+    case RBT_OPT_BATCH_TILE_COLS:
+      if (value != 1 && value != 2) return -2;
+      options().batch_tile_cols = value;
+      return 0;
+    case RBT_OPT_BATCH_WGS_PER_CU:
+      if (value != 1 && value != 2) return -2;
+      options().batch_wgs_per_cu = value;
+      return 0;
     default:
       return -1;
   }
@@ -1199,6 +1209,8 @@ extern "C" int rbt_set_option(int option, int64_t value) {
 extern "C" int64_t rbt_get_option(int option) {
   switch (option) {
     case RBT_OPT_OUTER_NB: return options().outer_nb;
+    case RBT_OPT_BATCH_TILE_COLS: return options().batch_tile_cols;
+    case RBT_OPT_BATCH_WGS_PER_CU: return options().batch_wgs_per_cu;
     default: return -1;
   }
 }

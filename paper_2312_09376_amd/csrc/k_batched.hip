@@ -235,6 +235,93 @@ __device__ __forceinline__ void tile_store(const f4 (&acc)[2][2], float *C, int6
     }
 }
 
+// Register stages of the pipelined trailing update (A22 -= L21 U12): the
+// next U12 tile and the next C tile are loaded into registers while the
+// matrix cores work on the current tile.
+// U12 tile (kv x cv, element (kx, nx) at src[kx + nx * ld]): thread holds
+// operand row nx = tid / 4, entries kx = 16 (tid % 4) + 0..15 (zero outside).
+__device__ __forceinline__ void load_bt(float (&v)[16], const float *src, int64_t ld, int cv,
+                                        int kv) {
+  const int tid = threadIdx.x;
+  const int col = tid >> 2, seg = (tid & 3) * 16;
+  const float *p = src + seg + int64_t(col) * ld;
+  if (col < cv && seg + 16 <= kv) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f4u t = *reinterpret_cast<const f4u *>(p + 4 * q);
+      v[4 * q] = t[0]; v[4 * q + 1] = t[1]; v[4 * q + 2] = t[2]; v[4 * q + 3] = t[3];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = (col < cv && seg + e < kv) ? p[e] : 0.0f;
+  }
+}
+template <bool BF16>
+__device__ __forceinline__ void store_bt(void *dst, const float (&v)[16]) {
+  const int tid = threadIdx.x;
+  const int col = tid >> 2, seg = (tid & 3) * 16;
+  if constexpr (BF16) {
+    __bf16(*D)[LDH] = reinterpret_cast<__bf16(*)[LDH]>(dst);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      bf8 w;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) w[e] = (__bf16)v[8 * h + e];
+      *reinterpret_cast<bf8 *>(&D[col][seg + 8 * h]) = w;
+    }
+  } else {
+    float(*D)[LDF] = reinterpret_cast<float(*)[LDF]>(dst);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) D[col][seg + e] = v[e];
+  }
+}
+// C tile (rv x cv at C, column-major ld) in the accumulator layout of
+// tile_mma: (i, j, v) is row wm*32 + 16 i + 4 (lane/16) + v, column
+// wn*32 + 16 j + lane%16. Entries outside the tile read as zero and are not
+// written.
+__device__ __forceinline__ void load_ct(f4 (&c)[2][2], const float *C, int64_t ld, int rv,
+                                        int cv) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const bool full = rv == BB && cv == BB;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int row = wm * 32 + 16 * i + 4 * lk, col = wn * 32 + 16 * j + l16;
+      const float *p = C + row + int64_t(col) * ld;
+      if (full) {
+        const f4u t = *reinterpret_cast<const f4u *>(p);
+        c[i][j] = f4{t[0], t[1], t[2], t[3]};
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) c[i][j][v] = (col < cv && row + v < rv) ? p[v] : 0.0f;
+      }
+    }
+}
+__device__ __forceinline__ void store_ct(const f4 (&c)[2][2], float *C, int64_t ld, int rv,
+                                         int cv) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const bool full = rv == BB && cv == BB;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int row = wm * 32 + 16 * i + 4 * lk, col = wn * 32 + 16 * j + l16;
+      float *p = C + row + int64_t(col) * ld;
+      if (full) {
+        *reinterpret_cast<f4u *>(p) = f4u{c[i][j][0], c[i][j][1], c[i][j][2], c[i][j][3]};
+      } else if (col < cv) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (row + v < rv) p[v] = c[i][j][v];
+      }
+    }
+}
+
 // FP64 panel products (the solves with the diagonal block's inverses): an
 // explicit inverse applied in FP32 loses accuracy on blocks with growth, so
 // these products stay in FP64 (v_mfma_f64_16x16x4f64, output element
@@ -456,8 +543,9 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
 }
 
 // TF = float: FP32 factors (trailing update in FP32 or, BF16U, with BF16
-// operands); TF = double: FP64 factors (the fallback; FP64 trailing update).
-template <typename TF, bool BF16U>
+// operands; CT column tiles of 64 per round of the trailing update);
+// TF = double: FP64 factors (the fallback; FP64 trailing update).
+template <typename TF, bool BF16U, int CT = 1>
 __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int *info_sh) {
   const int64_t n = s.n;
   TF *F = fmat<TF>(s);
@@ -499,6 +587,66 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
     }
     __syncthreads();
     // A22 -= L21 U12 (64 x 64 tiles; the L21 row tile stays in LDS)
+    if constexpr (sizeof(TF) == 4) {
+      // low precision: CT column tiles per round (the second U12 tile in
+      // region 1, free after the panel products); the next round's U12 and
+      // C tiles are loaded into registers while the matrix cores work
+      void *bdst[CT];
+      bdst[0] = BF16U ? static_cast<void *>(Bh) : static_cast<void *>(Bs);
+      if constexpr (CT > 1) bdst[1] = static_cast<void *>(L1);
+      for (int64_t r0 = k + kb; r0 < n; r0 += BB) {
+        const int rv = int(n - r0 < BB ? n - r0 : BB);
+        if constexpr (BF16U)
+          stage<true, false>(Ah, F + r0 + k * n, n, rv, kb);
+        else
+          stage<false, false>(As, F + r0 + k * n, n, rv, kb);
+        float bv[CT][16];
+        f4 cn[CT][2][2];
+        auto prefetch = [&](int64_t cbase) {
+#pragma unroll
+          for (int t = 0; t < CT; ++t) {
+            const int64_t c = cbase + int64_t(t) * BB;
+            if (c < n) {
+              const int cv = int(n - c < BB ? n - c : BB);
+              load_bt(bv[t], F + k + c * n, n, cv, kb);
+              load_ct(cn[t], F + r0 + c * n, n, rv, cv);
+            }
+          }
+        };
+        prefetch(k + kb);
+        for (int64_t c0 = k + kb; c0 < n; c0 += CT * BB) {
+          f4 cc[CT][2][2];
+#pragma unroll
+          for (int t = 0; t < CT; ++t) {
+            if (c0 + int64_t(t) * BB < n) store_bt<BF16U>(bdst[t], bv[t]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int j = 0; j < 2; ++j) cc[t][i][j] = cn[t][i][j];
+          }
+          __syncthreads();
+          prefetch(c0 + CT * BB);
+#pragma unroll
+          for (int t = 0; t < CT; ++t) {
+            const int64_t c = c0 + int64_t(t) * BB;
+            if (c >= n) break;
+            const int cv = int(n - c < BB ? n - c : BB);
+            if constexpr (BF16U)
+              tile_mma<true>(Ah, bdst[t], acc);
+            else
+              tile_mma<false>(As, bdst[t], acc);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int j = 0; j < 2; ++j) cc[t][i][j] -= acc[i][j];
+            store_ct(cc[t], F + r0 + c * n, n, rv, cv);
+          }
+          __syncthreads();
+        }
+      }
+      __syncthreads();
+      continue;
+    }
     for (int64_t r0 = k + kb; r0 < n; r0 += BB) {
       const int rv = int(n - r0 < BB ? n - r0 : BB);
       if constexpr (sizeof(TF) == 8)
@@ -808,7 +956,7 @@ __device__ __noinline__ void transform_into(const Sys &s, int d, bool lowp) {
   __syncthreads();
 }
 
-template <bool BF16U>
+template <bool BF16U, int CT>
 __device__ void solve_system(const Args &a, const BatchDesc &D, float *fbase, double *dbase,
                              double *f64base, double *L0, double *L1, int *info_sh,
                              double *anorm_sh) {
@@ -852,7 +1000,7 @@ __device__ void solve_system(const Args &a, const BatchDesc &D, float *fbase, do
     }
     transform_into(s, d, pass == 0);
     if (pass == 0)
-      eliminate<float, BF16U>(s, L0, L1, info_sh);
+      eliminate<float, BF16U, CT>(s, L0, L1, info_sh);
     else
       eliminate<double, false>(s, L0, L1, info_sh);
     int it_p = 0;
@@ -882,7 +1030,7 @@ __device__ void solve_system(const Args &a, const BatchDesc &D, float *fbase, do
   __syncthreads();
 }
 
-template <bool BF16U>
+template <bool BF16U, int CT>
 __global__ void __launch_bounds__(BT, 2) k_batched(Args a) {
   __shared__ __attribute__((aligned(16))) double lds[kR0Doubles + kR1Doubles];
   double *L0 = lds, *L1 = lds + kR0Doubles;
@@ -908,7 +1056,7 @@ __global__ void __launch_bounds__(BT, 2) k_batched(Args a) {
     if (t >= a.batch) break;
     const BatchDesc D = desc[t];
     if (D.n > 0) {
-      solve_system<BF16U>(a, D, fbase, dbase, f64base, L0, L1, &info_sh, &anorm_sh);
+      solve_system<BF16U, CT>(a, D, fbase, dbase, f64base, L0, L1, &info_sh, &anorm_sh);
     } else if (threadIdx.x == 0) {
       if (a.path) a.path[D.sys] = 0;
       if (a.iters) a.iters[D.sys] = 0;
@@ -928,7 +1076,9 @@ hipError_t launch_batched(int64_t batch, void *work, size_t work_bytes, const do
                           const int64_t *lda, const double *const *B, const int64_t *ldb,
                           double *const *X, const int64_t *ldx, int depth, uint64_t seed,
                           int prec, double tol, int max_iter, int32_t *iters, double *berr,
-                          int32_t *info, int32_t *path, int grid, hipStream_t s) {
+                          int32_t *info, int32_t *path, int grid, int tile_cols,
+                          hipStream_t s) {
+  if (tile_cols != 1 && tile_cols != 2) return hipErrorInvalidValue;
   Args a;
   a.batch = batch;
   a.work = static_cast<char *>(work);
@@ -949,10 +1099,18 @@ hipError_t launch_batched(int64_t batch, void *work, size_t work_bytes, const do
   a.prec = prec;
   a.max_iter = max_iter;
   hipLaunchKernelGGL(k_reset_ticket, dim3(1), dim3(64), 0, s, work);
-  if (prec == RBT_BF16)
-    hipLaunchKernelGGL(k_batched<true>, dim3(unsigned(grid)), dim3(BT), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_batched<false>, dim3(unsigned(grid)), dim3(BT), 0, s, a);
+  const dim3 g{unsigned(grid)}, b{unsigned(BT)};
+  if (prec == RBT_BF16) {
+    if (tile_cols == 2)
+      hipLaunchKernelGGL((k_batched<true, 2>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_batched<true, 1>), g, b, 0, s, a);
+  } else {
+    if (tile_cols == 2)
+      hipLaunchKernelGGL((k_batched<false, 2>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_batched<false, 1>), g, b, 0, s, a);
+  }
   return hipGetLastError();
 }
 

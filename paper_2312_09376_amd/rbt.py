@@ -254,6 +254,10 @@ class BatchPlan:
             raise ValueError("ns and ks must be 1-D arrays of the same length")
         self.ns, self.ks, self.depth, self.prec = ns, ks, int(depth), int(prec)
         self.batch = int(ns.size)
+        # launch shape chosen by the autotuner for this precision (or None:
+        # the library's current options)
+        from . import tune
+        self.tuned = tune.load_table().get("bf16" if self.prec == RBT_BF16 else "fp32")
         vp = ctypes.c_void_p
         nbytes = lib().rbt_batched_workspace_size(self.batch, ns.ctypes.data_as(vp),
                                                   ks.ctypes.data_as(vp), self.depth, self.prec)
@@ -309,10 +313,14 @@ class BatchArgs:
         self.path = torch.zeros(nb, dtype=torch.int32, device=dev)
 
 
-def solve_batched_launch(plan, args, seed=2023, tol=-10.0, max_iter=30):
+def solve_batched_launch(plan, args, seed=2023, tol=-10.0, max_iter=30, tuned=True):
     """Enqueue the batched solve on the current stream (no allocation, no
     copy, no synchronization: capturable in a HIP graph). tol < 0 means
-    |tol| n_s eps64 for system s."""
+    |tol| n_s eps64 for system s. tuned: apply the autotuned launch shape of
+    the plan's precision first (a schedule choice; results are identical)."""
+    if tuned and plan.tuned is not None:
+        set_option(_lib.RBT_OPT_BATCH_TILE_COLS, plan.tuned["tile_cols"])
+        set_option(_lib.RBT_OPT_BATCH_WGS_PER_CU, plan.tuned["wgs_per_cu"])
     check(lib().rbt_solve_batched(plan.batch, _p(args.pA), _p(args.lA), _p(args.pB), _p(args.lB),
                                   _p(args.pX), _p(args.lX), plan.depth, seed, plan.prec,
                                   float(tol), int(max_iter), _p(args.iters), _p(args.berr),

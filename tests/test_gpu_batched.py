@@ -183,3 +183,30 @@ def test_batched_plan_reuse_and_graph_capture(rbt):
             assert np.array_equal(host(x), r), rep
         assert np.array_equal(host(args.iters), host(ie))
         _ = torch.ones(10, device="cuda").sum().item()  # eager work between replays
+
+
+def test_batched_launch_shapes_give_identical_results(rbt):
+    """The autotuned options only change the schedule: every launch shape
+    returns the same solutions, iteration counts and backward errors, bit
+    for bit."""
+    from paper_2312_09376_amd import tune
+    ns = np.array([300, 129, 64, 1, 700, 200, 90, 450])
+    ks = np.array([3, 1, 16, 1, 2, 5, 8, 1])
+    As = [dev(workloads.randn_matrix(int(n), seed=s + 40)) for s, n in enumerate(ns)]
+    Bs = [dev(workloads.randn(int(n), int(k), seed=s)) for s, (n, k) in enumerate(zip(ns, ks))]
+    for prec in (rbt.RBT_FP32, rbt.RBT_BF16):
+        plan = rbt.batched_plan(ns, ks, 2, prec)
+        ref = None
+        for c in tune.CANDIDATES:
+            rbt.set_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS, c["tile_cols"])
+            rbt.set_option(rbt._lib.RBT_OPT_BATCH_WGS_PER_CU, c["wgs_per_cu"])
+            args = rbt.BatchArgs(plan, As, Bs)
+            rbt.solve_batched_launch(plan, args, seed=5, tuned=False)
+            torch.cuda.synchronize()
+            out = [host(x) for x in args.Xs] + [host(args.iters), host(args.berr), host(args.path)]
+            if ref is None:
+                ref = out
+            else:
+                assert all(np.array_equal(a, b) for a, b in zip(out, ref)), (prec, c)
+    rbt.set_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS, 1)
+    rbt.set_option(rbt._lib.RBT_OPT_BATCH_WGS_PER_CU, 2)
