@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-gepp", action="store_true", help="skip the GEPP comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=4096, help="oracle sample size")
+    ap.add_argument("--lookahead", type=int, default=-1, help="0/1 (-1: library default)")
     ap.add_argument("--outer-nb", type=int, default=0,
                     help="panel width of the elimination (multiple of 128; 0 = library default)")
     ap.add_argument("--mode", choices=["solve", "mixed", "batched", "backward", "copy"],
@@ -135,6 +136,9 @@ def mixed_mode(args):
     from paper_2312_09376_amd import rbt, workloads
     if args.outer_nb:
         rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, args.outer_nb)
+    if args.lookahead >= 0:
+        rbt.set_option(rbt._lib.RBT_OPT_LOOKAHEAD, args.lookahead)
+
     n, k, d = args.n, args.nrhs, args.depth
     tol = 10.0 * n * 2.0 ** -52
     prec = rbt.RBT_FP32 if args.prec == "fp32" else rbt.RBT_BF16
@@ -196,7 +200,8 @@ def mixed_mode(args):
         "config": {"workload": f"RBT+GENP {args.prec.upper()} elimination, FP64 {args.solver} "
                                f"refinement to berr<=10*n*eps, n={n}, nrhs={k}, depth {d}, "
                                f"A={args.matrix} seed 42, b~N(0,1) seed 64",
-                   "n": n, "nrhs": k, "depth": d, "outer_nb": W, "matrix": args.matrix},
+                   "n": n, "nrhs": k, "depth": d, "outer_nb": W, "matrix": args.matrix,
+                   "lookahead": rbt.get_option(rbt._lib.RBT_OPT_LOOKAHEAD)},
         "roofline": {"bound": "mfma",
                      "kernel": f"trailing-update GEMM (k_sgemm, {args.prec.upper()} MFMA)",
                      "achieved": round(gemm_tflops, 3), "peak": peak, "unit": "TFLOP/s",
@@ -438,6 +443,9 @@ def main():
         return
     if args.outer_nb:
         rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, args.outer_nb)
+    if args.lookahead >= 0:
+        rbt.set_option(rbt._lib.RBT_OPT_LOOKAHEAD, args.lookahead)
+
     n, k, d = args.n, args.nrhs, args.depth
     tol = 10.0 * n * 2.0 ** -52
 
@@ -503,7 +511,8 @@ def main():
         "config": {"workload": f"RBT+GENP FP64 solve, n={n}, nrhs={k}, depth {d}, A~N(0,1) seed 42, "
                                f"b~N(0,1) seed 64, FP64 refinement to berr<=10*n*eps",
                    "n": n, "nrhs": k, "depth": d,
-                   "outer_nb": rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)},
+                   "outer_nb": rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB),
+                   "lookahead": rbt.get_option(rbt._lib.RBT_OPT_LOOKAHEAD)},
         "roofline": {"bound": "mfma", "kernel": "trailing-update GEMM (k_dgemm, FP64 MFMA)",
                      "achieved": round(gemm_tflops, 3), "peak": PEAK_FP64_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(gemm_tflops / PEAK_FP64_MFMA_TFLOPS, 4),

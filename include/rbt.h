@@ -322,6 +322,16 @@ int rbt_solve_backward_mixed(int64_t n, int64_t nrhs, const float *LU, int64_t l
  * launch uses the values current when it is enqueued (or captured). */
 #define RBT_OPT_BATCH_TILE_COLS 2
 #define RBT_OPT_BATCH_WGS_PER_CU 3
+/* RBT_OPT_LOOKAHEAD: elimination (rbt_genp and every solve that factors).
+ *   1: while the next panel is factored on the caller's stream, the block
+ *   row and trailing update of the remaining columns run on a second stream
+ *   of the library (one per device, default priority, created on first
+ *   use, ordered by HIP events; the caller's stream waits for it before the
+ *   entry point returns). 0 (default): one stream. The factors are
+ *   bit-identical either way. On MI355X the overlap gains little: the
+ *   trailing GEMM's workgroups hold every CU's registers, so the panel
+ *   kernels wait for its tiles to drain. */
+#define RBT_OPT_LOOKAHEAD 4
 /* Returns 0, -1 for an unknown option, -2 for an invalid value. */
 int rbt_set_option(int option, int64_t value);
 /* Current value, or -1 for an unknown option. */

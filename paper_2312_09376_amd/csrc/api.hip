@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <cstdlib>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -132,6 +133,7 @@ struct Options {
   int64_t outer_nb = 1024;  // width of the panel whose trailing update is one GEMM
   int64_t batch_tile_cols = 1;  // batched: 64-column tiles per trailing-update round
   int64_t batch_wgs_per_cu = 2; // batched: persistent workgroups per compute unit
+  int64_t lookahead = 0;        // elimination: overlap panels with the trailing update
 };
 Options &options() {
   static Options o;
@@ -161,13 +163,43 @@ hipError_t gemm_sub(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda
 // T = double: FP64 throughout. T = float (mixed precision): FP32 storage;
 // diagonal blocks and triangular solves computed in FP64 and rounded on
 // store; GEMM updates with FP32 (prec RBT_FP32) or BF16 (RBT_BF16) operands.
+// Second stream of the elimination's lookahead, one per device, created on
+// first use (default priority, non-blocking) and kept until the process
+// ends.
+hipStream_t aux_stream() {
+  static std::mutex mu;
+  static std::vector<hipStream_t> per_dev;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (per_dev.size() <= size_t(dev)) per_dev.resize(dev + 1, nullptr);
+  if (per_dev[dev] == nullptr &&
+      hipStreamCreateWithFlags(&per_dev[dev], hipStreamNonBlocking) != hipSuccess)
+    per_dev[dev] = nullptr;
+  return per_dev[dev];
+}
+
+// Two events of one elimination (created per call, so that concurrent calls
+// never share them).
+struct EventPair {
+  hipEvent_t f = nullptr, b = nullptr;
+  bool ok() const { return f != nullptr && b != nullptr; }
+  EventPair() {
+    if (hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess) f = nullptr;
+    if (hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) b = nullptr;
+  }
+  ~EventPair() {
+    if (f) hipEventDestroy(f);
+    if (b) hipEventDestroy(b);
+  }
+};
+
 template <typename T>
 int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t s) {
   if (info) RBT_HIP_CHECK(launch_fill_i32(info, 0, s));
   const int64_t W = options().outer_nb;
-  for (int64_t k0 = 0; k0 < n; k0 += W) {
-    const int64_t w = n - k0 < W ? n - k0 : W;
-    // ---- panel A[k0:n, k0:k0+w] ----
+  // ---- factor the panel A[k0:n, k0:k0+w] (on s) ----
+  auto panel = [&](int64_t k0, int64_t w) -> int {
     for (int64_t k = k0; k < k0 + w; k += kNB) {
       const int kb = int(k0 + w - k < kNB ? k0 + w - k : kNB);
       T *A11 = A + k + k * lda;
@@ -190,29 +222,63 @@ int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t
                                lda, A + (k + kb) + (k + kb) * lda, lda, prec, false, s));
       }
     }
-    const int64_t rc = n - k0 - w;  // columns right of the panel
-    if (rc <= 0) continue;
-    // ---- block row U12 = L11^-1 A12 (L11: w x w unit lower) ----
+    return 0;
+  };
+  // ---- columns [c0, c0 + nc) right of the panel [k0, k0 + w): block row
+  // U12 = L11^-1 A12 (L11: w x w unit lower, kNB rows at a time), then
+  // A22 -= L21 U12 with one GEMM of depth w (on stream st) ----
+  auto update = [&](int64_t k0, int64_t w, int64_t c0, int64_t nc, hipStream_t st) -> int {
     for (int64_t k = k0; k < k0 + w; k += kNB) {
       const int kb = int(k0 + w - k < kNB ? k0 + w - k : kNB);
       const int64_t below = k0 + w - k - kb;
       {
-        StageScope t(kStagePanel, s, double(rc) * kb * kb);
-        RBT_HIP_CHECK(launch_trsm_left(TriMode::LN, kb, rc, A + k + k * lda, lda,
-                                       A + k + (k0 + w) * lda, lda, s));
+        StageScope t(kStagePanel, st, double(nc) * kb * kb);
+        RBT_HIP_CHECK(launch_trsm_left(TriMode::LN, kb, nc, A + k + k * lda, lda,
+                                       A + k + c0 * lda, lda, st));
       }
       if (below > 0) {
-        StageScope t(kStagePanel, s, 2.0 * double(below) * rc * kb);
-        RBT_HIP_CHECK(gemm_sub(below, rc, kb, A + (k + kb) + k * lda, lda, A + k + (k0 + w) * lda,
-                               lda, A + (k + kb) + (k0 + w) * lda, lda, prec, false, s));
+        StageScope t(kStagePanel, st, 2.0 * double(below) * nc * kb);
+        RBT_HIP_CHECK(gemm_sub(below, nc, kb, A + (k + kb) + k * lda, lda, A + k + c0 * lda, lda,
+                               A + (k + kb) + c0 * lda, lda, prec, false, st));
       }
     }
-    // ---- trailing update A22 -= L21 U12, depth w ----
-    {
-      StageScope t(kStageTrailing, s, 2.0 * double(rc) * rc * w);
-      RBT_HIP_CHECK(gemm_sub(rc, rc, w, A + (k0 + w) + k0 * lda, lda, A + k0 + (k0 + w) * lda, lda,
-                             A + (k0 + w) + (k0 + w) * lda, lda, prec, true, s));
+    const int64_t rows = n - k0 - w;
+    StageScope t(kStageTrailing, st, 2.0 * double(rows) * nc * w);
+    RBT_HIP_CHECK(gemm_sub(rows, nc, w, A + (k0 + w) + k0 * lda, lda, A + k0 + c0 * lda, lda,
+                           A + (k0 + w) + c0 * lda, lda, prec, true, st));
+    return 0;
+  };
+  // Lookahead: after panel p, stream s updates only the next panel's columns
+  // and factors that panel while the second stream updates the remaining
+  // columns (the bulk of the flops); s waits for it before the next block
+  // row, which reads those columns. The two streams touch disjoint columns
+  // and every element sees the same operations in the same order as without
+  // lookahead (the split is at a multiple of the GEMM tile), so the factors
+  // are identical either way.
+  hipStream_t s2 = options().lookahead ? aux_stream() : nullptr;
+  EventPair ev;
+  if (s2 != nullptr && !ev.ok()) s2 = nullptr;
+  if (n <= 0) return 0;
+  int rc = panel(0, n < W ? n : W);
+  if (rc) return rc;
+  for (int64_t k0 = 0;; k0 += W) {
+    const int64_t w = n - k0 < W ? n - k0 : W;
+    const int64_t rest = n - k0 - w;  // columns right of the panel
+    if (rest <= 0) break;
+    const int64_t wn = rest < W ? rest : W;  // next panel
+    const bool split = s2 != nullptr && rest > wn;
+    if (split) {
+      RBT_HIP_CHECK(hipEventRecord(ev.f, s));
+      RBT_HIP_CHECK(hipStreamWaitEvent(s2, ev.f, 0));
+      rc = update(k0, w, k0 + w + wn, rest - wn, s2);
+      if (rc) return rc;
+      RBT_HIP_CHECK(hipEventRecord(ev.b, s2));
     }
+    rc = update(k0, w, k0 + w, split ? wn : rest, s);
+    if (rc) return rc;
+    rc = panel(k0 + w, wn);
+    if (rc) return rc;
+    if (split) RBT_HIP_CHECK(hipStreamWaitEvent(s, ev.b, 0));
   }
   return 0;
 }
@@ -1201,6 +1267,10 @@ extern "C" int rbt_set_option(int option, int64_t value) {
       if (value != 1 && value != 2) return -2;
       options().batch_wgs_per_cu = value;
       return 0;
+    case RBT_OPT_LOOKAHEAD:
+      if (value != 0 && value != 1) return -2;
+      options().lookahead = value;
+      return 0;
     default:
       return -1;
   }
@@ -1211,6 +1281,7 @@ extern "C" int64_t rbt_get_option(int option) {
     case RBT_OPT_OUTER_NB: return options().outer_nb;
     case RBT_OPT_BATCH_TILE_COLS: return options().batch_tile_cols;
     case RBT_OPT_BATCH_WGS_PER_CU: return options().batch_wgs_per_cu;
+    case RBT_OPT_LOOKAHEAD: return options().lookahead;
     default: return -1;
   }
 }
