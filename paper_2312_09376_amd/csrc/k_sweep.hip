@@ -91,10 +91,12 @@ __global__ void __launch_bounds__(TPB)
     __syncthreads();
   };
 
-  // Single right-hand side: the diagonal block's inverse and the
-  // right-hand side do not depend on other blocks, so they are loaded into
-  // registers before any wait and leave the critical path of the sweep.
-  constexpr bool PRE = (NMAX == 1);
+  // The diagonal block's inverse and the block's right-hand side do not
+  // depend on other blocks: up to 8 right-hand sides they are loaded into
+  // registers before any wait and leave the critical path of the sweep;
+  // with 16 and FP32 factors the inverse is loaded right after the last
+  // accumulation; with 16 and FP64 factors at each use.
+  constexpr bool PRE = (NMAX <= 8);
   const double *Di = Winv + b * 2 * kNB * kNB +
                      ((MODE == TriMode::LN || MODE == TriMode::LT) ? 0 : kNB * kNB);
   auto load_dinv = [&](double (&ev)[SEGW]) {
@@ -115,10 +117,12 @@ __global__ void __launch_bounds__(TPB)
     }
   };
   double dpre[PRE ? SEGW : 1];
-  double bpre = 0.0;
+  double bpre[PRE ? NMAX : 1];
   if constexpr (PRE) {
     load_dinv(dpre);
-    if (sg == 0 && i < kb && N > 0) bpre = B[r0 + i];
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c)
+      bpre[c] = (sg == 0 && i < kb && c < N) ? B[(r0 + i) + int64_t(c) * ldb] : 0.0;
   }
 
   // ---- accumulate op(A)[b, j] x_j over the blocks solved before b ----
@@ -169,6 +173,17 @@ __global__ void __launch_bounds__(TPB)
     __syncthreads();
   }
 
+  // loads of the diagonal work, issued before the reductions (the FP64
+  // diagonal block of the refinement step only while registers allow)
+  constexpr bool EARLY_T = REFINE && NMAX <= 8;
+  TF et[REFINE ? SEGW : 1];
+  if constexpr (EARLY_T) load_tdiag(et);
+  // 16 right-hand sides: FP32 factors take the inverse here; FP64 factors
+  // (more registers live) load it at each use
+  constexpr bool EARLY_D = !PRE && !REFINE;
+  double dlate[EARLY_D ? SEGW : 1];
+  if constexpr (EARLY_D) load_dinv(dlate);
+
   // ---- r = b_b - acc ----
   double r[NMAX];
   reduce(acc, r);
@@ -178,7 +193,7 @@ __global__ void __launch_bounds__(TPB)
       // rows beyond kb summed clamped loads: zero them
       double bv;
       if constexpr (PRE)
-        bv = bpre;
+        bv = bpre[c];
       else
         bv = (i < kb && c < N) ? B[(r0 + i) + int64_t(c) * ldb] : 0.0;
       r[c] = (i < kb && c < N) ? bv - r[c] : 0.0;
@@ -193,6 +208,9 @@ __global__ void __launch_bounds__(TPB)
     if constexpr (PRE) {
 #pragma unroll
       for (int q = 0; q < SEGW; ++q) ev[q] = dpre[q];
+    } else if constexpr (EARLY_D) {
+#pragma unroll
+      for (int q = 0; q < SEGW; ++q) ev[q] = dlate[q];
     } else {
       load_dinv(ev);
     }
@@ -216,15 +234,14 @@ __global__ void __launch_bounds__(TPB)
       for (int c = 0; c < NMAX; ++c) xs[i][c] = x[c];
     }
     __syncthreads();
-    TF e[SEGW];
-    load_tdiag(e);
+    if constexpr (!EARLY_T) load_tdiag(et);
     double a[NMAX];
 #pragma unroll
     for (int c = 0; c < NMAX; ++c) a[c] = 0.0;
 #pragma unroll
     for (int q = 0; q < SEGW; ++q) {
       const int jj = sg * SEGW + q;
-      double v = double(e[q]);
+      double v = double(et[q]);
       if (jj >= kb || i >= kb) v = 0.0;
       else if (jj == i) v = UNIT ? 1.0 : v;
       else if (FWD ? (jj > i) : (jj < i)) v = 0.0;
