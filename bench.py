@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=10)
     ap.add_argument("--no-gepp", action="store_true", help="skip the GEPP comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-n", type=int, default=4096, help="oracle sample size")
+    ap.add_argument("--cpu-n", type=int, default=5120, help="oracle sample size (about 12 s of CPU work)")
     ap.add_argument("--lookahead", type=int, default=-1, help="0/1 (-1: library default)")
     ap.add_argument("--outer-nb", type=int, default=0,
                     help="panel width of the elimination (multiple of 128; 0 = library default)")
@@ -388,6 +388,20 @@ def backward_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def step_statistics(seconds):
+    """Mean and 99 % confidence half-width (Student t) of per-step times, ms."""
+    ms = [1e3 * x for x in seconds]
+    k = len(ms)
+    mean = sum(ms) / k
+    if k < 2:
+        return {"mean_ms": round(mean, 3), "ci99_ms": None, "n": k}
+    from scipy import stats
+    sd = math.sqrt(sum((x - mean) ** 2 for x in ms) / (k - 1))
+    half = float(stats.t.ppf(0.995, k - 1)) * sd / math.sqrt(k)
+    return {"mean_ms": round(mean, 3), "ci99_ms": round(half, 3), "n": k,
+            "min_ms": round(min(ms), 3), "max_ms": round(max(ms), 3)}
+
+
 def cpu_baseline(n, nrhs, depth, seed):
     """The oracle, as it stands, on the host cores: one full solve (coefficients,
     transform, elimination, solves, refinement to the same tolerance)."""
@@ -467,10 +481,12 @@ def main():
     rbt.timing_read()          # discard anything recorded so far
     rbt.timing_enable(True)
     iters = []
+    marks = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, _, it, be, info, _ = step()
+        _, _, it, be, info, _ = step()   # ends with a stream synchronization
+        marks.append(time.perf_counter())
         iters.append(it)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -480,6 +496,7 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     flops = (2.0 / 3.0) * n ** 3
     value = flops / (ms_step * 1e-3) / 1e12
+    step_stats = step_statistics([b - a for a, b in zip([t0] + marks[:-1], marks)])
     berr = float(be.item())
     ir_steps = [int(i.item()) for i in iters]
     info_v = int(info.item())
@@ -530,6 +547,7 @@ def main():
                        "avg_ms": round(k1_ms / max(k1_cnt, 1), 4),
                        "bytes_per_launch": k1_bytes / max(k1_cnt, 1)},
         "stages_ms_per_step": {s: round(v[0] / args.steps, 3) for s, v in stages.items()},
+        "step_ms": step_stats,
     }
 
     if not args.no_gepp:

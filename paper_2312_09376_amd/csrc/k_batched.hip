@@ -477,7 +477,7 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
         const double p = prow[cc];
         if (lane == 0 && c < kb && p == 0.0 && *info_sh == 0) *info_sh = int(k + c + 1);
         const bool act = lane > c;
-        const double la = xa[cc] / p;
+        const double la = xa[cc] * (1.0 / p);  // one division per pivot
         xa[cc] = act ? la : xa[cc];
 #pragma unroll
         for (int j = cc + 1; j < 16; ++j) {
@@ -527,10 +527,16 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
     const int j = lane;
     const double xj = 1.0 / S[j * LDS_ + j];
     T[j * LDS_ + j] = xj;
+    // reciprocal pivots in the unused padding row of T (one per column),
+    // read by the other lanes of this wavefront below
+    T[j * LDS_ + BB] = xj;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int i = j - 1; i >= 0; --i) {
       double a = 0.0;
       for (int t = i + 1; t <= j; ++t) a += S[t * LDS_ + i] * T[j * LDS_ + t];
-      T[j * LDS_ + i] = -a / S[i * LDS_ + i];
+      T[j * LDS_ + i] = -a * T[i * LDS_ + BB];
     }
   }
   __syncthreads();

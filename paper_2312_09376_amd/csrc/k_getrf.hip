@@ -89,7 +89,8 @@ __global__ void __launch_bounds__(256) k_diag_lu(int kb, T *__restrict__ A, int6
         if (lane == 0 && c < kb && p == 0.0 && info != nullptr)
           atomicCAS(info, 0, int32_t(gofs + c + 1));
         const bool acta = lane > c, actb = lane + 64 > c;
-        const double la = xa[cc] / p, lb = xb[cc] / p;
+        const double rp = 1.0 / p;  // one division per pivot (scaling as in LAPACK's getf2)
+        const double la = xa[cc] * rp, lb = xb[cc] * rp;
         xa[cc] = acta ? la : xa[cc];
         xb[cc] = actb ? lb : xb[cc];
 #pragma unroll

@@ -302,6 +302,91 @@ __global__ void __launch_bounds__(kRows) k_colabs(int64_t n, const double *__res
   if (threadIdx.x == 0) out[i] = sh[0];
 }
 
+// Transposed residual R = G - A^T L for N <= NMAX right-hand sides, with
+// the column sums of |A| (||A^T||_inf = ||A||_1) fused when ABS. A
+// workgroup owns tcols<NMAX>() columns of A (a quarter per wavefront) and
+// walks the rows in chunks of kRows: the chunk of L is staged in LDS and
+// reused by every column, each wavefront reads its columns of A as
+// coalesced runs, and the dot products are reduced across the wavefront at
+// the end. A is read once.
+template <int NMAX>
+constexpr int tcols() {
+  return NMAX >= 16 ? 8 : 16;
+}
+template <int NMAX, bool ABS>
+__global__ void __launch_bounds__(kRows) k_gemvT_sub(int64_t n, int N, const double *__restrict__ A,
+                                                     int64_t lda, const double *__restrict__ L,
+                                                     int64_t ldl, const double *__restrict__ G,
+                                                     int64_t ldg, double *__restrict__ R,
+                                                     int64_t ldr, double *__restrict__ colabs) {
+  constexpr int CW = tcols<NMAX>() / 4;  // columns per wavefront
+  __shared__ double Ls[kRows][NMAX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t j0 = int64_t(blockIdx.x) * tcols<NMAX>() + wave * CW;
+  double acc[CW][NMAX];
+  double aab[CW];
+#pragma unroll
+  for (int q = 0; q < CW; ++q) {
+    aab[q] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) acc[q][c] = 0.0;
+  }
+  for (int64_t i0 = 0; i0 < n; i0 += kRows) {
+    __syncthreads();
+    {
+      const int64_t i = i0 + threadIdx.x;
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c)
+        Ls[threadIdx.x][c] = (i < n && c < N) ? L[i + int64_t(c) * ldl] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int u = 0; u < kRows / 64; ++u) {
+      const int r = lane + 64 * u;
+      const int64_t i = i0 + r;
+      const bool rin = i < n;
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        const int64_t j = j0 + q;
+        // clamped, unconditional load; masked by rin / the column bound
+        const int64_t jc = j < n ? j : n - 1;
+        const double a0 = A[(rin ? i : n - 1) + jc * lda];
+        const double a = (rin && j < n) ? a0 : 0.0;
+        if constexpr (ABS) aab[q] += fabs(a);
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c) acc[q][c] += a * Ls[r][c];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CW; ++q) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) {
+      double v = acc[q][c];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      acc[q][c] = v;
+    }
+    if constexpr (ABS) {
+      double v = aab[q];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      aab[q] = v;
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      const int64_t j = j0 + q;
+      if (j >= n) continue;
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c)
+        if (c < N) R[j + int64_t(c) * ldr] = G[j + int64_t(c) * ldg] - acc[q][c];
+      if constexpr (ABS) colabs[j] = aab[q];
+    }
+  }
+}
+
 __global__ void k_fill_i32(int32_t *p, int32_t v) {
   if (threadIdx.x == 0) p[0] = v;
 }
@@ -543,14 +628,38 @@ hipError_t launch_residual_berr_T(int64_t n, int64_t nrhs, const double *A, int6
   }
   double *colabs = scratch;
   double *colstat = scratch + n;
-  if (with_anorm) {
-    hipLaunchKernelGGL(k_colabs, dim3(unsigned(n)), dim3(kRows), 0, s, n, A, lda, colabs);
-    hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(kRows), 0, s, n, colabs, anorm);
+  if (nrhs <= kSkinnyMax) {
+    const int N = int(nrhs);
+#define RBT_GEMVT(NM)                                                                          \
+  const dim3 g(unsigned((n + tcols<NM>() - 1) / tcols<NM>()));                                \
+  if (with_anorm)                                                                              \
+    hipLaunchKernelGGL((k_gemvT_sub<NM, true>), g, dim3(kRows), 0, s, n, N, A, lda, L, ldl, G,  \
+                       ldg, R, ldr, colabs);                                                   \
+  else                                                                                         \
+    hipLaunchKernelGGL((k_gemvT_sub<NM, false>), g, dim3(kRows), 0, s, n, N, A, lda, L, ldl, G, \
+                       ldg, R, ldr, colabs);
+    if (N <= 1) {
+      RBT_GEMVT(1)
+    } else if (N <= 4) {
+      RBT_GEMVT(4)
+    } else if (N <= 8) {
+      RBT_GEMVT(8)
+    } else {
+      RBT_GEMVT(16)
+    }
+#undef RBT_GEMVT
+    if (with_anorm)
+      hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(kRows), 0, s, n, colabs, anorm);
+  } else {
+    if (with_anorm) {
+      hipLaunchKernelGGL(k_colabs, dim3(unsigned(n)), dim3(kRows), 0, s, n, A, lda, colabs);
+      hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(kRows), 0, s, n, colabs, anorm);
+    }
+    hipLaunchKernelGGL(k_copy_cols, col_grid(n, nrhs), dim3(kRows), 0, s, n, nrhs, G, ldg, R, ldr);
+    hipError_t e = launch_dgemm(n, nrhs, n, A, lda, OpA::GeneralT, L, ldl, OpB::General, R, ldr,
+                                Acc::Subtract, s);
+    if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_copy_cols, col_grid(n, nrhs), dim3(kRows), 0, s, n, nrhs, G, ldg, R, ldr);
-  hipError_t e = launch_dgemm(n, nrhs, n, A, lda, OpA::GeneralT, L, ldl, OpB::General, R, ldr,
-                              Acc::Subtract, s);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_colmax, dim3(unsigned(nrhs)), dim3(kRows), 0, s, n, R, ldr, L, ldl, G, ldg,
                      colstat);
   hipLaunchKernelGGL(k_berr_final, dim3(1), dim3(64), 0, s, nrhs, colstat, anorm, berr);

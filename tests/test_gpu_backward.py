@@ -94,8 +94,10 @@ def test_autograd_finite_differences(rbt):
     h = 1e-6 * np.abs(A).max()
     rng = np.random.default_rng(0)
 
+    # The difference quotient's noise is the solve error of L over 2h, so the
+    # reference solves are refined to the FP64 limit, not just to 10 n eps.
     def loss(Am, Bm):
-        X, _, _, _, _, _ = rbt.solve_refine(dev(Am), dev(Bm), 2, 2023)
+        X, _, _, _, _, _ = rbt.solve_refine(dev(Am), dev(Bm), 2, 2023, tol=0.0, max_iter=3)
         return float((host(X) * C).sum())
 
     for _ in range(8):
@@ -150,3 +152,25 @@ def test_autograd_mixed_finite_differences(rbt):
     Xe = np.linalg.solve(A, B)
     assert relmax(gB, lam) <= 1e-9
     assert relmax(gA, -lam @ Xe.T) <= 1e-9
+
+
+@pytest.mark.parametrize("n,k", [(777, 1), (700, 3), (1000, 8), (600, 16), (500, 20)])
+def test_adjoint_residual_backward_error(rbt, n, k):
+    """With no refinement the reported backward error is that of the FP32
+    adjoint solve (far above the rounding of its FP64 evaluation): it equals
+    Eq. 7 of the returned lambda for A^T lambda = G, computed on the host."""
+    A = workloads.randn_matrix(n, seed=n + 9)
+    B = workloads.randn(n, k, seed=1)
+    G = workloads.randn(n, k, seed=2)
+    X, LU32, _, _, _, _ = rbt.solve_mixed(dev(A), dev(B), 2, 2023, prec=rbt.RBT_FP32,
+                                          solver=rbt.RBT_IR_GMRES)
+    _, dB, iters, berr = rbt.solve_backward_mixed(LU32, dev(A), X, dev(G), 2, 2023, max_iter=0,
+                                                  need_dA=False)
+    assert int(iters.item()) == 0
+    lam = host(dB)
+    R = G - A.T @ lam
+    anorm = np.abs(A).sum(axis=0).max()  # ||A^T||_inf = ||A||_1
+    be = max(np.abs(R[:, c]).max() / (anorm * np.abs(lam[:, c]).max() + np.abs(G[:, c]).max())
+             for c in range(k))
+    assert be > 1e-12  # well above the FP64 rounding of the residual
+    assert abs(float(berr.item()) - be) <= 1e-6 * be
