@@ -332,6 +332,14 @@ int rbt_solve_backward_mixed(int64_t n, int64_t nrhs, const float *LU, int64_t l
  *   trailing GEMM's workgroups hold every CU's registers, so the panel
  *   kernels wait for its tiles to drain. */
 #define RBT_OPT_LOOKAHEAD 4
+/* RBT_OPT_BF16_STAGED: BF16 elimination (prec RBT_BF16), 1 (default): the
+ *   trailing update rounds L21 and U12 to BF16 once into the workspace's
+ *   staging area and runs the large-tile BF16 GEMM; 0: operands rounded
+ *   tile by tile. Identical results. The staging area is part of
+ *   rbt_workspace_size(..., RBT_BF16) at the panel width current when it is
+ *   called; a smaller workspace (e.g. sized for RBT_FP32) or a wider panel
+ *   selects the tile-by-tile path. */
+#define RBT_OPT_BF16_STAGED 5
 /* Returns 0, -1 for an unknown option, -2 for an invalid value. */
 int rbt_set_option(int option, int64_t value);
 /* Current value, or -1 for an unknown option. */

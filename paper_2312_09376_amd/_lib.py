@@ -58,6 +58,7 @@ RBT_OPT_OUTER_NB = 1
 RBT_OPT_BATCH_TILE_COLS = 2
 RBT_OPT_BATCH_WGS_PER_CU = 3
 RBT_OPT_LOOKAHEAD = 4
+RBT_OPT_BF16_STAGED = 5
 STAGES = ["generate", "transform2", "transform_vec", "diag", "panel", "trailing", "solve",
           "residual"]
 

@@ -66,12 +66,26 @@ namespace {
 
 inline int64_t nblocks(int64_t n) { return (n + kNB - 1) / kNB; }
 
+// Tunable options (rbt_set_option).
+struct Options {
+  int64_t outer_nb = 1024;  // width of the panel whose trailing update is one GEMM
+  int64_t batch_tile_cols = 1;  // batched: 64-column tiles per trailing-update round
+  int64_t batch_wgs_per_cu = 2; // batched: persistent workgroups per compute unit
+  int64_t lookahead = 0;        // elimination: overlap panels with the trailing update
+  int64_t bf16_staged = 1;      // BF16 elimination: staged-operand trailing GEMM
+};
+Options &options() {
+  static Options o;
+  return o;
+}
+
 // Workspace layout of the composite entry points. The inverses of the
 // diagonal blocks (for the few-right-hand-side solves) come first, so that
 // rbt_getrs and the composite entry points agree on where they live.
 struct Layout {
   size_t winv, sync, coef, resid, partial, krylov, small, total;
   size_t o_winv, o_sync, o_coef, o_resid, o_partial, o_krylov, o_small;
+  size_t hstage, o_hstage, total_staged;  // BF16: operand staging of the trailing update
 };
 
 // GMRES-IR: Krylov basis per restart cycle and the reduction of the
@@ -96,7 +110,7 @@ size_t krylov_doubles(int64_t n) {
 
 // mixed: the mixed-precision entry point (GMRES work area; residual scratch
 // also for one group of <= 16 columns).
-Layout layout(int64_t n, int64_t nrhs, int d, bool mixed = false) {
+Layout layout(int64_t n, int64_t nrhs, int d, bool mixed = false, bool bf16 = false) {
   Layout L{};
   L.winv = align256(size_t(diag_inv_doubles(n)) * sizeof(double));
   L.sync = align256(size_t(sweep_sync_ints(n)) * sizeof(int32_t));
@@ -118,6 +132,12 @@ Layout layout(int64_t n, int64_t nrhs, int d, bool mixed = false) {
   L.o_krylov = L.o_partial + L.partial;
   L.o_small = L.o_krylov + L.krylov;
   L.total = L.o_small + L.small;
+  // BF16 operands of the trailing update at the current panel width (an
+  // optional area after the others: without it the elimination rounds the
+  // operands tile by tile)
+  L.hstage = bf16 ? align256(hgemm_stage_bytes(n, n, options().outer_nb)) : 0;
+  L.o_hstage = L.total;
+  L.total_staged = L.total + L.hstage;
   return L;
 }
 
@@ -128,17 +148,6 @@ T *at(void *base, size_t off) {
 
 inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
-// Tunable options (rbt_set_option).
-struct Options {
-  int64_t outer_nb = 1024;  // width of the panel whose trailing update is one GEMM
-  int64_t batch_tile_cols = 1;  // batched: 64-column tiles per trailing-update round
-  int64_t batch_wgs_per_cu = 2; // batched: persistent workgroups per compute unit
-  int64_t lookahead = 0;        // elimination: overlap panels with the trailing update
-};
-Options &options() {
-  static Options o;
-  return o;
-}
 
 // GEMM C -= A B of the elimination: FP64 on the FP64 matrix cores, or FP32
 // storage with FP32 or BF16 operands (FP32 accumulation).
@@ -194,8 +203,25 @@ struct EventPair {
   }
 };
 
+// Trailing update A22 -= L21 U12: the staged BF16 GEMM when the operands
+// are BF16 and the staging area fits, else the tile-by-tile GEMMs.
+hipError_t trailing_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                        const double *B, int64_t ldb, double *C, int64_t ldc, int prec,
+                        hipStream_t st, void *, size_t) {
+  return gemm_sub(M, N, K, A, lda, B, ldb, C, ldc, prec, true, st);
+}
+hipError_t trailing_sub(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda,
+                        const float *B, int64_t ldb, float *C, int64_t ldc, int prec,
+                        hipStream_t st, void *stage, size_t stage_bytes) {
+  if (prec == RBT_BF16 && options().bf16_staged && stage != nullptr && hgemm_supported(K) &&
+      stage_bytes >= hgemm_stage_bytes(M, N, K))
+    return launch_hgemm_sub(M, N, K, A, lda, B, ldb, C, ldc, stage, stage_bytes, st);
+  return gemm_sub(M, N, K, A, lda, B, ldb, C, ldc, prec, true, st);
+}
+
 template <typename T>
-int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t s) {
+int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t s,
+              void *stage = nullptr, size_t stage_bytes = 0) {
   if (info) RBT_HIP_CHECK(launch_fill_i32(info, 0, s));
   const int64_t W = options().outer_nb;
   // ---- factor the panel A[k0:n, k0:k0+w] (on s) ----
@@ -244,8 +270,10 @@ int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t
     }
     const int64_t rows = n - k0 - w;
     StageScope t(kStageTrailing, st, 2.0 * double(rows) * nc * w);
-    RBT_HIP_CHECK(gemm_sub(rows, nc, w, A + (k0 + w) + k0 * lda, lda, A + k0 + c0 * lda, lda,
-                           A + (k0 + w) + c0 * lda, lda, prec, true, st));
+    // the staging area serves one update at a time: not the lookahead's
+    RBT_HIP_CHECK(trailing_sub(rows, nc, w, A + (k0 + w) + k0 * lda, lda, A + k0 + c0 * lda, lda,
+                               A + (k0 + w) + c0 * lda, lda, prec, st,
+                               st == s ? stage : nullptr, stage_bytes));
     return 0;
   };
   // Lookahead: after panel p, stream s updates only the next panel's columns
@@ -650,7 +678,7 @@ using namespace rbt;
 extern "C" size_t rbt_workspace_size(int64_t n, int64_t nrhs, int depth, int precision) {
   if (n < 0 || nrhs < 0 || bad_depth(depth)) return 0;
   if (precision != RBT_FP64 && precision != RBT_FP32 && precision != RBT_BF16) return 0;
-  return layout(n, nrhs, depth, precision != RBT_FP64).total;
+  return layout(n, nrhs, depth, precision != RBT_FP64, precision == RBT_BF16).total_staged;
 }
 
 extern "C" int rbt_generate_device(int64_t n, int depth, uint64_t seed, double *dU, double *dV,
@@ -859,8 +887,12 @@ int mixed_impl(int64_t n, int64_t nrhs, const double *A, int64_t lda, float *LU,
                int32_t *info_dev, void *work, size_t work_bytes, hipStream_t s, int *it_out,
                bool *stalled) {
   *it_out = 0;
-  const Layout L = layout(n, nrhs, depth, true);
+  const Layout L = layout(n, nrhs, depth, true, prec == RBT_BF16);
   if (work_bytes < L.total) return RBT_ERR_WORKSPACE;
+  // the BF16 operand staging area, when the caller's workspace holds it
+  void *stage = (L.hstage > 0 && work_bytes >= L.total_staged) ? at<char>(work, L.o_hstage)
+                                                                : nullptr;
+  const size_t stage_bytes = stage ? L.hstage : 0;
   double *small = at<double>(work, L.o_small);
   double *berr = berr_dev ? berr_dev : small + 1;
   if (n == 0 || nrhs == 0) {
@@ -870,7 +902,7 @@ int mixed_impl(int64_t n, int64_t nrhs, const double *A, int64_t lda, float *LU,
       double *U = at<double>(work, L.o_coef);
       RBT_HIP_CHECK(generate_t(n, depth, seed, U, U + n * depth, s));
       RBT_HIP_CHECK(transform2_t(g, A, lda, LU, ldlu, RBT_FP32, U, U + n * depth, s));
-      return genp_impl(n, LU, ldlu, info_dev, prec, s);
+      return genp_impl(n, LU, ldlu, info_dev, prec, s, stage, stage_bytes);
     }
     if (info_dev) RBT_HIP_CHECK(launch_fill_i32(info_dev, 0, s));
     return 0;
@@ -885,7 +917,7 @@ int mixed_impl(int64_t n, int64_t nrhs, const double *A, int64_t lda, float *LU,
 
   RBT_HIP_CHECK(generate_t(n, depth, seed, U, V, s));
   RBT_HIP_CHECK(transform2_t(g, A, lda, LU, ldlu, RBT_FP32, U, V, s));
-  int rc = genp_impl(n, LU, ldlu, info_dev, prec, s);
+  int rc = genp_impl(n, LU, ldlu, info_dev, prec, s, stage, stage_bytes);
   if (rc) return rc;
   rc = diag_inverses_t(n, LU, ldlu, winv, s);
   if (rc) return rc;
@@ -1271,6 +1303,10 @@ extern "C" int rbt_set_option(int option, int64_t value) {
       if (value != 0 && value != 1) return -2;
       options().lookahead = value;
       return 0;
+    case RBT_OPT_BF16_STAGED:
+      if (value != 0 && value != 1) return -2;
+      options().bf16_staged = value;
+      return 0;
     default:
       return -1;
   }
@@ -1282,6 +1318,7 @@ extern "C" int64_t rbt_get_option(int option) {
     case RBT_OPT_BATCH_TILE_COLS: return options().batch_tile_cols;
     case RBT_OPT_BATCH_WGS_PER_CU: return options().batch_wgs_per_cu;
     case RBT_OPT_LOOKAHEAD: return options().lookahead;
+    case RBT_OPT_BF16_STAGED: return options().bf16_staged;
     default: return -1;
   }
 }

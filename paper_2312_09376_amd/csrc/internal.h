@@ -198,6 +198,14 @@ struct BatchDesc {
   int64_t pad[2];
 };
 constexpr size_t kBatchTableOffset = 256;  // descriptors follow the header
+// BF16-operand trailing update with operands staged once (k_hgemm.hip):
+// C (FP32) -= bf16(L21) bf16(U12); K must be a multiple of 64.
+size_t hgemm_stage_bytes(int64_t M, int64_t N, int64_t K);
+bool hgemm_supported(int64_t K);
+hipError_t launch_hgemm_sub(int64_t M, int64_t N, int64_t K, const float *L21, int64_t ldl,
+                            const float *U12, int64_t ldu, float *C, int64_t ldc, void *stage,
+                            size_t stage_bytes, hipStream_t s);
+
 hipError_t launch_batched(int64_t batch, void *work, size_t work_bytes, const double *const *A,
                           const int64_t *lda, const double *const *B, const int64_t *ldb,
                           double *const *X, const int64_t *ldx, int depth, uint64_t seed,

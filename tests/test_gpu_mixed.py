@@ -255,3 +255,27 @@ def test_guarded_classic_stall_rule(rbt):
     if int(path.item()) == 1:
         assert its[0] < 200
     assert float(berr.item()) <= 10 * n * EPS
+
+
+@pytest.mark.parametrize("n,W", [(3000, 1024), (1003, 256), (700, 128), (2500, 512)])
+def test_bf16_staged_gemm_identical(rbt, n, W):
+    """The staged BF16 trailing GEMM (operands rounded once, 256 x 256
+    tiles) sums the same BF16 products in the same order as the
+    tile-by-tile path: the factors are bit-identical."""
+    A = workloads.dominant(n, seed=n + 2)
+    B = workloads.randn(n, 1, seed=1)
+    old_w = rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)
+    rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, W)
+    try:
+        out = {}
+        for staged in (0, 1):
+            rbt.set_option(rbt._lib.RBT_OPT_BF16_STAGED, staged)
+            X, LU, _, _, _, _ = rbt.solve_mixed(dev(A), dev(B), 2, 2023, prec=rbt.RBT_BF16,
+                                                max_iter=2)
+            torch.cuda.synchronize()
+            out[staged] = (host(LU), host(X))
+        assert np.array_equal(out[0][0], out[1][0])
+        assert np.array_equal(out[0][1], out[1][1])
+    finally:
+        rbt.set_option(rbt._lib.RBT_OPT_BF16_STAGED, 1)
+        rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, old_w)
