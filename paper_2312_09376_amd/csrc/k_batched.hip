@@ -477,13 +477,11 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
         const double p = prow[cc];
         if (lane == 0 && c < kb && p == 0.0 && *info_sh == 0) *info_sh = int(k + c + 1);
         const bool act = lane > c;
-        const double la = xa[cc] * (1.0 / p);  // one division per pivot
+        // one division per pivot; rows above it take a zero multiplier
+        const double la = act ? xa[cc] * (1.0 / p) : 0.0;
         xa[cc] = act ? la : xa[cc];
 #pragma unroll
-        for (int j = cc + 1; j < 16; ++j) {
-          const double u = xa[j] - la * prow[j];
-          xa[j] = act ? u : xa[j];
-        }
+        for (int j = cc + 1; j < 16; ++j) xa[j] -= la * prow[j];
       }
 #pragma unroll
       for (int j = 0; j < 16; ++j)

@@ -5,10 +5,10 @@
 // held in LDS (column-major, leading dimension 129 so that row-wise and
 // column-wise lane patterns are both bank-conflict free) and eliminated in
 // eight 16-column steps:
-//   1. the 16-column panel is factored right-looking, rank-1, by wavefront 0
-//      alone: lane l holds rows l and l + 64 of the panel in registers and
-//      each pivot row is broadcast with readlane, so the 16 steps need no
-//      workgroup barrier;
+//   1. the 16-column panel is factored right-looking, rank-1, by the four
+//      wavefronts, one row per lane; every wavefront keeps its own copy of
+//      the panel's top 16 rows, so each pivot row is broadcast within the
+//      wavefront with readlane and the 16 steps need no workgroup barrier;
 //   2. the 16-row block of U to its right is solved by forward substitution
 //      with the panel's unit-lower 16 x 16 block (one lane per column);
 //   3. the trailing block takes a rank-16 update on the FP64 matrix cores,
@@ -49,62 +49,58 @@ __global__ void __launch_bounds__(256) k_diag_lu(int kb, T *__restrict__ A, int6
   // batch costs one memory latency instead of one per element.
   {
     const int r = tid & (NB - 1), c0 = tid >> 7;  // row, first column (0/1)
+    // unconditional loads at clamped valid indices, all 64 in flight,
+    // masked afterwards
+    T v[64];
+    const int rr = r < kb ? r : kb - 1;
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      // unconditional loads at clamped valid indices, masked afterwards
-      T v[32];
-      const int rr = r < kb ? r : kb - 1;
+    for (int i = 0; i < 64; ++i) {
+      const int c = c0 + 2 * i;
+      v[i] = A[rr + int64_t(c < kb ? c : kb - 1) * lda];
+    }
 #pragma unroll
-      for (int i = 0; i < 32; ++i) {
-        const int c = c0 + 2 * (32 * half + i);
-        v[i] = A[rr + int64_t(c < kb ? c : kb - 1) * lda];
-      }
-#pragma unroll
-      for (int i = 0; i < 32; ++i) {
-        const int c = c0 + 2 * (32 * half + i);
-        S[c * LD + r] = (r < kb && c < kb) ? double(v[i]) : ((r == c) ? 1.0 : 0.0);
-      }
+    for (int i = 0; i < 64; ++i) {
+      const int c = c0 + 2 * i;
+      S[c * LD + r] = (r < kb && c < kb) ? double(v[i]) : ((r == c) ? 1.0 : 0.0);
     }
   }
   __syncthreads();
 
   for (int c0 = 0; c0 < kb; c0 += PW) {
-    // ---- 1. panel factorization (rows >= c0, columns c0..c0+15), wave 0 ----
-    if (wave == 0) {
-      double xa[PW], xb[PW];  // rows lane and lane + 64
+    // ---- 1. panel factorization (rows >= c0, columns c0..c0+15) by all
+    // four wavefronts: lanes 0..15 of every wavefront hold the panel's top
+    // 16 rows and update their own copy (the copies see identical
+    // operations), so each pivot row is broadcast within the wavefront with
+    // readlane and no barrier is needed; lanes 16..63 hold one row below
+    // them each (48 per wavefront). Rows above the pivot take a zero
+    // multiplier. ----
+    {
+      const bool top = lane < PW;
+      const int row = top ? c0 + lane : c0 + PW + wave * 48 + (lane - PW);
+      const bool valid = row < NB;
+      const int rr = valid ? row : NB - 1;
+      double x[PW];
 #pragma unroll
-      for (int j = 0; j < PW; ++j) {
-        xa[j] = S[(c0 + j) * LD + lane];
-        xb[j] = S[(c0 + j) * LD + lane + 64];
-      }
+      for (int j = 0; j < PW; ++j) x[j] = S[(c0 + j) * LD + rr];
 #pragma unroll
       for (int cc = 0; cc < PW; ++cc) {
         const int c = c0 + cc;
-        const int owner = c & 63;
-        const bool upper = c >= 64;
         double prow[PW];
 #pragma unroll
-        for (int j = cc; j < PW; ++j) prow[j] = wave_bcast(upper ? xb[j] : xa[j], owner);
+        for (int j = cc; j < PW; ++j) prow[j] = wave_bcast(x[j], cc);
         const double p = prow[cc];
-        if (lane == 0 && c < kb && p == 0.0 && info != nullptr)
+        if (wave == 0 && lane == 0 && c < kb && p == 0.0 && info != nullptr)
           atomicCAS(info, 0, int32_t(gofs + c + 1));
-        const bool acta = lane > c, actb = lane + 64 > c;
+        const bool act = top ? lane > cc : valid;
         const double rp = 1.0 / p;  // one division per pivot (scaling as in LAPACK's getf2)
-        const double la = xa[cc] * rp, lb = xb[cc] * rp;
-        xa[cc] = acta ? la : xa[cc];
-        xb[cc] = actb ? lb : xb[cc];
+        const double l = act ? x[cc] * rp : 0.0;
+        x[cc] = act ? l : x[cc];
 #pragma unroll
-        for (int j = cc + 1; j < PW; ++j) {
-          const double ua = xa[j] - la * prow[j];
-          const double ub = xb[j] - lb * prow[j];
-          xa[j] = acta ? ua : xa[j];
-          xb[j] = actb ? ub : xb[j];
-        }
+        for (int j = cc + 1; j < PW; ++j) x[j] -= l * prow[j];
       }
+      if ((top && wave == 0) || (!top && valid)) {
 #pragma unroll
-      for (int j = 0; j < PW; ++j) {
-        if (lane >= c0) S[(c0 + j) * LD + lane] = xa[j];
-        if (lane + 64 >= c0) S[(c0 + j) * LD + lane + 64] = xb[j];
+        for (int j = 0; j < PW; ++j) S[(c0 + j) * LD + row] = x[j];
       }
     }
     __syncthreads();
@@ -125,22 +121,40 @@ __global__ void __launch_bounds__(256) k_diag_lu(int kb, T *__restrict__ A, int6
       for (int i = 0; i < PW; ++i) S[col * LD + c0 + i] = y[i];
     }
     __syncthreads();
-    // ---- 3. trailing rank-16 update on 16 x 16 tiles ----
+    // ---- 3. trailing rank-16 update on 16 x 16 tiles, two per wavefront
+    // at a time (tiles t and t + 4), so their LDS loads overlap ----
     const int nt = (NB - c1) / PW;
-    for (int t = wave; t < nt * nt; t += 4) {
+    const int ntt = nt * nt;
+    for (int t = wave; t < ntt; t += 8) {
+      const bool two = t + 4 < ntt;
+      const int tb = two ? t + 4 : t;
       const int i0 = c1 + PW * (t % nt), j0 = c1 + PW * (t / nt);
-      d4 acc;
+      const int i1 = c1 + PW * (tb % nt), j1 = c1 + PW * (tb / nt);
+      d4 acc0, acc1;
+      double a0[4], b0[4], a1[4], b1[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[v] = S[(j0 + l16) * LD + i0 + lk + 4 * v];
+      for (int v = 0; v < 4; ++v) {
+        acc0[v] = S[(j0 + l16) * LD + i0 + lk + 4 * v];
+        acc1[v] = S[(j1 + l16) * LD + i1 + lk + 4 * v];
+      }
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int k = c0 + 4 * kk + lk;
-        const double a = -S[k * LD + i0 + l16];
-        const double bv = S[(j0 + l16) * LD + k];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+        a0[kk] = -S[k * LD + i0 + l16];
+        b0[kk] = S[(j0 + l16) * LD + k];
+        a1[kk] = -S[k * LD + i1 + l16];
+        b1[kk] = S[(j1 + l16) * LD + k];
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) S[(j0 + l16) * LD + i0 + lk + 4 * v] = acc[v];
+      for (int kk = 0; kk < 4; ++kk) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[kk], b0[kk], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[kk], b1[kk], acc1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        S[(j0 + l16) * LD + i0 + lk + 4 * v] = acc0[v];
+        if (two) S[(j1 + l16) * LD + i1 + lk + 4 * v] = acc1[v];
+      }
     }
     __syncthreads();
   }

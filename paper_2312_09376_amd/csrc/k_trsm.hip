@@ -10,7 +10,8 @@
 //
 // LDS holds the right-hand-side strips and the eight 16 x 16 diagonal blocks
 // (80 KB, two workgroups per CU); the off-diagonal operands of each step are
-// prefetched from global memory into registers before its MFMA chain.
+// loaded from global memory into registers while the previous step's
+// barrier and substitution run.
 //
 // Left solves, op(T) X = B in place (B: kb x N):
 //   LN  T = L (unit lower)     forward  (panel U12 = L11^-1 A12, L y = b)
@@ -127,11 +128,12 @@ __global__ void __launch_bounds__(256, 2) k_trsm_left(int kb, int64_t N, const T
   __syncthreads();
 
   const int nbk = (kb + IB - 1) / IB;
-  for (int step = 0; step < nbk; ++step) {
-    const int I = FWD ? step : nbk - 1 - step;
-    const int ia = IB * I + l16;
-    // prefetch this step's off-diagonal operands: op(T)[ia][16 J + 4 kk + lk]
-    TT araw[NBK - 1][4];
+  // off-diagonal operands of a step, op(T)[16 I + l16][16 J + 4 kk + lk];
+  // those of step + 1 are loaded once the MFMAs of step have consumed these,
+  // so the loads are in flight during the barrier and the substitution
+  TT araw[NBK - 1][4];
+  auto load_step = [&](int st) {
+    const int ia = IB * (FWD ? st : nbk - 1 - st) + l16;
 #pragma unroll
     for (int s2 = 0; s2 < NBK - 1; ++s2) {
       const int J = FWD ? s2 : nbk - 1 - s2;
@@ -141,6 +143,11 @@ __global__ void __launch_bounds__(256, 2) k_trsm_left(int kb, int64_t N, const T
         araw[s2][kk] = op_t<MODE>(T, ldt, clampi(ia, kb - 1), clampi(kx < 0 ? 0 : kx, kb - 1));
       }
     }
+  };
+  load_step(0);
+  for (int step = 0; step < nbk; ++step) {
+    const int I = FWD ? step : nbk - 1 - step;
+    const int ia = IB * I + l16;
     double a[NBK - 1][4];
 #pragma unroll
     for (int s2 = 0; s2 < NBK - 1; ++s2) {
@@ -165,6 +172,7 @@ __global__ void __launch_bounds__(256, 2) k_trsm_left(int kb, int64_t N, const T
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) strip[(IB * I + lk + 4 * v) * IB + l16] -= acc0[v] + acc1[v];
+    if (step + 1 < nbk) load_step(step + 1);
     __syncthreads();
     // substitution inside the diagonal block: lane c < 16 owns column c
     const int bs = kb - IB * I < IB ? kb - IB * I : IB;
@@ -256,15 +264,21 @@ __global__ void __launch_bounds__(256, 2) k_trsm_right_upper(int kb, int64_t M, 
   __syncthreads();
 
   const int nbk = (kb + IB - 1) / IB;
-  for (int J = 0; J < nbk; ++J) {
-    const int jc = IB * J + l16;  // column of U this lane feeds
-    TT braw[NBK - 1][4];
+  // off-diagonal operands of step J, U[16 I + 4 kk + lk][16 J + l16]; those
+  // of J + 1 are loaded once the MFMAs of J have consumed these
+  TT braw[NBK - 1][4];
+  auto load_step = [&](int st) {
+    const int jc = IB * st + l16;
 #pragma unroll
     for (int I = 0; I < NBK - 1; ++I) {
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk)
         braw[I][kk] = T[clampi(IB * I + 4 * kk + lk, kb - 1) + int64_t(clampi(jc, kb - 1)) * ldt];
     }
+  };
+  load_step(0);
+  for (int J = 0; J < nbk; ++J) {
+    const int jc = IB * J + l16;  // column of U this lane feeds
     double b[NBK - 1][4];
 #pragma unroll
     for (int I = 0; I < NBK - 1; ++I) {
@@ -287,6 +301,7 @@ __global__ void __launch_bounds__(256, 2) k_trsm_right_upper(int kb, int64_t M, 
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) strip[(IB * J + l16) * IB + lk + 4 * v] -= acc0[v] + acc1[v];
+    if (J + 1 < nbk) load_step(J + 1);
     __syncthreads();
     // substitution inside the diagonal block: lane r < 16 owns row r
     const int bs = kb - IB * J < IB ? kb - IB * J : IB;
