@@ -45,6 +45,24 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
+// Global-memory pointers: the phase functions below are not inlined and
+// reach the factor storage through Sys, so the compiler cannot tell that it
+// is global memory and would use FLAT instructions, which also count against
+// the LDS counter (every wait for LDS data in the MFMA loop would then wait
+// for the prefetched global loads). The pipelined trailing update therefore
+// casts its pointers to the global address space explicitly.
+#define RBT_AS_GLOBAL __attribute__((address_space(1)))
+typedef float RBT_AS_GLOBAL gfloat;
+__device__ __forceinline__ f4u ld4(const float *p) { return *reinterpret_cast<const f4u *>(p); }
+__device__ __forceinline__ f4u ld4(const gfloat *p) {
+  return *reinterpret_cast<const f4u RBT_AS_GLOBAL *>(p);
+}
+__device__ __forceinline__ void st4(float *p, f4u v) { *reinterpret_cast<f4u *>(p) = v; }
+__device__ __forceinline__ void st4(gfloat *p, f4u v) {
+  *reinterpret_cast<f4u RBT_AS_GLOBAL *>(p) = v;
+}
+
+
 // LDS: region 0 (the diagonal block S, or the GEMM tiles, or the residual
 // buffers) and region 1 (the inverses T, kept through the panel products of
 // a step); the sweeps use both regions.
@@ -152,8 +170,8 @@ __device__ __forceinline__ void tile_mma(const void *sa, const void *sb, f4 (&ac
 // source whose element (r, k) is src[r + k * ld] (rmode: r runs down a
 // column) or src[k + r * ld] (kmode: k runs down a column). Entries with
 // r >= rv or k >= kv are zero.
-template <bool BF16, bool KMODE>
-__device__ __forceinline__ void stage(void *dst, const float *src, int64_t ld, int rv, int kv) {
+template <bool BF16, bool KMODE, typename PF>
+__device__ __forceinline__ void stage(void *dst, PF src, int64_t ld, int rv, int kv) {
   const int tid = threadIdx.x;
   // thread: column c = tid / 4 of the source, 16 consecutive entries
   const int col = tid >> 2, seg = (tid & 3) * 16;
@@ -161,11 +179,11 @@ __device__ __forceinline__ void stage(void *dst, const float *src, int64_t ld, i
   if (KMODE) {
     // source column = operand row r = col; entries k = seg..seg+15
     const bool full = col < rv && seg + 16 <= kv;
-    const float *p = src + seg + int64_t(col) * ld;
+    const PF p = src + seg + int64_t(col) * ld;
     if (full) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const f4u t = *reinterpret_cast<const f4u *>(p + 4 * q);
+        const f4u t = ld4(p + 4 * q);
         v[4 * q] = t[0]; v[4 * q + 1] = t[1]; v[4 * q + 2] = t[2]; v[4 * q + 3] = t[3];
       }
     } else {
@@ -184,11 +202,11 @@ __device__ __forceinline__ void stage(void *dst, const float *src, int64_t ld, i
   } else {
     // source column = operand k = col; entries r = seg..seg+15
     const bool full = col < kv && seg + 16 <= rv;
-    const float *p = src + seg + int64_t(col) * ld;
+    const PF p = src + seg + int64_t(col) * ld;
     if (full) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const f4u t = *reinterpret_cast<const f4u *>(p + 4 * q);
+        const f4u t = ld4(p + 4 * q);
         v[4 * q] = t[0]; v[4 * q + 1] = t[1]; v[4 * q + 2] = t[2]; v[4 * q + 3] = t[3];
       }
     } else {
@@ -240,15 +258,15 @@ __device__ __forceinline__ void tile_store(const f4 (&acc)[2][2], float *C, int6
 // matrix cores work on the current tile.
 // U12 tile (kv x cv, element (kx, nx) at src[kx + nx * ld]): thread holds
 // operand row nx = tid / 4, entries kx = 16 (tid % 4) + 0..15 (zero outside).
-__device__ __forceinline__ void load_bt(float (&v)[16], const float *src, int64_t ld, int cv,
-                                        int kv) {
+template <typename PF>
+__device__ __forceinline__ void load_bt(float (&v)[16], PF src, int64_t ld, int cv, int kv) {
   const int tid = threadIdx.x;
   const int col = tid >> 2, seg = (tid & 3) * 16;
-  const float *p = src + seg + int64_t(col) * ld;
+  const PF p = src + seg + int64_t(col) * ld;
   if (col < cv && seg + 16 <= kv) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const f4u t = *reinterpret_cast<const f4u *>(p + 4 * q);
+      const f4u t = ld4(p + 4 * q);
       v[4 * q] = t[0]; v[4 * q + 1] = t[1]; v[4 * q + 2] = t[2]; v[4 * q + 3] = t[3];
     }
   } else {
@@ -279,8 +297,8 @@ __device__ __forceinline__ void store_bt(void *dst, const float (&v)[16]) {
 // tile_mma: (i, j, v) is row wm*32 + 16 i + 4 (lane/16) + v, column
 // wn*32 + 16 j + lane%16. Entries outside the tile read as zero and are not
 // written.
-__device__ __forceinline__ void load_ct(f4 (&c)[2][2], const float *C, int64_t ld, int rv,
-                                        int cv) {
+template <typename PF>
+__device__ __forceinline__ void load_ct(f4 (&c)[2][2], PF C, int64_t ld, int rv, int cv) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int l16 = lane & 15, lk = lane >> 4;
@@ -290,9 +308,9 @@ __device__ __forceinline__ void load_ct(f4 (&c)[2][2], const float *C, int64_t l
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int row = wm * 32 + 16 * i + 4 * lk, col = wn * 32 + 16 * j + l16;
-      const float *p = C + row + int64_t(col) * ld;
+      const PF p = C + row + int64_t(col) * ld;
       if (full) {
-        const f4u t = *reinterpret_cast<const f4u *>(p);
+        const f4u t = ld4(p);
         c[i][j] = f4{t[0], t[1], t[2], t[3]};
       } else {
 #pragma unroll
@@ -300,8 +318,8 @@ __device__ __forceinline__ void load_ct(f4 (&c)[2][2], const float *C, int64_t l
       }
     }
 }
-__device__ __forceinline__ void store_ct(const f4 (&c)[2][2], float *C, int64_t ld, int rv,
-                                         int cv) {
+template <typename PF>
+__device__ __forceinline__ void store_ct(const f4 (&c)[2][2], PF C, int64_t ld, int rv, int cv) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int l16 = lane & 15, lk = lane >> 4;
@@ -311,9 +329,9 @@ __device__ __forceinline__ void store_ct(const f4 (&c)[2][2], float *C, int64_t 
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int row = wm * 32 + 16 * i + 4 * lk, col = wn * 32 + 16 * j + l16;
-      float *p = C + row + int64_t(col) * ld;
+      const PF p = C + row + int64_t(col) * ld;
       if (full) {
-        *reinterpret_cast<f4u *>(p) = f4u{c[i][j][0], c[i][j][1], c[i][j][2], c[i][j][3]};
+        st4(p, f4u{c[i][j][0], c[i][j][1], c[i][j][2], c[i][j][3]});
       } else if (col < cv) {
 #pragma unroll
         for (int v = 0; v < 4; ++v)
@@ -595,15 +613,16 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
       // low precision: CT column tiles per round (the second U12 tile in
       // region 1, free after the panel products); the next round's U12 and
       // C tiles are loaded into registers while the matrix cores work
+      gfloat *Fg = (gfloat *)F;
       void *bdst[CT];
       bdst[0] = BF16U ? static_cast<void *>(Bh) : static_cast<void *>(Bs);
       if constexpr (CT > 1) bdst[1] = static_cast<void *>(L1);
       for (int64_t r0 = k + kb; r0 < n; r0 += BB) {
         const int rv = int(n - r0 < BB ? n - r0 : BB);
         if constexpr (BF16U)
-          stage<true, false>(Ah, F + r0 + k * n, n, rv, kb);
+          stage<true, false>(Ah, Fg + r0 + k * n, n, rv, kb);
         else
-          stage<false, false>(As, F + r0 + k * n, n, rv, kb);
+          stage<false, false>(As, Fg + r0 + k * n, n, rv, kb);
         float bv[CT][16];
         f4 cn[CT][2][2];
         auto prefetch = [&](int64_t cbase) {
@@ -612,8 +631,8 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
             const int64_t c = cbase + int64_t(t) * BB;
             if (c < n) {
               const int cv = int(n - c < BB ? n - c : BB);
-              load_bt(bv[t], F + k + c * n, n, cv, kb);
-              load_ct(cn[t], F + r0 + c * n, n, rv, cv);
+              load_bt(bv[t], Fg + k + c * n, n, cv, kb);
+              load_ct(cn[t], Fg + r0 + c * n, n, rv, cv);
             }
           }
         };
@@ -643,7 +662,7 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
             for (int i = 0; i < 2; ++i)
 #pragma unroll
               for (int j = 0; j < 2; ++j) cc[t][i][j] -= acc[i][j];
-            store_ct(cc[t], F + r0 + c * n, n, rv, cv);
+            store_ct(cc[t], Fg + r0 + c * n, n, rv, cv);
           }
           __syncthreads();
         }
