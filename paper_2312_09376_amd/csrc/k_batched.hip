@@ -53,6 +53,12 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 // casts its pointers to the global address space explicitly.
 #define RBT_AS_GLOBAL __attribute__((address_space(1)))
 typedef float RBT_AS_GLOBAL gfloat;
+// The same for LDS pointers that reach a non-inlined function as
+// arguments: with the address space explicit, LDS accesses are plain ds
+// instructions on 32-bit addresses (no generic-to-LDS conversion per
+// access) and loads from valid LDS addresses can be issued unconditionally.
+#define RBT_AS_LDS __attribute__((address_space(3)))
+typedef double RBT_AS_LDS ldouble;
 __device__ __forceinline__ f4u ld4(const float *p) { return *reinterpret_cast<const f4u *>(p); }
 __device__ __forceinline__ f4u ld4(const gfloat *p) {
   return *reinterpret_cast<const f4u RBT_AS_GLOBAL *>(p);
@@ -461,8 +467,10 @@ __device__ __forceinline__ T *fmat(const Sys &s) {
 // T (LDS, FP64) <- L^-1 below the diagonal, U^-1 on and above; inverses
 // also to Inv (64 x 64, full, identity beyond kb); factors back to F.
 template <typename TF>
-__device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double *S, double *T,
+__device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double *S_in, double *T_in,
                                         double *Invb, int *info_sh) {
+  ldouble *S = (ldouble *)S_in;
+  ldouble *T = (ldouble *)T_in;
   TF *F = fmat<TF>(s);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   {
@@ -531,28 +539,61 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
     }
     __syncthreads();
   }
-  // inverses: wave 0 column j of L^-1 (rows > j), wave 1 column j of U^-1
+  // inverses, lane c of a wavefront owning column c (its own column of T,
+  // so no barriers): wave 0 L^-1 (strictly lower part of T), wave 1 U^-1
+  // (upper part with the diagonal). Rows are taken in a uniform order (L:
+  // top-down, U: bottom-up), so the factor entry of a step is one broadcast
+  // LDS read and the sum over the solved rows has a uniform range (masked
+  // per lane), unrolled into independent partial sums.
   if (wave == 0) {
-    const int j = lane;
-    for (int i = j + 1; i < BB; ++i) {
-      double a = -S[j * LDS_ + i];
-      for (int t = j + 1; t < i; ++t) a -= S[t * LDS_ + i] * T[j * LDS_ + t];
-      T[j * LDS_ + i] = a;
+    const int c = lane;
+    for (int i = 1; i < BB; ++i) {  // X[i][c] = -(L[i][c] + sum_{c<t<i} L[i][t] X[t][c]), i > c
+      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+      int t = 0;
+      for (; t + 4 <= i; t += 4) {
+        const double t0 = T[c * LDS_ + t + 0], t1 = T[c * LDS_ + t + 1];
+        const double t2 = T[c * LDS_ + t + 2], t3 = T[c * LDS_ + t + 3];
+        const double x0 = t + 0 > c ? t0 : (t + 0 == c ? 1.0 : 0.0);
+        const double x1 = t + 1 > c ? t1 : (t + 1 == c ? 1.0 : 0.0);
+        const double x2 = t + 2 > c ? t2 : (t + 2 == c ? 1.0 : 0.0);
+        const double x3 = t + 3 > c ? t3 : (t + 3 == c ? 1.0 : 0.0);
+        p0 += S[(t + 0) * LDS_ + i] * x0;
+        p1 += S[(t + 1) * LDS_ + i] * x1;
+        p2 += S[(t + 2) * LDS_ + i] * x2;
+        p3 += S[(t + 3) * LDS_ + i] * x3;
+      }
+      for (; t < i; ++t) {
+        const double tv = T[c * LDS_ + t];
+        const double x = t > c ? tv : (t == c ? 1.0 : 0.0);
+        p0 += S[t * LDS_ + i] * x;
+      }
+      if (i > c) T[c * LDS_ + i] = -((p0 + p1) + (p2 + p3));
     }
   } else if (wave == 1) {
-    const int j = lane;
-    const double xj = 1.0 / S[j * LDS_ + j];
-    T[j * LDS_ + j] = xj;
-    // reciprocal pivots in the unused padding row of T (one per column),
-    // read by the other lanes of this wavefront below
-    T[j * LDS_ + BB] = xj;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int i = j - 1; i >= 0; --i) {
-      double a = 0.0;
-      for (int t = i + 1; t <= j; ++t) a += S[t * LDS_ + i] * T[j * LDS_ + t];
-      T[j * LDS_ + i] = -a * T[i * LDS_ + BB];
+    const int c = lane;
+    T[c * LDS_ + c] = 1.0 / S[c * LDS_ + c];
+    for (int i = BB - 2; i >= 0; --i) {  // X[i][c] = -(sum_{i<t<=c} U[i][t] X[t][c]) / U[i][i], i < c
+      const double rd = 1.0 / S[i * LDS_ + i];
+      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+      int t = i + 1;
+      for (; t + 4 <= BB; t += 4) {
+        const double t0 = T[c * LDS_ + t + 0], t1 = T[c * LDS_ + t + 1];
+        const double t2 = T[c * LDS_ + t + 2], t3 = T[c * LDS_ + t + 3];
+        const double x0 = t + 0 <= c ? t0 : 0.0;
+        const double x1 = t + 1 <= c ? t1 : 0.0;
+        const double x2 = t + 2 <= c ? t2 : 0.0;
+        const double x3 = t + 3 <= c ? t3 : 0.0;
+        p0 += S[(t + 0) * LDS_ + i] * x0;
+        p1 += S[(t + 1) * LDS_ + i] * x1;
+        p2 += S[(t + 2) * LDS_ + i] * x2;
+        p3 += S[(t + 3) * LDS_ + i] * x3;
+      }
+      for (; t < BB; ++t) {
+        const double tv = T[c * LDS_ + t];
+        const double x = t <= c ? tv : 0.0;
+        p0 += S[t * LDS_ + i] * x;
+      }
+      if (i < c) T[c * LDS_ + i] = -((p0 + p1) + (p2 + p3)) * rd;
     }
   }
   __syncthreads();
