@@ -84,12 +84,13 @@ __device__ __forceinline__ float convert_out<float>(double x) { return float(x);
 
 // Two-sided pass on the block (row group at rb) x (column group at cb):
 // read once, all layers of the pass in registers, write once.
-template <int P, typename TO>
-__device__ __forceinline__ void transform2_block(const double *__restrict__ A, int64_t lda,
-                                                 TO *__restrict__ Out, int64_t ldo,
-                                                 const double *__restrict__ U,
-                                                 const double *__restrict__ V, const Pass &ps,
-                                                 int64_t rb, int64_t cb) {
+// (Pointer types are template parameters so that callers can pass pointers
+// qualified with the global address space.)
+template <int P, typename TO, typename PA, typename PO, typename PC>
+__device__ __forceinline__ void transform2_block(PA __restrict__ A, int64_t lda,
+                                                 PO __restrict__ Out, int64_t ldo,
+                                                 PC __restrict__ U, PC __restrict__ V,
+                                                 const Pass &ps, int64_t rb, int64_t cb) {
   constexpr int G = 1 << P;
   int64_t ri[G], ci[G];
   bool rv[G], cv[G];
@@ -157,9 +158,9 @@ __device__ __forceinline__ void transform2_block(const double *__restrict__ A, i
 
 // One-sided pass on column j of B for the group at rb. op T (U^T b):
 // layers hi..lo, mix then scale; op N (V x~): layers lo..hi, scale then mix.
-template <int P, int OP>
-__device__ __forceinline__ void transform_vec_block(double *__restrict__ B, int64_t ldb, int64_t j,
-                                                    const double *__restrict__ C, const Pass &ps,
+template <int P, int OP, typename PB, typename PC>
+__device__ __forceinline__ void transform_vec_block(PB __restrict__ B, int64_t ldb, int64_t j,
+                                                    PC __restrict__ C, const Pass &ps,
                                                     int64_t rb) {
   constexpr int G = 1 << P;
   int64_t ri[G];

@@ -754,14 +754,16 @@ __device__ __noinline__ void transform_vec_sys(const Sys &s, int d, double *Y, i
   const int64_t q = m >> d;
   const dev::Pass ps = dev::make_pass(s.n, q, d, 1, d);
   const int ng = int(ps.ngroups);
+  double RBT_AS_GLOBAL *Yg = (double RBT_AS_GLOBAL *)Y;
+  const double RBT_AS_GLOBAL *Cg = (const double RBT_AS_GLOBAL *)C;
   for (int e = threadIdx.x; e < ng * int(s.nrhs); e += BT) {
     const int gr = e % ng, j = e / ng;
     const int64_t rb = dev::group_base(ps, gr);
     if (rb >= s.n) continue;
     switch (d) {
-      case 1: dev::transform_vec_block<1, OP>(Y, ldy, j, C, ps, rb); break;
-      case 2: dev::transform_vec_block<2, OP>(Y, ldy, j, C, ps, rb); break;
-      default: dev::transform_vec_block<3, OP>(Y, ldy, j, C, ps, rb); break;
+      case 1: dev::transform_vec_block<1, OP>(Yg, ldy, j, Cg, ps, rb); break;
+      case 2: dev::transform_vec_block<2, OP>(Yg, ldy, j, Cg, ps, rb); break;
+      default: dev::transform_vec_block<3, OP>(Yg, ldy, j, Cg, ps, rb); break;
     }
   }
   __syncthreads();
@@ -778,14 +780,16 @@ __device__ __noinline__ void transform_vec_sys(const Sys &s, int d, double *Y, i
 // B[l / 16][l % 16]; output element (l, v) is row l / 16 + 4 v, column
 // l % 16. NRT: right-hand sides of the inverse product (>= N).
 template <bool LOWER, int NRT, typename TF>
-__device__ __noinline__ void sweep(const Sys &s, double *Y, int64_t ldy, double *L0) {
-  const TF *F = fmat<TF>(s);
+__device__ __noinline__ void sweep(const Sys &s, double *Y_in, int64_t ldy, double *L0) {
+  const TF RBT_AS_GLOBAL *F = (const TF RBT_AS_GLOBAL *)fmat<TF>(s);
+  double RBT_AS_GLOBAL *Y = (double RBT_AS_GLOBAL *)Y_in;
   const int64_t n = s.n;
   const int N = int(s.nrhs);
   const int tid = threadIdx.x, i = tid & 63, sg = tid >> 6;
   const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, lk = lane >> 4;
-  double(*part)[BB][NRT] = reinterpret_cast<double(*)[BB][NRT]>(L0);  // [4][64][NRT]
-  double(*xs)[NR] = reinterpret_cast<double(*)[NR]>(L0 + 4 * BB * NRT);  // [64][16]
+  ldouble *Ll = (ldouble *)L0;
+  double RBT_AS_LDS(*part)[BB][NRT] = reinterpret_cast<double RBT_AS_LDS(*)[BB][NRT]>(Ll);  // [4][64][NRT]
+  double RBT_AS_LDS(*xs)[NR] = reinterpret_cast<double RBT_AS_LDS(*)[NR]>(Ll + 4 * BB * NRT);  // [64][16]
   const int64_t nblk = (n + BB - 1) / BB;
   for (int64_t t = 0; t < nblk; ++t) {
     const int64_t b = LOWER ? t : nblk - 1 - t;
@@ -799,7 +803,7 @@ __device__ __noinline__ void sweep(const Sys &s, double *Y, int64_t ldy, double 
     }
     __syncthreads();
     // x_b = Dinv y_b
-    const double *Db = s.Inv + b * BB * BB;
+    const double RBT_AS_GLOBAL *Db = (const double RBT_AS_GLOBAL *)s.Inv + b * BB * BB;
     double dv[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) dv[q] = Db[i + (sg * 16 + q) * BB];
@@ -880,8 +884,13 @@ __device__ __noinline__ double residual(const Sys &s, double *L0, bool with_anor
   const int N = int(s.nrhs);
   const int tid = threadIdx.x;
   constexpr int KC = 256;  // columns of A per staged chunk of X
-  double(*xs)[NRT] = reinterpret_cast<double(*)[NRT]>(L0);  // [KC][NRT]
-  double *red = L0 + KC * NR;
+  ldouble *Ll = (ldouble *)L0;
+  double RBT_AS_LDS(*xs)[NRT] = reinterpret_cast<double RBT_AS_LDS(*)[NRT]>(Ll);  // [KC][NRT]
+  double *red = L0 + KC * NR;  // (wg_nanmax takes a plain pointer)
+  const double RBT_AS_GLOBAL *Ag = (const double RBT_AS_GLOBAL *)s.A;
+  const double RBT_AS_GLOBAL *Xg = (const double RBT_AS_GLOBAL *)s.Xm;
+  const double RBT_AS_GLOBAL *Bg = (const double RBT_AS_GLOBAL *)s.Bm;
+  double RBT_AS_GLOBAL *Rg = (double RBT_AS_GLOBAL *)s.R;
   double amax = 0.0;
   for (int64_t m0 = 0; m0 < n; m0 += BT) {
     const int64_t m = m0 + tid;
@@ -894,11 +903,11 @@ __device__ __noinline__ double residual(const Sys &s, double *L0, bool with_anor
       __syncthreads();
       for (int e = tid; e < KC * NRT; e += BT) {
         const int kx = e % KC, c = e / KC;  // consecutive threads: consecutive rows of X
-        xs[kx][c] = (kx < kc && c < N) ? s.Xm[(k0 + kx) + int64_t(c) * s.ldx] : 0.0;
+        xs[kx][c] = (kx < kc && c < N) ? Xg[(k0 + kx) + int64_t(c) * s.ldx] : 0.0;
       }
       __syncthreads();
       if (m < n) {
-        const double *Ap = s.A + m + k0 * s.lda;
+        const double RBT_AS_GLOBAL *Ap = Ag + m + k0 * s.lda;
         // batches of 32 loads in flight (kc is a multiple of 32 except at the end)
         int kx = 0;
 #pragma unroll 1
@@ -926,7 +935,7 @@ __device__ __noinline__ double residual(const Sys &s, double *L0, bool with_anor
       amax = nanmax(amax, asum);
 #pragma unroll
       for (int c = 0; c < NRT; ++c)
-        if (c < N) s.R[m + int64_t(c) * n] = s.Bm[m + int64_t(c) * s.ldb] - acc[c];
+        if (c < N) Rg[m + int64_t(c) * n] = Bg[m + int64_t(c) * s.ldb] - acc[c];
     }
   }
   __syncthreads();
@@ -940,9 +949,9 @@ __device__ __noinline__ double residual(const Sys &s, double *L0, bool with_anor
   for (int c = 0; c < N; ++c) {
     double rm = 0.0, xm = 0.0, bm = 0.0;
     for (int64_t m = tid; m < n; m += BT) {
-      rm = nanmax(rm, fabs(s.R[m + int64_t(c) * n]));
-      xm = nanmax(xm, fabs(s.Xm[m + int64_t(c) * s.ldx]));
-      bm = nanmax(bm, fabs(s.Bm[m + int64_t(c) * s.ldb]));
+      rm = nanmax(rm, fabs(Rg[m + int64_t(c) * n]));
+      xm = nanmax(xm, fabs(Xg[m + int64_t(c) * s.ldx]));
+      bm = nanmax(bm, fabs(Bg[m + int64_t(c) * s.ldb]));
     }
     const double r = wg_nanmax(rm, red);
     const double x = wg_nanmax(xm, red);
@@ -993,6 +1002,9 @@ __device__ void refine_system(const Sys &s, int d, double tol, int max_iter, dou
 
 // A~ = U^T A V into the FP32 (lowp) or FP64 factor storage.
 __device__ __noinline__ void transform_into(const Sys &s, int d, bool lowp) {
+  const double RBT_AS_GLOBAL *Ag = (const double RBT_AS_GLOBAL *)s.A;
+  const double RBT_AS_GLOBAL *Ug = (const double RBT_AS_GLOBAL *)s.U;
+  const double RBT_AS_GLOBAL *Vg = (const double RBT_AS_GLOBAL *)s.V;
   const int64_t n = s.n;
   const int64_t m = d > 0 ? ((((n - 1) >> d) + 1) << d) : n;
   const int64_t q = m >> d;
@@ -1003,17 +1015,17 @@ __device__ __noinline__ void transform_into(const Sys &s, int d, bool lowp) {
     if (rb >= n || cb >= n) continue;
     if (lowp) {
       switch (d) {
-        case 0: dev::transform2_block<0, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
-        case 1: dev::transform2_block<1, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
-        case 2: dev::transform2_block<2, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
-        default: dev::transform2_block<3, float>(s.A, s.lda, s.F, n, s.U, s.V, ps, rb, cb); break;
+        case 0: dev::transform2_block<0, float>(Ag, s.lda, (float RBT_AS_GLOBAL *)s.F, n, Ug, Vg, ps, rb, cb); break;
+        case 1: dev::transform2_block<1, float>(Ag, s.lda, (float RBT_AS_GLOBAL *)s.F, n, Ug, Vg, ps, rb, cb); break;
+        case 2: dev::transform2_block<2, float>(Ag, s.lda, (float RBT_AS_GLOBAL *)s.F, n, Ug, Vg, ps, rb, cb); break;
+        default: dev::transform2_block<3, float>(Ag, s.lda, (float RBT_AS_GLOBAL *)s.F, n, Ug, Vg, ps, rb, cb); break;
       }
     } else {
       switch (d) {
-        case 0: dev::transform2_block<0, double>(s.A, s.lda, s.F64, n, s.U, s.V, ps, rb, cb); break;
-        case 1: dev::transform2_block<1, double>(s.A, s.lda, s.F64, n, s.U, s.V, ps, rb, cb); break;
-        case 2: dev::transform2_block<2, double>(s.A, s.lda, s.F64, n, s.U, s.V, ps, rb, cb); break;
-        default: dev::transform2_block<3, double>(s.A, s.lda, s.F64, n, s.U, s.V, ps, rb, cb); break;
+        case 0: dev::transform2_block<0, double>(Ag, s.lda, (double RBT_AS_GLOBAL *)s.F64, n, Ug, Vg, ps, rb, cb); break;
+        case 1: dev::transform2_block<1, double>(Ag, s.lda, (double RBT_AS_GLOBAL *)s.F64, n, Ug, Vg, ps, rb, cb); break;
+        case 2: dev::transform2_block<2, double>(Ag, s.lda, (double RBT_AS_GLOBAL *)s.F64, n, Ug, Vg, ps, rb, cb); break;
+        default: dev::transform2_block<3, double>(Ag, s.lda, (double RBT_AS_GLOBAL *)s.F64, n, Ug, Vg, ps, rb, cb); break;
       }
     }
   }
