@@ -395,7 +395,7 @@ __device__ __forceinline__ void tile_store64(const d4 (&acc)[2][2], T *C, int64_
       for (int v = 0; v < 4; ++v) {
         const int row = wm * 32 + 16 * i + lk + 4 * v;
         if (row < rv) {
-          T *p = C + row + int64_t(col) * ld;
+          T RBT_AS_GLOBAL *p = (T RBT_AS_GLOBAL *)C + row + int64_t(col) * ld;
           if (SUB)
             *p = T(double(*p) - acc[i][j][v]);
           else
@@ -407,26 +407,29 @@ __device__ __forceinline__ void tile_store64(const d4 (&acc)[2][2], T *C, int64_
 
 // Stage a 64 x 64 block of F (FP32 or FP64, column-major, rows r0..,
 // cols c0..; rv x cv valid) in LDS as FP64 D[c * LDS_ + r] (zero outside).
+// (src is factor storage, D is LDS: both address spaces made explicit.)
 template <typename T>
-__device__ __forceinline__ void stage64(double *D, const T *src, int64_t ld, int rv, int cv) {
+__device__ __forceinline__ void stage64(double *D_in, const T *src_in, int64_t ld, int rv, int cv) {
+  ldouble *D = (ldouble *)D_in;
+  const T RBT_AS_GLOBAL *src = (const T RBT_AS_GLOBAL *)src_in;
   const int tid = threadIdx.x;
   const int col = tid >> 2, seg = (tid & 3) * 16;
   T v[16];
   if constexpr (sizeof(T) == 4) {
     if (col < cv && seg + 16 <= rv) {
-      const float *p = src + seg + int64_t(col) * ld;
+      const gfloat *p = src + seg + int64_t(col) * ld;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const f4u t = *reinterpret_cast<const f4u *>(p + 4 * q);
+        const f4u t = ld4(p + 4 * q);
         v[4 * q] = t[0]; v[4 * q + 1] = t[1]; v[4 * q + 2] = t[2]; v[4 * q + 3] = t[3];
       }
     } else {
-      const T *p = src + int64_t(col < cv ? col : 0) * ld;
+      const T RBT_AS_GLOBAL *p = src + int64_t(col < cv ? col : 0) * ld;
 #pragma unroll
       for (int e = 0; e < 16; ++e) v[e] = (col < cv && seg + e < rv) ? p[seg + e] : T(0);
     }
   } else {
-    const T *p = src + int64_t(col < cv ? col : 0) * ld;
+    const T RBT_AS_GLOBAL *p = src + int64_t(col < cv ? col : 0) * ld;
     const int rl = rv - 1;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -471,7 +474,8 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
                                         double *Invb, int *info_sh) {
   ldouble *S = (ldouble *)S_in;
   ldouble *T = (ldouble *)T_in;
-  TF *F = fmat<TF>(s);
+  TF RBT_AS_GLOBAL *F = (TF RBT_AS_GLOBAL *)fmat<TF>(s);
+  double RBT_AS_GLOBAL *Invg = (double RBT_AS_GLOBAL *)Invb;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   {
     const int r = tid & 63, cg = tid >> 6;
@@ -599,7 +603,7 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
   __syncthreads();
   for (int e = tid; e < BB * BB; e += BT) {
     const int r = e & 63, c = e >> 6;
-    Invb[r + c * BB] = T[c * LDS_ + r];
+    Invg[r + c * BB] = T[c * LDS_ + r];
     if (r < kb && c < kb) F[(k + r) + (k + c) * s.n] = TF(S[c * LDS_ + r]);
   }
   __syncthreads();
@@ -624,14 +628,15 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
     if (rest <= 0) break;
     f4 acc[2][2];
     d4 acc64[2][2];
-    const double *T = L1;  // L^-1 below the diagonal, U^-1 on and above (ld LDS_)
+    const ldouble *T = (const ldouble *)L1;  // L^-1 below the diagonal, U^-1 on and above (ld LDS_)
+    const ldouble *L0l = (const ldouble *)L0;
     // L21 = A21 U11^-1 (rows k+kb.., 64-row tiles), FP64 products
     for (int64_t r0 = k + kb; r0 < n; r0 += BB) {
       const int rv = int(n - r0 < BB ? n - r0 : BB);
       // stage A21 tile as [k][r]: element (r, kx) at L0[kx * LDS_ + r]
       stage64(L0, F + r0 + k * n, n, rv, kb);
       __syncthreads();
-      tile_mma64([&](int m, int kx) { return L0[kx * LDS_ + m]; },
+      tile_mma64([&](int m, int kx) { return L0l[kx * LDS_ + m]; },
                  [&](int kx, int nx) { return kx <= nx ? T[nx * LDS_ + kx] : 0.0; }, acc64);
       __syncthreads();
       tile_store64(acc64, F + r0 + k * n, n, rv, kb);
@@ -644,7 +649,7 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
       stage64(L0, F + k + c0 * n, n, kb, cv);
       __syncthreads();
       tile_mma64([&](int m, int kx) { return m > kx ? T[kx * LDS_ + m] : (m == kx ? 1.0 : 0.0); },
-                 [&](int kx, int nx) { return L0[nx * LDS_ + kx]; }, acc64);
+                 [&](int kx, int nx) { return L0l[nx * LDS_ + kx]; }, acc64);
       __syncthreads();
       tile_store64(acc64, F + k + c0 * n, n, kb, cv);
     }
@@ -970,8 +975,11 @@ template <int NRT, typename TF>
 __device__ void refine_system(const Sys &s, int d, double tol, int max_iter, double *L0,
                               double *anorm_sh, int *it_out, double *be_out) {
   const int64_t n = s.n;
+  double RBT_AS_GLOBAL *Xg = (double RBT_AS_GLOBAL *)s.Xm;
+  const double RBT_AS_GLOBAL *Bg = (const double RBT_AS_GLOBAL *)s.Bm;
+  const double RBT_AS_GLOBAL *Rg = (const double RBT_AS_GLOBAL *)s.R;
   for (int64_t e = threadIdx.x; e < n * s.nrhs; e += BT)
-    s.Xm[(e % n) + (e / n) * s.ldx] = s.Bm[(e % n) + (e / n) * s.ldb];
+    Xg[(e % n) + (e / n) * s.ldx] = Bg[(e % n) + (e / n) * s.ldb];
   __syncthreads();
   transform_vec_sys<RBT_OP_T>(s, d, s.Xm, s.ldx, s.U);
   sweep<true, NRT, TF>(s, s.Xm, s.ldx, L0);
@@ -992,7 +1000,7 @@ __device__ void refine_system(const Sys &s, int d, double tol, int max_iter, dou
     sweep<false, NRT, TF>(s, s.R, n, L0);
     transform_vec_sys<RBT_OP_N>(s, d, s.R, n, s.V);
     for (int64_t e = threadIdx.x; e < n * s.nrhs; e += BT)
-      s.Xm[(e % n) + (e / n) * s.ldx] += s.R[e];
+      Xg[(e % n) + (e / n) * s.ldx] += Rg[e];
     __syncthreads();
     ++it;
   }
