@@ -716,35 +716,70 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
       __syncthreads();
       continue;
     }
+    // FP64 factors (the fallback): the same pipeline with FP64 tiles; the
+    // L21 row tile stays in L0, the U12 tile goes through L1
+    double RBT_AS_GLOBAL *Fd = (double RBT_AS_GLOBAL *)F;
+    ldouble *L0d = (ldouble *)L0, *L1d = (ldouble *)L1;
+    const int tid = threadIdx.x;
+    const int bcol = tid >> 2, bseg = (tid & 3) * 16;  // U12 tile: column nx, rows kx
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1, l16 = lane & 15, lk = lane >> 4;
     for (int64_t r0 = k + kb; r0 < n; r0 += BB) {
       const int rv = int(n - r0 < BB ? n - r0 : BB);
-      if constexpr (sizeof(TF) == 8)
-        stage64(L0, F + r0 + k * n, n, rv, kb);   // (r, kx) at L0[kx * LDS_ + r]
-      else if constexpr (BF16U)
-        stage<true, false>(Ah, F + r0 + k * n, n, rv, kb);
-      else
-        stage<false, false>(As, F + r0 + k * n, n, rv, kb);
+      stage64(L0, F + r0 + k * n, n, rv, kb);  // (r, kx) at L0[kx * LDS_ + r]
+      double bv[16], cn[2][2][4];
+      auto prefetch = [&](int64_t c) {
+        const int cv = int(n - c < BB ? n - c : BB);
+        const double RBT_AS_GLOBAL *pb = Fd + k + (c + (bcol < cv ? bcol : 0)) * n;
+        const int rl = kb - 1;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const double x = pb[bseg + e < kb ? bseg + e : rl];
+          bv[e] = (bcol < cv && bseg + e < kb) ? x : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const int col = wn * 32 + 16 * j + l16;
+            const int cc = col < cv ? col : cv - 1;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = wm * 32 + 16 * i + lk + 4 * v;
+              const double x = Fd[(r0 + (row < rv ? row : rv - 1)) + (c + cc) * n];
+              cn[i][j][v] = (row < rv && col < cv) ? x : 0.0;
+            }
+          }
+      };
+      prefetch(k + kb);
       for (int64_t c0 = k + kb; c0 < n; c0 += BB) {
         const int cv = int(n - c0 < BB ? n - c0 : BB);
-        if constexpr (sizeof(TF) == 8)
-          stage64(L1, F + k + c0 * n, n, kb, cv);  // (kx, nx) at L1[nx * LDS_ + kx]
-        else if constexpr (BF16U)
-          stage<true, true>(Bh, F + k + c0 * n, n, cv, kb);
-        else
-          stage<false, true>(Bs, F + k + c0 * n, n, cv, kb);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) L1d[bcol * LDS_ + bseg + e] = bv[e];  // (kx, nx) at L1[nx * LDS_ + kx]
+        double cc[2][2][4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cc[i][j][v] = cn[i][j][v];
         __syncthreads();
-        if constexpr (sizeof(TF) == 8)
-          tile_mma64([&](int m, int kx) { return L0[kx * LDS_ + m]; },
-                     [&](int kx, int nx) { return L1[nx * LDS_ + kx]; }, acc64);
-        else if constexpr (BF16U)
-          tile_mma<true>(Ah, Bh, acc);
-        else
-          tile_mma<false>(As, Bs, acc);
+        if (c0 + BB < n) prefetch(c0 + BB);
+        tile_mma64([&](int m, int kx) { return L0d[kx * LDS_ + m]; },
+                   [&](int kx, int nx) { return L1d[nx * LDS_ + kx]; }, acc64);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const int col = wn * 32 + 16 * j + l16;
+            if (col >= cv) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = wm * 32 + 16 * i + lk + 4 * v;
+              if (row < rv) Fd[(r0 + row) + (c0 + col) * n] = cc[i][j][v] - acc64[i][j][v];
+            }
+          }
         __syncthreads();
-        if constexpr (sizeof(TF) == 8)
-          tile_store64<true>(acc64, F + r0 + c0 * n, n, rv, cv);
-        else
-          tile_store<true>(acc, F + r0 + c0 * n, n, rv, cv);
       }
     }
     __syncthreads();
