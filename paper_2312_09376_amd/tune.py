@@ -66,7 +66,7 @@ def _inputs(ns, ks, matrix):
     return As, Bs
 
 
-def time_candidates(prec, ns, ks, matrix="randn", reps=3, seed=2023, max_iter=30,
+def time_candidates(prec, ns, ks, matrix="randn", reps=3, seed=2023, max_iter=10,
                     candidates=CANDIDATES, log=print):
     """Time each candidate (graph replays of one launch over the batch) and
     check its outputs against the first candidate's. Returns the result
@@ -129,6 +129,7 @@ def main(argv=None):
     ap.add_argument("--prec", nargs="+", choices=PRECS, default=list(PRECS))
     ap.add_argument("--matrix", choices=["randn", "dominant"], default="randn")
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--max-iter", type=int, default=10, help="refinement cap (as the benchmark)")
     ap.add_argument("--out", default=TABLE)
     a = ap.parse_args(argv)
     if not torch.cuda.is_available():
@@ -136,10 +137,10 @@ def main(argv=None):
     ns, ks = workloads.batch_sizes(count=a.batch)
     table = {"device": torch.cuda.get_device_name(0),
              "workload": f"{a.batch} systems, n~U{{37..1500}}, nrhs~U{{1..16}} (seed 7), "
-                         f"A={a.matrix}, depth 2",
+                         f"A={a.matrix}, depth 2, max_iter {a.max_iter}",
              "batched": {}}
     for prec in a.prec:
-        res = time_candidates(prec, ns, ks, a.matrix, a.reps)
+        res = time_candidates(prec, ns, ks, a.matrix, a.reps, max_iter=a.max_iter)
         best = select(res)
         table["batched"][prec] = {"tile_cols": best["tile_cols"],
                                   "wgs_per_cu": best["wgs_per_cu"], "ms": round(best["ms"], 3),
