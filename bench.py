@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=10)
     ap.add_argument("--no-gepp", action="store_true", help="skip the GEPP comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-n", type=int, default=5120, help="oracle sample size (about 12 s of CPU work)")
+    ap.add_argument("--cpu-n", type=int, default=6144, help="oracle sample size (about 10-20 s of CPU work)")
     ap.add_argument("--lookahead", type=int, default=-1, help="0/1 (-1: library default)")
     ap.add_argument("--outer-nb", type=int, default=0,
                     help="panel width of the elimination (multiple of 128; 0 = library default)")
