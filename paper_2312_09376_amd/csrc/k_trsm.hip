@@ -1,17 +1,28 @@
 // Block triangular solves with a factored kb x kb diagonal block (kb <= 128)
 // of the elimination, 16 rows (columns) at a time: the update from the
 // blocks already solved runs on the FP64 matrix cores, and each 16 x 16
-// diagonal block is solved by plain substitution (one lane per right-hand
-// side), so the rounding behaviour is that of ordinary forward/back
-// substitution except that a division by a pivot is a multiplication by its
-// reciprocal (within one rounding of the quotient). (Multiplying by explicit
-// inverses of the diagonal blocks, even 16 x 16 ones, raised the backward
-// error several-fold on N(0,1) matrices with large growth.)
+// diagonal block is solved by plain substitution, so the rounding behaviour
+// is that of ordinary forward/back substitution except that a division by a
+// pivot is a multiplication by its reciprocal (within one rounding of the
+// quotient). (Multiplying by explicit inverses of the diagonal blocks, even
+// 16 x 16 ones, raised the backward error several-fold on N(0,1) matrices
+// with large growth.)
 //
-// LDS holds the right-hand-side strips and the eight 16 x 16 diagonal blocks
-// (80 KB, two workgroups per CU); the off-diagonal operands of each step are
-// loaded from global memory into registers while the previous step's
-// barrier and substitution run.
+// The kernels are latency-bound chains of eight dependent steps, so every
+// operand of the loop is staged in LDS once, with coalesced reads, before
+// the first step: the 28 off-diagonal 16 x 16 blocks of the triangle in
+// matrix-core operand order (56 KB), the eight diagonal blocks in the order
+// the substitution reads them (16 KB), and each wavefront's right-hand-side
+// strip (16 KB). After that a wavefront only talks to its own strip, so the
+// steps need no workgroup barrier (LDS accesses of one wavefront complete
+// in issue order). 136 KB of LDS: one workgroup per CU.
+//
+// Substitution inside a diagonal block: the 64 lanes hold 16 independent
+// right-hand sides x 4 lanes (a quad), lane q of a quad holding entries
+// q, q + 4, q + 8, q + 12. At pivot j the owner lane scales its entry and
+// a quad broadcast (DPP) hands it to the other three, which update their
+// entries. Every entry sees the same operations in the same order as in
+// one-lane-per-right-hand-side substitution.
 //
 // Left solves, op(T) X = B in place (B: kb x N):
 //   LN  T = L (unit lower)     forward  (panel U12 = L11^-1 A12, L y = b)
@@ -38,10 +49,12 @@ namespace rbt {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 constexpr int NB = kNB;  // 128
 constexpr int IB = 16;
 constexpr int NBK = NB / IB;  // 8 diagonal blocks
 constexpr int BLK = IB * IB;  // 256 doubles per block
+constexpr int NOFF = NBK * (NBK - 1) / 2;  // 28 off-diagonal blocks on one side
 
 template <TriMode MODE>
 constexpr bool forward_order() {
@@ -65,12 +78,78 @@ __device__ __forceinline__ TT op_t(const TT *T, int64_t ldt, int i, int j) {
 }
 __device__ __forceinline__ int clampi(int v, int hi) { return v < hi ? v : hi; }
 
+// Orders the LDS accesses of the lanes of one wavefront (no instruction).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// v of lane K of each quad, to all four lanes of the quad (DPP quad_perm)
+template <int K>
+__device__ __forceinline__ double quad_bcast_k(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(u)), K * 0x55, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(u >> 32)), K * 0x55, 0xF, 0xF, false);
+  return __builtin_bit_cast(double,
+                            (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32));
+}
+__device__ __forceinline__ double quad_bcast(double v, int k) {  // k: compile-time after unrolling
+  switch (k) {
+    case 0: return quad_bcast_k<0>(v);
+    case 1: return quad_bcast_k<1>(v);
+    case 2: return quad_bcast_k<2>(v);
+    default: return quad_bcast_k<3>(v);
+  }
+}
+
+// In-place substitution with one 16 x 16 diagonal block, quad layout: the
+// calling lane holds x[jj] = entry q + 4 jj of its right-hand side; tq[j * 16
+// + jj] is the coefficient of pivot j for entry q + 4 jj (reciprocal for
+// j's own entry; zero where unused); pivots j >= bs are skipped. FWD: entries
+// after the pivot are updated, else entries before it.
+template <bool FWD, bool UNIT>
+__device__ __forceinline__ void quad_substitute(double (&x)[4], const double *tq, int q, int bs) {
+  double tn[4];
+  const int j0 = FWD ? 0 : IB - 1;
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) tn[jj] = tq[j0 * IB + jj];
+#pragma unroll
+  for (int s = 0; s < IB; ++s) {
+    const int j = FWD ? s : IB - 1 - s;
+    const int jc = j >> 2, qc = j & 3;
+    double t[4];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) t[jj] = tn[jj];
+    if (s + 1 < IB) {  // next pivot's coefficients in flight during this one
+      const int jn = FWD ? j + 1 : j - 1;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) tn[jj] = tq[jn * IB + jj];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (j < bs) {
+      if constexpr (!UNIT) {
+        const double xs = x[jc] * t[jc];
+        x[jc] = q == qc ? xs : x[jc];
+      }
+      const double b = quad_bcast(x[jc], qc);
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        if (FWD ? (4 * jj + 3 <= j) : (4 * jj >= j)) continue;  // no entry of jj on that side
+        const double nx = __builtin_fma(-t[jj], b, x[jj]);
+        const bool all = FWD ? (4 * jj > j) : (4 * jj + 3 < j);
+        x[jj] = (all || (FWD ? q + 4 * jj > j : q + 4 * jj < j)) ? nx : x[jj];
+      }
+    }
+  }
+}
+
 // BATCH: blockIdx.y selects diagonal block b of an n x n factor (T and B
 // offset by b * kNB (1 + ldt) and b * bstride, kb = min(kNB, n - b kNB)), and
 // the right-hand side is the identity (X = op(T_bb)^-1): used to form the
 // inverses of the diagonal blocks once per factorization.
 template <TriMode MODE, bool BATCH, typename TT, typename TB>
-__global__ void __launch_bounds__(256, 2) k_trsm_left(int kb, int64_t N, const TT *T,
+__global__ void __launch_bounds__(256, 1) k_trsm_left(int kb, int64_t N, const TT *T,
                                                       int64_t ldt, TB *B, int64_t ldb,
                                                       int64_t n, int64_t bstride) {
   if constexpr (BATCH) {
@@ -81,16 +160,24 @@ __global__ void __launch_bounds__(256, 2) k_trsm_left(int kb, int64_t N, const T
     T += r0 + r0 * ldt;
     B += b * bstride;
   }
-  __shared__ double dblk[NBK * BLK];        // diagonal blocks of op(T), element (i,j) at j*16+i
+  // dblk: op(T)(i, j) of diagonal block b at b*256 + j*16 + (i%4)*4 + i/4
+  // (reciprocal on the diagonal of non-unit modes); ablk: off-diagonal block
+  // (I, J), J before I, at p*256 + lane*4 + kk = op(T)(16I + l16, 16J + 4kk +
+  // lk), p = I(I-1)/2 + J (forward) or J(J-1)/2 + I (backward)
+  __shared__ __attribute__((aligned(16))) double dblk[NBK * BLK];
+  __shared__ __attribute__((aligned(16))) double ablk[NOFF * BLK];
   __shared__ double strip_all[4][NB * IB];  // per wavefront: row-major 128 x 16
   constexpr bool FWD = forward_order<MODE>();
+  constexpr bool TRANS = MODE == TriMode::UT || MODE == TriMode::LT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
   double *strip = strip_all[wave];
   const int64_t col0 = int64_t(blockIdx.x) * 64 + wave * 16;
 
-  {  // stage the diagonal blocks (reciprocal on the diagonal of non-unit modes)
-    const int i = threadIdx.x % IB, j = threadIdx.x / IB;
+  {  // stage the diagonal blocks and the off-diagonal operands, coalesced:
+     // consecutive threads read consecutive addresses of the stored T
+    const int f = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int i = TRANS ? g : f, j = TRANS ? f : g;  // element (i, j) of a block of op(T)
     TT raw[NBK];
 #pragma unroll
     for (int b = 0; b < NBK; ++b)
@@ -100,8 +187,26 @@ __global__ void __launch_bounds__(256, 2) k_trsm_left(int kb, int64_t N, const T
       const int gi = IB * b + i, gj = IB * b + j;
       double v = (gi < kb && gj < kb) ? double(raw[b]) : (i == j ? 1.0 : 0.0);
       if (!unit_diag<MODE>() && i == j) v = 1.0 / v;
-      dblk[b * BLK + j * IB + i] = v;
+      dblk[b * BLK + j * IB + (i & 3) * 4 + (i >> 2)] = v;
     }
+    TT oraw[NOFF];
+#pragma unroll
+    for (int p = 0, I = 1; I < NBK; ++I)
+#pragma unroll
+      for (int J = 0; J < I; ++J, ++p) {
+        // forward: block (I, J) below the diagonal; backward: (J, I) above it
+        const int bi = FWD ? I : J, bj = FWD ? J : I;
+        oraw[p] = op_t<MODE>(T, ldt, clampi(IB * bi + i, kb - 1), clampi(IB * bj + j, kb - 1));
+      }
+    const int slot = (16 * (j & 3) + i) * 4 + (j >> 2);  // lane (lk = j%4, l16 = i), kk = j/4
+#pragma unroll
+    for (int p = 0, I = 1; I < NBK; ++I)
+#pragma unroll
+      for (int J = 0; J < I; ++J, ++p) {
+        const int bi = FWD ? I : J, bj = FWD ? J : I;
+        const int gi = IB * bi + i, gj = IB * bj + j;
+        ablk[p * BLK + slot] = (gi < kb && gj < kb) ? double(oraw[p]) : 0.0;
+      }
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {  // strip: lane = row (two halves), 16 columns
@@ -128,83 +233,37 @@ __global__ void __launch_bounds__(256, 2) k_trsm_left(int kb, int64_t N, const T
   __syncthreads();
 
   const int nbk = (kb + IB - 1) / IB;
-  // off-diagonal operands of a step, op(T)[16 I + l16][16 J + 4 kk + lk];
-  // those of step + 1 are loaded once the MFMAs of step have consumed these,
-  // so the loads are in flight during the barrier and the substitution
-  TT araw[NBK - 1][4];
-  auto load_step = [&](int st) {
-    const int ia = IB * (FWD ? st : nbk - 1 - st) + l16;
-#pragma unroll
-    for (int s2 = 0; s2 < NBK - 1; ++s2) {
-      const int J = FWD ? s2 : nbk - 1 - s2;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int kx = IB * J + 4 * kk + lk;
-        araw[s2][kk] = op_t<MODE>(T, ldt, clampi(ia, kb - 1), clampi(kx < 0 ? 0 : kx, kb - 1));
-      }
-    }
-  };
-  load_step(0);
+  const int cc = lane >> 2, q = lane & 3;  // substitution: right-hand side cc, entries q + 4 jj
   for (int step = 0; step < nbk; ++step) {
     const int I = FWD ? step : nbk - 1 - step;
-    const int ia = IB * I + l16;
-    double a[NBK - 1][4];
-#pragma unroll
-    for (int s2 = 0; s2 < NBK - 1; ++s2) {
-      const int J = FWD ? s2 : nbk - 1 - s2;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int kx = IB * J + 4 * kk + lk;
-        a[s2][kk] = (s2 < step && ia < kb && kx >= 0 && kx < kb) ? double(araw[s2][kk]) : 0.0;
-      }
-    }
     d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s2 = 0; s2 < NBK - 1; ++s2) {
       if (s2 < step) {
         const int J = FWD ? s2 : nbk - 1 - s2;
+        const int p = FWD ? I * (I - 1) / 2 + J : J * (J - 1) / 2 + I;
+        const d2 a01 = *reinterpret_cast<const d2 *>(ablk + p * BLK + lane * 4);
+        const d2 a23 = *reinterpret_cast<const d2 *>(ablk + p * BLK + lane * 4 + 2);
         const int k0 = IB * J + lk;
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2][0], strip[(k0) * IB + l16], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2][1], strip[(k0 + 4) * IB + l16], acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2][2], strip[(k0 + 8) * IB + l16], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2][3], strip[(k0 + 12) * IB + l16], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a01[0], strip[(k0) * IB + l16], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a01[1], strip[(k0 + 4) * IB + l16], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a23[0], strip[(k0 + 8) * IB + l16], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a23[1], strip[(k0 + 12) * IB + l16], acc1, 0, 0, 0);
       }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) strip[(IB * I + lk + 4 * v) * IB + l16] -= acc0[v] + acc1[v];
-    if (step + 1 < nbk) load_step(step + 1);
-    __syncthreads();
-    // substitution inside the diagonal block: lane c < 16 owns column c
+    wave_sync();
     const int bs = kb - IB * I < IB ? kb - IB * I : IB;
-    if (lane < IB) {
-      const int o = IB * I;
-      const double *tb = dblk + I * BLK;
-      double x[IB];
+    const int o = IB * I;
+    double x[4];
 #pragma unroll
-      for (int i = 0; i < IB; ++i) x[i] = strip[(o + i) * IB + lane];
-      if constexpr (FWD) {
+    for (int jj = 0; jj < 4; ++jj) x[jj] = strip[(o + q + 4 * jj) * IB + cc];
+    quad_substitute<FWD, unit_diag<MODE>()>(x, dblk + I * BLK + q * 4, q, bs);
 #pragma unroll
-        for (int j = 0; j < IB; ++j) {
-          if (j < bs) {
-            if constexpr (!unit_diag<MODE>()) x[j] *= tb[j * IB + j];
-#pragma unroll
-            for (int i = j + 1; i < IB; ++i) x[i] -= tb[j * IB + i] * x[j];
-          }
-        }
-      } else {
-#pragma unroll
-        for (int j = IB - 1; j >= 0; --j) {
-          if (j < bs) {
-            if constexpr (!unit_diag<MODE>()) x[j] *= tb[j * IB + j];
-#pragma unroll
-            for (int i = 0; i < j; ++i) x[i] -= tb[j * IB + i] * x[j];
-          }
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < IB; ++i) strip[(o + i) * IB + lane] = (i < bs) ? x[i] : 0.0;
-    }
-    __syncthreads();
+    for (int jj = 0; jj < 4; ++jj)
+      strip[(o + q + 4 * jj) * IB + cc] = (q + 4 * jj < bs) ? x[jj] : 0.0;
+    wave_sync();
   }
 
 #pragma unroll
@@ -219,17 +278,21 @@ __global__ void __launch_bounds__(256, 2) k_trsm_left(int kb, int64_t N, const T
 }
 
 template <typename TT>
-__global__ void __launch_bounds__(256, 2) k_trsm_right_upper(int kb, int64_t M, const TT *T,
+__global__ void __launch_bounds__(256, 1) k_trsm_right_upper(int kb, int64_t M, const TT *T,
                                                              int64_t ldt, TT *B,
                                                              int64_t ldb) {
-  __shared__ double dblk[NBK * BLK];        // diagonal blocks of U, element (r,c) at r*16+c
+  // dblk: U(r, c) of diagonal block b at b*256 + r*16 + (c%4)*4 + c/4
+  // (reciprocal on the diagonal); ublk: block (I, J), I < J, at p*256 +
+  // lane*4 + kk = U(16I + 4kk + lk, 16J + l16), p = J(J-1)/2 + I
+  __shared__ __attribute__((aligned(16))) double dblk[NBK * BLK];
+  __shared__ __attribute__((aligned(16))) double ublk[NOFF * BLK];
   __shared__ double strip_all[4][NB * IB];  // per wavefront: column-major 16 x 128
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
   double *strip = strip_all[wave];
   const int64_t row0 = int64_t(blockIdx.x) * 64 + wave * 16;
 
-  {
+  {  // stage the triangle, consecutive threads on consecutive rows of U
     const int r = threadIdx.x % IB, c = threadIdx.x / IB;
     TT raw[NBK];
 #pragma unroll
@@ -240,8 +303,22 @@ __global__ void __launch_bounds__(256, 2) k_trsm_right_upper(int kb, int64_t M, 
       const int gi = IB * b + r, gj = IB * b + c;
       double v = (gi < kb && gj < kb) ? double(raw[b]) : (r == c ? 1.0 : 0.0);
       if (r == c) v = 1.0 / v;
-      dblk[b * BLK + r * IB + c] = v;
+      dblk[b * BLK + r * IB + (c & 3) * 4 + (c >> 2)] = v;
     }
+    TT uraw[NOFF];
+#pragma unroll
+    for (int p = 0, J = 1; J < NBK; ++J)
+#pragma unroll
+      for (int I = 0; I < J; ++I, ++p)
+        uraw[p] = T[clampi(IB * I + r, kb - 1) + int64_t(clampi(IB * J + c, kb - 1)) * ldt];
+    const int slot = (16 * (r & 3) + c) * 4 + (r >> 2);  // lane (lk = r%4, l16 = c), kk = r/4
+#pragma unroll
+    for (int p = 0, J = 1; J < NBK; ++J)
+#pragma unroll
+      for (int I = 0; I < J; ++I, ++p) {
+        const int gi = IB * I + r, gj = IB * J + c;
+        ublk[p * BLK + slot] = (gi < kb && gj < kb) ? double(uraw[p]) : 0.0;
+      }
   }
   {
     // lane = (row r = lane % 16, column group lane / 16): columns cg + 4u
@@ -264,65 +341,35 @@ __global__ void __launch_bounds__(256, 2) k_trsm_right_upper(int kb, int64_t M, 
   __syncthreads();
 
   const int nbk = (kb + IB - 1) / IB;
-  // off-diagonal operands of step J, U[16 I + 4 kk + lk][16 J + l16]; those
-  // of J + 1 are loaded once the MFMAs of J have consumed these
-  TT braw[NBK - 1][4];
-  auto load_step = [&](int st) {
-    const int jc = IB * st + l16;
-#pragma unroll
-    for (int I = 0; I < NBK - 1; ++I) {
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-        braw[I][kk] = T[clampi(IB * I + 4 * kk + lk, kb - 1) + int64_t(clampi(jc, kb - 1)) * ldt];
-    }
-  };
-  load_step(0);
+  const int rq = lane >> 2, q = lane & 3;  // substitution: row rq, entries q + 4 jj
   for (int J = 0; J < nbk; ++J) {
-    const int jc = IB * J + l16;  // column of U this lane feeds
-    double b[NBK - 1][4];
-#pragma unroll
-    for (int I = 0; I < NBK - 1; ++I) {
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int kx = IB * I + 4 * kk + lk;
-        b[I][kk] = (I < J && kx < kb && jc < kb) ? double(braw[I][kk]) : 0.0;
-      }
-    }
     d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int I = 0; I < NBK - 1; ++I) {
       if (I < J) {
+        const int p = J * (J - 1) / 2 + I;
+        const d2 b01 = *reinterpret_cast<const d2 *>(ublk + p * BLK + lane * 4);
+        const d2 b23 = *reinterpret_cast<const d2 *>(ublk + p * BLK + lane * 4 + 2);
         const int k0 = IB * I + lk;
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0) * IB + l16], b[I][0], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 4) * IB + l16], b[I][1], acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 8) * IB + l16], b[I][2], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 12) * IB + l16], b[I][3], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0) * IB + l16], b01[0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 4) * IB + l16], b01[1], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 8) * IB + l16], b23[0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 12) * IB + l16], b23[1], acc1, 0, 0, 0);
       }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) strip[(IB * J + l16) * IB + lk + 4 * v] -= acc0[v] + acc1[v];
-    if (J + 1 < nbk) load_step(J + 1);
-    __syncthreads();
-    // substitution inside the diagonal block: lane r < 16 owns row r
+    wave_sync();
     const int bs = kb - IB * J < IB ? kb - IB * J : IB;
-    if (lane < IB) {
-      const int o = IB * J;
-      const double *tb = dblk + J * BLK;
-      double x[IB];
+    const int o = IB * J;
+    double x[4];
 #pragma unroll
-      for (int c = 0; c < IB; ++c) x[c] = strip[(o + c) * IB + lane];
+    for (int jj = 0; jj < 4; ++jj) x[jj] = strip[(o + q + 4 * jj) * IB + rq];
+    quad_substitute<true, false>(x, dblk + J * BLK + q * 4, q, bs);
 #pragma unroll
-      for (int c = 0; c < IB; ++c) {
-        if (c < bs) {
-          x[c] *= tb[c * IB + c];
-#pragma unroll
-          for (int c2 = c + 1; c2 < IB; ++c2) x[c2] -= x[c] * tb[c * IB + c2];
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < IB; ++c) strip[(o + c) * IB + lane] = (c < bs) ? x[c] : 0.0;
-    }
-    __syncthreads();
+    for (int jj = 0; jj < 4; ++jj)
+      strip[(o + q + 4 * jj) * IB + rq] = (q + 4 * jj < bs) ? x[jj] : 0.0;
+    wave_sync();
   }
 
   {
