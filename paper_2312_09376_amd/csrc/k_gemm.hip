@@ -213,16 +213,54 @@ __global__ void __launch_bounds__(256, 2)
     cur ^= 1;
   }
 
-  // epilogue: lane holds C[m0 + wm*64 + i*16 + l16][n0 + wn*64 + j*16 + lk + 4*v]
+  // epilogue: lane holds C[m0 + wm*64 + i*16 + l16][n0 + wn*64 + j*16 + lk + 4*v].
+  // Whole tiles load the C values of row block i + 1 before storing row
+  // block i, so 16 loads per lane are in flight at a time (the compiler
+  // cannot move a load of C above a store to C, which would otherwise cost
+  // one round trip per element); edge tiles take the element-wise path.
+  const int64_t r0 = m0 + wm * 64 + l16, c0 = n0 + wn * 64 + lk;
+  if (m0 + BM <= M && n0 + BN <= N) {
+    double *cp = C + r0 + c0 * ldc;
+    if constexpr (AC == Acc::Overwrite) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) cp[i * 16 + (j * 16 + 4 * v) * ldc] = acc[i][j][v];
+    } else {
+      double cv[2][16];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cv[0][4 * j + v] = cp[(j * 16 + 4 * v) * ldc];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (i + 1 < 4) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              cv[(i + 1) & 1][4 * j + v] = cp[(i + 1) * 16 + (j * 16 + 4 * v) * ldc];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            cp[i * 16 + (j * 16 + 4 * v) * ldc] = cv[i & 1][4 * j + v] - acc[i][j][v];
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int64_t row = m0 + wm * 64 + i * 16 + l16;
+    const int64_t row = r0 + i * 16;
     if (row >= M) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t col = n0 + wn * 64 + j * 16 + lk + 4 * v;
+        const int64_t col = c0 + j * 16 + 4 * v;
         if (col < N) {
           double *p = C + row + col * ldc;
           if constexpr (AC != Acc::Overwrite)

@@ -149,7 +149,34 @@ __global__ void __launch_bounds__(512, 1)
     cur ^= 1;
   }
 
-  // epilogue: acc[i][j][v] = (L21 U12)[m0 + wm*128 + 16 i + 4 lk + v][n0 + wn*64 + 16 j + l16]
+  // epilogue: acc[i][j][v] = (L21 U12)[m0 + wm*128 + 16 i + 4 lk + v][n0 + wn*64 + 16 j + l16].
+  // Whole tiles keep the loads of C two row blocks ahead of the stores (a
+  // load of C cannot be moved above a store to C by the compiler, which
+  // would otherwise cost one round trip per load); edge tiles go one by one.
+  if (m0 + HM <= M && n0 + HN <= N) {
+    float *cp = C + (m0 + wm * 128 + 4 * lk) + (n0 + wn * 64 + l16) * ldc;
+    f4u c[3][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) c[i][j] = *reinterpret_cast<const f4u *>(cp + 16 * i + 16 * j * ldc);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (i + 2 < 8) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          c[(i + 2) % 3][j] = *reinterpret_cast<const f4u *>(cp + 16 * (i + 2) + 16 * j * ldc);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        f4u r = c[i % 3][j];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) r[v] -= acc[i][j][v];
+        *reinterpret_cast<f4u *>(cp + 16 * i + 16 * j * ldc) = r;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int64_t row = m0 + wm * 128 + 16 * i + 4 * lk;

@@ -212,7 +212,28 @@ __global__ void __launch_bounds__(256, 2)
     cur ^= 1;
   }
 
-  // epilogue: acc[i][j][v] = (A B)[m0 + wm*64 + 16 i + 4 lk + v][n0 + wn*64 + 16 j + l16]
+  // epilogue: acc[i][j][v] = (A B)[m0 + wm*64 + 16 i + 4 lk + v][n0 + wn*64 + 16 j + l16].
+  // Whole tiles issue all 16 loads of C before the first store (a load of C
+  // cannot be moved above a store to C by the compiler, which would
+  // otherwise cost one round trip per load); edge tiles go element-wise.
+  if (m0 + BM <= M && n0 + BN <= N) {
+    float *cp = C + (m0 + wm * 64 + 4 * lk) + (n0 + wn * 64 + l16) * ldc;
+    f4u c[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        c[i][j] = *reinterpret_cast<const f4u *>(cp + 16 * i + 16 * j * ldc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) c[i][j][v] -= acc[i][j][v];
+        *reinterpret_cast<f4u *>(cp + 16 * i + 16 * j * ldc) = c[i][j];
+      }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t row = m0 + wm * 64 + 16 * i + 4 * lk;
