@@ -90,6 +90,11 @@ enum class Acc { Overwrite, Subtract, SubtractTrailing };
 hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, OpA opa,
                         const double *B, int64_t ldb, OpB opb, double *C, int64_t ldc, Acc acc,
                         hipStream_t s);
+// C -= A B (General operands) with 64 x 64 (tile = 64) or 128 x 128 block
+// tiles; the results are identical (tuning and tests).
+hipError_t launch_dgemm_tiles(int tile, int64_t M, int64_t N, int64_t K, const double *A,
+                              int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc,
+                              hipStream_t s);
 // k_sgemm.hip : C -= A B with FP32 storage; bf16: BF16 operands on the matrix
 // cores (FP32 accumulation), else FP32 operands. trailing: separate kernel
 // instance for the trailing update (same arithmetic).

@@ -8,7 +8,8 @@
 // Tiling: 256 threads = 4 wavefronts in a 2 x 2 grid, block tile 128 x 128,
 // wavefront tile 64 x 64 = 4 x 4 MFMA tiles of v_mfma_f64_16x16x4_f64,
 // K staged through LDS in slices of 16 with a register-prefetched double
-// buffer (one barrier per slice).
+// buffer (one barrier per slice). The depth-128 updates inside and beside
+// the panel use 64 x 64 block tiles instead (k_dgemm_small).
 //
 // Operand order: each MFMA computes a 16 x 16 tile of C^T (first operand a
 // B^T fragment, second an A^T fragment). The accumulator layout of the f64
@@ -273,6 +274,159 @@ __global__ void __launch_bounds__(256, 2)
   }
 }
 
+// Small tiles for the updates inside and beside the panel (C -= A B with
+// K = 128 and one dimension of at most 896): 64 x 64 block tiles, 4
+// wavefronts of 32 x 32 (2 x 2 MFMA tiles), K in slices of 16, 34 KB of LDS
+// so that four workgroups share a CU. A grid of 128 x 128 tiles leaves most
+// CUs idle or with one tile for these shapes; four times as many tiles of a
+// quarter of the work fill the chip and overlap one tile's prologue and
+// epilogue with the others' matrix-core work. Every output element
+// accumulates the same products in the same order as with the large tiles,
+// so the result is identical.
+constexpr int SM = 64, SN = 64, SK = 16;
+
+template <Acc AC>
+__global__ void __launch_bounds__(256, 4)
+    k_dgemm_small(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                  const double *B, int64_t ldb, double *C, int64_t ldc, int tiles_m, int total) {
+  __shared__ double As[2][SK][SM + PADA];
+  __shared__ double Bs[2][SN][SK + PADB];
+
+  int pid = blockIdx.x;
+  const int full = (total / 8) * 8;
+  if (pid < full) pid = (pid % 8) * (total / 8) + pid / 8;
+  const int tiles_n = total / tiles_m;
+  const int group = pid / (GM * tiles_n);
+  const int first_m = group * GM;
+  const int gsize = (tiles_m - first_m) < GM ? (tiles_m - first_m) : GM;
+  const int in_group = pid - group * GM * tiles_n;
+  const int tm = first_m + in_group % gsize, tn = in_group / gsize;
+  const int64_t m0 = int64_t(tm) * SM, n0 = int64_t(tn) * SN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+
+  d4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  // A slice (64 x 16): rows 2 (tid % 32) + {0,1}, columns tid / 32 + {0, 8};
+  // B slice (16 x 64): column tid / 4, rows 4 (tid % 4) + 0..3
+  double ra[4], rb[4];
+  const bool interior = (m0 + SM <= M) && (n0 + SN <= N);
+  auto load_stage = [&](int64_t k0) {
+    const int64_t ma = m0 + 2 * (tid & 31), ka = k0 + (tid >> 5);
+    const int64_t nb = n0 + (tid >> 2), kb = k0 + 4 * (tid & 3);
+    if (interior && k0 + SK <= K) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const d2u v = *reinterpret_cast<const d2u *>(A + ma + (ka + 8 * p) * lda);
+        ra[2 * p] = v[0];
+        ra[2 * p + 1] = v[1];
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const d2u v = *reinterpret_cast<const d2u *>(B + (kb + 2 * p) + nb * ldb);
+        rb[2 * p] = v[0];
+        rb[2 * p + 1] = v[1];
+      }
+      return;
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      ra[2 * p] = load_a<OpA::General>(A, lda, ma, ka + 8 * p, M, K);
+      ra[2 * p + 1] = load_a<OpA::General>(A, lda, ma + 1, ka + 8 * p, M, K);
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) rb[p] = load_b<OpB::General>(B, ldb, kb + p, nb, K, N);
+  };
+  auto store_stage = [&](int s) {
+    const int ma = 2 * (tid & 31), ka = tid >> 5;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      As[s][ka + 8 * p][ma] = ra[2 * p];
+      As[s][ka + 8 * p][ma + 1] = ra[2 * p + 1];
+    }
+    const int nb = tid >> 2, kb = 4 * (tid & 3);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) Bs[s][nb][kb + p] = rb[p];
+  };
+
+  load_stage(0);
+  store_stage(0);
+  __syncthreads();
+  int cur = 0;
+  for (int64_t k0 = 0; k0 < K; k0 += SK) {
+    const bool has_next = k0 + SK < K;
+    if (has_next) load_stage(k0 + SK);
+#pragma unroll
+    for (int kk = 0; kk < SK / 4; ++kk) {
+      double af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) af[i] = As[cur][kk * 4 + lk][wm * 32 + i * 16 + l16];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bf[j] = Bs[cur][wn * 32 + j * 16 + l16][kk * 4 + lk];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j], af[i], acc[i][j], 0, 0, 0);
+    }
+    if (has_next) store_stage(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  // epilogue: lane holds C[m0 + wm*32 + i*16 + l16][n0 + wn*32 + j*16 + lk + 4*v]
+  const int64_t r0 = m0 + wm * 32 + l16, c0 = n0 + wn * 32 + lk;
+  if (interior) {
+    double *cp = C + r0 + c0 * ldc;
+    double cv[2][2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cv[i][j][v] = cp[i * 16 + (j * 16 + 4 * v) * ldc];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cp[i * 16 + (j * 16 + 4 * v) * ldc] = cv[i][j][v] - acc[i][j][v];
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int64_t row = r0 + i * 16;
+    if (row >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t col = c0 + j * 16 + 4 * v;
+        if (col < N) {
+          double *p = C + row + col * ldc;
+          *p = *p - acc[i][j][v];
+        }
+      }
+  }
+}
+
+hipError_t launch_small(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                        const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t s) {
+  const int64_t tm = (M + SM - 1) / SM, tn = (N + SN - 1) / SN;
+  const int64_t total = tm * tn;
+  if (total > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_dgemm_small<Acc::Subtract>), dim3(unsigned(total)), dim3(256), 0, s, M, N,
+                     K, A, lda, B, ldb, C, ldc, int(tm), int(total));
+  return hipGetLastError();
+}
+
 template <OpA OA, OpB OB, Acc AC>
 hipError_t launch_t(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
                     const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t s) {
@@ -286,6 +440,15 @@ hipError_t launch_t(int64_t M, int64_t N, int64_t K, const double *A, int64_t ld
 
 }  // namespace
 
+hipError_t launch_dgemm_tiles(int tile, int64_t M, int64_t N, int64_t K, const double *A,
+                              int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc,
+                              hipStream_t s) {
+  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  if (tile == 64) return launch_small(M, N, K, A, lda, B, ldb, C, ldc, s);
+  return launch_t<OpA::General, OpB::General, Acc::SubtractTrailing>(M, N, K, A, lda, B, ldb, C,
+                                                                     ldc, s);
+}
+
 hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, OpA opa,
                         const double *B, int64_t ldb, OpB opb, double *C, int64_t ldc, Acc acc,
                         hipStream_t s) {
@@ -294,10 +457,13 @@ hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, const double *A, int64_
     if (acc != Acc::Overwrite) return hipSuccess;
     return hipErrorInvalidValue;  // C = 0 is never requested by the solver
   }
+  // the updates inside and beside the panel (and of the block solves) run
+  // on the small tiles, the trailing update on the large ones
+  if (opa == OpA::General && opb == OpB::General && acc == Acc::Subtract)
+    return launch_small(M, N, K, A, lda, B, ldb, C, ldc, s);
 #define RBT_GEMM_CASE(OA_, OB_, AC_)                                              \
   if (opa == OA_ && opb == OB_ && acc == AC_)                                    \
     return launch_t<OA_, OB_, AC_>(M, N, K, A, lda, B, ldb, C, ldc, s);
-  RBT_GEMM_CASE(OpA::General, OpB::General, Acc::Subtract)
   RBT_GEMM_CASE(OpA::General, OpB::General, Acc::SubtractTrailing)
   RBT_GEMM_CASE(OpA::GeneralT, OpB::General, Acc::Subtract)
   RBT_GEMM_CASE(OpA::General, OpB::Upper, Acc::Overwrite)
