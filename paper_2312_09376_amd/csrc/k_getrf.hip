@@ -10,7 +10,7 @@
 //      the panel's top 16 rows, so each pivot row is broadcast within the
 //      wavefront with readlane and the 16 steps need no workgroup barrier;
 //   2. the 16-row block of U to its right is solved by forward substitution
-//      with the panel's unit-lower 16 x 16 block (one lane per column);
+//      with the panel's unit-lower 16 x 16 block (four lanes per column);
 //   3. the trailing block takes a rank-16 update on the FP64 matrix cores,
 //      16 x 16 tiles shared out over the four wavefronts; each tile's
 //      accumulator starts from the LDS values and the L operand is negated.
@@ -34,6 +34,24 @@ __device__ __forceinline__ double wave_bcast(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
   return __hiloint2double(hi, lo);
+}
+
+// v of lane K of each quad, to all four lanes of the quad (DPP quad_perm)
+template <int K>
+__device__ __forceinline__ double quad_bcast_k(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(u)), K * 0x55, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(u >> 32)), K * 0x55, 0xF, 0xF, false);
+  return __builtin_bit_cast(double,
+                            (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32));
+}
+__device__ __forceinline__ double quad_bcast(double v, int k) {  // k: compile-time after unrolling
+  switch (k) {
+    case 0: return quad_bcast_k<0>(v);
+    case 1: return quad_bcast_k<1>(v);
+    case 2: return quad_bcast_k<2>(v);
+    default: return quad_bcast_k<3>(v);
+  }
 }
 
 template <typename T>
@@ -82,21 +100,33 @@ __global__ void __launch_bounds__(256) k_diag_lu(int kb, T *__restrict__ A, int6
       double x[PW];
 #pragma unroll
       for (int j = 0; j < PW; ++j) x[j] = S[(c0 + j) * LD + rr];
+      // The loop body is kept free of branches (a zero pivot is found after
+      // it; the reciprocal and the scaled entry are pinned before the
+      // selects), so that the compiler can start a pivot's division while
+      // the previous pivot's updates are still issuing.
 #pragma unroll
       for (int cc = 0; cc < PW; ++cc) {
-        const int c = c0 + cc;
         double prow[PW];
 #pragma unroll
         for (int j = cc; j < PW; ++j) prow[j] = wave_bcast(x[j], cc);
         const double p = prow[cc];
-        if (wave == 0 && lane == 0 && c < kb && p == 0.0 && info != nullptr)
-          atomicCAS(info, 0, int32_t(gofs + c + 1));
         const bool act = top ? lane > cc : valid;
-        const double rp = 1.0 / p;  // one division per pivot (scaling as in LAPACK's getf2)
-        const double l = act ? x[cc] * rp : 0.0;
+        double rp = 1.0 / p;  // one division per pivot (scaling as in LAPACK's getf2)
+        __asm__ volatile("" : "+v"(rp));
+        double lm = x[cc] * rp;
+        __asm__ volatile("" : "+v"(lm));
+        const double l = act ? lm : 0.0;
         x[cc] = act ? l : x[cc];
 #pragma unroll
         for (int j = cc + 1; j < PW; ++j) x[j] -= l * prow[j];
+      }
+      {  // first zero pivot of the panel: top lane j of wavefront 0 holds pivot j in x[j]
+        double d = x[0];
+#pragma unroll
+        for (int j = 1; j < PW; ++j) d = lane == j ? x[j] : d;
+        const unsigned long long z = __ballot(top && c0 + lane < kb && d == 0.0);
+        if (wave == 0 && lane == 0 && z != 0 && info != nullptr)
+          atomicCAS(info, 0, int32_t(gofs + c0 + __ffsll(z)));
       }
       if ((top && wave == 0) || (!top && valid)) {
 #pragma unroll
@@ -107,18 +137,57 @@ __global__ void __launch_bounds__(256) k_diag_lu(int kb, T *__restrict__ A, int6
 
     const int c1 = c0 + PW;  // first column/row after the panel
     if (c1 >= NB) break;
-    // ---- 2. U block row: rows c0..c0+15, columns c1..127 ----
-    if (tid < NB - c1) {
-      const int col = c1 + tid;
-      double y[PW];
+    // ---- 2. U block row: rows c0..c0+15, columns c1..127, by forward
+    // substitution with the unit-lower 16 x 16 block: four lanes per column
+    // (lane q of a quad holds rows q, q + 4, q + 8, q + 12), columns
+    // c1 + g and c1 + 64 + g for quad g, the pivot entry passed on by a quad
+    // broadcast and the next pivot's coefficients read during this one.
+    // Every entry sees the same operations in the same order as one-lane-
+    // per-column substitution. ----
+    {
+      const int g = tid >> 2, q = tid & 3;
+      const int colA = c1 + g, colB = c1 + 64 + g;
+      const bool hasA = colA < NB, hasB = colB < NB;
+      const int ca = hasA ? colA : NB - 1, cb = hasB ? colB : NB - 1;
+      double ya[4], yb[4];
 #pragma unroll
-      for (int i = 0; i < PW; ++i) y[i] = S[col * LD + c0 + i];
+      for (int jj = 0; jj < 4; ++jj) {
+        ya[jj] = S[ca * LD + c0 + q + 4 * jj];
+        yb[jj] = S[cb * LD + c0 + q + 4 * jj];
+      }
+      double tn[4];
 #pragma unroll
-      for (int i = 0; i < PW; ++i)
+      for (int jj = 0; jj < 4; ++jj) tn[jj] = S[c0 * LD + c0 + q + 4 * jj];
 #pragma unroll
-        for (int i2 = i + 1; i2 < PW; ++i2) y[i2] -= S[(c0 + i) * LD + c0 + i2] * y[i];
+      for (int j = 0; j < PW; ++j) {  // pivot j: entries i > j lose L(i, j) y_j
+        const int jc = j >> 2, qc = j & 3;
+        double t[4];
 #pragma unroll
-      for (int i = 0; i < PW; ++i) S[col * LD + c0 + i] = y[i];
+        for (int jj = 0; jj < 4; ++jj) t[jj] = tn[jj];
+        if (j + 1 < PW) {
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) tn[jj] = S[(c0 + j + 1) * LD + c0 + q + 4 * jj];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const double ba = quad_bcast(ya[jc], qc), bb = quad_bcast(yb[jc], qc);
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          if (4 * jj + 3 <= j) continue;
+          const bool upd = 4 * jj > j || q + 4 * jj > j;
+          const double na = __builtin_fma(-t[jj], ba, ya[jj]);
+          const double nb = __builtin_fma(-t[jj], bb, yb[jj]);
+          ya[jj] = upd ? na : ya[jj];
+          yb[jj] = upd ? nb : yb[jj];
+        }
+      }
+      if (hasA) {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) S[colA * LD + c0 + q + 4 * jj] = ya[jj];
+      }
+      if (hasB) {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) S[colB * LD + c0 + q + 4 * jj] = yb[jj];
+      }
     }
     __syncthreads();
     // ---- 3. trailing rank-16 update on 16 x 16 tiles, two per wavefront
