@@ -237,10 +237,8 @@ int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t
       const int64_t pc = k0 + w - k - kb;   // panel columns right of it
       {
         StageScope t(kStagePanel, s, double(rows) * kb * kb + double(pc) * kb * kb);
-        RBT_HIP_CHECK(launch_trsm_right_upper(kb, rows, A11, lda, A + (k + kb) + k * lda, lda, s));
-        if (pc > 0)
-          RBT_HIP_CHECK(launch_trsm_left(TriMode::LN, kb, pc, A11, lda, A + k + (k + kb) * lda,
-                                         lda, s));
+        RBT_HIP_CHECK(launch_panel_trsm(kb, rows, pc, A11, lda, A + (k + kb) + k * lda,
+                                        A + k + (k + kb) * lda, lda, s));
       }
       if (pc > 0 && rows > 0) {
         StageScope t(kStagePanel, s, 2.0 * double(rows) * pc * kb);

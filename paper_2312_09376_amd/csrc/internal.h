@@ -126,6 +126,12 @@ hipError_t launch_trsm_right_upper(int kb, int64_t M, const double *T, int64_t l
                                    int64_t ldb, hipStream_t s);
 hipError_t launch_trsm_right_upper(int kb, int64_t M, const float *T, int64_t ldt, float *B,
                                    int64_t ldb, hipStream_t s);
+// Both solves of a panel step in one launch: Br (M x kb) <- Br U^-1 and
+// Bl (kb x N) <- L^-1 Bl with the factored block T (same ldb for both).
+hipError_t launch_panel_trsm(int kb, int64_t M, int64_t N, const double *T, int64_t ldt,
+                             double *Br, double *Bl, int64_t ldb, hipStream_t s);
+hipError_t launch_panel_trsm(int kb, int64_t M, int64_t N, const float *T, int64_t ldt, float *Br,
+                             float *Bl, int64_t ldb, hipStream_t s);
 // Inverses of all kNB x kNB diagonal blocks of the factors of an n x n
 // elimination: block b's L^-1 at W + b * 2 kNB^2 and U^-1 at
 // W + b * 2 kNB^2 + kNB^2 (ld kNB). Needs diag_inv_doubles(n) doubles.

@@ -148,10 +148,19 @@ __device__ __forceinline__ void quad_substitute(double (&x)[4], const double *tq
 // offset by b * kNB (1 + ldt) and b * bstride, kb = min(kNB, n - b kNB)), and
 // the right-hand side is the identity (X = op(T_bb)^-1): used to form the
 // inverses of the diagonal blocks once per factorization.
+// LDS of one workgroup of either solve: diagonal blocks, off-diagonal
+// blocks, four right-hand-side strips (136 KB).
+struct TrsmSmem {
+  __attribute__((aligned(16))) double dblk[NBK * BLK];
+  __attribute__((aligned(16))) double oblk[NOFF * BLK];
+  __attribute__((aligned(16))) double strip[4][NB * IB];
+};
+
+// Left solve of the 64 columns [64 bx, 64 bx + 64) of B.
 template <TriMode MODE, bool BATCH, typename TT, typename TB>
-__global__ void __launch_bounds__(256, 1) k_trsm_left(int kb, int64_t N, const TT *T,
-                                                      int64_t ldt, TB *B, int64_t ldb,
-                                                      int64_t n, int64_t bstride) {
+__device__ __forceinline__ void trsm_left_body(int kb, int64_t N, const TT *T, int64_t ldt,
+                                               TB *B, int64_t ldb, int64_t n, int64_t bstride,
+                                               int64_t bx, TrsmSmem &sm) {
   if constexpr (BATCH) {
     const int64_t b = blockIdx.y;
     const int64_t r0 = b * NB;
@@ -164,15 +173,14 @@ __global__ void __launch_bounds__(256, 1) k_trsm_left(int kb, int64_t N, const T
   // (reciprocal on the diagonal of non-unit modes); ablk: off-diagonal block
   // (I, J), J before I, at p*256 + lane*4 + kk = op(T)(16I + l16, 16J + 4kk +
   // lk), p = I(I-1)/2 + J (forward) or J(J-1)/2 + I (backward)
-  __shared__ __attribute__((aligned(16))) double dblk[NBK * BLK];
-  __shared__ __attribute__((aligned(16))) double ablk[NOFF * BLK];
-  __shared__ double strip_all[4][NB * IB];  // per wavefront: row-major 128 x 16
+  double *dblk = sm.dblk;
+  double *ablk = sm.oblk;
   constexpr bool FWD = forward_order<MODE>();
   constexpr bool TRANS = MODE == TriMode::UT || MODE == TriMode::LT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
-  double *strip = strip_all[wave];
-  const int64_t col0 = int64_t(blockIdx.x) * 64 + wave * 16;
+  double *strip = sm.strip[wave];  // row-major 128 x 16
+  const int64_t col0 = bx * 64 + wave * 16;
 
   {  // stage the diagonal blocks and the off-diagonal operands, coalesced:
      // consecutive threads read consecutive addresses of the stored T
@@ -277,20 +285,28 @@ __global__ void __launch_bounds__(256, 1) k_trsm_left(int kb, int64_t N, const T
   }
 }
 
+template <TriMode MODE, bool BATCH, typename TT, typename TB>
+__global__ void __launch_bounds__(256, 1) k_trsm_left(int kb, int64_t N, const TT *T,
+                                                      int64_t ldt, TB *B, int64_t ldb,
+                                                      int64_t n, int64_t bstride) {
+  __shared__ TrsmSmem sm;
+  trsm_left_body<MODE, BATCH>(kb, N, T, ldt, B, ldb, n, bstride, int64_t(blockIdx.x), sm);
+}
+
+// Right solve of the 64 rows [64 bx, 64 bx + 64) of B.
 template <typename TT>
-__global__ void __launch_bounds__(256, 1) k_trsm_right_upper(int kb, int64_t M, const TT *T,
-                                                             int64_t ldt, TT *B,
-                                                             int64_t ldb) {
+__device__ __forceinline__ void trsm_right_upper_body(int kb, int64_t M, const TT *T, int64_t ldt,
+                                                      TT *B, int64_t ldb, int64_t bx,
+                                                      TrsmSmem &sm) {
   // dblk: U(r, c) of diagonal block b at b*256 + r*16 + (c%4)*4 + c/4
   // (reciprocal on the diagonal); ublk: block (I, J), I < J, at p*256 +
   // lane*4 + kk = U(16I + 4kk + lk, 16J + l16), p = J(J-1)/2 + I
-  __shared__ __attribute__((aligned(16))) double dblk[NBK * BLK];
-  __shared__ __attribute__((aligned(16))) double ublk[NOFF * BLK];
-  __shared__ double strip_all[4][NB * IB];  // per wavefront: column-major 16 x 128
+  double *dblk = sm.dblk;
+  double *ublk = sm.oblk;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
-  double *strip = strip_all[wave];
-  const int64_t row0 = int64_t(blockIdx.x) * 64 + wave * 16;
+  double *strip = sm.strip[wave];  // column-major 16 x 128
+  const int64_t row0 = bx * 64 + wave * 16;
 
   {  // stage the triangle, consecutive threads on consecutive rows of U
     const int r = threadIdx.x % IB, c = threadIdx.x / IB;
@@ -383,6 +399,31 @@ __global__ void __launch_bounds__(256, 1) k_trsm_right_upper(int kb, int64_t M, 
   }
 }
 
+template <typename TT>
+__global__ void __launch_bounds__(256, 1) k_trsm_right_upper(int kb, int64_t M, const TT *T,
+                                                             int64_t ldt, TT *B, int64_t ldb) {
+  __shared__ TrsmSmem sm;
+  trsm_right_upper_body(kb, M, T, ldt, B, ldb, int64_t(blockIdx.x), sm);
+}
+
+// Both solves of a panel step with one factored diagonal block, which are
+// independent: L21 = A21 U11^-1 (the first gr workgroups, 64 rows each) and
+// U12 = L11^-1 A12 for the panel's columns to the right (the rest, 64
+// columns each). One launch instead of two, and the short left solve runs
+// beside the right one.
+template <typename TT>
+__global__ void __launch_bounds__(256, 1) k_panel_trsm(int kb, int64_t M, int64_t N, const TT *T,
+                                                       int64_t ldt, TT *Br, TT *Bl, int64_t ldb,
+                                                       int64_t gr) {
+  __shared__ TrsmSmem sm;
+  const int64_t bx = blockIdx.x;
+  if (bx < gr)
+    trsm_right_upper_body(kb, M, T, ldt, Br, ldb, bx, sm);
+  else
+    trsm_left_body<TriMode::LN, false>(kb, N, T, ldt, Bl, ldb, int64_t(0), int64_t(0), bx - gr,
+                                       sm);
+}
+
 template <typename TT, typename TB>
 hipError_t trsm_left_t(TriMode mode, int kb, int64_t N, const TT *T, int64_t ldt, TB *B,
                        int64_t ldb, hipStream_t s) {
@@ -410,6 +451,18 @@ hipError_t diag_inverses_t(int64_t n, const TT *LU, int64_t ld, double *W, hipSt
                      int64_t(NB), LU, ld, W, int64_t(NB), n, int64_t(2 * NB * NB));
   hipLaunchKernelGGL((k_trsm_left<TriMode::UN, true, TT, double>), grid, dim3(256), 0, s, NB,
                      int64_t(NB), LU, ld, W + NB * NB, int64_t(NB), n, int64_t(2 * NB * NB));
+  return hipGetLastError();
+}
+
+template <typename TT>
+hipError_t panel_trsm_t(int kb, int64_t M, int64_t N, const TT *T, int64_t ldt, TT *Br, TT *Bl,
+                        int64_t ldb, hipStream_t s) {
+  if (kb <= 0 || (M <= 0 && N <= 0)) return hipSuccess;
+  if (kb > kNB) return hipErrorInvalidValue;
+  const int64_t gr = M > 0 ? (M + 63) / 64 : 0, gl = N > 0 ? (N + 63) / 64 : 0;
+  if (gr + gl > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_panel_trsm<TT>, dim3(unsigned(gr + gl)), dim3(256), 0, s, kb, M, N, T, ldt,
+                     Br, Bl, ldb, gr);
   return hipGetLastError();
 }
 
@@ -447,6 +500,14 @@ hipError_t launch_trsm_right_upper(int kb, int64_t M, const double *T, int64_t l
 hipError_t launch_trsm_right_upper(int kb, int64_t M, const float *T, int64_t ldt, float *B,
                                    int64_t ldb, hipStream_t s) {
   return trsm_right_upper_t(kb, M, T, ldt, B, ldb, s);
+}
+hipError_t launch_panel_trsm(int kb, int64_t M, int64_t N, const double *T, int64_t ldt,
+                             double *Br, double *Bl, int64_t ldb, hipStream_t s) {
+  return panel_trsm_t(kb, M, N, T, ldt, Br, Bl, ldb, s);
+}
+hipError_t launch_panel_trsm(int kb, int64_t M, int64_t N, const float *T, int64_t ldt, float *Br,
+                             float *Bl, int64_t ldb, hipStream_t s) {
+  return panel_trsm_t(kb, M, N, T, ldt, Br, Bl, ldb, s);
 }
 
 }  // namespace rbt
