@@ -32,9 +32,9 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 # of known size (FETCH x 2.000, WRITE x 1.000). Valid only for the kernel
 # source and the workload they were taken on: reported as null otherwise.
 TRAILING_TRAFFIC = {"source": "paper_2312_09376_amd/csrc/k_gemm.hip",
-                    "sha256": "b69180937539ca298702ab98419575983b7e9a29a355c9afeb4baa75ce7e1056",
+                    "sha256": "f3f42d7cb3dd4c544e7022c28fd2c447c74d403fce5a4be1d401b83bf1967610",
                     "n": 20000, "nrhs": 1, "depth": 2, "outer_nb": 1024,
-                    "bytes_per_launch": 6.901e9}
+                    "bytes_per_launch": 6.527e9}
 
 
 def parse():
