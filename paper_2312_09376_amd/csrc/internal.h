@@ -101,6 +101,11 @@ hipError_t launch_dgemm_tiles(int tile, int64_t M, int64_t N, int64_t K, const d
 hipError_t launch_sgemm_sub(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda,
                             const float *B, int64_t ldb, float *C, int64_t ldc, bool bf16,
                             bool trailing, hipStream_t s);
+// C -= A B (non-trailing instance) with 64 x 64 (tile = 64) or 128 x 128 block
+// tiles; the results are identical (tuning and tests).
+hipError_t launch_sgemm_tiles(int tile, int64_t M, int64_t N, int64_t K, const float *A,
+                              int64_t lda, const float *B, int64_t ldb, float *C, int64_t ldc,
+                              bool bf16, hipStream_t s);
 
 // k_getrf.hip : factor the kb x kb diagonal block in place (kb <= kNB);
 // first exact zero pivot -> *info = gofs + c + 1. FP32 blocks are eliminated
