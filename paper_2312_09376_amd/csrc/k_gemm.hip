@@ -140,10 +140,42 @@ __global__ void __launch_bounds__(256, 2)
     }
   };
 
+  // Edge tiles of the plain product: rows >= M and columns >= N only feed
+  // outputs that are never stored, so they are read at clamped addresses
+  // inside A and B with the same 16-byte loads (a row pair at r reads rows
+  // rc, rc + 1 with rc = min(r, M - 2): row r's value is the first or the
+  // second of them).
+  const bool clamped = (OA == OpA::General) && (OB == OpB::General) && !interior && M >= 2;
+  auto load_stage_clamped = [&](int64_t k0) {
+    const int64_t r = m0 + 2 * (tid & 63);
+    const int64_t rc = r < M - 1 ? r : M - 2;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int64_t k = k0 + (tid >> 6) + 4 * p;
+      const d2u v = *reinterpret_cast<const d2u *>(A + rc + k * lda);
+      ra[2 * p] = r == rc ? v[0] : v[1];
+      ra[2 * p + 1] = v[1];
+    }
+    const int64_t nb = n0 + (tid >> 1);
+    const double *bp = B + (k0 + 8 * (tid & 1)) + (nb < N ? nb : N - 1) * ldb;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const d2u v = *reinterpret_cast<const d2u *>(bp + 2 * p);
+      rb[2 * p] = v[0];
+      rb[2 * p + 1] = v[1];
+    }
+  };
+
   auto load_stage = [&](int64_t k0) {
-    if (interior && k0 + BK <= K) {
-      load_stage_fast(k0);
-      return;
+    if (k0 + BK <= K) {
+      if (interior) {
+        load_stage_fast(k0);
+        return;
+      }
+      if (clamped) {
+        load_stage_clamped(k0);
+        return;
+      }
     }
     if constexpr (a_m_contiguous<OA>()) {
 #pragma unroll
@@ -215,10 +247,11 @@ __global__ void __launch_bounds__(256, 2)
   }
 
   // epilogue: lane holds C[m0 + wm*64 + i*16 + l16][n0 + wn*64 + j*16 + lk + 4*v].
-  // Whole tiles load the C values of row block i + 1 before storing row
-  // block i, so 16 loads per lane are in flight at a time (the compiler
-  // cannot move a load of C above a store to C, which would otherwise cost
-  // one round trip per element); edge tiles take the element-wise path.
+  // The C values of row block i + 1 are loaded before row block i is
+  // stored, so 16 loads per lane are in flight at a time (a load of C cannot
+  // be moved above a store to C by the compiler, which would otherwise cost
+  // one round trip per element). Edge tiles load at clamped addresses inside
+  // C and store only their elements inside it.
   const int64_t r0 = m0 + wm * 64 + l16, c0 = n0 + wn * 64 + lk;
   if (m0 + BM <= M && n0 + BN <= N) {
     double *cp = C + r0 + c0 * ldc;
@@ -253,23 +286,33 @@ __global__ void __launch_bounds__(256, 2)
     }
     return;
   }
+  // edge tile: one column offset per (j, v) (clamped), rows per i
+  int64_t coff[16];
+  bool cin[16];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t col = c0 + j * 16 + 4 * v;
+      cin[4 * j + v] = col < N;
+      coff[4 * j + v] = (col < N ? col : N - 1) * ldc;
+    }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t row = r0 + i * 16;
     if (row >= M) continue;
+    double *cr = C + row;
+    if constexpr (AC == Acc::Overwrite) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+      for (int e = 0; e < 16; ++e)
+        if (cin[e]) cr[coff[e]] = acc[i][e >> 2][e & 3];
+    } else {
+      double cv[16];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t col = c0 + j * 16 + 4 * v;
-        if (col < N) {
-          double *p = C + row + col * ldc;
-          if constexpr (AC != Acc::Overwrite)
-            *p = *p - acc[i][j][v];
-          else
-            *p = acc[i][j][v];
-        }
-      }
+      for (int e = 0; e < 16; ++e) cv[e] = cr[coff[e]];
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        if (cin[e]) cr[coff[e]] = cv[e] - acc[i][e >> 2][e & 3];
     }
   }
 }
@@ -321,16 +364,21 @@ __global__ void __launch_bounds__(256, 4)
   auto load_stage = [&](int64_t k0) {
     const int64_t ma = m0 + 2 * (tid & 31), ka = k0 + (tid >> 5);
     const int64_t nb = n0 + (tid >> 2), kb = k0 + 4 * (tid & 3);
-    if (interior && k0 + SK <= K) {
+    if (k0 + SK <= K && (interior || M >= 2)) {
+      // edge tiles read rows >= M and columns >= N (outputs never stored) at
+      // clamped addresses: a row pair at ma reads rows mc, mc + 1, mc =
+      // min(ma, M - 2), and row ma's value is the first or second of them
+      const int64_t mc = ma < M - 1 ? ma : M - 2;
+      const int64_t nc = nb < N ? nb : N - 1;
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
-        const d2u v = *reinterpret_cast<const d2u *>(A + ma + (ka + 8 * p) * lda);
-        ra[2 * p] = v[0];
+        const d2u v = *reinterpret_cast<const d2u *>(A + mc + (ka + 8 * p) * lda);
+        ra[2 * p] = ma == mc ? v[0] : v[1];
         ra[2 * p + 1] = v[1];
       }
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
-        const d2u v = *reinterpret_cast<const d2u *>(B + (kb + 2 * p) + nb * ldb);
+        const d2u v = *reinterpret_cast<const d2u *>(B + (kb + 2 * p) + nc * ldb);
         rb[2 * p] = v[0];
         rb[2 * p + 1] = v[1];
       }
@@ -400,20 +448,28 @@ __global__ void __launch_bounds__(256, 4)
         for (int v = 0; v < 4; ++v) cp[i * 16 + (j * 16 + 4 * v) * ldc] = cv[i][j][v] - acc[i][j][v];
     return;
   }
+  // edge tile: loads at clamped columns, stores inside C only
+  int64_t coff[8];
+  bool cin[8];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t col = c0 + j * 16 + 4 * v;
+      cin[4 * j + v] = col < N;
+      coff[4 * j + v] = (col < N ? col : N - 1) * ldc;
+    }
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const int64_t row = r0 + i * 16;
     if (row >= M) continue;
+    double *cr = C + row;
+    double cv[8];
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int e = 0; e < 8; ++e) cv[e] = cr[coff[e]];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t col = c0 + j * 16 + 4 * v;
-        if (col < N) {
-          double *p = C + row + col * ldc;
-          *p = *p - acc[i][j][v];
-        }
-      }
+    for (int e = 0; e < 8; ++e)
+      if (cin[e]) cr[coff[e]] = cv[e] - acc[i][e >> 2][e & 3];
   }
 }
 
