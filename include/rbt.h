@@ -308,8 +308,10 @@ int rbt_solve_backward_mixed(int64_t n, int64_t nrhs, const float *LU, int64_t l
 /* Tuning options (process-wide; not thread safe).
  * RBT_OPT_OUTER_NB: width of the panels of the elimination whose trailing
  *   update is a single GEMM (multiple of 128, 128..2048; default 1024). The
- *   diagonal blocks are always 128 x 128. Changes only the order of the
- *   roundings, not the method. */
+ *   first panel also takes the n mod 128 columns that do not fill a 128-wide
+ *   diagonal block (except with BF16 updates), so that every trailing update
+ *   covers whole 128-blocks. Changes only the order of the roundings, not
+ *   the method. */
 #define RBT_OPT_OUTER_NB 1
 /* RBT_OPT_BATCH_TILE_COLS: rbt_solve_batched, 64-column tiles of the
  *   low-precision trailing update per round (1 or 2; default 1): more tiles

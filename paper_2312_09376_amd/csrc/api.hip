@@ -285,13 +285,22 @@ int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t
   EventPair ev;
   if (s2 != nullptr && !ev.ok()) s2 = nullptr;
   if (n <= 0) return 0;
-  int rc = panel(0, n < W ? n : W);
+  // The first panel also takes the n mod kNB columns that do not fill a
+  // diagonal block, so that every trailing update is a whole number of
+  // 128-wide blocks (a partial tile row and column cost the large-tile GEMM
+  // as much as whole ones). Not with BF16 updates: their staged GEMM wants
+  // a depth that is a multiple of 64.
+  const int64_t r0 = prec == RBT_BF16 ? 0 : n % kNB;
+  auto width = [&](int64_t k0) {
+    const int64_t w = k0 == 0 ? W + r0 : W;
+    return n - k0 < w ? n - k0 : w;
+  };
+  int rc = panel(0, width(0));
   if (rc) return rc;
-  for (int64_t k0 = 0;; k0 += W) {
-    const int64_t w = n - k0 < W ? n - k0 : W;
+  for (int64_t k0 = 0, w = width(0);; k0 += w, w = width(k0)) {
     const int64_t rest = n - k0 - w;  // columns right of the panel
     if (rest <= 0) break;
-    const int64_t wn = rest < W ? rest : W;  // next panel
+    const int64_t wn = width(k0 + w);  // next panel
     const bool split = s2 != nullptr && rest > wn;
     if (split) {
       RBT_HIP_CHECK(hipEventRecord(ev.f, s));
