@@ -32,9 +32,22 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 # of known size (FETCH x 2.000, WRITE x 1.000). Valid only for the kernel
 # source and the workload they were taken on: reported as null otherwise.
 TRAILING_TRAFFIC = {"source": "paper_2312_09376_amd/csrc/k_gemm.hip",
-                    "sha256": "f3f42d7cb3dd4c544e7022c28fd2c447c74d403fce5a4be1d401b83bf1967610",
+                    "sha256": "c7863a42e47448753fef8e84ba2512d4591aded0bbc9a7874dd5fc477e8c0a3d",
                     "n": 20000, "nrhs": 1, "depth": 2, "outer_nb": 1024,
-                    "bytes_per_launch": 6.527e9}
+                    "bytes_per_launch": 5.339e9}
+
+
+def trailing_shapes(n, W, remainder=True):
+    """(rc, w) of every trailing update of the blocked elimination: rc rows
+    and columns remain right of a panel of width w. The first panel also takes
+    the n mod 128 columns (not with BF16 updates: remainder=False)."""
+    k0, w = 0, min(n, W + (n % 128 if remainder else 0))
+    out = []
+    while n - k0 - w > 0:
+        out.append((n - k0 - w, w))
+        k0 += w
+        w = min(n - k0, W)
+    return out
 
 
 def parse():
@@ -188,8 +201,8 @@ def mixed_mode(args):
     peak = PEAK_FP32_MFMA_TFLOPS if args.prec == "fp32" else PEAK_BF16_MFMA_TFLOPS
     gemm_tflops = tr_work / (tr_ms * 1e-3) / 1e12 if tr_ms > 0 else 0.0
     W = rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)
-    tr_bytes = sum(8.0 * rc * rc + 8.0 * rc * W for rc in
-                   (n - k0 - W for k0 in range(0, n, W)) if rc > 0) * args.steps
+    tr_bytes = sum(8.0 * rc * rc + 8.0 * rc * w for rc, w in
+                   trailing_shapes(n, W, args.prec != "bf16")) * args.steps
     out = {
         "metric": f"mixed-precision solve TFLOP/s (2/3·n³, FP64-accurate result), "
                   f"{args.prec.upper()} elimination + FP64 {args.solver} refinement",
@@ -505,8 +518,7 @@ def main():
     # algorithmic bytes of a trailing update: read + write A22 (16 rc^2) and
     # read L21, U12 (16 rc w); with flops 2 rc^2 w this is 8/w + 8/rc per flop
     W = rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)
-    tr_bytes = sum(16.0 * rc * rc + 16.0 * rc * W for rc in
-                   (n - k0 - W for k0 in range(0, n, W)) if rc > 0) * args.steps
+    tr_bytes = sum(16.0 * rc * rc + 16.0 * rc * w for rc, w in trailing_shapes(n, W)) * args.steps
     gemm_avg_ms = tr_ms / max(tr_cnt, 1)
     gemm_tflops = tr_work / (tr_ms * 1e-3) / 1e12 if tr_ms > 0 else 0.0
     k1_ms, k1_cnt, k1_bytes = stages["transform2"]
