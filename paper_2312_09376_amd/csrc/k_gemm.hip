@@ -80,27 +80,18 @@ constexpr bool a_m_contiguous() {
   return OA == OpA::General || OA == OpA::UnitLower || OA == OpA::Upper;
 }
 
-template <OpA OA, OpB OB, Acc AC>
-__global__ void __launch_bounds__(256, 2)
-    k_dgemm(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, const double *B,
-            int64_t ldb, double *C, int64_t ldc, int tiles_m,
-            int total) {
-  __shared__ double As[2][BK][BM + PADA];
-  __shared__ double Bs[2][BN][BK + PADB];
-
-  // XCD-aware remap, then grouped tile order (groups of GM tile rows,
-  // column-major inside a group)
-  int pid = blockIdx.x;
-  const int full = (total / 8) * 8;
-  if (pid < full) pid = (pid % 8) * (total / 8) + pid / 8;
-  const int tiles_n = total / tiles_m;
-  const int group = pid / (GM * tiles_n);
-  const int first_m = group * GM;
-  const int gsize = (tiles_m - first_m) < GM ? (tiles_m - first_m) : GM;
-  const int in_group = pid - group * GM * tiles_n;
-  const int tm = first_m + in_group % gsize, tn = in_group / gsize;
-  const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
-
+// One 128 x 128 block tile at (m0, n0). FAST: an interior tile of the plain
+// product with K a multiple of BK (the kernel checks), which takes the
+// unguarded loads in every slice and the whole-tile epilogue with no
+// per-slice branches between the matrix-core blocks (3 % faster than
+// choosing the load path slice by slice); every other tile takes the
+// general body. Both compute the same products in the same order.
+template <OpA OA, OpB OB, Acc AC, bool FAST>
+__device__ __forceinline__ void dgemm_tile(int64_t M, int64_t N, int64_t K, const double *A,
+                                           int64_t lda, const double *B, int64_t ldb, double *C,
+                                           int64_t ldc, int64_t m0, int64_t n0,
+                                           double (&As)[2][BK][BM + PADA],
+                                           double (&Bs)[2][BN][BK + PADB]) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -121,8 +112,8 @@ __global__ void __launch_bounds__(256, 2)
   // Interior tiles of the plain product take unguarded 16-byte loads (the
   // operands are only 8-byte aligned in general, which these loads accept);
   // edge tiles and the last, partial K slice take the guarded path.
-  const bool interior = (OA == OpA::General) && (OB == OpB::General) && (m0 + BM <= M) &&
-                        (n0 + BN <= N);
+  const bool interior = FAST || ((OA == OpA::General) && (OB == OpB::General) &&
+                                  (m0 + BM <= M) && (n0 + BN <= N));
   auto load_stage_fast = [&](int64_t k0) {
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
@@ -167,6 +158,10 @@ __global__ void __launch_bounds__(256, 2)
   };
 
   auto load_stage = [&](int64_t k0) {
+    if constexpr (FAST) {
+      load_stage_fast(k0);
+      return;
+    }
     if (k0 + BK <= K) {
       if (interior) {
         load_stage_fast(k0);
@@ -253,7 +248,7 @@ __global__ void __launch_bounds__(256, 2)
   // one round trip per element). Edge tiles load at clamped addresses inside
   // C and store only their elements inside it.
   const int64_t r0 = m0 + wm * 64 + l16, c0 = n0 + wn * 64 + lk;
-  if (m0 + BM <= M && n0 + BN <= N) {
+  if (FAST || (m0 + BM <= M && n0 + BN <= N)) {
     double *cp = C + r0 + c0 * ldc;
     if constexpr (AC == Acc::Overwrite) {
 #pragma unroll
@@ -317,6 +312,36 @@ __global__ void __launch_bounds__(256, 2)
   }
 }
 
+template <OpA OA, OpB OB, Acc AC>
+__global__ void __launch_bounds__(256, 2)
+    k_dgemm(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, const double *B,
+            int64_t ldb, double *C, int64_t ldc, int tiles_m,
+            int total) {
+  __shared__ double As[2][BK][BM + PADA];
+  __shared__ double Bs[2][BN][BK + PADB];
+
+  // XCD-aware remap, then grouped tile order (groups of GM tile rows,
+  // column-major inside a group)
+  int pid = blockIdx.x;
+  const int full = (total / 8) * 8;
+  if (pid < full) pid = (pid % 8) * (total / 8) + pid / 8;
+  const int tiles_n = total / tiles_m;
+  const int group = pid / (GM * tiles_n);
+  const int first_m = group * GM;
+  const int gsize = (tiles_m - first_m) < GM ? (tiles_m - first_m) : GM;
+  const int in_group = pid - group * GM * tiles_n;
+  const int tm = first_m + in_group % gsize, tn = in_group / gsize;
+  const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
+
+  if constexpr (OA == OpA::General && OB == OpB::General) {
+    if (m0 + BM <= M && n0 + BN <= N && K % BK == 0) {
+      dgemm_tile<OA, OB, AC, true>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, As, Bs);
+      return;
+    }
+  }
+  dgemm_tile<OA, OB, AC, false>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, As, Bs);
+}
+
 // Small tiles for the updates inside and beside the panel (C -= A B with
 // K = 128 and one dimension of at most 896): 64 x 64 block tiles, 4
 // wavefronts of 32 x 32 (2 x 2 MFMA tiles), K in slices of 16, 34 KB of LDS
@@ -328,24 +353,15 @@ __global__ void __launch_bounds__(256, 2)
 // so the result is identical.
 constexpr int SM = 64, SN = 64, SK = 16;
 
-template <Acc AC>
-__global__ void __launch_bounds__(256, 4)
-    k_dgemm_small(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
-                  const double *B, int64_t ldb, double *C, int64_t ldc, int tiles_m, int total) {
-  __shared__ double As[2][SK][SM + PADA];
-  __shared__ double Bs[2][SN][SK + PADB];
-
-  int pid = blockIdx.x;
-  const int full = (total / 8) * 8;
-  if (pid < full) pid = (pid % 8) * (total / 8) + pid / 8;
-  const int tiles_n = total / tiles_m;
-  const int group = pid / (GM * tiles_n);
-  const int first_m = group * GM;
-  const int gsize = (tiles_m - first_m) < GM ? (tiles_m - first_m) : GM;
-  const int in_group = pid - group * GM * tiles_n;
-  const int tm = first_m + in_group % gsize, tn = in_group / gsize;
-  const int64_t m0 = int64_t(tm) * SM, n0 = int64_t(tn) * SN;
-
+// One 64 x 64 block tile at (m0, n0); FAST as for the large tiles (an
+// interior tile with K a multiple of SK: plain loads, whole-tile epilogue,
+// no per-slice branches; 8-10 % faster on the panel shapes).
+template <Acc AC, bool FAST>
+__device__ __forceinline__ void small_tile(int64_t M, int64_t N, int64_t K, const double *A,
+                                           int64_t lda, const double *B, int64_t ldb, double *C,
+                                           int64_t ldc, int64_t m0, int64_t n0,
+                                           double (&As)[2][SK][SM + PADA],
+                                           double (&Bs)[2][SN][SK + PADB]) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -360,10 +376,25 @@ __global__ void __launch_bounds__(256, 4)
   // A slice (64 x 16): rows 2 (tid % 32) + {0,1}, columns tid / 32 + {0, 8};
   // B slice (16 x 64): column tid / 4, rows 4 (tid % 4) + 0..3
   double ra[4], rb[4];
-  const bool interior = (m0 + SM <= M) && (n0 + SN <= N);
+  const bool interior = FAST || ((m0 + SM <= M) && (n0 + SN <= N));
   auto load_stage = [&](int64_t k0) {
     const int64_t ma = m0 + 2 * (tid & 31), ka = k0 + (tid >> 5);
     const int64_t nb = n0 + (tid >> 2), kb = k0 + 4 * (tid & 3);
+    if constexpr (FAST) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const d2u v = *reinterpret_cast<const d2u *>(A + ma + (ka + 8 * p) * lda);
+        ra[2 * p] = v[0];
+        ra[2 * p + 1] = v[1];
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const d2u v = *reinterpret_cast<const d2u *>(B + (kb + 2 * p) + nb * ldb);
+        rb[2 * p] = v[0];
+        rb[2 * p + 1] = v[1];
+      }
+      return;
+    }
     if (k0 + SK <= K && (interior || M >= 2)) {
       // edge tiles read rows >= M and columns >= N (outputs never stored) at
       // clamped addresses: a row pair at ma reads rows mc, mc + 1, mc =
@@ -471,6 +502,30 @@ __global__ void __launch_bounds__(256, 4)
     for (int e = 0; e < 8; ++e)
       if (cin[e]) cr[coff[e]] = cv[e] - acc[i][e >> 2][e & 3];
   }
+}
+
+template <Acc AC>
+__global__ void __launch_bounds__(256, 4)
+    k_dgemm_small(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                  const double *B, int64_t ldb, double *C, int64_t ldc, int tiles_m, int total) {
+  __shared__ double As[2][SK][SM + PADA];
+  __shared__ double Bs[2][SN][SK + PADB];
+
+  int pid = blockIdx.x;
+  const int full = (total / 8) * 8;
+  if (pid < full) pid = (pid % 8) * (total / 8) + pid / 8;
+  const int tiles_n = total / tiles_m;
+  const int group = pid / (GM * tiles_n);
+  const int first_m = group * GM;
+  const int gsize = (tiles_m - first_m) < GM ? (tiles_m - first_m) : GM;
+  const int in_group = pid - group * GM * tiles_n;
+  const int tm = first_m + in_group % gsize, tn = in_group / gsize;
+  const int64_t m0 = int64_t(tm) * SM, n0 = int64_t(tn) * SN;
+
+  if (m0 + SM <= M && n0 + SN <= N && K % SK == 0)
+    small_tile<AC, true>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, As, Bs);
+  else
+    small_tile<AC, false>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, As, Bs);
 }
 
 hipError_t launch_small(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
