@@ -52,24 +52,16 @@ struct Smem<kBF16> {
   alignas(16) __bf16 Bh[2][BN][BK + PAD_H];
 };
 
-template <int MODE, bool TRAILING>
-__global__ void __launch_bounds__(256, 2)
-    k_sgemm(int64_t M, int64_t N, int64_t K, const float *__restrict__ A, int64_t lda,
-            const float *__restrict__ B, int64_t ldb, float *C, int64_t ldc, int tiles_m,
-            int total) {
-  __shared__ Smem<MODE> sm;
-
-  int pid = blockIdx.x;
-  const int full = (total / 8) * 8;
-  if (pid < full) pid = (pid % 8) * (total / 8) + pid / 8;
-  const int tiles_n = total / tiles_m;
-  const int group = pid / (GM * tiles_n);
-  const int first_m = group * GM;
-  const int gsize = (tiles_m - first_m) < GM ? (tiles_m - first_m) : GM;
-  const int in_group = pid - group * GM * tiles_n;
-  const int tm = first_m + in_group % gsize, tn = in_group / gsize;
-  const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
-
+// One 128 x 128 block tile at (m0, n0). FAST: an interior tile with K a
+// multiple of BK (the kernel checks): unguarded loads in every slice and the
+// whole-tile epilogue, with no per-slice branches between the matrix-core
+// blocks. Every other tile takes the general body; both compute the same
+// products in the same order.
+template <int MODE, bool FAST>
+__device__ __forceinline__ void sgemm_tile(int64_t M, int64_t N, int64_t K,
+                                           const float *__restrict__ A, int64_t lda,
+                                           const float *__restrict__ B, int64_t ldb, float *C,
+                                           int64_t ldc, int64_t m0, int64_t n0, Smem<MODE> &sm) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -90,10 +82,10 @@ __global__ void __launch_bounds__(256, 2)
   const int hm = tid & (BM - 1), hk = 16 * (tid >> 7);
   const int bn = tid >> 1, bk = 16 * (tid & 1);
   f4 ra[4], rb[4];
-  const bool interior = (m0 + BM <= M) && (n0 + BN <= N);
+  const bool interior = FAST || ((m0 + BM <= M) && (n0 + BN <= N));
 
   auto load_stage = [&](int64_t k0) {
-    const bool fast = interior && k0 + BK <= K;
+    const bool fast = FAST || (interior && k0 + BK <= K);
     if constexpr (MODE == kF32) {
       if (fast) {
 #pragma unroll
@@ -217,7 +209,7 @@ __global__ void __launch_bounds__(256, 2)
   // Whole tiles issue all 16 loads of C before the first store (a load of C
   // cannot be moved above a store to C by the compiler, which would
   // otherwise cost one round trip per load); edge tiles go element-wise.
-  if (m0 + BM <= M && n0 + BN <= N) {
+  if (interior) {
     float *cp = C + (m0 + wm * 64 + 4 * lk) + (n0 + wn * 64 + l16) * ldc;
     f4u c[4][4];
 #pragma unroll
@@ -257,6 +249,29 @@ __global__ void __launch_bounds__(256, 2)
   }
 }
 
+template <int MODE, bool TRAILING>
+__global__ void __launch_bounds__(256, 2)
+    k_sgemm(int64_t M, int64_t N, int64_t K, const float *__restrict__ A, int64_t lda,
+            const float *__restrict__ B, int64_t ldb, float *C, int64_t ldc, int tiles_m,
+            int total) {
+  __shared__ Smem<MODE> sm;
+
+  int pid = blockIdx.x;
+  const int full = (total / 8) * 8;
+  if (pid < full) pid = (pid % 8) * (total / 8) + pid / 8;
+  const int tiles_n = total / tiles_m;
+  const int group = pid / (GM * tiles_n);
+  const int first_m = group * GM;
+  const int gsize = (tiles_m - first_m) < GM ? (tiles_m - first_m) : GM;
+  const int in_group = pid - group * GM * tiles_n;
+  const int tm = first_m + in_group % gsize, tn = in_group / gsize;
+  const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
+  if (m0 + BM <= M && n0 + BN <= N && K % BK == 0)
+    sgemm_tile<MODE, true>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sm);
+  else
+    sgemm_tile<MODE, false>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sm);
+}
+
 // Small tiles for the depth-128 updates inside and beside the panel (one
 // dimension at most 896): 64 x 64 block tiles, 4 wavefronts of 32 x 32 (2 x 2
 // MFMA tiles), K in slices of 32, 34 KB (FP32) / 20 KB (BF16) of LDS so that
@@ -277,24 +292,13 @@ struct SmemS<kBF16> {
   alignas(16) __bf16 Bh[2][SN][BK + PAD_H];
 };
 
-template <int MODE>
-__global__ void __launch_bounds__(256, 4)
-    k_sgemm_small(int64_t M, int64_t N, int64_t K, const float *__restrict__ A, int64_t lda,
-                  const float *__restrict__ B, int64_t ldb, float *C, int64_t ldc, int tiles_m,
-                  int total) {
-  __shared__ SmemS<MODE> sm;
-
-  int pid = blockIdx.x;
-  const int full = (total / 8) * 8;
-  if (pid < full) pid = (pid % 8) * (total / 8) + pid / 8;
-  const int tiles_n = total / tiles_m;
-  const int group = pid / (GM * tiles_n);
-  const int first_m = group * GM;
-  const int gsize = (tiles_m - first_m) < GM ? (tiles_m - first_m) : GM;
-  const int in_group = pid - group * GM * tiles_n;
-  const int tm = first_m + in_group % gsize, tn = in_group / gsize;
-  const int64_t m0 = int64_t(tm) * SM, n0 = int64_t(tn) * SN;
-
+// One 64 x 64 block tile; FAST as for the large tiles.
+template <int MODE, bool FAST>
+__device__ __forceinline__ void sgemm_small_tile(int64_t M, int64_t N, int64_t K,
+                                                 const float *__restrict__ A, int64_t lda,
+                                                 const float *__restrict__ B, int64_t ldb,
+                                                 float *C, int64_t ldc, int64_t m0, int64_t n0,
+                                                 SmemS<MODE> &sm) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -315,10 +319,10 @@ __global__ void __launch_bounds__(256, 4)
   const int hm = tid & (SM - 1), hk = 8 * (tid >> 6);
   const int bn = tid >> 2, bk = 8 * (tid & 3);
   f4 ra[2], rb[2];
-  const bool interior = (m0 + SM <= M) && (n0 + SN <= N);
+  const bool interior = FAST || ((m0 + SM <= M) && (n0 + SN <= N));
 
   auto load_stage = [&](int64_t k0) {
-    const bool fast = interior && k0 + BK <= K;
+    const bool fast = FAST || (interior && k0 + BK <= K);
     if constexpr (MODE == kF32) {
       if (fast) {
 #pragma unroll
@@ -466,6 +470,29 @@ __global__ void __launch_bounds__(256, 4)
         if (row + v < M) p[v] -= acc[i][j][v];
     }
   }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256, 4)
+    k_sgemm_small(int64_t M, int64_t N, int64_t K, const float *__restrict__ A, int64_t lda,
+                  const float *__restrict__ B, int64_t ldb, float *C, int64_t ldc, int tiles_m,
+                  int total) {
+  __shared__ SmemS<MODE> sm;
+
+  int pid = blockIdx.x;
+  const int full = (total / 8) * 8;
+  if (pid < full) pid = (pid % 8) * (total / 8) + pid / 8;
+  const int tiles_n = total / tiles_m;
+  const int group = pid / (GM * tiles_n);
+  const int first_m = group * GM;
+  const int gsize = (tiles_m - first_m) < GM ? (tiles_m - first_m) : GM;
+  const int in_group = pid - group * GM * tiles_n;
+  const int tm = first_m + in_group % gsize, tn = in_group / gsize;
+  const int64_t m0 = int64_t(tm) * SM, n0 = int64_t(tn) * SN;
+  if (m0 + SM <= M && n0 + SN <= N && K % BK == 0)
+    sgemm_small_tile<MODE, true>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sm);
+  else
+    sgemm_small_tile<MODE, false>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sm);
 }
 
 template <int MODE>
