@@ -125,6 +125,13 @@ __global__ void __launch_bounds__(TPB)
       bpre[c] = (sg == 0 && i < kb && c < N) ? B[(r0 + i) + int64_t(c) * ldb] : 0.0;
   }
 
+  // One right-hand side with FP64 factors: the diagonal block of the
+  // refinement step is loaded here too (after the last wait its memory
+  // latency would sit on the sweep's critical path).
+  constexpr bool PRE_T = REFINE && NMAX == 1;
+  TF etp[PRE_T ? SEGW : 1];
+  if constexpr (PRE_T) load_tdiag(etp);
+
   // ---- accumulate op(A)[b, j] x_j over the blocks solved before b ----
   double acc[NMAX];
 #pragma unroll
@@ -177,7 +184,12 @@ __global__ void __launch_bounds__(TPB)
   // diagonal block of the refinement step only while registers allow)
   constexpr bool EARLY_T = REFINE && NMAX <= 8;
   TF et[REFINE ? SEGW : 1];
-  if constexpr (EARLY_T) load_tdiag(et);
+  if constexpr (PRE_T) {
+#pragma unroll
+    for (int q = 0; q < SEGW; ++q) et[q] = etp[q];
+  } else if constexpr (EARLY_T) {
+    load_tdiag(et);
+  }
   // 16 right-hand sides: FP32 factors take the inverse here; FP64 factors
   // (more registers live) load it at each use
   constexpr bool EARLY_D = !PRE && !REFINE;
@@ -269,7 +281,9 @@ __global__ void __launch_bounds__(TPB)
     for (int c = 0; c < NMAX; ++c)
       if (c < N) coherent_store(&B[(r0 + i) + int64_t(c) * ldb], x[c]);
   }
-  __threadfence();
+  // only the threads that stored need the device-scope fence (one per
+  // wavefront of them instead of all eight: each fence writes back the L2)
+  if (sg == 0) __threadfence();
   __syncthreads();
   // every block of a smaller ticket is published (this one consumed them
   // all) and none of a larger ticket is, so done == t here
