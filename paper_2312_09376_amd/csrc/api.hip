@@ -162,6 +162,26 @@ hipError_t gemm_sub(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda
   return launch_sgemm_sub(M, N, K, A, lda, B, ldb, C, ldc, prec == RBT_BF16, trailing, s);
 }
 
+// Both updates that follow a diagonal block's solves inside a panel:
+// C0 -= A0 B0 (the panel's columns right of the block, rows below it) and
+// C1 -= A1 B1 (the block row's columns right of the panel, the panel's rows
+// below the block); depth K, leading dimension ld. One launch in FP64.
+hipError_t gemm_sub2(int64_t K, int64_t ld, int64_t M0, int64_t N0, const double *A0,
+                     const double *B0, double *C0, int64_t M1, int64_t N1, const double *A1,
+                     const double *B1, double *C1, int /*prec*/, hipStream_t s) {
+  return launch_dgemm_sub2(K, ld, M0, N0, A0, B0, C0, M1, N1, A1, B1, C1, s);
+}
+hipError_t gemm_sub2(int64_t K, int64_t ld, int64_t M0, int64_t N0, const float *A0,
+                     const float *B0, float *C0, int64_t M1, int64_t N1, const float *A1,
+                     const float *B1, float *C1, int prec, hipStream_t s) {
+  if (M0 > 0 && N0 > 0) {
+    const hipError_t e = gemm_sub(M0, N0, K, A0, ld, B0, ld, C0, ld, prec, false, s);
+    if (e != hipSuccess) return e;
+  }
+  if (M1 > 0 && N1 > 0) return gemm_sub(M1, N1, K, A1, ld, B1, ld, C1, ld, prec, false, s);
+  return hipSuccess;
+}
+
 // Blocked right-looking elimination without pivoting, two levels:
 // the matrix is processed in panels of width W (a multiple of kNB); inside a
 // panel, kNB-wide steps factor the diagonal block, solve the rows below it
@@ -224,8 +244,14 @@ int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t
               void *stage = nullptr, size_t stage_bytes = 0) {
   if (info) RBT_HIP_CHECK(launch_fill_i32(info, 0, s));
   const int64_t W = options().outer_nb;
-  // ---- factor the panel A[k0:n, k0:k0+w] (on s) ----
-  auto panel = [&](int64_t k0, int64_t w) -> int {
+  // ---- factor the panel A[k0:n, k0:k0+w] (on s). The nt columns right of
+  // the panel take their block row U12 = L11^-1 A12 here as well, kNB rows
+  // at a time: each diagonal block's left solve runs over the panel's
+  // columns and those nt together, and the update of the panel's rows below
+  // the block joins the panel's own update in one launch (the same
+  // operations on every element as solving the block row after the panel,
+  // in fewer launches). ----
+  auto panel = [&](int64_t k0, int64_t w, int64_t nt) -> int {
     for (int64_t k = k0; k < k0 + w; k += kNB) {
       const int kb = int(k0 + w - k < kNB ? k0 + w - k : kNB);
       T *A11 = A + k + k * lda;
@@ -234,25 +260,28 @@ int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t
         RBT_HIP_CHECK(launch_diag_lu(kb, A11, lda, k, info, s));
       }
       const int64_t rows = n - k - kb;      // rows below the diagonal block
-      const int64_t pc = k0 + w - k - kb;   // panel columns right of it
+      const int64_t pc = k0 + w - k - kb;   // panel columns right of it (= panel rows below it)
       {
-        StageScope t(kStagePanel, s, double(rows) * kb * kb + double(pc) * kb * kb);
-        RBT_HIP_CHECK(launch_panel_trsm(kb, rows, pc, A11, lda, A + (k + kb) + k * lda,
+        StageScope t(kStagePanel, s, double(rows) * kb * kb + double(pc + nt) * kb * kb);
+        RBT_HIP_CHECK(launch_panel_trsm(kb, rows, pc + nt, A11, lda, A + (k + kb) + k * lda,
                                         A + k + (k + kb) * lda, lda, s));
       }
-      if (pc > 0 && rows > 0) {
-        StageScope t(kStagePanel, s, 2.0 * double(rows) * pc * kb);
-        RBT_HIP_CHECK(gemm_sub(rows, pc, kb, A + (k + kb) + k * lda, lda, A + k + (k + kb) * lda,
-                               lda, A + (k + kb) + (k + kb) * lda, lda, prec, false, s));
+      if (pc > 0 && (rows > 0 || nt > 0)) {
+        StageScope t(kStagePanel, s, 2.0 * double(kb) * (double(rows) * pc + double(pc) * nt));
+        RBT_HIP_CHECK(gemm_sub2(kb, lda, rows, pc, A + (k + kb) + k * lda, A + k + (k + kb) * lda,
+                                A + (k + kb) + (k + kb) * lda, pc, nt, A + (k + kb) + k * lda,
+                                A + k + (k0 + w) * lda, A + (k + kb) + (k0 + w) * lda, prec, s));
       }
     }
     return 0;
   };
   // ---- columns [c0, c0 + nc) right of the panel [k0, k0 + w): block row
-  // U12 = L11^-1 A12 (L11: w x w unit lower, kNB rows at a time), then
-  // A22 -= L21 U12 with one GEMM of depth w (on stream st) ----
-  auto update = [&](int64_t k0, int64_t w, int64_t c0, int64_t nc, hipStream_t st) -> int {
-    for (int64_t k = k0; k < k0 + w; k += kNB) {
+  // U12 = L11^-1 A12 (L11: w x w unit lower, kNB rows at a time; skipped
+  // when the panel solved it: rows_done), then A22 -= L21 U12 with one GEMM
+  // of depth w (on stream st) ----
+  auto update = [&](int64_t k0, int64_t w, int64_t c0, int64_t nc, hipStream_t st,
+                    bool rows_done) -> int {
+    for (int64_t k = k0; k < k0 + w && !rows_done; k += kNB) {
       const int kb = int(k0 + w - k < kNB ? k0 + w - k : kNB);
       const int64_t below = k0 + w - k - kb;
       {
@@ -295,23 +324,28 @@ int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t
     const int64_t w = k0 == 0 ? W + r0 : W;
     return n - k0 < w ? n - k0 : w;
   };
-  int rc = panel(0, width(0));
+  // Without lookahead every panel solves the block rows of all columns to
+  // its right; with it the block rows stay in the updates, which the second
+  // stream runs while the next panel is factored.
+  const bool la = s2 != nullptr;
+  auto trailing_cols = [&](int64_t k0, int64_t w) { return la ? int64_t(0) : n - k0 - w; };
+  int rc = panel(0, width(0), trailing_cols(0, width(0)));
   if (rc) return rc;
   for (int64_t k0 = 0, w = width(0);; k0 += w, w = width(k0)) {
     const int64_t rest = n - k0 - w;  // columns right of the panel
     if (rest <= 0) break;
     const int64_t wn = width(k0 + w);  // next panel
-    const bool split = s2 != nullptr && rest > wn;
+    const bool split = la && rest > wn;
     if (split) {
       RBT_HIP_CHECK(hipEventRecord(ev.f, s));
       RBT_HIP_CHECK(hipStreamWaitEvent(s2, ev.f, 0));
-      rc = update(k0, w, k0 + w + wn, rest - wn, s2);
+      rc = update(k0, w, k0 + w + wn, rest - wn, s2, !la);
       if (rc) return rc;
       RBT_HIP_CHECK(hipEventRecord(ev.b, s2));
     }
-    rc = update(k0, w, k0 + w, split ? wn : rest, s);
+    rc = update(k0, w, k0 + w, split ? wn : rest, s, !la);
     if (rc) return rc;
-    rc = panel(k0 + w, wn);
+    rc = panel(k0 + w, wn, trailing_cols(k0 + w, wn));
     if (rc) return rc;
     if (split) RBT_HIP_CHECK(hipStreamWaitEvent(s, ev.b, 0));
   }

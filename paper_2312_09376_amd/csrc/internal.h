@@ -95,6 +95,13 @@ hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, const double *A, int64_
 hipError_t launch_dgemm_tiles(int tile, int64_t M, int64_t N, int64_t K, const double *A,
                               int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc,
                               hipStream_t s);
+// C0 -= A0 B0 (M0 x N0) and C1 -= A1 B1 (M1 x N1), General operands, depth K,
+// leading dimension ld for all six, in one launch of the 64 x 64 tiles (the
+// same results as two launches of launch_dgemm with Acc::Subtract). The two
+// C regions must not overlap each other or the other update's operands.
+hipError_t launch_dgemm_sub2(int64_t K, int64_t ld, int64_t M0, int64_t N0, const double *A0,
+                             const double *B0, double *C0, int64_t M1, int64_t N1,
+                             const double *A1, const double *B1, double *C1, hipStream_t s);
 // k_sgemm.hip : C -= A B with FP32 storage; bf16: BF16 operands on the matrix
 // cores (FP32 accumulation), else FP32 operands. trailing: separate kernel
 // instance for the trailing update (same arithmetic).

@@ -504,14 +504,15 @@ __device__ __forceinline__ void small_tile(int64_t M, int64_t N, int64_t K, cons
   }
 }
 
+// Tile `bid` of a grid of `total` 64 x 64 tiles over C (M x N), with the
+// same XCD-aware and grouped order as the large tiles.
 template <Acc AC>
-__global__ void __launch_bounds__(256, 4)
-    k_dgemm_small(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
-                  const double *B, int64_t ldb, double *C, int64_t ldc, int tiles_m, int total) {
-  __shared__ double As[2][SK][SM + PADA];
-  __shared__ double Bs[2][SN][SK + PADB];
-
-  int pid = blockIdx.x;
+__device__ __forceinline__ void small_grid_tile(int bid, int64_t M, int64_t N, int64_t K,
+                                                const double *A, int64_t lda, const double *B,
+                                                int64_t ldb, double *C, int64_t ldc, int tiles_m,
+                                                int total, double (&As)[2][SK][SM + PADA],
+                                                double (&Bs)[2][SN][SK + PADB]) {
+  int pid = bid;
   const int full = (total / 8) * 8;
   if (pid < full) pid = (pid % 8) * (total / 8) + pid / 8;
   const int tiles_n = total / tiles_m;
@@ -528,6 +529,42 @@ __global__ void __launch_bounds__(256, 4)
     small_tile<AC, false>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, As, Bs);
 }
 
+template <Acc AC>
+__global__ void __launch_bounds__(256, 4)
+    k_dgemm_small(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                  const double *B, int64_t ldb, double *C, int64_t ldc, int tiles_m, int total) {
+  __shared__ double As[2][SK][SM + PADA];
+  __shared__ double Bs[2][SN][SK + PADB];
+  small_grid_tile<AC>(int(blockIdx.x), M, N, K, A, lda, B, ldb, C, ldc, tiles_m, total, As, Bs);
+}
+
+// Two updates C -= A B of one depth K and one leading dimension in one
+// launch: workgroups [0, start1) take the tiles of the first (the ids
+// beyond its tile count exit; start1 is a multiple of 8 so that both keep
+// their XCD order), the rest those of the second. Each tile computes what
+// it computes in a launch of its own.
+struct SubGemm {
+  int64_t M, N;
+  const double *A, *B;
+  double *C;
+  int tiles_m, total;
+};
+
+__global__ void __launch_bounds__(256, 4)
+    k_dgemm_small2(int64_t K, int64_t ld, SubGemm p0, SubGemm p1, int start1) {
+  __shared__ double As[2][SK][SM + PADA];
+  __shared__ double Bs[2][SN][SK + PADB];
+  int bid = int(blockIdx.x);
+  if (bid >= start1) {
+    bid -= start1;
+    small_grid_tile<Acc::Subtract>(bid, p1.M, p1.N, K, p1.A, ld, p1.B, ld, p1.C, ld, p1.tiles_m,
+                                   p1.total, As, Bs);
+  } else if (bid < p0.total) {
+    small_grid_tile<Acc::Subtract>(bid, p0.M, p0.N, K, p0.A, ld, p0.B, ld, p0.C, ld, p0.tiles_m,
+                                   p0.total, As, Bs);
+  }
+}
+
 hipError_t launch_small(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
                         const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t s) {
   const int64_t tm = (M + SM - 1) / SM, tn = (N + SN - 1) / SN;
@@ -536,6 +573,15 @@ hipError_t launch_small(int64_t M, int64_t N, int64_t K, const double *A, int64_
   hipLaunchKernelGGL((k_dgemm_small<Acc::Subtract>), dim3(unsigned(total)), dim3(256), 0, s, M, N,
                      K, A, lda, B, ldb, C, ldc, int(tm), int(total));
   return hipGetLastError();
+}
+
+SubGemm sub_gemm(int64_t M, int64_t N, const double *A, const double *B, double *C) {
+  SubGemm g{M, N, A, B, C, 0, 0};
+  if (M > 0 && N > 0) {
+    g.tiles_m = int((M + SM - 1) / SM);
+    g.total = int(int64_t(g.tiles_m) * ((N + SN - 1) / SN));
+  }
+  return g;
 }
 
 template <OpA OA, OpB OB, Acc AC>
@@ -584,6 +630,20 @@ hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, const double *A, int64_
   RBT_GEMM_CASE(OpA::UpperT, OpB::General, Acc::Overwrite)
 #undef RBT_GEMM_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_dgemm_sub2(int64_t K, int64_t ld, int64_t M0, int64_t N0, const double *A0,
+                             const double *B0, double *C0, int64_t M1, int64_t N1,
+                             const double *A1, const double *B1, double *C1, hipStream_t s) {
+  if (K <= 0) return hipSuccess;
+  const int64_t t0 = M0 > 0 && N0 > 0 ? ((M0 + SM - 1) / SM) * ((N0 + SN - 1) / SN) : 0;
+  const int64_t t1 = M1 > 0 && N1 > 0 ? ((M1 + SM - 1) / SM) * ((N1 + SN - 1) / SN) : 0;
+  const int64_t start1 = (t0 + 7) / 8 * 8;
+  if (start1 + t1 > 0x7fffffff) return hipErrorInvalidValue;
+  if (start1 + t1 == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dgemm_small2, dim3(unsigned(start1 + t1)), dim3(256), 0, s, K, ld,
+                     sub_gemm(M0, N0, A0, B0, C0), sub_gemm(M1, N1, A1, B1, C1), int(start1));
+  return hipGetLastError();
 }
 
 }  // namespace rbt
