@@ -1,18 +1,19 @@
 // Diagonal-block kernel of the blocked elimination without pivoting.
 //
-// One workgroup of 256 threads factors a kb x kb diagonal block (kb <= 128)
+// One workgroup of 512 threads factors a kb x kb diagonal block (kb <= 128)
 // in place, A = L U with unit-lower L (Sec. 1, step 2: GENP). The block is
 // held in LDS (column-major, leading dimension 129 so that row-wise and
 // column-wise lane patterns are both bank-conflict free) and eliminated in
 // eight 16-column steps:
-//   1. the 16-column panel is factored right-looking, rank-1, by the four
-//      wavefronts, one row per lane; every wavefront keeps its own copy of
+//   1. the 16-column panel is factored right-looking, rank-1, by four of the
+//      eight wavefronts, one row per lane; every wavefront keeps its own copy of
 //      the panel's top 16 rows, so each pivot row is broadcast within the
 //      wavefront with readlane and the 16 steps need no workgroup barrier;
 //   2. the 16-row block of U to its right is solved by forward substitution
 //      with the panel's unit-lower 16 x 16 block (four lanes per column);
 //   3. the trailing block takes a rank-16 update on the FP64 matrix cores,
-//      16 x 16 tiles shared out over the four wavefronts; each tile's
+//      16 x 16 tiles shared out over the eight wavefronts (two per SIMD, so
+//      one wavefront's LDS accesses overlap the other's products); each tile's
 //      accumulator starts from the LDS values and the L operand is negated.
 // Rows and columns beyond kb hold the identity, so they never disturb the
 // active part. The block may be stored in FP32 (mixed-precision elimination):
@@ -28,6 +29,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int NB = kNB;  // 128
 constexpr int LD = NB + 1;
 constexpr int PW = 16;   // panel width
+constexpr int NT = 512;  // threads
+constexpr int NW = NT / 64;
 
 // Value of v in lane `src` (uniform) of the wavefront.
 __device__ __forceinline__ double wave_bcast(double v, int src) {
@@ -55,7 +58,7 @@ __device__ __forceinline__ double quad_bcast(double v, int k) {  // k: compile-t
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_diag_lu(int kb, T *__restrict__ A, int64_t lda,
+__global__ void __launch_bounds__(NT) k_diag_lu(int kb, T *__restrict__ A, int64_t lda,
                                                  int64_t gofs, int32_t *__restrict__ info) {
   __shared__ double S[NB * LD];
 
@@ -66,19 +69,19 @@ __global__ void __launch_bounds__(256) k_diag_lu(int kb, T *__restrict__ A, int6
   // Staging: every load of a batch is issued before any is consumed, so the
   // batch costs one memory latency instead of one per element.
   {
-    const int r = tid & (NB - 1), c0 = tid >> 7;  // row, first column (0/1)
-    // unconditional loads at clamped valid indices, all 64 in flight,
+    const int r = tid & (NB - 1), c0 = tid >> 7;  // row, first column (0..3)
+    // unconditional loads at clamped valid indices, all 32 in flight,
     // masked afterwards
-    T v[64];
+    T v[NB * NB / NT];
     const int rr = r < kb ? r : kb - 1;
 #pragma unroll
-    for (int i = 0; i < 64; ++i) {
-      const int c = c0 + 2 * i;
+    for (int i = 0; i < NB * NB / NT; ++i) {
+      const int c = c0 + (NT / NB) * i;
       v[i] = A[rr + int64_t(c < kb ? c : kb - 1) * lda];
     }
 #pragma unroll
-    for (int i = 0; i < 64; ++i) {
-      const int c = c0 + 2 * i;
+    for (int i = 0; i < NB * NB / NT; ++i) {
+      const int c = c0 + (NT / NB) * i;
       S[c * LD + r] = (r < kb && c < kb) ? double(v[i]) : ((r == c) ? 1.0 : 0.0);
     }
   }
@@ -92,7 +95,7 @@ __global__ void __launch_bounds__(256) k_diag_lu(int kb, T *__restrict__ A, int6
     // readlane and no barrier is needed; lanes 16..63 hold one row below
     // them each (48 per wavefront). Rows above the pivot take a zero
     // multiplier. ----
-    {
+    if (wave < 4) {
       const bool top = lane < PW;
       const int row = top ? c0 + lane : c0 + PW + wave * 48 + (lane - PW);
       const bool valid = row < NB;
@@ -139,22 +142,18 @@ __global__ void __launch_bounds__(256) k_diag_lu(int kb, T *__restrict__ A, int6
     if (c1 >= NB) break;
     // ---- 2. U block row: rows c0..c0+15, columns c1..127, by forward
     // substitution with the unit-lower 16 x 16 block: four lanes per column
-    // (lane q of a quad holds rows q, q + 4, q + 8, q + 12), columns
-    // c1 + g and c1 + 64 + g for quad g, the pivot entry passed on by a quad
-    // broadcast and the next pivot's coefficients read during this one.
-    // Every entry sees the same operations in the same order as one-lane-
-    // per-column substitution. ----
+    // (lane q of a quad holds rows q, q + 4, q + 8, q + 12), column c1 + g
+    // for quad g, the pivot entry passed on by a quad broadcast and the next
+    // pivot's coefficients read during this one. Every entry sees the same
+    // operations in the same order as one-lane-per-column substitution. ----
     {
       const int g = tid >> 2, q = tid & 3;
-      const int colA = c1 + g, colB = c1 + 64 + g;
-      const bool hasA = colA < NB, hasB = colB < NB;
-      const int ca = hasA ? colA : NB - 1, cb = hasB ? colB : NB - 1;
-      double ya[4], yb[4];
+      const int colA = c1 + g;
+      const bool hasA = colA < NB;
+      const int ca = hasA ? colA : NB - 1;
+      double ya[4];
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        ya[jj] = S[ca * LD + c0 + q + 4 * jj];
-        yb[jj] = S[cb * LD + c0 + q + 4 * jj];
-      }
+      for (int jj = 0; jj < 4; ++jj) ya[jj] = S[ca * LD + c0 + q + 4 * jj];
       double tn[4];
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) tn[jj] = S[c0 * LD + c0 + q + 4 * jj];
@@ -169,34 +168,28 @@ __global__ void __launch_bounds__(256) k_diag_lu(int kb, T *__restrict__ A, int6
           for (int jj = 0; jj < 4; ++jj) tn[jj] = S[(c0 + j + 1) * LD + c0 + q + 4 * jj];
         }
         __builtin_amdgcn_sched_barrier(0);
-        const double ba = quad_bcast(ya[jc], qc), bb = quad_bcast(yb[jc], qc);
+        const double ba = quad_bcast(ya[jc], qc);
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
           if (4 * jj + 3 <= j) continue;
           const bool upd = 4 * jj > j || q + 4 * jj > j;
           const double na = __builtin_fma(-t[jj], ba, ya[jj]);
-          const double nb = __builtin_fma(-t[jj], bb, yb[jj]);
           ya[jj] = upd ? na : ya[jj];
-          yb[jj] = upd ? nb : yb[jj];
         }
       }
       if (hasA) {
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) S[colA * LD + c0 + q + 4 * jj] = ya[jj];
       }
-      if (hasB) {
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) S[colB * LD + c0 + q + 4 * jj] = yb[jj];
-      }
     }
     __syncthreads();
     // ---- 3. trailing rank-16 update on 16 x 16 tiles, two per wavefront
-    // at a time (tiles t and t + 4), so their LDS loads overlap ----
+    // at a time (tiles t and t + NW), so their LDS loads overlap ----
     const int nt = (NB - c1) / PW;
     const int ntt = nt * nt;
-    for (int t = wave; t < ntt; t += 8) {
-      const bool two = t + 4 < ntt;
-      const int tb = two ? t + 4 : t;
+    for (int t = wave; t < ntt; t += 2 * NW) {
+      const bool two = t + NW < ntt;
+      const int tb = two ? t + NW : t;
       const int i0 = c1 + PW * (t % nt), j0 = c1 + PW * (t / nt);
       const int i1 = c1 + PW * (tb % nt), j1 = c1 + PW * (tb / nt);
       d4 acc0, acc1;
@@ -231,8 +224,8 @@ __global__ void __launch_bounds__(256) k_diag_lu(int kb, T *__restrict__ A, int6
   {
     const int rr = tid & (NB - 1), c0 = tid >> 7;
 #pragma unroll 16
-    for (int i = 0; i < 64; ++i) {
-      const int c = c0 + 2 * i;
+    for (int i = 0; i < NB * NB / NT; ++i) {
+      const int c = c0 + (NT / NB) * i;
       if (rr < kb && c < kb) A[rr + int64_t(c) * lda] = T(S[c * LD + rr]);
     }
   }
@@ -244,7 +237,7 @@ template <typename T>
 hipError_t diag_lu_t(int kb, T *A, int64_t lda, int64_t gofs, int32_t *info, hipStream_t s) {
   if (kb <= 0) return hipSuccess;
   if (kb > kNB) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_diag_lu<T>, dim3(1), dim3(256), 0, s, kb, A, lda, gofs, info);
+  hipLaunchKernelGGL(k_diag_lu<T>, dim3(1), dim3(NT), 0, s, kb, A, lda, gofs, info);
   return hipGetLastError();
 }
 
