@@ -249,7 +249,9 @@ __device__ __forceinline__ void sgemm_tile(int64_t M, int64_t N, int64_t K,
   }
 }
 
-template <int MODE, bool TRAILING>
+// WHOLE: every tile is interior and K a multiple of BK (the launcher
+// checks); the kernel then holds only the fast tile body.
+template <int MODE, bool TRAILING, bool WHOLE = false>
 __global__ void __launch_bounds__(256, 2)
     k_sgemm(int64_t M, int64_t N, int64_t K, const float *__restrict__ A, int64_t lda,
             const float *__restrict__ B, int64_t ldb, float *C, int64_t ldc, int tiles_m,
@@ -266,9 +268,9 @@ __global__ void __launch_bounds__(256, 2)
   const int in_group = pid - group * GM * tiles_n;
   const int tm = first_m + in_group % gsize, tn = in_group / gsize;
   const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
-  if (m0 + BM <= M && n0 + BN <= N && K % BK == 0)
+  if (WHOLE || (m0 + BM <= M && n0 + BN <= N && K % BK == 0))
     sgemm_tile<MODE, true>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sm);
-  else
+  else if constexpr (!WHOLE)
     sgemm_tile<MODE, false>(M, N, K, A, lda, B, ldb, C, ldc, m0, n0, sm);
 }
 
@@ -512,6 +514,13 @@ hipError_t launch_t(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda
   const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
   const int64_t total = tm * tn;
   if (total > 0x7fffffff) return hipErrorInvalidValue;
+  if constexpr (TRAILING) {
+    if (M % BM == 0 && N % BN == 0 && K % BK == 0) {
+      hipLaunchKernelGGL((k_sgemm<MODE, TRAILING, true>), dim3(unsigned(total)), dim3(256), 0, s,
+                         M, N, K, A, lda, B, ldb, C, ldc, int(tm), int(total));
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((k_sgemm<MODE, TRAILING>), dim3(unsigned(total)), dim3(256), 0, s, M, N, K,
                      A, lda, B, ldb, C, ldc, int(tm), int(total));
   return hipGetLastError();
