@@ -106,6 +106,32 @@ def test_genp_matches_oracle(rbt, n):
     assert np.abs(L - LUo).max() <= 1e-12 * max(1.0, np.abs(LUo).max())
 
 
+@pytest.mark.parametrize("n,W", [(700, 256), (1290, 512), (640, 128), (1000, 384)])
+def test_genp_multi_panel_matches_oracle(rbt, n, W):
+    """Several panels (Sec. 1, step 2: GENP): the first panel also takes the
+    n mod 128 columns, the trailing updates cover whole 128 x 128 tiles, and
+    each diagonal block's left solve and depth-128 updates reach the block
+    row right of the panel. Element by element against the oracle's
+    unblocked elimination on I + 0.3 N(0,1)/sqrt(n), whose leading minors are
+    all well conditioned (without pivoting, a matrix with ill-conditioned
+    leading minors amplifies the different rounding order of the blocked
+    elimination), and L U = A to the rounding bound of elimination."""
+    A = workloads.dominant(n, seed=n + 7)
+    LUo, info_o = osolve.genp_unblocked(A)
+    old_w = rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)
+    rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, W)
+    try:
+        LU, info = rbt.genp(dev(A))
+        torch.cuda.synchronize()
+    finally:
+        rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, old_w)
+    assert int(info.item()) == info_o == 0
+    L = host(LU)
+    assert np.abs(L - LUo).max() <= 1e-12 * max(1.0, np.abs(LUo).max())
+    Lm, Um = np.tril(L, -1) + np.eye(n), np.triu(L)
+    assert np.abs(Lm @ Um - A).max() <= 2 * n * EPS * (np.abs(Lm) @ np.abs(Um)).max()
+
+
 def test_genp_randn_reconstruction(rbt):
     n = 700
     A = workloads.randn_matrix(n, seed=1)
