@@ -185,10 +185,11 @@ hipError_t gemm_sub2(int64_t K, int64_t ld, int64_t M0, int64_t N0, const float 
 // Blocked right-looking elimination without pivoting, two levels:
 // the matrix is processed in panels of width W (a multiple of kNB); inside a
 // panel, kNB-wide steps factor the diagonal block, solve the rows below it
-// (L part) and update the rest of the panel only; then the panel's block row
-// U12 = L11^-1 A12 is solved (kNB rows at a time) and the trailing matrix is
-// updated by one GEMM of depth W, which keeps the GEMM's read-modify-write of
-// A22 well under the HBM bandwidth at matrix-core rate.
+// (L part) and its block row (U part, kNB rows of the panel's block row
+// U12 = L11^-1 A12 at a time), and update the rest of the panel and of its
+// block row; then the trailing matrix is updated by one GEMM of depth W,
+// which keeps the GEMM's read-modify-write of A22 well under the HBM
+// bandwidth at matrix-core rate.
 // T = double: FP64 throughout. T = float (mixed precision): FP32 storage;
 // diagonal blocks and triangular solves computed in FP64 and rounded on
 // store; GEMM updates with FP32 (prec RBT_FP32) or BF16 (RBT_BF16) operands.

@@ -18,8 +18,9 @@
 // bounded (kSpinLimit sleeps); a workgroup that reaches the bound records it
 // in the error word and goes on, so the grid always drains.
 //
-// Coherence across XCDs: x_b is stored with agent-scope atomic stores, then
-// a device fence and a release store of `done`; waiters poll `done` with
+// Coherence across XCDs: x_b is stored with agent-scope atomic stores by
+// the threads that hold it, each of them takes a device fence, and after a
+// workgroup barrier one thread makes a release store of `done`; waiters poll `done` with
 // relaxed agent-scope loads (no cache invalidation per poll), take one
 // acquire fence when it has advanced, and read x_j with agent-scope atomic
 // loads.
@@ -181,7 +182,8 @@ __global__ void __launch_bounds__(TPB)
   }
 
   // loads of the diagonal work, issued before the reductions (the FP64
-  // diagonal block of the refinement step only while registers allow)
+  // diagonal block of the refinement step only while registers allow;
+  // with one right-hand side it was loaded before the waits)
   constexpr bool EARLY_T = REFINE && NMAX <= 8;
   TF et[REFINE ? SEGW : 1];
   if constexpr (PRE_T) {
