@@ -13,9 +13,9 @@
 // the first step: the 28 off-diagonal 16 x 16 blocks of the triangle in
 // matrix-core operand order (56 KB), the eight diagonal blocks in the order
 // the substitution reads them (16 KB), and each wavefront's right-hand-side
-// strip (16 KB). After that a wavefront only talks to its own strip, so the
-// steps need no workgroup barrier (LDS accesses of one wavefront complete
-// in issue order). 136 KB of LDS: one workgroup per CU.
+// strip (17 KB, padded rows). After that a wavefront only talks to its own
+// strip, so the steps need no workgroup barrier (LDS accesses of one
+// wavefront complete in issue order). 140 KB of LDS: one workgroup per CU.
 //
 // Substitution inside a diagonal block: the 64 lanes hold 16 independent
 // right-hand sides x 4 lanes (a quad), lane q of a quad holding entries
@@ -55,6 +55,11 @@ constexpr int IB = 16;
 constexpr int NBK = NB / IB;  // 8 diagonal blocks
 constexpr int BLK = IB * IB;  // 256 doubles per block
 constexpr int NOFF = NBK * (NBK - 1) / 2;  // 28 off-diagonal blocks on one side
+// A wavefront's strip holds 128 vectors of 16 doubles, 17 apart: with a
+// stride of 16 (128 bytes) the lanes that each own one vector hit the same
+// LDS banks when staging and storing it back (65 % of the LDS cycles were
+// bank conflicts).
+constexpr int SLD = IB + 1;
 
 template <TriMode MODE>
 constexpr bool forward_order() {
@@ -153,7 +158,7 @@ __device__ __forceinline__ void quad_substitute(double (&x)[4], const double *tq
 struct TrsmSmem {
   __attribute__((aligned(16))) double dblk[NBK * BLK];
   __attribute__((aligned(16))) double oblk[NOFF * BLK];
-  __attribute__((aligned(16))) double strip[4][NB * IB];
+  __attribute__((aligned(16))) double strip[4][NB * SLD];
 };
 
 // Left solve of the 64 columns [64 bx, 64 bx + 64) of B.
@@ -223,7 +228,7 @@ __device__ __forceinline__ void trsm_left_body(int kb, int64_t N, const TT *T, i
 #pragma unroll
       for (int c = 0; c < IB; ++c) {
         const int64_t col = col0 + c;
-        strip[row * IB + c] = (row < kb && col < N && row == col) ? 1.0 : 0.0;
+        strip[row * SLD + c] = (row < kb && col < N && row == col) ? 1.0 : 0.0;
       }
     } else {
       TB raw[IB];
@@ -235,7 +240,7 @@ __device__ __forceinline__ void trsm_left_body(int kb, int64_t N, const TT *T, i
       }
 #pragma unroll
       for (int c = 0; c < IB; ++c)
-        strip[row * IB + c] = (row < kb && col0 + c < N) ? double(raw[c]) : 0.0;
+        strip[row * SLD + c] = (row < kb && col0 + c < N) ? double(raw[c]) : 0.0;
     }
   }
   __syncthreads();
@@ -253,24 +258,24 @@ __device__ __forceinline__ void trsm_left_body(int kb, int64_t N, const TT *T, i
         const d2 a01 = *reinterpret_cast<const d2 *>(ablk + p * BLK + lane * 4);
         const d2 a23 = *reinterpret_cast<const d2 *>(ablk + p * BLK + lane * 4 + 2);
         const int k0 = IB * J + lk;
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a01[0], strip[(k0) * IB + l16], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a01[1], strip[(k0 + 4) * IB + l16], acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a23[0], strip[(k0 + 8) * IB + l16], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a23[1], strip[(k0 + 12) * IB + l16], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a01[0], strip[(k0) * SLD + l16], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a01[1], strip[(k0 + 4) * SLD + l16], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a23[0], strip[(k0 + 8) * SLD + l16], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a23[1], strip[(k0 + 12) * SLD + l16], acc1, 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) strip[(IB * I + lk + 4 * v) * IB + l16] -= acc0[v] + acc1[v];
+    for (int v = 0; v < 4; ++v) strip[(IB * I + lk + 4 * v) * SLD + l16] -= acc0[v] + acc1[v];
     wave_sync();
     const int bs = kb - IB * I < IB ? kb - IB * I : IB;
     const int o = IB * I;
     double x[4];
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) x[jj] = strip[(o + q + 4 * jj) * IB + cc];
+    for (int jj = 0; jj < 4; ++jj) x[jj] = strip[(o + q + 4 * jj) * SLD + cc];
     quad_substitute<FWD, unit_diag<MODE>()>(x, dblk + I * BLK + q * 4, q, bs);
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj)
-      strip[(o + q + 4 * jj) * IB + cc] = (q + 4 * jj < bs) ? x[jj] : 0.0;
+      strip[(o + q + 4 * jj) * SLD + cc] = (q + 4 * jj < bs) ? x[jj] : 0.0;
     wave_sync();
   }
 
@@ -280,7 +285,7 @@ __device__ __forceinline__ void trsm_left_body(int kb, int64_t N, const TT *T, i
 #pragma unroll
     for (int c = 0; c < IB; ++c) {
       const int64_t col = col0 + c;
-      if (row < kb && col < N) B[row + col * ldb] = TB(strip[row * IB + c]);
+      if (row < kb && col < N) B[row + col * ldb] = TB(strip[row * SLD + c]);
     }
   }
 }
@@ -350,7 +355,7 @@ __device__ __forceinline__ void trsm_right_upper_body(int kb, int64_t M, const T
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int c = cg + 4 * (16 * h + u);
-        strip[c * IB + r] = (row < M && c < kb) ? double(raw[u]) : 0.0;
+        strip[c * SLD + r] = (row < M && c < kb) ? double(raw[u]) : 0.0;
       }
     }
   }
@@ -367,24 +372,24 @@ __device__ __forceinline__ void trsm_right_upper_body(int kb, int64_t M, const T
         const d2 b01 = *reinterpret_cast<const d2 *>(ublk + p * BLK + lane * 4);
         const d2 b23 = *reinterpret_cast<const d2 *>(ublk + p * BLK + lane * 4 + 2);
         const int k0 = IB * I + lk;
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0) * IB + l16], b01[0], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 4) * IB + l16], b01[1], acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 8) * IB + l16], b23[0], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 12) * IB + l16], b23[1], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0) * SLD + l16], b01[0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 4) * SLD + l16], b01[1], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 8) * SLD + l16], b23[0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 12) * SLD + l16], b23[1], acc1, 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) strip[(IB * J + l16) * IB + lk + 4 * v] -= acc0[v] + acc1[v];
+    for (int v = 0; v < 4; ++v) strip[(IB * J + l16) * SLD + lk + 4 * v] -= acc0[v] + acc1[v];
     wave_sync();
     const int bs = kb - IB * J < IB ? kb - IB * J : IB;
     const int o = IB * J;
     double x[4];
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) x[jj] = strip[(o + q + 4 * jj) * IB + rq];
+    for (int jj = 0; jj < 4; ++jj) x[jj] = strip[(o + q + 4 * jj) * SLD + rq];
     quad_substitute<true, false>(x, dblk + J * BLK + q * 4, q, bs);
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj)
-      strip[(o + q + 4 * jj) * IB + rq] = (q + 4 * jj < bs) ? x[jj] : 0.0;
+      strip[(o + q + 4 * jj) * SLD + rq] = (q + 4 * jj < bs) ? x[jj] : 0.0;
     wave_sync();
   }
 
@@ -394,7 +399,7 @@ __device__ __forceinline__ void trsm_right_upper_body(int kb, int64_t M, const T
 #pragma unroll
     for (int u = 0; u < 32; ++u) {
       const int c = cg + 4 * u;
-      if (row < M && c < kb) B[row + int64_t(c) * ldb] = TT(strip[c * IB + r]);
+      if (row < M && c < kb) B[row + int64_t(c) * ldb] = TT(strip[c * SLD + r]);
     }
   }
 }
