@@ -23,7 +23,7 @@
  *   - Return value: 0 on success; -i if argument i (1-based) is invalid (the
  *     check is synchronous and nothing is enqueued); RBT_ERR_HIP if a HIP
  *     runtime call failed; RBT_ERR_WORKSPACE if the workspace is too small;
- *     RBT_ERR_UNSUPPORTED for a configuration this build does not implement.
+ *     RBT_ERR_UNSUPPORTED for a configuration the library does not implement.
  *   - Packed coefficients: U and V are n x depth FP64 arrays (ld = n) whose
  *     column k is the diagonal of R_{k+1} (Sec. 3, packed storage of Alg. 1).
  *     Layer 1 is the single full-size butterfly of Eq. 3.
