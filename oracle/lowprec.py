@@ -7,9 +7,13 @@ FP64, transforms it, rounds A~ to FP32, eliminates without pivoting in FP32
 (or with BF16-rounded operands and FP32 accumulation in the trailing update),
 and refines the solution in FP64.
 
-The kernels' summation order differs from this emulation, so only the final
-FP64 solution is compared with the FP64 oracle (error stated per result).
-Refinement iteration counts: parity unpinned.
+The kernels' summation order differs from this emulation, so the factors are
+compared entry by entry within a bound derived from the componentwise
+backward error of elimination, and the final FP64 solution with the FP64
+oracle (error stated per result). Pinned in tests/test_oracle_lowprec.py
+(exact dyadic factors, the scalar definition at block width 1, componentwise
+backward-error bounds, LAPACK solution). Refinement iteration counts: parity
+unpinned.
 """
 import numpy as np
 

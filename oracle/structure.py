@@ -66,13 +66,6 @@ def partners(n, d):
     return table
 
 
-def is_top(n, d, layer, i):
-    """True if index i sits in the top half of its layer-`layer` butterfly."""
-    m = reference_size(n, d)
-    h = m >> layer
-    return (i % (2 * h)) < h
-
-
 def recursive_sizes(size, h, depth):
     """Butterfly sizes per layer from the Eq. 4 alignment rule.
 
