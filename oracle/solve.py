@@ -135,13 +135,14 @@ def lu_solve(LU, B):
     return backward_upper(LU, forward_unit_lower(LU, B))
 
 
-def rbt_solve(A, B, U, V, d, nb=None):
-    """The method of Eq. 1: returns (X, LU of A~, info)."""
-    At = transform.two_sided(A, U, V, d)
-    Bt = transform.apply_transpose_left(B, U, d)
+def rbt_solve(A, B, U, V, d, nb=None, granule=1):
+    """The method of Eq. 1: returns (X, LU of A~, info). granule: the
+    reference size of the butterflies (structure.reference_size)."""
+    At = transform.two_sided(A, U, V, d, granule)
+    Bt = transform.apply_transpose_left(B, U, d, granule)
     LU, info = genp(At, nb)
     Xt = lu_solve(LU, Bt)
-    X = transform.apply_left(Xt, V, d)
+    X = transform.apply_left(Xt, V, d, granule)
     return X, LU, info
 
 

@@ -7,7 +7,10 @@ packed coefficient column k of Algorithm 1 is layer k+1.
 
 Readings (listed in DESIGN.md):
   * m is the non-tiled reference size 2^d * ceil(n / 2^d) (Sec. 3, text after
-    Algorithm 1).
+    Algorithm 1); with a granule g > 1 it is the tiled reference size
+    2^d * g * ceil(n / (2^d * g)) of the same passage (g = the tile size
+    n_b), and with g = lcm(p, q) * n_b the communication-free size of Eq. 8
+    (Sec. 6.4) for a p x q process grid.
   * every layer uses the global half-size h_l = m / 2^l, as Algorithm 1 does;
     it is not recomputed per child (Eq. 4 allows either).
   * a slot whose start is >= n holds no index and is skipped; slot extents are
@@ -19,17 +22,28 @@ Readings (listed in DESIGN.md):
 
 Parity: pinned by Lemma 1 brute force, the Hadamard special case, the Eq. 6
 worked example, the recursive builder (Lemma 2 recursion) and Eq. 4
-invariants (tests/test_oracle_structure.py).
+invariants (tests/test_oracle_structure.py); the tiled and Eq. 8 sizes by
+tile alignment of every butterfly, the Sec. 6 statement of the top half in
+tiles, and the Sec. 6.4 statements of which sizes need communication.
 """
+import math
 
 
-def reference_size(n, d):
-    """Non-tiled reference size m = 2^d ceil(n / 2^d) (Sec. 3, after Alg. 1)."""
-    g = 1 << d
+def reference_size(n, d, granule=1):
+    """Reference size m = 2^d g ceil(n / (2^d g)) (Sec. 3, after Alg. 1):
+    g = 1 is the non-tiled size 2^d ceil(n / 2^d), g = n_b the tiled one."""
+    g = (1 << d) * granule
     return g * ((n + g - 1) // g)
 
 
-def layer_butterflies(n, d, layer):
+def comm_free_granule(nb, p, q):
+    """Granule of Eq. 8 (Sec. 6.4): lcm(p, q) tiles of size nb, for a p x q
+    process grid; the top half of layer 1 is then
+    lcm(p, q) 2^(d-1) ceil(n_t 2^-d / lcm(p, q)) tiles."""
+    return (p * q // math.gcd(p, q)) * nb
+
+
+def layer_butterflies(n, d, layer, granule=1):
     """Butterflies of one layer (Eq. 3 numbering, 1 <= layer <= d).
 
     Returns a list of (start, h, mu, nu): the butterfly covers rows
@@ -37,7 +51,7 @@ def layer_butterflies(n, d, layer):
     down, and rows start+mu .. start+mu+nu-1 are unpaired.  Follows the loop
     nest of Algorithm 1 with its global half-size h = m / 2^layer.
     """
-    m = reference_size(n, d)
+    m = reference_size(n, d, granule)
     h = m >> layer
     out = []
     for b in range(1 << (layer - 1)):
@@ -50,7 +64,7 @@ def layer_butterflies(n, d, layer):
     return out
 
 
-def partners(n, d):
+def partners(n, d, granule=1):
     """partner[l-1][i]: index paired with i in layer l, or -1 if unpaired.
 
     Built from the butterfly list above (pairs (s+t, s+h+t), t < mu).
@@ -58,7 +72,7 @@ def partners(n, d):
     table = []
     for layer in range(1, d + 1):
         p = [-1] * n
-        for (s, h, mu, nu) in layer_butterflies(n, d, layer):
+        for (s, h, mu, nu) in layer_butterflies(n, d, layer, granule):
             for t in range(mu):
                 p[s + t] = s + h + t
                 p[s + h + t] = s + t
@@ -87,3 +101,22 @@ def recursive_sizes(size, h, depth):
     right = recursive_sizes(mu, h // 2, depth - 1) if mu > 0 else [[] for _ in range(depth - 1)]
     deeper = [left[k] + right[k] for k in range(depth - 1)]
     return [here] + deeper
+
+
+def communicating_layers(n, d, nb, p, q, granule=1):
+    """Layers whose two-sided application needs data from another process
+    when A is distributed 2-D block-cyclically in nb x nb tiles over a p x q
+    grid (tile row I on process row I mod p, tile column J on process column
+    J mod q): layer l communicates if a pair (i, j) of it has its two rows on
+    different process rows (the U side) or its two columns on different
+    process columns (the V side). Brute force over all pairs."""
+    out = []
+    for layer, part in enumerate(partners(n, d, granule), start=1):
+        rows = cols = False
+        for i, j in enumerate(part):
+            if j > i:
+                rows = rows or (i // nb) % p != (j // nb) % p
+                cols = cols or (i // nb) % q != (j // nb) % q
+        if rows or cols:
+            out.append(layer)
+    return out

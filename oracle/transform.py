@@ -37,11 +37,11 @@ def butterfly_matrix(m, mu, nu):
     return O
 
 
-def layer_matrix(n, d, layer):
+def layer_matrix(n, d, layer, granule=1):
     """O_layer: block-diagonal of the layer's butterflies (Eq. 3)."""
     O = np.zeros((n, n))
     covered = 0
-    for (s, h, mu, nu) in structure.layer_butterflies(n, d, layer):
+    for (s, h, mu, nu) in structure.layer_butterflies(n, d, layer, granule):
         size = 2 * mu + nu
         # A butterfly's rows are contiguous: [s, s + 2mu + nu), top half first,
         # the pair partner of s+t is s+h+t = s+mu+nu+t when the bottom half is
@@ -54,11 +54,11 @@ def layer_matrix(n, d, layer):
     return O
 
 
-def dense_rbt(n, d, coeff):
+def dense_rbt(n, d, coeff, granule=1):
     """Dense U = O_d R_d ... O_1 R_1 (Eq. 3) from packed coefficients (n x d)."""
     Umat = np.eye(n)
     for layer in range(1, d + 1):
-        Umat = layer_matrix(n, d, layer) @ np.diag(coeff[:, layer - 1]) @ Umat
+        Umat = layer_matrix(n, d, layer, granule) @ np.diag(coeff[:, layer - 1]) @ Umat
     return Umat
 
 
@@ -82,9 +82,9 @@ def dense_rbt_recursive_parker(coeff):
     return np.block([[top, Z], [Z, bot]]) @ O @ R
 
 
-def _pairs(n, d, layer):
+def _pairs(n, d, layer, granule=1):
     a, b = [], []
-    for (s, h, mu, nu) in structure.layer_butterflies(n, d, layer):
+    for (s, h, mu, nu) in structure.layer_butterflies(n, d, layer, granule):
         a.extend(range(s, s + mu))
         b.extend(range(s + h, s + h + mu))
     return np.array(a, dtype=np.int64), np.array(b, dtype=np.int64)
@@ -97,39 +97,39 @@ def _mix_rows(X, a, b):
     X[b] = (xa - xb) / SQRT2
 
 
-def apply_transpose_left(X, coeff, d):
+def apply_transpose_left(X, coeff, d, granule=1):
     """Return coeff-RBT^T @ X for X of shape (n,) or (n, k); O(d n k) work."""
     X = np.array(X, dtype=np.float64, copy=True)
     n = X.shape[0]
     for layer in range(d, 0, -1):
-        a, b = _pairs(n, d, layer)
+        a, b = _pairs(n, d, layer, granule)
         _mix_rows(X, a, b)
         c = coeff[:, layer - 1]
         X *= c if X.ndim == 1 else c[:, None]
     return X
 
 
-def apply_left(X, coeff, d):
+def apply_left(X, coeff, d, granule=1):
     """Return coeff-RBT @ X (the undo order: scale, then mix, l = 1..d)."""
     X = np.array(X, dtype=np.float64, copy=True)
     n = X.shape[0]
     for layer in range(1, d + 1):
         c = coeff[:, layer - 1]
         X *= c if X.ndim == 1 else c[:, None]
-        a, b = _pairs(n, d, layer)
+        a, b = _pairs(n, d, layer, granule)
         _mix_rows(X, a, b)
     return X
 
 
-def two_sided(A, U, V, d):
+def two_sided(A, U, V, d, granule=1):
     """A~ = U^T A V by packed butterflies (Eq. 1): rows with U, columns with V."""
-    T = apply_transpose_left(A, U, d)
-    return apply_transpose_left(T.T, V, d).T.copy()
+    T = apply_transpose_left(A, U, d, granule)
+    return apply_transpose_left(T.T, V, d, granule).T.copy()
 
 
-def two_sided_dense(A, U, V, d):
+def two_sided_dense(A, U, V, d, granule=1):
     """A~ = U^T A V with the explicit dense factors (small n only)."""
     n = A.shape[0]
-    Ud = dense_rbt(n, d, U)
-    Vd = dense_rbt(n, d, V)
+    Ud = dense_rbt(n, d, U, granule)
+    Vd = dense_rbt(n, d, V, granule)
     return Ud.T @ A @ Vd

@@ -132,3 +132,102 @@ def test_lemma1_minors_brute_force():
                     else:
                         assert 2.0 ** (-k / 2) * (1 - 1e-12) <= abs(det) <= 1 + 1e-12
     assert count == 82770   # all k x k minors of every O^<m>_{mu,nu}, m <= 8
+
+
+# ---- tiled reference size (Sec. 3, after Algorithm 1) and Eq. 8 (Sec. 6.4) ----
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("nb", [1, 2, 3, 8, 16])
+def test_tiled_butterflies_align_to_tiles(d, nb):
+    """With m = 2^d nb ceil(n / (2^d nb)) every butterfly of every layer
+    starts and splits on a tile boundary, so a tile never straddles two
+    halves (the purpose the paper gives for the tiled m)."""
+    for n in list(range(1, 80)) + [255, 1000, 1003]:
+        m = structure.reference_size(n, d, nb)
+        assert m % ((1 << d) * nb) == 0 and m >= n and m - n < (1 << d) * nb
+        for layer in range(1, d + 1):
+            for (s, h, mu, nu) in structure.layer_butterflies(n, d, layer, nb):
+                assert s % nb == 0 and h % nb == 0, (n, d, nb, layer, s, h)
+        if nb == 1:
+            assert m == structure.reference_size(n, d)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_tiled_top_half_in_tiles(d):
+    """Sec. 6: the top half of layer 1 is 2^(d-1) ceil(n_t 2^-d) tiles,
+    n_t = ceil(n / n_b); it equals half the tiled reference size."""
+    for nb in (4, 7, 512):
+        for n in (1, 5, 100, 1001, 23040, 69120, 150000):
+            nt = -(-n // nb)
+            tiles = (1 << (d - 1)) * (-(-nt // (1 << d)))
+            assert structure.reference_size(n, d, nb) // 2 == tiles * nb
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("nb", [1, 3, 8])
+def test_tiled_structure_keeps_eq4_and_orthogonality(d, nb):
+    """The tiled structure is still a depth-d RBT of Eq. 3: Eq. 4 alignment
+    (recursive builder at the tiled half-size) and orthogonal layers."""
+    for n in (1, 7, 13, 40, 77, 129):
+        m = structure.reference_size(n, d, nb)
+        rec = structure.recursive_sizes(n, m // 2, d)
+        for layer in range(1, d + 1):
+            loops = [(2 * mu + nu, mu, nu)
+                     for (s, h, mu, nu) in structure.layer_butterflies(n, d, layer, nb)]
+            assert loops == rec[layer - 1], (n, d, nb, layer)
+            O = transform.layer_matrix(n, d, layer, nb)
+            assert np.allclose(O @ O.T, np.eye(n), atol=1e-15)
+
+
+def _paper_sweep():
+    """tests/golden/comm_free_sizes.txt: the Sec. 6.4 statements."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "comm_free_sizes.txt")
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                key, rest = line.split("=", 1)
+                vals[key.strip()] = [int(v) for v in rest.split()]
+    return vals
+
+
+def test_paper_sweep_communication_statements():
+    """Sec. 6.4: with tiles of 512, depth 2 and a 4 x 4 process grid, the
+    sizes 23040 i (i = 1..11) need no communication exactly for 23040,
+    138240 and 253440, and only one layer communicates for 69120, 184320
+    and 207360 (brute force over every pair of the tiled structure)."""
+    g = _paper_sweep()
+    nb, d, p, q = g["nb"][0], g["depth"][0], g["grid"][0], g["grid"][1]
+    none, one = [], []
+    for i in range(1, 12):
+        n = g["base"][0] * i
+        layers = structure.communicating_layers(n, d, nb, p, q, granule=nb)
+        if not layers:
+            none.append(n)
+        elif len(layers) == 1:
+            one.append(n)
+    assert none == g["no_communication"]
+    assert one == g["one_layer"]
+
+
+@pytest.mark.parametrize("p,q", [(4, 4), (2, 3), (3, 2), (4, 6), (1, 5)])
+def test_eq8_size_is_communication_free(p, q):
+    """Eq. 8: with the granule lcm(p, q) n_b no layer needs another process's
+    data, for any n; its top half of layer 1 is the formula of Eq. 8 in
+    tiles."""
+    nb, d = 4, 2
+    gran = structure.comm_free_granule(nb, p, q)
+    lcm = gran // nb
+    rng = np.random.default_rng(p * 10 + q)
+    for n in [1, 9, 64, 97] + list(rng.integers(100, 1200, size=6)):
+        n = int(n)
+        assert structure.communicating_layers(n, d, nb, p, q, granule=gran) == []
+        nt = -(-n // nb)
+        eq8_tiles = lcm * (1 << (d - 1)) * (-(-nt // ((1 << d) * lcm)))
+        assert structure.reference_size(n, d, gran) // 2 == eq8_tiles * nb
+    # the plain tiled size does communicate for some n on a grid with p, q > 1
+    if p > 1:
+        assert any(structure.communicating_layers(n, d, nb, p, q, granule=nb)
+                   for n in range(50, 400, 7))

@@ -136,19 +136,22 @@ def test_parker_recursion():
                                transform.dense_rbt_recursive_parker(C), atol=1e-14)
 
 
-def test_packed_equals_dense():
-    rng = np.random.default_rng(7)
-    for d in range(0, 6):
+@pytest.mark.parametrize("granule", [1, 3, 8])
+def test_packed_equals_dense(granule):
+    """Packed O(d n^2) application = product with the dense Eq. 2/Eq. 3
+    factors, for the non-tiled (granule 1) and tiled reference sizes."""
+    rng = np.random.default_rng(7 + granule)
+    for d in range(0, 6 if granule == 1 else 4):
         for n in list(range(1, 40)) + [63, 64, 65, 97]:
             U = np.exp(rng.uniform(-1, 1, (n, d)) / 20)
             V = np.exp(rng.uniform(-1, 1, (n, d)) / 20)
             A = rng.standard_normal((n, n))
             X = rng.standard_normal((n, 3))
-            Ud = transform.dense_rbt(n, d, U)
-            assert np.allclose(transform.apply_transpose_left(X, U, d), Ud.T @ X, atol=1e-13)
-            assert np.allclose(transform.apply_left(X, U, d), Ud @ X, atol=1e-13)
-            assert np.allclose(transform.two_sided(A, U, V, d),
-                               transform.two_sided_dense(A, U, V, d), atol=1e-13)
+            Ud = transform.dense_rbt(n, d, U, granule)
+            assert np.allclose(transform.apply_transpose_left(X, U, d, granule), Ud.T @ X, atol=1e-13)
+            assert np.allclose(transform.apply_left(X, U, d, granule), Ud @ X, atol=1e-13)
+            assert np.allclose(transform.two_sided(A, U, V, d, granule),
+                               transform.two_sided_dense(A, U, V, d, granule), atol=1e-13)
 
 
 def test_exact_dense_factor_matches():
