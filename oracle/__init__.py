@@ -19,6 +19,8 @@ Modules
   solve       GENP, triangular solves, undo-V, backward error (Eq. 7),
               iterative refinement (Sec. 5), adjoint of the solve
   lowprec     emulated FP32 / BF16 GENP for the mixed-precision path
+  pivoted     partial-pivoting elimination and solve (the robust re-solve of
+              the Sec. 5 fallback)
 
 Parity status per function is listed in each module header.  Every function
 here is pinned by a test in tests/test_oracle_*.py against something other
@@ -26,4 +28,4 @@ than itself (paper's worked example, closed forms, exact rational arithmetic,
 library routines on special cases), except where a header says
 "parity unpinned".
 """
-from . import structure, coeffs, transform, solve, lowprec  # noqa: F401
+from . import structure, coeffs, transform, solve, lowprec, pivoted  # noqa: F401
