@@ -71,3 +71,33 @@ def generate(n, d, seed):
             U[i, layer - 1] = coefficient(seed, 0, layer, i)
             V[i, layer - 1] = coefficient(seed, 1, layer, i)
     return U, V
+
+
+def angle(seed, side, layer, i):
+    """Random angle of the rotation butterflies (Sec. 3, the butterflies based
+    on block rotations): theta = 2 pi u with u uniform on [0, 1), drawn from
+    the same counter as the diagonal coefficients at the top index i of the
+    pair (reading listed in the design doc: the paper fixes no law)."""
+    u = (draw(seed, counter(side, layer, i)) >> 11) * (2.0 ** -53)
+    return 2.0 * math.pi * u
+
+
+def generate_rotations(n, d, seed, granule=1):
+    """Packed rotation coefficients (n x d for U and V): for a pair (a, b) of
+    layer l (a in the top half), C[a, l-1] = cos(theta_a) and
+    C[b, l-1] = sin(theta_a); an unpaired index holds 1 (its rotation is by
+    0 degrees: the identity)."""
+    from . import structure
+    if d > 64:
+        raise ValueError("depth above 64 is not representable in the counter")
+    out = []
+    for side in (0, 1):
+        C = np.ones((n, d), dtype=np.float64)
+        for layer, part in enumerate(structure.partners(n, d, granule), start=1):
+            for a, b in enumerate(part):
+                if b > a:
+                    t = angle(seed, side, layer, a)
+                    C[a, layer - 1] = math.cos(t)
+                    C[b, layer - 1] = math.sin(t)
+        out.append(C)
+    return out[0], out[1]

@@ -146,6 +146,19 @@ def rbt_solve(A, B, U, V, d, nb=None, granule=1):
     return X, LU, info
 
 
+def rbt_solve_kind(A, B, U, V, d, kind="diag", granule=1, sides=2, nb=None):
+    """The method of Eq. 1 with either butterfly kind (transform.transform_pair)
+    and one or two sides (sides = 1: A~ = U^T A and x = x~, Sec. 7).
+    Returns (X, LU of A~, info)."""
+    fwd, undo = transform.transform_pair(kind)
+    At = transform.two_sided_kind(A, U, V, d, kind, granule, sides)
+    Bt = fwd(B, U, d, granule)
+    LU, info = genp(At, nb)
+    Xt = lu_solve(LU, Bt)
+    X = Xt if sides == 1 else undo(Xt, V, d, granule)
+    return X, LU, info
+
+
 def backward_error(A, X, B):
     """Eq. 7, infinity norms, per column; returns the maximum over columns."""
     A = np.asarray(A, dtype=np.float64)

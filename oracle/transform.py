@@ -133,3 +133,81 @@ def two_sided_dense(A, U, V, d, granule=1):
     Ud = dense_rbt(n, d, U, granule)
     Vd = dense_rbt(n, d, V, granule)
     return Ud.T @ A @ Vd
+
+
+# ---- rotation butterflies (Sec. 3: block rotations, R_l = I) ----
+#
+# Layer matrix: every butterfly is [[C, 0, S], [0, I, 0], [S, 0, -C]] with
+# C = diag(cos t), S = diag(sin t) over its mu pairs (rotation of 0 degrees,
+# the identity, on the nu unpaired rows); U = O_d ... O_1 with no diagonal
+# factors. Each O_l is symmetric and orthogonal, so U^T x applies layers
+# d..1 and U x layers 1..d, each mixing a pair (a, b) into
+# (c x_a + s x_b, s x_a - c x_b). Packed coefficients: coeffs.generate_rotations.
+
+
+def rotation_layer_matrix(n, d, layer, coeff, granule=1):
+    """Dense O_layer of the rotation RBT from packed cos/sin coefficients."""
+    O = np.eye(n)
+    for (s, h, mu, nu) in structure.layer_butterflies(n, d, layer, granule):
+        for t in range(mu):
+            a, b = s + t, s + h + t
+            c, sn = coeff[a, layer - 1], coeff[b, layer - 1]
+            O[a, a], O[a, b], O[b, a], O[b, b] = c, sn, sn, -c
+    return O
+
+
+def dense_rotation_rbt(n, d, coeff, granule=1):
+    """Dense U = O_d ... O_1 of the rotation RBT."""
+    Umat = np.eye(n)
+    for layer in range(1, d + 1):
+        Umat = rotation_layer_matrix(n, d, layer, coeff, granule) @ Umat
+    return Umat
+
+
+def _rotate_rows(X, a, b, c, s):
+    xa = X[a].copy()
+    xb = X[b].copy()
+    if X.ndim == 1:
+        X[a] = c * xa + s * xb
+        X[b] = s * xa - c * xb
+    else:
+        X[a] = c[:, None] * xa + s[:, None] * xb
+        X[b] = s[:, None] * xa - c[:, None] * xb
+
+
+def rotation_apply_transpose_left(X, coeff, d, granule=1):
+    """coeff-rotation-RBT^T @ X (layers d..1)."""
+    X = np.array(X, dtype=np.float64, copy=True)
+    n = X.shape[0]
+    for layer in range(d, 0, -1):
+        a, b = _pairs(n, d, layer, granule)
+        _rotate_rows(X, a, b, coeff[a, layer - 1], coeff[b, layer - 1])
+    return X
+
+
+def rotation_apply_left(X, coeff, d, granule=1):
+    """coeff-rotation-RBT @ X (layers 1..d)."""
+    X = np.array(X, dtype=np.float64, copy=True)
+    n = X.shape[0]
+    for layer in range(1, d + 1):
+        a, b = _pairs(n, d, layer, granule)
+        _rotate_rows(X, a, b, coeff[a, layer - 1], coeff[b, layer - 1])
+    return X
+
+
+def transform_pair(kind):
+    """(U^T x, U x) routines of a butterfly kind: "diag" (Eq. 3, random
+    diagonals and the butterflies of Eq. 2) or "rotation"."""
+    if kind == "rotation":
+        return rotation_apply_transpose_left, rotation_apply_left
+    return apply_transpose_left, apply_left
+
+
+def two_sided_kind(A, U, V, d, kind="diag", granule=1, sides=2):
+    """A~ = U^T A V (sides = 2) or U^T A (sides = 1, the one-sided RBT of
+    Sec. 7) for either butterfly kind."""
+    fwd, _ = transform_pair(kind)
+    T = fwd(A, U, d, granule)
+    if sides == 1:
+        return T
+    return fwd(T.T, V, d, granule).T.copy()

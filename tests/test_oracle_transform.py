@@ -229,3 +229,64 @@ def test_eq1_exact_solution_invariance():
         xf, _, info = solve.rbt_solve(Af, bf, Uf, Vf, d)
         assert info == 0
         assert np.allclose(xf, [float(v) for v in x], rtol=1e-12, atol=1e-14)
+
+
+# ---- rotation butterflies (Sec. 3) and the one-sided RBT (Sec. 7) ----
+
+@pytest.mark.parametrize("granule", [1, 4])
+def test_rotation_rbt_at_45_degrees_is_the_hadamard_butterfly(granule):
+    """A rotation by 45 degrees on every pair is the butterfly of Eq. 2, so the
+    rotation RBT then equals the Eq. 3 RBT with unit diagonals."""
+    for d in (1, 2, 3):
+        for n in (1, 5, 8, 13, 64, 77):
+            C = np.ones((n, d))
+            for layer, part in enumerate(structure.partners(n, d, granule), start=1):
+                for a, b in enumerate(part):
+                    if b >= 0:
+                        C[a, layer - 1] = np.sqrt(0.5)  # cos 45 = sin 45
+            R = transform.dense_rotation_rbt(n, d, C, granule)
+            H = transform.dense_rbt(n, d, np.ones((n, d)), granule)
+            assert np.allclose(R, H, atol=1e-15), (n, d)
+
+
+def test_rotation_rbt_orthogonal_and_packed_equals_dense():
+    rng = np.random.default_rng(3)
+    for d in (1, 2, 3, 5):
+        for n in (1, 2, 7, 16, 33, 100):
+            U, V = coeffs.generate_rotations(n, d, 99)
+            # cos^2 + sin^2 = 1 on every pair (the defining constraint)
+            for layer, part in enumerate(structure.partners(n, d), start=1):
+                for a, b in enumerate(part):
+                    if b > a:
+                        assert abs(U[a, layer - 1] ** 2 + U[b, layer - 1] ** 2 - 1) < 1e-15
+                    elif b < 0:
+                        assert U[a, layer - 1] == 1.0
+            Ud = transform.dense_rotation_rbt(n, d, U)
+            assert np.allclose(Ud.T @ Ud, np.eye(n), atol=1e-14)
+            X = rng.standard_normal((n, 3))
+            assert np.allclose(transform.rotation_apply_transpose_left(X, U, d), Ud.T @ X,
+                               atol=1e-13)
+            assert np.allclose(transform.rotation_apply_left(X, U, d), Ud @ X, atol=1e-13)
+            A = rng.standard_normal((n, n))
+            Vd = transform.dense_rotation_rbt(n, d, V)
+            assert np.allclose(transform.two_sided_kind(A, U, V, d, "rotation"), Ud.T @ A @ Vd,
+                               atol=1e-12)
+            assert np.allclose(transform.two_sided_kind(A, U, V, d, "diag", sides=1),
+                               transform.dense_rbt(n, d, U).T @ A, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind,sides", [("rotation", 2), ("diag", 1), ("rotation", 1)])
+def test_kind_and_sides_solve_the_system(kind, sides):
+    """Eq. 1 holds for any invertible U, V: rotation and one-sided RBTs give
+    A^-1 b (exact rational check is in Q(sqrt2) only for Eq. 3; here against
+    LAPACK on a well-conditioned matrix)."""
+    from oracle import solve
+    from paper_2312_09376_amd import workloads
+    n, d = 120, 2
+    A = workloads.shifted(n, seed=4)
+    B = workloads.randn(n, 2, seed=5)
+    U, V = (coeffs.generate_rotations(n, d, 7) if kind == "rotation"
+            else coeffs.generate(n, d, 7))
+    X, _, info = solve.rbt_solve_kind(A, B, U, V, d, kind=kind, sides=sides)
+    assert info == 0
+    assert np.allclose(X, np.linalg.solve(A, B), rtol=1e-10, atol=1e-12)
