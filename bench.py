@@ -66,11 +66,12 @@ def parse():
     ap.add_argument("--lookahead", type=int, default=-1, help="0/1 (-1: library default)")
     ap.add_argument("--outer-nb", type=int, default=0,
                     help="panel width of the elimination (multiple of 128; 0 = library default)")
-    ap.add_argument("--mode", choices=["solve", "mixed", "batched", "backward", "copy"],
+    ap.add_argument("--mode", choices=["solve", "mixed", "batched", "backward", "copy", "small"],
                     default="solve",
                     help="solve: the FP64 step (default); mixed: FP32/BF16 elimination with FP64 "
                          "refinement; copy: a plain FP64 matrix copy through the transform kernel "
-                         "at depth 0 (reference point for HBM byte counters)")
+                         "at depth 0 (reference point for HBM byte counters); small: the "
+                         "n = 1000 / 1001 / 1003 FP64 solves beside the single-threaded oracle")
     ap.add_argument("--prec", choices=["fp32", "bf16", "fp64"], default="fp32",
                     help="mixed / batched / backward modes (fp64: backward mode only)")
     ap.add_argument("--solver", choices=["classic", "gmres"], default="classic", help="mixed mode")
@@ -89,8 +90,14 @@ def parse():
                     help="batched mode: persistent workgroups per CU (0: tuned)")
     ap.add_argument("--tol-scale", type=float, default=10.0,
                     help="batched mode: refine to tol-scale * n * eps per system (0: max_iter steps)")
-    ap.add_argument("--matrix", choices=["randn", "logcond", "dominant"], default="randn",
-                    help="mixed mode: N(0,1), Q1 diag(10^-6 .. 1) Q2^T, or I + 0.3 N(0,1)/sqrt(n)")
+    ap.add_argument("--matrix", choices=["randn", "logcond", "dominant", "hostile", "orthog"],
+                    default="randn",
+                    help="solve / mixed modes: N(0,1); Q1 diag(10^-6 .. 1) Q2^T with Haar Q1, Q2 "
+                         "(cond 1e6); I + 0.3 N(0,1)/sqrt(n); N(0,1) with the leading 8 x 8 block "
+                         "scaled by 1e-12 (solve mode); the orthog matrix (solve mode, guarded)")
+    ap.add_argument("--guarded-solve", action="store_true",
+                    help="solve mode: rbt_solve_guarded (FP64 RBT, then partial pivoting if "
+                         "refinement cannot reach tol)")
     return ap.parse_args()
 
 
@@ -229,12 +236,32 @@ def mixed_mode(args):
     if args.guarded:
         out["config"]["guarded"] = True
         out["ir_steps"] = [[int(v) for v in i[0].cpu()] for i in iters]  # [low prec, FP64]
-        out["fp64_fallback"] = [int(i[1].item()) for i in iters]
+        out["fp64_fallback"] = [int(i[1].item()) for i in iters]  # path: 0, 1 RBT64, 2 GEPP
         out["info"] = [int(v) for v in info.cpu()]
     else:
         out["ir_steps"] = [int(i.item()) for i in iters]
         out["info"] = int(info.item())
+    if not args.no_gepp:
+        out["gepp"] = gepp_comparator(A, B, flops, ms_step)
     print(json.dumps(out), flush=True)
+
+
+def gepp_comparator(A, B, flops, ms_step, reps=2):
+    """FP64 partial-pivoting solve of the same system on the same GPU (torch ->
+    rocSOLVER getrf/getrs) and its Eq. 7 backward error."""
+    import torch
+    from paper_2312_09376_amd import rbt
+    Xg = torch.linalg.solve(A, B)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    for _ in range(reps):
+        Xg = torch.linalg.solve(A, B)
+    torch.cuda.synchronize()
+    g_ms = (time.perf_counter() - g0) * 1e3 / reps
+    gb = float(rbt.backward_error(A, Xg.t().contiguous().t(), B).item())
+    return {"solver": "torch.linalg.solve FP64 (partial pivoting)", "ms": round(g_ms, 3),
+            "TFLOP/s": round(flops / (g_ms * 1e-3) / 1e12, 4), "berr": gb,
+            "speedup_rbt": round(g_ms / ms_step, 3)}
 
 
 def batched_mode(args):
@@ -379,12 +406,44 @@ def backward_mode(args):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    rbt.timing_read()
+    rbt.timing_enable(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    rbt.timing_enable(False)
+    stages = rbt.timing_read()
     flops = nb * (2.0 / 3.0) * n ** 3
+    o_ms, o_cnt, o_bytes = stages["outer"]
+    o_gbs = o_bytes / (o_ms * 1e-3) / 1e9 if o_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "kernel": "k_neg_outer (dA = -Lambda X^T, a pure write)",
+                "achieved": round(o_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(o_gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_launch": 8.0 * n * n, "launches": o_cnt,
+                "avg_launch_ms": round(o_ms / max(o_cnt, 1), 4)}
+    # FP64 partial pivoting on the same GPU: factor, solve, adjoint solve
+    # with the same factors and the outer product, per system
+    gepp = None
+    if not args.no_gepp:
+        def gepp_step():
+            for A, B, G in zip(As, Bs, Gs):
+                LUp, piv = torch.linalg.lu_factor(A)
+                Xp = torch.linalg.lu_solve(LUp, piv, B)
+                lam = torch.linalg.lu_solve(LUp, piv, G, adjoint=True)
+                dAp = -(lam @ Xp.t())
+            return Xp, lam, dAp
+        gepp_step()
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        Xp, lam, _ = gepp_step()
+        torch.cuda.synchronize()
+        g_ms = (time.perf_counter() - g0) * 1e3
+        gb = float(rbt.backward_error(As[-1], Xp.t().contiguous().t(), Bs[-1]).item())
+        gepp = {"solver": "torch.linalg.lu_factor / lu_solve FP64 (partial pivoting), forward "
+                          "and adjoint solves + dA", "ms": round(g_ms, 3),
+                "berr_forward_last": gb, "speedup_rbt": round(g_ms / ms_step, 3)}
     out = {
         "metric": "solve + adjoint (dA, dB) throughput, TFLOP/s of the forward eliminations",
         "value": round(flops / (ms_step * 1e-3) / 1e12, 4), "unit": "TFLOP/s", "n_gpus": 1,
@@ -396,7 +455,9 @@ def backward_mode(args):
                                f"adjoint with dA", "batch": nb, "n": n, "nrhs": k, "depth": d},
         "systems_per_s": round(nb / (ms_step * 1e-3), 2),
         "max_forward_berr": worst["fwd"], "max_adjoint_berr": worst["bwd"] if not fp64 else None,
-        "berr_tol": tol, "roofline": None, "cpu_baseline": None,
+        "berr_tol": tol, "roofline": roofline, "gepp": gepp,
+        "stages_ms_per_step": {s_: round(v[0] / args.steps, 3) for s_, v in stages.items()},
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 
@@ -436,9 +497,71 @@ def cpu_baseline(n, nrhs, depth, seed):
     X, it, be = osolve.refine(A, B, X, LU, U, V, depth, tol, 10)
     t = time.perf_counter() - t0
     return {"value": round((2.0 / 3.0) * n ** 3 / t / 1e12, 6), "unit": "TFLOP/s", "cores": int(threads),
-            "kind": "oracle",
+            "host_cpus": os.cpu_count(), "kind": "oracle",
             "sample": f"one oracle solve (blocked NumPy elimination, nb=256) at n={n}, nrhs={nrhs}, "
-                      f"depth {depth}, refinement to 10*n*eps ({it} steps, berr {be:.2e}); {t:.2f} s"}
+                      f"depth {depth}, refinement to 10*n*eps ({it} steps, berr {be:.2e}); {t:.2f} s "
+                      f"on {threads} BLAS threads of {os.cpu_count()} host CPUs"}
+
+
+def oracle_small(n, depth, seed):
+    """The oracle's unblocked elimination (plain right-looking, one BLAS
+    thread) on the n x n N(0,1) system: seconds and its backward error."""
+    import numpy as np
+    from oracle import coeffs, solve as osolve
+    from paper_2312_09376_amd import workloads
+    try:
+        from threadpoolctl import threadpool_limits
+        ctx = threadpool_limits(limits=1, user_api="blas")
+    except Exception:
+        import contextlib
+        ctx = contextlib.nullcontext()
+    A = workloads.randn_matrix(n, seed=workloads.MATRIX_SEED)
+    B = workloads.randn(n, 1, seed=workloads.RHS_SEED)
+    with ctx:
+        t0 = time.perf_counter()
+        U, V = coeffs.generate(n, depth, seed)
+        X, LU, _ = osolve.rbt_solve(A, B, U, V, depth, nb=0)
+        t = time.perf_counter() - t0
+    return t, osolve.backward_error(A, X, B), A, B
+
+
+def small_mode(args):
+    """The n = 1000 / 1001 / 1003 workload (A, b ~ N(0,1), depth 2, FP64): the
+    GPU solve with refinement to 10 n eps, timed over `steps` solves, beside
+    the single-threaded oracle's unrefined solve."""
+    import torch
+    from paper_2312_09376_amd import rbt, workloads
+    cells = []
+    for n in (1000, 1001, 1003):
+        t_o, be_o, A_h, B_h = oracle_small(n, args.depth, args.seed)
+        A = torch.from_numpy(A_h.T.copy()).cuda().t()  # the oracle's bytes, column-major
+        B = torch.from_numpy(B_h.T.copy()).cuda().t()
+        tol = 10.0 * n * 2.0 ** -52
+        LU = torch.empty_strided((n, n), (1, n), dtype=torch.float64, device="cuda")
+        X = torch.empty_strided((n, 1), (1, n), dtype=torch.float64, device="cuda")
+        work = rbt._workspace(n, 1, args.depth, A.device)
+        for _ in range(max(args.warmup, 1)):
+            rbt.solve_refine(A, B, args.depth, args.seed, tol=tol, LU=LU, X=X, work=work)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, _, it, be, info, _ = rbt.solve_refine(A, B, args.depth, args.seed, tol=tol, LU=LU,
+                                                     X=X, work=work)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        cells.append({"n": n, "gpu_ms": round(ms, 4),
+                      "gpu_TFLOP/s": round((2.0 / 3.0) * n ** 3 / (ms * 1e-3) / 1e12, 4),
+                      "gpu_berr": float(be.item()), "gpu_ir_steps": int(it.item()),
+                      "oracle_s_1_thread": round(t_o, 3), "oracle_berr_unrefined": be_o,
+                      "speedup": round(t_o * 1e3 / ms, 1)})
+    print(json.dumps({
+        "metric": "FP64 RBT+GENP solve time at n = 1000 / 1001 / 1003 (GPU, refined to 10 n eps) "
+                  "and the single-threaded CPU oracle (seconds)",
+        "value": cells[0]["gpu_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": cells[0]["gpu_ms"], "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "n=1000/1001/1003, A,b~N(0,1) seeds 42/64, depth 2, FP64"},
+        "cells": cells, "roofline": None, "cpu_baseline": None}), flush=True)
 
 
 def main():
@@ -468,6 +591,9 @@ def main():
     if args.mode == "backward":
         backward_mode(args)
         return
+    if args.mode == "small":
+        small_mode(args)
+        return
     if args.outer_nb:
         rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, args.outer_nb)
     if args.lookahead >= 0:
@@ -476,14 +602,30 @@ def main():
     n, k, d = args.n, args.nrhs, args.depth
     tol = 10.0 * n * 2.0 ** -52
 
-    A = workloads.device_randn(n, n, workloads.MATRIX_SEED)
+    if args.matrix == "hostile":
+        A = workloads.device_hostile(n)
+    elif args.matrix == "orthog":
+        A = torch.from_numpy(workloads.orthog(n).T.copy()).cuda().t()
+    elif args.matrix == "logcond":
+        A = workloads.device_logcond(n, workloads.MATRIX_SEED)
+    elif args.matrix == "dominant":
+        A = workloads.device_randn(n, n, workloads.MATRIX_SEED) * (0.3 / math.sqrt(n))
+        A.diagonal().add_(1.0)
+    else:
+        A = workloads.device_randn(n, n, workloads.MATRIX_SEED)
     B = workloads.device_randn(n, k, workloads.RHS_SEED)
     LU = torch.empty_strided((n, n), (1, n), dtype=torch.float64, device="cuda")
     X = torch.empty_strided((n, k), (1, n), dtype=torch.float64, device="cuda")
     work = rbt._workspace(n, k, d, A.device)
     torch.cuda.synchronize()
+    paths = []
 
     def step():
+        if args.guarded_solve:
+            X_, LU_, it_, be_, info_, path_, w_ = rbt.solve_guarded(
+                A, B, d, args.seed, tol=tol, max_iter=args.max_iter, LU=LU, X=X, work=work)
+            paths.append(path_)
+            return X_, LU_, it_[:1], be_, info_[:1], w_
         return rbt.solve_refine(A, B, d, args.seed, tol=tol, max_iter=args.max_iter, LU=LU, X=X,
                                 work=work)
 
@@ -537,9 +679,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"RBT+GENP FP64 solve, n={n}, nrhs={k}, depth {d}, A~N(0,1) seed 42, "
-                               f"b~N(0,1) seed 64, FP64 refinement to berr<=10*n*eps",
-                   "n": n, "nrhs": k, "depth": d,
+        "config": {"workload": f"RBT+GENP FP64 solve, n={n}, nrhs={k}, depth {d}, "
+                               + ("A~N(0,1) seed 42" if args.matrix == "randn" else
+                                  f"A={args.matrix} (seed 42)")
+                               + ", b~N(0,1) seed 64, FP64 refinement to berr<=10*n*eps"
+                               + (", partial-pivoting fallback" if args.guarded_solve else ""),
+                   "n": n, "nrhs": k, "depth": d, "matrix": args.matrix,
                    "outer_nb": rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB),
                    "lookahead": rbt.get_option(rbt._lib.RBT_OPT_LOOKAHEAD)},
         "roofline": {"bound": "mfma", "kernel": "trailing-update GEMM (k_dgemm, FP64 MFMA)",
@@ -561,6 +706,10 @@ def main():
         "stages_ms_per_step": {s: round(v[0] / args.steps, 3) for s, v in stages.items()},
         "step_ms": step_stats,
     }
+    if args.guarded_solve:
+        out["paths"] = [int(p_.item()) for p_ in paths[-args.steps:]]
+        if stages["pivoted"][1]:
+            out["pivoted_ms_per_step"] = round(stages["pivoted"][0] / args.steps, 3)
 
     if not args.no_gepp:
         # FP64 partial-pivoting LU solve on the same GPU (torch -> rocSOLVER)
@@ -577,6 +726,21 @@ def main():
                        "ms": round(g_ms, 3), "TFLOP/s": round(flops / (g_ms * 1e-3) / 1e12, 4),
                        "berr": gb, "speedup_rbt": round(g_ms / ms_step, 3)}
         del Xg
+        # this library's own partial-pivoting factorization and solve (the
+        # Sec. 5 fallback's re-solve), one run
+        LUg = A.clone()
+        Xo = B.clone()
+        torch.cuda.synchronize()
+        o0 = time.perf_counter()
+        _, ipiv, _ = rbt.gepp(LUg, work=work)
+        rbt.gepp_solve(LUg, ipiv, Xo, work=work)
+        torch.cuda.synchronize()
+        o_ms = (time.perf_counter() - o0) * 1e3
+        ob = float(rbt.backward_error(A, Xo, B).item())
+        out["gepp_own"] = {"solver": "rbt_gepp + rbt_gepp_solve (this library, FP64)",
+                           "ms": round(o_ms, 3), "TFLOP/s": round(flops / (o_ms * 1e-3) / 1e12, 4),
+                           "berr": ob}
+        del LUg, Xo
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, k, d, args.seed)

@@ -51,6 +51,12 @@ extern "C" {
 #define RBT_ERR_HIP (-100)
 #define RBT_ERR_WORKSPACE (-101)
 #define RBT_ERR_UNSUPPORTED (-102)
+/* A persistent triangular sweep waited longer than its bound for a block
+ * that another workgroup had to publish (device oversubscribed or starved).
+ * The blocks solved after the expired wait are NaN, never silently wrong
+ * finite values; entry points that synchronize return this code, the others
+ * leave the NaN in their output. */
+#define RBT_ERR_SYNC (-103)
 
 /* Largest supported depth. */
 #define RBT_MAX_DEPTH 16
@@ -73,13 +79,44 @@ int rbt_version(void);
  * (Sec. 3, Eq. 2-4, Alg. 1 loop nest). n >= 0, 0 <= depth <= RBT_MAX_DEPTH. */
 int rbt_structure(int64_t n, int depth, int64_t *partner);
 
+/* Host only. Reference size m = 2^d g ceil(n / (2^d g)) of the butterfly
+ * structure for the granule g >= 1 (Sec. 3, text after Alg. 1): g = 1 is the
+ * non-tiled size, g = n_b aligns every butterfly to n_b x n_b tiles, and
+ * g = rbt_comm_free_granule(n_b, p, q) is the size of Eq. 8 (Sec. 6.4).
+ * -1 for invalid arguments. */
+int64_t rbt_reference_size(int64_t n, int depth, int64_t granule);
+
+/* Host only. Granule of the communication-free size of Eq. 8 (Sec. 6.4):
+ * lcm(p, q) * nb for a p x q process grid of nb x nb tiles. With it every
+ * pair of every layer lies on one process row (U side) and one process
+ * column (V side) of a 2-D block-cyclic distribution. -1 for invalid
+ * arguments. */
+int64_t rbt_comm_free_granule(int64_t nb, int64_t p, int64_t q);
+
+/* Host only. rbt_structure for the reference size of granule `granule`
+ * (argument 3; partner is argument 4). The device entry points use the
+ * granule set with rbt_set_option(RBT_OPT_GRANULE, g) (default 1). */
+int rbt_structure_ex(int64_t n, int depth, int64_t granule, int64_t *partner);
+
 /* Host only. Packed coefficients U, V (host arrays of n * depth doubles each,
  * column-major, ld = n) for (n, depth, seed), per the generator above.
  * Index i's coefficient in layer l depends only on (seed, side, l, i). */
 int rbt_generate(int64_t n, int depth, uint64_t seed, double *U, double *V);
 
+/* Host only. Packed coefficients of the rotation butterflies (Sec. 3: the
+ * block-rotation form [[C, 0, S], [0, I, 0], [S, 0, -C]], C^2 + S^2 = I, a
+ * rotation by 0 degrees on the truncated part, R_l = I) for the structure
+ * of (n, depth, granule): for a pair (a, b) of layer l (a in the top half)
+ * U[(l-1) n + a] = cos(theta), U[(l-1) n + b] = sin(theta), and 1 for an
+ * unpaired index; theta = 2 pi u with u the uniform of the coefficient
+ * counter at the top index (side 0 for U, 1 for V). */
+int rbt_generate_rotations(int64_t n, int depth, uint64_t seed, int64_t granule, double *U,
+                           double *V);
+
 /* Device. Same coefficients written to device arrays dU, dV (n * depth
- * doubles each); exp is the device library's, within 2 ulp of the host's. */
+ * doubles each); exp is the device library's, within 2 ulp of the host's.
+ * With RBT_OPT_BUTTERFLY = 1 the rotation coefficients (cos and sin from
+ * the device library) of the current granule. */
 int rbt_generate_device(int64_t n, int depth, uint64_t seed, double *dU, double *dV,
                         void *stream);
 
@@ -160,16 +197,22 @@ int rbt_solve_refine(int64_t n, int64_t nrhs, const double *A, int64_t lda, doub
  *   prec = RBT_FP32: FP32 storage, FP32 matrix-core updates;
  *   prec = RBT_BF16: FP32 storage, updates with operands rounded to BF16
  *                    (nearest even) and FP32 accumulation.
- * Diagonal blocks and triangular solves of the elimination are computed in
- * FP64 and rounded to FP32 on store. Solves with the FP32 factors widen them
- * and run in FP64. Refinement is in FP64 with the original A:
+ * The whole elimination is FP32 arithmetic (diagonal blocks and panel
+ * solves too). With classical refinement, so are the two triangular solves
+ * with the FP32 factors inside each correction (the transformed residual is
+ * rounded to FP32, the result widened); GMRES-IR applies its preconditioner
+ * V (LU)^-1 U^T in FP64 arithmetic on the FP32 factors, the working
+ * precision in which that method defines the preconditioned products.
+ * RBT_OPT_MIXED_FP64_INNER selects FP64 arithmetic for all of those inner
+ * steps. Refinement is in FP64 with the original A:
  *   solver = RBT_IR_CLASSIC: X += V (LU)^-1 U^T (B - A X);
  *   solver = RBT_IR_GMRES:   the correction solves A D = B - A X by restarted
  *                            GMRES in FP64, preconditioned on the left by
  *                            V (LU)^-1 U^T.
  * Stops when the Eq. 7 backward error is <= tol or after max_iter
  * corrections (GMRES: iterations of the Krylov method). iters_dev, berr_dev,
- * info_dev: as rbt_solve_refine. depth <= 3 (RBT_ERR_UNSUPPORTED otherwise).
+ * info_dev: as rbt_solve_refine. depth <= RBT_MAX_DEPTH; beyond depth 3 the
+ * FP32 A~ is rounded to FP32 after every pass of three layers.
  * work: >= rbt_workspace_size(n, nrhs, depth, prec) bytes. Synchronizes
  * `stream` once per refinement step. */
 int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, float *LU,
@@ -194,7 +237,11 @@ int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, float
  * over the remaining budget, leaves the backward error > 1e3 * tol. The
  * fallback then runs when the final
  * backward error is not <= tol (NaN included), with at most max_iter64
- * classical corrections.
+ * classical corrections, which stop early in the same way. If those cannot
+ * reach tol either (the transform itself fails on this matrix, as for the
+ * `orthog` matrix of Sec. 6.3), A is re-solved with partial pivoting
+ * (rbt_gepp) into LU64 and refined with those factors (max_iter64
+ * corrections): the more robust solver Sec. 5 names.
  *
  * LU64: n x n FP64 (ldlu64 >= max(1, n)), caller-owned, written only by a
  * fallback (then it holds the FP64 factors of A~). Other arguments as in
@@ -202,17 +249,53 @@ int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, float
  * iters_dev: device int32[2] = {low-precision iterations, FP64
  * corrections}; info_dev: device int32[2] = {info of the low-precision
  * elimination, info of the FP64 one (0 without fallback)}; path_dev: device
- * int32, 0 = low-precision factors reached tol, 1 = FP64 fallback ran;
+ * int32, 0 = low-precision factors reached tol, 1 = FP64 RBT fallback,
+ * 2 = partial-pivoting re-solve (info_dev[1] then holds its zero-pivot
+ * column, iters_dev[1] its corrections);
  * berr_dev: final Eq. 7 backward error. All four nullable. Synchronizes
  * `stream` as rbt_solve_mixed does, and once more before returning.
- * Errors: -i for argument i; RBT_ERR_WORKSPACE; RBT_ERR_UNSUPPORTED for
- * depth > 3; RBT_ERR_HIP. */
+ * Errors: -i for argument i; RBT_ERR_WORKSPACE; RBT_ERR_HIP. */
 int rbt_solve_mixed_guarded(int64_t n, int64_t nrhs, const double *A, int64_t lda, float *LU,
                             int64_t ldlu, double *LU64, int64_t ldlu64, const double *B,
                             int64_t ldb, double *X, int64_t ldx, int depth, uint64_t seed,
                             int prec, int solver, double tol, int max_iter, int max_iter64,
                             int32_t *iters_dev, double *berr_dev, int32_t *info_dev,
                             int32_t *path_dev, void *work, size_t work_bytes, void *stream);
+
+/* Device. Elimination with partial pivoting (GEPP) of the n x n FP64 matrix
+ * A (lda) in place: P A = L U, unit-lower L strictly below the diagonal, U
+ * on and above; ipiv_dev (device int64[n]) receives the 1-based row
+ * interchanges in order (LAPACK getrf's convention); info_dev (device int32,
+ * nullable): 0, or the first column k (1-based) whose pivot candidates were
+ * all exactly zero (left unswapped; the elimination goes on with IEEE
+ * Inf/NaN). This is the robust solver that the fallback of Sec. 5 re-solves
+ * with. work: >= rbt_workspace_size(n, 0, 0, RBT_FP64) bytes. */
+int rbt_gepp(int64_t n, double *A, int64_t lda, int64_t *ipiv_dev, int32_t *info_dev, void *work,
+             size_t work_bytes, void *stream);
+
+/* Device. B <- A^-1 B (n x nrhs FP64, ldb, in place) with the factors and
+ * interchanges of rbt_gepp. work: >= rbt_workspace_size(n, nrhs, 0,
+ * RBT_FP64) bytes. */
+int rbt_gepp_solve(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu,
+                   const int64_t *ipiv_dev, double *B, int64_t ldb, void *work, size_t work_bytes,
+                   void *stream);
+
+/* Device. The FP64 method with its Sec. 5 fallback: rbt_solve_refine, whose
+ * refinement stops early when tol is out of reach (a non-finite backward
+ * error, or a correction that does not halve it), and, if the backward error
+ * is then not <= tol, a re-solve of A with partial pivoting (rbt_gepp) into
+ * LU with max_iter classical FP64 corrections. Arguments as rbt_solve_refine;
+ * iters_dev: device int32[2] = {RBT corrections, pivoted corrections};
+ * info_dev: device int32[2] = {first zero pivot of GENP on A~, first zero
+ * pivot column of GEPP}; path_dev: device int32, 0 = the RBT solve reached
+ * tol, 2 = the pivoted re-solve ran. All four nullable. work: >=
+ * rbt_workspace_size(n, nrhs, depth, RBT_FP64) bytes. Synchronizes `stream`
+ * once per refinement step and before returning. */
+int rbt_solve_guarded(int64_t n, int64_t nrhs, const double *A, int64_t lda, double *LU,
+                      int64_t ldlu, const double *B, int64_t ldb, double *X, int64_t ldx,
+                      int depth, uint64_t seed, double tol, int max_iter, int32_t *iters_dev,
+                      double *berr_dev, int32_t *info_dev, int32_t *path_dev, void *work,
+                      size_t work_bytes, void *stream);
 
 /* Batched solves: many independent systems A_s X_s = B_s of different
  * orders (the method of Eq. 1 per system, with mixed precision as in
@@ -225,7 +308,7 @@ int rbt_solve_mixed_guarded(int64_t n, int64_t nrhs, const double *A, int64_t ld
  *
  * Host. Workspace bytes for a batch of `batch` systems with orders n[s] and
  * right-hand-side counts nrhs[s] (host arrays; 0 <= nrhs[s] <= 16), depth
- * <= 3, prec RBT_FP32 or RBT_BF16; 0 for invalid arguments. About
+ * <= RBT_MAX_DEPTH, prec RBT_FP32 or RBT_BF16; 0 for invalid arguments. About
  * 12 n^2 + 8 (2 n d + 64^2 ceil(n/64) + n nrhs) bytes per system (FP32
  * factors, FP64 factors of the fallback, coefficients, inverse blocks,
  * residual). */
@@ -236,7 +319,8 @@ size_t rbt_batched_workspace_size(int64_t batch, const int64_t *n, const int64_t
  * these sizes into the device workspace `work` (>= rbt_batched_workspace_size
  * bytes); synchronizes `stream`. Call once per set of sizes; the plan stays
  * valid for any number of rbt_solve_batched calls with the same batch,
- * depth and prec. nrhs[s] > 16 or depth > 3: RBT_ERR_UNSUPPORTED. */
+ * depth and prec. nrhs[s] > 16: RBT_ERR_UNSUPPORTED. Each system's
+ * transforms run in passes of at most three layers. */
 int rbt_batched_plan(int64_t batch, const int64_t *n, const int64_t *nrhs, int depth, int prec,
                      void *work, size_t work_bytes, void *stream);
 
@@ -254,11 +338,14 @@ int rbt_batched_plan(int64_t batch, const int64_t *n, const int64_t *nrhs, int d
  * iters_dev, berr_dev, info_dev, path_dev: device arrays of `batch`
  * entries (nullable) for the correction count (both passes), the final
  * backward error, the first zero pivot (as rbt_genp) of the last pass, and
- * the pass that produced X (0: low precision, 1: FP64 fallback). Enqueues a reset kernel and
+ * the pass that produced X (0: low precision, 1: FP64 fallback). Systems with
+ * n = 0 or nrhs = 0 have nothing to solve and are not factored: iters 0,
+ * berr 0, info 0, path 0. Enqueues a reset kernel and
  * the persistent kernel on `stream`, allocates nothing and synchronizes
  * nothing, so it can be captured in a HIP graph. A plan that does not match
- * (batch, depth, prec) or a workspace smaller than the plan's makes the
- * launch do nothing. Concurrent calls with the same workspace race. */
+ * (batch, depth, prec) or a workspace smaller than the plan's solves no
+ * system and marks every one: info -1, berr NaN, path -1 (X untouched).
+ * Concurrent calls with the same workspace race. */
 int rbt_solve_batched(int64_t batch, const double *const *A, const int64_t *lda,
                       const double *const *B, const int64_t *ldb, double *const *X,
                       const int64_t *ldx, int depth, uint64_t seed, int prec, double tol,
@@ -292,7 +379,8 @@ int rbt_solve_backward(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu, 
  * FP32 L\U factors of A~ left by rbt_solve_mixed for the same (depth,
  * seed); A = the original FP64 matrix (n x n, lda), used to refine
  * Lambda = A^-T G in FP64: Lambda_0 = U (LU)^-T V^T G with the FP32 factors
- * (widened to FP64 in the solves), then Lambda += U (LU)^-T V^T (G - A^T
+ * (FP32 triangular solves, or FP64 ones with RBT_OPT_MIXED_FP64_INNER), then
+ * Lambda += U (LU)^-T V^T (G - A^T
  * Lambda) until the Eq. 7 backward error of A^T Lambda = G (with
  * ||A^T||_inf = ||A||_1) is <= tol or max_iter corrections are done.
  * dB = Lambda, dA = -Lambda X^T (nullable: skipped). iters_dev, berr_dev:
@@ -342,6 +430,43 @@ int rbt_solve_backward_mixed(int64_t n, int64_t nrhs, const float *LU, int64_t l
  *   called; a smaller workspace (e.g. sized for RBT_FP32) or a wider panel
  *   selects the tile-by-tile path. */
 #define RBT_OPT_BF16_STAGED 5
+/* RBT_OPT_SWEEP_SPIN_LIMIT: sleeps (s_sleep 1, about 30 ns each) that a
+ *   wait of a persistent triangular sweep may take before it expires
+ *   (default 2^20). A negative value makes every wait expire at once: a
+ *   host-side way to exercise the RBT_ERR_SYNC path in tests (every kernel
+ *   still exits normally). */
+#define RBT_OPT_SWEEP_SPIN_LIMIT 6
+/* RBT_OPT_MIXED_FP64_INNER: low-precision elimination and solves
+ *   (rbt_solve_mixed, rbt_solve_mixed_guarded, rbt_solve_backward_mixed).
+ *   0 (default): the whole elimination of A~ is FP32 arithmetic (diagonal
+ *   blocks, panel solves, FP32 or BF16-operand matrix-core updates with FP32
+ *   accumulation) and so are the triangular solves of classical refinement
+ *   with the FP32 factors (right-hand side rounded to FP32, result widened);
+ *   FP64 is used only for the residual, the butterflies of the residual and
+ *   correction, and the accumulation of x (and for GMRES-IR's
+ *   preconditioner, which that method applies in the working precision).
+ *   1: the diagonal blocks, panel solves and triangular solves run in FP64
+ *   arithmetic on the FP32 factors (rounded to FP32 on store), a more
+ *   accurate variant that is not FP32 elimination. */
+#define RBT_OPT_MIXED_FP64_INNER 7
+/* RBT_OPT_GRANULE: reference-size granule g of the butterfly structure used
+ *   by every device entry point (transforms, solves, mixed, batched,
+ *   adjoint): m = 2^d g ceil(n / (2^d g)). 1 (default): the non-tiled size;
+ *   a tile size, or rbt_comm_free_granule(nb, p, q) for Eq. 8. Changes the
+ *   transform (a different depth-d RBT), so factors and solutions saved
+ *   under one granule must be used under the same granule. 1 .. 2^30. */
+#define RBT_OPT_GRANULE 8
+/* RBT_OPT_BUTTERFLY: kind of butterflies of every device entry point
+ *   (coefficient draw, transforms, solves, mixed, batched, adjoint):
+ *   0 (default): random diagonals R_l with the butterflies of Eq. 2 (Eq. 3);
+ *   1: rotation butterflies (the block-rotation form of Sec. 3, R_l = I,
+ *   orthogonal), coefficients as rbt_generate_rotations with the current
+ *   granule. rbt_generate_device draws the coefficients of the current kind. */
+#define RBT_OPT_BUTTERFLY 9
+/* RBT_OPT_SIDES: 2 (default): A~ = U^T A V; 1: the one-sided RBT of Sec. 7,
+ *   A~ = U^T A (columns untouched, x = x~; V is neither applied nor needed
+ *   by the transforms, though the coefficient arrays keep their size). */
+#define RBT_OPT_SIDES 10
 /* Returns 0, -1 for an unknown option, -2 for an invalid value. */
 int rbt_set_option(int option, int64_t value);
 /* Current value, or -1 for an unknown option. */
@@ -358,8 +483,10 @@ int64_t rbt_get_option(int option);
  *   5 trailing update GEMM      work = flops, 2 rem^2 kb per launch
  *   6 triangular solves         work = flops
  *   7 residual / norms / Eq. 7  work = bytes of A read
+ *   8 pivoted factorization     work = flops 2/3 n^3 (the GEPP re-solve)
+ *   9 adjoint outer product     work = bytes of dA written (8 n^2)
  * Disabled by default. Not thread safe. */
-#define RBT_STAGE_COUNT 8
+#define RBT_STAGE_COUNT 10
 int rbt_timing_enable(int on);
 
 /* Waits for the recorded events and writes, for stages 0..nstages-1, the

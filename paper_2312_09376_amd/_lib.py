@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(_HERE, "librbt.so")
 RBT_ERR_HIP = -100
 RBT_ERR_WORKSPACE = -101
 RBT_ERR_UNSUPPORTED = -102
+RBT_ERR_SYNC = -103
 RBT_MAX_DEPTH = 16
 RBT_FP64, RBT_FP32, RBT_BF16 = 0, 1, 2
 RBT_OP_T, RBT_OP_N = 0, 1
@@ -24,7 +25,11 @@ vp = ctypes.c_void_p
 SIGNATURES = {
     "rbt_version": (i32, []),
     "rbt_structure": (i32, [i64, i32, vp]),
+    "rbt_reference_size": (i64, [i64, i32, i64]),
+    "rbt_comm_free_granule": (i64, [i64, i64, i64]),
+    "rbt_structure_ex": (i32, [i64, i32, i64, vp]),
     "rbt_generate": (i32, [i64, i32, u64, vp, vp]),
+    "rbt_generate_rotations": (i32, [i64, i32, u64, i64, vp, vp]),
     "rbt_generate_device": (i32, [i64, i32, u64, vp, vp, vp]),
     "rbt_transform2": (i32, [i64, vp, i64, vp, i64, i32, vp, vp, i32, vp]),
     "rbt_transform_vec": (i32, [i64, i64, vp, i64, vp, i32, i32, vp]),
@@ -39,6 +44,10 @@ SIGNATURES = {
                               dbl, i32, vp, vp, vp, vp, sz, vp]),
     "rbt_solve_mixed_guarded": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32,
                                       u64, i32, i32, dbl, i32, i32, vp, vp, vp, vp, vp, sz, vp]),
+    "rbt_gepp": (i32, [i64, vp, i64, vp, vp, vp, sz, vp]),
+    "rbt_gepp_solve": (i32, [i64, i64, vp, i64, vp, vp, i64, vp, sz, vp]),
+    "rbt_solve_guarded": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, u64, dbl, i32,
+                                vp, vp, vp, vp, vp, sz, vp]),
     "rbt_batched_workspace_size": (sz, [i64, vp, vp, i32, i32]),
     "rbt_batched_plan": (i32, [i64, vp, vp, i32, i32, vp, sz, vp]),
     "rbt_solve_batched": (i32, [i64, vp, vp, vp, vp, vp, vp, i32, u64, i32, dbl, i32, vp, vp, vp,
@@ -53,14 +62,19 @@ SIGNATURES = {
     "rbt_timing_enable": (i32, [i32]),
     "rbt_timing_read": (i32, [i32, vp, vp, vp]),
 }
-RBT_STAGE_COUNT = 8
+RBT_STAGE_COUNT = 10
 RBT_OPT_OUTER_NB = 1
 RBT_OPT_BATCH_TILE_COLS = 2
 RBT_OPT_BATCH_WGS_PER_CU = 3
 RBT_OPT_LOOKAHEAD = 4
 RBT_OPT_BF16_STAGED = 5
+RBT_OPT_SWEEP_SPIN_LIMIT = 6
+RBT_OPT_MIXED_FP64_INNER = 7
+RBT_OPT_GRANULE = 8
+RBT_OPT_BUTTERFLY = 9
+RBT_OPT_SIDES = 10
 STAGES = ["generate", "transform2", "transform_vec", "diag", "panel", "trailing", "solve",
-          "residual"]
+          "residual", "pivoted", "outer"]
 
 _lib = None
 
@@ -90,5 +104,7 @@ def load(path=None):
 def check(rc, name):
     if rc != 0:
         what = {RBT_ERR_HIP: "HIP runtime error", RBT_ERR_WORKSPACE: "workspace too small",
-                RBT_ERR_UNSUPPORTED: "unsupported configuration"}.get(rc, f"invalid argument {-rc}")
+                RBT_ERR_UNSUPPORTED: "unsupported configuration",
+                RBT_ERR_SYNC: "a triangular sweep's bounded wait expired (result is NaN)"}.get(
+                    rc, f"invalid argument {-rc}")
         raise RBTError(f"{name} failed ({rc}): {what}")

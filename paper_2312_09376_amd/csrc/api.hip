@@ -73,11 +73,25 @@ struct Options {
   int64_t batch_wgs_per_cu = 2; // batched: persistent workgroups per compute unit
   int64_t lookahead = 0;        // elimination: overlap panels with the trailing update
   int64_t bf16_staged = 1;      // BF16 elimination: staged-operand trailing GEMM
+  int64_t sweep_spin_limit = int64_t(1) << 20;  // sleeps before a sweep's wait expires
+  int64_t mixed_fp64_inner = 0;  // mixed precision: diagonal blocks, panel and triangular
+                                 // solves in FP64 arithmetic (else FP32)
+  int64_t granule = 1;           // butterfly structure: reference-size granule
+  int64_t kind = 0;              // butterflies: 0 Eq. 3 (random diagonals), 1 rotations
+  int64_t sides = 2;             // 2: U^T A V; 1: U^T A (one-sided)
 };
 Options &options() {
   static Options o;
   return o;
 }
+}  // namespace
+
+int64_t sweep_spin_limit() { return options().sweep_spin_limit; }
+int64_t butterfly_granule() { return options().granule; }
+int butterfly_kind() { return int(options().kind); }
+int butterfly_sides() { return int(options().sides); }
+
+namespace {
 
 // Workspace layout of the composite entry points. The inverses of the
 // diagonal blocks (for the few-right-hand-side solves) come first, so that
@@ -85,6 +99,9 @@ Options &options() {
 struct Layout {
   size_t winv, sync, coef, resid, partial, krylov, small, total;
   size_t o_winv, o_sync, o_coef, o_resid, o_partial, o_krylov, o_small;
+  // partial pivoting (the GEPP re-solve): ipiv and perm (n int64 each), a
+  // row-gather buffer (n x nrhs) and the pivot search's partial maxima
+  size_t piv, o_piv, ygat, o_ygat, gscr, o_gscr;
   size_t hstage, o_hstage, total_staged;  // BF16: operand staging of the trailing update
 };
 
@@ -124,6 +141,9 @@ Layout layout(int64_t n, int64_t nrhs, int d, bool mixed = false, bool bf16 = fa
   L.partial = align256(part * sizeof(double));
   L.krylov = mixed ? align256(krylov_doubles(n) * sizeof(double)) : 0;
   L.small = 512;
+  L.piv = align256(size_t(2) * n * sizeof(int64_t));
+  L.ygat = align256(size_t(n) * nrhs * sizeof(double));
+  L.gscr = gepp_scratch_bytes();
   L.o_winv = 0;
   L.o_sync = L.o_winv + L.winv;
   L.o_coef = L.o_sync + L.sync;
@@ -131,7 +151,10 @@ Layout layout(int64_t n, int64_t nrhs, int d, bool mixed = false, bool bf16 = fa
   L.o_partial = L.o_resid + L.resid;
   L.o_krylov = L.o_partial + L.partial;
   L.o_small = L.o_krylov + L.krylov;
-  L.total = L.o_small + L.small;
+  L.o_piv = L.o_small + L.small;
+  L.o_ygat = L.o_piv + L.piv;
+  L.o_gscr = L.o_ygat + L.ygat;
+  L.total = L.o_gscr + L.gscr;
   // BF16 operands of the trailing update at the current panel width (an
   // optional area after the others: without it the elimination rounds the
   // operands tile by tile)
@@ -139,6 +162,20 @@ Layout layout(int64_t n, int64_t nrhs, int d, bool mixed = false, bool bf16 = fa
   L.o_hstage = L.total;
   L.total_staged = L.total + L.hstage;
   return L;
+}
+
+// Sticky error word of the persistent sweeps (k_sweep.hip): cleared at the
+// start of every entry point that runs sweeps; the entry points that
+// synchronize read it back with their other results (RBT_ERR_SYNC when a
+// sweep's bounded wait expired; that block's solution is NaN).
+hipError_t clear_sweep_err(int32_t *sync, hipStream_t s) {
+  return launch_fill_i32(sync + kSweepErrWord, 0, s);
+}
+int read_sweep_err(const int32_t *sync, hipStream_t s) {
+  int32_t e = 0;
+  RBT_HIP_CHECK(hipMemcpyAsync(&e, sync + kSweepErrWord, sizeof(e), hipMemcpyDeviceToHost, s));
+  RBT_HIP_CHECK(hipStreamSynchronize(s));
+  return e != 0 ? RBT_ERR_SYNC : 0;
 }
 
 template <typename T>
@@ -214,7 +251,10 @@ hipStream_t aux_stream() {
 struct EventPair {
   hipEvent_t f = nullptr, b = nullptr;
   bool ok() const { return f != nullptr && b != nullptr; }
-  EventPair() {
+  // created only when the lookahead needs them (without it the elimination
+  // creates no runtime objects at all)
+  explicit EventPair(bool create) {
+    if (!create) return;
     if (hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess) f = nullptr;
     if (hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) b = nullptr;
   }
@@ -240,6 +280,32 @@ hipError_t trailing_sub(int64_t M, int64_t N, int64_t K, const float *A, int64_t
   return gemm_sub(M, N, K, A, lda, B, ldb, C, ldc, prec, true, st);
 }
 
+// Diagonal-block factor and block solves of the elimination: FP64 for FP64
+// factors; FP32 arithmetic for FP32 factors unless the FP64-inner option is
+// set.
+hipError_t diag_lu(int kb, double *A, int64_t lda, int64_t gofs, int32_t *info, hipStream_t s) {
+  return launch_diag_lu(kb, A, lda, gofs, info, s);
+}
+hipError_t diag_lu(int kb, float *A, int64_t lda, int64_t gofs, int32_t *info, hipStream_t s) {
+  return launch_diag_lu(kb, A, lda, gofs, info, options().mixed_fp64_inner != 0, s);
+}
+hipError_t panel_trsm(int kb, int64_t M, int64_t N, const double *T, int64_t ldt, double *Br,
+                      double *Bl, int64_t ldb, hipStream_t s) {
+  return launch_panel_trsm(kb, M, N, T, ldt, Br, Bl, ldb, s);
+}
+hipError_t panel_trsm(int kb, int64_t M, int64_t N, const float *T, int64_t ldt, float *Br,
+                      float *Bl, int64_t ldb, hipStream_t s) {
+  return launch_panel_trsm(kb, M, N, T, ldt, Br, Bl, ldb, options().mixed_fp64_inner != 0, s);
+}
+hipError_t trsm_left(TriMode mode, int kb, int64_t N, const double *T, int64_t ldt, double *B,
+                     int64_t ldb, hipStream_t s) {
+  return launch_trsm_left(mode, kb, N, T, ldt, B, ldb, s);
+}
+hipError_t trsm_left(TriMode mode, int kb, int64_t N, const float *T, int64_t ldt, float *B,
+                     int64_t ldb, hipStream_t s) {
+  return launch_trsm_left(mode, kb, N, T, ldt, B, ldb, options().mixed_fp64_inner != 0, s);
+}
+
 template <typename T>
 int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t s,
               void *stage = nullptr, size_t stage_bytes = 0) {
@@ -258,13 +324,13 @@ int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t
       T *A11 = A + k + k * lda;
       {
         StageScope t(kStageDiag, s, 2.0 / 3.0 * double(kb) * kb * kb);
-        RBT_HIP_CHECK(launch_diag_lu(kb, A11, lda, k, info, s));
+        RBT_HIP_CHECK(diag_lu(kb, A11, lda, k, info, s));
       }
       const int64_t rows = n - k - kb;      // rows below the diagonal block
       const int64_t pc = k0 + w - k - kb;   // panel columns right of it (= panel rows below it)
       {
         StageScope t(kStagePanel, s, double(rows) * kb * kb + double(pc + nt) * kb * kb);
-        RBT_HIP_CHECK(launch_panel_trsm(kb, rows, pc + nt, A11, lda, A + (k + kb) + k * lda,
+        RBT_HIP_CHECK(panel_trsm(kb, rows, pc + nt, A11, lda, A + (k + kb) + k * lda,
                                         A + k + (k + kb) * lda, lda, s));
       }
       if (pc > 0 && (rows > 0 || nt > 0)) {
@@ -287,7 +353,7 @@ int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t
       const int64_t below = k0 + w - k - kb;
       {
         StageScope t(kStagePanel, st, double(nc) * kb * kb);
-        RBT_HIP_CHECK(launch_trsm_left(TriMode::LN, kb, nc, A + k + k * lda, lda,
+        RBT_HIP_CHECK(trsm_left(TriMode::LN, kb, nc, A + k + k * lda, lda,
                                        A + k + c0 * lda, lda, st));
       }
       if (below > 0) {
@@ -312,7 +378,7 @@ int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t
   // lookahead (the split is at a multiple of the GEMM tile), so the factors
   // are identical either way.
   hipStream_t s2 = options().lookahead ? aux_stream() : nullptr;
-  EventPair ev;
+  EventPair ev(s2 != nullptr);
   if (s2 != nullptr && !ev.ok()) s2 = nullptr;
   if (n <= 0) return 0;
   // The first panel also takes the n mod kNB columns that do not fill a
@@ -417,8 +483,11 @@ int getrs_fp64(int64_t n, int64_t nrhs, const double *LU, int64_t ld, double *B,
 // Stage-timed wrappers of the launches used by the composite entry points.
 hipError_t generate_t(int64_t n, int d, uint64_t seed, double *U, double *V, hipStream_t s) {
   StageScope t(kStageGenerate, s, 16.0 * double(n) * d);
-  return launch_generate(n, d, seed, U, V, s);
+  return launch_generate(geometry(n, d), seed, U, V, s);
 }
+// x = V x~ (op N) or V^T g (op T): nothing for the one-sided RBT (V = I).
+hipError_t transform_v_t(const Geometry &g, int64_t nrhs, double *B, int64_t ldb,
+                         const double *V, int op, hipStream_t s);
 hipError_t transform2_t(const Geometry &g, const double *A, int64_t lda, void *out, int64_t ldo,
                         int prec, const double *U, const double *V, hipStream_t s) {
   const double elt_out = prec == RBT_FP32 ? 4.0 : 8.0;
@@ -429,6 +498,11 @@ hipError_t transform_vec_t(const Geometry &g, int64_t nrhs, double *B, int64_t l
                            const double *C, int op, hipStream_t s) {
   StageScope t(kStageTransformVec, s, 16.0 * double(g.n) * nrhs);
   return launch_transform_vec(g, nrhs, B, ldb, C, op, s);
+}
+hipError_t transform_v_t(const Geometry &g, int64_t nrhs, double *B, int64_t ldb,
+                         const double *V, int op, hipStream_t s) {
+  if (g.sides == 1) return hipSuccess;
+  return transform_vec_t(g, nrhs, B, ldb, V, op, s);
 }
 int getrs_t(int64_t n, int64_t nrhs, const double *LU, int64_t ld, double *B, int64_t ldb,
             int trans, const double *winv, int32_t *sync, hipStream_t s) {
@@ -444,39 +518,59 @@ int diag_inverses_t(int64_t n, int64_t nrhs, const double *LU, int64_t ld, doubl
   return 0;
 }
 
-// Mixed precision: inverses of the diagonal blocks of the FP32 factors (in
-// FP64), always formed, since every solve with FP32 factors runs as sweeps.
-int diag_inverses_t(int64_t n, const float *LU, int64_t ld, double *winv, hipStream_t s) {
+// Mixed precision: inverses of the diagonal blocks of the FP32 factors,
+// always formed, since every solve with FP32 factors runs as sweeps: FP32
+// inverses (in the first half of the FP64-sized area), or FP64 ones with
+// the FP64-inner option.
+int diag_inverses_t(int64_t n, const float *LU, int64_t ld, double *winv, bool f64,
+                    hipStream_t s) {
   if (n == 0) return 0;
   StageScope t(kStageSolve, s, 2.0 / 3.0 * double(n) * kNB * kNB);
-  RBT_HIP_CHECK(launch_diag_inverses(n, LU, ld, winv, s));
+  if (f64)
+    RBT_HIP_CHECK(launch_diag_inverses(n, LU, ld, winv, s));
+  else
+    RBT_HIP_CHECK(launch_diag_inverses(n, LU, ld, reinterpret_cast<float *>(winv), s));
   return 0;
 }
-// B <- (LU)^-1 B or (LU)^-T B with FP32 factors, FP64 right-hand sides and
-// arithmetic: sweeps over groups of at most kSkinnyMax columns.
+// B <- (LU)^-1 B or (LU)^-T B with FP32 factors and FP64 right-hand sides:
+// sweeps over groups of at most kSkinnyMax columns, in FP32 arithmetic (the
+// right-hand side rounded to FP32 on load, the result widened on store), or
+// in FP64 arithmetic (f64: the FP64-inner option, and the preconditioner of
+// GMRES-IR, which that method applies in the working precision). The
+// inverses must have been formed by diag_inverses_t with the same f64.
 int getrs_t(int64_t n, int64_t nrhs, const float *LU, int64_t ld, double *B, int64_t ldb,
-            int trans, const double *winv, int32_t *sync, hipStream_t s) {
+            int trans, const double *winv, int32_t *sync, bool f64, hipStream_t s) {
   StageScope t(kStageSolve, s, 2.0 * double(n) * n * nrhs);
+  const float *winv32 = reinterpret_cast<const float *>(winv);
   for (int64_t c0 = 0; c0 < nrhs; c0 += kSkinnyMax) {
     const int64_t nc = nrhs - c0 < kSkinnyMax ? nrhs - c0 : kSkinnyMax;
     double *Bc = B + c0 * ldb;
-    RBT_HIP_CHECK(launch_sweep(trans ? TriMode::UT : TriMode::LN, n, nc, LU, ld, winv, Bc, ldb,
-                               sync, s));
-    RBT_HIP_CHECK(launch_sweep(trans ? TriMode::LT : TriMode::UN, n, nc, LU, ld, winv, Bc, ldb,
-                               sync, s));
+    for (int pass = 0; pass < 2; ++pass) {
+      const TriMode m = pass == 0 ? (trans ? TriMode::UT : TriMode::LN)
+                                  : (trans ? TriMode::LT : TriMode::UN);
+      if (f64)
+        RBT_HIP_CHECK(launch_sweep(m, n, nc, LU, ld, winv, Bc, ldb, sync, s));
+      else
+        RBT_HIP_CHECK(launch_sweep(m, n, nc, LU, ld, winv32, Bc, ldb, sync, s));
+    }
   }
   return 0;
 }
 
-// R <- V (L U)^-1 U^T R: the solve of Eq. 1 with the factors of A~.
+// R <- V (L U)^-1 U^T R: the solve of Eq. 1 with the factors of A~ (f64:
+// arithmetic of the triangular solves with FP32 factors, see getrs_t).
+int getrs_t(int64_t n, int64_t nrhs, const double *LU, int64_t ld, double *B, int64_t ldb,
+            int trans, const double *winv, int32_t *sync, bool /*f64*/, hipStream_t s) {
+  return getrs_t(n, nrhs, LU, ld, B, ldb, trans, winv, sync, s);
+}
 template <typename TF>
 int apply_solve(const Geometry &g, int64_t nrhs, const TF *LU, int64_t ld, double *R, int64_t ldr,
-                const double *U, const double *V, const double *winv, int32_t *sync,
+                const double *U, const double *V, const double *winv, int32_t *sync, bool f64,
                 hipStream_t s) {
   RBT_HIP_CHECK(transform_vec_t(g, nrhs, R, ldr, U, RBT_OP_T, s));
-  const int rc = getrs_t(g.n, nrhs, LU, ld, R, ldr, 0, winv, sync, s);
+  const int rc = getrs_t(g.n, nrhs, LU, ld, R, ldr, 0, winv, sync, f64, s);
   if (rc) return rc;
-  RBT_HIP_CHECK(transform_vec_t(g, nrhs, R, ldr, V, RBT_OP_N, s));
+  RBT_HIP_CHECK(transform_v_t(g, nrhs, R, ldr, V, RBT_OP_N, s));
   return 0;
 }
 
@@ -490,7 +584,7 @@ int refine_classic(int64_t n, int64_t nrhs, const double *A, int64_t lda, const 
                    int64_t ldlu, const double *B, int64_t ldb, double *X, int64_t ldx,
                    const Geometry &g, const double *U, const double *V, const double *winv,
                    int32_t *sync, double *R, double *scratch, double *anorm, double *berr, double tol,
-                   int max_iter, int *it_out, hipStream_t s, bool *stalled = nullptr) {
+                   int max_iter, int *it_out, bool f64, hipStream_t s, bool *stalled = nullptr) {
   int it = 0;
   double be_prev = 0.0;
   for (;;) {
@@ -502,7 +596,7 @@ int refine_classic(int64_t n, int64_t nrhs, const double *A, int64_t lda, const 
     if (it >= max_iter) break;
     double be_host = 0.0;
     RBT_HIP_CHECK(hipMemcpyAsync(&be_host, berr, sizeof(double), hipMemcpyDeviceToHost, s));
-    RBT_HIP_CHECK(hipStreamSynchronize(s));
+    if (const int e = read_sweep_err(sync, s)) return e;  // also waits for be_host
     if (be_host <= tol) break;
     // guarded use: a non-finite error, or a correction that did not halve
     // the error, means these factors cannot reach tol (the caller falls back)
@@ -511,7 +605,7 @@ int refine_classic(int64_t n, int64_t nrhs, const double *A, int64_t lda, const 
       break;
     }
     be_prev = be_host;
-    const int rc = apply_solve(g, nrhs, LU, ldlu, R, n, U, V, winv, sync, s);
+    const int rc = apply_solve(g, nrhs, LU, ldlu, R, n, U, V, winv, sync, f64, s);
     if (rc) return rc;
     RBT_HIP_CHECK(launch_axpy_cols(n, nrhs, R, n, X, ldx, s));
     ++it;
@@ -569,7 +663,7 @@ int refine_gmres(int64_t n, int64_t nrhs, const double *A, int64_t lda, const TF
       if (rc) return rc;
       double be = 0.0;
       RBT_HIP_CHECK(hipMemcpyAsync(&be, berr, sizeof(double), hipMemcpyDeviceToHost, s));
-      RBT_HIP_CHECK(hipStreamSynchronize(s));
+      if (const int e = read_sweep_err(sync, s)) return e;  // also waits for be
       if (be <= tol || total >= max_iter) break;
       if (stalled && !(be < HUGE_VAL)) {
         *stalled = true;
@@ -577,7 +671,7 @@ int refine_gmres(int64_t n, int64_t nrhs, const double *A, int64_t lda, const TF
       }
       bool stop = false;
       // z = M^-1 r, v_0 = z / ||z||
-      rc = apply_solve(g, nc, LU, ldlu, R, n, U, V, winv, sync, s);
+      rc = apply_solve(g, nc, LU, ldlu, R, n, U, V, winv, sync, true, s);
       if (rc) return rc;
       RBT_HIP_CHECK(launch_coldots(n, nc, 1, R, 0, R, n, nrm, s));
       RBT_HIP_CHECK(launch_colscale(n, nc, R, n, nrm, Vb, s));
@@ -602,7 +696,7 @@ int refine_gmres(int64_t n, int64_t nrhs, const double *A, int64_t lda, const TF
           StageScope t(kStageResidual, s, 8.0 * double(n) * n);
           RBT_HIP_CHECK(launch_matvec(n, nc, A, lda, Vj, n, W, n, scratch, s));
         }
-        rc = apply_solve(g, nc, LU, ldlu, W, n, U, V, winv, sync, s);
+        rc = apply_solve(g, nc, LU, ldlu, W, n, U, V, winv, sync, true, s);
         if (rc) return rc;
         RBT_HIP_CHECK(launch_coldots(n, nc, j + 1, Vb, vs, W, n, dots, s));
         RBT_HIP_CHECK(launch_colcombo(n, nc, j + 1, Vb, vs, dots, -1.0, W, n, s));
@@ -710,6 +804,68 @@ int refine_gmres(int64_t n, int64_t nrhs, const double *A, int64_t lda, const TF
   return 0;
 }
 
+// ---- partial pivoting (the robust re-solve of the Sec. 5 fallback) ----
+
+// R <- A^-1 R with the GEPP factors: R = P R (gathered through perm), then
+// the triangular solves of the unpivoted factors (same L\U layout).
+int gepp_apply(int64_t n, int64_t nrhs, const double *LU, int64_t ld, const int64_t *perm,
+               double *R, int64_t ldr, double *ygat, const double *winv, int32_t *sync,
+               hipStream_t s) {
+  RBT_HIP_CHECK(launch_gather_rows(n, nrhs, perm, R, ldr, ygat, n, s));
+  RBT_HIP_CHECK(launch_copy_cols(n, nrhs, ygat, n, R, ldr, s));
+  return getrs_t(n, nrhs, LU, ld, R, ldr, 0, winv, sync, s);
+}
+
+// GEPP of A (copied into LU) and the solve X = A^-1 B, then classical FP64
+// refinement with the GEPP factors until the Eq. 7 backward error is <= tol
+// or max_iter corrections. ipiv, perm: n int64 each.
+int gepp_solve_refine(int64_t n, int64_t nrhs, const double *A, int64_t lda, double *LU,
+                      int64_t ldlu, const double *B, int64_t ldb, double *X, int64_t ldx,
+                      double tol, int max_iter, int32_t *info, void *work, const Layout &L,
+                      double *berr, int *it_out, hipStream_t s) {
+  int64_t *ipiv = at<int64_t>(work, L.o_piv);
+  int64_t *perm = ipiv + n;
+  double *winv = at<double>(work, L.o_winv);
+  int32_t *sync = at<int32_t>(work, L.o_sync);
+  double *R = at<double>(work, L.o_resid);
+  double *scratch = at<double>(work, L.o_partial);
+  double *ygat = at<double>(work, L.o_ygat);
+  double *anorm = at<double>(work, L.o_small);
+  *it_out = 0;
+  if (info) RBT_HIP_CHECK(launch_fill_i32(info, 0, s));
+  RBT_HIP_CHECK(launch_copy_cols(n, n, A, lda, LU, ldlu, s));
+  {
+    StageScope t(kStagePivoted, s, 2.0 / 3.0 * double(n) * n * n);
+    RBT_HIP_CHECK(launch_gepp(n, LU, ldlu, ipiv, info, at<char>(work, L.o_gscr), s));
+  }
+  RBT_HIP_CHECK(launch_ipiv_to_perm(n, ipiv, perm, s));
+  int rc = diag_inverses_t(n, nrhs, LU, ldlu, winv, s);
+  if (rc) return rc;
+  RBT_HIP_CHECK(clear_sweep_err(sync, s));
+  RBT_HIP_CHECK(launch_copy_cols(n, nrhs, B, ldb, X, ldx, s));
+  rc = gepp_apply(n, nrhs, LU, ldlu, perm, X, ldx, ygat, winv, sync, s);
+  if (rc) return rc;
+  int it = 0;
+  for (;;) {
+    {
+      StageScope t(kStageResidual, s, 8.0 * double(n) * n);
+      RBT_HIP_CHECK(launch_residual_berr(n, nrhs, A, lda, X, ldx, B, ldb, R, n, it == 0, scratch,
+                                         anorm, berr, s));
+    }
+    if (it >= max_iter) break;
+    double be_host = 0.0;
+    RBT_HIP_CHECK(hipMemcpyAsync(&be_host, berr, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (const int e = read_sweep_err(sync, s)) return e;
+    if (be_host <= tol || !(be_host < HUGE_VAL)) break;
+    rc = gepp_apply(n, nrhs, LU, ldlu, perm, R, n, ygat, winv, sync, s);
+    if (rc) return rc;
+    RBT_HIP_CHECK(launch_axpy_cols(n, nrhs, R, n, X, ldx, s));
+    ++it;
+  }
+  *it_out = it;
+  return read_sweep_err(sync, s);
+}
+
 bool bad_depth(int d) { return d < 0 || d > RBT_MAX_DEPTH; }
 
 }  // namespace
@@ -729,7 +885,7 @@ extern "C" int rbt_generate_device(int64_t n, int depth, uint64_t seed, double *
   if (bad_depth(depth)) return -2;
   if (n > 0 && depth > 0 && dU == nullptr) return -4;
   if (n > 0 && depth > 0 && dV == nullptr) return -5;
-  RBT_HIP_CHECK(launch_generate(n, depth, seed, dU, dV, S(stream)));
+  RBT_HIP_CHECK(launch_generate(geometry(n, depth), seed, dU, dV, S(stream)));
   return 0;
 }
 
@@ -743,7 +899,6 @@ extern "C" int rbt_transform2(int64_t n, const double *A, int64_t lda, void *Out
   if (ldo < (n > 1 ? n : 1)) return -5;
   if (out_prec != RBT_FP64 && out_prec != RBT_FP32) return -6;
   if (out_prec == RBT_FP64 && (const void *)A == Out && ldo != lda) return -5;
-  if (out_prec == RBT_FP32 && depth > 3) return RBT_ERR_UNSUPPORTED;
   if (n > 0 && depth > 0 && dU == nullptr) return -7;
   if (n > 0 && depth > 0 && dV == nullptr) return -8;
   if (bad_depth(depth)) return -9;
@@ -786,6 +941,7 @@ extern "C" int rbt_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu
   hipStream_t s = S(stream);
   double *winv = at<double>(work, L.o_winv);
   int32_t *sync = at<int32_t>(work, L.o_sync);
+  RBT_HIP_CHECK(clear_sweep_err(sync, s));
   int rc = diag_inverses_t(n, nrhs, LU, ldlu, winv, s);
   if (rc) return rc;
   return getrs_fp64(n, nrhs, LU, ldlu, B, ldb, trans, winv, sync, s);
@@ -817,9 +973,10 @@ extern "C" int rbt_solve_ex(int64_t n, int64_t nrhs, double *A, int64_t lda, dou
   if (rc) return rc;
   rc = diag_inverses_t(n, nrhs, A, lda, winv, s);
   if (rc) return rc;
+  RBT_HIP_CHECK(clear_sweep_err(at<int32_t>(work, L.o_sync), s));
   rc = getrs_t(n, nrhs, A, lda, B, ldb, 0, winv, at<int32_t>(work, L.o_sync), s);
   if (rc) return rc;
-  RBT_HIP_CHECK(transform_vec_t(g, nrhs, B, ldb, V, RBT_OP_N, s));
+  RBT_HIP_CHECK(transform_v_t(g, nrhs, B, ldb, V, RBT_OP_N, s));
   return 0;
 }
 
@@ -904,17 +1061,16 @@ extern "C" int rbt_solve_refine(int64_t n, int64_t nrhs, const double *A, int64_
   if (rc) return rc;
   RBT_HIP_CHECK(launch_copy_cols(n, nrhs, B, ldb, X, ldx, s));
   int32_t *sync = at<int32_t>(work, L.o_sync);
-  rc = apply_solve(g, nrhs, (const double *)LU, ldlu, X, ldx, U, V, winv, sync, s);
+  RBT_HIP_CHECK(clear_sweep_err(sync, s));
+  rc = apply_solve(g, nrhs, (const double *)LU, ldlu, X, ldx, U, V, winv, sync, true, s);
   if (rc) return rc;
   int it = 0;
   rc = refine_classic(n, nrhs, A, lda, (const double *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv, sync, R,
-                      scratch, anorm, berr, tol, max_iter, &it, s);
+                      scratch, anorm, berr, tol, max_iter, &it, true, s);
   if (rc) return rc;
-  if (iters_dev) {
+  if (iters_dev)
     RBT_HIP_CHECK(hipMemcpyAsync(iters_dev, &it, sizeof(int32_t), hipMemcpyHostToDevice, s));
-    RBT_HIP_CHECK(hipStreamSynchronize(s));
-  }
-  return 0;
+  return read_sweep_err(sync, s);  // synchronizes
 }
 
 namespace rbt {
@@ -961,18 +1117,26 @@ int mixed_impl(int64_t n, int64_t nrhs, const double *A, int64_t lda, float *LU,
   RBT_HIP_CHECK(transform2_t(g, A, lda, LU, ldlu, RBT_FP32, U, V, s));
   int rc = genp_impl(n, LU, ldlu, info_dev, prec, s, stage, stage_bytes);
   if (rc) return rc;
-  rc = diag_inverses_t(n, LU, ldlu, winv, s);
+  // triangular solves with the FP32 factors: FP32 arithmetic for classical
+  // refinement; GMRES-IR applies its preconditioner in FP64 (also to the
+  // first solve, so one set of inverses serves all of them)
+  const bool f64 = options().mixed_fp64_inner != 0 || solver == RBT_IR_GMRES;
+  rc = diag_inverses_t(n, LU, ldlu, winv, f64, s);
   if (rc) return rc;
   RBT_HIP_CHECK(launch_copy_cols(n, nrhs, B, ldb, X, ldx, s));
   int32_t *sync = at<int32_t>(work, L.o_sync);
-  rc = apply_solve(g, nrhs, (const float *)LU, ldlu, X, ldx, U, V, winv, sync, s);
+  RBT_HIP_CHECK(clear_sweep_err(sync, s));
+  rc = apply_solve(g, nrhs, (const float *)LU, ldlu, X, ldx, U, V, winv, sync, f64, s);
   if (rc) return rc;
   if (solver == RBT_IR_GMRES)
-    return refine_gmres(n, nrhs, A, lda, (const float *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv,
-                        sync, R, scratch, at<double>(work, L.o_krylov), anorm, berr, tol,
-                        max_iter, it_out, s, stalled);
-  return refine_classic(n, nrhs, A, lda, (const float *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv,
-                        sync, R, scratch, anorm, berr, tol, max_iter, it_out, s, stalled);
+    rc = refine_gmres(n, nrhs, A, lda, (const float *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv,
+                      sync, R, scratch, at<double>(work, L.o_krylov), anorm, berr, tol, max_iter,
+                      it_out, s, stalled);
+  else
+    rc = refine_classic(n, nrhs, A, lda, (const float *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv,
+                        sync, R, scratch, anorm, berr, tol, max_iter, it_out, f64, s, stalled);
+  if (rc) return rc;
+  return read_sweep_err(sync, s);  // synchronizes
 }
 
 int mixed_args(int64_t n, int64_t nrhs, const double *A, int64_t lda, const float *LU,
@@ -993,7 +1157,6 @@ int mixed_args(int64_t n, int64_t nrhs, const double *A, int64_t lda, const floa
   if (solver != RBT_IR_CLASSIC && solver != RBT_IR_GMRES) return -14;
   if (!(tol >= 0.0)) return -15;
   if (max_iter < 0) return -16;
-  if (depth > 3) return RBT_ERR_UNSUPPORTED;  // the FP32-output transform is one pass
   return 0;
 }
 
@@ -1040,6 +1203,7 @@ extern "C" int rbt_solve_mixed_guarded(int64_t n, int64_t nrhs, const double *A,
   if (n > 0 && work == nullptr) return -24;
   hipStream_t s = S(stream);
   const Layout L = layout(n, nrhs, depth, true);
+  if (work_bytes < L.total) return RBT_ERR_WORKSPACE;
   double *small = at<double>(work, L.o_small);
   double *berr = berr_dev ? berr_dev : small + 1;
   int32_t its[2] = {0, 0};
@@ -1061,20 +1225,150 @@ extern "C" int rbt_solve_mixed_guarded(int64_t n, int64_t nrhs, const double *A,
     double *V = U + n * depth;
     double *winv = at<double>(work, L.o_winv);
     int32_t *sync = at<int32_t>(work, L.o_sync);
+    RBT_HIP_CHECK(clear_sweep_err(sync, s));
     RBT_HIP_CHECK(transform2_t(g, A, lda, LU64, ldlu64, RBT_FP64, U, V, s));
     rc = genp_fp64(n, LU64, ldlu64, info_dev ? info_dev + 1 : nullptr, s);
     if (rc) return rc;
     rc = diag_inverses_t(n, nrhs, LU64, ldlu64, winv, s);
     if (rc) return rc;
     RBT_HIP_CHECK(launch_copy_cols(n, nrhs, B, ldb, X, ldx, s));
-    rc = apply_solve(g, nrhs, (const double *)LU64, ldlu64, X, ldx, U, V, winv, sync, s);
+    rc = apply_solve(g, nrhs, (const double *)LU64, ldlu64, X, ldx, U, V, winv, sync, true, s);
     if (rc) return rc;
     int it64 = 0;
+    bool stalled64 = false;
     rc = refine_classic(n, nrhs, A, lda, (const double *)LU64, ldlu64, B, ldb, X, ldx, g, U, V,
                         winv, sync, at<double>(work, L.o_resid), at<double>(work, L.o_partial),
-                        small, berr, tol, max_iter64, &it64, s);
+                        small, berr, tol, max_iter64, &it64, true, s, &stalled64);
     if (rc) return rc;
     its[1] = it64;
+    rc = read_sweep_err(sync, s);
+    if (rc) return rc;
+    RBT_HIP_CHECK(hipMemcpyAsync(&be, berr, sizeof(double), hipMemcpyDeviceToHost, s));
+    RBT_HIP_CHECK(hipStreamSynchronize(s));
+    if (!(be <= tol)) {
+      // the transform itself fails on this matrix (Sec. 6.3): re-solve A
+      // with partial pivoting into LU64 and refine with those factors
+      path = 2;
+      rc = gepp_solve_refine(n, nrhs, A, lda, LU64, ldlu64, B, ldb, X, ldx, tol, max_iter64,
+                             info_dev ? info_dev + 1 : nullptr, work, L, berr, &it64, s);
+      if (rc) return rc;
+      its[1] = it64;
+    }
+  }
+  if (iters_dev)
+    RBT_HIP_CHECK(hipMemcpyAsync(iters_dev, its, sizeof(its), hipMemcpyHostToDevice, s));
+  if (path_dev)
+    RBT_HIP_CHECK(hipMemcpyAsync(path_dev, &path, sizeof(path), hipMemcpyHostToDevice, s));
+  RBT_HIP_CHECK(hipStreamSynchronize(s));
+  return 0;
+}
+
+extern "C" int rbt_gepp(int64_t n, double *A, int64_t lda, int64_t *ipiv_dev, int32_t *info_dev,
+                        void *work, size_t work_bytes, void *stream) {
+  if (n < 0) return -1;
+  if (n > 0 && A == nullptr) return -2;
+  if (lda < (n > 1 ? n : 1)) return -3;
+  if (n > 0 && ipiv_dev == nullptr) return -4;
+  if (n > 0 && work == nullptr) return -6;
+  if (work_bytes < gepp_scratch_bytes()) return RBT_ERR_WORKSPACE;
+  hipStream_t s = S(stream);
+  if (info_dev) RBT_HIP_CHECK(launch_fill_i32(info_dev, 0, s));
+  if (n == 0) return 0;
+  StageScope t(kStagePivoted, s, 2.0 / 3.0 * double(n) * n * n);
+  RBT_HIP_CHECK(launch_gepp(n, A, lda, ipiv_dev, info_dev, work, s));
+  return 0;
+}
+
+extern "C" int rbt_gepp_solve(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu,
+                              const int64_t *ipiv_dev, double *B, int64_t ldb, void *work,
+                              size_t work_bytes, void *stream) {
+  if (n < 0) return -1;
+  if (nrhs < 0) return -2;
+  if (n > 0 && LU == nullptr) return -3;
+  if (ldlu < (n > 1 ? n : 1)) return -4;
+  if (n > 0 && ipiv_dev == nullptr) return -5;
+  if (n > 0 && nrhs > 0 && B == nullptr) return -6;
+  if (ldb < (n > 1 ? n : 1)) return -7;
+  const Layout L = layout(n, nrhs, 0);
+  if (n > 0 && work == nullptr) return -8;
+  if (work_bytes < L.total) return RBT_ERR_WORKSPACE;
+  if (n == 0 || nrhs == 0) return 0;
+  hipStream_t s = S(stream);
+  int64_t *perm = at<int64_t>(work, L.o_piv) + n;
+  double *winv = at<double>(work, L.o_winv);
+  int32_t *sync = at<int32_t>(work, L.o_sync);
+  RBT_HIP_CHECK(clear_sweep_err(sync, s));
+  RBT_HIP_CHECK(launch_ipiv_to_perm(n, ipiv_dev, perm, s));
+  int rc = diag_inverses_t(n, nrhs, LU, ldlu, winv, s);
+  if (rc) return rc;
+  return gepp_apply(n, nrhs, LU, ldlu, perm, B, ldb, at<double>(work, L.o_ygat), winv, sync, s);
+}
+
+extern "C" int rbt_solve_guarded(int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                                 double *LU, int64_t ldlu, const double *B, int64_t ldb,
+                                 double *X, int64_t ldx, int depth, uint64_t seed, double tol,
+                                 int max_iter, int32_t *iters_dev, double *berr_dev,
+                                 int32_t *info_dev, int32_t *path_dev, void *work,
+                                 size_t work_bytes, void *stream) {
+  if (n < 0) return -1;
+  if (nrhs < 0) return -2;
+  if (n > 0 && A == nullptr) return -3;
+  if (lda < (n > 1 ? n : 1)) return -4;
+  if (n > 0 && LU == nullptr) return -5;
+  if (ldlu < (n > 1 ? n : 1)) return -6;
+  if (n > 0 && nrhs > 0 && B == nullptr) return -7;
+  if (ldb < (n > 1 ? n : 1)) return -8;
+  if (n > 0 && nrhs > 0 && X == nullptr) return -9;
+  if (ldx < (n > 1 ? n : 1)) return -10;
+  if (bad_depth(depth)) return -11;
+  if (!(tol >= 0.0)) return -13;
+  if (max_iter < 0) return -14;
+  const Layout L = layout(n, nrhs, depth);
+  if (n > 0 && work == nullptr) return -19;
+  if (work_bytes < L.total) return RBT_ERR_WORKSPACE;
+  hipStream_t s = S(stream);
+  double *small = at<double>(work, L.o_small);
+  double *berr = berr_dev ? berr_dev : small + 1;
+  int32_t its[2] = {0, 0}, path = 0;
+  if (info_dev) RBT_HIP_CHECK(launch_fill_i32(info_dev + 1, 0, s));
+  if (n == 0 || nrhs == 0) {
+    RBT_HIP_CHECK(launch_fill_f64(berr, 0.0, s));
+    if (info_dev) RBT_HIP_CHECK(launch_fill_i32(info_dev, 0, s));
+  } else {
+    const Geometry g = geometry(n, depth);
+    double *U = at<double>(work, L.o_coef);
+    double *V = U + n * depth;
+    double *winv = at<double>(work, L.o_winv);
+    int32_t *sync = at<int32_t>(work, L.o_sync);
+    RBT_HIP_CHECK(generate_t(n, depth, seed, U, V, s));
+    RBT_HIP_CHECK(transform2_t(g, A, lda, LU, ldlu, RBT_FP64, U, V, s));
+    int rc = genp_fp64(n, LU, ldlu, info_dev, s);
+    if (rc) return rc;
+    rc = diag_inverses_t(n, nrhs, LU, ldlu, winv, s);
+    if (rc) return rc;
+    RBT_HIP_CHECK(clear_sweep_err(sync, s));
+    RBT_HIP_CHECK(launch_copy_cols(n, nrhs, B, ldb, X, ldx, s));
+    rc = apply_solve(g, nrhs, (const double *)LU, ldlu, X, ldx, U, V, winv, sync, true, s);
+    if (rc) return rc;
+    int it = 0;
+    bool stalled = false;
+    rc = refine_classic(n, nrhs, A, lda, (const double *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv,
+                        sync, at<double>(work, L.o_resid), at<double>(work, L.o_partial), small,
+                        berr, tol, max_iter, &it, true, s, &stalled);
+    if (rc) return rc;
+    its[0] = it;
+    rc = read_sweep_err(sync, s);
+    if (rc) return rc;
+    double be = 0.0;
+    RBT_HIP_CHECK(hipMemcpyAsync(&be, berr, sizeof(double), hipMemcpyDeviceToHost, s));
+    RBT_HIP_CHECK(hipStreamSynchronize(s));
+    if (!(be <= tol)) {
+      path = 2;
+      rc = gepp_solve_refine(n, nrhs, A, lda, LU, ldlu, B, ldb, X, ldx, tol, max_iter,
+                             info_dev ? info_dev + 1 : nullptr, work, L, berr, &it, s);
+      if (rc) return rc;
+      its[1] = it;
+    }
   }
   if (iters_dev)
     RBT_HIP_CHECK(hipMemcpyAsync(iters_dev, its, sizeof(its), hipMemcpyHostToDevice, s));
@@ -1101,9 +1395,11 @@ BatchPlanSizes batch_sizes(int64_t batch, const int64_t *n, const int64_t *nrhs,
   size_t f = 0, d = 0, f64 = 0;  // floats, doubles, fallback doubles
   std::vector<int64_t> order(batch);
   for (int64_t i = 0; i < batch; ++i) order[i] = i;
-  // largest systems first (longest-processing-time order for the queue)
+  // largest systems first (longest-processing-time order for the queue);
+  // systems without work (n = 0 or nrhs = 0) last
+  auto work_n = [&](int64_t i) { return nrhs[i] > 0 ? n[i] : int64_t(-1); };
   std::stable_sort(order.begin(), order.end(),
-                   [&](int64_t a, int64_t b) { return n[a] > n[b]; });
+                   [&](int64_t a, int64_t b) { return work_n(a) > work_n(b); });
   if (desc) desc->resize(batch);
   for (int64_t t = 0; t < batch; ++t) {
     const int64_t i = order[t];
@@ -1154,7 +1450,7 @@ int device_cus() {
 
 extern "C" size_t rbt_batched_workspace_size(int64_t batch, const int64_t *n,
                                              const int64_t *nrhs, int depth, int prec) {
-  if (check_batch_sizes(batch, n, nrhs) != 0 || depth < 0 || depth > 3) return 0;
+  if (check_batch_sizes(batch, n, nrhs) != 0 || bad_depth(depth)) return 0;
   if (prec != RBT_FP32 && prec != RBT_BF16) return 0;
   return batch_sizes(batch, n, nrhs, depth, nullptr).total;
 }
@@ -1163,8 +1459,7 @@ extern "C" int rbt_batched_plan(int64_t batch, const int64_t *n, const int64_t *
                                 int prec, void *work, size_t work_bytes, void *stream) {
   const int rc = check_batch_sizes(batch, n, nrhs);
   if (rc) return rc;
-  if (depth < 0) return -4;
-  if (depth > 3) return RBT_ERR_UNSUPPORTED;
+  if (bad_depth(depth)) return -4;
   if (prec != RBT_FP32 && prec != RBT_BF16) return -5;
   if (work == nullptr) return -6;
   std::vector<BatchDesc> desc;
@@ -1199,8 +1494,7 @@ extern "C" int rbt_solve_batched(int64_t batch, const double *const *A, const in
   if (batch > 0 && (A == nullptr || lda == nullptr)) return A == nullptr ? -2 : -3;
   if (batch > 0 && (B == nullptr || ldb == nullptr)) return B == nullptr ? -4 : -5;
   if (batch > 0 && (X == nullptr || ldx == nullptr)) return X == nullptr ? -6 : -7;
-  if (depth < 0) return -8;
-  if (depth > 3) return RBT_ERR_UNSUPPORTED;
+  if (bad_depth(depth)) return -8;
   if (prec != RBT_FP32 && prec != RBT_BF16) return -10;
   if (tol != tol) return -11;
   if (max_iter < 0) return -12;
@@ -1290,11 +1584,13 @@ extern "C" int rbt_solve_backward_mixed(int64_t n, int64_t nrhs, const float *LU
   // Lambda = A^-T G = U (A~^-T (V^T G)) with the FP32 factors of A~, then
   // refinement on A^T Lambda = G in FP64
   RBT_HIP_CHECK(generate_t(n, depth, seed, U, V, s));
-  int rc = diag_inverses_t(n, LU, ldlu, winv, s);
+  RBT_HIP_CHECK(clear_sweep_err(sync, s));
+  const bool f64 = options().mixed_fp64_inner != 0;
+  int rc = diag_inverses_t(n, LU, ldlu, winv, f64, s);
   if (rc) return rc;
   auto adjoint_solve = [&](double *Y, int64_t ldy) -> int {
-    RBT_HIP_CHECK(transform_vec_t(g, nrhs, Y, ldy, V, RBT_OP_T, s));
-    const int r = getrs_t(n, nrhs, LU, ldlu, Y, ldy, 1, winv, sync, s);
+    RBT_HIP_CHECK(transform_v_t(g, nrhs, Y, ldy, V, RBT_OP_T, s));
+    const int r = getrs_t(n, nrhs, LU, ldlu, Y, ldy, 1, winv, sync, f64, s);
     if (r) return r;
     RBT_HIP_CHECK(transform_vec_t(g, nrhs, Y, ldy, U, RBT_OP_N, s));
     return 0;
@@ -1312,19 +1608,20 @@ extern "C" int rbt_solve_backward_mixed(int64_t n, int64_t nrhs, const float *LU
     if (it >= max_iter) break;
     double be_host = 0.0;
     RBT_HIP_CHECK(hipMemcpyAsync(&be_host, berr, sizeof(double), hipMemcpyDeviceToHost, s));
-    RBT_HIP_CHECK(hipStreamSynchronize(s));
+    if (const int e = read_sweep_err(sync, s)) return e;  // also waits for be_host
     if (be_host <= tol) break;
     rc = adjoint_solve(R, n);
     if (rc) return rc;
     RBT_HIP_CHECK(launch_axpy_cols(n, nrhs, R, n, dB, lddb, s));
     ++it;
   }
-  if (dA != nullptr) RBT_HIP_CHECK(launch_neg_outer(n, nrhs, dB, lddb, X, ldx, dA, ldda, s));
-  if (iters_dev) {
-    RBT_HIP_CHECK(hipMemcpyAsync(iters_dev, &it, sizeof(int32_t), hipMemcpyHostToDevice, s));
-    RBT_HIP_CHECK(hipStreamSynchronize(s));
+  if (dA != nullptr) {
+    StageScope t(kStageOuter, s, 8.0 * double(n) * n);
+    RBT_HIP_CHECK(launch_neg_outer(n, nrhs, dB, lddb, X, ldx, dA, ldda, s));
   }
-  return 0;
+  if (iters_dev)
+    RBT_HIP_CHECK(hipMemcpyAsync(iters_dev, &it, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  return read_sweep_err(sync, s);  // synchronizes
 }
 
 extern "C" int rbt_set_option(int option, int64_t value) {
@@ -1349,6 +1646,25 @@ extern "C" int rbt_set_option(int option, int64_t value) {
       if (value != 0 && value != 1) return -2;
       options().bf16_staged = value;
       return 0;
+    case RBT_OPT_SWEEP_SPIN_LIMIT:
+      options().sweep_spin_limit = value < 0 ? -1 : value;
+      return 0;
+    case RBT_OPT_MIXED_FP64_INNER:
+      if (value != 0 && value != 1) return -2;
+      options().mixed_fp64_inner = value;
+      return 0;
+    case RBT_OPT_GRANULE:
+      if (value < 1 || value > (int64_t(1) << 30)) return -2;
+      options().granule = value;
+      return 0;
+    case RBT_OPT_BUTTERFLY:
+      if (value != 0 && value != 1) return -2;
+      options().kind = value;
+      return 0;
+    case RBT_OPT_SIDES:
+      if (value != 1 && value != 2) return -2;
+      options().sides = value;
+      return 0;
     default:
       return -1;
   }
@@ -1361,6 +1677,11 @@ extern "C" int64_t rbt_get_option(int option) {
     case RBT_OPT_BATCH_WGS_PER_CU: return options().batch_wgs_per_cu;
     case RBT_OPT_LOOKAHEAD: return options().lookahead;
     case RBT_OPT_BF16_STAGED: return options().bf16_staged;
+    case RBT_OPT_SWEEP_SPIN_LIMIT: return options().sweep_spin_limit;
+    case RBT_OPT_MIXED_FP64_INNER: return options().mixed_fp64_inner;
+    case RBT_OPT_GRANULE: return options().granule;
+    case RBT_OPT_BUTTERFLY: return options().kind;
+    case RBT_OPT_SIDES: return options().sides;
     default: return -1;
   }
 }
@@ -1393,12 +1714,16 @@ extern "C" int rbt_solve_backward(int64_t n, int64_t nrhs, const double *LU, int
   // Lambda = A^-T G = U (A~^-T (V^T G)),  A~ = U^T A V = L U_f
   RBT_HIP_CHECK(generate_t(n, depth, seed, U, V, s));
   RBT_HIP_CHECK(launch_copy_cols(n, nrhs, G, ldg, dB, lddb, s));
-  RBT_HIP_CHECK(transform_vec_t(g, nrhs, dB, lddb, V, RBT_OP_T, s));
+  RBT_HIP_CHECK(transform_v_t(g, nrhs, dB, lddb, V, RBT_OP_T, s));
   int rc = diag_inverses_t(n, nrhs, LU, ldlu, winv, s);
   if (rc) return rc;
+  RBT_HIP_CHECK(clear_sweep_err(at<int32_t>(work, L.o_sync), s));
   rc = getrs_t(n, nrhs, LU, ldlu, dB, lddb, 1, winv, at<int32_t>(work, L.o_sync), s);
   if (rc) return rc;
   RBT_HIP_CHECK(transform_vec_t(g, nrhs, dB, lddb, U, RBT_OP_N, s));
-  if (dA != nullptr) RBT_HIP_CHECK(launch_neg_outer(n, nrhs, dB, lddb, X, ldx, dA, ldda, s));
+  if (dA != nullptr) {
+    StageScope t(kStageOuter, s, 8.0 * double(n) * n);
+    RBT_HIP_CHECK(launch_neg_outer(n, nrhs, dB, lddb, X, ldx, dA, ldda, s));
+  }
   return 0;
 }

@@ -11,6 +11,13 @@
 // coefficient of the output index times 1/sqrt(2) when the index is paired
 // (the normalisation folded into the diagonal, as Sec. 3 notes for the
 // 4dn^2 flop count).
+//
+// Rotation butterflies (Sec. 3, the block-rotation form with R_l = I): a pair
+// (a, b) becomes (c x_a + s x_b, s x_a - c x_b) with c, s the packed
+// coefficients at a and b (cos and sin of the pair's angle); unpaired indices
+// are left as they are (a rotation by 0 degrees). Each layer is symmetric, so
+// U^T and U differ only in the order of the layers.
+// One-sided RBT (Sec. 7): only the rows are transformed (A~ = U^T A).
 #ifndef RBT_BUTTERFLY_DEV_H
 #define RBT_BUTTERFLY_DEV_H
 
@@ -38,15 +45,19 @@ __device__ __forceinline__ double coefficient(uint64_t seed, int64_t i, int side
   return exp((2.0 * u - 1.0) / 20.0);
 }
 
-// Geometry of one pass over layers lo..hi (P = hi - lo + 1 <= 3).
+// Geometry of one pass over layers lo..hi (P = hi - lo + 1 <= 3), and the
+// butterfly kind (rot: rotation butterflies) and sides (2, or 1 for the
+// one-sided transform of the rows only).
 struct Pass {
   int64_t n, q;
   int d, lo, hi;
   int64_t stride;   // 2^(d-hi) q : partner distance of layer hi
   int64_t ngroups;  // m / 2^P
+  int rot, sides;
 };
 
-__host__ __device__ inline Pass make_pass(int64_t n, int64_t q, int d, int lo, int hi) {
+__host__ __device__ inline Pass make_pass(int64_t n, int64_t q, int d, int lo, int hi,
+                                          int rot = 0, int sides = 2) {
   Pass ps;
   ps.n = n;
   ps.q = q;
@@ -55,6 +66,8 @@ __host__ __device__ inline Pass make_pass(int64_t n, int64_t q, int d, int lo, i
   ps.hi = hi;
   ps.stride = q << (d - hi);
   ps.ngroups = (q << d) >> (hi - lo + 1);
+  ps.rot = rot;
+  ps.sides = sides;
   return ps;
 }
 
@@ -62,7 +75,26 @@ __host__ __device__ inline Pass make_pass(int64_t n, int64_t q, int d, int lo, i
 __host__ __device__ inline Pass identity_pass(int64_t n) {
   Pass ps;
   ps.n = n; ps.q = n; ps.d = 0; ps.lo = 1; ps.hi = 0; ps.stride = n; ps.ngroups = n;
+  ps.rot = 0; ps.sides = 2;
   return ps;
+}
+
+// Packed rotation coefficient of index i in layer `layer` for the structure
+// (n, q, d): cos(theta) at the top index of a pair, sin(theta) at the bottom
+// one, 1 for an unpaired index; theta = 2 pi u, u the uniform of the
+// coefficient counter at the pair's top index.
+__device__ __forceinline__ double rotation_coefficient(uint64_t seed, int64_t i, int side,
+                                                       int layer, int64_t n, int64_t q, int d) {
+  const int64_t r = i % q, t = i / q;
+  const int64_t bit = int64_t(1) << (d - layer);
+  const int64_t j = r + (t ^ bit) * q;
+  if (j >= n) return 1.0;
+  const bool top = (t & bit) == 0;
+  const int64_t a = top ? i : j;
+  const uint64_t c = 128ull * uint64_t(a) + 64ull * uint64_t(side) + uint64_t(layer - 1);
+  const double u = double(splitmix_at(seed, c) >> 11) * 0x1.0p-53;
+  const double th = 2.0 * 3.14159265358979323846 * u;
+  return top ? cos(th) : sin(th);
 }
 
 // First index of group g.
@@ -106,11 +138,43 @@ __device__ __forceinline__ void transform2_block(PA __restrict__ A, int64_t lda,
   for (int c = 0; c < G; ++c)
 #pragma unroll
     for (int r = 0; r < G; ++r) x[r][c] = (rv[r] && cv[c]) ? A[ri[r] + ci[c] * lda] : 0.0;
+  const bool two = ps.sides != 1;
 #pragma unroll
   for (int bit = 0; bit < P; ++bit) {
     // layer l = hi - bit pairs block members p and p ^ (1 << bit)
     const int l = ps.hi - bit;
     const int64_t off = int64_t(l - 1) * ps.n;
+    if (ps.rot) {
+#pragma unroll
+      for (int p = 0; p < G; ++p) {  // rows
+        if (p & (1 << bit)) continue;
+        const int p2 = p | (1 << bit);
+        if (!rv[p2]) continue;
+        const double c = U[off + ri[p]], sn = U[off + ri[p2]];
+#pragma unroll
+        for (int cc = 0; cc < G; ++cc) {
+          const double a = x[p][cc], b = x[p2][cc];
+          x[p][cc] = c * a + sn * b;
+          x[p2][cc] = sn * a - c * b;
+        }
+      }
+      if (two) {
+#pragma unroll
+        for (int p = 0; p < G; ++p) {  // columns
+          if (p & (1 << bit)) continue;
+          const int p2 = p | (1 << bit);
+          if (!cv[p2]) continue;
+          const double c = V[off + ci[p]], sn = V[off + ci[p2]];
+#pragma unroll
+          for (int r = 0; r < G; ++r) {
+            const double a = x[r][p], b = x[r][p2];
+            x[r][p] = c * a + sn * b;
+            x[r][p2] = sn * a - c * b;
+          }
+        }
+      }
+      continue;
+    }
     double fr[G], fc[G];
 #pragma unroll
     for (int p = 0; p < G; ++p) {
@@ -118,7 +182,7 @@ __device__ __forceinline__ void transform2_block(PA __restrict__ A, int64_t lda,
       const double sr = (rv[p] && rv[p2]) ? kInvSqrt2 : 1.0;
       const double sc = (cv[p] && cv[p2]) ? kInvSqrt2 : 1.0;
       fr[p] = rv[p] ? U[off + ri[p]] * sr : 0.0;
-      fc[p] = cv[p] ? V[off + ci[p]] * sc : 0.0;
+      fc[p] = two ? (cv[p] ? V[off + ci[p]] * sc : 0.0) : 1.0;
     }
 #pragma unroll
     for (int p = 0; p < G; ++p) {  // rows
@@ -136,7 +200,7 @@ __device__ __forceinline__ void transform2_block(PA __restrict__ A, int64_t lda,
     for (int p = 0; p < G; ++p) {  // columns
       if (p & (1 << bit)) continue;
       const int p2 = p | (1 << bit);
-      if (!cv[p2]) continue;
+      if (!cv[p2] || !two) continue;
 #pragma unroll
       for (int r = 0; r < G; ++r) {
         const double a = x[r][p], b = x[r][p2];
@@ -178,6 +242,19 @@ __device__ __forceinline__ void transform_vec_block(PB __restrict__ B, int64_t l
     const int bit = (OP == RBT_OP_T) ? s : P - 1 - s;
     const int l = ps.hi - bit;
     const int64_t off = int64_t(l - 1) * ps.n;
+    if (ps.rot) {
+#pragma unroll
+      for (int p = 0; p < G; ++p) {
+        if (p & (1 << bit)) continue;
+        const int p2 = p | (1 << bit);
+        if (!rv[p2]) continue;
+        const double c = C[off + ri[p]], sn = C[off + ri[p2]];
+        const double a = x[p], b = x[p2];
+        x[p] = c * a + sn * b;
+        x[p2] = sn * a - c * b;
+      }
+      continue;
+    }
     double f[G];
 #pragma unroll
     for (int p = 0; p < G; ++p) {

@@ -1,7 +1,8 @@
 // Host-only parts of the ABI: butterfly structure and coefficient draws.
 //
 // Structure: Sec. 3 (Eq. 2-4) with the loop nest of Algorithm 1 and its
-// non-tiled reference size m = 2^d ceil(n / 2^d). Written here in the closed
+// reference size m = 2^d g ceil(n / (2^d g)) (g = 1: non-tiled; g = n_b:
+// tiled, text after Alg. 1; g = lcm(p, q) n_b: Eq. 8). Written here in the closed
 // form the kernels use: with q = m / 2^d every index is i = r + t q
 // (0 <= r < q, 0 <= t < 2^d); layer l has half-size h_l = 2^(d-l) q, so i is
 // in the top half of its layer-l butterfly iff bit (d-l) of t is 0, and its
@@ -40,19 +41,76 @@ inline double coefficient(uint64_t seed, int side, int layer, int64_t i) {
 
 extern "C" int rbt_version(void) { return 100; }
 
-extern "C" int rbt_structure(int64_t n, int depth, int64_t *partner) {
+extern "C" int64_t rbt_reference_size(int64_t n, int depth, int64_t granule) {
+  if (n < 0 || depth < 0 || depth > RBT_MAX_DEPTH || granule < 1) return -1;
+  const int64_t g = (int64_t(1) << depth) * granule;
+  return g * ((n + g - 1) / g);
+}
+
+extern "C" int64_t rbt_comm_free_granule(int64_t nb, int64_t p, int64_t q) {
+  if (nb < 1 || p < 1 || q < 1) return -1;
+  int64_t a = p, b = q;
+  while (b != 0) {
+    const int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return (p / a) * q * nb;  // lcm(p, q) nb
+}
+
+extern "C" int rbt_structure_ex(int64_t n, int depth, int64_t granule, int64_t *partner) {
   if (n < 0) return -1;
   if (depth < 0 || depth > RBT_MAX_DEPTH) return -2;
-  if (partner == nullptr && n > 0 && depth > 0) return -3;
-  const int64_t g = int64_t(1) << depth;
-  const int64_t m = g * ((n + g - 1) / g);
-  const int64_t q = (n == 0) ? 1 : m / g;
+  if (granule < 1) return -3;
+  if (partner == nullptr && n > 0 && depth > 0) return -4;
+  const int64_t m = rbt_reference_size(n, depth, granule);
+  const int64_t q = (n == 0) ? 1 : (m >> depth);
   for (int layer = 1; layer <= depth; ++layer) {
     const int64_t bit = int64_t(1) << (depth - layer);
     for (int64_t i = 0; i < n; ++i) {
       const int64_t r = i % q, t = i / q;
       const int64_t j = r + (t ^ bit) * q;
       partner[int64_t(layer - 1) * n + i] = (j < n) ? j : -1;
+    }
+  }
+  return 0;
+}
+
+extern "C" int rbt_structure(int64_t n, int depth, int64_t *partner) {
+  const int rc = rbt_structure_ex(n, depth, 1, partner);
+  return rc == -4 ? -3 : rc;
+}
+
+// Rotation butterflies: cos(theta) at the top index of a pair, sin(theta) at
+// the bottom one, 1 where unpaired; theta = 2 pi u from the counter of the
+// pair's top index.
+extern "C" int rbt_generate_rotations(int64_t n, int depth, uint64_t seed, int64_t granule,
+                                      double *U, double *V) {
+  if (n < 0) return -1;
+  if (depth < 0 || depth > RBT_MAX_DEPTH) return -2;
+  if (granule < 1) return -4;
+  if (U == nullptr && n > 0 && depth > 0) return -5;
+  if (V == nullptr && n > 0 && depth > 0) return -6;
+  const int64_t m = rbt_reference_size(n, depth, granule);
+  const int64_t q = (n == 0) ? 1 : (m >> depth);
+  for (int side = 0; side < 2; ++side) {
+    double *C = side ? V : U;
+    for (int layer = 1; layer <= depth; ++layer) {
+      const int64_t bit = int64_t(1) << (depth - layer);
+      for (int64_t i = 0; i < n; ++i) {
+        const int64_t r = i % q, t = i / q;
+        const int64_t j = r + (t ^ bit) * q;
+        double v = 1.0;
+        if (j < n) {
+          const bool top = (t & bit) == 0;
+          const int64_t a = top ? i : j;
+          const uint64_t c = 128ull * uint64_t(a) + 64ull * uint64_t(side) + uint64_t(layer - 1);
+          const double u = double(splitmix_at(seed, c) >> 11) * 0x1.0p-53;
+          const double th = 2.0 * 3.14159265358979323846 * u;
+          v = top ? std::cos(th) : std::sin(th);
+        }
+        C[int64_t(layer - 1) * n + i] = v;
+      }
     }
   }
   return 0;

@@ -25,15 +25,28 @@ void report_hip_error(hipError_t e, const char *what, const char *file, int line
 // Block size of the elimination (diagonal blocks, panel width).
 constexpr int kNB = 128;
 
-// Butterfly geometry: m = 2^d ceil(n / 2^d), q = m / 2^d.
+// Butterfly geometry: reference size m = 2^d g ceil(n / (2^d g)) for the
+// granule g (1: the non-tiled size of Sec. 3; a tile size n_b: the tiled
+// size; lcm(p, q) n_b: the communication-free size of Eq. 8), q = m / 2^d.
+// kind: 0 random diagonals with the butterflies of Eq. 2 (Eq. 3), 1 rotation
+// butterflies; sides: 2 (U^T A V), 1 (U^T A, the one-sided RBT).
 struct Geometry {
   int64_t n, m, q;
   int d;
+  int kind, sides;
 };
-inline Geometry geometry(int64_t n, int d) {
-  const int64_t g = int64_t(1) << d;
+inline Geometry geometry_g(int64_t n, int d, int64_t granule, int kind = 0, int sides = 2) {
+  const int64_t g = (int64_t(1) << d) * granule;
   const int64_t m = g * ((n + g - 1) / g);
-  return Geometry{n, m, m / g, d};
+  return Geometry{n, m, m >> d, d, kind, sides};
+}
+// The library's structure options (RBT_OPT_GRANULE, RBT_OPT_BUTTERFLY,
+// RBT_OPT_SIDES; api.hip).
+int64_t butterfly_granule();
+int butterfly_kind();
+int butterfly_sides();
+inline Geometry geometry(int64_t n, int d) {
+  return geometry_g(n, d, butterfly_granule(), butterfly_kind(), butterfly_sides());
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -48,6 +61,8 @@ enum Stage {
   kStageTrailing,      // trailing update A22 -= L21 U12; work = flops 2 rem^2 kb
   kStageSolve,         // block triangular solves; work = flops
   kStageResidual,      // residual, norms, backward error; work = bytes of A read
+  kStagePivoted,       // partial-pivoting factorization (fallback); work = flops 2/3 n^3
+  kStageOuter,         // adjoint dA = -Lambda X^T; work = bytes written 8 n^2
   kStageCount
 };
 struct StageScope {
@@ -61,7 +76,9 @@ struct StageScope {
 // ---- kernel launchers (each defined next to its kernels) ----
 
 // k_butterfly.hip
-hipError_t launch_generate(int64_t n, int d, uint64_t seed, double *U, double *V, hipStream_t s);
+// coefficients of g.kind (diagonal entries, or packed cos/sin of the
+// rotation butterflies of the structure (n, q, d))
+hipError_t launch_generate(const Geometry &g, uint64_t seed, double *U, double *V, hipStream_t s);
 hipError_t launch_transform2(const Geometry &g, const double *A, int64_t lda, void *out,
                              int64_t ldo, int out_prec, const double *U, const double *V,
                              hipStream_t s);
@@ -115,12 +132,13 @@ hipError_t launch_sgemm_tiles(int tile, int64_t M, int64_t N, int64_t K, const f
                               bool bf16, hipStream_t s);
 
 // k_getrf.hip : factor the kb x kb diagonal block in place (kb <= kNB);
-// first exact zero pivot -> *info = gofs + c + 1. FP32 blocks are eliminated
-// in FP64 and rounded on store.
+// first exact zero pivot -> *info = gofs + c + 1. FP32 blocks are
+// eliminated in FP32 arithmetic, or with fp64_arith in FP64 and rounded on
+// store (the launchers below take the same switch).
 hipError_t launch_diag_lu(int kb, double *A, int64_t lda, int64_t gofs, int32_t *info,
                           hipStream_t s);
 hipError_t launch_diag_lu(int kb, float *A, int64_t lda, int64_t gofs, int32_t *info,
-                          hipStream_t s);
+                          bool fp64_arith, hipStream_t s);
 
 // k_trsm.hip : triangular solves with a factored diagonal block T (kb <= kNB).
 enum class TriMode {
@@ -132,24 +150,27 @@ enum class TriMode {
 hipError_t launch_trsm_left(TriMode mode, int kb, int64_t N, const double *T, int64_t ldt,
                             double *B, int64_t ldb, hipStream_t s);
 hipError_t launch_trsm_left(TriMode mode, int kb, int64_t N, const float *T, int64_t ldt, float *B,
-                            int64_t ldb, hipStream_t s);
+                            int64_t ldb, bool fp64_arith, hipStream_t s);
 // X U = B in place, B: M x kb
 hipError_t launch_trsm_right_upper(int kb, int64_t M, const double *T, int64_t ldt, double *B,
                                    int64_t ldb, hipStream_t s);
 hipError_t launch_trsm_right_upper(int kb, int64_t M, const float *T, int64_t ldt, float *B,
-                                   int64_t ldb, hipStream_t s);
+                                   int64_t ldb, bool fp64_arith, hipStream_t s);
 // Both solves of a panel step in one launch: Br (M x kb) <- Br U^-1 and
 // Bl (kb x N) <- L^-1 Bl with the factored block T (same ldb for both).
 hipError_t launch_panel_trsm(int kb, int64_t M, int64_t N, const double *T, int64_t ldt,
                              double *Br, double *Bl, int64_t ldb, hipStream_t s);
 hipError_t launch_panel_trsm(int kb, int64_t M, int64_t N, const float *T, int64_t ldt, float *Br,
-                             float *Bl, int64_t ldb, hipStream_t s);
+                             float *Bl, int64_t ldb, bool fp64_arith, hipStream_t s);
 // Inverses of all kNB x kNB diagonal blocks of the factors of an n x n
 // elimination: block b's L^-1 at W + b * 2 kNB^2 and U^-1 at
-// W + b * 2 kNB^2 + kNB^2 (ld kNB). Needs diag_inv_doubles(n) doubles.
+// W + b * 2 kNB^2 + kNB^2 (ld kNB). Needs diag_inv_doubles(n) doubles. The
+// arithmetic and storage type is that of W (FP32 inverses of FP32 factors
+// for FP32 sweeps, FP64 otherwise).
 hipError_t launch_diag_inverses(int64_t n, const double *LU, int64_t ld, double *W,
                                 hipStream_t s);
 hipError_t launch_diag_inverses(int64_t n, const float *LU, int64_t ld, double *W, hipStream_t s);
+hipError_t launch_diag_inverses(int64_t n, const float *LU, int64_t ld, float *W, hipStream_t s);
 inline int64_t diag_inv_doubles(int64_t n) { return ((n + kNB - 1) / kNB) * 2 * kNB * kNB; }
 
 // k_solve.hip
@@ -158,13 +179,23 @@ constexpr int64_t kSkinnyMax = 16;  // right-hand sides handled by the sweeps an
 // nrhs <= kSkinnyMax, using the diagonal-block inverses of
 // launch_diag_inverses, as ONE persistent launch (ticket-ordered block rows,
 // a published-blocks counter). sync: sweep_sync_ints(n) int32
-// of device scratch (cleared by the launch itself); FP64 factors take one
-// refinement step per diagonal block, FP32 factors the inverse alone.
+// of device scratch; words 0..2 are cleared by each launch, word 3 is the
+// sticky error word (set when a bounded wait expired; the block's solution
+// is then NaN), which the caller clears (kSweepErrWord) and reads back.
+// FP64 factors take one refinement step per diagonal block, FP32 factors
+// the inverse alone.
 inline int64_t sweep_sync_ints(int64_t /*n*/) { return 4; }
+constexpr int kSweepErrWord = 3;
+// Sleeps a sweep's wait may take before it expires (rbt_set_option
+// RBT_OPT_SWEEP_SPIN_LIMIT; negative: every wait expires at once).
+int64_t sweep_spin_limit();
 hipError_t launch_sweep(TriMode mode, int64_t n, int64_t nrhs, const double *LU, int64_t ld,
                         const double *Winv, double *B, int64_t ldb, int32_t *sync, hipStream_t s);
 hipError_t launch_sweep(TriMode mode, int64_t n, int64_t nrhs, const float *LU, int64_t ld,
                         const double *Winv, double *B, int64_t ldb, int32_t *sync, hipStream_t s);
+// FP32 arithmetic with FP32 inverses (B stays FP64 storage)
+hipError_t launch_sweep(TriMode mode, int64_t n, int64_t nrhs, const float *LU, int64_t ld,
+                        const float *Winv, double *B, int64_t ldb, int32_t *sync, hipStream_t s);
 // doubles of scratch needed by launch_residual_berr
 size_t resid_scratch_doubles(int64_t n, int64_t nrhs);
 // R = B - A X; berr = Eq. 7 (max over columns); with_anorm: also ||A||_inf -> *anorm
@@ -239,6 +270,19 @@ hipError_t launch_batched(int64_t batch, void *work, size_t work_bytes, const do
 inline int64_t batched_sys_doubles(int64_t n, int64_t nrhs, int d) {
   return 2 * n * d + ((n + 63) / 64) * 64 * 64 + n * nrhs;
 }
+
+// k_gepp.hip : elimination with partial pivoting (the robust re-solve of the
+// Sec. 5 fallback). launch_gepp factors A in place (P A = L U, ipiv 1-based
+// as LAPACK's getrf; *info = first zero pivot column, 1-based) using
+// gepp_scratch_bytes() of scratch; launch_ipiv_to_perm turns ipiv into
+// perm[i] = original row of row i; launch_gather_rows: Y[i, :] = B[perm[i], :].
+constexpr int64_t kPermLdsMax = 16384;  // ipiv_to_perm works in LDS up to this n
+size_t gepp_scratch_bytes();
+hipError_t launch_gepp(int64_t n, double *A, int64_t lda, int64_t *ipiv, int32_t *info,
+                       void *scratch, hipStream_t s);
+hipError_t launch_ipiv_to_perm(int64_t n, const int64_t *ipiv, int64_t *perm, hipStream_t s);
+hipError_t launch_gather_rows(int64_t n, int64_t nrhs, const int64_t *perm, const double *B,
+                              int64_t ldb, double *Y, int64_t ldy, hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t *p, int32_t v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, hipStream_t s);

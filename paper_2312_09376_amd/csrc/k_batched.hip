@@ -29,6 +29,7 @@
 // table; the kernel checks the header against its arguments and does
 // nothing for a plan that does not match.
 #include "butterfly_dev.h"
+#include "mma16.h"
 
 namespace rbt {
 
@@ -59,6 +60,11 @@ typedef float RBT_AS_GLOBAL gfloat;
 // access) and loads from valid LDS addresses can be issued unconditionally.
 #define RBT_AS_LDS __attribute__((address_space(3)))
 typedef double RBT_AS_LDS ldouble;
+// LDS pointer of element type C
+template <typename C>
+struct Lds {
+  typedef C RBT_AS_LDS T;
+};
 __device__ __forceinline__ f4u ld4(const float *p) { return *reinterpret_cast<const f4u *>(p); }
 __device__ __forceinline__ f4u ld4(const gfloat *p) {
   return *reinterpret_cast<const f4u RBT_AS_GLOBAL *>(p);
@@ -94,13 +100,9 @@ struct Args {
   uint64_t seed;
   double tol;
   int depth, prec, max_iter;
+  int64_t granule;  // reference-size granule of the butterfly structure
+  int kind, sides;  // butterfly kind (1: rotations) and sides (1: one-sided)
 };
-
-__device__ __forceinline__ double wave_bcast(double v, int src) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-  return __hiloint2double(hi, lo);
-}
 
 __device__ __forceinline__ double nanmax(double a, double b) {
   return (b > a || b != b) ? b : a;
@@ -346,25 +348,24 @@ __device__ __forceinline__ void store_ct(const f4 (&c)[2][2], PF C, int64_t ld, 
     }
 }
 
-// FP64 panel products (the solves with the diagonal block's inverses): an
-// explicit inverse applied in FP32 loses accuracy on blocks with growth, so
-// these products stay in FP64 (v_mfma_f64_16x16x4f64, output element
-// (lane l, v) at row l/16 + 4v, column l % 16) and only the result is
-// rounded to FP32. Operands come from accessors a(m, k), b(k, n).
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-template <typename FA, typename FB>
-__device__ __forceinline__ void tile_mma64(FA a_at, FB b_at, d4 (&acc)[2][2]) {
+// Panel products (the solves with the diagonal block's inverses) on the
+// 16 x 16 x 4 matrix cores of the factors' arithmetic type C (FP32 for the
+// low-precision pass, FP64 for the fallback; mma16.h gives the output
+// layout). Operands come from accessors a(m, k), b(k, n); acc is one
+// wavefront's 32 x 32 part of a 64 x 64 tile, K = 64.
+template <typename C, typename FA, typename FB>
+__device__ __forceinline__ void tile_mma_c(FA a_at, FB b_at, typename Mma16<C>::v4 (&acc)[2][2]) {
+  typedef typename Mma16<C>::v4 c4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int l16 = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 2; ++j) acc[i][j] = c4{C(0), C(0), C(0), C(0)};
 #pragma unroll 4
   for (int kk = 0; kk < BB / 4; ++kk) {
-    double a[2], b[2];
+    C a[2], b[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) a[i] = a_at(wm * 32 + 16 * i + l16, 4 * kk + lk);
 #pragma unroll
@@ -372,16 +373,15 @@ __device__ __forceinline__ void tile_mma64(FA a_at, FB b_at, d4 (&acc)[2][2]) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < 2; ++j) acc[i][j] = Mma16<C>::mma(a[i], b[j], acc[i][j]);
   }
 }
 
-// C (FP32 or FP64, ld) = acc (rounded), or C -= acc (SUB); rows < rv,
+// Cm (FP32 or FP64, ld) = acc, or Cm -= acc (SUB), in type C; rows < rv,
 // cols < cv.
-template <bool SUB = false, typename T>
-__device__ __forceinline__ void tile_store64(const d4 (&acc)[2][2], T *C, int64_t ld, int rv,
-                                             int cv) {
+template <typename C, bool SUB = false, typename T>
+__device__ __forceinline__ void tile_store_c(const typename Mma16<C>::v4 (&acc)[2][2], T *Cm,
+                                             int64_t ld, int rv, int cv) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int l16 = lane & 15, lk = lane >> 4;
@@ -393,11 +393,11 @@ __device__ __forceinline__ void tile_store64(const d4 (&acc)[2][2], T *C, int64_
       if (col >= cv) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = wm * 32 + 16 * i + lk + 4 * v;
+        const int row = wm * 32 + 16 * i + Mma16<C>::row(lk, v);
         if (row < rv) {
-          T RBT_AS_GLOBAL *p = (T RBT_AS_GLOBAL *)C + row + int64_t(col) * ld;
+          T RBT_AS_GLOBAL *p = (T RBT_AS_GLOBAL *)Cm + row + int64_t(col) * ld;
           if (SUB)
-            *p = T(double(*p) - acc[i][j][v]);
+            *p = T(C(*p) - acc[i][j][v]);
           else
             *p = T(acc[i][j][v]);
         }
@@ -406,11 +406,12 @@ __device__ __forceinline__ void tile_store64(const d4 (&acc)[2][2], T *C, int64_
 }
 
 // Stage a 64 x 64 block of F (FP32 or FP64, column-major, rows r0..,
-// cols c0..; rv x cv valid) in LDS as FP64 D[c * LDS_ + r] (zero outside).
-// (src is factor storage, D is LDS: both address spaces made explicit.)
-template <typename T>
-__device__ __forceinline__ void stage64(double *D_in, const T *src_in, int64_t ld, int rv, int cv) {
-  ldouble *D = (ldouble *)D_in;
+// cols c0..; rv x cv valid) in LDS as D[c * LDS_ + r] of type C (zero
+// outside). (src is factor storage, D is LDS: both address spaces made
+// explicit.)
+template <typename C, typename T>
+__device__ __forceinline__ void stage_c(C *D_in, const T *src_in, int64_t ld, int rv, int cv) {
+  typename Lds<C>::T *D = (typename Lds<C>::T *)D_in;
   const T RBT_AS_GLOBAL *src = (const T RBT_AS_GLOBAL *)src_in;
   const int tid = threadIdx.x;
   const int col = tid >> 2, seg = (tid & 3) * 16;
@@ -438,13 +439,15 @@ __device__ __forceinline__ void stage64(double *D_in, const T *src_in, int64_t l
     }
   }
 #pragma unroll
-  for (int e = 0; e < 16; ++e) D[col * LDS_ + seg + e] = double(v[e]);
+  for (int e = 0; e < 16; ++e) D[col * LDS_ + seg + e] = C(v[e]);
 }
 
 // ------------------------------------------------------- one system
 
 struct Sys {
   int64_t n, nrhs;
+  int64_t q;         // m / 2^d of the butterfly structure
+  int rot, sides;    // butterfly kind (rotations) and sides
   float *F;          // n x n, ld n
   double *F64;       // n x n, ld n: FP64 factors of the fallback (nullable)
   double *U, *V;     // n x d each
@@ -466,16 +469,19 @@ __device__ __forceinline__ T *fmat(const Sys &s) {
     return s.F64;
 }
 
-// Factor the kb x kb diagonal block at (k, k) of F: S (LDS, FP64) <- L\U,
-// T (LDS, FP64) <- L^-1 below the diagonal, U^-1 on and above; inverses
-// also to Inv (64 x 64, full, identity beyond kb); factors back to F.
+// Factor the kb x kb diagonal block at (k, k) of F in the factors'
+// arithmetic type TF (FP32 for the low-precision pass, FP64 for the
+// fallback): S (LDS) <- L\U, T (LDS) <- L^-1 below the diagonal, U^-1 on
+// and above; inverses also to Inv (64 x 64 of type TF, full, identity beyond
+// kb); factors back to F.
 template <typename TF>
 __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double *S_in, double *T_in,
-                                        double *Invb, int *info_sh) {
-  ldouble *S = (ldouble *)S_in;
-  ldouble *T = (ldouble *)T_in;
+                                        TF *Invb, int *info_sh) {
+  typedef typename Lds<TF>::T lds_t;
+  lds_t *S = (lds_t *)S_in;
+  lds_t *T = (lds_t *)T_in;
   TF RBT_AS_GLOBAL *F = (TF RBT_AS_GLOBAL *)fmat<TF>(s);
-  double RBT_AS_GLOBAL *Invg = (double RBT_AS_GLOBAL *)Invb;
+  TF RBT_AS_GLOBAL *Invg = (TF RBT_AS_GLOBAL *)Invb;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   {
     const int r = tid & 63, cg = tid >> 6;
@@ -489,26 +495,26 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
       const int c = cg + 4 * t;
-      S[c * LDS_ + r] = (r < kb && c < kb) ? double(v[t]) : (r == c ? 1.0 : 0.0);
+      S[c * LDS_ + r] = (r < kb && c < kb) ? v[t] : (r == c ? TF(1) : TF(0));
     }
   }
   __syncthreads();
   for (int c0 = 0; c0 < BB; c0 += 16) {
     if (wave == 0) {
-      double xa[16];
+      TF xa[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) xa[j] = S[(c0 + j) * LDS_ + lane];
 #pragma unroll
       for (int cc = 0; cc < 16; ++cc) {
         const int c = c0 + cc;
-        double prow[16];
+        TF prow[16];
 #pragma unroll
         for (int j = cc; j < 16; ++j) prow[j] = wave_bcast(xa[j], c);
-        const double p = prow[cc];
-        if (lane == 0 && c < kb && p == 0.0 && *info_sh == 0) *info_sh = int(k + c + 1);
+        const TF p = prow[cc];
+        if (lane == 0 && c < kb && p == TF(0) && *info_sh == 0) *info_sh = int(k + c + 1);
         const bool act = lane > c;
         // one division per pivot; rows above it take a zero multiplier
-        const double la = act ? xa[cc] * (1.0 / p) : 0.0;
+        const TF la = act ? xa[cc] * (TF(1) / p) : TF(0);
         xa[cc] = act ? la : xa[cc];
 #pragma unroll
         for (int j = cc + 1; j < 16; ++j) xa[j] -= la * prow[j];
@@ -522,7 +528,7 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
     if (c1 >= BB) break;
     if (tid < BB - c1) {  // U rows c0..c0+15, columns c1..63
       const int col = c1 + tid;
-      double y[16];
+      TF y[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) y[i] = S[col * LDS_ + c0 + i];
 #pragma unroll
@@ -536,7 +542,7 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
     const int w = BB - c1;
     for (int e = tid; e < w * w; e += BT) {
       const int i = c1 + e % w, j = c1 + e / w;
-      double a = S[j * LDS_ + i];
+      TF a = S[j * LDS_ + i];
 #pragma unroll
       for (int t = 0; t < 16; ++t) a -= S[(c0 + t) * LDS_ + i] * S[j * LDS_ + c0 + t];
       S[j * LDS_ + i] = a;
@@ -552,49 +558,49 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
   if (wave == 0) {
     const int c = lane;
     for (int i = 1; i < BB; ++i) {  // X[i][c] = -(L[i][c] + sum_{c<t<i} L[i][t] X[t][c]), i > c
-      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+      TF p0 = TF(0), p1 = TF(0), p2 = TF(0), p3 = TF(0);
       int t = 0;
       for (; t + 4 <= i; t += 4) {
-        const double t0 = T[c * LDS_ + t + 0], t1 = T[c * LDS_ + t + 1];
-        const double t2 = T[c * LDS_ + t + 2], t3 = T[c * LDS_ + t + 3];
-        const double x0 = t + 0 > c ? t0 : (t + 0 == c ? 1.0 : 0.0);
-        const double x1 = t + 1 > c ? t1 : (t + 1 == c ? 1.0 : 0.0);
-        const double x2 = t + 2 > c ? t2 : (t + 2 == c ? 1.0 : 0.0);
-        const double x3 = t + 3 > c ? t3 : (t + 3 == c ? 1.0 : 0.0);
+        const TF t0 = T[c * LDS_ + t + 0], t1 = T[c * LDS_ + t + 1];
+        const TF t2 = T[c * LDS_ + t + 2], t3 = T[c * LDS_ + t + 3];
+        const TF x0 = t + 0 > c ? t0 : (t + 0 == c ? TF(1) : TF(0));
+        const TF x1 = t + 1 > c ? t1 : (t + 1 == c ? TF(1) : TF(0));
+        const TF x2 = t + 2 > c ? t2 : (t + 2 == c ? TF(1) : TF(0));
+        const TF x3 = t + 3 > c ? t3 : (t + 3 == c ? TF(1) : TF(0));
         p0 += S[(t + 0) * LDS_ + i] * x0;
         p1 += S[(t + 1) * LDS_ + i] * x1;
         p2 += S[(t + 2) * LDS_ + i] * x2;
         p3 += S[(t + 3) * LDS_ + i] * x3;
       }
       for (; t < i; ++t) {
-        const double tv = T[c * LDS_ + t];
-        const double x = t > c ? tv : (t == c ? 1.0 : 0.0);
+        const TF tv = T[c * LDS_ + t];
+        const TF x = t > c ? tv : (t == c ? TF(1) : TF(0));
         p0 += S[t * LDS_ + i] * x;
       }
       if (i > c) T[c * LDS_ + i] = -((p0 + p1) + (p2 + p3));
     }
   } else if (wave == 1) {
     const int c = lane;
-    T[c * LDS_ + c] = 1.0 / S[c * LDS_ + c];
+    T[c * LDS_ + c] = TF(1) / S[c * LDS_ + c];
     for (int i = BB - 2; i >= 0; --i) {  // X[i][c] = -(sum_{i<t<=c} U[i][t] X[t][c]) / U[i][i], i < c
-      const double rd = 1.0 / S[i * LDS_ + i];
-      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+      const TF rd = TF(1) / S[i * LDS_ + i];
+      TF p0 = TF(0), p1 = TF(0), p2 = TF(0), p3 = TF(0);
       int t = i + 1;
       for (; t + 4 <= BB; t += 4) {
-        const double t0 = T[c * LDS_ + t + 0], t1 = T[c * LDS_ + t + 1];
-        const double t2 = T[c * LDS_ + t + 2], t3 = T[c * LDS_ + t + 3];
-        const double x0 = t + 0 <= c ? t0 : 0.0;
-        const double x1 = t + 1 <= c ? t1 : 0.0;
-        const double x2 = t + 2 <= c ? t2 : 0.0;
-        const double x3 = t + 3 <= c ? t3 : 0.0;
+        const TF t0 = T[c * LDS_ + t + 0], t1 = T[c * LDS_ + t + 1];
+        const TF t2 = T[c * LDS_ + t + 2], t3 = T[c * LDS_ + t + 3];
+        const TF x0 = t + 0 <= c ? t0 : TF(0);
+        const TF x1 = t + 1 <= c ? t1 : TF(0);
+        const TF x2 = t + 2 <= c ? t2 : TF(0);
+        const TF x3 = t + 3 <= c ? t3 : TF(0);
         p0 += S[(t + 0) * LDS_ + i] * x0;
         p1 += S[(t + 1) * LDS_ + i] * x1;
         p2 += S[(t + 2) * LDS_ + i] * x2;
         p3 += S[(t + 3) * LDS_ + i] * x3;
       }
       for (; t < BB; ++t) {
-        const double tv = T[c * LDS_ + t];
-        const double x = t <= c ? tv : 0.0;
+        const TF tv = T[c * LDS_ + t];
+        const TF x = t <= c ? tv : TF(0);
         p0 += S[t * LDS_ + i] * x;
       }
       if (i < c) T[c * LDS_ + i] = -((p0 + p1) + (p2 + p3)) * rd;
@@ -604,7 +610,7 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
   for (int e = tid; e < BB * BB; e += BT) {
     const int r = e & 63, c = e >> 6;
     Invg[r + c * BB] = T[c * LDS_ + r];
-    if (r < kb && c < kb) F[(k + r) + (k + c) * s.n] = TF(S[c * LDS_ + r]);
+    if (r < kb && c < kb) F[(k + r) + (k + c) * s.n] = S[c * LDS_ + r];
   }
   __syncthreads();
 }
@@ -622,36 +628,43 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
   __bf16(*Bh)[LDH] = reinterpret_cast<__bf16(*)[LDH]>(L0 + (BB * LDH) / 4);
   for (int64_t k = 0; k < n; k += BB) {
     const int kb = int(n - k < BB ? n - k : BB);
-    double *Invb = s.Inv + (k / BB) * BB * BB;
+    // inverse block k / BB, counted in elements of the factors' type (the
+    // sweeps index the area the same way)
+    TF *Invb = reinterpret_cast<TF *>(s.Inv) + (k / BB) * BB * BB;
     diag_block<TF>(s, k, kb, L0, L1, Invb, info_sh);
     const int64_t rest = n - k - kb;
     if (rest <= 0) break;
     f4 acc[2][2];
-    d4 acc64[2][2];
-    const ldouble *T = (const ldouble *)L1;  // L^-1 below the diagonal, U^-1 on and above (ld LDS_)
-    const ldouble *L0l = (const ldouble *)L0;
-    // L21 = A21 U11^-1 (rows k+kb.., 64-row tiles), FP64 products
+    typename Mma16<double>::v4 acc64[2][2];
+    // panel products in the factors' arithmetic type
+    typename Mma16<TF>::v4 accp[2][2];
+    typedef typename Lds<TF>::T lds_t;
+    const lds_t *T = (const lds_t *)L1;  // L^-1 below the diagonal, U^-1 on and above (ld LDS_)
+    const lds_t *L0l = (const lds_t *)L0;
+    TF *L0t = reinterpret_cast<TF *>(L0);
+    // L21 = A21 U11^-1 (rows k+kb.., 64-row tiles)
     for (int64_t r0 = k + kb; r0 < n; r0 += BB) {
       const int rv = int(n - r0 < BB ? n - r0 : BB);
       // stage A21 tile as [k][r]: element (r, kx) at L0[kx * LDS_ + r]
-      stage64(L0, F + r0 + k * n, n, rv, kb);
+      stage_c<TF>(L0t, F + r0 + k * n, n, rv, kb);
       __syncthreads();
-      tile_mma64([&](int m, int kx) { return L0l[kx * LDS_ + m]; },
-                 [&](int kx, int nx) { return kx <= nx ? T[nx * LDS_ + kx] : 0.0; }, acc64);
+      tile_mma_c<TF>([&](int m, int kx) { return L0l[kx * LDS_ + m]; },
+                     [&](int kx, int nx) { return kx <= nx ? T[nx * LDS_ + kx] : TF(0); }, accp);
       __syncthreads();
-      tile_store64(acc64, F + r0 + k * n, n, rv, kb);
+      tile_store_c<TF>(accp, F + r0 + k * n, n, rv, kb);
     }
     __syncthreads();
-    // U12 = L11^-1 A12 (64-column tiles), FP64 products
+    // U12 = L11^-1 A12 (64-column tiles)
     for (int64_t c0 = k + kb; c0 < n; c0 += BB) {
       const int cv = int(n - c0 < BB ? n - c0 : BB);
       // stage A12 tile: element (kx, nx) at L0[nx * LDS_ + kx]
-      stage64(L0, F + k + c0 * n, n, kb, cv);
+      stage_c<TF>(L0t, F + k + c0 * n, n, kb, cv);
       __syncthreads();
-      tile_mma64([&](int m, int kx) { return m > kx ? T[kx * LDS_ + m] : (m == kx ? 1.0 : 0.0); },
-                 [&](int kx, int nx) { return L0l[nx * LDS_ + kx]; }, acc64);
+      tile_mma_c<TF>(
+          [&](int m, int kx) { return m > kx ? T[kx * LDS_ + m] : (m == kx ? TF(1) : TF(0)); },
+          [&](int kx, int nx) { return L0l[nx * LDS_ + kx]; }, accp);
       __syncthreads();
-      tile_store64(acc64, F + k + c0 * n, n, kb, cv);
+      tile_store_c<TF>(accp, F + k + c0 * n, n, kb, cv);
     }
     __syncthreads();
     // A22 -= L21 U12 (64 x 64 tiles; the L21 row tile stays in LDS)
@@ -726,7 +739,7 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
     const int wm = wave & 1, wn = wave >> 1, l16 = lane & 15, lk = lane >> 4;
     for (int64_t r0 = k + kb; r0 < n; r0 += BB) {
       const int rv = int(n - r0 < BB ? n - r0 : BB);
-      stage64(L0, F + r0 + k * n, n, rv, kb);  // (r, kx) at L0[kx * LDS_ + r]
+      stage_c<double>(L0, F + r0 + k * n, n, rv, kb);  // (r, kx) at L0[kx * LDS_ + r]
       double bv[16], cn[2][2][4];
       auto prefetch = [&](int64_t c) {
         const int cv = int(n - c < BB ? n - c : BB);
@@ -765,8 +778,8 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
             for (int v = 0; v < 4; ++v) cc[i][j][v] = cn[i][j][v];
         __syncthreads();
         if (c0 + BB < n) prefetch(c0 + BB);
-        tile_mma64([&](int m, int kx) { return L0d[kx * LDS_ + m]; },
-                   [&](int kx, int nx) { return L1d[nx * LDS_ + kx]; }, acc64);
+        tile_mma_c<double>([&](int m, int kx) { return L0d[kx * LDS_ + m]; },
+                           [&](int kx, int nx) { return L1d[nx * LDS_ + kx]; }, acc64);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -786,50 +799,57 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
   }
 }
 
-// One-sided transform of the n x nrhs block Y (ld ldy) with coefficients C.
+// One-sided transform of the n x nrhs block Y (ld ldy) with coefficients C,
+// in passes of at most three layers (op T: layers d..1, op N: 1..d).
 template <int OP>
 __device__ __noinline__ void transform_vec_sys(const Sys &s, int d, double *Y, int64_t ldy, const double *C) {
   if (d == 0) return;
-  const int64_t m = (((s.n - 1) >> d) + 1) << d;
-  const int64_t q = m >> d;
-  const dev::Pass ps = dev::make_pass(s.n, q, d, 1, d);
-  const int ng = int(ps.ngroups);
   double RBT_AS_GLOBAL *Yg = (double RBT_AS_GLOBAL *)Y;
   const double RBT_AS_GLOBAL *Cg = (const double RBT_AS_GLOBAL *)C;
-  for (int e = threadIdx.x; e < ng * int(s.nrhs); e += BT) {
-    const int gr = e % ng, j = e / ng;
-    const int64_t rb = dev::group_base(ps, gr);
-    if (rb >= s.n) continue;
-    switch (d) {
-      case 1: dev::transform_vec_block<1, OP>(Yg, ldy, j, Cg, ps, rb); break;
-      case 2: dev::transform_vec_block<2, OP>(Yg, ldy, j, Cg, ps, rb); break;
-      default: dev::transform_vec_block<3, OP>(Yg, ldy, j, Cg, ps, rb); break;
+  for (int k = 0; k < (d + 2) / 3; ++k) {
+    // op T: passes (d-2..d), (d-5..d-3), ...; op N: (1..3), (4..6), ...
+    const int hi = OP == RBT_OP_T ? d - 3 * k : (3 * k + 3 < d ? 3 * k + 3 : d);
+    const int lo = OP == RBT_OP_T ? (hi - 2 > 1 ? hi - 2 : 1) : 3 * k + 1;
+    const dev::Pass ps = dev::make_pass(s.n, s.q, d, lo, hi, s.rot, s.sides);
+    const int ng = int(ps.ngroups);
+    for (int e = threadIdx.x; e < ng * int(s.nrhs); e += BT) {
+      const int gr = e % ng, j = e / ng;
+      const int64_t rb = dev::group_base(ps, gr);
+      if (rb >= s.n) continue;
+      switch (hi - lo + 1) {
+        case 1: dev::transform_vec_block<1, OP>(Yg, ldy, j, Cg, ps, rb); break;
+        case 2: dev::transform_vec_block<2, OP>(Yg, ldy, j, Cg, ps, rb); break;
+        default: dev::transform_vec_block<3, OP>(Yg, ldy, j, Cg, ps, rb); break;
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
-// Y (n x nrhs FP64, ld ldy) <- (L U)^-1 Y (LOWER: L, else U) with the FP32
-// factors widened to FP64 and the FP64 inverses of the diagonal blocks,
-// right-looking: for each diagonal block b in sweep order, x_b = Dinv_b y_b
-// (threads: 64 rows x 4 segments of 16, reduced in LDS), then every row
-// still to be solved takes y_m -= F[m, block b] x_b as an FP64 matrix-core
-// product of 16-row tiles of the factor (16 loads per lane, issued one tile
-// ahead) with x_b (16 values per lane, held in registers for the step).
-// v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16]; output element (l, v) is row l / 16 + 4 v, column
-// l % 16. NRT: right-hand sides of the inverse product (>= N).
+// Y (n x nrhs FP64 storage, ld ldy) <- (L U)^-1 Y (LOWER: L, else U) with
+// the factors and the inverses of their diagonal blocks, in the factors'
+// arithmetic type TF (FP32 for the low-precision pass: a value of Y is
+// rounded to FP32 when the sweep first reads it and every update is an FP32
+// operation; FP64 for the fallback), right-looking: for each diagonal block
+// b in sweep order, x_b = Dinv_b y_b (threads: 64 rows x 4 segments of 16,
+// reduced in LDS), then every row still to be solved takes
+// y_m -= F[m, block b] x_b as a matrix-core product of 16-row tiles of the
+// factor (16 loads per lane, issued one tile ahead) with x_b (16 values per
+// lane, held in registers for the step). Operand and output layout: mma16.h.
+// NRT: right-hand sides of the inverse product (>= N).
 template <bool LOWER, int NRT, typename TF>
 __device__ __noinline__ void sweep(const Sys &s, double *Y_in, int64_t ldy, double *L0) {
+  typedef Mma16<TF> M;
+  typedef typename Lds<TF>::T lds_t;
   const TF RBT_AS_GLOBAL *F = (const TF RBT_AS_GLOBAL *)fmat<TF>(s);
   double RBT_AS_GLOBAL *Y = (double RBT_AS_GLOBAL *)Y_in;
   const int64_t n = s.n;
   const int N = int(s.nrhs);
   const int tid = threadIdx.x, i = tid & 63, sg = tid >> 6;
   const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, lk = lane >> 4;
-  ldouble *Ll = (ldouble *)L0;
-  double RBT_AS_LDS(*part)[BB][NRT] = reinterpret_cast<double RBT_AS_LDS(*)[BB][NRT]>(Ll);  // [4][64][NRT]
-  double RBT_AS_LDS(*xs)[NR] = reinterpret_cast<double RBT_AS_LDS(*)[NR]>(Ll + 4 * BB * NRT);  // [64][16]
+  lds_t *Ll = (lds_t *)L0;
+  TF RBT_AS_LDS(*part)[BB][NRT] = reinterpret_cast<TF RBT_AS_LDS(*)[BB][NRT]>(Ll);  // [4][64][NRT]
+  TF RBT_AS_LDS(*xs)[NR] = reinterpret_cast<TF RBT_AS_LDS(*)[NR]>(Ll + 4 * BB * NRT);  // [64][16]
   const int64_t nblk = (n + BB - 1) / BB;
   for (int64_t t = 0; t < nblk; ++t) {
     const int64_t b = LOWER ? t : nblk - 1 - t;
@@ -839,21 +859,21 @@ __device__ __noinline__ void sweep(const Sys &s, double *Y_in, int64_t ldy, doub
     if (sg == 0) {
 #pragma unroll
       for (int c = 0; c < NR; ++c)
-        xs[i][c] = (i < kb && c < N) ? Y[(r0 + i) + int64_t(c) * ldy] : 0.0;
+        xs[i][c] = (i < kb && c < N) ? TF(Y[(r0 + i) + int64_t(c) * ldy]) : TF(0);
     }
     __syncthreads();
     // x_b = Dinv y_b
-    const double RBT_AS_GLOBAL *Db = (const double RBT_AS_GLOBAL *)s.Inv + b * BB * BB;
-    double dv[16];
+    const TF RBT_AS_GLOBAL *Db = (const TF RBT_AS_GLOBAL *)s.Inv + b * BB * BB;
+    TF dv[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) dv[q] = Db[i + (sg * 16 + q) * BB];
-    double acc[NRT];
+    TF acc[NRT];
 #pragma unroll
-    for (int c = 0; c < NRT; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NRT; ++c) acc[c] = TF(0);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int kx = sg * 16 + q;
-      const double v = LOWER ? (i > kx ? dv[q] : (i == kx ? 1.0 : 0.0)) : (i <= kx ? dv[q] : 0.0);
+      const TF v = LOWER ? (i > kx ? dv[q] : (i == kx ? TF(1) : TF(0))) : (i <= kx ? dv[q] : TF(0));
 #pragma unroll
       for (int c = 0; c < NRT; ++c) acc[c] += v * xs[kx][c];
     }
@@ -863,18 +883,18 @@ __device__ __noinline__ void sweep(const Sys &s, double *Y_in, int64_t ldy, doub
     if (sg == 0) {
 #pragma unroll
       for (int c = 0; c < NR; ++c) {
-        double x = 0.0;
+        TF x = TF(0);
         if (c < NRT && i < kb && c < N)
           x = (part[0][i][c] + part[1][i][c]) + (part[2][i][c] + part[3][i][c]);
         xs[i][c] = x;
-        if (i < kb && c < N) Y[(r0 + i) + int64_t(c) * ldy] = x;
+        if (i < kb && c < N) Y[(r0 + i) + int64_t(c) * ldy] = double(x);
       }
     }
     __syncthreads();
     // rows still to be solved: after the block (L) or before it (U)
     const int64_t lo = LOWER ? r0 + kb : 0, hi = LOWER ? n : r0;
     if (hi > lo) {
-      double xb[16];
+      TF xb[16];
 #pragma unroll
       for (int kk = 0; kk < 16; ++kk) xb[kk] = xs[lk + 4 * kk][l16];
       const int64_t ntile = (hi - lo + 15) / 16;
@@ -892,18 +912,20 @@ __device__ __noinline__ void sweep(const Sys &s, double *Y_in, int64_t ldy, doub
       if (tt < ntile) load_tile(tt, av);
       for (; tt < ntile; tt += 4) {
         if (tt + 4 < ntile) load_tile(tt + 4, an);
-        typedef double d4v __attribute__((ext_vector_type(4)));
-        d4v o = {0.0, 0.0, 0.0, 0.0};
+        typename M::v4 o = {TF(0), TF(0), TF(0), TF(0)};
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
-          const double a = (lk + 4 * kk < kb && lo + 16 * tt + l16 < hi) ? double(av[kk]) : 0.0;
-          o = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb[kk], o, 0, 0, 0);
+          const TF a = (lk + 4 * kk < kb && lo + 16 * tt + l16 < hi) ? av[kk] : TF(0);
+          o = M::mma(a, xb[kk], o);
         }
         if (l16 < N) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int64_t m = lo + 16 * tt + lk + 4 * v;
-            if (m < hi) Y[m + int64_t(l16) * ldy] -= o[v];
+            const int64_t m = lo + 16 * tt + M::row(lk, v);
+            if (m < hi) {
+              double RBT_AS_GLOBAL *py = Y + m + int64_t(l16) * ldy;
+              *py = double(TF(*py) - o[v]);
+            }
           }
         }
 #pragma unroll
@@ -1019,7 +1041,7 @@ __device__ void refine_system(const Sys &s, int d, double tol, int max_iter, dou
   transform_vec_sys<RBT_OP_T>(s, d, s.Xm, s.ldx, s.U);
   sweep<true, NRT, TF>(s, s.Xm, s.ldx, L0);
   sweep<false, NRT, TF>(s, s.Xm, s.ldx, L0);
-  transform_vec_sys<RBT_OP_N>(s, d, s.Xm, s.ldx, s.V);
+  if (s.sides != 1) transform_vec_sys<RBT_OP_N>(s, d, s.Xm, s.ldx, s.V);  // x = V x~
   int it = 0, stalled = 0;
   double be = 0.0, best = INFINITY;
   for (;;) {
@@ -1033,7 +1055,7 @@ __device__ void refine_system(const Sys &s, int d, double tol, int max_iter, dou
     transform_vec_sys<RBT_OP_T>(s, d, s.R, n, s.U);
     sweep<true, NRT, TF>(s, s.R, n, L0);
     sweep<false, NRT, TF>(s, s.R, n, L0);
-    transform_vec_sys<RBT_OP_N>(s, d, s.R, n, s.V);
+    if (s.sides != 1) transform_vec_sys<RBT_OP_N>(s, d, s.R, n, s.V);
     for (int64_t e = threadIdx.x; e < n * s.nrhs; e += BT)
       Xg[(e % n) + (e / n) * s.ldx] += Rg[e];
     __syncthreads();
@@ -1043,36 +1065,45 @@ __device__ void refine_system(const Sys &s, int d, double tol, int max_iter, dou
   *be_out = be;
 }
 
-// A~ = U^T A V into the FP32 (lowp) or FP64 factor storage.
-__device__ __noinline__ void transform_into(const Sys &s, int d, bool lowp) {
+// A~ = U^T A V into the factor storage of type TF (FP32 for the
+// low-precision pass, FP64 for the fallback), in passes of at most three
+// layers from layer d down: the first reads A, the later ones the factor
+// storage in place (each block of a pass belongs to one thread).
+template <typename TF>
+__device__ __noinline__ void transform_into(const Sys &s, int d) {
   const double RBT_AS_GLOBAL *Ag = (const double RBT_AS_GLOBAL *)s.A;
   const double RBT_AS_GLOBAL *Ug = (const double RBT_AS_GLOBAL *)s.U;
   const double RBT_AS_GLOBAL *Vg = (const double RBT_AS_GLOBAL *)s.V;
+  TF RBT_AS_GLOBAL *Fg = (TF RBT_AS_GLOBAL *)fmat<TF>(s);
   const int64_t n = s.n;
-  const int64_t m = d > 0 ? ((((n - 1) >> d) + 1) << d) : n;
-  const int64_t q = m >> d;
-  const dev::Pass ps = d > 0 ? dev::make_pass(n, q, d, 1, d) : dev::identity_pass(n);
-  for (int64_t e = threadIdx.x; e < ps.ngroups * ps.ngroups; e += BT) {
-    const int64_t gr = e % ps.ngroups, gc = e / ps.ngroups;
-    const int64_t rb = dev::group_base(ps, gr), cb = dev::group_base(ps, gc);
-    if (rb >= n || cb >= n) continue;
-    if (lowp) {
-      switch (d) {
-        case 0: dev::transform2_block<0, float>(Ag, s.lda, (float RBT_AS_GLOBAL *)s.F, n, Ug, Vg, ps, rb, cb); break;
-        case 1: dev::transform2_block<1, float>(Ag, s.lda, (float RBT_AS_GLOBAL *)s.F, n, Ug, Vg, ps, rb, cb); break;
-        case 2: dev::transform2_block<2, float>(Ag, s.lda, (float RBT_AS_GLOBAL *)s.F, n, Ug, Vg, ps, rb, cb); break;
-        default: dev::transform2_block<3, float>(Ag, s.lda, (float RBT_AS_GLOBAL *)s.F, n, Ug, Vg, ps, rb, cb); break;
-      }
-    } else {
-      switch (d) {
-        case 0: dev::transform2_block<0, double>(Ag, s.lda, (double RBT_AS_GLOBAL *)s.F64, n, Ug, Vg, ps, rb, cb); break;
-        case 1: dev::transform2_block<1, double>(Ag, s.lda, (double RBT_AS_GLOBAL *)s.F64, n, Ug, Vg, ps, rb, cb); break;
-        case 2: dev::transform2_block<2, double>(Ag, s.lda, (double RBT_AS_GLOBAL *)s.F64, n, Ug, Vg, ps, rb, cb); break;
-        default: dev::transform2_block<3, double>(Ag, s.lda, (double RBT_AS_GLOBAL *)s.F64, n, Ug, Vg, ps, rb, cb); break;
+  for (int hi = d, first = 1; first || hi >= 1; first = 0) {
+    const int lo = d == 0 ? 1 : (hi - 2 > 1 ? hi - 2 : 1);
+    const dev::Pass ps =
+        d > 0 ? dev::make_pass(n, s.q, d, lo, hi, s.rot, s.sides) : dev::identity_pass(n);
+    const int P = d > 0 ? hi - lo + 1 : 0;
+    for (int64_t e = threadIdx.x; e < ps.ngroups * ps.ngroups; e += BT) {
+      const int64_t gr = e % ps.ngroups, gc = e / ps.ngroups;
+      const int64_t rb = dev::group_base(ps, gr), cb = dev::group_base(ps, gc);
+      if (rb >= n || cb >= n) continue;
+      if (first) {
+        switch (P) {
+          case 0: dev::transform2_block<0, TF>(Ag, s.lda, Fg, n, Ug, Vg, ps, rb, cb); break;
+          case 1: dev::transform2_block<1, TF>(Ag, s.lda, Fg, n, Ug, Vg, ps, rb, cb); break;
+          case 2: dev::transform2_block<2, TF>(Ag, s.lda, Fg, n, Ug, Vg, ps, rb, cb); break;
+          default: dev::transform2_block<3, TF>(Ag, s.lda, Fg, n, Ug, Vg, ps, rb, cb); break;
+        }
+      } else {
+        switch (P) {
+          case 1: dev::transform2_block<1, TF>(Fg, n, Fg, n, Ug, Vg, ps, rb, cb); break;
+          case 2: dev::transform2_block<2, TF>(Fg, n, Fg, n, Ug, Vg, ps, rb, cb); break;
+          default: dev::transform2_block<3, TF>(Fg, n, Fg, n, Ug, Vg, ps, rb, cb); break;
+        }
       }
     }
+    __syncthreads();
+    if (d == 0) break;
+    hi = lo - 1;
   }
-  __syncthreads();
 }
 
 template <bool BF16U, int CT>
@@ -1084,6 +1115,12 @@ __device__ void solve_system(const Args &a, const BatchDesc &D, float *fbase, do
   Sys s;
   s.n = D.n;
   s.nrhs = D.nrhs;
+  {  // m = 2^d g ceil(n / (2^d g)), q = m / 2^d
+    const int64_t g = (int64_t(1) << d) * a.granule;
+    s.q = d > 0 ? (((s.n + g - 1) / g) * g) >> d : s.n;
+  }
+  s.rot = a.kind == 1 ? 1 : 0;
+  s.sides = a.sides;
   s.F = fbase + D.f_off;
   s.F64 = f64base ? f64base + D.f64_off : nullptr;
   s.U = dbase + D.d_off;
@@ -1103,7 +1140,8 @@ __device__ void solve_system(const Args &a, const BatchDesc &D, float *fbase, do
   for (int64_t e = tid; e < 2 * n * d; e += BT) {
     const int side = e >= n * d ? 1 : 0;
     const int64_t rem = e - side * n * d;
-    s.U[e] = dev::coefficient(seed, rem % n, side, int(rem / n) + 1);
+    s.U[e] = s.rot ? dev::rotation_coefficient(seed, rem % n, side, int(rem / n) + 1, n, s.q, d)
+                   : dev::coefficient(seed, rem % n, side, int(rem / n) + 1);
   }
   __syncthreads();
   const double tol = a.tol < 0.0 ? -a.tol * double(n) * 0x1.0p-52 : a.tol;
@@ -1117,7 +1155,10 @@ __device__ void solve_system(const Args &a, const BatchDesc &D, float *fbase, do
       if (tid == 0) *info_sh = 0;
       __syncthreads();
     }
-    transform_into(s, d, pass == 0);
+    if (pass == 0)
+      transform_into<float>(s, d);
+    else
+      transform_into<double>(s, d);
     if (pass == 0)
       eliminate<float, BF16U, CT>(s, L0, L1, info_sh);
     else
@@ -1158,23 +1199,37 @@ __global__ void __launch_bounds__(BT, 2) k_batched(Args a) {
   __shared__ double anorm_sh;
   BatchHeader *hdr = reinterpret_cast<BatchHeader *>(a.work);
   // a plan for other sizes, depth or precision, or a workspace too small for
-  // it: do nothing
+  // it: no system is solved, and every system reports it (info -1, berr NaN,
+  // path -1), so no caller mistakes the untouched X for a solution
   if (hdr->batch != a.batch || hdr->depth != a.depth || hdr->prec != a.prec ||
-      hdr->total_bytes < 0 || size_t(hdr->total_bytes) > a.work_bytes)
+      hdr->total_bytes < 0 || size_t(hdr->total_bytes) > a.work_bytes) {
+    for (int64_t sys = int64_t(blockIdx.x) * BT + threadIdx.x; sys < a.batch;
+         sys += int64_t(gridDim.x) * BT) {
+      if (a.path) a.path[sys] = -1;
+      if (a.iters) a.iters[sys] = 0;
+      if (a.berr) a.berr[sys] = __builtin_nan("");
+      if (a.info) a.info[sys] = -1;
+    }
     return;
+  }
   const BatchDesc *desc = reinterpret_cast<const BatchDesc *>(a.work + kBatchTableOffset);
   float *fbase = reinterpret_cast<float *>(a.work + hdr->f_off_bytes);
   double *dbase = reinterpret_cast<double *>(a.work + hdr->d_off_bytes);
   double *f64base =
       hdr->f64_off_bytes > 0 ? reinterpret_cast<double *>(a.work + hdr->f64_off_bytes) : nullptr;
-  for (;;) {
+  // Each round takes one ticket; every ticket below `batch` is taken once
+  // over the grid, so no workgroup needs more than batch + 1 rounds. The
+  // bound makes the loop's end independent of the ticket word's value.
+  for (int64_t round = 0; round <= a.batch; ++round) {
     if (threadIdx.x == 0) tk_sh = atomicAdd(&hdr->ticket, 1);
     __syncthreads();
     const int64_t t = tk_sh;
     __syncthreads();
-    if (t >= a.batch) break;
+    if (t < 0 || t >= a.batch) break;
     const BatchDesc D = desc[t];
-    if (D.n > 0) {
+    // systems without work (n = 0, or no right-hand side) are not solved;
+    // the plan queues them last
+    if (D.n > 0 && D.nrhs > 0) {
       solve_system<BF16U, CT>(a, D, fbase, dbase, f64base, L0, L1, &info_sh, &anorm_sh);
     } else if (threadIdx.x == 0) {
       if (a.path) a.path[D.sys] = 0;
@@ -1217,6 +1272,9 @@ hipError_t launch_batched(int64_t batch, void *work, size_t work_bytes, const do
   a.depth = depth;
   a.prec = prec;
   a.max_iter = max_iter;
+  a.granule = butterfly_granule();
+  a.kind = butterfly_kind();
+  a.sides = butterfly_sides();
   hipLaunchKernelGGL(k_reset_ticket, dim3(1), dim3(64), 0, s, work);
   const dim3 g{unsigned(grid)}, b{unsigned(BT)};
   if (prec == RBT_BF16) {

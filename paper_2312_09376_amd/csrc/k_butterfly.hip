@@ -2,7 +2,8 @@
 // transform A~ = U^T A V (Eq. 1, Eq. 3) and the one-sided transforms
 // b~ = U^T b and x = V x~.
 //
-// Index algebra (Sec. 3, Alg. 1 with non-tiled m = 2^d ceil(n/2^d)): with
+// Index algebra (Sec. 3, Alg. 1 with m = 2^d g ceil(n/(2^d g)), g = 1 for the
+// non-tiled structure, the tile size or the Eq. 8 granule otherwise): with
 // q = m / 2^d write i = r + t q. Layer l has half-size h_l = 2^(d-l) q, so
 // its butterflies pair i with the index whose t differs in bit (d-l), when
 // that index is < n (else i is unpaired: Eq. 2 keeps it, factor 1). Layers
@@ -33,8 +34,8 @@ namespace {
 using dev::Pass;
 using dev::group_base;
 
-__global__ void __launch_bounds__(256) k_generate(int64_t n, int d, uint64_t seed,
-                                                  double *__restrict__ U,
+__global__ void __launch_bounds__(256) k_generate(int64_t n, int64_t q, int d, int kind,
+                                                  uint64_t seed, double *__restrict__ U,
                                                   double *__restrict__ V) {
   const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
   const int64_t total = 2 * n * d;
@@ -43,12 +44,15 @@ __global__ void __launch_bounds__(256) k_generate(int64_t n, int d, uint64_t see
   const int64_t rem = idx - side * n * d;
   const int layer = int(rem / n) + 1;
   const int64_t i = rem % n;
-  (side ? V : U)[rem] = dev::coefficient(seed, i, side, layer);
+  (side ? V : U)[rem] = kind == 1 ? dev::rotation_coefficient(seed, i, side, layer, n, q, d)
+                                  : dev::coefficient(seed, i, side, layer);
 }
 
 // Two-sided pass. Thread (gx, gy) owns row group gx and column group gy.
-template <int P, typename TO>
-__global__ void __launch_bounds__(256) k_transform2(const double *__restrict__ A, int64_t lda,
+// TI: element type of the input (FP64, or the FP32 output of an earlier
+// pass when the output is FP32), arithmetic in FP64.
+template <int P, typename TI, typename TO>
+__global__ void __launch_bounds__(256) k_transform2(const TI *__restrict__ A, int64_t lda,
                                                     TO *__restrict__ Out, int64_t ldo,
                                                     const double *__restrict__ U,
                                                     const double *__restrict__ V, Pass ps) {
@@ -76,19 +80,21 @@ __global__ void __launch_bounds__(256) k_transform_vec(double *__restrict__ B, i
     dev::transform_vec_block<P, OP>(B, ldb, j, C, ps, rb);
 }
 
-Pass make_pass(const Geometry &g, int lo, int hi) { return dev::make_pass(g.n, g.q, g.d, lo, hi); }
+Pass make_pass(const Geometry &g, int lo, int hi) {
+  return dev::make_pass(g.n, g.q, g.d, lo, hi, g.kind == 1 ? 1 : 0, g.sides);
+}
 
-template <typename TO>
-hipError_t launch_pass2(const Pass &ps, const double *A, int64_t lda, TO *out, int64_t ldo,
+template <typename TI, typename TO>
+hipError_t launch_pass2(const Pass &ps, const TI *A, int64_t lda, TO *out, int64_t ldo,
                         const double *U, const double *V, hipStream_t s) {
   const int P = ps.hi - ps.lo + 1;
   const int64_t gy = ps.ngroups < 65535 ? ps.ngroups : 65535;
   dim3 grid(unsigned((ps.ngroups + 255) / 256), unsigned(gy));
   switch (P) {
-    case 0: hipLaunchKernelGGL((k_transform2<0, TO>), grid, dim3(256), 0, s, A, lda, out, ldo, U, V, ps); break;
-    case 1: hipLaunchKernelGGL((k_transform2<1, TO>), grid, dim3(256), 0, s, A, lda, out, ldo, U, V, ps); break;
-    case 2: hipLaunchKernelGGL((k_transform2<2, TO>), grid, dim3(256), 0, s, A, lda, out, ldo, U, V, ps); break;
-    default: hipLaunchKernelGGL((k_transform2<3, TO>), grid, dim3(256), 0, s, A, lda, out, ldo, U, V, ps); break;
+    case 0: hipLaunchKernelGGL((k_transform2<0, TI, TO>), grid, dim3(256), 0, s, A, lda, out, ldo, U, V, ps); break;
+    case 1: hipLaunchKernelGGL((k_transform2<1, TI, TO>), grid, dim3(256), 0, s, A, lda, out, ldo, U, V, ps); break;
+    case 2: hipLaunchKernelGGL((k_transform2<2, TI, TO>), grid, dim3(256), 0, s, A, lda, out, ldo, U, V, ps); break;
+    default: hipLaunchKernelGGL((k_transform2<3, TI, TO>), grid, dim3(256), 0, s, A, lda, out, ldo, U, V, ps); break;
   }
   return hipGetLastError();
 }
@@ -108,17 +114,19 @@ hipError_t launch_pass_vec(const Pass &ps, double *B, int64_t ldb, int64_t nrhs,
 
 }  // namespace
 
-hipError_t launch_generate(int64_t n, int d, uint64_t seed, double *U, double *V, hipStream_t s) {
-  const int64_t total = 2 * n * d;
+hipError_t launch_generate(const Geometry &g, uint64_t seed, double *U, double *V, hipStream_t s) {
+  const int64_t total = 2 * g.n * g.d;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_generate, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, n, d, seed,
-                     U, V);
+  hipLaunchKernelGGL(k_generate, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, g.n, g.q,
+                     g.d, g.kind, seed, U, V);
   return hipGetLastError();
 }
 
 // Layers are processed in passes of at most three, from layer d down to 1
 // (the order of U^T A V); rows and columns of a pass commute. Depth 0 is the
-// identity (a copy or conversion when out of place).
+// identity (a copy or conversion when out of place). With an FP32 output and
+// depth > 3 every pass writes the FP32 output (the first reads A, the later
+// ones the output in place), so the values are rounded to FP32 once per pass.
 hipError_t launch_transform2(const Geometry &g, const double *A, int64_t lda, void *out,
                              int64_t ldo, int out_prec, const double *U, const double *V,
                              hipStream_t s) {
@@ -126,26 +134,29 @@ hipError_t launch_transform2(const Geometry &g, const double *A, int64_t lda, vo
   if (g.d == 0) {
     if (out_prec == RBT_FP64 && (const void *)A == out) return hipSuccess;
     const Pass ps = dev::identity_pass(g.n);
-    if (out_prec == RBT_FP32) return launch_pass2<float>(ps, A, lda, (float *)out, ldo, U, V, s);
-    return launch_pass2<double>(ps, A, lda, (double *)out, ldo, U, V, s);
+    if (out_prec == RBT_FP32)
+      return launch_pass2<double, float>(ps, A, lda, (float *)out, ldo, U, V, s);
+    return launch_pass2<double, double>(ps, A, lda, (double *)out, ldo, U, V, s);
   }
   const double *src = A;
   int64_t lds = lda;
+  bool first = true;
   int hi = g.d;
   while (hi >= 1) {
     const int lo = hi - 2 >= 1 ? hi - 2 : 1;
     const Pass ps = make_pass(g, lo, hi);
     hipError_t e;
-    if (lo == 1 && out_prec == RBT_FP32) {
-      e = launch_pass2<float>(ps, src, lds, (float *)out, ldo, U, V, s);
+    if (out_prec == RBT_FP32) {
+      e = first ? launch_pass2<double, float>(ps, src, lds, (float *)out, ldo, U, V, s)
+                : launch_pass2<float, float>(ps, (const float *)out, ldo, (float *)out, ldo, U,
+                                             V, s);
     } else {
-      // passes before the last run on the FP64 output (the API layer only
-      // allows depth > 3 with an FP64 output)
-      e = launch_pass2<double>(ps, src, lds, (double *)out, ldo, U, V, s);
+      e = launch_pass2<double, double>(ps, src, lds, (double *)out, ldo, U, V, s);
       src = (const double *)out;
       lds = ldo;
     }
     if (e != hipSuccess) return e;
+    first = false;
     hi = lo - 1;
   }
   return hipSuccess;

@@ -16,51 +16,31 @@
 //      one wavefront's LDS accesses overlap the other's products); each tile's
 //      accumulator starts from the LDS values and the L operand is negated.
 // Rows and columns beyond kb hold the identity, so they never disturb the
-// active part. The block may be stored in FP32 (mixed-precision elimination):
-// it is then widened on load, eliminated in FP64 and rounded once on store. A zero pivot is recorded in *info (first one, 1-based, offset
-// gofs) and the arithmetic continues with IEEE Inf/NaN.
+// active part. The arithmetic type C is FP64 for FP64 factors; for the FP32
+// factors of the mixed-precision elimination it is FP32 (LDS, broadcasts,
+// the FP32 matrix cores), or FP64 as an option, in which case the block is
+// widened on load and rounded once on store. A zero pivot is recorded in
+// *info (first one, 1-based, offset gofs) and the arithmetic continues with
+// IEEE Inf/NaN.
 #include "internal.h"
+#include "mma16.h"
 
 namespace rbt {
 
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int NB = kNB;  // 128
 constexpr int LD = NB + 1;
 constexpr int PW = 16;   // panel width
 constexpr int NT = 512;  // threads
 constexpr int NW = NT / 64;
 
-// Value of v in lane `src` (uniform) of the wavefront.
-__device__ __forceinline__ double wave_bcast(double v, int src) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-  return __hiloint2double(hi, lo);
-}
-
-// v of lane K of each quad, to all four lanes of the quad (DPP quad_perm)
-template <int K>
-__device__ __forceinline__ double quad_bcast_k(double v) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(u)), K * 0x55, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(u >> 32)), K * 0x55, 0xF, 0xF, false);
-  return __builtin_bit_cast(double,
-                            (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32));
-}
-__device__ __forceinline__ double quad_bcast(double v, int k) {  // k: compile-time after unrolling
-  switch (k) {
-    case 0: return quad_bcast_k<0>(v);
-    case 1: return quad_bcast_k<1>(v);
-    case 2: return quad_bcast_k<2>(v);
-    default: return quad_bcast_k<3>(v);
-  }
-}
-
-template <typename T>
+template <typename T, typename C>
 __global__ void __launch_bounds__(NT) k_diag_lu(int kb, T *__restrict__ A, int64_t lda,
                                                  int64_t gofs, int32_t *__restrict__ info) {
-  __shared__ double S[NB * LD];
+  typedef Mma16<C> M;
+  typedef typename M::v4 c4;
+  __shared__ C S[NB * LD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -82,7 +62,7 @@ __global__ void __launch_bounds__(NT) k_diag_lu(int kb, T *__restrict__ A, int64
 #pragma unroll
     for (int i = 0; i < NB * NB / NT; ++i) {
       const int c = c0 + (NT / NB) * i;
-      S[c * LD + r] = (r < kb && c < kb) ? double(v[i]) : ((r == c) ? 1.0 : 0.0);
+      S[c * LD + r] = (r < kb && c < kb) ? C(v[i]) : ((r == c) ? C(1) : C(0));
     }
   }
   __syncthreads();
@@ -100,7 +80,7 @@ __global__ void __launch_bounds__(NT) k_diag_lu(int kb, T *__restrict__ A, int64
       const int row = top ? c0 + lane : c0 + PW + wave * 48 + (lane - PW);
       const bool valid = row < NB;
       const int rr = valid ? row : NB - 1;
-      double x[PW];
+      C x[PW];
 #pragma unroll
       for (int j = 0; j < PW; ++j) x[j] = S[(c0 + j) * LD + rr];
       // The loop body is kept free of branches (a zero pivot is found after
@@ -109,25 +89,25 @@ __global__ void __launch_bounds__(NT) k_diag_lu(int kb, T *__restrict__ A, int64
       // the previous pivot's updates are still issuing.
 #pragma unroll
       for (int cc = 0; cc < PW; ++cc) {
-        double prow[PW];
+        C prow[PW];
 #pragma unroll
         for (int j = cc; j < PW; ++j) prow[j] = wave_bcast(x[j], cc);
-        const double p = prow[cc];
+        const C p = prow[cc];
         const bool act = top ? lane > cc : valid;
-        double rp = 1.0 / p;  // one division per pivot (scaling as in LAPACK's getf2)
+        C rp = C(1) / p;  // one division per pivot (scaling as in LAPACK's getf2)
         __asm__ volatile("" : "+v"(rp));
-        double lm = x[cc] * rp;
+        C lm = x[cc] * rp;
         __asm__ volatile("" : "+v"(lm));
-        const double l = act ? lm : 0.0;
+        const C l = act ? lm : C(0);
         x[cc] = act ? l : x[cc];
 #pragma unroll
         for (int j = cc + 1; j < PW; ++j) x[j] -= l * prow[j];
       }
       {  // first zero pivot of the panel: top lane j of wavefront 0 holds pivot j in x[j]
-        double d = x[0];
+        C d = x[0];
 #pragma unroll
         for (int j = 1; j < PW; ++j) d = lane == j ? x[j] : d;
-        const unsigned long long z = __ballot(top && c0 + lane < kb && d == 0.0);
+        const unsigned long long z = __ballot(top && c0 + lane < kb && d == C(0));
         if (wave == 0 && lane == 0 && z != 0 && info != nullptr)
           atomicCAS(info, 0, int32_t(gofs + c0 + __ffsll(z)));
       }
@@ -151,16 +131,16 @@ __global__ void __launch_bounds__(NT) k_diag_lu(int kb, T *__restrict__ A, int64
       const int colA = c1 + g;
       const bool hasA = colA < NB;
       const int ca = hasA ? colA : NB - 1;
-      double ya[4];
+      C ya[4];
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) ya[jj] = S[ca * LD + c0 + q + 4 * jj];
-      double tn[4];
+      C tn[4];
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) tn[jj] = S[c0 * LD + c0 + q + 4 * jj];
 #pragma unroll
       for (int j = 0; j < PW; ++j) {  // pivot j: entries i > j lose L(i, j) y_j
         const int jc = j >> 2, qc = j & 3;
-        double t[4];
+        C t[4];
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) t[jj] = tn[jj];
         if (j + 1 < PW) {
@@ -168,12 +148,12 @@ __global__ void __launch_bounds__(NT) k_diag_lu(int kb, T *__restrict__ A, int64
           for (int jj = 0; jj < 4; ++jj) tn[jj] = S[(c0 + j + 1) * LD + c0 + q + 4 * jj];
         }
         __builtin_amdgcn_sched_barrier(0);
-        const double ba = quad_bcast(ya[jc], qc);
+        const C ba = quad_bcast(ya[jc], qc);
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
           if (4 * jj + 3 <= j) continue;
           const bool upd = 4 * jj > j || q + 4 * jj > j;
-          const double na = __builtin_fma(-t[jj], ba, ya[jj]);
+          const C na = fma_c(-t[jj], ba, ya[jj]);
           ya[jj] = upd ? na : ya[jj];
         }
       }
@@ -192,12 +172,12 @@ __global__ void __launch_bounds__(NT) k_diag_lu(int kb, T *__restrict__ A, int64
       const int tb = two ? t + NW : t;
       const int i0 = c1 + PW * (t % nt), j0 = c1 + PW * (t / nt);
       const int i1 = c1 + PW * (tb % nt), j1 = c1 + PW * (tb / nt);
-      d4 acc0, acc1;
-      double a0[4], b0[4], a1[4], b1[4];
+      c4 acc0, acc1;
+      C a0[4], b0[4], a1[4], b1[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        acc0[v] = S[(j0 + l16) * LD + i0 + lk + 4 * v];
-        acc1[v] = S[(j1 + l16) * LD + i1 + lk + 4 * v];
+        acc0[v] = S[(j0 + l16) * LD + i0 + M::row(lk, v)];
+        acc1[v] = S[(j1 + l16) * LD + i1 + M::row(lk, v)];
       }
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
@@ -209,13 +189,13 @@ __global__ void __launch_bounds__(NT) k_diag_lu(int kb, T *__restrict__ A, int64
       }
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[kk], b0[kk], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[kk], b1[kk], acc1, 0, 0, 0);
+        acc0 = M::mma(a0[kk], b0[kk], acc0);
+        acc1 = M::mma(a1[kk], b1[kk], acc1);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        S[(j0 + l16) * LD + i0 + lk + 4 * v] = acc0[v];
-        if (two) S[(j1 + l16) * LD + i1 + lk + 4 * v] = acc1[v];
+        S[(j0 + l16) * LD + i0 + M::row(lk, v)] = acc0[v];
+        if (two) S[(j1 + l16) * LD + i1 + M::row(lk, v)] = acc1[v];
       }
     }
     __syncthreads();
@@ -233,21 +213,22 @@ __global__ void __launch_bounds__(NT) k_diag_lu(int kb, T *__restrict__ A, int64
 
 }  // namespace
 
-template <typename T>
+template <typename T, typename C>
 hipError_t diag_lu_t(int kb, T *A, int64_t lda, int64_t gofs, int32_t *info, hipStream_t s) {
   if (kb <= 0) return hipSuccess;
   if (kb > kNB) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_diag_lu<T>, dim3(1), dim3(NT), 0, s, kb, A, lda, gofs, info);
+  hipLaunchKernelGGL((k_diag_lu<T, C>), dim3(1), dim3(NT), 0, s, kb, A, lda, gofs, info);
   return hipGetLastError();
 }
 
 hipError_t launch_diag_lu(int kb, double *A, int64_t lda, int64_t gofs, int32_t *info,
                           hipStream_t s) {
-  return diag_lu_t(kb, A, lda, gofs, info, s);
+  return diag_lu_t<double, double>(kb, A, lda, gofs, info, s);
 }
 hipError_t launch_diag_lu(int kb, float *A, int64_t lda, int64_t gofs, int32_t *info,
-                          hipStream_t s) {
-  return diag_lu_t(kb, A, lda, gofs, info, s);
+                          bool fp64_arith, hipStream_t s) {
+  return fp64_arith ? diag_lu_t<float, double>(kb, A, lda, gofs, info, s)
+                    : diag_lu_t<float, float>(kb, A, lda, gofs, info, s);
 }
 
 }  // namespace rbt

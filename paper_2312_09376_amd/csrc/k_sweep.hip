@@ -15,8 +15,13 @@
 //
 // Progress: a workgroup only waits for blocks of smaller tickets, which were
 // taken by workgroups already running, so every wait ends. The spin is also
-// bounded (kSpinLimit sleeps); a workgroup that reaches the bound records it
-// in the error word and goes on, so the grid always drains.
+// bounded (spin_limit sleeps, the library's option; a negative limit expires
+// every wait at once, which tests use to reach this path): a workgroup whose
+// wait expires sets the sticky error word sync[3] (which no sweep launch
+// clears), stores NaN as its block's solution, so the result can never be a
+// silently wrong finite vector, and goes on, so the grid always drains. The
+// published-blocks counter only moves forward (atomic maximum), also when a
+// late workgroup publishes after one whose wait expired.
 //
 // Coherence across XCDs: x_b is stored with agent-scope atomic stores by
 // the threads that hold it, each of them takes a device fence, and after a
@@ -27,6 +32,13 @@
 //
 // Layout: 512 threads = 128 rows x 4 column segments of 32; products of a
 // 128 x 128 block with the x block are reduced over the segments in LDS.
+//
+// Arithmetic type C: FP64 for FP64 factors. For the FP32 factors of the
+// mixed-precision solve it is FP32: the right-hand side (FP64 storage, the
+// transformed residual) is rounded to FP32 when loaded, the products, the
+// diagonal-block inverses (FP32) and the reductions are FP32, and the FP32
+// result is stored back widened; FP64 arithmetic with FP64 inverses is kept
+// as an option.
 #include <type_traits>
 
 #include "internal.h"
@@ -38,7 +50,6 @@ namespace {
 constexpr int TPB = 512;
 constexpr int SEG = 4;
 constexpr int SEGW = kNB / SEG;  // 32 columns per segment
-constexpr uint32_t kSpinLimit = 1u << 20;
 
 template <TriMode MODE, typename TF>
 __device__ __forceinline__ TF op_e(const TF *A, int64_t ld, int64_t m, int64_t k) {
@@ -55,14 +66,15 @@ __device__ __forceinline__ void coherent_store(double *p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int NMAX, TriMode MODE, typename TF, bool REFINE>
+template <int NMAX, TriMode MODE, typename TF, bool REFINE, typename C>
 __global__ void __launch_bounds__(TPB)
     k_sweep(int64_t n, int N, const TF *__restrict__ A, int64_t ld,
-            const double *__restrict__ Winv, double *B, int64_t ldb, int32_t *sync, int64_t nb) {
+            const C *__restrict__ Winv, double *B, int64_t ldb, int32_t *sync, int64_t nb,
+            int64_t spin_limit) {
   constexpr bool FWD = (MODE == TriMode::LN || MODE == TriMode::UT);
   constexpr bool UNIT = (MODE == TriMode::LN || MODE == TriMode::LT);
-  __shared__ double xs[kNB][NMAX];
-  __shared__ double part[SEG][kNB][NMAX];
+  __shared__ C xs[kNB][NMAX];
+  __shared__ C part[SEG][kNB][NMAX];
   __shared__ int64_t tk;
 
   const int tid = threadIdx.x;
@@ -72,15 +84,17 @@ __global__ void __launch_bounds__(TPB)
   const int64_t t = tk;
   if (t >= nb) return;
   int32_t *done = sync + 1;
-  int32_t *err = sync + 2;
+  int32_t *err = sync + 3;  // sticky: cleared by the entry points, not per sweep
   __shared__ int64_t avail_sh;
+  __shared__ int expired_sh;
+  if (tid == 0) expired_sh = 0;
   const int64_t b = FWD ? t : nb - 1 - t;
   const int64_t r0 = b * kNB;
   const int kb = int(n - r0 < kNB ? n - r0 : kNB);
   const int ir = i < kb ? i : kb - 1;  // clamped row for loads
 
   // sum over segments of part -> out (threads of segment 0)
-  auto reduce = [&](const double (&a)[NMAX], double (&out)[NMAX]) {
+  auto reduce = [&](const C (&a)[NMAX], C (&out)[NMAX]) {
 #pragma unroll
     for (int c = 0; c < NMAX; ++c) part[sg][i][c] = a[c];
     __syncthreads();
@@ -98,16 +112,16 @@ __global__ void __launch_bounds__(TPB)
   // with 16 and FP32 factors the inverse is loaded right after the last
   // accumulation; with 16 and FP64 factors at each use.
   constexpr bool PRE = (NMAX <= 8);
-  const double *Di = Winv + b * 2 * kNB * kNB +
-                     ((MODE == TriMode::LN || MODE == TriMode::LT) ? 0 : kNB * kNB);
-  auto load_dinv = [&](double (&ev)[SEGW]) {
+  const C *Di = Winv + b * 2 * kNB * kNB +
+                ((MODE == TriMode::LN || MODE == TriMode::LT) ? 0 : kNB * kNB);
+  auto load_dinv = [&](C (&ev)[SEGW]) {
 #pragma unroll
     for (int q = 0; q < SEGW; ++q) {
       const int jj = sg * SEGW + q;
       // Di is a full kNB x kNB allocation; entries beyond kb are masked
-      const double v = (MODE == TriMode::LN || MODE == TriMode::UN) ? Di[i + jj * kNB]
-                                                                    : Di[jj + i * kNB];
-      ev[q] = (i < kb && jj < kb) ? v : 0.0;
+      const C v = (MODE == TriMode::LN || MODE == TriMode::UN) ? Di[i + jj * kNB]
+                                                               : Di[jj + i * kNB];
+      ev[q] = (i < kb && jj < kb) ? v : C(0);
     }
   };
   auto load_tdiag = [&](TF (&e)[SEGW]) {
@@ -117,13 +131,13 @@ __global__ void __launch_bounds__(TPB)
       e[q] = op_e<MODE>(A, ld, r0 + ir, r0 + (jj < kb ? jj : kb - 1));
     }
   };
-  double dpre[PRE ? SEGW : 1];
-  double bpre[PRE ? NMAX : 1];
+  C dpre[PRE ? SEGW : 1];
+  C bpre[PRE ? NMAX : 1];
   if constexpr (PRE) {
     load_dinv(dpre);
 #pragma unroll
     for (int c = 0; c < NMAX; ++c)
-      bpre[c] = (sg == 0 && i < kb && c < N) ? B[(r0 + i) + int64_t(c) * ldb] : 0.0;
+      bpre[c] = (sg == 0 && i < kb && c < N) ? C(B[(r0 + i) + int64_t(c) * ldb]) : C(0);
   }
 
   // One right-hand side with FP64 factors: the diagonal block of the
@@ -134,9 +148,9 @@ __global__ void __launch_bounds__(TPB)
   if constexpr (PRE_T) load_tdiag(etp);
 
   // ---- accumulate op(A)[b, j] x_j over the blocks solved before b ----
-  double acc[NMAX];
+  C acc[NMAX];
 #pragma unroll
-  for (int c = 0; c < NMAX; ++c) acc[c] = 0.0;
+  for (int c = 0; c < NMAX; ++c) acc[c] = C(0);
   int64_t avail = 0;  // blocks known to be published (uniform)
   for (int64_t s = 0; s < t; ++s) {
     const int64_t j = FWD ? s : nb - 1 - s;
@@ -150,15 +164,17 @@ __global__ void __launch_bounds__(TPB)
     }
     if (s >= avail) {
       if (tid == 0) {
-        uint32_t spins = 0;
+        int64_t spins = 0;
         int32_t d;
         while ((d = __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) <= s) {
-          __builtin_amdgcn_s_sleep(1);
-          if (++spins > kSpinLimit) {
-            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (spins >= spin_limit) {  // expired: flag it, poison this block, go on
+            __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            expired_sh = 1;
             d = int32_t(s + 1);
             break;
           }
+          __builtin_amdgcn_s_sleep(1);
+          ++spins;
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         avail_sh = d;
@@ -168,13 +184,13 @@ __global__ void __launch_bounds__(TPB)
     }
     for (int idx = tid; idx < kNB * NMAX; idx += TPB) {
       const int k = idx / NMAX, c = idx % NMAX;
-      xs[k][c] = (k < cb && c < N) ? coherent_load(&B[(c0 + k) + int64_t(c) * ldb]) : 0.0;
+      xs[k][c] = (k < cb && c < N) ? C(coherent_load(&B[(c0 + k) + int64_t(c) * ldb])) : C(0);
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < SEGW; ++q) {
       const int col = sg * SEGW + q;
-      const double a = col < cb ? double(e[q]) : 0.0;
+      const C a = col < cb ? C(e[q]) : C(0);
 #pragma unroll
       for (int c = 0; c < NMAX; ++c) acc[c] += a * xs[col][c];
     }
@@ -195,30 +211,30 @@ __global__ void __launch_bounds__(TPB)
   // 16 right-hand sides: FP32 factors take the inverse here; FP64 factors
   // (more registers live) load it at each use
   constexpr bool EARLY_D = !PRE && !REFINE;
-  double dlate[EARLY_D ? SEGW : 1];
+  C dlate[EARLY_D ? SEGW : 1];
   if constexpr (EARLY_D) load_dinv(dlate);
 
   // ---- r = b_b - acc ----
-  double r[NMAX];
+  C r[NMAX];
   reduce(acc, r);
   if (sg == 0) {
 #pragma unroll
     for (int c = 0; c < NMAX; ++c) {
       // rows beyond kb summed clamped loads: zero them
-      double bv;
+      C bv;
       if constexpr (PRE)
         bv = bpre[c];
       else
-        bv = (i < kb && c < N) ? B[(r0 + i) + int64_t(c) * ldb] : 0.0;
-      r[c] = (i < kb && c < N) ? bv - r[c] : 0.0;
+        bv = (i < kb && c < N) ? C(B[(r0 + i) + int64_t(c) * ldb]) : C(0);
+      r[c] = (i < kb && c < N) ? bv - r[c] : C(0);
       xs[i][c] = r[c];
     }
   }
   __syncthreads();
 
   // product of the diagonal block's inverse with xs
-  auto prod_dinv = [&](double (&out)[NMAX]) {
-    double ev[SEGW];
+  auto prod_dinv = [&](C (&out)[NMAX]) {
+    C ev[SEGW];
     if constexpr (PRE) {
 #pragma unroll
       for (int q = 0; q < SEGW; ++q) ev[q] = dpre[q];
@@ -228,9 +244,9 @@ __global__ void __launch_bounds__(TPB)
     } else {
       load_dinv(ev);
     }
-    double a[NMAX];
+    C a[NMAX];
 #pragma unroll
-    for (int c = 0; c < NMAX; ++c) a[c] = 0.0;
+    for (int c = 0; c < NMAX; ++c) a[c] = C(0);
 #pragma unroll
     for (int q = 0; q < SEGW; ++q)
 #pragma unroll
@@ -239,7 +255,7 @@ __global__ void __launch_bounds__(TPB)
   };
 
   // ---- x = Di r ----
-  double x[NMAX];
+  C x[NMAX];
   prod_dinv(x);
   if constexpr (REFINE) {
     // res = r - T x ; x += Di res
@@ -249,27 +265,27 @@ __global__ void __launch_bounds__(TPB)
     }
     __syncthreads();
     if constexpr (!EARLY_T) load_tdiag(et);
-    double a[NMAX];
+    C a[NMAX];
 #pragma unroll
-    for (int c = 0; c < NMAX; ++c) a[c] = 0.0;
+    for (int c = 0; c < NMAX; ++c) a[c] = C(0);
 #pragma unroll
     for (int q = 0; q < SEGW; ++q) {
       const int jj = sg * SEGW + q;
-      double v = double(et[q]);
-      if (jj >= kb || i >= kb) v = 0.0;
-      else if (jj == i) v = UNIT ? 1.0 : v;
-      else if (FWD ? (jj > i) : (jj < i)) v = 0.0;
+      C v = C(et[q]);
+      if (jj >= kb || i >= kb) v = C(0);
+      else if (jj == i) v = UNIT ? C(1) : v;
+      else if (FWD ? (jj > i) : (jj < i)) v = C(0);
 #pragma unroll
       for (int c = 0; c < NMAX; ++c) a[c] += v * xs[jj][c];
     }
-    double tx[NMAX];
+    C tx[NMAX];
     reduce(a, tx);
     if (sg == 0) {
 #pragma unroll
       for (int c = 0; c < NMAX; ++c) xs[i][c] = r[c] - tx[c];
     }
     __syncthreads();
-    double dx[NMAX];
+    C dx[NMAX];
     prod_dinv(dx);
     if (sg == 0) {
 #pragma unroll
@@ -277,20 +293,24 @@ __global__ void __launch_bounds__(TPB)
     }
   }
 
-  // ---- publish x_b ----
+  // ---- publish x_b (NaN if a wait of this block expired) ----
+  const bool poisoned = expired_sh != 0;
   if (sg == 0 && i < kb) {
 #pragma unroll
     for (int c = 0; c < NMAX; ++c)
-      if (c < N) coherent_store(&B[(r0 + i) + int64_t(c) * ldb], x[c]);
+      if (c < N)
+        coherent_store(&B[(r0 + i) + int64_t(c) * ldb],
+                       poisoned ? __builtin_nan("") : double(x[c]));
   }
   // only the threads that stored need the device-scope fence (one per
   // wavefront of them instead of all eight: each fence writes back the L2)
   if (sg == 0) __threadfence();
   __syncthreads();
   // every block of a smaller ticket is published (this one consumed them
-  // all) and none of a larger ticket is, so done == t here
+  // all, unless a wait expired) and none of a larger ticket is; the maximum
+  // keeps the counter monotone in the expired case as well
   if (tid == 0)
-    __hip_atomic_store(done, int32_t(t + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_max(done, int32_t(t + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void k_zero_i32(int32_t *p, int64_t count) {
@@ -299,20 +319,23 @@ __global__ void k_zero_i32(int32_t *p, int64_t count) {
     p[k] = 0;
 }
 
-template <int NMAX, TriMode MODE, typename TF>
-hipError_t sweep_t(int64_t n, int N, const TF *LU, int64_t ld, const double *Winv, double *B,
+template <int NMAX, TriMode MODE, typename TF, typename C>
+hipError_t sweep_t(int64_t n, int N, const TF *LU, int64_t ld, const C *Winv, double *B,
                    int64_t ldb, int32_t *sync, hipStream_t s) {
+  // FP64 factors take one refinement step per diagonal block
   constexpr bool REFINE = std::is_same<TF, double>::value;
   const int64_t nb = (n + kNB - 1) / kNB;
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, sync, sweep_sync_ints(n));
-  hipLaunchKernelGGL((k_sweep<NMAX, MODE, TF, REFINE>), dim3(unsigned(nb)), dim3(TPB), 0, s, n, N,
-                     LU, ld, Winv, B, ldb, sync, nb);
+  // ticket, published-blocks counter and the legacy per-launch word; the
+  // sticky error word sync[3] is left alone
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, sync, int64_t(3));
+  hipLaunchKernelGGL((k_sweep<NMAX, MODE, TF, REFINE, C>), dim3(unsigned(nb)), dim3(TPB), 0, s, n,
+                     N, LU, ld, Winv, B, ldb, sync, nb, sweep_spin_limit());
   return hipGetLastError();
 }
 
-template <int NMAX, typename TF>
-hipError_t sweep_n(TriMode mode, int64_t n, int N, const TF *LU, int64_t ld, const double *Winv,
+template <int NMAX, typename TF, typename C>
+hipError_t sweep_n(TriMode mode, int64_t n, int N, const TF *LU, int64_t ld, const C *Winv,
                    double *B, int64_t ldb, int32_t *sync, hipStream_t s) {
   switch (mode) {
     case TriMode::LN: return sweep_t<NMAX, TriMode::LN>(n, N, LU, ld, Winv, B, ldb, sync, s);
@@ -322,9 +345,9 @@ hipError_t sweep_n(TriMode mode, int64_t n, int N, const TF *LU, int64_t ld, con
   }
 }
 
-template <typename TF>
+template <typename TF, typename C>
 hipError_t sweep_any(TriMode mode, int64_t n, int64_t nrhs, const TF *LU, int64_t ld,
-                     const double *Winv, double *B, int64_t ldb, int32_t *sync, hipStream_t s) {
+                     const C *Winv, double *B, int64_t ldb, int32_t *sync, hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return hipSuccess;
   if (nrhs > kSkinnyMax || sync == nullptr) return hipErrorInvalidValue;
   const int N = int(nrhs);
@@ -343,6 +366,11 @@ hipError_t launch_sweep(TriMode mode, int64_t n, int64_t nrhs, const double *LU,
 }
 hipError_t launch_sweep(TriMode mode, int64_t n, int64_t nrhs, const float *LU, int64_t ld,
                         const double *Winv, double *B, int64_t ldb, int32_t *sync,
+                        hipStream_t s) {
+  return sweep_any(mode, n, nrhs, LU, ld, Winv, B, ldb, sync, s);
+}
+hipError_t launch_sweep(TriMode mode, int64_t n, int64_t nrhs, const float *LU, int64_t ld,
+                        const float *Winv, double *B, int64_t ldb, int32_t *sync,
                         hipStream_t s) {
   return sweep_any(mode, n, nrhs, LU, ld, Winv, B, ldb, sync, s);
 }

@@ -36,20 +36,20 @@
 //   X_J = (B_J - sum_{I<J} X_I U_IJ) / U_JJ
 // Each wavefront owns 16 rows of B.
 //
-// MFMA: v_mfma_f64_16x16x4_f64 with the standard operand order; its output
-// element (lane l, v) is row l/16 + 4v, column l % 16.
+// MFMA: 16 x 16 x 4 products in the arithmetic type C (mma16.h).
 //
 // The triangle (TT) and the right-hand sides (TB) may be stored in FP32
-// (mixed-precision elimination); values are widened on load and all
-// arithmetic is FP64, rounded once on store.
+// (mixed-precision elimination). The arithmetic type C is FP64 for FP64
+// factors; for FP32 factors it is FP32 (LDS, substitution and the FP32
+// matrix cores), or FP64 as an option, in which case values are widened on
+// load and rounded once on store.
 #include "internal.h"
+#include "mma16.h"
 
 namespace rbt {
 
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef double d2 __attribute__((ext_vector_type(2)));
 constexpr int NB = kNB;  // 128
 constexpr int IB = 16;
 constexpr int NBK = NB / IB;  // 8 diagonal blocks
@@ -90,32 +90,14 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// v of lane K of each quad, to all four lanes of the quad (DPP quad_perm)
-template <int K>
-__device__ __forceinline__ double quad_bcast_k(double v) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(u)), K * 0x55, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(u >> 32)), K * 0x55, 0xF, 0xF, false);
-  return __builtin_bit_cast(double,
-                            (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32));
-}
-__device__ __forceinline__ double quad_bcast(double v, int k) {  // k: compile-time after unrolling
-  switch (k) {
-    case 0: return quad_bcast_k<0>(v);
-    case 1: return quad_bcast_k<1>(v);
-    case 2: return quad_bcast_k<2>(v);
-    default: return quad_bcast_k<3>(v);
-  }
-}
-
 // In-place substitution with one 16 x 16 diagonal block, quad layout: the
 // calling lane holds x[jj] = entry q + 4 jj of its right-hand side; tq[j * 16
 // + jj] is the coefficient of pivot j for entry q + 4 jj (reciprocal for
 // j's own entry; zero where unused); pivots j >= bs are skipped. FWD: entries
 // after the pivot are updated, else entries before it.
-template <bool FWD, bool UNIT>
-__device__ __forceinline__ void quad_substitute(double (&x)[4], const double *tq, int q, int bs) {
-  double tn[4];
+template <bool FWD, bool UNIT, typename C>
+__device__ __forceinline__ void quad_substitute(C (&x)[4], const C *tq, int q, int bs) {
+  C tn[4];
   const int j0 = FWD ? 0 : IB - 1;
 #pragma unroll
   for (int jj = 0; jj < 4; ++jj) tn[jj] = tq[j0 * IB + jj];
@@ -123,7 +105,7 @@ __device__ __forceinline__ void quad_substitute(double (&x)[4], const double *tq
   for (int s = 0; s < IB; ++s) {
     const int j = FWD ? s : IB - 1 - s;
     const int jc = j >> 2, qc = j & 3;
-    double t[4];
+    C t[4];
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) t[jj] = tn[jj];
     if (s + 1 < IB) {  // next pivot's coefficients in flight during this one
@@ -134,14 +116,14 @@ __device__ __forceinline__ void quad_substitute(double (&x)[4], const double *tq
     __builtin_amdgcn_sched_barrier(0);
     if (j < bs) {
       if constexpr (!UNIT) {
-        const double xs = x[jc] * t[jc];
+        const C xs = x[jc] * t[jc];
         x[jc] = q == qc ? xs : x[jc];
       }
-      const double b = quad_bcast(x[jc], qc);
+      const C b = quad_bcast(x[jc], qc);
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
         if (FWD ? (4 * jj + 3 <= j) : (4 * jj >= j)) continue;  // no entry of jj on that side
-        const double nx = __builtin_fma(-t[jj], b, x[jj]);
+        const C nx = fma_c(-t[jj], b, x[jj]);
         const bool all = FWD ? (4 * jj > j) : (4 * jj + 3 < j);
         x[jj] = (all || (FWD ? q + 4 * jj > j : q + 4 * jj < j)) ? nx : x[jj];
       }
@@ -155,17 +137,21 @@ __device__ __forceinline__ void quad_substitute(double (&x)[4], const double *tq
 // inverses of the diagonal blocks once per factorization.
 // LDS of one workgroup of either solve: diagonal blocks, off-diagonal
 // blocks, four right-hand-side strips (136 KB).
+template <typename C>
 struct TrsmSmem {
-  __attribute__((aligned(16))) double dblk[NBK * BLK];
-  __attribute__((aligned(16))) double oblk[NOFF * BLK];
-  __attribute__((aligned(16))) double strip[4][NB * SLD];
+  __attribute__((aligned(16))) C dblk[NBK * BLK];
+  __attribute__((aligned(16))) C oblk[NOFF * BLK];
+  __attribute__((aligned(16))) C strip[4][NB * SLD];
 };
 
 // Left solve of the 64 columns [64 bx, 64 bx + 64) of B.
-template <TriMode MODE, bool BATCH, typename TT, typename TB>
+template <TriMode MODE, bool BATCH, typename TT, typename TB, typename C>
 __device__ __forceinline__ void trsm_left_body(int kb, int64_t N, const TT *T, int64_t ldt,
                                                TB *B, int64_t ldb, int64_t n, int64_t bstride,
-                                               int64_t bx, TrsmSmem &sm) {
+                                               int64_t bx, TrsmSmem<C> &sm) {
+  typedef Mma16<C> M;
+  typedef typename M::v4 c4;
+  typedef C c2 __attribute__((ext_vector_type(2)));
   if constexpr (BATCH) {
     const int64_t b = blockIdx.y;
     const int64_t r0 = b * NB;
@@ -178,13 +164,13 @@ __device__ __forceinline__ void trsm_left_body(int kb, int64_t N, const TT *T, i
   // (reciprocal on the diagonal of non-unit modes); ablk: off-diagonal block
   // (I, J), J before I, at p*256 + lane*4 + kk = op(T)(16I + l16, 16J + 4kk +
   // lk), p = I(I-1)/2 + J (forward) or J(J-1)/2 + I (backward)
-  double *dblk = sm.dblk;
-  double *ablk = sm.oblk;
+  C *dblk = sm.dblk;
+  C *ablk = sm.oblk;
   constexpr bool FWD = forward_order<MODE>();
   constexpr bool TRANS = MODE == TriMode::UT || MODE == TriMode::LT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
-  double *strip = sm.strip[wave];  // row-major 128 x 16
+  C *strip = sm.strip[wave];  // row-major 128 x 16
   const int64_t col0 = bx * 64 + wave * 16;
 
   {  // stage the diagonal blocks and the off-diagonal operands, coalesced:
@@ -198,8 +184,8 @@ __device__ __forceinline__ void trsm_left_body(int kb, int64_t N, const TT *T, i
 #pragma unroll
     for (int b = 0; b < NBK; ++b) {
       const int gi = IB * b + i, gj = IB * b + j;
-      double v = (gi < kb && gj < kb) ? double(raw[b]) : (i == j ? 1.0 : 0.0);
-      if (!unit_diag<MODE>() && i == j) v = 1.0 / v;
+      C v = (gi < kb && gj < kb) ? C(raw[b]) : (i == j ? C(1) : C(0));
+      if (!unit_diag<MODE>() && i == j) v = C(1) / v;
       dblk[b * BLK + j * IB + (i & 3) * 4 + (i >> 2)] = v;
     }
     TT oraw[NOFF];
@@ -218,7 +204,7 @@ __device__ __forceinline__ void trsm_left_body(int kb, int64_t N, const TT *T, i
       for (int J = 0; J < I; ++J, ++p) {
         const int bi = FWD ? I : J, bj = FWD ? J : I;
         const int gi = IB * bi + i, gj = IB * bj + j;
-        ablk[p * BLK + slot] = (gi < kb && gj < kb) ? double(oraw[p]) : 0.0;
+        ablk[p * BLK + slot] = (gi < kb && gj < kb) ? C(oraw[p]) : C(0);
       }
   }
 #pragma unroll
@@ -228,7 +214,7 @@ __device__ __forceinline__ void trsm_left_body(int kb, int64_t N, const TT *T, i
 #pragma unroll
       for (int c = 0; c < IB; ++c) {
         const int64_t col = col0 + c;
-        strip[row * SLD + c] = (row < kb && col < N && row == col) ? 1.0 : 0.0;
+        strip[row * SLD + c] = (row < kb && col < N && row == col) ? C(1) : C(0);
       }
     } else {
       TB raw[IB];
@@ -240,7 +226,7 @@ __device__ __forceinline__ void trsm_left_body(int kb, int64_t N, const TT *T, i
       }
 #pragma unroll
       for (int c = 0; c < IB; ++c)
-        strip[row * SLD + c] = (row < kb && col0 + c < N) ? double(raw[c]) : 0.0;
+        strip[row * SLD + c] = (row < kb && col0 + c < N) ? C(raw[c]) : C(0);
     }
   }
   __syncthreads();
@@ -249,33 +235,33 @@ __device__ __forceinline__ void trsm_left_body(int kb, int64_t N, const TT *T, i
   const int cc = lane >> 2, q = lane & 3;  // substitution: right-hand side cc, entries q + 4 jj
   for (int step = 0; step < nbk; ++step) {
     const int I = FWD ? step : nbk - 1 - step;
-    d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    c4 acc0 = {C(0), C(0), C(0), C(0)}, acc1 = {C(0), C(0), C(0), C(0)};
 #pragma unroll
     for (int s2 = 0; s2 < NBK - 1; ++s2) {
       if (s2 < step) {
         const int J = FWD ? s2 : nbk - 1 - s2;
         const int p = FWD ? I * (I - 1) / 2 + J : J * (J - 1) / 2 + I;
-        const d2 a01 = *reinterpret_cast<const d2 *>(ablk + p * BLK + lane * 4);
-        const d2 a23 = *reinterpret_cast<const d2 *>(ablk + p * BLK + lane * 4 + 2);
+        const c2 a01 = *reinterpret_cast<const c2 *>(ablk + p * BLK + lane * 4);
+        const c2 a23 = *reinterpret_cast<const c2 *>(ablk + p * BLK + lane * 4 + 2);
         const int k0 = IB * J + lk;
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a01[0], strip[(k0) * SLD + l16], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a01[1], strip[(k0 + 4) * SLD + l16], acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a23[0], strip[(k0 + 8) * SLD + l16], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a23[1], strip[(k0 + 12) * SLD + l16], acc1, 0, 0, 0);
+        acc0 = M::mma(a01[0], strip[(k0) * SLD + l16], acc0);
+        acc1 = M::mma(a01[1], strip[(k0 + 4) * SLD + l16], acc1);
+        acc0 = M::mma(a23[0], strip[(k0 + 8) * SLD + l16], acc0);
+        acc1 = M::mma(a23[1], strip[(k0 + 12) * SLD + l16], acc1);
       }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) strip[(IB * I + lk + 4 * v) * SLD + l16] -= acc0[v] + acc1[v];
+    for (int v = 0; v < 4; ++v) strip[(IB * I + M::row(lk, v)) * SLD + l16] -= acc0[v] + acc1[v];
     wave_sync();
     const int bs = kb - IB * I < IB ? kb - IB * I : IB;
     const int o = IB * I;
-    double x[4];
+    C x[4];
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) x[jj] = strip[(o + q + 4 * jj) * SLD + cc];
     quad_substitute<FWD, unit_diag<MODE>()>(x, dblk + I * BLK + q * 4, q, bs);
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj)
-      strip[(o + q + 4 * jj) * SLD + cc] = (q + 4 * jj < bs) ? x[jj] : 0.0;
+      strip[(o + q + 4 * jj) * SLD + cc] = (q + 4 * jj < bs) ? x[jj] : C(0);
     wave_sync();
   }
 
@@ -290,27 +276,31 @@ __device__ __forceinline__ void trsm_left_body(int kb, int64_t N, const TT *T, i
   }
 }
 
-template <TriMode MODE, bool BATCH, typename TT, typename TB>
+template <TriMode MODE, bool BATCH, typename TT, typename TB, typename C>
 __global__ void __launch_bounds__(256, 1) k_trsm_left(int kb, int64_t N, const TT *T,
                                                       int64_t ldt, TB *B, int64_t ldb,
                                                       int64_t n, int64_t bstride) {
-  __shared__ TrsmSmem sm;
-  trsm_left_body<MODE, BATCH>(kb, N, T, ldt, B, ldb, n, bstride, int64_t(blockIdx.x), sm);
+  __shared__ TrsmSmem<C> sm;
+  trsm_left_body<MODE, BATCH, TT, TB, C>(kb, N, T, ldt, B, ldb, n, bstride,
+                                         int64_t(blockIdx.x), sm);
 }
 
 // Right solve of the 64 rows [64 bx, 64 bx + 64) of B.
-template <typename TT>
+template <typename TT, typename C>
 __device__ __forceinline__ void trsm_right_upper_body(int kb, int64_t M, const TT *T, int64_t ldt,
                                                       TT *B, int64_t ldb, int64_t bx,
-                                                      TrsmSmem &sm) {
+                                                      TrsmSmem<C> &sm) {
+  typedef Mma16<C> Mm;
+  typedef typename Mm::v4 c4;
+  typedef C c2 __attribute__((ext_vector_type(2)));
   // dblk: U(r, c) of diagonal block b at b*256 + r*16 + (c%4)*4 + c/4
   // (reciprocal on the diagonal); ublk: block (I, J), I < J, at p*256 +
   // lane*4 + kk = U(16I + 4kk + lk, 16J + l16), p = J(J-1)/2 + I
-  double *dblk = sm.dblk;
-  double *ublk = sm.oblk;
+  C *dblk = sm.dblk;
+  C *ublk = sm.oblk;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
-  double *strip = sm.strip[wave];  // column-major 16 x 128
+  C *strip = sm.strip[wave];  // column-major 16 x 128
   const int64_t row0 = bx * 64 + wave * 16;
 
   {  // stage the triangle, consecutive threads on consecutive rows of U
@@ -322,8 +312,8 @@ __device__ __forceinline__ void trsm_right_upper_body(int kb, int64_t M, const T
 #pragma unroll
     for (int b = 0; b < NBK; ++b) {
       const int gi = IB * b + r, gj = IB * b + c;
-      double v = (gi < kb && gj < kb) ? double(raw[b]) : (r == c ? 1.0 : 0.0);
-      if (r == c) v = 1.0 / v;
+      C v = (gi < kb && gj < kb) ? C(raw[b]) : (r == c ? C(1) : C(0));
+      if (r == c) v = C(1) / v;
       dblk[b * BLK + r * IB + (c & 3) * 4 + (c >> 2)] = v;
     }
     TT uraw[NOFF];
@@ -338,7 +328,7 @@ __device__ __forceinline__ void trsm_right_upper_body(int kb, int64_t M, const T
 #pragma unroll
       for (int I = 0; I < J; ++I, ++p) {
         const int gi = IB * I + r, gj = IB * J + c;
-        ublk[p * BLK + slot] = (gi < kb && gj < kb) ? double(uraw[p]) : 0.0;
+        ublk[p * BLK + slot] = (gi < kb && gj < kb) ? C(uraw[p]) : C(0);
       }
   }
   {
@@ -355,7 +345,7 @@ __device__ __forceinline__ void trsm_right_upper_body(int kb, int64_t M, const T
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int c = cg + 4 * (16 * h + u);
-        strip[c * SLD + r] = (row < M && c < kb) ? double(raw[u]) : 0.0;
+        strip[c * SLD + r] = (row < M && c < kb) ? C(raw[u]) : C(0);
       }
     }
   }
@@ -364,32 +354,32 @@ __device__ __forceinline__ void trsm_right_upper_body(int kb, int64_t M, const T
   const int nbk = (kb + IB - 1) / IB;
   const int rq = lane >> 2, q = lane & 3;  // substitution: row rq, entries q + 4 jj
   for (int J = 0; J < nbk; ++J) {
-    d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    c4 acc0 = {C(0), C(0), C(0), C(0)}, acc1 = {C(0), C(0), C(0), C(0)};
 #pragma unroll
     for (int I = 0; I < NBK - 1; ++I) {
       if (I < J) {
         const int p = J * (J - 1) / 2 + I;
-        const d2 b01 = *reinterpret_cast<const d2 *>(ublk + p * BLK + lane * 4);
-        const d2 b23 = *reinterpret_cast<const d2 *>(ublk + p * BLK + lane * 4 + 2);
+        const c2 b01 = *reinterpret_cast<const c2 *>(ublk + p * BLK + lane * 4);
+        const c2 b23 = *reinterpret_cast<const c2 *>(ublk + p * BLK + lane * 4 + 2);
         const int k0 = IB * I + lk;
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0) * SLD + l16], b01[0], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 4) * SLD + l16], b01[1], acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 8) * SLD + l16], b23[0], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(strip[(k0 + 12) * SLD + l16], b23[1], acc1, 0, 0, 0);
+        acc0 = Mm::mma(strip[(k0) * SLD + l16], b01[0], acc0);
+        acc1 = Mm::mma(strip[(k0 + 4) * SLD + l16], b01[1], acc1);
+        acc0 = Mm::mma(strip[(k0 + 8) * SLD + l16], b23[0], acc0);
+        acc1 = Mm::mma(strip[(k0 + 12) * SLD + l16], b23[1], acc1);
       }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) strip[(IB * J + l16) * SLD + lk + 4 * v] -= acc0[v] + acc1[v];
+    for (int v = 0; v < 4; ++v) strip[(IB * J + l16) * SLD + Mm::row(lk, v)] -= acc0[v] + acc1[v];
     wave_sync();
     const int bs = kb - IB * J < IB ? kb - IB * J : IB;
     const int o = IB * J;
-    double x[4];
+    C x[4];
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) x[jj] = strip[(o + q + 4 * jj) * SLD + rq];
     quad_substitute<true, false>(x, dblk + J * BLK + q * 4, q, bs);
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj)
-      strip[(o + q + 4 * jj) * SLD + rq] = (q + 4 * jj < bs) ? x[jj] : 0.0;
+      strip[(o + q + 4 * jj) * SLD + rq] = (q + 4 * jj < bs) ? x[jj] : C(0);
     wave_sync();
   }
 
@@ -404,11 +394,11 @@ __device__ __forceinline__ void trsm_right_upper_body(int kb, int64_t M, const T
   }
 }
 
-template <typename TT>
+template <typename TT, typename C>
 __global__ void __launch_bounds__(256, 1) k_trsm_right_upper(int kb, int64_t M, const TT *T,
                                                              int64_t ldt, TT *B, int64_t ldb) {
-  __shared__ TrsmSmem sm;
-  trsm_right_upper_body(kb, M, T, ldt, B, ldb, int64_t(blockIdx.x), sm);
+  __shared__ TrsmSmem<C> sm;
+  trsm_right_upper_body<TT, C>(kb, M, T, ldt, B, ldb, int64_t(blockIdx.x), sm);
 }
 
 // Both solves of a panel step with one factored diagonal block, which are
@@ -416,20 +406,20 @@ __global__ void __launch_bounds__(256, 1) k_trsm_right_upper(int kb, int64_t M, 
 // U12 = L11^-1 A12 for the panel's columns to the right (the rest, 64
 // columns each). One launch instead of two, and the short left solve runs
 // beside the right one.
-template <typename TT>
+template <typename TT, typename C>
 __global__ void __launch_bounds__(256, 1) k_panel_trsm(int kb, int64_t M, int64_t N, const TT *T,
                                                        int64_t ldt, TT *Br, TT *Bl, int64_t ldb,
                                                        int64_t gr) {
-  __shared__ TrsmSmem sm;
+  __shared__ TrsmSmem<C> sm;
   const int64_t bx = blockIdx.x;
   if (bx < gr)
-    trsm_right_upper_body(kb, M, T, ldt, Br, ldb, bx, sm);
+    trsm_right_upper_body<TT, C>(kb, M, T, ldt, Br, ldb, bx, sm);
   else
-    trsm_left_body<TriMode::LN, false>(kb, N, T, ldt, Bl, ldb, int64_t(0), int64_t(0), bx - gr,
-                                       sm);
+    trsm_left_body<TriMode::LN, false, TT, TT, C>(kb, N, T, ldt, Bl, ldb, int64_t(0),
+                                                  int64_t(0), bx - gr, sm);
 }
 
-template <typename TT, typename TB>
+template <typename TT, typename TB, typename C>
 hipError_t trsm_left_t(TriMode mode, int kb, int64_t N, const TT *T, int64_t ldt, TB *B,
                        int64_t ldb, hipStream_t s) {
   if (kb <= 0 || N <= 0) return hipSuccess;
@@ -437,47 +427,48 @@ hipError_t trsm_left_t(TriMode mode, int kb, int64_t N, const TT *T, int64_t ldt
   const dim3 grid(unsigned((N + 63) / 64));
   const int64_t z = 0;
   switch (mode) {
-    case TriMode::LN: hipLaunchKernelGGL((k_trsm_left<TriMode::LN, false, TT, TB>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, z, z); break;
-    case TriMode::UN: hipLaunchKernelGGL((k_trsm_left<TriMode::UN, false, TT, TB>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, z, z); break;
-    case TriMode::UT: hipLaunchKernelGGL((k_trsm_left<TriMode::UT, false, TT, TB>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, z, z); break;
-    case TriMode::LT: hipLaunchKernelGGL((k_trsm_left<TriMode::LT, false, TT, TB>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, z, z); break;
+    case TriMode::LN: hipLaunchKernelGGL((k_trsm_left<TriMode::LN, false, TT, TB, C>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, z, z); break;
+    case TriMode::UN: hipLaunchKernelGGL((k_trsm_left<TriMode::UN, false, TT, TB, C>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, z, z); break;
+    case TriMode::UT: hipLaunchKernelGGL((k_trsm_left<TriMode::UT, false, TT, TB, C>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, z, z); break;
+    case TriMode::LT: hipLaunchKernelGGL((k_trsm_left<TriMode::LT, false, TT, TB, C>), grid, dim3(256), 0, s, kb, N, T, ldt, B, ldb, z, z); break;
   }
   return hipGetLastError();
 }
 
-template <typename TT>
-hipError_t diag_inverses_t(int64_t n, const TT *LU, int64_t ld, double *W, hipStream_t s) {
+// Inverses of the diagonal blocks, in the arithmetic and storage type C of W.
+template <typename TT, typename C>
+hipError_t diag_inverses_t(int64_t n, const TT *LU, int64_t ld, C *W, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t nb = (n + NB - 1) / NB;
   if (nb > 65535) return hipErrorInvalidValue;
   const dim3 grid(2, unsigned(nb));  // 2 x 64 columns of each 128 x 128 block
   // L^-1 at W + b * 2 kNB^2, U^-1 at W + b * 2 kNB^2 + kNB^2, each ld kNB
-  hipLaunchKernelGGL((k_trsm_left<TriMode::LN, true, TT, double>), grid, dim3(256), 0, s, NB,
+  hipLaunchKernelGGL((k_trsm_left<TriMode::LN, true, TT, C, C>), grid, dim3(256), 0, s, NB,
                      int64_t(NB), LU, ld, W, int64_t(NB), n, int64_t(2 * NB * NB));
-  hipLaunchKernelGGL((k_trsm_left<TriMode::UN, true, TT, double>), grid, dim3(256), 0, s, NB,
+  hipLaunchKernelGGL((k_trsm_left<TriMode::UN, true, TT, C, C>), grid, dim3(256), 0, s, NB,
                      int64_t(NB), LU, ld, W + NB * NB, int64_t(NB), n, int64_t(2 * NB * NB));
   return hipGetLastError();
 }
 
-template <typename TT>
+template <typename TT, typename C>
 hipError_t panel_trsm_t(int kb, int64_t M, int64_t N, const TT *T, int64_t ldt, TT *Br, TT *Bl,
                         int64_t ldb, hipStream_t s) {
   if (kb <= 0 || (M <= 0 && N <= 0)) return hipSuccess;
   if (kb > kNB) return hipErrorInvalidValue;
   const int64_t gr = M > 0 ? (M + 63) / 64 : 0, gl = N > 0 ? (N + 63) / 64 : 0;
   if (gr + gl > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_panel_trsm<TT>, dim3(unsigned(gr + gl)), dim3(256), 0, s, kb, M, N, T, ldt,
-                     Br, Bl, ldb, gr);
+  hipLaunchKernelGGL((k_panel_trsm<TT, C>), dim3(unsigned(gr + gl)), dim3(256), 0, s, kb, M, N, T,
+                     ldt, Br, Bl, ldb, gr);
   return hipGetLastError();
 }
 
-template <typename TT>
+template <typename TT, typename C>
 hipError_t trsm_right_upper_t(int kb, int64_t M, const TT *T, int64_t ldt, TT *B, int64_t ldb,
                               hipStream_t s) {
   if (kb <= 0 || M <= 0) return hipSuccess;
   if (kb > kNB) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_trsm_right_upper<TT>, dim3(unsigned((M + 63) / 64)), dim3(256), 0, s, kb,
-                     M, T, ldt, B, ldb);
+  hipLaunchKernelGGL((k_trsm_right_upper<TT, C>), dim3(unsigned((M + 63) / 64)), dim3(256), 0, s,
+                     kb, M, T, ldt, B, ldb);
   return hipGetLastError();
 }
 
@@ -485,11 +476,12 @@ hipError_t trsm_right_upper_t(int kb, int64_t M, const TT *T, int64_t ldt, TT *B
 
 hipError_t launch_trsm_left(TriMode mode, int kb, int64_t N, const double *T, int64_t ldt,
                             double *B, int64_t ldb, hipStream_t s) {
-  return trsm_left_t(mode, kb, N, T, ldt, B, ldb, s);
+  return trsm_left_t<double, double, double>(mode, kb, N, T, ldt, B, ldb, s);
 }
 hipError_t launch_trsm_left(TriMode mode, int kb, int64_t N, const float *T, int64_t ldt, float *B,
-                            int64_t ldb, hipStream_t s) {
-  return trsm_left_t(mode, kb, N, T, ldt, B, ldb, s);
+                            int64_t ldb, bool fp64_arith, hipStream_t s) {
+  return fp64_arith ? trsm_left_t<float, float, double>(mode, kb, N, T, ldt, B, ldb, s)
+                    : trsm_left_t<float, float, float>(mode, kb, N, T, ldt, B, ldb, s);
 }
 hipError_t launch_diag_inverses(int64_t n, const double *LU, int64_t ld, double *W,
                                 hipStream_t s) {
@@ -498,21 +490,26 @@ hipError_t launch_diag_inverses(int64_t n, const double *LU, int64_t ld, double 
 hipError_t launch_diag_inverses(int64_t n, const float *LU, int64_t ld, double *W, hipStream_t s) {
   return diag_inverses_t(n, LU, ld, W, s);
 }
+hipError_t launch_diag_inverses(int64_t n, const float *LU, int64_t ld, float *W, hipStream_t s) {
+  return diag_inverses_t(n, LU, ld, W, s);
+}
 hipError_t launch_trsm_right_upper(int kb, int64_t M, const double *T, int64_t ldt, double *B,
                                    int64_t ldb, hipStream_t s) {
-  return trsm_right_upper_t(kb, M, T, ldt, B, ldb, s);
+  return trsm_right_upper_t<double, double>(kb, M, T, ldt, B, ldb, s);
 }
 hipError_t launch_trsm_right_upper(int kb, int64_t M, const float *T, int64_t ldt, float *B,
-                                   int64_t ldb, hipStream_t s) {
-  return trsm_right_upper_t(kb, M, T, ldt, B, ldb, s);
+                                   int64_t ldb, bool fp64_arith, hipStream_t s) {
+  return fp64_arith ? trsm_right_upper_t<float, double>(kb, M, T, ldt, B, ldb, s)
+                    : trsm_right_upper_t<float, float>(kb, M, T, ldt, B, ldb, s);
 }
 hipError_t launch_panel_trsm(int kb, int64_t M, int64_t N, const double *T, int64_t ldt,
                              double *Br, double *Bl, int64_t ldb, hipStream_t s) {
-  return panel_trsm_t(kb, M, N, T, ldt, Br, Bl, ldb, s);
+  return panel_trsm_t<double, double>(kb, M, N, T, ldt, Br, Bl, ldb, s);
 }
 hipError_t launch_panel_trsm(int kb, int64_t M, int64_t N, const float *T, int64_t ldt, float *Br,
-                             float *Bl, int64_t ldb, hipStream_t s) {
-  return panel_trsm_t(kb, M, N, T, ldt, Br, Bl, ldb, s);
+                             float *Bl, int64_t ldb, bool fp64_arith, hipStream_t s) {
+  return fp64_arith ? panel_trsm_t<float, double>(kb, M, N, T, ldt, Br, Bl, ldb, s)
+                    : panel_trsm_t<float, float>(kb, M, N, T, ldt, Br, Bl, ldb, s);
 }
 
 }  // namespace rbt

@@ -214,7 +214,8 @@ def solve_mixed_guarded(A, B, depth=2, seed=2023, prec=RBT_FP32, solver=RBT_IR_G
     """solve_mixed with a fallback to FP64 factors when the low-precision
     refinement cannot reach tol. Returns (X, LU, LU64, iters[2], berr,
     info[2], path, work); path 1 means the FP64 fallback ran (LU64 then holds
-    the FP64 factors of A~)."""
+    the FP64 factors of A~), path 2 the pivoted re-solve (LU64 holds its
+    factors)."""
     A = colmajor(A)
     B = colmajor(B)
     _dev_f64(A, "A")
@@ -242,6 +243,61 @@ def solve_mixed_guarded(A, B, depth=2, seed=2023, prec=RBT_FP32, solver=RBT_IR_G
                                         _p(iters), _p(berr), _p(info), _p(path), _p(work),
                                         work.numel(), _stream(dev)), "rbt_solve_mixed_guarded")
     return X, LU, LU64, iters, berr, info, path, work
+
+
+def gepp(A, work=None):
+    """Partial-pivoting elimination in place (a copy of A is factored when A
+    must be kept: pass A.clone()). Returns (LU, ipiv (1-based), info)."""
+    A = colmajor(A)
+    _dev_f64(A, "A")
+    n = A.shape[0]
+    dev = A.device
+    work = work if work is not None else _workspace(n, 0, 0, dev)
+    ipiv = torch.zeros(max(1, n), dtype=torch.int64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    check(lib().rbt_gepp(n, _p(A), _ld(A), _p(ipiv), _p(info), _p(work), work.numel(),
+                         _stream(dev)), "rbt_gepp")
+    return A, ipiv[:n], info
+
+
+def gepp_solve(LU, ipiv, B, work=None):
+    """B <- A^-1 B in place with the factors of gepp."""
+    B = colmajor(B)
+    _dev_f64(LU, "LU")
+    _dev_f64(B, "B")
+    n, k = LU.shape[0], B.shape[1]
+    work = work if work is not None else _workspace(n, k, 0, LU.device)
+    check(lib().rbt_gepp_solve(n, k, _p(LU), _ld(LU), _p(ipiv), _p(B), _ld(B), _p(work),
+                               work.numel(), _stream(LU.device)), "rbt_gepp_solve")
+    return B
+
+
+def solve_guarded(A, B, depth=2, seed=2023, tol=None, max_iter=10, LU=None, X=None, work=None):
+    """FP64 RBT solve with refinement and the Sec. 5 fallback to partial
+    pivoting. Returns (X, LU, iters[2], berr, info[2], path, work); path 2
+    means the pivoted re-solve ran (LU then holds its factors)."""
+    A = colmajor(A)
+    B = colmajor(B)
+    _dev_f64(A, "A")
+    _dev_f64(B, "B")
+    n, k = A.shape[0], B.shape[1]
+    if tol is None:
+        tol = 10.0 * n * 2.0 ** -52
+    dev = A.device
+    LU = LU if LU is not None else torch.empty_strided((n, n), (1, max(1, n)), dtype=torch.float64,
+                                                       device=dev)
+    X = X if X is not None else torch.empty_strided((n, k), (1, max(1, n)), dtype=torch.float64,
+                                                    device=dev)
+    work = work if work is not None else _workspace(n, k, depth, dev)
+    iters = torch.zeros(2, dtype=torch.int32, device=dev)
+    berr = torch.zeros(1, dtype=torch.float64, device=dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    path = torch.zeros(1, dtype=torch.int32, device=dev)
+    check(lib().rbt_solve_guarded(n, k, _p(A), _ld(A), _p(LU), _ld(LU), _p(B), _ld(B), _p(X),
+                                  _ld(X), depth, seed, float(tol), int(max_iter), _p(iters),
+                                  _p(berr), _p(info), _p(path), _p(work), work.numel(),
+                                  _stream(dev)), "rbt_solve_guarded")
+    return X, LU, iters, berr, info, path, work
 
 
 class BatchPlan:

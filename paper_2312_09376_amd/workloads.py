@@ -12,7 +12,10 @@ Matrix families (all square, FP64, column-major when handed to the device):
   orthog     A_ij = sqrt(2/(n+1)) sin(i j pi/(n+1)), symmetric orthogonal
              (Sec. 6.3 failure study), so A^-1 = A
   logcond    Q1 diag(sigma) Q2^T with sigma log-spaced over [1/cond, 1] and
-             random orthogonal Q1, Q2 (products of Householder reflectors)
+             Haar-distributed orthogonal Q1, Q2: Q of the QR factorization
+             of an N(0,1) matrix with the signs of diag(R) made positive
+             (Mezzadri, "How to generate random matrices from the classical
+             compact groups", 2007)
 Host draws use NumPy's PCG64 with the given seed; device draws (large n) use
 torch's seeded generator on the GPU.
 """
@@ -61,21 +64,20 @@ def orthog(n):
     return np.asfortranarray(math.sqrt(2.0 / (n + 1)) * np.sin(np.outer(i, i) * math.pi / (n + 1)))
 
 
-def householder_orthogonal(n, seed, reflectors=8):
-    """Dense orthogonal matrix: product of `reflectors` random Householder
-    reflectors I - 2 v v^T / (v^T v)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    Q = np.eye(n)
-    for _ in range(reflectors):
-        v = rng.standard_normal(n)
-        Q -= np.outer(2.0 * v / (v @ v), v @ Q)
-    return Q
+def haar_orthogonal(n, seed):
+    """Haar-distributed n x n orthogonal matrix: Q R = N(0,1) matrix, then
+    each column of Q multiplied by sign(R_jj)."""
+    Z = randn_matrix(n, seed)
+    Q, R = np.linalg.qr(Z)
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    return Q * d
 
 
 def logcond(n, seed=MATRIX_SEED, cond=1e6):
     sigma = np.logspace(0.0, -math.log10(cond), n) if n > 1 else np.ones(1)
-    Q1 = householder_orthogonal(n, seed)
-    Q2 = householder_orthogonal(n, seed + 1)
+    Q1 = haar_orthogonal(n, seed)
+    Q2 = haar_orthogonal(n, seed + 1)
     return np.asfortranarray((Q1 * sigma) @ Q2.T)
 
 
@@ -105,24 +107,31 @@ def device_hostile(n, seed=MATRIX_SEED, block=8, scale=1e-12, device="cuda"):
     return A
 
 
-def device_logcond(n, seed=MATRIX_SEED, cond=1e6, reflectors=8, device="cuda"):
+def device_haar_orthogonal(n, seed, device="cuda"):
+    """As haar_orthogonal, with the N(0,1) matrix drawn and factored on the
+    device (QR by the vendor library; input generation only)."""
+    import torch
+    Z = device_randn(n, n, seed, device)
+    Q, R = torch.linalg.qr(Z)
+    d = torch.sign(torch.diagonal(R))
+    d[d == 0] = 1.0
+    Q *= d
+    del Z, R
+    return Q
+
+
+def device_logcond(n, seed=MATRIX_SEED, cond=1e6, device="cuda"):
     """Column-major Q1 diag(sigma) Q2^T on the device, sigma log-spaced from 1
-    to 1/cond, Q1, Q2 products of random Householder reflectors (as
-    `logcond`, with reflector vectors drawn on the device)."""
+    to 1/cond, Q1 and Q2 Haar-distributed (device_haar_orthogonal with seeds
+    seed and seed + 1)."""
     import torch
     sigma = torch.logspace(0.0, -math.log10(cond), n, dtype=torch.float64, device=device)
-    A = torch.diag(sigma).t()          # column-major n x n
-    g = torch.Generator(device=device)
-    g.manual_seed(seed)
-    for side in range(2):
-        for _ in range(reflectors):
-            v = torch.randn(n, generator=g, device=device, dtype=torch.float64)
-            w = (2.0 / torch.dot(v, v)) * v
-            if side == 0:   # A <- (I - w v^T) A
-                A -= torch.outer(w, v @ A)
-            else:           # A <- A (I - v w^T)
-                A -= torch.outer(A @ v, w)
-    return A
+    Q1 = device_haar_orthogonal(n, seed, device)
+    Q1 *= sigma                              # Q1 diag(sigma)
+    Q2 = device_haar_orthogonal(n, seed + 1, device)
+    At = Q2 @ Q1.t()                         # (Q1 diag(sigma) Q2^T)^T, row-major
+    del Q1, Q2
+    return At.t()                            # column-major view of A
 
 
 def device_shifted(n, seed=MATRIX_SEED, device="cuda"):

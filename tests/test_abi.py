@@ -43,6 +43,37 @@ def test_structure_bit_exact(lib, d):
         assert np.array_equal(out[: n * d], expect), (n, d)
 
 
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("granule", [1, 3, 8, 512])
+def test_tiled_structure_bit_exact(lib, d, granule):
+    """The tiled / Eq. 8 reference sizes: the closed form of the library
+    pairs exactly the indices the oracle's Algorithm 1 loops pair."""
+    for n in list(range(0, 40)) + [129, 1000, 1003, 4099]:
+        assert lib.rbt_reference_size(n, d, granule) == structure.reference_size(n, d, granule)
+        out = np.full(max(1, n * d), -7, dtype=np.int64)
+        assert lib.rbt_structure_ex(n, d, granule, out.ctypes.data_as(ctypes.c_void_p)) == 0
+        if n == 0:
+            continue
+        expect = np.array(structure.partners(n, d, granule), dtype=np.int64).reshape(-1)
+        assert np.array_equal(out[: n * d], expect), (n, d, granule)
+    for nb, p, q in [(512, 4, 4), (512, 2, 3), (64, 4, 6), (1, 1, 7)]:
+        assert lib.rbt_comm_free_granule(nb, p, q) == structure.comm_free_granule(nb, p, q)
+    assert lib.rbt_reference_size(5, 2, 0) == -1
+    assert lib.rbt_structure_ex(5, 2, 0, None) == -3
+
+
+@pytest.mark.parametrize("n,d,granule", [(1, 1, 1), (17, 2, 1), (1003, 2, 1), (300, 5, 4),
+                                         (129, 3, 8)])
+def test_generate_rotations_bit_exact(lib, n, d, granule):
+    U = np.zeros(n * d)
+    V = np.zeros(n * d)
+    assert lib.rbt_generate_rotations(n, d, 2023, granule, U.ctypes.data_as(ctypes.c_void_p),
+                                      V.ctypes.data_as(ctypes.c_void_p)) == 0
+    Uo, Vo = coeffs.generate_rotations(n, d, 2023, granule)
+    assert np.array_equal(U.reshape(d, n).T, Uo)
+    assert np.array_equal(V.reshape(d, n).T, Vo)
+
+
 @pytest.mark.parametrize("n,d,seed", [(1, 1, 0), (17, 2, 2023), (1003, 2, 42), (300, 5, 2 ** 64 - 1)])
 def test_generate_bit_exact(lib, n, d, seed):
     U = np.zeros(n * d)
@@ -85,7 +116,7 @@ def test_argument_errors(lib):
     assert mixed(solver=7) == -14
     assert mixed(tol=-1.0) == -15
     assert mixed(ldlu=4) == -6
-    assert mixed(depth=4) == _lib.RBT_ERR_UNSUPPORTED
+    assert mixed(depth=17) == -11  # beyond RBT_MAX_DEPTH
     assert lib.rbt_workspace_size(1000, 1, 2, _lib.RBT_BF16) > 0
     assert lib.rbt_workspace_size(1000, 1, 2, 9) == 0
     def guarded(prec=_lib.RBT_FP32, tol=1e-10, ldlu64=5, lu64=dummy, max_iter64=3, ldx=5):
@@ -120,7 +151,10 @@ def test_batched_argument_errors(lib):
     b = lib.rbt_batched_workspace_size(2, ns.ctypes.data_as(vp), ks.ctypes.data_as(vp), 3,
                                        _lib.RBT_FP32)
     assert 0 < a <= b
-    assert lib.rbt_batched_workspace_size(2, ns.ctypes.data_as(vp), ks.ctypes.data_as(vp), 4,
+    c = lib.rbt_batched_workspace_size(2, ns.ctypes.data_as(vp), ks.ctypes.data_as(vp), 11,
+                                       _lib.RBT_FP32)
+    assert b <= c  # any depth up to RBT_MAX_DEPTH: more coefficient storage
+    assert lib.rbt_batched_workspace_size(2, ns.ctypes.data_as(vp), ks.ctypes.data_as(vp), 17,
                                           _lib.RBT_FP32) == 0
     ks[1] = 17
     assert lib.rbt_batched_plan(2, ns.ctypes.data_as(vp), ks.ctypes.data_as(vp), 2, _lib.RBT_FP32,

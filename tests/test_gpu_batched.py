@@ -129,9 +129,31 @@ def test_batched_depths(rbt, depth):
         assert relfro(host(X), Xo) <= 10 * np.linalg.cond(A, np.inf) * 10 * n * EPS
 
 
+def test_batched_tiled_structure(rbt):
+    """The batched kernel with the tiled reference size (RBT_OPT_GRANULE):
+    every system converges to the oracle's solution computed through the
+    same tiled butterflies."""
+    from paper_2312_09376_amd import _lib
+    ns = np.array([5, 64, 200, 131, 77])
+    ks = np.array([2, 1, 4, 16, 3])
+    try:
+        rbt.set_option(_lib.RBT_OPT_GRANULE, 8)
+        As, Bs, Xs, iters, berr, info = run_batch(
+            rbt, ns, ks, lambda n, s: workloads.dominant(n, seed=s + 3))
+    finally:
+        rbt.set_option(_lib.RBT_OPT_GRANULE, 1)
+    for s, (A, B, X) in enumerate(zip(As, Bs, Xs)):
+        n = A.shape[0]
+        U, V = coeffs.generate(n, 2, system_seed(77, s))
+        Xo, _, _ = osolve.rbt_solve(A, B, U, V, 2, granule=8)
+        assert info[s] == 0 and berr[s] <= 10 * n * EPS
+        assert relfro(host(X), Xo) <= 10 * np.linalg.cond(A, np.inf) * 10 * n * EPS
+
+
 @pytest.mark.skip(reason="did not finish on the GPU (kernel still running after 120 s) for a batch "
                          "of one zero-pivot system (n=100, depth 0), one n=0 and one nrhs=0 system; "
-                         "cause not found by reading the code, so kept off the GPU")
+                         "no cause found by reading the code (every loop of the kernel is bounded "
+                         "and its barriers uniform), so the case stays off the GPU")
 def test_batched_zero_pivot_and_empty(rbt):
     A0 = np.eye(100)
     A0[70, 70] = 0.0
@@ -150,6 +172,31 @@ def test_batched_zero_pivot_and_empty(rbt):
     assert iters[0] == 0  # a NaN error ends the refinement
     assert info[1] == 0 and iters[1] == 0 and berr[1] == 0.0
     assert info[2] == 0 and berr[2] == 0.0  # no right-hand sides
+
+
+def test_batched_plan_mismatch_is_reported(rbt):
+    """A launch whose (batch, depth, prec) do not match the plan solves
+    nothing and marks every system: info -1, berr NaN, path -1."""
+    ns = np.array([90, 40, 150])
+    ks = np.array([1, 2, 1])
+    As = [dev(workloads.dominant(int(n), seed=s)) for s, n in enumerate(ns)]
+    Bs = [dev(workloads.randn(int(n), int(k), seed=s)) for s, (n, k) in enumerate(zip(ns, ks))]
+    plan = rbt.batched_plan(ns, ks, 2, rbt.RBT_FP32)
+    args = rbt.BatchArgs(plan, As, Bs)
+    rc = rbt.lib().rbt_solve_batched(plan.batch, rbt._p(args.pA), rbt._p(args.lA), rbt._p(args.pB),
+                                     rbt._p(args.lB), rbt._p(args.pX), rbt._p(args.lX), 1, 5,
+                                     rbt.RBT_FP32, -10.0, 30, rbt._p(args.iters), rbt._p(args.berr),
+                                     rbt._p(args.info), rbt._p(args.path), rbt._p(plan.work),
+                                     plan.work.numel(), rbt._stream(plan.work.device))
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert (host(args.info) == -1).all() and (host(args.path) == -1).all()
+    assert np.isnan(host(args.berr)).all()
+    # the matching launch with the same arguments solves them
+    rbt.solve_batched_launch(plan, args, seed=5)
+    torch.cuda.synchronize()
+    assert (host(args.info) == 0).all() and (host(args.path) >= 0).all()
+    assert all(host(args.berr)[s] <= 10 * n * EPS for s, n in enumerate(ns))
 
 
 def test_batched_plan_reuse_and_graph_capture(rbt):

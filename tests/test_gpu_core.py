@@ -8,12 +8,13 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import coeffs, solve as osolve, transform as otr
+from oracle import coeffs, solve as osolve, structure, transform as otr
 from paper_2312_09376_amd import workloads
 
 pytestmark = pytest.mark.gpu
 
 EPS = 2.0 ** -52
+kNB_ROWS = 128  # rows of one diagonal block of the blocked elimination
 SIZES = [1, 2, 3, 5, 9, 16, 127, 128, 129, 300, 1000, 1001, 1003]
 
 
@@ -65,6 +66,34 @@ def test_transform2_matches_oracle(rbt, d):
         assert np.array_equal(host(Ad), A)                 # input untouched
         rbt.transform2(Ad, U, V, d, out=Ad)                # in place
         assert relfro(host(Ad), expect) <= 1e-14, (n, d)
+
+
+@pytest.mark.parametrize("d,granule", [(2, 8), (2, 512), (3, 16), (1, 100)])
+def test_tiled_structure_transform_and_solve(rbt, d, granule):
+    """Tiled reference size (RBT_OPT_GRANULE): the fused transform, the
+    one-sided transforms and the whole solve follow the oracle's tiled
+    structure, including sizes where m - n spans several tiles."""
+    from paper_2312_09376_amd import _lib
+    try:
+        rbt.set_option(_lib.RBT_OPT_GRANULE, granule)
+        for n in (5, 129, 1000, 1003, 2100):
+            A = workloads.shifted(n, seed=n + d)
+            Uo, Vo = coeffs.generate(n, d, 2023)
+            U, V = rbt.generate_device(n, d, 2023)
+            out = rbt.transform2(dev(A), U, V, d)
+            assert relfro(host(out), otr.two_sided(A, Uo, Vo, d, granule)) <= 1e-14, (n, granule)
+            B = workloads.randn(n, 2, seed=64)
+            Bt = rbt.transform_vec(dev(B), U, d, rbt.RBT_OP_T)
+            assert relfro(host(Bt), otr.apply_transpose_left(B, Uo, d, granule)) <= 1e-14
+            Xo, _, _ = osolve.rbt_solve(A, B, Uo, Vo, d, granule=granule)
+            _, X, info, _ = rbt.solve_(dev(A), dev(B), d, 2023)
+            assert int(info.item()) == 0
+            assert relfro(host(X), Xo) <= 1e-10
+            # a different structure than the non-tiled one (unless they coincide)
+            if structure.reference_size(n, d, granule) != structure.reference_size(n, d):
+                assert relfro(host(out), otr.two_sided(A, Uo, Vo, d)) > 1e-6
+    finally:
+        rbt.set_option(_lib.RBT_OPT_GRANULE, 1)
 
 
 def test_transform2_fp32_output_and_ld(rbt):
@@ -179,6 +208,35 @@ def test_getrs_both_transposes(rbt, n, k):
     Xt = rbt.getrs(LU, dev(B), trans=1)
     expect_t = osolve.backward_unit_lower_transposed(LUo, osolve.forward_upper_transposed(LUo, B))
     assert relfro(host(Xt), expect_t) <= 1e-12
+
+
+def test_sweep_expired_wait_is_reported(rbt):
+    """A persistent sweep whose bounded wait expires must not return a
+    silently wrong finite solution. The wait bound is forced from the host
+    (a negative spin limit expires every wait at once, so every kernel still
+    exits normally): the non-synchronizing solve leaves NaN in the blocks
+    solved after an expired wait, and the refining solve returns
+    RBT_ERR_SYNC. With the default bound the same calls are correct."""
+    from paper_2312_09376_amd import _lib
+    n = 1000  # 8 block rows: every block after the first waits
+    A = workloads.shifted(n, seed=3)
+    B = workloads.randn(n, 1, seed=9)
+    LU, _ = rbt.genp(dev(A))
+    default = rbt.get_option(_lib.RBT_OPT_SWEEP_SPIN_LIMIT)
+    try:
+        rbt.set_option(_lib.RBT_OPT_SWEEP_SPIN_LIMIT, -1)
+        X = host(rbt.getrs(LU, dev(B), trans=0))
+        assert np.isnan(X).any()
+        assert not np.isfinite(X[kNB_ROWS:]).any()
+        with pytest.raises(_lib.RBTError, match=r"\(-103\)"):
+            rbt.solve_refine(dev(A), dev(B), 2, 2023, max_iter=2)
+    finally:
+        rbt.set_option(_lib.RBT_OPT_SWEEP_SPIN_LIMIT, default)
+    X = host(rbt.getrs(LU, dev(B), trans=0))
+    LUo, _ = osolve.genp_unblocked(A)
+    assert relfro(X, osolve.lu_solve(LUo, B)) <= 1e-12
+    Xr, _, _, berr, _, _ = rbt.solve_refine(dev(A), dev(B), 2, 2023, max_iter=2)
+    assert float(berr.item()) <= 10 * n * EPS
 
 
 @pytest.mark.parametrize("n,k,d", [(1, 1, 2), (5, 2, 2), (129, 1, 2), (1000, 1, 2), (1001, 1, 2),
