@@ -165,6 +165,23 @@ int rbt_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu, double *B
 int rbt_solve_ex(int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_t ldb, int depth,
                  uint64_t seed, int32_t *info_dev, void *work, size_t work_bytes, void *stream);
 
+/* Device. rbt_solve_ex for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): no
+ * workspace argument, and no allocation or allocating library call. The
+ * workspace is a library-owned device array of RBT_NOALLOC_SCRATCH_MB MiB on
+ * each GPU the library runs on (held until the process ends; its address is
+ * looked up once per device on the first call there). Sizes whose workspace
+ * rbt_workspace_size(n, nrhs, depth, RBT_FP64) exceeds it return
+ * RBT_ERR_WORKSPACE (n <= 28000 or so with one right-hand side, about
+ * 9000 with sixteen). Every
+ * call on one GPU uses the same array: calls that overlap on one GPU (other
+ * streams, other threads) race; the array keeps the last call's contents and
+ * the solve writes every part it reads. Arguments and results as
+ * rbt_solve_ex (work and work_bytes omitted). */
+#define RBT_NOALLOC_SCRATCH_MB 96
+int rbt_solve_ex_noalloc(int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_t ldb,
+                         int depth, uint64_t seed, int32_t *info_dev, void *stream);
+
 /* Device. As rbt_solve_ex, but the library allocates its workspace with
  * hipMallocAsync/hipFreeAsync on `stream`. */
 int rbt_solve(int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_t ldb, int depth,

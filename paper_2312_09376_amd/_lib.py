@@ -14,6 +14,7 @@ RBT_ERR_WORKSPACE = -101
 RBT_ERR_UNSUPPORTED = -102
 RBT_ERR_SYNC = -103
 RBT_MAX_DEPTH = 16
+RBT_NOALLOC_SCRATCH_MB = 96
 RBT_FP64, RBT_FP32, RBT_BF16 = 0, 1, 2
 RBT_OP_T, RBT_OP_N = 0, 1
 RBT_IR_CLASSIC, RBT_IR_GMRES = 0, 1
@@ -37,6 +38,7 @@ SIGNATURES = {
     "rbt_genp": (i32, [i64, vp, i64, vp, vp]),
     "rbt_getrs": (i32, [i64, i64, vp, i64, vp, i64, i32, vp, sz, vp]),
     "rbt_solve_ex": (i32, [i64, i64, vp, i64, vp, i64, i32, u64, vp, vp, sz, vp]),
+    "rbt_solve_ex_noalloc": (i32, [i64, i64, vp, i64, vp, i64, i32, u64, vp, vp]),
     "rbt_solve": (i32, [i64, i64, vp, i64, vp, i64, i32, u64, vp]),
     "rbt_solve_refine": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, u64, dbl, i32,
                                vp, vp, vp, vp, sz, vp]),

@@ -992,6 +992,46 @@ extern "C" int rbt_solve(int64_t n, int64_t nrhs, double *A, int64_t lda, double
   return rc;
 }
 
+// ---- allocation-free entry point ----
+namespace rbt {
+namespace {
+// Workspace of rbt_solve_ex_noalloc: one array per GPU, held until the
+// process ends. Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoAllocBytes = size_t(RBT_NOALLOC_SCRATCH_MB) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on each device, with that device current), or nullptr on failure.
+void *scratch_ptr() {
+  static std::mutex mu;
+  static std::vector<void *> per_dev;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (per_dev.size() <= size_t(dev)) per_dev.resize(dev + 1, nullptr);
+  if (per_dev[dev] == nullptr) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    per_dev[dev] = p;
+  }
+  return per_dev[dev];
+}
+}  // namespace
+}  // namespace rbt
+
+extern "C" int rbt_solve_ex_noalloc(int64_t n, int64_t nrhs, double *A, int64_t lda, double *B,
+                                    int64_t ldb, int depth, uint64_t seed, int32_t *info_dev,
+                                    void *stream) {
+  if (n < 0) return -1;
+  if (nrhs < 0) return -2;
+  if (bad_depth(depth)) return -7;
+  if (layout(n, nrhs, depth).total > kNoAllocBytes) return RBT_ERR_WORKSPACE;
+  void *work = scratch_ptr();
+  if (work == nullptr) return RBT_ERR_HIP;
+  return rbt_solve_ex(n, nrhs, A, lda, B, ldb, depth, seed, info_dev, work, kNoAllocBytes, stream);
+}
+
 extern "C" int rbt_backward_error(int64_t n, int64_t nrhs, const double *A, int64_t lda,
                                   const double *X, int64_t ldx, const double *B, int64_t ldb,
                                   double *berr_dev, void *work, size_t work_bytes, void *stream) {
