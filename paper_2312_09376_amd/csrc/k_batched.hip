@@ -8,22 +8,23 @@
 // <= tol (Sec. 5).
 //
 // Per system, in the workspace: F (n x n FP32, ld n) holds A~ and then its
-// L\U factors; the FP64 area holds U, V (n x d each), the FP64 inverses of
-// the 64 x 64 diagonal blocks (strictly lower part: L^-1, upper part with
-// the diagonal: U^-1, one 64 x 64 array per block) and the residual
-// (n x nrhs).
+// L\U factors; the FP64 area holds U, V (n x d each), the inverses of the
+// 64 x 64 diagonal blocks (strictly lower part: L^-1, upper part with the
+// diagonal: U^-1, one 64 x 64 array per block, in the factors' type) and
+// the residual (n x nrhs); the fallback area holds FP64 factors.
 //
-// Elimination, per 64-column step k (right-looking):
-//   diagonal block in LDS (FP64): 16-column panels factored by wavefront 0
-//   with readlane broadcasts, U rows by substitution, rank-16 updates;
-//   its inverses L^-1 and U^-1 by substitution (one column per lane:
-//   wavefront 0 the columns of L^-1, wavefront 1 those of U^-1);
-//   L21 = A21 U11^-1 and U12 = L11^-1 A12 as FP64 products with the
-//   inverses (v_mfma_f64_16x16x4f64; rounded to FP32 once), and
-//   A22 -= L21 U12 in FP32 (v_mfma_f32_16x16x4f32; BF16 mode:
-//   v_mfma_f32_16x16x32_bf16), all on the matrix cores in 64 x 64 tiles.
-// Solves: block sweeps over the factors (widened to FP64) with the FP64
-// inverses of the diagonal blocks.
+// Elimination, per 64-column step k (right-looking), in the factors'
+// arithmetic type (FP32 for the low-precision pass, FP64 for the fallback):
+//   diagonal block in LDS: 16-column panels factored by wavefront 0 with
+//   readlane broadcasts, U rows by substitution, rank-16 updates; its
+//   inverses L^-1 and U^-1 by substitution (one column per lane: wavefront
+//   0 the columns of L^-1, wavefront 1 those of U^-1);
+//   L21 = A21 U11^-1 and U12 = L11^-1 A12 as matrix-core products with the
+//   inverses (FP32: plus one refinement step, X += (A - X D) D^-1), and
+//   A22 -= L21 U12 (FP32: v_mfma_f32_16x16x4f32, or BF16 operands on
+//   v_mfma_f32_16x16x32_bf16), all in 64 x 64 tiles.
+// Solves: block sweeps over the factors with the inverses of the diagonal
+// blocks (FP32: plus one refinement step per block).
 //
 // The host plan (rbt_batched_plan) writes the header and the descriptor
 // table; the kernel checks the header against its arguments and does
@@ -80,7 +81,7 @@ __device__ __forceinline__ void st4(gfloat *p, f4u v) {
 // a step); the sweeps use both regions.
 constexpr int kR0Doubles = BB * LDS_;       // 4160 doubles
 constexpr int kR1Doubles = BB * LDS_;
-static_assert(5 * BB * NR <= kR0Doubles + kR1Doubles, "sweep buffers exceed LDS");  // part + xs
+static_assert(7 * BB * NR <= kR0Doubles + kR1Doubles, "sweep buffers exceed LDS");  // part, xs, ys, x0s
 static_assert(256 * NR + BT / 64 <= kR0Doubles, "residual buffers exceed region 0");
 
 struct Args {
@@ -405,6 +406,39 @@ __device__ __forceinline__ void tile_store_c(const typename Mma16<C>::v4 (&acc)[
     }
 }
 
+template <typename C>
+__device__ __forceinline__ void add_acc(typename Mma16<C>::v4 (&a)[2][2],
+                                        const typename Mma16<C>::v4 (&b)[2][2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) a[i][j] += b[i][j];
+}
+
+// D[col * LDS_ + row] = acc (SUB: D -= acc) for the tile elements of this
+// lane (LDS, type C, all 64 x 64 entries).
+template <typename C, bool SUB = false>
+__device__ __forceinline__ void tile_to_lds(const typename Mma16<C>::v4 (&acc)[2][2],
+                                            typename Lds<C>::T *D) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = wn * 32 + 16 * j + l16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wm * 32 + 16 * i + Mma16<C>::row(lk, v);
+        if (SUB)
+          D[col * LDS_ + row] -= acc[i][j][v];
+        else
+          D[col * LDS_ + row] = acc[i][j][v];
+      }
+    }
+}
+
 // Stage a 64 x 64 block of F (FP32 or FP64, column-major, rows r0..,
 // cols c0..; rv x cv valid) in LDS as D[c * LDS_ + r] of type C (zero
 // outside). (src is factor storage, D is LDS: both address spaces made
@@ -607,10 +641,14 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
     }
   }
   __syncthreads();
+  // FP32: a copy of L\U (identity beyond kb) in the second half of region 1
+  // for the refinement step of the panel products
+  lds_t *Sc = T + BB * LDS_;
   for (int e = tid; e < BB * BB; e += BT) {
     const int r = e & 63, c = e >> 6;
     Invg[r + c * BB] = T[c * LDS_ + r];
     if (r < kb && c < kb) F[(k + r) + (k + c) * s.n] = S[c * LDS_ + r];
+    if constexpr (sizeof(TF) == 4) Sc[c * LDS_ + r] = S[c * LDS_ + r];
   }
   __syncthreads();
 }
@@ -636,11 +674,21 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
     if (rest <= 0) break;
     f4 acc[2][2];
     typename Mma16<double>::v4 acc64[2][2];
-    // panel products in the factors' arithmetic type
-    typename Mma16<TF>::v4 accp[2][2];
+    // panel products in the factors' arithmetic type. A product with an
+    // explicit inverse of the diagonal block is accurate to kappa(block) u
+    // only; in FP32 that is too coarse for refinement to converge on
+    // high-growth N(0,1) systems, so the FP32 products take one
+    // refinement step (region 0 holds the staged panel tile and the first
+    // product, region 1 the inverses and a copy of L\U). The FP64 factors
+    // of the fallback use the inverses alone (kappa u64 is small).
+    constexpr bool kRefinePanel = sizeof(TF) == 4;
+    typename Mma16<TF>::v4 accp[2][2], accq[2][2];
     typedef typename Lds<TF>::T lds_t;
     const lds_t *T = (const lds_t *)L1;  // L^-1 below the diagonal, U^-1 on and above (ld LDS_)
+    const lds_t *Sc = T + BB * LDS_;     // FP32: L\U of the diagonal block
     const lds_t *L0l = (const lds_t *)L0;
+    lds_t *L0w = (lds_t *)L0;
+    lds_t *X0s = L0w + BB * LDS_;        // FP32: the first product
     TF *L0t = reinterpret_cast<TF *>(L0);
     // L21 = A21 U11^-1 (rows k+kb.., 64-row tiles)
     for (int64_t r0 = k + kb; r0 < n; r0 += BB) {
@@ -648,8 +696,20 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
       // stage A21 tile as [k][r]: element (r, kx) at L0[kx * LDS_ + r]
       stage_c<TF>(L0t, F + r0 + k * n, n, rv, kb);
       __syncthreads();
-      tile_mma_c<TF>([&](int m, int kx) { return L0l[kx * LDS_ + m]; },
-                     [&](int kx, int nx) { return kx <= nx ? T[nx * LDS_ + kx] : TF(0); }, accp);
+      auto uinv = [&](int kx, int nx) { return kx <= nx ? T[nx * LDS_ + kx] : TF(0); };
+      tile_mma_c<TF>([&](int m, int kx) { return L0l[kx * LDS_ + m]; }, uinv, accp);
+      if constexpr (kRefinePanel) {
+        // one refinement step: R = A21 - X U11 (over the staged A21), then
+        // X += R U11^-1
+        tile_to_lds<TF>(accp, X0s);
+        __syncthreads();
+        tile_mma_c<TF>([&](int m, int kx) { return X0s[kx * LDS_ + m]; },
+                       [&](int kx, int nx) { return kx <= nx ? Sc[nx * LDS_ + kx] : TF(0); }, accq);
+        tile_to_lds<TF, true>(accq, L0w);
+        __syncthreads();
+        tile_mma_c<TF>([&](int m, int kx) { return L0l[kx * LDS_ + m]; }, uinv, accq);
+        add_acc<TF>(accp, accq);
+      }
       __syncthreads();
       tile_store_c<TF>(accp, F + r0 + k * n, n, rv, kb);
     }
@@ -660,9 +720,22 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
       // stage A12 tile: element (kx, nx) at L0[nx * LDS_ + kx]
       stage_c<TF>(L0t, F + k + c0 * n, n, kb, cv);
       __syncthreads();
-      tile_mma_c<TF>(
-          [&](int m, int kx) { return m > kx ? T[kx * LDS_ + m] : (m == kx ? TF(1) : TF(0)); },
-          [&](int kx, int nx) { return L0l[nx * LDS_ + kx]; }, accp);
+      auto linv = [&](int m, int kx) {
+        return m > kx ? T[kx * LDS_ + m] : (m == kx ? TF(1) : TF(0));
+      };
+      tile_mma_c<TF>(linv, [&](int kx, int nx) { return L0l[nx * LDS_ + kx]; }, accp);
+      if constexpr (kRefinePanel) {
+        // R = A12 - L11 X (over the staged A12), then X += L11^-1 R
+        tile_to_lds<TF>(accp, X0s);
+        __syncthreads();
+        tile_mma_c<TF>(
+            [&](int m, int kx) { return m > kx ? Sc[kx * LDS_ + m] : (m == kx ? TF(1) : TF(0)); },
+            [&](int kx, int nx) { return X0s[nx * LDS_ + kx]; }, accq);
+        tile_to_lds<TF, true>(accq, L0w);
+        __syncthreads();
+        tile_mma_c<TF>(linv, [&](int kx, int nx) { return L0l[nx * LDS_ + kx]; }, accq);
+        add_acc<TF>(accp, accq);
+      }
       __syncthreads();
       tile_store_c<TF>(accp, F + k + c0 * n, n, kb, cv);
     }
@@ -850,6 +923,9 @@ __device__ __noinline__ void sweep(const Sys &s, double *Y_in, int64_t ldy, doub
   lds_t *Ll = (lds_t *)L0;
   TF RBT_AS_LDS(*part)[BB][NRT] = reinterpret_cast<TF RBT_AS_LDS(*)[BB][NRT]>(Ll);  // [4][64][NRT]
   TF RBT_AS_LDS(*xs)[NR] = reinterpret_cast<TF RBT_AS_LDS(*)[NR]>(Ll + 4 * BB * NRT);  // [64][16]
+  // FP32 refinement step: y_b and the first x_b
+  TF RBT_AS_LDS(*ys)[NR] = reinterpret_cast<TF RBT_AS_LDS(*)[NR]>(Ll + 4 * BB * NRT + BB * NR);
+  TF RBT_AS_LDS(*x0s)[NR] = reinterpret_cast<TF RBT_AS_LDS(*)[NR]>(Ll + 4 * BB * NRT + 2 * BB * NR);
   const int64_t nblk = (n + BB - 1) / BB;
   for (int64_t t = 0; t < nblk; ++t) {
     const int64_t b = LOWER ? t : nblk - 1 - t;
@@ -858,39 +934,107 @@ __device__ __noinline__ void sweep(const Sys &s, double *Y_in, int64_t ldy, doub
     // y_b -> LDS
     if (sg == 0) {
 #pragma unroll
-      for (int c = 0; c < NR; ++c)
-        xs[i][c] = (i < kb && c < N) ? TF(Y[(r0 + i) + int64_t(c) * ldy]) : TF(0);
+      for (int c = 0; c < NR; ++c) {
+        const TF y = (i < kb && c < N) ? TF(Y[(r0 + i) + int64_t(c) * ldy]) : TF(0);
+        xs[i][c] = y;
+        if constexpr (sizeof(TF) == 4) ys[i][c] = y;
+      }
     }
     __syncthreads();
-    // x_b = Dinv y_b
+    // x_b = Dinv y_b: part[sg][i][:] = sum over this segment's 16 columns of
+    // Dinv(i, kx) xs[kx][:], then the four segments are added
     const TF RBT_AS_GLOBAL *Db = (const TF RBT_AS_GLOBAL *)s.Inv + b * BB * BB;
-    TF dv[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) dv[q] = Db[i + (sg * 16 + q) * BB];
-    TF acc[NRT];
-#pragma unroll
-    for (int c = 0; c < NRT; ++c) acc[c] = TF(0);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    // (entries read from the inverse where they are used: an array of them
+    // held through the loops below would be indexed dynamically)
+    auto dinv = [&](int q) {
       const int kx = sg * 16 + q;
-      const TF v = LOWER ? (i > kx ? dv[q] : (i == kx ? TF(1) : TF(0))) : (i <= kx ? dv[q] : TF(0));
+      const TF d = Db[i + kx * BB];
+      return LOWER ? (i > kx ? d : (i == kx ? TF(1) : TF(0))) : (i <= kx ? d : TF(0));
+    };
+    auto part_sum = [&](int c) {
+      return (part[0][i][c] + part[1][i][c]) + (part[2][i][c] + part[3][i][c]);
+    };
+    {
+      TF acc[NRT];
 #pragma unroll
-      for (int c = 0; c < NRT; ++c) acc[c] += v * xs[kx][c];
+      for (int c = 0; c < NRT; ++c) acc[c] = TF(0);
+#pragma unroll 2
+      for (int q = 0; q < 16; ++q) {
+        const TF v = dinv(q);
+#pragma unroll
+        for (int c = 0; c < NRT; ++c) acc[c] += v * xs[sg * 16 + q][c];
+      }
+#pragma unroll
+      for (int c = 0; c < NRT; ++c) part[sg][i][c] = acc[c];
     }
-#pragma unroll
-    for (int c = 0; c < NRT; ++c) part[sg][i][c] = acc[c];
     __syncthreads();
     if (sg == 0) {
 #pragma unroll
       for (int c = 0; c < NR; ++c) {
         TF x = TF(0);
-        if (c < NRT && i < kb && c < N)
-          x = (part[0][i][c] + part[1][i][c]) + (part[2][i][c] + part[3][i][c]);
+        if (c < NRT && i < kb && c < N) x = part_sum(c < NRT ? c : 0);
         xs[i][c] = x;
-        if (i < kb && c < N) Y[(r0 + i) + int64_t(c) * ldy] = double(x);
+        if constexpr (sizeof(TF) == 4)
+          x0s[i][c] = x;
+        else if (i < kb && c < N)
+          Y[(r0 + i) + int64_t(c) * ldy] = double(x);
       }
     }
     __syncthreads();
+    if constexpr (sizeof(TF) == 4) {
+      // FP32: one refinement step against the diagonal block itself, so the
+      // block solve is not limited to kappa(block) u32 (the product with an
+      // explicit inverse alone is): r = y_b - D x_b, x_b += Dinv r
+      {
+        const int ic = i < kb ? i : kb - 1;
+        TF acc[NRT];
+#pragma unroll
+        for (int c = 0; c < NRT; ++c) acc[c] = TF(0);
+#pragma unroll 2
+        for (int q = 0; q < 16; ++q) {
+          const int kx = sg * 16 + q;
+          const TF f = F[(r0 + ic) + (r0 + (kx < kb ? kx : kb - 1)) * n];
+          const bool in = i < kb && kx < kb;
+          const TF v = LOWER ? (i == kx ? TF(1) : (in && kx < i ? f : TF(0)))
+                             : (in && kx >= i ? f : (i == kx ? TF(1) : TF(0)));
+#pragma unroll
+          for (int c = 0; c < NRT; ++c) acc[c] += v * xs[kx][c];
+        }
+#pragma unroll
+        for (int c = 0; c < NRT; ++c) part[sg][i][c] = acc[c];
+      }
+      __syncthreads();
+      if (sg == 0) {
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+          xs[i][c] = (c < NRT && i < kb && c < N) ? ys[i][c] - part_sum(c < NRT ? c : 0) : TF(0);
+      }
+      __syncthreads();
+      {
+        TF acc[NRT];
+#pragma unroll
+        for (int c = 0; c < NRT; ++c) acc[c] = TF(0);
+#pragma unroll 2
+        for (int q = 0; q < 16; ++q) {
+          const TF v = dinv(q);
+#pragma unroll
+          for (int c = 0; c < NRT; ++c) acc[c] += v * xs[sg * 16 + q][c];
+        }
+#pragma unroll
+        for (int c = 0; c < NRT; ++c) part[sg][i][c] = acc[c];
+      }
+      __syncthreads();
+      if (sg == 0) {
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+          TF x = x0s[i][c];
+          if (c < NRT && i < kb && c < N) x += part_sum(c < NRT ? c : 0);
+          xs[i][c] = x;
+          if (i < kb && c < N) Y[(r0 + i) + int64_t(c) * ldy] = double(x);
+        }
+      }
+      __syncthreads();
+    }
     // rows still to be solved: after the block (L) or before it (U)
     const int64_t lo = LOWER ? r0 + kb : 0, hi = LOWER ? n : r0;
     if (hi > lo) {
