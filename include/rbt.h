@@ -195,7 +195,8 @@ int rbt_solve(int64_t n, int64_t nrhs, double *A, int64_t lda, double *B, int64_
  * (infinity norms, maximum over columns) is <= tol or max_iter steps are
  * done. iters_dev (device int32) and berr_dev (device double) receive the
  * step count and the final backward error (both nullable). This entry point
- * synchronizes `stream` once per refinement step to test convergence. */
+ * synchronizes `stream` once per refinement step to test convergence,
+ * unless RBT_OPT_CAPTURABLE is set (then it never synchronizes). */
 int rbt_solve_refine(int64_t n, int64_t nrhs, const double *A, int64_t lda, double *LU,
                      int64_t ldlu, const double *B, int64_t ldb, double *X, int64_t ldx, int depth,
                      uint64_t seed, double tol, int max_iter, int32_t *iters_dev, double *berr_dev,
@@ -484,6 +485,21 @@ int rbt_solve_backward_mixed(int64_t n, int64_t nrhs, const float *LU, int64_t l
  *   A~ = U^T A (columns untouched, x = x~; V is neither applied nor needed
  *   by the transforms, though the coefficient arrays keep their size). */
 #define RBT_OPT_SIDES 10
+/* RBT_OPT_CAPTURABLE: refinement of rbt_solve_refine and of rbt_solve_mixed
+ *   with RBT_IR_CLASSIC (the stationary refinement of Sec. 5).
+ *   0 (default): the host tests the Eq. 7 error after every step (one
+ *   stream synchronization per step) and stops launching.
+ *   1: no host test, synchronization or host-device copy in the call, so
+ *   the call can be captured in a HIP graph: all max_iter steps are
+ *   enqueued, and the kernels of a step return at once when a device word,
+ *   set by the step's convergence test, says the error has reached tol.
+ *   Same residuals, corrections, step count and final error as with 0;
+ *   iters_dev is written on the device. Requires nrhs <= 16 (else
+ *   RBT_ERR_UNSUPPORTED; also for RBT_IR_GMRES, whose small least-squares
+ *   problems are solved on the host). An expired sweep wait is not reported
+ *   as RBT_ERR_SYNC in this mode: the poisoned solution gives a NaN
+ *   backward error. */
+#define RBT_OPT_CAPTURABLE 11
 /* Returns 0, -1 for an unknown option, -2 for an invalid value. */
 int rbt_set_option(int option, int64_t value);
 /* Current value, or -1 for an unknown option. */

@@ -44,16 +44,19 @@ def genp_unblocked(A):
     return LU, info
 
 
-def genp_blocked(A, nb=256):
+def genp_blocked(A, nb=256, max_panels=None):
     """Same elimination as genp_unblocked, grouped in column panels of width
     nb so the trailing update is one matrix product per panel; it differs from
     the unblocked form only in the order of the roundings.
+    max_panels: stop after that many panels (the factors are then those of
+    the first max_panels * nb columns and the untouched Schur complement; used
+    only to time a sample of the elimination).
     """
     LU = np.array(A, dtype=np.float64, copy=True)
     n = LU.shape[0]
     info = 0
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
-        for k0 in range(0, n, nb):
+        for k0 in range(0, n if max_panels is None else min(n, max_panels * nb), nb):
             k1 = min(k0 + nb, n)
             # eliminate inside the panel columns k0..k1-1 (all rows below)
             for k in range(k0, k1):

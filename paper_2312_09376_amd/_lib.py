@@ -75,6 +75,7 @@ RBT_OPT_MIXED_FP64_INNER = 7
 RBT_OPT_GRANULE = 8
 RBT_OPT_BUTTERFLY = 9
 RBT_OPT_SIDES = 10
+RBT_OPT_CAPTURABLE = 11
 STAGES = ["generate", "transform2", "transform_vec", "diag", "panel", "trailing", "solve",
           "residual", "pivoted", "outer"]
 

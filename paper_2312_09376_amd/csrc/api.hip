@@ -79,6 +79,7 @@ struct Options {
   int64_t granule = 1;           // butterfly structure: reference-size granule
   int64_t kind = 0;              // butterflies: 0 Eq. 3 (random diagonals), 1 rotations
   int64_t sides = 2;             // 2: U^T A V; 1: U^T A (one-sided)
+  int64_t capturable = 0;        // refinement without host tests (graph capturable)
 };
 Options &options() {
   static Options o;
@@ -614,6 +615,40 @@ int refine_classic(int64_t n, int64_t nrhs, const double *A, int64_t lda, const 
   return 0;
 }
 
+// Capturable form of refine_classic (the same residuals, corrections and
+// stopping rule): all max_iter steps are enqueued at once and each step's
+// kernels are gated by a device word that the step's convergence test sets
+// when the Eq. 7 error is <= tol, so no host test, synchronization or copy
+// is needed and the whole refinement can be captured in a HIP graph. The
+// step count goes to *iters on the device. Right-hand sides: at most
+// kSkinnyMax (the gated sweep path).
+template <typename TF>
+int refine_classic_device(int64_t n, int64_t nrhs, const double *A, int64_t lda, const TF *LU,
+                          int64_t ldlu, const double *B, int64_t ldb, double *X, int64_t ldx,
+                          const Geometry &g, const double *U, const double *V,
+                          const double *winv, int32_t *sync, double *R, double *scratch,
+                          double *anorm, double *berr, double tol, int max_iter, int32_t *gate,
+                          int32_t *iters, bool f64, hipStream_t s) {
+  RBT_HIP_CHECK(launch_fill_i32(gate, 0, s));
+  RBT_HIP_CHECK(launch_fill_i32(iters, 0, s));
+  {
+    StageScope t(kStageResidual, s, 8.0 * double(n) * n);
+    RBT_HIP_CHECK(launch_residual_berr(n, nrhs, A, lda, X, ldx, B, ldb, R, n, true, scratch,
+                                       anorm, berr, s));
+  }
+  RefineGate on(gate);
+  for (int it = 0; it < max_iter; ++it) {
+    RBT_HIP_CHECK(launch_refine_step(berr, tol, gate, iters, s));
+    const int rc = apply_solve(g, nrhs, LU, ldlu, R, n, U, V, winv, sync, f64, s);
+    if (rc) return rc;
+    RBT_HIP_CHECK(launch_axpy_cols(n, nrhs, R, n, X, ldx, s));
+    StageScope t(kStageResidual, s, 8.0 * double(n) * n);
+    RBT_HIP_CHECK(launch_residual_berr(n, nrhs, A, lda, X, ldx, B, ldb, R, n, false, scratch,
+                                       anorm, berr, s));
+  }
+  return 0;
+}
+
 // GMRES-IR: each refinement step solves A D = R (R = B - A X in FP64 with
 // the original A) by restarted GMRES in FP64, left-preconditioned by
 // M^-1 = V (LU)^-1 U^T (the solve of Eq. 1 with the low-precision factors),
@@ -1074,6 +1109,7 @@ extern "C" int rbt_solve_refine(int64_t n, int64_t nrhs, const double *A, int64_
   if (bad_depth(depth)) return -11;
   if (!(tol >= 0.0)) return -13;
   if (max_iter < 0) return -14;
+  if (options().capturable && nrhs > kSkinnyMax) return RBT_ERR_UNSUPPORTED;
   const Layout L = layout(n, nrhs, depth);
   if (n > 0 && work == nullptr) return -18;
   if (work_bytes < L.total) return RBT_ERR_WORKSPACE;
@@ -1104,6 +1140,13 @@ extern "C" int rbt_solve_refine(int64_t n, int64_t nrhs, const double *A, int64_
   RBT_HIP_CHECK(clear_sweep_err(sync, s));
   rc = apply_solve(g, nrhs, (const double *)LU, ldlu, X, ldx, U, V, winv, sync, true, s);
   if (rc) return rc;
+  if (options().capturable) {
+    // no host test: an expired sweep wait shows as a NaN backward error
+    int32_t *words = reinterpret_cast<int32_t *>(small + 32);
+    return refine_classic_device(n, nrhs, A, lda, (const double *)LU, ldlu, B, ldb, X, ldx, g,
+                                 U, V, winv, sync, R, scratch, anorm, berr, tol, max_iter,
+                                 words, iters_dev ? iters_dev : words + 1, true, s);
+  }
   int it = 0;
   rc = refine_classic(n, nrhs, A, lda, (const double *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv, sync, R,
                       scratch, anorm, berr, tol, max_iter, &it, true, s);
@@ -1123,7 +1166,7 @@ int mixed_impl(int64_t n, int64_t nrhs, const double *A, int64_t lda, float *LU,
                const double *B, int64_t ldb, double *X, int64_t ldx, int depth, uint64_t seed,
                int prec, int solver, double tol, int max_iter, double *berr_dev,
                int32_t *info_dev, void *work, size_t work_bytes, hipStream_t s, int *it_out,
-               bool *stalled) {
+               bool *stalled, int32_t *iters_cap = nullptr) {
   *it_out = 0;
   const Layout L = layout(n, nrhs, depth, true, prec == RBT_BF16);
   if (work_bytes < L.total) return RBT_ERR_WORKSPACE;
@@ -1135,6 +1178,7 @@ int mixed_impl(int64_t n, int64_t nrhs, const double *A, int64_t lda, float *LU,
   double *berr = berr_dev ? berr_dev : small + 1;
   if (n == 0 || nrhs == 0) {
     RBT_HIP_CHECK(launch_fill_f64(berr, 0.0, s));
+    if (iters_cap) RBT_HIP_CHECK(launch_fill_i32(iters_cap, 0, s));
     if (n > 0) {  // still factor, as the square case of rbt_genp
       const Geometry g = geometry(n, depth);
       double *U = at<double>(work, L.o_coef);
@@ -1168,6 +1212,12 @@ int mixed_impl(int64_t n, int64_t nrhs, const double *A, int64_t lda, float *LU,
   RBT_HIP_CHECK(clear_sweep_err(sync, s));
   rc = apply_solve(g, nrhs, (const float *)LU, ldlu, X, ldx, U, V, winv, sync, f64, s);
   if (rc) return rc;
+  if (iters_cap != nullptr) {
+    int32_t *words = reinterpret_cast<int32_t *>(small + 32);
+    return refine_classic_device(n, nrhs, A, lda, (const float *)LU, ldlu, B, ldb, X, ldx, g, U,
+                                 V, winv, sync, R, scratch, anorm, berr, tol, max_iter, words,
+                                 iters_cap, f64, s);
+  }
   if (solver == RBT_IR_GMRES)
     rc = refine_gmres(n, nrhs, A, lda, (const float *)LU, ldlu, B, ldb, X, ldx, g, U, V, winv,
                       sync, R, scratch, at<double>(work, L.o_krylov), anorm, berr, tol, max_iter,
@@ -1214,6 +1264,15 @@ extern "C" int rbt_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t
   if (n > 0 && work == nullptr) return -20;
   hipStream_t s = S(stream);
   int it = 0;
+  if (options().capturable) {
+    if (solver != RBT_IR_CLASSIC || nrhs > kSkinnyMax) return RBT_ERR_UNSUPPORTED;
+    const Layout L = layout(n, nrhs, depth, true, prec == RBT_BF16);
+    if (work_bytes < L.total) return RBT_ERR_WORKSPACE;
+    int32_t *words = reinterpret_cast<int32_t *>(at<double>(work, L.o_small) + 32);
+    return mixed_impl(n, nrhs, A, lda, LU, ldlu, B, ldb, X, ldx, depth, seed, prec, solver, tol,
+                      max_iter, berr_dev, info_dev, work, work_bytes, s, &it, nullptr,
+                      iters_dev ? iters_dev : words + 1);
+  }
   rc = mixed_impl(n, nrhs, A, lda, LU, ldlu, B, ldb, X, ldx, depth, seed, prec, solver, tol,
                   max_iter, berr_dev, info_dev, work, work_bytes, s, &it, nullptr);
   if (rc) return rc;
@@ -1705,6 +1764,10 @@ extern "C" int rbt_set_option(int option, int64_t value) {
       if (value != 1 && value != 2) return -2;
       options().sides = value;
       return 0;
+    case RBT_OPT_CAPTURABLE:
+      if (value != 0 && value != 1) return -2;
+      options().capturable = value;
+      return 0;
     default:
       return -1;
   }
@@ -1722,6 +1785,7 @@ extern "C" int64_t rbt_get_option(int option) {
     case RBT_OPT_GRANULE: return options().granule;
     case RBT_OPT_BUTTERFLY: return options().kind;
     case RBT_OPT_SIDES: return options().sides;
+    case RBT_OPT_CAPTURABLE: return options().capturable;
     default: return -1;
   }
 }

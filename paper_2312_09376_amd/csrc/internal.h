@@ -25,6 +25,28 @@ void report_hip_error(hipError_t e, const char *what, const char *file, int line
 // Block size of the elimination (diagonal blocks, panel width).
 constexpr int kNB = 128;
 
+// Refinement gate of the capturable refinement: while a RefineGate is alive
+// on the calling thread, the launchers of the kernels of one refinement step
+// (residual and backward error, one-sided transforms, persistent sweeps,
+// the update of X) pass its device word to those kernels, which return at
+// once when the word is nonzero. The word is set on the device when the
+// backward error has reached tol, so the remaining steps of a fixed count of
+// enqueued steps do nothing and no host test is needed between steps.
+const int32_t *refine_gate();
+struct RefineGate {
+  explicit RefineGate(const int32_t *gate);
+  ~RefineGate();
+  const int32_t *prev;
+};
+__device__ __forceinline__ bool gated(const int32_t *gate) {
+  return gate != nullptr && __hip_atomic_load(gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+// One step of the device-side convergence test: if *gate is 0, set it to
+// (*berr <= tol) and, when the error is still above tol, count the
+// correction that follows in *iters.
+hipError_t launch_refine_step(const double *berr, double tol, int32_t *gate, int32_t *iters,
+                              hipStream_t s);
+
 // Butterfly geometry: reference size m = 2^d g ceil(n / (2^d g)) for the
 // granule g (1: the non-tiled size of Sec. 3; a tile size n_b: the tiled
 // size; lcm(p, q) n_b: the communication-free size of Eq. 8), q = m / 2^d.

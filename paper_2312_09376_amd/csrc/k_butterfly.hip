@@ -71,7 +71,9 @@ __global__ void __launch_bounds__(256) k_transform2(const TI *__restrict__ A, in
 template <int P, int OP>
 __global__ void __launch_bounds__(256) k_transform_vec(double *__restrict__ B, int64_t ldb,
                                                        int64_t nrhs,
-                                                       const double *__restrict__ C, Pass ps) {
+                                                       const double *__restrict__ C, Pass ps,
+                                                       const int32_t *gate) {
+  if (gated(gate)) return;
   const int64_t gr = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (gr >= ps.ngroups) return;
   const int64_t rb = group_base(ps, gr);
@@ -105,9 +107,9 @@ hipError_t launch_pass_vec(const Pass &ps, double *B, int64_t ldb, int64_t nrhs,
   const int P = ps.hi - ps.lo + 1;
   dim3 grid(unsigned((ps.ngroups + 255) / 256), unsigned(nrhs < 65535 ? nrhs : 65535));
   switch (P) {
-    case 1: hipLaunchKernelGGL((k_transform_vec<1, OP>), grid, dim3(256), 0, s, B, ldb, nrhs, C, ps); break;
-    case 2: hipLaunchKernelGGL((k_transform_vec<2, OP>), grid, dim3(256), 0, s, B, ldb, nrhs, C, ps); break;
-    default: hipLaunchKernelGGL((k_transform_vec<3, OP>), grid, dim3(256), 0, s, B, ldb, nrhs, C, ps); break;
+    case 1: hipLaunchKernelGGL((k_transform_vec<1, OP>), grid, dim3(256), 0, s, B, ldb, nrhs, C, ps, refine_gate()); break;
+    case 2: hipLaunchKernelGGL((k_transform_vec<2, OP>), grid, dim3(256), 0, s, B, ldb, nrhs, C, ps, refine_gate()); break;
+    default: hipLaunchKernelGGL((k_transform_vec<3, OP>), grid, dim3(256), 0, s, B, ldb, nrhs, C, ps, refine_gate()); break;
   }
   return hipGetLastError();
 }

@@ -25,7 +25,9 @@ __global__ void __launch_bounds__(kRows) k_gemv_partial(int64_t M, int N, int64_
                                                         const double *__restrict__ X,
                                                         int64_t ldx,
                                                         double *__restrict__ partial,
-                                                        double *__restrict__ abspart) {
+                                                        double *__restrict__ abspart,
+                                                        const int32_t *gate) {
+  if (gated(gate)) return;
   __shared__ double xs[kChunk][NMAX];
   const int64_t c = blockIdx.y;
   const int64_t k0 = c * kChunk;
@@ -92,7 +94,8 @@ __global__ void __launch_bounds__(kRows) k_resid_reduce(
     int64_t M, int N, int64_t chunks, const double *__restrict__ partial,
     const double *__restrict__ abspart, const double *__restrict__ Bm, int64_t ldb,
     const double *__restrict__ X, int64_t ldx, double *__restrict__ R, int64_t ldr,
-    double *__restrict__ blockstat) {
+    double *__restrict__ blockstat, const int32_t *gate) {
+  if (gated(gate)) return;
   __shared__ double sh[kRows];
   const int64_t m = int64_t(blockIdx.x) * kRows + threadIdx.x;
   const bool ok = m < M;
@@ -130,7 +133,9 @@ template <int NMAX, bool ABS>
 __global__ void __launch_bounds__(kRows) k_berr_blocks(int64_t nblk, int N,
                                                        const double *__restrict__ blockstat,
                                                        double *__restrict__ anorm,
-                                                       double *__restrict__ berr) {
+                                                       double *__restrict__ berr,
+                                                       const int32_t *gate) {
+  if (gated(gate)) return;
   __shared__ double sh[kRows];
   const int stride = 3 * NMAX + 1;
   double a;
@@ -236,7 +241,9 @@ __global__ void k_berr_final(int64_t nrhs, const double *__restrict__ colstat,
 
 __global__ void __launch_bounds__(kRows) k_axpy_cols(int64_t n, int64_t nrhs,
                                                     const double *__restrict__ D, int64_t ldd,
-                                                    double *__restrict__ X, int64_t ldx) {
+                                                    double *__restrict__ X, int64_t ldx,
+                                                    const int32_t *gate) {
+  if (gated(gate)) return;
   const int64_t i = int64_t(blockIdx.x) * kRows + threadIdx.x;
   if (i >= n) return;
   for (int64_t c = blockIdx.y; c < nrhs; c += gridDim.y) X[i + c * ldx] += D[i + c * ldd];
@@ -250,37 +257,48 @@ __global__ void __launch_bounds__(kRows) k_copy_cols(int64_t n, int64_t nrhs,
   for (int64_t c = blockIdx.y; c < nrhs; c += gridDim.y) D[i + c * ldd] = S[i + c * lds];
 }
 
-// dA = -L X^T (n x n, rank nrhs): lanes along rows of dA, so every store is
-// a coalesced column run; the kernel is bound by the n^2 writes.
+// dA = -L X^T (n x n, rank nrhs), bound by the n^2 writes: a lane owns two
+// consecutive rows of 16 columns, so every store instruction writes 1 KB of
+// one column per wavefront (16-byte stores; the operands are only 8-byte
+// aligned in general, which these stores accept), and the stores are
+// non-temporal (dA is written once and not read back here, so it should not
+// displace cached data). The X entries of a column chunk are the same for
+// every lane (scalar loads). Each element sums l_k x_k in the order
+// k = 0..nrhs-1.
+typedef double d2s __attribute__((ext_vector_type(2), aligned(8)));
 __global__ void __launch_bounds__(kRows) k_neg_outer(int64_t n, int64_t nrhs,
                                                     const double *__restrict__ Lm, int64_t ldl,
                                                     const double *__restrict__ X, int64_t ldx,
                                                     double *__restrict__ dA, int64_t ldda) {
-  const int64_t i = int64_t(blockIdx.x) * kRows + threadIdx.x;
+  const int64_t i = (int64_t(blockIdx.x) * kRows + threadIdx.x) * 2;
   if (i >= n) return;
-  constexpr int KC = 16;
+  const bool pair = i + 1 < n;
   for (int64_t j0 = int64_t(blockIdx.y) * 16; j0 < n; j0 += int64_t(gridDim.y) * 16) {
-    double acc[16];
+    double a0[16], a1[16];
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
-    for (int64_t k0 = 0; k0 < nrhs; k0 += KC) {
+    for (int jj = 0; jj < 16; ++jj) a0[jj] = a1[jj] = 0.0;
+    for (int64_t k = 0; k < nrhs; ++k) {
+      const double l0 = Lm[i + k * ldl];
+      const double l1 = pair ? Lm[i + 1 + k * ldl] : 0.0;
 #pragma unroll
-      for (int kk = 0; kk < KC; ++kk) {
-        const int64_t k = k0 + kk;
-        if (k < nrhs) {
-          const double l = Lm[i + k * ldl];
-#pragma unroll
-          for (int jj = 0; jj < 16; ++jj) {
-            const int64_t j = j0 + jj;
-            acc[jj] += (j < n) ? l * X[j + k * ldx] : 0.0;
-          }
-        }
+      for (int jj = 0; jj < 16; ++jj) {
+        const int64_t j = j0 + jj;
+        const double x = (j < n) ? X[j + k * ldx] : 0.0;
+        a0[jj] += l0 * x;
+        a1[jj] += l1 * x;
       }
     }
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
       const int64_t j = j0 + jj;
-      if (j < n) dA[i + j * ldda] = -acc[jj];
+      if (j >= n) break;
+      double *p = dA + i + j * ldda;
+      if (pair) {
+        const d2s v = {-a0[jj], -a1[jj]};
+        __builtin_nontemporal_store(v, reinterpret_cast<d2s *>(p));
+      } else {
+        __builtin_nontemporal_store(-a0[jj], p);
+      }
     }
   }
 }
@@ -387,6 +405,15 @@ __global__ void __launch_bounds__(kRows) k_gemvT_sub(int64_t n, int N, const dou
   }
 }
 
+__global__ void k_refine_step(const double *__restrict__ berr, double tol, int32_t *gate,
+                              int32_t *iters) {
+  if (threadIdx.x != 0 || *gate != 0) return;
+  if (*berr <= tol)  // a NaN error never stops the steps
+    *gate = 1;
+  else
+    *iters += 1;
+}
+
 __global__ void k_fill_i32(int32_t *p, int32_t v) {
   if (threadIdx.x == 0) p[0] = v;
 }
@@ -469,13 +496,13 @@ hipError_t resid_t(int64_t n, int N, const double *A, int64_t lda, const double 
   const int64_t nblk = (n + kRows - 1) / kRows;
   const dim3 g2 = dim3(unsigned(nblk), unsigned(chunks));
   if (with_anorm) {
-    hipLaunchKernelGGL((k_gemv_partial<NMAX, true>), g2, dim3(kRows), 0, s, n, N, n, A, lda, X, ldx, partial, abspart);
-    hipLaunchKernelGGL((k_resid_reduce<NMAX, true>), dim3(unsigned(nblk)), dim3(kRows), 0, s, n, N, chunks, partial, abspart, B, ldb, X, ldx, R, ldr, blockstat);
-    hipLaunchKernelGGL((k_berr_blocks<NMAX, true>), dim3(1), dim3(kRows), 0, s, nblk, N, blockstat, anorm, berr);
+    hipLaunchKernelGGL((k_gemv_partial<NMAX, true>), g2, dim3(kRows), 0, s, n, N, n, A, lda, X, ldx, partial, abspart, refine_gate());
+    hipLaunchKernelGGL((k_resid_reduce<NMAX, true>), dim3(unsigned(nblk)), dim3(kRows), 0, s, n, N, chunks, partial, abspart, B, ldb, X, ldx, R, ldr, blockstat, refine_gate());
+    hipLaunchKernelGGL((k_berr_blocks<NMAX, true>), dim3(1), dim3(kRows), 0, s, nblk, N, blockstat, anorm, berr, refine_gate());
   } else {
-    hipLaunchKernelGGL((k_gemv_partial<NMAX, false>), g2, dim3(kRows), 0, s, n, N, n, A, lda, X, ldx, partial, abspart);
-    hipLaunchKernelGGL((k_resid_reduce<NMAX, false>), dim3(unsigned(nblk)), dim3(kRows), 0, s, n, N, chunks, partial, abspart, B, ldb, X, ldx, R, ldr, blockstat);
-    hipLaunchKernelGGL((k_berr_blocks<NMAX, false>), dim3(1), dim3(kRows), 0, s, nblk, N, blockstat, anorm, berr);
+    hipLaunchKernelGGL((k_gemv_partial<NMAX, false>), g2, dim3(kRows), 0, s, n, N, n, A, lda, X, ldx, partial, abspart, refine_gate());
+    hipLaunchKernelGGL((k_resid_reduce<NMAX, false>), dim3(unsigned(nblk)), dim3(kRows), 0, s, n, N, chunks, partial, abspart, B, ldb, X, ldx, R, ldr, blockstat, refine_gate());
+    hipLaunchKernelGGL((k_berr_blocks<NMAX, false>), dim3(1), dim3(kRows), 0, s, nblk, N, blockstat, anorm, berr, refine_gate());
   }
   return hipGetLastError();
 }
@@ -532,7 +559,7 @@ hipError_t launch_residual_berr(int64_t n, int64_t nrhs, const double *A, int64_
 hipError_t launch_axpy_cols(int64_t n, int64_t nrhs, const double *D, int64_t ldd, double *X,
                             int64_t ldx, hipStream_t s) {
   if (n == 0 || nrhs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_axpy_cols, col_grid(n, nrhs), dim3(kRows), 0, s, n, nrhs, D, ldd, X, ldx);
+  hipLaunchKernelGGL(k_axpy_cols, col_grid(n, nrhs), dim3(kRows), 0, s, n, nrhs, D, ldd, X, ldx, refine_gate());
   return hipGetLastError();
 }
 
@@ -548,8 +575,22 @@ hipError_t launch_neg_outer(int64_t n, int64_t nrhs, const double *Lm, int64_t l
                             hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int64_t cols = (n + 15) / 16;
-  const dim3 grid(unsigned((n + kRows - 1) / kRows), unsigned(cols < 1024 ? cols : 1024));
+  const int64_t rows2 = (n + 1) / 2;  // two rows per lane
+  const dim3 grid(unsigned((rows2 + kRows - 1) / kRows), unsigned(cols < 1024 ? cols : 1024));
   hipLaunchKernelGGL(k_neg_outer, grid, dim3(kRows), 0, s, n, nrhs, Lm, ldl, X, ldx, dA, ldda);
+  return hipGetLastError();
+}
+
+namespace {
+thread_local const int32_t *t_gate = nullptr;
+}
+const int32_t *refine_gate() { return t_gate; }
+RefineGate::RefineGate(const int32_t *gate) : prev(t_gate) { t_gate = gate; }
+RefineGate::~RefineGate() { t_gate = prev; }
+
+hipError_t launch_refine_step(const double *berr, double tol, int32_t *gate, int32_t *iters,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_step, dim3(1), dim3(64), 0, s, berr, tol, gate, iters);
   return hipGetLastError();
 }
 
@@ -574,7 +615,7 @@ hipError_t launch_matvec(int64_t n, int64_t nrhs, const double *A, int64_t lda, 
   double *partial = scratch;
 #define RBT_MATVEC(NM)                                                                          \
   hipLaunchKernelGGL((k_gemv_partial<NM, false>), g2, dim3(kRows), 0, s, n, N, n, A, lda, X,   \
-                     ldx, partial, (double *)nullptr);                                          \
+                     ldx, partial, (double *)nullptr, refine_gate());                                          \
   hipLaunchKernelGGL((k_gemv_sum<NM>), dim3(unsigned(nblk)), dim3(kRows), 0, s, n, N, chunks,   \
                      partial, Y, ldy);
   if (N <= 1) {

@@ -5,8 +5,8 @@
 // Each workgroup takes a ticket (atomic counter) and handles the block row
 // of that rank in sweep order: it accumulates op(A)[b, j] x_j over the
 // blocks j solved before it, then solves its diagonal block with the
-// precomputed inverse (x = Di r; for FP64 factors one more step,
-// x += Di (r - T x), keeps the backward error of substitution) and
+// precomputed inverse (x = Di r; for FP64 factors and FP32 arithmetic one
+// more step, x += Di (r - T x), keeps the backward error of substitution) and
 // publishes x_b. Blocks are published strictly in ticket order, so one
 // counter `done` (= number of published blocks) replaces per-block flags: a
 // workgroup that needs block s waits until done > s, then consumes every
@@ -70,7 +70,10 @@ template <int NMAX, TriMode MODE, typename TF, bool REFINE, typename C>
 __global__ void __launch_bounds__(TPB)
     k_sweep(int64_t n, int N, const TF *__restrict__ A, int64_t ld,
             const C *__restrict__ Winv, double *B, int64_t ldb, int32_t *sync, int64_t nb,
-            int64_t spin_limit) {
+            int64_t spin_limit, const int32_t *gate) {
+  // (the gate is read before any ticket is taken: every workgroup of a gated
+  // launch returns here)
+  if (gated(gate)) return;
   constexpr bool FWD = (MODE == TriMode::LN || MODE == TriMode::UT);
   constexpr bool UNIT = (MODE == TriMode::LN || MODE == TriMode::LT);
   __shared__ C xs[kNB][NMAX];
@@ -322,15 +325,17 @@ __global__ void k_zero_i32(int32_t *p, int64_t count) {
 template <int NMAX, TriMode MODE, typename TF, typename C>
 hipError_t sweep_t(int64_t n, int N, const TF *LU, int64_t ld, const C *Winv, double *B,
                    int64_t ldb, int32_t *sync, hipStream_t s) {
-  // FP64 factors take one refinement step per diagonal block
-  constexpr bool REFINE = std::is_same<TF, double>::value;
+  // one refinement step per diagonal block for FP64 factors and for FP32
+  // arithmetic (a product with an explicit FP32 inverse alone is accurate to
+  // kappa(block) u32 only); FP64 arithmetic on FP32 factors needs none
+  constexpr bool REFINE = std::is_same<TF, double>::value || std::is_same<C, float>::value;
   const int64_t nb = (n + kNB - 1) / kNB;
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
   // ticket, published-blocks counter and the legacy per-launch word; the
   // sticky error word sync[3] is left alone
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, sync, int64_t(3));
   hipLaunchKernelGGL((k_sweep<NMAX, MODE, TF, REFINE, C>), dim3(unsigned(nb)), dim3(TPB), 0, s, n,
-                     N, LU, ld, Winv, B, ldb, sync, nb, sweep_spin_limit());
+                     N, LU, ld, Winv, B, ldb, sync, nb, sweep_spin_limit(), refine_gate());
   return hipGetLastError();
 }
 
