@@ -228,9 +228,10 @@ hipError_t gemm_sub2(int64_t K, int64_t ld, int64_t M0, int64_t N0, const float 
 // block row; then the trailing matrix is updated by one GEMM of depth W,
 // which keeps the GEMM's read-modify-write of A22 well under the HBM
 // bandwidth at matrix-core rate.
-// T = double: FP64 throughout. T = float (mixed precision): FP32 storage;
-// diagonal blocks and triangular solves computed in FP64 and rounded on
-// store; GEMM updates with FP32 (prec RBT_FP32) or BF16 (RBT_BF16) operands.
+// T = double: FP64 throughout. T = float (mixed precision): FP32 storage
+// and FP32 arithmetic (diagonal blocks, triangular solves, GEMM updates with
+// FP32 (prec RBT_FP32) or BF16 (RBT_BF16) operands), unless the FP64-inner
+// option asks for FP64 diagonal blocks and solves.
 // Second stream of the elimination's lookahead, one per device, created on
 // first use (default priority, non-blocking) and kept until the process
 // ends.

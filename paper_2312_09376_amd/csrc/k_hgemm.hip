@@ -10,7 +10,7 @@
 // 2 bytes per element instead of the 4 that every tile would otherwise fetch
 // and convert. The GEMM then runs 256 x 256 tiles with 8 wavefronts (2 x 4,
 // 128 x 64 each = 8 x 4 tiles of v_mfma_f32_16x16x32_bf16), K staged through
-// LDS in slices of 64 with a register-prefetched double buffer. Per slice a
+// LDS in slices of 64, double-buffered, loads two slices ahead. Per slice a
 // workgroup reads 64 KB for 8.4 MFLOP: four times the arithmetic intensity
 // of the 128 x 128 FP32-operand tile.
 //
@@ -128,13 +128,19 @@ __global__ void __launch_bounds__(512, 1)
     }
   };
 
+  // slice s is multiplied from LDS buffer s % 2 while slice s + 1 goes from
+  // registers into the other buffer (free since the barrier that ended slice
+  // s - 1) and the loads of slice s + 2 are in flight
   load(0);
   store(0);
+  if (HK < K) load(HK);
   __syncthreads();
   int cur = 0;
   for (int64_t k0 = 0; k0 < K; k0 += HK) {
-    const bool has_next = k0 + HK < K;
-    if (has_next) load(k0 + HK);
+    if (k0 + HK < K) {
+      store(cur ^ 1);
+      if (k0 + 2 * HK < K) load(k0 + 2 * HK);
+    }
 #pragma unroll
     for (int kk = 0; kk < HK / 32; ++kk) {
       bf8 a[8], b[4];
@@ -152,7 +158,6 @@ __global__ void __launch_bounds__(512, 1)
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (has_next) store(cur ^ 1);
     __syncthreads();
     cur ^= 1;
   }

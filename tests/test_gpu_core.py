@@ -311,9 +311,9 @@ def test_backward_error_kernel(rbt):
 
 @pytest.mark.parametrize("n,W", [(3000, 1024), (1000, 256), (2200, 512)])
 def test_lookahead_factors_identical(rbt, n, W):
-    """The lookahead only reorders launches over disjoint columns: FP64 and
-    FP32 factors are bit-identical with it on and off, and the mixed solve
-    gives the same solution."""
+    """The lookahead only reorders launches over disjoint columns on two
+    streams: FP64, FP32 and BF16-update factors are bit-identical with it on
+    and off, and the mixed solves give the same solution."""
     A = workloads.shifted(n, seed=n)
     old_w = rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)
     rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, W)
@@ -325,12 +325,15 @@ def test_lookahead_factors_identical(rbt, n, W):
             B = workloads.randn(n, 2, seed=1)
             X, LU32, _, _, _, _ = rbt.solve_mixed(dev(A), dev(B), 2, 2023, prec=rbt.RBT_FP32,
                                                   max_iter=5)
+            Xh, LU16, _, _, _, _ = rbt.solve_mixed(dev(A), dev(B), 2, 2023, prec=rbt.RBT_BF16,
+                                                   max_iter=20)
             torch.cuda.synchronize()
-            out[la] = (host(LU), host(LU32), host(X), int(info.item()))
+            out[la] = (host(LU), host(LU32), host(X), int(info.item()), host(LU16),
+                             host(Xh))
         for a, b in zip(out[0], out[1]):
             assert np.array_equal(a, b)
-        Lm = np.tril(out[1][0], -1) + np.eye(n)
-        res = np.abs(Lm @ np.triu(out[1][0]) - A).max() / np.abs(A).max()
+        Lm = np.tril(out[0][0], -1) + np.eye(n)
+        res = np.abs(Lm @ np.triu(out[0][0]) - A).max() / np.abs(A).max()
         assert res <= 50 * n * EPS
     finally:
         rbt.set_option(rbt._lib.RBT_OPT_LOOKAHEAD, 0)
