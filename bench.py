@@ -31,10 +31,24 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 # runs (rocprofv3 --pmc) scaled by what the same counters read for a plain copy
 # of known size (FETCH x 2.000, WRITE x 1.000). Valid only for the kernel
 # source and the workload they were taken on: reported as null otherwise.
-TRAILING_TRAFFIC = {"source": "paper_2312_09376_amd/csrc/k_gemm.hip",
-                    "sha256": "cd064f89968f0e242177948f6fad7a7d0a8deea95567454ad17bee080fbabd6a",
-                    "n": 20000, "nrhs": 1, "depth": 2, "outer_nb": 1024,
-                    "bytes_per_launch": 5.474e9}
+# HBM bytes per launch of a benchmark's dominant kernel, from rocprofv3 counter
+# runs (FETCH_SIZE x 2 + WRITE_SIZE x 1 in KiB, scaled by a plain copy of known
+# size): valid only while the kernel's source is the one the counters were taken
+# with, and for the configuration they were taken on.
+KERNEL_TRAFFIC = {
+    "fp64": {"source": "paper_2312_09376_amd/csrc/k_gemm.hip",
+             "sha256": "cd064f89968f0e242177948f6fad7a7d0a8deea95567454ad17bee080fbabd6a",
+             "config": {"n": 20000, "nrhs": 1, "depth": 2, "outer_nb": 1024},
+             "bytes_per_launch": 5.474e9},
+    "bf16": {"source": "paper_2312_09376_amd/csrc/k_hgemm.hip",
+             "sha256": "a2e326c4190c3373b06045510896c621b5b597abc03e3147a85aefe0e7c2de42",
+             "config": {"n": 32768, "nrhs": 1, "depth": 2, "outer_nb": 1024, "matrix": "dominant"},
+             "bytes_per_launch": (2 * 1404887.8 + 1466817.7) * 1024},
+    "batched_fp32": {"source": "paper_2312_09376_amd/csrc/k_batched.hip",
+                     "sha256": "2fe1aba6dca853b8cdfd8d736bb339f19e71ad44b91d5cec404a16e795ca8bea",
+                     "config": {"batch": 2048, "depth": 2, "matrix": "randn"},
+                     "bytes_per_launch": (2 * 189180403.3 + 92088656.0) * 1024},
+}
 
 
 def trailing_shapes(n, W, remainder=True):
@@ -62,7 +76,7 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=10)
     ap.add_argument("--no-gepp", action="store_true", help="skip the GEPP comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-panels", type=int, default=2,
+    ap.add_argument("--cpu-panels", type=int, default=4,
                     help="oracle sample: panels (of 256 columns) of the benchmarked elimination")
     ap.add_argument("--lookahead", type=int, default=-1, help="0/1 (-1: library default)")
     ap.add_argument("--outer-nb", type=int, default=0,
@@ -136,16 +150,17 @@ def copy_mode(args):
         "cpu_baseline": None}), flush=True)
 
 
-def measured_traffic(n, nrhs, depth, outer_nb):
+def measured_traffic(key, **config):
     import hashlib
-    t = TRAILING_TRAFFIC
+    t = KERNEL_TRAFFIC.get(key)
+    if t is None:
+        return None
     try:
         with open(os.path.join(ROOT, t["source"]), "rb") as f:
             digest = hashlib.sha256(f.read()).hexdigest()
     except OSError:
         return None
-    if digest != t["sha256"] or (n, nrhs, depth, outer_nb) != (t["n"], t["nrhs"], t["depth"],
-                                                                t["outer_nb"]):
+    if digest != t["sha256"] or any(config.get(k) != v for k, v in t["config"].items()):
         return None
     return t["bytes_per_launch"]
 
@@ -209,6 +224,10 @@ def mixed_mode(args):
     peak = PEAK_FP32_MFMA_TFLOPS if args.prec == "fp32" else PEAK_BF16_MFMA_TFLOPS
     gemm_tflops = tr_work / (tr_ms * 1e-3) / 1e12 if tr_ms > 0 else 0.0
     W = rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)
+    # BF16 updates run the staged k_hgemm (the trailing stage then also holds
+    # its two operand conversions); the guarded solve may add FP64 updates
+    staged = (args.prec == "bf16" and not args.guarded
+              and rbt.get_option(rbt._lib.RBT_OPT_BF16_STAGED) == 1)
     tr_bytes = sum(8.0 * rc * rc + 8.0 * rc * w for rc, w in
                    trailing_shapes(n, W, args.prec != "bf16")) * args.steps
     out = {
@@ -224,9 +243,12 @@ def mixed_mode(args):
                    "n": n, "nrhs": k, "depth": d, "outer_nb": W, "matrix": args.matrix,
                    "lookahead": rbt.get_option(rbt._lib.RBT_OPT_LOOKAHEAD)},
         "roofline": {"bound": "mfma",
-                     "kernel": f"trailing-update GEMM (k_sgemm, {args.prec.upper()} MFMA)",
+                     "kernel": ("trailing-update GEMM (k_hgemm and its operand staging, BF16 MFMA)"
+                                if staged else f"trailing-update GEMM (k_sgemm, {args.prec.upper()} MFMA)"),
                      "achieved": round(gemm_tflops, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(gemm_tflops / peak, 4), "traffic": None,
+                     "frac": round(gemm_tflops / peak, 4),
+                     "traffic": (measured_traffic("bf16", n=n, nrhs=k, depth=d, outer_nb=W,
+                                                  matrix=args.matrix) if staged else None),
                      "algorithmic_bytes_per_launch": tr_bytes / max(tr_cnt, 1),
                      "launches": tr_cnt, "avg_launch_ms": round(tr_ms / max(tr_cnt, 1), 4),
                      "flops_per_launch": tr_work / max(tr_cnt, 1)},
@@ -243,13 +265,14 @@ def mixed_mode(args):
         out["ir_steps"] = [int(i.item()) for i in iters]
         out["info"] = int(info.item())
     if not args.no_gepp:
-        out["gepp"] = gepp_comparator(A, B, flops, ms_step)
+        out["gepp"] = gepp_comparator(A, B, flops, ms_step, X=X)
     print(json.dumps(out), flush=True)
 
 
-def gepp_comparator(A, B, flops, ms_step, reps=2):
+def gepp_comparator(A, B, flops, ms_step, reps=2, X=None):
     """FP64 partial-pivoting solve of the same system on the same GPU (torch ->
-    rocSOLVER getrf/getrs) and its Eq. 7 backward error."""
+    rocSOLVER getrf/getrs) and its Eq. 7 backward error; with X (this
+    library's solution), also max|X - X_gepp| / max|X_gepp|."""
     import torch
     from paper_2312_09376_amd import rbt
     Xg = torch.linalg.solve(A, B)
@@ -260,9 +283,12 @@ def gepp_comparator(A, B, flops, ms_step, reps=2):
     torch.cuda.synchronize()
     g_ms = (time.perf_counter() - g0) * 1e3 / reps
     gb = float(rbt.backward_error(A, Xg.t().contiguous().t(), B).item())
-    return {"solver": "torch.linalg.solve FP64 (partial pivoting)", "ms": round(g_ms, 3),
-            "TFLOP/s": round(flops / (g_ms * 1e-3) / 1e12, 4), "berr": gb,
-            "speedup_rbt": round(g_ms / ms_step, 3)}
+    out = {"solver": "torch.linalg.solve FP64 (partial pivoting)", "ms": round(g_ms, 3),
+           "TFLOP/s": round(flops / (g_ms * 1e-3) / 1e12, 4), "berr": gb,
+           "speedup_rbt": round(g_ms / ms_step, 3)}
+    if X is not None:
+        out["rel_diff_to_rbt_x"] = float(((X - Xg).abs().max() / Xg.abs().max()).item())
+    return out
 
 
 def batched_mode(args):
@@ -350,7 +376,11 @@ def batched_mode(args):
         "systems_per_s": round(args.batch / (ms_step * 1e-3), 1),
         "roofline": {"bound": "mfma", "kernel": "k_batched (persistent, whole method per system)",
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "frac": round(achieved / peak, 4),
+                     "traffic": (measured_traffic("batched_fp32", batch=args.batch, depth=d,
+                                                  matrix=args.matrix)
+                                 if args.prec == "fp32" and not args.batch_n and not args.batch_nrhs
+                                 else None),
                      "avg_launch_ms": round(ms_gpu, 4), "flops_per_launch": flops},
         "converged": converged, "max_iters": int(iters.max()), "mean_iters": float(iters.mean()),
         "max_berr_over_tol": float(np.max(berr / tols)), "zero_pivots": int(np.sum(info != 0)),
@@ -477,7 +507,7 @@ def step_statistics(seconds):
             "min_ms": round(min(ms), 3), "max_ms": round(max(ms), 3)}
 
 
-def cpu_baseline(n, nrhs, depth, seed, panels=2, nb=256):
+def cpu_baseline(n, nrhs, depth, seed, panels=4, nb=256):
     """The oracle, as it stands, on the host cores, on a bounded sample of the
     benchmarked solve: the oracle's blocked elimination over the first
     `panels` panels (width nb) of the benchmarked n x n matrix (same seed).
@@ -702,7 +732,8 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "trailing-update GEMM (k_dgemm, FP64 MFMA)",
                      "achieved": round(gemm_tflops, 3), "peak": PEAK_FP64_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(gemm_tflops / PEAK_FP64_MFMA_TFLOPS, 4),
-                     "traffic": measured_traffic(n, k, d, rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)),
+                     "traffic": measured_traffic("fp64", n=n, nrhs=k, depth=d,
+                                                 outer_nb=rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)),
                      "traffic_unit": "bytes per launch (HBM read + write, counter runs)",
                      "algorithmic_bytes_per_launch": tr_bytes / max(tr_cnt, 1),
                      "launches": tr_cnt,
