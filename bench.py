@@ -99,8 +99,9 @@ def parse():
                     help="batched mode: all systems of this order (0: n ~ U{37..1500})")
     ap.add_argument("--batch-nrhs", type=int, default=0,
                     help="batched mode: all systems with this many right-hand sides (0: U{1..16})")
-    ap.add_argument("--batch-tile-cols", type=int, default=0,
-                    help="batched mode: 64-column tiles per trailing-update round (0: tuned)")
+    ap.add_argument("--batch-tile-cols2-min-n", type=int, default=-1,
+                    help="batched mode: systems with n >= this take two 64-column tiles per "
+                         "trailing-update round, smaller ones one (-1: tuned)")
     ap.add_argument("--batch-wgs", type=int, default=0,
                     help="batched mode: persistent workgroups per CU (0: tuned)")
     ap.add_argument("--tol-scale", type=float, default=10.0,
@@ -316,9 +317,10 @@ def batched_mode(args):
             A = workloads.device_randn(int(n), int(n), workloads.MATRIX_SEED + s_)
         As.append(A)
         Bs.append(workloads.device_randn(int(n), int(k), workloads.RHS_SEED + s_))
-    tuned = not (args.batch_tile_cols or args.batch_wgs)  # explicit shape overrides the table
-    if args.batch_tile_cols:
-        rbt.set_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS, args.batch_tile_cols)
+    # an explicit shape overrides the tuned table
+    tuned = args.batch_tile_cols2_min_n < 0 and not args.batch_wgs
+    if args.batch_tile_cols2_min_n >= 0:
+        rbt.set_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS2_MIN_N, args.batch_tile_cols2_min_n)
     if args.batch_wgs:
         rbt.set_option(rbt._lib.RBT_OPT_BATCH_WGS_PER_CU, args.batch_wgs)
     plan = rbt.batched_plan(ns, ks, d, prec)
@@ -371,7 +373,7 @@ def batched_mode(args):
                                f"launch replayed from a HIP graph",
                    "batch": args.batch, "depth": d, "matrix": args.matrix,
                    "sum_n2": int(np.sum(ns.astype(np.int64) ** 2)), "flops": flops,
-                   "tile_cols": rbt.get_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS),
+                   "tile_cols2_min_n": rbt.get_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS2_MIN_N),
                    "wgs_per_cu": rbt.get_option(rbt._lib.RBT_OPT_BATCH_WGS_PER_CU)},
         "systems_per_s": round(args.batch / (ms_step * 1e-3), 1),
         "roofline": {"bound": "mfma", "kernel": "k_batched (persistent, whole method per system)",

@@ -419,17 +419,22 @@ int rbt_solve_backward_mixed(int64_t n, int64_t nrhs, const float *LU, int64_t l
  *   covers whole 128-blocks. Changes only the order of the roundings, not
  *   the method. */
 #define RBT_OPT_OUTER_NB 1
-/* RBT_OPT_BATCH_TILE_COLS: rbt_solve_batched, 64-column tiles of the
- *   low-precision trailing update per round (1 or 2; default 1): more tiles
- *   per round, fewer barriers, more registers.
+/* RBT_OPT_BATCH_TILE_COLS2_MIN_N: rbt_solve_batched, systems with
+ *   n >= value take two 64-column tiles per round of the low-precision
+ *   trailing update (fewer barriers and restagings of the row tile, more
+ *   registers), smaller systems one (>= 0; default INT64_MAX: one for all).
+ * RBT_OPT_BATCH_TILE_COLS: the same choice for every system (1: value
+ *   INT64_MAX above, 2: value 0); reads 1 or 2, or 0 for a split by n.
  * RBT_OPT_BATCH_WGS_PER_CU: rbt_solve_batched, persistent workgroups per
  *   compute unit (1 or 2; default 2).
- * Both change the schedule only: every system's arithmetic is the same. The
- * package's autotuner times every combination on the device and keeps a
+ * All change the schedule only: every system's arithmetic is the same. The
+ * package's autotuner times the candidates (size thresholds at the bounds
+ * of its n-buckets, workgroups per compute unit) on the device and keeps a
  * table per precision, which its binding applies before each launch; a
  * launch uses the values current when it is enqueued (or captured). */
 #define RBT_OPT_BATCH_TILE_COLS 2
 #define RBT_OPT_BATCH_WGS_PER_CU 3
+#define RBT_OPT_BATCH_TILE_COLS2_MIN_N 12
 /* RBT_OPT_LOOKAHEAD: elimination (rbt_genp and every solve that factors).
  *   1: while the next panel is factored on the caller's stream, the block
  *   row and trailing update of the remaining columns run on a second stream

@@ -76,6 +76,7 @@ RBT_OPT_GRANULE = 8
 RBT_OPT_BUTTERFLY = 9
 RBT_OPT_SIDES = 10
 RBT_OPT_CAPTURABLE = 11
+RBT_OPT_BATCH_TILE_COLS2_MIN_N = 12
 STAGES = ["generate", "transform2", "transform_vec", "diag", "panel", "trailing", "solve",
           "residual", "pivoted", "outer"]
 

@@ -69,7 +69,9 @@ inline int64_t nblocks(int64_t n) { return (n + kNB - 1) / kNB; }
 // Tunable options (rbt_set_option).
 struct Options {
   int64_t outer_nb = 1024;  // width of the panel whose trailing update is one GEMM
-  int64_t batch_tile_cols = 1;  // batched: 64-column tiles per trailing-update round
+  // batched: systems with n >= this take two 64-column tiles per round of
+  // the low-precision trailing update, the others one (INT64_MAX: one for all)
+  int64_t batch_ct2_min_n = INT64_MAX;
   int64_t batch_wgs_per_cu = 2; // batched: persistent workgroups per compute unit
   int64_t lookahead = 0;        // elimination: overlap panels with the trailing update
   int64_t bf16_staged = 1;      // BF16 elimination: staged-operand trailing GEMM
@@ -1605,7 +1607,7 @@ extern "C" int rbt_solve_batched(int64_t batch, const double *const *A, const in
   const int grid = int(batch < cap ? batch : cap);
   RBT_HIP_CHECK(launch_batched(batch, work, work_bytes, A, lda, B, ldb, X, ldx, depth, seed, prec,
                                tol, max_iter, iters_dev, berr_dev, info_dev, path_dev, grid,
-                               int(options().batch_tile_cols), S(stream)));
+                               options().batch_ct2_min_n, S(stream)));
   return 0;
 }
 
@@ -1730,9 +1732,13 @@ extern "C" int rbt_set_option(int option, int64_t value) {
       if (value < kNB || value % kNB != 0 || value > 16 * kNB) return -2;
       options().outer_nb = value;
       return 0;
-    case RBT_OPT_BATCH_TILE_COLS:
+    case RBT_OPT_BATCH_TILE_COLS:  // one tile count for every system
       if (value != 1 && value != 2) return -2;
-      options().batch_tile_cols = value;
+      options().batch_ct2_min_n = value == 2 ? 0 : INT64_MAX;
+      return 0;
+    case RBT_OPT_BATCH_TILE_COLS2_MIN_N:
+      if (value < 0) return -2;
+      options().batch_ct2_min_n = value;
       return 0;
     case RBT_OPT_BATCH_WGS_PER_CU:
       if (value != 1 && value != 2) return -2;
@@ -1777,7 +1783,9 @@ extern "C" int rbt_set_option(int option, int64_t value) {
 extern "C" int64_t rbt_get_option(int option) {
   switch (option) {
     case RBT_OPT_OUTER_NB: return options().outer_nb;
-    case RBT_OPT_BATCH_TILE_COLS: return options().batch_tile_cols;
+    case RBT_OPT_BATCH_TILE_COLS:
+      return options().batch_ct2_min_n == 0 ? 2 : (options().batch_ct2_min_n == INT64_MAX ? 1 : 0);
+    case RBT_OPT_BATCH_TILE_COLS2_MIN_N: return options().batch_ct2_min_n;
     case RBT_OPT_BATCH_WGS_PER_CU: return options().batch_wgs_per_cu;
     case RBT_OPT_LOOKAHEAD: return options().lookahead;
     case RBT_OPT_BF16_STAGED: return options().bf16_staged;

@@ -286,7 +286,7 @@ hipError_t launch_batched(int64_t batch, void *work, size_t work_bytes, const do
                           const int64_t *lda, const double *const *B, const int64_t *ldb,
                           double *const *X, const int64_t *ldx, int depth, uint64_t seed,
                           int prec, double tol, int max_iter, int32_t *iters, double *berr,
-                          int32_t *info, int32_t *path, int grid, int tile_cols,
+                          int32_t *info, int32_t *path, int grid, int64_t ct2_min_n,
                           hipStream_t s);
 // FP64 doubles of one batched system's area (U, V, inverse blocks of 64, residual)
 inline int64_t batched_sys_doubles(int64_t n, int64_t nrhs, int d) {

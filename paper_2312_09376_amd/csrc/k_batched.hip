@@ -103,6 +103,7 @@ struct Args {
   int depth, prec, max_iter;
   int64_t granule;  // reference-size granule of the butterfly structure
   int kind, sides;  // butterfly kind (1: rotations) and sides (1: one-sided)
+  int64_t ct2_min_n;  // systems with n >= this: two 64-column tiles per round
 };
 
 __device__ __forceinline__ double nanmax(double a, double b) {
@@ -1250,7 +1251,7 @@ __device__ __noinline__ void transform_into(const Sys &s, int d) {
   }
 }
 
-template <bool BF16U, int CT>
+template <bool BF16U>
 __device__ void solve_system(const Args &a, const BatchDesc &D, float *fbase, double *dbase,
                              double *f64base, double *L0, double *L1, int *info_sh,
                              double *anorm_sh) {
@@ -1303,8 +1304,10 @@ __device__ void solve_system(const Args &a, const BatchDesc &D, float *fbase, do
       transform_into<float>(s, d);
     else
       transform_into<double>(s, d);
-    if (pass == 0)
-      eliminate<float, BF16U, CT>(s, L0, L1, info_sh);
+    if (pass == 0 && s.n >= a.ct2_min_n)
+      eliminate<float, BF16U, 2>(s, L0, L1, info_sh);
+    else if (pass == 0)
+      eliminate<float, BF16U, 1>(s, L0, L1, info_sh);
     else
       eliminate<double, false>(s, L0, L1, info_sh);
     int it_p = 0;
@@ -1334,7 +1337,7 @@ __device__ void solve_system(const Args &a, const BatchDesc &D, float *fbase, do
   __syncthreads();
 }
 
-template <bool BF16U, int CT>
+template <bool BF16U>
 __global__ void __launch_bounds__(BT, 2) k_batched(Args a) {
   __shared__ __attribute__((aligned(16))) double lds[kR0Doubles + kR1Doubles];
   double *L0 = lds, *L1 = lds + kR0Doubles;
@@ -1374,7 +1377,7 @@ __global__ void __launch_bounds__(BT, 2) k_batched(Args a) {
     // systems without work (n = 0, or no right-hand side) are not solved;
     // the plan queues them last
     if (D.n > 0 && D.nrhs > 0) {
-      solve_system<BF16U, CT>(a, D, fbase, dbase, f64base, L0, L1, &info_sh, &anorm_sh);
+      solve_system<BF16U>(a, D, fbase, dbase, f64base, L0, L1, &info_sh, &anorm_sh);
     } else if (threadIdx.x == 0) {
       if (a.path) a.path[D.sys] = 0;
       if (a.iters) a.iters[D.sys] = 0;
@@ -1394,9 +1397,9 @@ hipError_t launch_batched(int64_t batch, void *work, size_t work_bytes, const do
                           const int64_t *lda, const double *const *B, const int64_t *ldb,
                           double *const *X, const int64_t *ldx, int depth, uint64_t seed,
                           int prec, double tol, int max_iter, int32_t *iters, double *berr,
-                          int32_t *info, int32_t *path, int grid, int tile_cols,
+                          int32_t *info, int32_t *path, int grid, int64_t ct2_min_n,
                           hipStream_t s) {
-  if (tile_cols != 1 && tile_cols != 2) return hipErrorInvalidValue;
+  if (ct2_min_n < 0) return hipErrorInvalidValue;
   Args a;
   a.batch = batch;
   a.work = static_cast<char *>(work);
@@ -1419,19 +1422,13 @@ hipError_t launch_batched(int64_t batch, void *work, size_t work_bytes, const do
   a.granule = butterfly_granule();
   a.kind = butterfly_kind();
   a.sides = butterfly_sides();
+  a.ct2_min_n = ct2_min_n;
   hipLaunchKernelGGL(k_reset_ticket, dim3(1), dim3(64), 0, s, work);
   const dim3 g{unsigned(grid)}, b{unsigned(BT)};
-  if (prec == RBT_BF16) {
-    if (tile_cols == 2)
-      hipLaunchKernelGGL((k_batched<true, 2>), g, b, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_batched<true, 1>), g, b, 0, s, a);
-  } else {
-    if (tile_cols == 2)
-      hipLaunchKernelGGL((k_batched<false, 2>), g, b, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_batched<false, 1>), g, b, 0, s, a);
-  }
+  if (prec == RBT_BF16)
+    hipLaunchKernelGGL((k_batched<true>), g, b, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_batched<false>), g, b, 0, s, a);
   return hipGetLastError();
 }
 

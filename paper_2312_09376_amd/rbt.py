@@ -375,7 +375,7 @@ def solve_batched_launch(plan, args, seed=2023, tol=-10.0, max_iter=30, tuned=Tr
     |tol| n_s eps64 for system s. tuned: apply the autotuned launch shape of
     the plan's precision first (a schedule choice; results are identical)."""
     if tuned and plan.tuned is not None:
-        set_option(_lib.RBT_OPT_BATCH_TILE_COLS, plan.tuned["tile_cols"])
+        set_option(_lib.RBT_OPT_BATCH_TILE_COLS2_MIN_N, plan.tuned["tile_cols2_min_n"])
         set_option(_lib.RBT_OPT_BATCH_WGS_PER_CU, plan.tuned["wgs_per_cu"])
     check(lib().rbt_solve_batched(plan.batch, _p(args.pA), _p(args.lA), _p(args.pB), _p(args.lB),
                                   _p(args.pX), _p(args.lX), plan.depth, seed, plan.prec,

@@ -1,13 +1,18 @@
-"""Autotuner for the batched solver's launch shape.
+"""Autotuner for the batched solver's tile shape and launch shape.
 
 rbt_solve_batched has two schedule parameters (library options):
-  RBT_OPT_BATCH_TILE_COLS   64-column tiles per round of the low-precision
-                            trailing update (1 or 2),
-  RBT_OPT_BATCH_WGS_PER_CU  persistent workgroups per compute unit (1 or 2).
+  RBT_OPT_BATCH_TILE_COLS2_MIN_N  systems with n >= this take two 64-column
+                                  tiles per round of the low-precision
+                                  trailing update, smaller ones one: the
+                                  tile shape per n-bucket,
+  RBT_OPT_BATCH_WGS_PER_CU        persistent workgroups per compute unit (1
+                                  or 2).
 Neither changes any system's arithmetic, so every candidate must reproduce
 the first candidate's solutions, iteration counts and backward errors bit for
-bit; a candidate that does not is rejected. Among the accepted candidates the
-fastest (median of graph replays) wins.
+bit; a candidate that does not is rejected. The candidate thresholds are the
+bounds of the n-buckets (BUCKETS; 0: two tiles for all, NEVER: one for all).
+Among the accepted candidates the fastest (median of graph replays of one
+launch over the whole batch) wins.
 
     python -m paper_2312_09376_amd.tune [--batch 2048] [--prec fp32 bf16]
 
@@ -15,7 +20,7 @@ times every candidate on the GPU for a batch of the requested shape and
 writes the winners to tuned_batched.json beside this file. BatchPlan reads
 that table and solve_batched_launch applies the entry of the plan's
 precision before each launch (without a table the library's defaults hold:
-one tile per round, two workgroups per compute unit)."""
+one tile per round for every system, two workgroups per compute unit)."""
 import argparse
 import json
 import math
@@ -23,33 +28,36 @@ import os
 import statistics
 
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_batched.json")
-CANDIDATES = [{"tile_cols": tc, "wgs_per_cu": w} for tc in (1, 2) for w in (1, 2)]
+NEVER = 2 ** 63 - 1  # threshold above every n: one tile per round for all systems
+BUCKETS = (0, 256, 512, 768, 1024, 1280, NEVER)
+CANDIDATES = [{"tile_cols2_min_n": t, "wgs_per_cu": w} for t in BUCKETS for w in (1, 2)]
 PRECS = ("fp32", "bf16")
 
 
 def select(results):
-    """The fastest accepted candidate. results: dicts with tile_cols,
-    wgs_per_cu, ms and ok. Ties go to the smaller tile count (fewer live
-    registers). Raises ValueError when no candidate was accepted."""
+    """The fastest accepted candidate. results: dicts with tile_cols2_min_n,
+    wgs_per_cu, ms and ok. Ties go to the higher threshold (fewer systems
+    with the two-tile round, which holds more registers), then to more
+    workgroups. Raises ValueError when no candidate was accepted."""
     ok = [r for r in results if r["ok"] and math.isfinite(r["ms"])]
     if not ok:
         raise ValueError("no candidate reproduced the reference outputs")
-    return min(ok, key=lambda r: (r["ms"], r["tile_cols"], -r["wgs_per_cu"]))
+    return min(ok, key=lambda r: (r["ms"], -r["tile_cols2_min_n"], -r["wgs_per_cu"]))
 
 
 def load_table(path=TABLE):
-    """{prec: {"tile_cols": t, "wgs_per_cu": w}} from the table, or {} if
-    there is none."""
+    """{prec: {"tile_cols2_min_n": t, "wgs_per_cu": w}} from the table, or {}
+    if there is none."""
     if not os.path.exists(path):
         return {}
     with open(path) as f:
         data = json.load(f)
     out = {}
     for prec, e in data.get("batched", {}).items():
-        tc, w = int(e["tile_cols"]), int(e["wgs_per_cu"])
-        if prec not in PRECS or tc not in (1, 2) or w not in (1, 2):
+        t, w = int(e["tile_cols2_min_n"]), int(e["wgs_per_cu"])
+        if prec not in PRECS or t < 0 or t > NEVER or w not in (1, 2):
             raise ValueError(f"invalid entry in {path}: {prec}: {e}")
-        out[prec] = {"tile_cols": tc, "wgs_per_cu": w}
+        out[prec] = {"tile_cols2_min_n": t, "wgs_per_cu": w}
     return out
 
 
@@ -70,19 +78,19 @@ def time_candidates(prec, ns, ks, matrix="randn", reps=3, seed=2023, max_iter=10
                     candidates=CANDIDATES, log=print):
     """Time each candidate (graph replays of one launch over the batch) and
     check its outputs against the first candidate's. Returns the result
-    dicts (tile_cols, wgs_per_cu, ms, ok)."""
+    dicts (tile_cols2_min_n, wgs_per_cu, ms, ok)."""
     import torch
     from . import rbt
     p = rbt.RBT_FP32 if prec == "fp32" else rbt.RBT_BF16
     As, Bs = _inputs(ns, ks, matrix)
     plan = rbt.batched_plan(ns, ks, 2, p)
-    saved = (rbt.get_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS),
+    saved = (rbt.get_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS2_MIN_N),
              rbt.get_option(rbt._lib.RBT_OPT_BATCH_WGS_PER_CU))
     ref = None
     results = []
     try:
         for c in candidates:
-            rbt.set_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS, c["tile_cols"])
+            rbt.set_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS2_MIN_N, c["tile_cols2_min_n"])
             rbt.set_option(rbt._lib.RBT_OPT_BATCH_WGS_PER_CU, c["wgs_per_cu"])
             args = rbt.BatchArgs(plan, As, Bs)
             stream = torch.cuda.Stream()
@@ -111,12 +119,12 @@ def time_candidates(prec, ns, ks, matrix="randn", reps=3, seed=2023, max_iter=10
                 ok = (all(torch.equal(a, b) for a, b in zip(out[0], ref[0]))
                       and all(torch.equal(a, b) for a, b in zip(out[1:], ref[1:])))
             r = dict(c, ms=statistics.median(times), ok=bool(ok))
-            log(f"  {prec} tile_cols={c['tile_cols']} wgs_per_cu={c['wgs_per_cu']}: "
+            log(f"  {prec} tile_cols2_min_n={c['tile_cols2_min_n']} wgs_per_cu={c['wgs_per_cu']}: "
                 f"{r['ms']:.3f} ms{'' if ok else ' (outputs differ: rejected)'}")
             results.append(r)
             del graph
     finally:
-        rbt.set_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS, saved[0])
+        rbt.set_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS2_MIN_N, saved[0])
         rbt.set_option(rbt._lib.RBT_OPT_BATCH_WGS_PER_CU, saved[1])
     return results
 
@@ -142,10 +150,10 @@ def main(argv=None):
     for prec in a.prec:
         res = time_candidates(prec, ns, ks, a.matrix, a.reps, max_iter=a.max_iter)
         best = select(res)
-        table["batched"][prec] = {"tile_cols": best["tile_cols"],
+        table["batched"][prec] = {"tile_cols2_min_n": best["tile_cols2_min_n"],
                                   "wgs_per_cu": best["wgs_per_cu"], "ms": round(best["ms"], 3),
                                   "candidates": res}
-        print(f"{prec}: tile_cols={best['tile_cols']} wgs_per_cu={best['wgs_per_cu']} "
+        print(f"{prec}: tile_cols2_min_n={best['tile_cols2_min_n']} wgs_per_cu={best['wgs_per_cu']} "
               f"({best['ms']:.3f} ms)", flush=True)
     with open(a.out, "w") as f:
         json.dump(table, f, indent=1)

@@ -268,7 +268,7 @@ def test_batched_launch_shapes_give_identical_results(rbt):
         plan = rbt.batched_plan(ns, ks, 2, prec)
         ref = None
         for c in tune.CANDIDATES:
-            rbt.set_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS, c["tile_cols"])
+            rbt.set_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS2_MIN_N, c["tile_cols2_min_n"])
             rbt.set_option(rbt._lib.RBT_OPT_BATCH_WGS_PER_CU, c["wgs_per_cu"])
             args = rbt.BatchArgs(plan, As, Bs)
             rbt.solve_batched_launch(plan, args, seed=5, tuned=False)
@@ -278,5 +278,5 @@ def test_batched_launch_shapes_give_identical_results(rbt):
                 ref = out
             else:
                 assert all(np.array_equal(a, b) for a, b in zip(out, ref)), (prec, c)
-    rbt.set_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS, 1)
+    rbt.set_option(rbt._lib.RBT_OPT_BATCH_TILE_COLS2_MIN_N, tune.NEVER)
     rbt.set_option(rbt._lib.RBT_OPT_BATCH_WGS_PER_CU, 2)
