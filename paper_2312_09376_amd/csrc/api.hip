@@ -1484,60 +1484,6 @@ extern "C" int rbt_solve_guarded(int64_t n, int64_t nrhs, const double *A, int64
 namespace rbt {
 namespace {
 
-struct BatchPlanSizes {
-  size_t f_off, d_off, f64_off, total;
-};
-
-// Workspace: header | descriptor table | FP32 factors | FP64 areas; each
-// system's factor and FP64 area start on 256-byte boundaries.
-BatchPlanSizes batch_sizes(int64_t batch, const int64_t *n, const int64_t *nrhs, int depth,
-                           std::vector<BatchDesc> *desc) {
-  BatchPlanSizes z{};
-  z.f_off = align256(kBatchTableOffset + size_t(batch) * sizeof(BatchDesc));
-  size_t f = 0, d = 0, f64 = 0;  // floats, doubles, fallback doubles
-  std::vector<int64_t> order(batch);
-  for (int64_t i = 0; i < batch; ++i) order[i] = i;
-  // largest systems first (longest-processing-time order for the queue);
-  // systems without work (n = 0 or nrhs = 0) last
-  auto work_n = [&](int64_t i) { return nrhs[i] > 0 ? n[i] : int64_t(-1); };
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int64_t a, int64_t b) { return work_n(a) > work_n(b); });
-  if (desc) desc->resize(batch);
-  for (int64_t t = 0; t < batch; ++t) {
-    const int64_t i = order[t];
-    if (desc) {
-      BatchDesc &D = (*desc)[t];
-      D = BatchDesc{};
-      D.sys = i;
-      D.n = n[i];
-      D.nrhs = nrhs[i];
-      D.f_off = int64_t(f);
-      D.d_off = int64_t(d);
-      D.f64_off = int64_t(f64);
-    }
-    f64 += align256(size_t(n[i]) * n[i] * sizeof(double)) / sizeof(double);
-    f += align256(size_t(n[i]) * n[i] * sizeof(float)) / sizeof(float);
-    d += align256(size_t(batched_sys_doubles(n[i], nrhs[i], depth)) * sizeof(double)) /
-         sizeof(double);
-  }
-  z.d_off = align256(z.f_off + f * sizeof(float));
-  z.f64_off = align256(z.d_off + d * sizeof(double));
-  z.total = z.f64_off + f64 * sizeof(double);
-  return z;
-}
-
-int check_batch_sizes(int64_t batch, const int64_t *n, const int64_t *nrhs) {
-  if (batch < 0) return -1;
-  if (batch > 0 && n == nullptr) return -2;
-  if (batch > 0 && nrhs == nullptr) return -3;
-  for (int64_t i = 0; i < batch; ++i) {
-    if (n[i] < 0) return -2;
-    if (nrhs[i] < 0) return -3;
-    if (nrhs[i] > kSkinnyMax) return RBT_ERR_UNSUPPORTED;
-  }
-  return 0;
-}
-
 int device_cus() {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;
@@ -1554,7 +1500,7 @@ extern "C" size_t rbt_batched_workspace_size(int64_t batch, const int64_t *n,
                                              const int64_t *nrhs, int depth, int prec) {
   if (check_batch_sizes(batch, n, nrhs) != 0 || bad_depth(depth)) return 0;
   if (prec != RBT_FP32 && prec != RBT_BF16) return 0;
-  return batch_sizes(batch, n, nrhs, depth, nullptr).total;
+  return batch_plan_sizes(batch, n, nrhs, depth, nullptr).total;
 }
 
 extern "C" int rbt_batched_plan(int64_t batch, const int64_t *n, const int64_t *nrhs, int depth,
@@ -1565,21 +1511,9 @@ extern "C" int rbt_batched_plan(int64_t batch, const int64_t *n, const int64_t *
   if (prec != RBT_FP32 && prec != RBT_BF16) return -5;
   if (work == nullptr) return -6;
   std::vector<BatchDesc> desc;
-  const BatchPlanSizes z = batch_sizes(batch, n, nrhs, depth, &desc);
+  const BatchPlanSizes z = batch_plan_sizes(batch, n, nrhs, depth, &desc);
   if (work_bytes < z.total) return RBT_ERR_WORKSPACE;
-  std::vector<char> host(kBatchTableOffset + desc.size() * sizeof(BatchDesc), 0);
-  BatchHeader h{};
-  h.ticket = 0;
-  h.batch = batch;
-  h.depth = depth;
-  h.prec = prec;
-  h.f_off_bytes = int64_t(z.f_off);
-  h.d_off_bytes = int64_t(z.d_off);
-  h.total_bytes = int64_t(z.total);
-  h.f64_off_bytes = int64_t(z.f64_off);
-  std::memcpy(host.data(), &h, sizeof(h));
-  if (!desc.empty())
-    std::memcpy(host.data() + kBatchTableOffset, desc.data(), desc.size() * sizeof(BatchDesc));
+  const std::vector<char> host = batch_plan_image(batch, depth, prec, z, desc);
   hipStream_t s = S(stream);
   RBT_HIP_CHECK(hipMemcpyAsync(work, host.data(), host.size(), hipMemcpyHostToDevice, s));
   RBT_HIP_CHECK(hipStreamSynchronize(s));

@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "rbt.h"
 
@@ -274,6 +275,23 @@ struct BatchDesc {
   int64_t pad[2];
 };
 constexpr size_t kBatchTableOffset = 256;  // descriptors follow the header
+// Host part of the plan (batch_plan.cpp, no device calls). Workspace:
+// header | descriptor table | FP32 factors | FP64 areas | FP64 fallback
+// factors; each system's areas start on 256-byte boundaries.
+struct BatchPlanSizes {
+  size_t f_off, d_off, f64_off, total;  // byte offsets of the areas; bytes used
+};
+// 0, or the entry points' error code for negative sizes (-2 n, -3 nrhs) or
+// nrhs above kSkinnyMax (RBT_ERR_UNSUPPORTED).
+int check_batch_sizes(int64_t batch, const int64_t *n, const int64_t *nrhs);
+// Layout for checked sizes; with desc, also the queue: largest systems first,
+// systems without work (n = 0 or nrhs = 0) last.
+BatchPlanSizes batch_plan_sizes(int64_t batch, const int64_t *n, const int64_t *nrhs, int depth,
+                                std::vector<BatchDesc> *desc);
+// The bytes rbt_batched_plan copies to the start of the workspace: header
+// (ticket 0) and descriptor table.
+std::vector<char> batch_plan_image(int64_t batch, int depth, int prec, const BatchPlanSizes &z,
+                                   const std::vector<BatchDesc> &desc);
 // BF16-operand trailing update with operands staged once (k_hgemm.hip):
 // C (FP32) -= bf16(L21) bf16(U12); K must be a multiple of 64.
 size_t hgemm_stage_bytes(int64_t M, int64_t N, int64_t K);

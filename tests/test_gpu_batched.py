@@ -173,10 +173,13 @@ def test_batched_tiled_structure(rbt):
         assert relfro(host(X), Xo) <= 10 * np.linalg.cond(A, np.inf) * 10 * n * EPS
 
 
-@pytest.mark.skip(reason="did not finish on the GPU (kernel still running after 120 s) for a batch "
-                         "of one zero-pivot system (n=100, depth 0), one n=0 and one nrhs=0 system; "
-                         "no cause found by reading the code (every loop of the kernel is bounded "
-                         "and its barriers uniform), so the case stays off the GPU")
+@pytest.mark.skip(reason="did not finish on the GPU (kernel still running after 120 s) in one run of "
+                         "an earlier build, for a batch of one zero-pivot system (n=100, depth 0), "
+                         "one n=0 and one nrhs=0 system. No cause is shown: the host build of that "
+                         "build and of the current kernel runs this batch to completion, in bounds, "
+                         "with uniform barriers and concurrent workgroups "
+                         "(test_host_batched.py::test_zero_pivot_and_empty_systems), so the case "
+                         "stays off the GPU")
 def test_batched_zero_pivot_and_empty(rbt):
     A0 = np.eye(100)
     A0[70, 70] = 0.0
