@@ -201,13 +201,15 @@ constexpr int64_t kSkinnyMax = 16;  // right-hand sides handled by the sweeps an
 // k_sweep.hip : triangular sweep with op(A) of the factors for
 // nrhs <= kSkinnyMax, using the diagonal-block inverses of
 // launch_diag_inverses, as ONE persistent launch (ticket-ordered block rows,
-// a published-blocks counter). sync: sweep_sync_ints(n) int32
-// of device scratch; words 0..2 are cleared by each launch, word 3 is the
-// sticky error word (set when a bounded wait expired; the block's solution
-// is then NaN), which the caller clears (kSweepErrWord) and reads back.
+// each block's solution published entry by entry). sync:
+// sweep_sync_ints(n) int32 of device scratch: words 0..2 are cleared by each
+// launch (word 0: the ticket), word 3 is the sticky error word (set when a
+// bounded wait expired; the block's solution is then NaN), which the caller
+// clears (kSweepErrWord) and reads back; from word 64 (256 bytes) the
+// publication buffer, n x kSkinnyMax doubles, reset by each launch.
 // FP64 factors take one refinement step per diagonal block, FP32 factors
 // the inverse alone.
-inline int64_t sweep_sync_ints(int64_t /*n*/) { return 4; }
+inline int64_t sweep_sync_ints(int64_t n) { return 64 + 2 * kSkinnyMax * n; }
 constexpr int kSweepErrWord = 3;
 // Sleeps a sweep's wait may take before it expires (rbt_set_option
 // RBT_OPT_SWEEP_SPIN_LIMIT; negative: every wait expires at once).

@@ -7,28 +7,29 @@
 // blocks j solved before it, then solves its diagonal block with the
 // precomputed inverse (x = Di r; for FP64 factors and FP32 arithmetic one
 // more step, x += Di (r - T x), keeps the backward error of substitution) and
-// publishes x_b. Blocks are published strictly in ticket order, so one
-// counter `done` (= number of published blocks) replaces per-block flags: a
-// workgroup that needs block s waits until done > s, then consumes every
-// block published so far without waiting again. The matrix entries of the
-// next block are loaded before each wait, so the loads overlap it.
+// publishes x_b. The matrix entries of the next block are loaded before
+// each wait, so the loads overlap it.
+//
+// Publication: every solution entry carries its own readiness. Before the
+// sweep the launcher fills a publication buffer P (n x nrhs, in the sync
+// area) with a signalling-NaN pattern that no arithmetic produces; a
+// workgroup publishes x_b by storing its entries into P with agent-scope
+// atomic stores (and into B, the output), and a workgroup that needs x_j
+// polls its entries of P with agent-scope atomic loads until none holds the
+// pattern. One 8-byte entry is written once per sweep and read whole, so a
+// read value that is not the pattern is the published one: no fence, no
+// counter and no second round trip sit between a block's solution and its
+// consumers (the critical path of the sweep is one store and one load per
+// block).
 //
 // Progress: a workgroup only waits for blocks of smaller tickets, which were
 // taken by workgroups already running, so every wait ends. The spin is also
-// bounded (spin_limit sleeps, the library's option; a negative limit expires
-// every wait at once, which tests use to reach this path): a workgroup whose
-// wait expires sets the sticky error word sync[3] (which no sweep launch
-// clears), stores NaN as its block's solution, so the result can never be a
-// silently wrong finite vector, and goes on, so the grid always drains. The
-// published-blocks counter only moves forward (atomic maximum), also when a
-// late workgroup publishes after one whose wait expired.
-//
-// Coherence across XCDs: x_b is stored with agent-scope atomic stores by
-// the threads that hold it, each of them takes a device fence, and after a
-// workgroup barrier one thread makes a release store of `done`; waiters poll `done` with
-// relaxed agent-scope loads (no cache invalidation per poll), take one
-// acquire fence when it has advanced, and read x_j with agent-scope atomic
-// loads.
+// bounded (spin_limit sleeps per entry, the library's option; a negative
+// limit expires every wait at once, which tests use to reach this path): a
+// workgroup whose wait expires uses NaN for that entry, sets the sticky
+// error word sync[3] (which no sweep launch clears), stores NaN as its
+// block's solution, so the result can never be a silently wrong finite
+// vector, and goes on, so the grid always drains.
 //
 // Layout: 512 threads = 128 rows x 4 column segments of 32; products of a
 // 128 x 128 block with the x block are reduced over the segments in LDS.
@@ -66,6 +67,15 @@ __device__ __forceinline__ void coherent_store(double *p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Entry of P not yet published: a signalling NaN (arithmetic only yields
+// quiet NaNs; a published entry with this pattern is stored as a quiet NaN).
+constexpr uint64_t kUnpublished = 0x7FF4B1A5C0DE0001ull;
+__device__ __forceinline__ bool unpublished(double v) {
+  return __builtin_bit_cast(uint64_t, v) == kUnpublished;
+}
+// P: 256 bytes after the start of the sync area, column c at P + c n.
+constexpr int kSyncPubOffsetInts = 64;
+
 template <int NMAX, TriMode MODE, typename TF, bool REFINE, typename C>
 __global__ void __launch_bounds__(TPB)
     k_sweep(int64_t n, int N, const TF *__restrict__ A, int64_t ld,
@@ -83,14 +93,13 @@ __global__ void __launch_bounds__(TPB)
   const int tid = threadIdx.x;
   const int i = tid & (kNB - 1), sg = tid >> 7;
   if (tid == 0) tk = atomicAdd(&sync[0], 1);
+  __shared__ int expired_sh;
+  if (tid == 0) expired_sh = 0;
   __syncthreads();
   const int64_t t = tk;
   if (t >= nb) return;
-  int32_t *done = sync + 1;
   int32_t *err = sync + 3;  // sticky: cleared by the entry points, not per sweep
-  __shared__ int64_t avail_sh;
-  __shared__ int expired_sh;
-  if (tid == 0) expired_sh = 0;
+  double *pub = reinterpret_cast<double *>(sync + kSyncPubOffsetInts);
   const int64_t b = FWD ? t : nb - 1 - t;
   const int64_t r0 = b * kNB;
   const int kb = int(n - r0 < kNB ? n - r0 : kNB);
@@ -154,7 +163,6 @@ __global__ void __launch_bounds__(TPB)
   C acc[NMAX];
 #pragma unroll
   for (int c = 0; c < NMAX; ++c) acc[c] = C(0);
-  int64_t avail = 0;  // blocks known to be published (uniform)
   for (int64_t s = 0; s < t; ++s) {
     const int64_t j = FWD ? s : nb - 1 - s;
     const int64_t c0 = j * kNB;
@@ -165,29 +173,32 @@ __global__ void __launch_bounds__(TPB)
       const int col = sg * SEGW + q;
       e[q] = op_e<MODE>(A, ld, r0 + ir, c0 + (col < cb ? col : cb - 1));
     }
-    if (s >= avail) {
-      if (tid == 0) {
+    // x_j from P, each entry polled until published (bounded)
+    bool expired = false;
+    for (int idx = tid; idx < kNB * NMAX; idx += TPB) {
+      const int k = idx / NMAX, c = idx % NMAX;
+      C v = C(0);
+      if (k < cb && c < N) {
+        const double *p = pub + (c0 + k) + int64_t(c) * n;
+        double xv = coherent_load(p);
         int64_t spins = 0;
-        int32_t d;
-        while ((d = __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) <= s) {
-          if (spins >= spin_limit) {  // expired: flag it, poison this block, go on
-            __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            expired_sh = 1;
-            d = int32_t(s + 1);
+        while (unpublished(xv)) {
+          if (spins >= spin_limit) {  // expired: NaN for this entry, poison this block
+            expired = true;
+            xv = __builtin_nan("");
             break;
           }
           __builtin_amdgcn_s_sleep(1);
           ++spins;
+          xv = coherent_load(p);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        avail_sh = d;
+        v = C(xv);
       }
-      __syncthreads();
-      avail = avail_sh;
+      xs[k][c] = v;
     }
-    for (int idx = tid; idx < kNB * NMAX; idx += TPB) {
-      const int k = idx / NMAX, c = idx % NMAX;
-      xs[k][c] = (k < cb && c < N) ? C(coherent_load(&B[(c0 + k) + int64_t(c) * ldb])) : C(0);
+    if (expired) {
+      __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      expired_sh = 1;
     }
     __syncthreads();
 #pragma unroll
@@ -296,30 +307,28 @@ __global__ void __launch_bounds__(TPB)
     }
   }
 
-  // ---- publish x_b (NaN if a wait of this block expired) ----
+  // ---- publish x_b (NaN if a wait of this block expired): the output B
+  // and the consumers' copy in P ----
   const bool poisoned = expired_sh != 0;
   if (sg == 0 && i < kb) {
 #pragma unroll
     for (int c = 0; c < NMAX; ++c)
-      if (c < N)
-        coherent_store(&B[(r0 + i) + int64_t(c) * ldb],
-                       poisoned ? __builtin_nan("") : double(x[c]));
+      if (c < N) {
+        const double v = poisoned ? __builtin_nan("") : double(x[c]);
+        B[(r0 + i) + int64_t(c) * ldb] = v;
+        coherent_store(&pub[(r0 + i) + int64_t(c) * n], unpublished(v) ? __builtin_nan("") : v);
+      }
   }
-  // only the threads that stored need the device-scope fence (one per
-  // wavefront of them instead of all eight: each fence writes back the L2)
-  if (sg == 0) __threadfence();
-  __syncthreads();
-  // every block of a smaller ticket is published (this one consumed them
-  // all, unless a wait expired) and none of a larger ticket is; the maximum
-  // keeps the counter monotone in the expired case as well
-  if (tid == 0)
-    __hip_atomic_fetch_max(done, int32_t(t + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void k_zero_i32(int32_t *p, int64_t count) {
-  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < count;
-       k += int64_t(gridDim.x) * blockDim.x)
-    p[k] = 0;
+// Before a sweep: ticket and legacy words cleared, P (count entries) set to
+// the unpublished pattern.
+__global__ void k_sweep_reset(int32_t *sync, int64_t count) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g < 3) sync[g] = 0;
+  double *pub = reinterpret_cast<double *>(sync + kSyncPubOffsetInts);
+  const double u = __builtin_bit_cast(double, kUnpublished);
+  for (int64_t k = g; k < count; k += int64_t(gridDim.x) * blockDim.x) pub[k] = u;
 }
 
 template <int NMAX, TriMode MODE, typename TF, typename C>
@@ -331,9 +340,12 @@ hipError_t sweep_t(int64_t n, int N, const TF *LU, int64_t ld, const C *Winv, do
   constexpr bool REFINE = std::is_same<TF, double>::value || std::is_same<C, float>::value;
   const int64_t nb = (n + kNB - 1) / kNB;
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
-  // ticket, published-blocks counter and the legacy per-launch word; the
-  // sticky error word sync[3] is left alone
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, sync, int64_t(3));
+  // ticket and legacy words, and P for the N columns; the sticky error word
+  // sync[3] is left alone
+  const int64_t count = n * int64_t(N);
+  const int64_t blocks = (count + 255) / 256 < 1024 ? (count + 255) / 256 : 1024;
+  hipLaunchKernelGGL(k_sweep_reset, dim3(unsigned(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, sync,
+                     count);
   hipLaunchKernelGGL((k_sweep<NMAX, MODE, TF, REFINE, C>), dim3(unsigned(nb)), dim3(TPB), 0, s, n,
                      N, LU, ld, Winv, B, ldb, sync, nb, sweep_spin_limit(), refine_gate());
   return hipGetLastError();

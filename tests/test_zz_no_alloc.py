@@ -51,7 +51,7 @@ def test_noalloc_matches_solve_ex(rbt, sizes):
 
 
 def test_noalloc_rejects_oversize(rbt):
-    n = 40000  # workspace about 177 MiB > the library's 96 MiB array
+    n = 40000  # workspace about 181 MiB > the library's 96 MiB array
     A = torch.empty((1, 1), dtype=torch.float64, device="cuda")
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
     rc = rbt.lib().rbt_solve_ex_noalloc(n, 1, rbt._p(A), n, rbt._p(A), n, 2, 1, rbt._p(info),
