@@ -144,20 +144,35 @@ struct TrsmSmem {
   __attribute__((aligned(16))) C strip[4][NB * SLD];
 };
 
-// Left solves, op(T) X = B in place: the triangle of op(T) staged once per
-// workgroup (stage_left_triangle, then a workgroup barrier), then each
-// wavefront solves 16-column strips of B on its own (left_strip).
-// dblk: op(T)(i, j) of diagonal block b at b*256 + j*16 + (i%4)*4 + i/4
-// (reciprocal on the diagonal of non-unit modes); ablk: off-diagonal block
-// (I, J), J before I, at p*256 + lane*4 + kk = op(T)(16I + l16, 16J + 4kk +
-// lk), p = I(I-1)/2 + J (forward) or J(J-1)/2 + I (backward)
-template <TriMode MODE, typename TT, typename C>
-__device__ __forceinline__ void stage_left_triangle(int kb, const TT *T, int64_t ldt,
-                                                    TrsmSmem<C> &sm) {
+// Left solve of the 64 columns [64 bx, 64 bx + 64) of B.
+template <TriMode MODE, bool BATCH, typename TT, typename TB, typename C>
+__device__ __forceinline__ void trsm_left_body(int kb, int64_t N, const TT *T, int64_t ldt,
+                                               TB *B, int64_t ldb, int64_t n, int64_t bstride,
+                                               int64_t bx, TrsmSmem<C> &sm) {
+  typedef Mma16<C> M;
+  typedef typename M::v4 c4;
+  typedef C c2 __attribute__((ext_vector_type(2)));
+  if constexpr (BATCH) {
+    const int64_t b = blockIdx.y;
+    const int64_t r0 = b * NB;
+    kb = int(n - r0 < NB ? n - r0 : NB);
+    N = kb;
+    T += r0 + r0 * ldt;
+    B += b * bstride;
+  }
+  // dblk: op(T)(i, j) of diagonal block b at b*256 + j*16 + (i%4)*4 + i/4
+  // (reciprocal on the diagonal of non-unit modes); ablk: off-diagonal block
+  // (I, J), J before I, at p*256 + lane*4 + kk = op(T)(16I + l16, 16J + 4kk +
+  // lk), p = I(I-1)/2 + J (forward) or J(J-1)/2 + I (backward)
   C *dblk = sm.dblk;
   C *ablk = sm.oblk;
   constexpr bool FWD = forward_order<MODE>();
   constexpr bool TRANS = MODE == TriMode::UT || MODE == TriMode::LT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  C *strip = sm.strip[wave];  // row-major 128 x 16
+  const int64_t col0 = bx * 64 + wave * 16;
+
   {  // stage the diagonal blocks and the off-diagonal operands, coalesced:
      // consecutive threads read consecutive addresses of the stored T
     const int f = threadIdx.x & 15, g = threadIdx.x >> 4;
@@ -192,22 +207,6 @@ __device__ __forceinline__ void stage_left_triangle(int kb, const TT *T, int64_t
         ablk[p * BLK + slot] = (gi < kb && gj < kb) ? C(oraw[p]) : C(0);
       }
   }
-}
-
-// Strip of the 16 columns [col0, col0 + 16) of B (kb x N), by the calling
-// wavefront alone. BATCH: the right-hand side is the identity.
-template <TriMode MODE, bool BATCH, typename TT, typename TB, typename C>
-__device__ __forceinline__ void left_strip(int kb, int64_t N, TB *B, int64_t ldb, int64_t col0,
-                                           TrsmSmem<C> &sm) {
-  typedef Mma16<C> M;
-  typedef typename M::v4 c4;
-  typedef C c2 __attribute__((ext_vector_type(2)));
-  const C *dblk = sm.dblk;
-  const C *ablk = sm.oblk;
-  constexpr bool FWD = forward_order<MODE>();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int l16 = lane & 15, lk = lane >> 4;
-  C *strip = sm.strip[wave];  // row-major 128 x 16
 #pragma unroll
   for (int h = 0; h < 2; ++h) {  // strip: lane = row (two halves), 16 columns
     const int row = lane + 64 * h;
@@ -230,7 +229,7 @@ __device__ __forceinline__ void left_strip(int kb, int64_t N, TB *B, int64_t ldb
         strip[row * SLD + c] = (row < kb && col0 + c < N) ? C(raw[c]) : C(0);
     }
   }
-  wave_sync();
+  __syncthreads();
 
   const int nbk = (kb + IB - 1) / IB;
   const int cc = lane >> 2, q = lane & 3;  // substitution: right-hand side cc, entries q + 4 jj
@@ -277,24 +276,6 @@ __device__ __forceinline__ void left_strip(int kb, int64_t N, TB *B, int64_t ldb
   }
 }
 
-// Left solve of the 64 columns [64 bx, 64 bx + 64) of B.
-template <TriMode MODE, bool BATCH, typename TT, typename TB, typename C>
-__device__ __forceinline__ void trsm_left_body(int kb, int64_t N, const TT *T, int64_t ldt,
-                                               TB *B, int64_t ldb, int64_t n, int64_t bstride,
-                                               int64_t bx, TrsmSmem<C> &sm) {
-  if constexpr (BATCH) {
-    const int64_t b = blockIdx.y;
-    const int64_t r0 = b * NB;
-    kb = int(n - r0 < NB ? n - r0 : NB);
-    N = kb;
-    T += r0 + r0 * ldt;
-    B += b * bstride;
-  }
-  stage_left_triangle<MODE, TT, C>(kb, T, ldt, sm);
-  __syncthreads();
-  left_strip<MODE, BATCH, TT, TB, C>(kb, N, B, ldb, bx * 64 + (threadIdx.x >> 6) * 16, sm);
-}
-
 template <TriMode MODE, bool BATCH, typename TT, typename TB, typename C>
 __global__ void __launch_bounds__(256, 1) k_trsm_left(int kb, int64_t N, const TT *T,
                                                       int64_t ldt, TB *B, int64_t ldb,
@@ -304,17 +285,24 @@ __global__ void __launch_bounds__(256, 1) k_trsm_left(int kb, int64_t N, const T
                                          int64_t(blockIdx.x), sm);
 }
 
-// Right solve, X U = B in place: the triangle staged once per workgroup
-// (stage_upper_triangle, then a workgroup barrier), then each wavefront
-// solves 16-row strips of B on its own (right_strip).
-// dblk: U(r, c) of diagonal block b at b*256 + r*16 + (c%4)*4 + c/4
-// (reciprocal on the diagonal); ublk: block (I, J), I < J, at p*256 +
-// lane*4 + kk = U(16I + 4kk + lk, 16J + l16), p = J(J-1)/2 + I
+// Right solve of the 64 rows [64 bx, 64 bx + 64) of B.
 template <typename TT, typename C>
-__device__ __forceinline__ void stage_upper_triangle(int kb, const TT *T, int64_t ldt,
-                                                     TrsmSmem<C> &sm) {
+__device__ __forceinline__ void trsm_right_upper_body(int kb, int64_t M, const TT *T, int64_t ldt,
+                                                      TT *B, int64_t ldb, int64_t bx,
+                                                      TrsmSmem<C> &sm) {
+  typedef Mma16<C> Mm;
+  typedef typename Mm::v4 c4;
+  typedef C c2 __attribute__((ext_vector_type(2)));
+  // dblk: U(r, c) of diagonal block b at b*256 + r*16 + (c%4)*4 + c/4
+  // (reciprocal on the diagonal); ublk: block (I, J), I < J, at p*256 +
+  // lane*4 + kk = U(16I + 4kk + lk, 16J + l16), p = J(J-1)/2 + I
   C *dblk = sm.dblk;
   C *ublk = sm.oblk;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  C *strip = sm.strip[wave];  // column-major 16 x 128
+  const int64_t row0 = bx * 64 + wave * 16;
+
   {  // stage the triangle, consecutive threads on consecutive rows of U
     const int r = threadIdx.x % IB, c = threadIdx.x / IB;
     TT raw[NBK];
@@ -343,21 +331,6 @@ __device__ __forceinline__ void stage_upper_triangle(int kb, const TT *T, int64_
         ublk[p * BLK + slot] = (gi < kb && gj < kb) ? C(uraw[p]) : C(0);
       }
   }
-}
-
-// Strip of the 16 rows [row0, row0 + 16) of B (M x kb), by the calling
-// wavefront alone.
-template <typename TT, typename C>
-__device__ __forceinline__ void right_strip(int kb, int64_t M, TT *B, int64_t ldb, int64_t row0,
-                                            TrsmSmem<C> &sm) {
-  typedef Mma16<C> Mm;
-  typedef typename Mm::v4 c4;
-  typedef C c2 __attribute__((ext_vector_type(2)));
-  const C *dblk = sm.dblk;
-  const C *ublk = sm.oblk;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int l16 = lane & 15, lk = lane >> 4;
-  C *strip = sm.strip[wave];  // column-major 16 x 128
   {
     // lane = (row r = lane % 16, column group lane / 16): columns cg + 4u
     const int r = lane % IB, cg = lane / IB;
@@ -376,7 +349,7 @@ __device__ __forceinline__ void right_strip(int kb, int64_t M, TT *B, int64_t ld
       }
     }
   }
-  wave_sync();
+  __syncthreads();
 
   const int nbk = (kb + IB - 1) / IB;
   const int rq = lane >> 2, q = lane & 3;  // substitution: row rq, entries q + 4 jj
@@ -421,16 +394,6 @@ __device__ __forceinline__ void right_strip(int kb, int64_t M, TT *B, int64_t ld
   }
 }
 
-// Right solve of the 64 rows [64 bx, 64 bx + 64) of B.
-template <typename TT, typename C>
-__device__ __forceinline__ void trsm_right_upper_body(int kb, int64_t M, const TT *T, int64_t ldt,
-                                                      TT *B, int64_t ldb, int64_t bx,
-                                                      TrsmSmem<C> &sm) {
-  stage_upper_triangle<TT, C>(kb, T, ldt, sm);
-  __syncthreads();
-  right_strip<TT, C>(kb, M, B, ldb, bx * 64 + (threadIdx.x >> 6) * 16, sm);
-}
-
 template <typename TT, typename C>
 __global__ void __launch_bounds__(256, 1) k_trsm_right_upper(int kb, int64_t M, const TT *T,
                                                              int64_t ldt, TT *B, int64_t ldb) {
@@ -439,37 +402,21 @@ __global__ void __launch_bounds__(256, 1) k_trsm_right_upper(int kb, int64_t M, 
 }
 
 // Both solves of a panel step with one factored diagonal block, which are
-// independent: L21 = A21 U11^-1 (M x kb, strips of 16 rows) and U12 =
-// L11^-1 A12 (kb x N, strips of 16 columns), in one persistent launch of
-// about one workgroup per compute unit: the first gr workgroups stage U11
-// once and take the right solve's strips, the other gl stage L11 once and
-// take the left solve's, strip w + k 4 g to wavefront w of workgroup g (k =
-// 0, 1, ...). Every strip sees the operations of its own one-workgroup
-// solve, so the split does not change the results.
+// independent: L21 = A21 U11^-1 (the first gr workgroups, 64 rows each) and
+// U12 = L11^-1 A12 for the panel's columns to the right (the rest, 64
+// columns each). One launch instead of two, and the short left solve runs
+// beside the right one.
 template <typename TT, typename C>
 __global__ void __launch_bounds__(256, 1) k_panel_trsm(int kb, int64_t M, int64_t N, const TT *T,
                                                        int64_t ldt, TT *Br, TT *Bl, int64_t ldb,
-                                                       int64_t gr, int64_t gl) {
+                                                       int64_t gr) {
   __shared__ TrsmSmem<C> sm;
   const int64_t bx = blockIdx.x;
-  const int wave = threadIdx.x >> 6;
-  if (bx < gr) {
-    stage_upper_triangle<TT, C>(kb, T, ldt, sm);
-    __syncthreads();
-    const int64_t strips = (M + IB - 1) / IB;
-    for (int64_t st = bx * 4 + wave; st < strips; st += gr * 4) {
-      right_strip<TT, C>(kb, M, Br, ldb, st * IB, sm);
-      wave_sync();
-    }
-  } else {
-    stage_left_triangle<TriMode::LN, TT, C>(kb, T, ldt, sm);
-    __syncthreads();
-    const int64_t strips = (N + IB - 1) / IB;
-    for (int64_t st = (bx - gr) * 4 + wave; st < strips; st += gl * 4) {
-      left_strip<TriMode::LN, false, TT, TT, C>(kb, N, Bl, ldb, st * IB, sm);
-      wave_sync();
-    }
-  }
+  if (bx < gr)
+    trsm_right_upper_body<TT, C>(kb, M, T, ldt, Br, ldb, bx, sm);
+  else
+    trsm_left_body<TriMode::LN, false, TT, TT, C>(kb, N, T, ldt, Bl, ldb, int64_t(0),
+                                                  int64_t(0), bx - gr, sm);
 }
 
 template <typename TT, typename TB, typename C>
@@ -503,42 +450,15 @@ hipError_t diag_inverses_t(int64_t n, const TT *LU, int64_t ld, C *W, hipStream_
   return hipGetLastError();
 }
 
-// Compute units of the current device (256 on MI355X), cached per device.
-int device_cu_count() {
-  static int cached[64] = {};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (cached[dev] == 0) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-    cached[dev] = cus;
-  }
-  return cached[dev];
-}
-
 template <typename TT, typename C>
 hipError_t panel_trsm_t(int kb, int64_t M, int64_t N, const TT *T, int64_t ldt, TT *Br, TT *Bl,
                         int64_t ldb, hipStream_t s) {
   if (kb <= 0 || (M <= 0 && N <= 0)) return hipSuccess;
   if (kb > kNB) return hipErrorInvalidValue;
-  // workgroups of 64 rows (columns) each, at most as many as fit on the
-  // device at once (one per compute unit with FP64 LDS operands, two with
-  // FP32), shared in proportion to the two solves' strips
-  const int64_t wr = M > 0 ? (M + 63) / 64 : 0, wl = N > 0 ? (N + 63) / 64 : 0;
-  const int64_t cus = int64_t(device_cu_count()) * (sizeof(C) == 4 ? 2 : 1);
-  int64_t gr = wr, gl = wl;
-  if (wr + wl > cus) {
-    gr = wr > 0 ? (cus * wr + (wr + wl) / 2) / (wr + wl) : 0;
-    if (wr > 0 && gr < 1) gr = 1;
-    if (wl > 0 && gr > cus - 1) gr = cus - 1;
-    gl = wl > 0 ? cus - gr : 0;
-    if (gr > wr) gr = wr;
-    if (gl > wl) gl = wl;
-  }
+  const int64_t gr = M > 0 ? (M + 63) / 64 : 0, gl = N > 0 ? (N + 63) / 64 : 0;
+  if (gr + gl > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_panel_trsm<TT, C>), dim3(unsigned(gr + gl)), dim3(256), 0, s, kb, M, N, T,
-                     ldt, Br, Bl, ldb, gr, gl);
+                     ldt, Br, Bl, ldb, gr);
   return hipGetLastError();
 }
 
