@@ -106,6 +106,20 @@ struct Args {
   int64_t ct2_min_n;  // systems with n >= this: two 64-column tiles per round
 };
 
+// A value that is the same in every lane, moved to scalar registers: the
+// phase functions below are not inlined and read sizes, strides and base
+// pointers through Sys, so the compiler cannot tell they are uniform and
+// would keep them (and every address formed from them) in vector registers.
+__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(uint64_t(v) >> 32))));
+  return int64_t((uint64_t(hi) << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T *wave_uniform(T *p) {
+  return reinterpret_cast<T *>(wave_uniform(int64_t(reinterpret_cast<uintptr_t>(p))));
+}
+
 __device__ __forceinline__ double nanmax(double a, double b) {
   return (b > a || b != b) ? b : a;
 }
@@ -499,9 +513,9 @@ struct Sys {
 template <typename T>
 __device__ __forceinline__ T *fmat(const Sys &s) {
   if constexpr (sizeof(T) == 4)
-    return s.F;
+    return wave_uniform(s.F);
   else
-    return s.F64;
+    return wave_uniform(s.F64);
 }
 
 // Factor the kb x kb diagonal block at (k, k) of F in the factors'
@@ -516,7 +530,8 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
   lds_t *S = (lds_t *)S_in;
   lds_t *T = (lds_t *)T_in;
   TF RBT_AS_GLOBAL *F = (TF RBT_AS_GLOBAL *)fmat<TF>(s);
-  TF RBT_AS_GLOBAL *Invg = (TF RBT_AS_GLOBAL *)Invb;
+  TF RBT_AS_GLOBAL *Invg = (TF RBT_AS_GLOBAL *)wave_uniform(Invb);
+  const int64_t n = wave_uniform(s.n);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   {
     const int r = tid & 63, cg = tid >> 6;
@@ -525,7 +540,7 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
       const int c = cg + 4 * t;
-      v[t] = F[(k + rr) + (k + (c < kb ? c : kb - 1)) * s.n];
+      v[t] = F[(k + rr) + (k + (c < kb ? c : kb - 1)) * n];
     }
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
@@ -648,7 +663,7 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
   for (int e = tid; e < BB * BB; e += BT) {
     const int r = e & 63, c = e >> 6;
     Invg[r + c * BB] = T[c * LDS_ + r];
-    if (r < kb && c < kb) F[(k + r) + (k + c) * s.n] = S[c * LDS_ + r];
+    if (r < kb && c < kb) F[(k + r) + (k + c) * n] = S[c * LDS_ + r];
     if constexpr (sizeof(TF) == 4) Sc[c * LDS_ + r] = S[c * LDS_ + r];
   }
   __syncthreads();
@@ -659,8 +674,9 @@ __device__ __noinline__ void diag_block(const Sys &s, int64_t k, int kb, double 
 // TF = double: FP64 factors (the fallback; FP64 trailing update).
 template <typename TF, bool BF16U, int CT = 1>
 __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int *info_sh) {
-  const int64_t n = s.n;
+  const int64_t n = wave_uniform(s.n);
   TF *F = fmat<TF>(s);
+  TF *Inv = reinterpret_cast<TF *>(wave_uniform(s.Inv));
   float(*As)[LDF] = reinterpret_cast<float(*)[LDF]>(L0);
   float(*Bs)[LDF] = reinterpret_cast<float(*)[LDF]>(L0 + (BB * LDF + 1) / 2);
   __bf16(*Ah)[LDH] = reinterpret_cast<__bf16(*)[LDH]>(L0);
@@ -669,7 +685,7 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
     const int kb = int(n - k < BB ? n - k : BB);
     // inverse block k / BB, counted in elements of the factors' type (the
     // sweeps index the area the same way)
-    TF *Invb = reinterpret_cast<TF *>(s.Inv) + (k / BB) * BB * BB;
+    TF *Invb = Inv + (k / BB) * BB * BB;
     diag_block<TF>(s, k, kb, L0, L1, Invb, info_sh);
     const int64_t rest = n - k - kb;
     if (rest <= 0) break;
@@ -876,20 +892,23 @@ __device__ __noinline__ void eliminate(const Sys &s, double *L0, double *L1, int
 // One-sided transform of the n x nrhs block Y (ld ldy) with coefficients C,
 // in passes of at most three layers (op T: layers d..1, op N: 1..d).
 template <int OP>
-__device__ __noinline__ void transform_vec_sys(const Sys &s, int d, double *Y, int64_t ldy, const double *C) {
+__device__ __noinline__ void transform_vec_sys(const Sys &s, int d, double *Y, int64_t ldy_in,
+                                               const double *C) {
   if (d == 0) return;
-  double RBT_AS_GLOBAL *Yg = (double RBT_AS_GLOBAL *)Y;
-  const double RBT_AS_GLOBAL *Cg = (const double RBT_AS_GLOBAL *)C;
+  double RBT_AS_GLOBAL *Yg = (double RBT_AS_GLOBAL *)wave_uniform(Y);
+  const double RBT_AS_GLOBAL *Cg = (const double RBT_AS_GLOBAL *)wave_uniform(C);
+  const int64_t ldy = wave_uniform(ldy_in), n = wave_uniform(s.n), q = wave_uniform(s.q);
+  const int nrhs = int(wave_uniform(s.nrhs));
   for (int k = 0; k < (d + 2) / 3; ++k) {
     // op T: passes (d-2..d), (d-5..d-3), ...; op N: (1..3), (4..6), ...
     const int hi = OP == RBT_OP_T ? d - 3 * k : (3 * k + 3 < d ? 3 * k + 3 : d);
     const int lo = OP == RBT_OP_T ? (hi - 2 > 1 ? hi - 2 : 1) : 3 * k + 1;
-    const dev::Pass ps = dev::make_pass(s.n, s.q, d, lo, hi, s.rot, s.sides);
+    const dev::Pass ps = dev::make_pass(n, q, d, lo, hi, s.rot, s.sides);
     const int ng = int(ps.ngroups);
-    for (int e = threadIdx.x; e < ng * int(s.nrhs); e += BT) {
+    for (int e = threadIdx.x; e < ng * nrhs; e += BT) {
       const int gr = e % ng, j = e / ng;
       const int64_t rb = dev::group_base(ps, gr);
-      if (rb >= s.n) continue;
+      if (rb >= n) continue;
       switch (hi - lo + 1) {
         case 1: dev::transform_vec_block<1, OP>(Yg, ldy, j, Cg, ps, rb); break;
         case 2: dev::transform_vec_block<2, OP>(Yg, ldy, j, Cg, ps, rb); break;
@@ -912,13 +931,15 @@ __device__ __noinline__ void transform_vec_sys(const Sys &s, int d, double *Y, i
 // lane, held in registers for the step). Operand and output layout: mma16.h.
 // NRT: right-hand sides of the inverse product (>= N).
 template <bool LOWER, int NRT, typename TF>
-__device__ __noinline__ void sweep(const Sys &s, double *Y_in, int64_t ldy, double *L0) {
+__device__ __noinline__ void sweep(const Sys &s, double *Y_in, int64_t ldy_in, double *L0) {
   typedef Mma16<TF> M;
   typedef typename Lds<TF>::T lds_t;
   const TF RBT_AS_GLOBAL *F = (const TF RBT_AS_GLOBAL *)fmat<TF>(s);
-  double RBT_AS_GLOBAL *Y = (double RBT_AS_GLOBAL *)Y_in;
-  const int64_t n = s.n;
-  const int N = int(s.nrhs);
+  const TF RBT_AS_GLOBAL *Inv = (const TF RBT_AS_GLOBAL *)wave_uniform(s.Inv);
+  double RBT_AS_GLOBAL *Y = (double RBT_AS_GLOBAL *)wave_uniform(Y_in);
+  const int64_t ldy = wave_uniform(ldy_in);
+  const int64_t n = wave_uniform(s.n);
+  const int N = int(wave_uniform(s.nrhs));
   const int tid = threadIdx.x, i = tid & 63, sg = tid >> 6;
   const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, lk = lane >> 4;
   lds_t *Ll = (lds_t *)L0;
@@ -944,7 +965,7 @@ __device__ __noinline__ void sweep(const Sys &s, double *Y_in, int64_t ldy, doub
     __syncthreads();
     // x_b = Dinv y_b: part[sg][i][:] = sum over this segment's 16 columns of
     // Dinv(i, kx) xs[kx][:], then the four segments are added
-    const TF RBT_AS_GLOBAL *Db = (const TF RBT_AS_GLOBAL *)s.Inv + b * BB * BB;
+    const TF RBT_AS_GLOBAL *Db = Inv + b * BB * BB;
     // (entries read from the inverse where they are used: an array of them
     // held through the loops below would be indexed dynamically)
     auto dinv = [&](int q) {
@@ -1052,11 +1073,30 @@ __device__ __noinline__ void sweep(const Sys &s, double *Y_in, int64_t ldy, doub
           av[kk] = F[mc + (r0 + (kx < kb ? kx : kb - 1)) * n];
         }
       };
+      // the lane's four entries of Y in the tile (column l16), read with the
+      // tile's factor entries one tile ahead: a row always belongs to the
+      // same wavefront (lo moves by whole 4-tile rounds), so no other
+      // wavefront writes them in between
+      const int yc = l16 < N ? l16 : N - 1;
+      auto load_y = [&](int64_t tt, double (&yv)[4]) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t m = lo + 16 * tt + M::row(lk, v);
+          yv[v] = Y[(m < hi ? m : hi - 1) + int64_t(yc) * ldy];
+        }
+      };
       TF av[16], an[16];
+      double yv[4], yn[4];
       int64_t tt = wave;
-      if (tt < ntile) load_tile(tt, av);
+      if (tt < ntile) {
+        load_tile(tt, av);
+        load_y(tt, yv);
+      }
       for (; tt < ntile; tt += 4) {
-        if (tt + 4 < ntile) load_tile(tt + 4, an);
+        if (tt + 4 < ntile) {
+          load_tile(tt + 4, an);
+          load_y(tt + 4, yn);
+        }
         typename M::v4 o = {TF(0), TF(0), TF(0), TF(0)};
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
@@ -1067,14 +1107,13 @@ __device__ __noinline__ void sweep(const Sys &s, double *Y_in, int64_t ldy, doub
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int64_t m = lo + 16 * tt + M::row(lk, v);
-            if (m < hi) {
-              double RBT_AS_GLOBAL *py = Y + m + int64_t(l16) * ldy;
-              *py = double(TF(*py) - o[v]);
-            }
+            if (m < hi) Y[m + int64_t(l16) * ldy] = double(TF(yv[v]) - o[v]);
           }
         }
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) av[kk] = an[kk];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) yv[v] = yn[v];
       }
     }
     __syncthreads();
@@ -1087,17 +1126,18 @@ __device__ __noinline__ void sweep(const Sys &s, double *Y_in, int64_t ldy, doub
 // |R|, |X|, |B| in a second, small pass.
 template <int NRT>
 __device__ __noinline__ double residual(const Sys &s, double *L0, bool with_anorm, double *anorm) {
-  const int64_t n = s.n;
-  const int N = int(s.nrhs);
+  const int64_t n = wave_uniform(s.n);
+  const int N = int(wave_uniform(s.nrhs));
+  const int64_t lda = wave_uniform(s.lda), ldx = wave_uniform(s.ldx), ldb = wave_uniform(s.ldb);
   const int tid = threadIdx.x;
   constexpr int KC = 256;  // columns of A per staged chunk of X
   ldouble *Ll = (ldouble *)L0;
   double RBT_AS_LDS(*xs)[NRT] = reinterpret_cast<double RBT_AS_LDS(*)[NRT]>(Ll);  // [KC][NRT]
   double *red = L0 + KC * NR;  // (wg_nanmax takes a plain pointer)
-  const double RBT_AS_GLOBAL *Ag = (const double RBT_AS_GLOBAL *)s.A;
-  const double RBT_AS_GLOBAL *Xg = (const double RBT_AS_GLOBAL *)s.Xm;
-  const double RBT_AS_GLOBAL *Bg = (const double RBT_AS_GLOBAL *)s.Bm;
-  double RBT_AS_GLOBAL *Rg = (double RBT_AS_GLOBAL *)s.R;
+  const double RBT_AS_GLOBAL *Ag = (const double RBT_AS_GLOBAL *)wave_uniform(s.A);
+  const double RBT_AS_GLOBAL *Xg = (const double RBT_AS_GLOBAL *)wave_uniform(s.Xm);
+  const double RBT_AS_GLOBAL *Bg = (const double RBT_AS_GLOBAL *)wave_uniform(s.Bm);
+  double RBT_AS_GLOBAL *Rg = (double RBT_AS_GLOBAL *)wave_uniform(s.R);
   double amax = 0.0;
   for (int64_t m0 = 0; m0 < n; m0 += BT) {
     const int64_t m = m0 + tid;
@@ -1110,18 +1150,21 @@ __device__ __noinline__ double residual(const Sys &s, double *L0, bool with_anor
       __syncthreads();
       for (int e = tid; e < KC * NRT; e += BT) {
         const int kx = e % KC, c = e / KC;  // consecutive threads: consecutive rows of X
-        xs[kx][c] = (kx < kc && c < N) ? Xg[(k0 + kx) + int64_t(c) * s.ldx] : 0.0;
+        xs[kx][c] = (kx < kc && c < N) ? Xg[(k0 + kx) + int64_t(c) * ldx] : 0.0;
       }
       __syncthreads();
       if (m < n) {
-        const double RBT_AS_GLOBAL *Ap = Ag + m + k0 * s.lda;
-        // batches of 32 loads in flight (kc is a multiple of 32 except at the end)
+        const double RBT_AS_GLOBAL *Ap = Ag + m + k0 * lda;
+        // batches of 32 loads in flight (kc is a multiple of 32 except at the
+        // end): all issued before the first product uses one
         int kx = 0;
 #pragma unroll 1
         for (; kx + 32 <= kc; kx += 32) {
           double av[32];
+          const double RBT_AS_GLOBAL *p = Ap + int64_t(kx) * lda;
 #pragma unroll
-          for (int q = 0; q < 32; ++q) av[q] = Ap[int64_t(kx + q) * s.lda];
+          for (int q = 0; q < 32; ++q) av[q] = p[int64_t(q) * lda];
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int q = 0; q < 32; ++q) {
             if (with_anorm) asum += fabs(av[q]);
@@ -1131,7 +1174,7 @@ __device__ __noinline__ double residual(const Sys &s, double *L0, bool with_anor
         }
 #pragma unroll 1
         for (; kx < kc; ++kx) {
-          const double a = Ap[int64_t(kx) * s.lda];
+          const double a = Ap[int64_t(kx) * lda];
           if (with_anorm) asum += fabs(a);
 #pragma unroll
           for (int c = 0; c < NRT; ++c) acc[c] += a * xs[kx][c];
@@ -1142,7 +1185,7 @@ __device__ __noinline__ double residual(const Sys &s, double *L0, bool with_anor
       amax = nanmax(amax, asum);
 #pragma unroll
       for (int c = 0; c < NRT; ++c)
-        if (c < N) Rg[m + int64_t(c) * n] = Bg[m + int64_t(c) * s.ldb] - acc[c];
+        if (c < N) Rg[m + int64_t(c) * n] = Bg[m + int64_t(c) * ldb] - acc[c];
     }
   }
   __syncthreads();
@@ -1157,8 +1200,8 @@ __device__ __noinline__ double residual(const Sys &s, double *L0, bool with_anor
     double rm = 0.0, xm = 0.0, bm = 0.0;
     for (int64_t m = tid; m < n; m += BT) {
       rm = nanmax(rm, fabs(Rg[m + int64_t(c) * n]));
-      xm = nanmax(xm, fabs(Xg[m + int64_t(c) * s.ldx]));
-      bm = nanmax(bm, fabs(Bg[m + int64_t(c) * s.ldb]));
+      xm = nanmax(xm, fabs(Xg[m + int64_t(c) * ldx]));
+      bm = nanmax(bm, fabs(Bg[m + int64_t(c) * ldb]));
     }
     const double r = wg_nanmax(rm, red);
     const double x = wg_nanmax(xm, red);
@@ -1216,15 +1259,15 @@ __device__ void refine_system(const Sys &s, int d, double tol, int max_iter, dou
 // storage in place (each block of a pass belongs to one thread).
 template <typename TF>
 __device__ __noinline__ void transform_into(const Sys &s, int d) {
-  const double RBT_AS_GLOBAL *Ag = (const double RBT_AS_GLOBAL *)s.A;
-  const double RBT_AS_GLOBAL *Ug = (const double RBT_AS_GLOBAL *)s.U;
-  const double RBT_AS_GLOBAL *Vg = (const double RBT_AS_GLOBAL *)s.V;
+  const double RBT_AS_GLOBAL *Ag = (const double RBT_AS_GLOBAL *)wave_uniform(s.A);
+  const double RBT_AS_GLOBAL *Ug = (const double RBT_AS_GLOBAL *)wave_uniform(s.U);
+  const double RBT_AS_GLOBAL *Vg = (const double RBT_AS_GLOBAL *)wave_uniform(s.V);
   TF RBT_AS_GLOBAL *Fg = (TF RBT_AS_GLOBAL *)fmat<TF>(s);
-  const int64_t n = s.n;
+  const int64_t n = wave_uniform(s.n), lda = wave_uniform(s.lda), q = wave_uniform(s.q);
   for (int hi = d, first = 1; first || hi >= 1; first = 0) {
     const int lo = d == 0 ? 1 : (hi - 2 > 1 ? hi - 2 : 1);
     const dev::Pass ps =
-        d > 0 ? dev::make_pass(n, s.q, d, lo, hi, s.rot, s.sides) : dev::identity_pass(n);
+        d > 0 ? dev::make_pass(n, q, d, lo, hi, s.rot, s.sides) : dev::identity_pass(n);
     const int P = d > 0 ? hi - lo + 1 : 0;
     for (int64_t e = threadIdx.x; e < ps.ngroups * ps.ngroups; e += BT) {
       const int64_t gr = e % ps.ngroups, gc = e / ps.ngroups;
@@ -1232,10 +1275,10 @@ __device__ __noinline__ void transform_into(const Sys &s, int d) {
       if (rb >= n || cb >= n) continue;
       if (first) {
         switch (P) {
-          case 0: dev::transform2_block<0, TF>(Ag, s.lda, Fg, n, Ug, Vg, ps, rb, cb); break;
-          case 1: dev::transform2_block<1, TF>(Ag, s.lda, Fg, n, Ug, Vg, ps, rb, cb); break;
-          case 2: dev::transform2_block<2, TF>(Ag, s.lda, Fg, n, Ug, Vg, ps, rb, cb); break;
-          default: dev::transform2_block<3, TF>(Ag, s.lda, Fg, n, Ug, Vg, ps, rb, cb); break;
+          case 0: dev::transform2_block<0, TF>(Ag, lda, Fg, n, Ug, Vg, ps, rb, cb); break;
+          case 1: dev::transform2_block<1, TF>(Ag, lda, Fg, n, Ug, Vg, ps, rb, cb); break;
+          case 2: dev::transform2_block<2, TF>(Ag, lda, Fg, n, Ug, Vg, ps, rb, cb); break;
+          default: dev::transform2_block<3, TF>(Ag, lda, Fg, n, Ug, Vg, ps, rb, cb); break;
         }
       } else {
         switch (P) {
@@ -1370,7 +1413,7 @@ __global__ void __launch_bounds__(BT, 2) k_batched(Args a) {
   for (int64_t round = 0; round <= a.batch; ++round) {
     if (threadIdx.x == 0) tk_sh = atomicAdd(&hdr->ticket, 1);
     __syncthreads();
-    const int64_t t = tk_sh;
+    const int64_t t = wave_uniform(tk_sh);
     __syncthreads();
     if (t < 0 || t >= a.batch) break;
     const BatchDesc D = desc[t];

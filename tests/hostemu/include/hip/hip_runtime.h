@@ -123,6 +123,9 @@ extern thread_local emu::Index threadIdx, blockIdx, blockDim, gridDim;
 
 #define __syncthreads() ::emu::sync_threads(__FILE__, __LINE__)
 #define __builtin_amdgcn_readlane(v, src) ::emu::readlane((v), (src))
+// every lane is active where the kernels read the first lane
+#define __builtin_amdgcn_readfirstlane(v) ::emu::readlane((v), 0)
+#define __builtin_amdgcn_sched_barrier(mask) ((void)0)
 #define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) \
   ::emu::update_dpp((old), (src), (ctrl), (rm), (bm), (bc))
 #define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, cbsz, abid, blgp) \
