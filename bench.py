@@ -27,10 +27,6 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 
-# HBM bytes per trailing-update launch, from FETCH_SIZE and WRITE_SIZE counter
-# runs (rocprofv3 --pmc) scaled by what the same counters read for a plain copy
-# of known size (FETCH x 2.000, WRITE x 1.000). Valid only for the kernel
-# source and the workload they were taken on: reported as null otherwise.
 # HBM bytes per launch of a benchmark's dominant kernel, from rocprofv3 counter
 # runs (FETCH_SIZE x 2 + WRITE_SIZE x 1 in KiB, scaled by a plain copy of known
 # size): valid only while the kernel's source is the one the counters were taken
@@ -39,15 +35,15 @@ KERNEL_TRAFFIC = {
     "fp64": {"source": "paper_2312_09376_amd/csrc/k_gemm.hip",
              "sha256": "cd064f89968f0e242177948f6fad7a7d0a8deea95567454ad17bee080fbabd6a",
              "config": {"n": 20000, "nrhs": 1, "depth": 2, "outer_nb": 1024},
-             "bytes_per_launch": 5.474e9},
+             "bytes_per_launch": (2 * 2178986.5 + 985088.0) * 1024},
     "bf16": {"source": "paper_2312_09376_amd/csrc/k_hgemm.hip",
              "sha256": "a2e326c4190c3373b06045510896c621b5b597abc03e3147a85aefe0e7c2de42",
              "config": {"n": 32768, "nrhs": 1, "depth": 2, "outer_nb": 1024, "matrix": "dominant"},
-             "bytes_per_launch": (2 * 1404887.8 + 1466817.7) * 1024},
+             "bytes_per_launch": (2 * 1424417.0 + 1461608.6) * 1024},
     "batched_fp32": {"source": "paper_2312_09376_amd/csrc/k_batched.hip",
-                     "sha256": "2fe1aba6dca853b8cdfd8d736bb339f19e71ad44b91d5cec404a16e795ca8bea",
+                     "sha256": "3e931707a2cec70653f35bda832c91770d0af62339d4936353ee0a6cb2850d32",
                      "config": {"batch": 2048, "depth": 2, "matrix": "randn"},
-                     "bytes_per_launch": (2 * 189180403.3 + 92088656.0) * 1024},
+                     "bytes_per_launch": (2 * 187575530.8 + 92377023.8) * 1024},
 }
 
 
