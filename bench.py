@@ -47,6 +47,24 @@ KERNEL_TRAFFIC = {
 }
 
 
+def stage_breakdown(rbt, step, steps):
+    """Per-stage milliseconds per step from `steps` extra steps with every
+    stage timed. Each timed scope records two events on the stream (a few
+    microseconds of device time apiece), so the measured steps time only the
+    kernels the benchmark line reports and the breakdown comes from here."""
+    import torch
+    if steps <= 0:
+        return {}
+    torch.cuda.synchronize()
+    rbt.timing_read()
+    rbt.timing_enable(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    rbt.timing_enable(False)
+    return {s_: round(v[0] / steps, 3) for s_, v in rbt.timing_read().items()}
+
+
 def trailing_shapes(n, W, remainder=True):
     """(rc, w) of every trailing update of the blocked elimination: rc rows
     and columns remain right of a panel of width w. The first panel also takes
@@ -72,6 +90,9 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=10)
     ap.add_argument("--no-gepp", action="store_true", help="skip the GEPP comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--stage-steps", type=int, default=2,
+                    help="extra steps after the measured ones with every stage timed, for the "
+                         "stage breakdown (the measured steps time only the reported kernels)")
     ap.add_argument("--cpu-panels", type=int, default=4,
                     help="oracle sample: panels (of 256 columns) of the benchmarked elimination")
     ap.add_argument("--lookahead", type=int, default=-1, help="0/1 (-1: library default)")
@@ -204,7 +225,7 @@ def mixed_mode(args):
         step()
     torch.cuda.synchronize()
     rbt.timing_read()
-    rbt.timing_enable(True)
+    rbt.timing_enable(True, stages=("trailing",))
     iters = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -214,6 +235,7 @@ def mixed_mode(args):
     t1 = time.perf_counter()
     rbt.timing_enable(False)
     stages = rbt.timing_read()
+    breakdown = stage_breakdown(rbt, step, args.stage_steps)
     ms_step = (t1 - t0) * 1e3 / args.steps
     flops = (2.0 / 3.0) * n ** 3
     berr = float(be.item())
@@ -250,7 +272,7 @@ def mixed_mode(args):
                      "launches": tr_cnt, "avg_launch_ms": round(tr_ms / max(tr_cnt, 1), 4),
                      "flops_per_launch": tr_work / max(tr_cnt, 1)},
         "berr": berr, "berr_tol": tol, "converged": berr <= tol,
-        "stages_ms_per_step": {s_: round(v[0] / args.steps, 3) for s_, v in stages.items()},
+        "stages_ms_per_step": breakdown,
         "cpu_baseline": None,
     }
     if args.guarded:
@@ -436,7 +458,7 @@ def backward_mode(args):
         step()
     torch.cuda.synchronize()
     rbt.timing_read()
-    rbt.timing_enable(True)
+    rbt.timing_enable(True, stages=("outer",))
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
@@ -444,6 +466,7 @@ def backward_mode(args):
     ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
     rbt.timing_enable(False)
     stages = rbt.timing_read()
+    breakdown = stage_breakdown(rbt, step, args.stage_steps)
     flops = nb * (2.0 / 3.0) * n ** 3
     o_ms, o_cnt, o_bytes = stages["outer"]
     o_gbs = o_bytes / (o_ms * 1e-3) / 1e9 if o_ms > 0 else 0.0
@@ -485,7 +508,7 @@ def backward_mode(args):
         "systems_per_s": round(nb / (ms_step * 1e-3), 2),
         "max_forward_berr": worst["fwd"], "max_adjoint_berr": worst["bwd"] if not fp64 else None,
         "berr_tol": tol, "roofline": roofline, "gepp": gepp,
-        "stages_ms_per_step": {s_: round(v[0] / args.steps, 3) for s_, v in stages.items()},
+        "stages_ms_per_step": breakdown,
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
@@ -674,7 +697,10 @@ def main():
     torch.cuda.synchronize()
 
     rbt.timing_read()          # discard anything recorded so far
-    rbt.timing_enable(True)
+    # the measured steps time only the kernels this line reports (the
+    # trailing update and the transform); the stage breakdown comes from
+    # extra steps afterwards
+    rbt.timing_enable(True, stages=("trailing", "transform2", "pivoted"))
     iters = []
     marks = []
     torch.cuda.synchronize()
@@ -687,6 +713,8 @@ def main():
     t1 = time.perf_counter()
     rbt.timing_enable(False)
     stages = rbt.timing_read()
+    paths_measured = list(paths)
+    breakdown = stage_breakdown(rbt, step, args.stage_steps)
 
     ms_step = (t1 - t0) * 1e3 / args.steps
     flops = (2.0 / 3.0) * n ** 3
@@ -744,11 +772,11 @@ def main():
         "transform2": {"GB/s": round(k1_gbs, 1), "frac_hbm": round(k1_gbs / PEAK_HBM_GBS, 4),
                        "avg_ms": round(k1_ms / max(k1_cnt, 1), 4),
                        "bytes_per_launch": k1_bytes / max(k1_cnt, 1)},
-        "stages_ms_per_step": {s: round(v[0] / args.steps, 3) for s, v in stages.items()},
+        "stages_ms_per_step": breakdown,
         "step_ms": step_stats,
     }
     if args.guarded_solve:
-        out["paths"] = [int(p_.item()) for p_ in paths[-args.steps:]]
+        out["paths"] = [int(p_.item()) for p_ in paths_measured[-args.steps:]]
         if stages["pivoted"][1]:
             out["pivoted_ms_per_step"] = round(stages["pivoted"][0] / args.steps, 3)
 

@@ -523,8 +523,14 @@ int64_t rbt_get_option(int option);
  *   7 residual / norms / Eq. 7  work = bytes of A read
  *   8 pivoted factorization     work = flops 2/3 n^3 (the GEPP re-solve)
  *   9 adjoint outer product     work = bytes of dA written (8 n^2)
- * Disabled by default. Not thread safe. */
+ * Disabled by default. Not thread safe. Each timed scope records two events
+ * on the stream, a few microseconds of device time apiece: to time one
+ * kernel inside a measured run, restrict timing to its stage with
+ * RBT_OPT_TIMING_STAGES. */
 #define RBT_STAGE_COUNT 10
+/* RBT_OPT_TIMING_STAGES: stages timed while timing is enabled, bit s for
+ *   stage s (1 .. 2^RBT_STAGE_COUNT - 1; default: all stages). */
+#define RBT_OPT_TIMING_STAGES 13
 int rbt_timing_enable(int on);
 
 /* Waits for the recorded events and writes, for stages 0..nstages-1, the

@@ -25,6 +25,7 @@ void report_hip_error(hipError_t e, const char *what, const char *file, int line
 namespace {
 struct TimingState {
   bool on = false;
+  uint32_t mask = (1u << kStageCount) - 1;  // stages timed while on (RBT_OPT_TIMING_STAGES)
   struct Rec {
     int stage;
     hipEvent_t a, b;
@@ -41,7 +42,7 @@ TimingState &timing() {
 
 StageScope::StageScope(int stage, hipStream_t s, double work) : stage_(stage), s_(s) {
   TimingState &t = timing();
-  if (!t.on) return;
+  if (!t.on || ((t.mask >> stage) & 1u) == 0) return;
   if (hipEventCreate(&start_) != hipSuccess) {
     start_ = nullptr;
     return;
@@ -1709,6 +1710,10 @@ extern "C" int rbt_set_option(int option, int64_t value) {
       if (value != 0 && value != 1) return -2;
       options().capturable = value;
       return 0;
+    case RBT_OPT_TIMING_STAGES:
+      if (value < 1 || value >= (int64_t(1) << kStageCount)) return -2;
+      timing().mask = uint32_t(value);
+      return 0;
     default:
       return -1;
   }
@@ -1729,6 +1734,7 @@ extern "C" int64_t rbt_get_option(int option) {
     case RBT_OPT_BUTTERFLY: return options().kind;
     case RBT_OPT_SIDES: return options().sides;
     case RBT_OPT_CAPTURABLE: return options().capturable;
+    case RBT_OPT_TIMING_STAGES: return int64_t(timing().mask);
     default: return -1;
   }
 }

@@ -405,8 +405,12 @@ def backward_error(A, X, B, work=None):
     return berr
 
 
-def timing_enable(on=True):
-    """Record HIP events around each stage of the composite entry points."""
+def timing_enable(on=True, stages=None):
+    """Record HIP events around each stage of the composite entry points
+    (stages: names from _lib.STAGES to time; None: all of them)."""
+    mask = ((1 << _lib.RBT_STAGE_COUNT) - 1 if stages is None
+            else sum(1 << _lib.STAGES.index(s) for s in stages))
+    set_option(_lib.RBT_OPT_TIMING_STAGES, mask)
     check(lib().rbt_timing_enable(1 if on else 0), "rbt_timing_enable")
 
 

@@ -338,3 +338,34 @@ def test_lookahead_factors_identical(rbt, n, W):
     finally:
         rbt.set_option(rbt._lib.RBT_OPT_LOOKAHEAD, 0)
         rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, old_w)
+
+
+def test_stage_timing_mask(rbt):
+    """RBT_OPT_TIMING_STAGES restricts the timed scopes to the chosen stages
+    (the benchmark times only the kernel it reports inside measured steps);
+    the factors do not depend on it."""
+    from paper_2312_09376_amd import _lib
+    n = 2100  # two panels of width 1024 plus the remainder: two trailing updates
+    A = dev(workloads.shifted(n, seed=4))
+    try:
+        rbt.timing_read()
+        rbt.timing_enable(True, stages=("trailing",))
+        LU1, _ = rbt.genp(A)
+        torch.cuda.synchronize()
+        rbt.timing_enable(False)
+        t = rbt.timing_read()
+        assert t["trailing"][1] > 0 and t["trailing"][0] > 0
+        assert all(v[1] == 0 for k, v in t.items() if k != "trailing"), t
+        rbt.timing_enable(True)
+        LU2, _ = rbt.genp(A)
+        torch.cuda.synchronize()
+        rbt.timing_enable(False)
+        t = rbt.timing_read()
+        assert t["diag"][1] > 0 and t["panel"][1] > 0 and t["trailing"][1] > 0
+        assert torch.equal(LU1, LU2)
+        with pytest.raises(_lib.RBTError):
+            rbt.set_option(_lib.RBT_OPT_TIMING_STAGES, 0)
+    finally:
+        rbt.timing_enable(False)
+        rbt.set_option(_lib.RBT_OPT_TIMING_STAGES, (1 << _lib.RBT_STAGE_COUNT) - 1)
+        rbt.timing_read()
