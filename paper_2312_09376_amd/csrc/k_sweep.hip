@@ -152,10 +152,10 @@ __global__ void __launch_bounds__(TPB)
       bpre[c] = (sg == 0 && i < kb && c < N) ? C(B[(r0 + i) + int64_t(c) * ldb]) : C(0);
   }
 
-  // One right-hand side with FP64 factors: the diagonal block of the
-  // refinement step is loaded here too (after the last wait its memory
-  // latency would sit on the sweep's critical path).
-  constexpr bool PRE_T = REFINE && NMAX == 1;
+  // The diagonal block of the refinement step is loaded here too where
+  // registers allow (one right-hand side; FP32 factors up to eight): after
+  // the last wait its memory latency would sit on the sweep's critical path.
+  constexpr bool PRE_T = REFINE && (NMAX == 1 || (sizeof(TF) == 4 && NMAX <= 8));
   TF etp[PRE_T ? SEGW : 1];
   if constexpr (PRE_T) load_tdiag(etp);
 
@@ -173,28 +173,67 @@ __global__ void __launch_bounds__(TPB)
       const int col = sg * SEGW + q;
       e[q] = op_e<MODE>(A, ld, r0 + ir, c0 + (col < cb ? col : cb - 1));
     }
-    // x_j from P, each entry polled until published (bounded)
+    // x_j from P, each entry polled until published (bounded). A thread's
+    // entries (two or four with 8 or 16 right-hand sides) are all loaded
+    // before any is waited on, so a published block costs one round trip.
     bool expired = false;
-    for (int idx = tid; idx < kNB * NMAX; idx += TPB) {
-      const int k = idx / NMAX, c = idx % NMAX;
-      C v = C(0);
-      if (k < cb && c < N) {
-        const double *p = pub + (c0 + k) + int64_t(c) * n;
-        double xv = coherent_load(p);
-        int64_t spins = 0;
-        while (unpublished(xv)) {
-          if (spins >= spin_limit) {  // expired: NaN for this entry, poison this block
-            expired = true;
-            xv = __builtin_nan("");
-            break;
+    constexpr int PER = (kNB * NMAX + TPB - 1) / TPB;
+    // entry (k, c) sits at P[(c0 + k) + c n]: consecutive lanes take
+    // consecutive k, so a wavefront's polls read contiguous memory
+    if constexpr (PER == 1) {
+      const int k = tid % kNB, c = tid / kNB;
+      if (tid < kNB * NMAX) {
+        C v = C(0);
+        if (k < cb && c < N) {
+          const double *p = pub + (c0 + k) + int64_t(c) * n;
+          double xv = coherent_load(p);
+          int64_t spins = 0;
+          while (unpublished(xv)) {
+            if (spins >= spin_limit) {  // expired: NaN for this entry, poison this block
+              expired = true;
+              xv = __builtin_nan("");
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            ++spins;
+            xv = coherent_load(p);
           }
-          __builtin_amdgcn_s_sleep(1);
-          ++spins;
-          xv = coherent_load(p);
+          v = C(xv);
         }
-        v = C(xv);
+        xs[k][c] = v;
       }
-      xs[k][c] = v;
+    } else {
+      double xv[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * TPB;
+        const int k = idx % kNB, c = idx / kNB;
+        xv[q] = 0.0;
+        if (idx < kNB * NMAX && k < cb && c < N) xv[q] = coherent_load(pub + (c0 + k) + int64_t(c) * n);
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * TPB;
+        const int k = idx % kNB, c = idx / kNB;
+        if (idx >= kNB * NMAX) continue;
+        C v = C(0);
+        if (k < cb && c < N) {
+          const double *p = pub + (c0 + k) + int64_t(c) * n;
+          int64_t spins = 0;
+          while (unpublished(xv[q])) {
+            if (spins >= spin_limit) {  // expired: NaN for this entry, poison this block
+              expired = true;
+              xv[q] = __builtin_nan("");
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            ++spins;
+            xv[q] = coherent_load(p);
+          }
+          v = C(xv[q]);
+        }
+        xs[k][c] = v;
+      }
     }
     if (expired) {
       __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
