@@ -112,6 +112,9 @@ def parse():
                          "refinement cannot reach tol (max-iter is then its budget)")
     ap.add_argument("--max-iter64", type=int, default=10, help="guarded mixed mode: FP64 budget")
     ap.add_argument("--batch", type=int, default=2048, help="batched mode: number of systems")
+    ap.add_argument("--streams", type=int, default=16,
+                    help="backward mode: host threads, one stream each, over which the "
+                         "independent systems are dealt")
     ap.add_argument("--batch-n", type=int, default=0,
                     help="batched mode: all systems of this order (0: n ~ U{37..1500})")
     ap.add_argument("--batch-nrhs", type=int, default=0,
@@ -452,8 +455,13 @@ def backward_mode(args):
     `batch` systems: A_s = N(0,1)/sqrt(n) + I (seed 42 + s), B_s, G_s ~ N(0,1)
     (n x nrhs). fp64: FP64 solve with refinement and the FP64 adjoint;
     fp32/bf16: low-precision factors with FP64 GMRES refinement forward and
-    FP64 refinement of the adjoint solve."""
+    FP64 refinement of the adjoint solve. The systems are independent: they
+    are dealt round-robin to `--streams` host threads, each with its own
+    stream, factors and workspace (the elimination of one system at these
+    sizes is a chain of latency-bound launches that fills a fraction of the
+    GPU)."""
     import torch
+    from concurrent.futures import ThreadPoolExecutor
     from paper_2312_09376_amd import rbt, workloads
     n, k, d = args.n, args.nrhs, args.depth
     nb = args.batch
@@ -467,29 +475,44 @@ def backward_mode(args):
     Gs = [workloads.device_randn(n, k, 1000 + s_) for s_ in range(nb)]
     fp64 = args.prec == "fp64"
     prec = {"fp32": rbt.RBT_FP32, "bf16": rbt.RBT_BF16, "fp64": rbt.RBT_FP64}[args.prec]
-    LU = torch.empty_strided((n, n), (1, n), dtype=torch.float64 if fp64 else torch.float32,
-                             device="cuda")
-    X = torch.empty_strided((n, k), (1, n), dtype=torch.float64, device="cuda")
-    work = rbt._workspace(n, k, d, As[0].device, prec)
+    S = max(1, min(args.streams, nb))
+    streams = [torch.cuda.Stream() for _ in range(S)]  # default priority
+    bufs = []
+    for _ in range(S):
+        LU = torch.empty_strided((n, n), (1, n), dtype=torch.float64 if fp64 else torch.float32,
+                                 device="cuda")
+        X = torch.empty_strided((n, k), (1, n), dtype=torch.float64, device="cuda")
+        bufs.append((LU, X, rbt._workspace(n, k, d, As[0].device, prec)))
     torch.cuda.synchronize()
-    worst = {"fwd": 0.0, "bwd": 0.0}
+    errs = []  # (forward berr, adjoint berr or None) tensors, read after the timing
+
+    def part(t_, stride=S):
+        LU, X, work = bufs[t_]
+        out = []
+        with torch.cuda.stream(streams[t_]):
+            for i_ in range(t_, nb, stride):
+                A, B, G = As[i_], Bs[i_], Gs[i_]
+                if fp64:
+                    _, _, _, be, _, _ = rbt.solve_refine(A, B, d, args.seed, tol=tol,
+                                                         max_iter=args.max_iter, LU=LU, X=X,
+                                                         work=work)
+                    dA, dB = rbt.solve_backward(LU, X, G, d, args.seed, work=work)
+                    bb = None
+                else:
+                    _, _, _, be, _, _ = rbt.solve_mixed(A, B, d, args.seed, prec=prec,
+                                                        solver=rbt.RBT_IR_GMRES, tol=tol,
+                                                        max_iter=args.max_iter, LU=LU, X=X,
+                                                        work=work)
+                    dA, dB, _, bb = rbt.solve_backward_mixed(LU, A, X, G, d, args.seed, tol=tol,
+                                                             max_iter=args.max_iter, work=work)
+                out.append((be, bb))
+        return out
+
+    pool = ThreadPoolExecutor(max_workers=S)
 
     def step():
-        for A, B, G in zip(As, Bs, Gs):
-            if fp64:
-                _, _, _, be, _, _ = rbt.solve_refine(A, B, d, args.seed, tol=tol,
-                                                     max_iter=args.max_iter, LU=LU, X=X, work=work)
-                dA, dB = rbt.solve_backward(LU, X, G, d, args.seed, work=work)
-                bb = None
-            else:
-                _, _, _, be, _, _ = rbt.solve_mixed(A, B, d, args.seed, prec=prec,
-                                                    solver=rbt.RBT_IR_GMRES, tol=tol,
-                                                    max_iter=args.max_iter, LU=LU, X=X, work=work)
-                dA, dB, _, bb = rbt.solve_backward_mixed(LU, A, X, G, d, args.seed, tol=tol,
-                                                         max_iter=args.max_iter, work=work)
-            worst["fwd"] = max(worst["fwd"], float(be.item()))
-            if bb is not None:
-                worst["bwd"] = max(worst["bwd"], float(bb.item()))
+        for out in pool.map(part, range(S)):
+            errs.extend(out)
 
     for _ in range(args.warmup):
         step()
@@ -503,7 +526,18 @@ def backward_mode(args):
     ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
     rbt.timing_enable(False)
     stages = rbt.timing_read()
+    if S > 1:
+        # in the timed steps the dA launches share the GPU with the other
+        # streams' work; the kernel's own rate is timed in one pass over the
+        # systems on one stream
+        rbt.timing_enable(True, stages=("outer",))
+        errs.extend(part(0, 1))
+        torch.cuda.synchronize()
+        rbt.timing_enable(False)
+        stages = rbt.timing_read()
     breakdown = stage_breakdown(rbt, step, args.stage_steps)
+    worst = {"fwd": max(float(e[0].item()) for e in errs),
+             "bwd": max((float(e[1].item()) for e in errs if e[1] is not None), default=0.0)}
     flops = nb * (2.0 / 3.0) * n ** 3
     o_ms, o_cnt, o_bytes = stages["outer"]
     o_gbs = o_bytes / (o_ms * 1e-3) / 1e9 if o_ms > 0 else 0.0
@@ -511,18 +545,24 @@ def backward_mode(args):
                 "achieved": round(o_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(o_gbs / PEAK_HBM_GBS, 4), "traffic": None,
                 "algorithmic_bytes_per_launch": 8.0 * n * n, "launches": o_cnt,
-                "avg_launch_ms": round(o_ms / max(o_cnt, 1), 4)}
+                "avg_launch_ms": round(o_ms / max(o_cnt, 1), 4),
+                "timed": "in the timed steps" if S == 1 else "one pass on one stream"}
     # FP64 partial pivoting on the same GPU: factor, solve, adjoint solve
     # with the same factors and the outer product, per system
     gepp = None
     if not args.no_gepp:
-        def gepp_step():
-            for A, B, G in zip(As, Bs, Gs):
-                LUp, piv = torch.linalg.lu_factor(A)
-                Xp = torch.linalg.lu_solve(LUp, piv, B)
-                lam = torch.linalg.lu_solve(LUp, piv, G, adjoint=True)
-                dAp = -(lam @ Xp.t())
+        def gepp_part(t_):
+            with torch.cuda.stream(streams[t_]):
+                for i_ in range(t_, nb, S):
+                    A, B, G = As[i_], Bs[i_], Gs[i_]
+                    LUp, piv = torch.linalg.lu_factor(A)
+                    Xp = torch.linalg.lu_solve(LUp, piv, B)
+                    lam = torch.linalg.lu_solve(LUp, piv, G, adjoint=True)
+                    dAp = -(lam @ Xp.t())
             return Xp, lam, dAp
+
+        def gepp_step():  # the same streams and threads as the solves
+            return list(pool.map(gepp_part, range(S)))[(nb - 1) % S]
         gepp_step()
         torch.cuda.synchronize()
         g0 = time.perf_counter()
@@ -541,13 +581,16 @@ def backward_mode(args):
         "data": "synthetic",
         "config": {"workload": f"{nb} systems, n={n}, nrhs={k}, depth {d}, A=N(0,1)/sqrt(n)+I "
                                f"(seed 42+s), forward {args.prec.upper()} solve to 10 n eps + "
-                               f"adjoint with dA", "batch": nb, "n": n, "nrhs": k, "depth": d},
+                               f"adjoint with dA", "batch": nb, "n": n, "nrhs": k, "depth": d,
+                   "streams": S},
         "systems_per_s": round(nb / (ms_step * 1e-3), 2),
         "max_forward_berr": worst["fwd"], "max_adjoint_berr": worst["bwd"] if not fp64 else None,
         "berr_tol": tol, "roofline": roofline, "gepp": gepp,
         "stages_ms_per_step": breakdown,
         "cpu_baseline": None,
     }
+    if S > 1:
+        out["stages_note"] = "stage times are summed over the concurrent streams"
     print(json.dumps(out), flush=True)
 
 

@@ -21,9 +21,12 @@ void report_hip_error(hipError_t e, const char *what, const char *file, int line
 // ---- stage timing ----
 // When enabled, composite entry points bracket each stage with a pair of HIP
 // events on the caller's stream; rbt_timing_read waits for them and returns
-// per-stage totals. Off by default (no events are recorded).
+// per-stage totals. Off by default (no events are recorded). The records
+// are guarded by a mutex: calls on several host threads (one stream each)
+// may be timed together.
 namespace {
 struct TimingState {
+  std::mutex mu;
   bool on = false;
   uint32_t mask = (1u << kStageCount) - 1;  // stages timed while on (RBT_OPT_TIMING_STAGES)
   struct Rec {
@@ -48,6 +51,7 @@ StageScope::StageScope(int stage, hipStream_t s, double work) : stage_(stage), s
     return;
   }
   hipEventRecord(start_, s_);
+  std::lock_guard<std::mutex> lock(t.mu);
   t.work[stage] += work;
   t.launches[stage] += 1;
 }
@@ -60,7 +64,9 @@ StageScope::~StageScope() {
     return;
   }
   hipEventRecord(end, s_);
-  timing().recs.push_back({stage_, start_, end});
+  TimingState &t = timing();
+  std::lock_guard<std::mutex> lock(t.mu);
+  t.recs.push_back({stage_, start_, end});
 }
 
 namespace {
@@ -1554,6 +1560,7 @@ extern "C" int rbt_timing_enable(int on) {
 extern "C" int rbt_timing_read(int nstages, double *ms, int64_t *launches, double *work) {
   if (nstages < 0) return -1;
   TimingState &t = timing();
+  std::lock_guard<std::mutex> lock(t.mu);
   double acc[kStageCount] = {};
   int rc = 0;
   for (auto &r : t.recs) {
