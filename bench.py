@@ -34,12 +34,14 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 KERNEL_TRAFFIC = {
     "fp64": {"source": "paper_2312_09376_amd/csrc/k_gemm.hip",
              "sha256": "cd064f89968f0e242177948f6fad7a7d0a8deea95567454ad17bee080fbabd6a",
-             "config": {"n": 20000, "nrhs": 1, "depth": 2, "outer_nb": 1024},
-             "bytes_per_launch": (2 * 2178986.5 + 985088.0) * 1024},
+             "config": {"n": 20000, "nrhs": 1, "depth": 2, "outer_nb": 2048},
+             "bytes_per_launch": (2 * 3752645.5 + 957781.3) * 1024},
     "bf16": {"source": "paper_2312_09376_amd/csrc/k_hgemm.hip",
              "sha256": "a2e326c4190c3373b06045510896c621b5b597abc03e3147a85aefe0e7c2de42",
-             "config": {"n": 32768, "nrhs": 1, "depth": 2, "outer_nb": 1024, "matrix": "dominant"},
-             "bytes_per_launch": (2 * 1424417.0 + 1461608.6) * 1024},
+             "config": {"n": 32768, "nrhs": 1, "depth": 2, "outer_nb": 2048, "matrix": "dominant"},
+             # k_hgemm plus its two operand conversions (the timed trailing stage)
+             "bytes_per_launch": ((2 * 1811397.4 + 1448020.9) + (2 * 65548.8 + 109875.7)
+                                  + (2 * 65561.2 + 65536.0)) * 1024},
     "batched_fp32": {"source": "paper_2312_09376_amd/csrc/k_batched.hip",
                      "sha256": "3e931707a2cec70653f35bda832c91770d0af62339d4936353ee0a6cb2850d32",
                      "config": {"batch": 2048, "depth": 2, "matrix": "randn"},
@@ -96,6 +98,9 @@ def parse():
     ap.add_argument("--cpu-panels", type=int, default=4,
                     help="oracle sample: panels (of 256 columns) of the benchmarked elimination")
     ap.add_argument("--lookahead", type=int, default=-1, help="0/1 (-1: library default)")
+    ap.add_argument("--panel-split", type=int, default=-1,
+                    help="order inside a panel: 0 block by block, 1 recursive halves "
+                         "(-1: library default)")
     ap.add_argument("--outer-nb", type=int, default=0,
                     help="panel width of the elimination (multiple of 128; 0 = library default)")
     ap.add_argument("--mode", choices=["solve", "mixed", "batched", "backward", "copy", "small"],
@@ -195,6 +200,8 @@ def mixed_mode(args):
         rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, args.outer_nb)
     if args.lookahead >= 0:
         rbt.set_option(rbt._lib.RBT_OPT_LOOKAHEAD, args.lookahead)
+    if args.panel_split >= 0:
+        rbt.set_option(rbt._lib.RBT_OPT_PANEL_SPLIT, args.panel_split)
 
     n, k, d = args.n, args.nrhs, args.depth
     tol = 10.0 * n * 2.0 ** -52
@@ -307,7 +314,8 @@ def mixed_mode(args):
                                f"refinement to berr<=10*n*eps, n={n}, nrhs={k}, depth {d}, "
                                f"A={args.matrix} seed 42, b~N(0,1) seed 64",
                    "n": n, "nrhs": k, "depth": d, "outer_nb": W, "matrix": args.matrix,
-                   "lookahead": rbt.get_option(rbt._lib.RBT_OPT_LOOKAHEAD)},
+                   "lookahead": rbt.get_option(rbt._lib.RBT_OPT_LOOKAHEAD),
+                   "panel_split": rbt.get_option(rbt._lib.RBT_OPT_PANEL_SPLIT)},
         "roofline": roofline,
         "berr": berr, "berr_tol": tol, "converged": berr <= tol,
         "stages_ms_per_step": breakdown,
@@ -741,6 +749,8 @@ def main():
         rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, args.outer_nb)
     if args.lookahead >= 0:
         rbt.set_option(rbt._lib.RBT_OPT_LOOKAHEAD, args.lookahead)
+    if args.panel_split >= 0:
+        rbt.set_option(rbt._lib.RBT_OPT_PANEL_SPLIT, args.panel_split)
 
     n, k, d = args.n, args.nrhs, args.depth
     tol = 10.0 * n * 2.0 ** -52
@@ -834,7 +844,8 @@ def main():
                                + (", partial-pivoting fallback" if args.guarded_solve else ""),
                    "n": n, "nrhs": k, "depth": d, "matrix": args.matrix,
                    "outer_nb": rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB),
-                   "lookahead": rbt.get_option(rbt._lib.RBT_OPT_LOOKAHEAD)},
+                   "lookahead": rbt.get_option(rbt._lib.RBT_OPT_LOOKAHEAD),
+                   "panel_split": rbt.get_option(rbt._lib.RBT_OPT_PANEL_SPLIT)},
         "roofline": {"bound": "mfma", "kernel": "trailing-update GEMM (k_dgemm, FP64 MFMA)",
                      "achieved": round(gemm_tflops, 3), "peak": PEAK_FP64_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(gemm_tflops / PEAK_FP64_MFMA_TFLOPS, 4),

@@ -413,7 +413,7 @@ int rbt_solve_backward_mixed(int64_t n, int64_t nrhs, const float *LU, int64_t l
 
 /* Tuning options (process-wide; not thread safe).
  * RBT_OPT_OUTER_NB: width of the panels of the elimination whose trailing
- *   update is a single GEMM (multiple of 128, 128..2048; default 1024). The
+ *   update is a single GEMM (multiple of 128, 128..2048; default 2048). The
  *   first panel also takes the n mod 128 columns that do not fill a 128-wide
  *   diagonal block (except with BF16 updates), so that every trailing update
  *   covers whole 128-blocks. Changes only the order of the roundings, not
@@ -505,6 +505,17 @@ int rbt_solve_backward_mixed(int64_t n, int64_t nrhs, const float *LU, int64_t l
  *   as RBT_ERR_SYNC in this mode: the poisoned solution gives a NaN
  *   backward error. */
 #define RBT_OPT_CAPTURABLE 11
+/* RBT_OPT_PANEL_SPLIT: order of the work inside a panel of the elimination
+ *   (every entry point that factors). 0: one 128-wide diagonal
+ *   block after another, each followed by a depth-128 update of the panel's
+ *   remaining columns and block rows. 1: recursive halves: the left half of
+ *   the panel (whole 128-blocks) is factored first, then one update of
+ *   depth = its width, then the right half, recursively down to 128. Every
+ *   element receives the same updates, grouped into fewer, deeper products
+ *   (a different order of the roundings, not a different method); the
+ *   lookahead's block-row solves follow the same order, so the factors stay
+ *   identical with and without lookahead. Default 1. */
+#define RBT_OPT_PANEL_SPLIT 14
 /* Returns 0, -1 for an unknown option, -2 for an invalid value. */
 int rbt_set_option(int option, int64_t value);
 /* Current value, or -1 for an unknown option. */

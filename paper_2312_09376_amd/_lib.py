@@ -78,6 +78,7 @@ RBT_OPT_SIDES = 10
 RBT_OPT_CAPTURABLE = 11
 RBT_OPT_BATCH_TILE_COLS2_MIN_N = 12
 RBT_OPT_TIMING_STAGES = 13
+RBT_OPT_PANEL_SPLIT = 14
 STAGES = ["generate", "transform2", "transform_vec", "diag", "panel", "trailing", "solve",
           "residual", "pivoted", "outer"]
 

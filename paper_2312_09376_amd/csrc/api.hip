@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <cstdlib>
+#include <functional>
 #include <mutex>
 #include <vector>
 
@@ -75,7 +76,7 @@ inline int64_t nblocks(int64_t n) { return (n + kNB - 1) / kNB; }
 
 // Tunable options (rbt_set_option).
 struct Options {
-  int64_t outer_nb = 1024;  // width of the panel whose trailing update is one GEMM
+  int64_t outer_nb = 2048;  // width of the panel whose trailing update is one GEMM
   // batched: systems with n >= this take two 64-column tiles per round of
   // the low-precision trailing update, the others one (INT64_MAX: one for all)
   int64_t batch_ct2_min_n = INT64_MAX;
@@ -89,6 +90,7 @@ struct Options {
   int64_t kind = 0;              // butterflies: 0 Eq. 3 (random diagonals), 1 rotations
   int64_t sides = 2;             // 2: U^T A V; 1: U^T A (one-sided)
   int64_t capturable = 0;        // refinement without host tests (graph capturable)
+  int64_t panel_split = 1;       // panel: 0 one 128-block after another, 1 recursive halves
 };
 Options &options() {
   static Options o;
@@ -329,7 +331,69 @@ int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t
   // the block joins the panel's own update in one launch (the same
   // operations on every element as solving the block row after the panel,
   // in fewer launches). ----
+  const bool halves = options().panel_split != 0;
+  // ---- recursive order of the same panel (RBT_OPT_PANEL_SPLIT = 1): the
+  // columns [k, k + w) of a panel whose block-row solves reach column e are
+  // split into a left part of ceil(blocks / 2) whole 128-blocks and the
+  // rest. The left part is factored first (its diagonal blocks' left solves
+  // reach column e); then, with depth h = its width, the rows below it are
+  // updated in the right part's columns and the right part's rows in the
+  // columns beyond it (up to e), in one launch; then the right part. Every
+  // element receives the same updates as in the block-by-block order, in
+  // fewer and deeper products: the depth-128 updates become depth-h ones
+  // (h up to W / 2), which run closer to the matrix cores' rate and read
+  // and write the panel's columns fewer times. ----
+  std::function<int(int64_t, int64_t, int64_t)> halves_panel =
+      [&](int64_t k, int64_t w, int64_t e) -> int {
+    if (w <= kNB) {
+      const int kb = int(w);
+      T *A11 = A + k + k * lda;
+      {
+        StageScope t(kStageDiag, s, 2.0 / 3.0 * double(kb) * kb * kb);
+        RBT_HIP_CHECK(diag_lu(kb, A11, lda, k, info, s));
+      }
+      const int64_t rows = n - k - kb, cols = e - k - kb;
+      StageScope t(kStagePanel, s, double(rows) * kb * kb + double(cols) * kb * kb);
+      RBT_HIP_CHECK(panel_trsm(kb, rows, cols, A11, lda, A + (k + kb) + k * lda,
+                               A + k + (k + kb) * lda, lda, s));
+      return 0;
+    }
+    const int64_t h = ((w + kNB - 1) / kNB + 1) / 2 * kNB;
+    int rc = halves_panel(k, h, e);
+    if (rc) return rc;
+    const int64_t rows = n - k - h, wr = w - h, beyond = e - k - w;
+    {
+      StageScope t(kStagePanel, s, 2.0 * double(h) * (double(rows) * wr + double(wr) * beyond));
+      RBT_HIP_CHECK(gemm_sub2(h, lda, rows, wr, A + (k + h) + k * lda, A + k + (k + h) * lda,
+                              A + (k + h) + (k + h) * lda, wr, beyond, A + (k + h) + k * lda,
+                              A + k + (k + w) * lda, A + (k + h) + (k + w) * lda, prec, s));
+    }
+    return halves_panel(k + h, wr, e);
+  };
+  // ---- block rows U12 = L11^-1 A12 of the columns [c0, c0 + nc) for the
+  // panel rows [k, k + w), in the recursive order above (used by the
+  // lookahead's updates, so that they give the same factors as the panel's
+  // own block-row solves) ----
+  std::function<int(int64_t, int64_t, int64_t, int64_t, hipStream_t)> halves_rows =
+      [&](int64_t k, int64_t w, int64_t c0, int64_t nc, hipStream_t st) -> int {
+    if (w <= kNB) {
+      StageScope t(kStagePanel, st, double(nc) * w * w);
+      RBT_HIP_CHECK(trsm_left(TriMode::LN, int(w), nc, A + k + k * lda, lda, A + k + c0 * lda,
+                              lda, st));
+      return 0;
+    }
+    const int64_t h = ((w + kNB - 1) / kNB + 1) / 2 * kNB;
+    int rc = halves_rows(k, h, c0, nc, st);
+    if (rc) return rc;
+    {
+      StageScope t(kStagePanel, st, 2.0 * double(w - h) * nc * h);
+      RBT_HIP_CHECK(gemm_sub(w - h, nc, h, A + (k + h) + k * lda, lda, A + k + c0 * lda, lda,
+                             A + (k + h) + c0 * lda, lda, prec, false, st));
+    }
+    return halves_rows(k + h, w - h, c0, nc, st);
+  };
   auto panel = [&](int64_t k0, int64_t w, int64_t nt) -> int {
+    if (halves) return halves_panel(k0, w, k0 + w + nt);
     for (int64_t k = k0; k < k0 + w; k += kNB) {
       const int kb = int(k0 + w - k < kNB ? k0 + w - k : kNB);
       T *A11 = A + k + k * lda;
@@ -359,6 +423,11 @@ int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t
   // of depth w (on stream st) ----
   auto update = [&](int64_t k0, int64_t w, int64_t c0, int64_t nc, hipStream_t st,
                     bool rows_done) -> int {
+    if (halves && !rows_done) {
+      const int rc = halves_rows(k0, w, c0, nc, st);
+      if (rc) return rc;
+      rows_done = true;
+    }
     for (int64_t k = k0; k < k0 + w && !rows_done; k += kNB) {
       const int kb = int(k0 + w - k < kNB ? k0 + w - k : kNB);
       const int64_t below = k0 + w - k - kb;
@@ -1717,6 +1786,10 @@ extern "C" int rbt_set_option(int option, int64_t value) {
       if (value != 0 && value != 1) return -2;
       options().capturable = value;
       return 0;
+    case RBT_OPT_PANEL_SPLIT:
+      if (value != 0 && value != 1) return -2;
+      options().panel_split = value;
+      return 0;
     case RBT_OPT_TIMING_STAGES:
       if (value < 1 || value >= (int64_t(1) << kStageCount)) return -2;
       timing().mask = uint32_t(value);
@@ -1741,6 +1814,7 @@ extern "C" int64_t rbt_get_option(int option) {
     case RBT_OPT_BUTTERFLY: return options().kind;
     case RBT_OPT_SIDES: return options().sides;
     case RBT_OPT_CAPTURABLE: return options().capturable;
+    case RBT_OPT_PANEL_SPLIT: return options().panel_split;
     case RBT_OPT_TIMING_STAGES: return int64_t(timing().mask);
     default: return -1;
   }

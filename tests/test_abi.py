@@ -32,6 +32,38 @@ def test_version(lib):
     assert lib.rbt_version() >= 100
 
 
+def test_option_constants_match_header():
+    """The binding's option and stage constants are the header's #defines."""
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"#define\s+(RBT_(?:OPT|STAGE)_[A-Z0-9_]+)\s+(\d+)", text))
+    assert len(defs) >= 14
+    for name, value in defs.items():
+        assert getattr(_lib, name) == int(value), name
+
+
+def test_panel_options(lib):
+    """Panel width and panel order: defaults, accepted values, rejected
+    values (-2), host-only (no GPU call)."""
+    lib.rbt_get_option.restype = ctypes.c_int64
+    lib.rbt_set_option.argtypes = [ctypes.c_int, ctypes.c_int64]
+    get = lambda o: lib.rbt_get_option(o)
+    w0, s0 = get(_lib.RBT_OPT_OUTER_NB), get(_lib.RBT_OPT_PANEL_SPLIT)
+    assert (w0, s0) == (2048, 1)
+    try:
+        for v in (0, 1):
+            assert lib.rbt_set_option(_lib.RBT_OPT_PANEL_SPLIT, v) == 0
+            assert get(_lib.RBT_OPT_PANEL_SPLIT) == v
+        assert lib.rbt_set_option(_lib.RBT_OPT_PANEL_SPLIT, 2) == -2
+        assert lib.rbt_set_option(_lib.RBT_OPT_PANEL_SPLIT, -1) == -2
+        for v in (128, 1152, 2048):
+            assert lib.rbt_set_option(_lib.RBT_OPT_OUTER_NB, v) == 0
+        for v in (0, 100, 2176):
+            assert lib.rbt_set_option(_lib.RBT_OPT_OUTER_NB, v) == -2
+    finally:
+        lib.rbt_set_option(_lib.RBT_OPT_OUTER_NB, w0)
+        lib.rbt_set_option(_lib.RBT_OPT_PANEL_SPLIT, s0)
+
+
 @pytest.mark.parametrize("d", [0, 1, 2, 3, 4, 6])
 def test_structure_bit_exact(lib, d):
     for n in list(range(0, 70)) + [127, 128, 129, 1000, 1001, 1003, 4099]:

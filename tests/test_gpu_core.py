@@ -135,8 +135,9 @@ def test_genp_matches_oracle(rbt, n):
     assert np.abs(L - LUo).max() <= 1e-12 * max(1.0, np.abs(LUo).max())
 
 
-@pytest.mark.parametrize("n,W", [(700, 256), (1290, 512), (640, 128), (1000, 384)])
-def test_genp_multi_panel_matches_oracle(rbt, n, W):
+@pytest.mark.parametrize("split", [0, 1])
+@pytest.mark.parametrize("n,W", [(700, 256), (1290, 512), (640, 128), (1000, 384), (2500, 1152)])
+def test_genp_multi_panel_matches_oracle(rbt, n, W, split):
     """Several panels (Sec. 1, step 2: GENP): the first panel also takes the
     n mod 128 columns, the trailing updates cover whole 128 x 128 tiles, and
     each diagonal block's left solve and depth-128 updates reach the block
@@ -144,16 +145,21 @@ def test_genp_multi_panel_matches_oracle(rbt, n, W):
     unblocked elimination on I + 0.3 N(0,1)/sqrt(n), whose leading minors are
     all well conditioned (without pivoting, a matrix with ill-conditioned
     leading minors amplifies the different rounding order of the blocked
-    elimination), and L U = A to the rounding bound of elimination."""
+    elimination), and L U = A to the rounding bound of elimination. Both
+    orders of the work inside a panel: block by block, and recursive halves
+    (RBT_OPT_PANEL_SPLIT), whose deeper updates regroup the same products."""
     A = workloads.dominant(n, seed=n + 7)
     LUo, info_o = osolve.genp_unblocked(A)
     old_w = rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)
+    old_s = rbt.get_option(rbt._lib.RBT_OPT_PANEL_SPLIT)
     rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, W)
+    rbt.set_option(rbt._lib.RBT_OPT_PANEL_SPLIT, split)
     try:
         LU, info = rbt.genp(dev(A))
         torch.cuda.synchronize()
     finally:
         rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, old_w)
+        rbt.set_option(rbt._lib.RBT_OPT_PANEL_SPLIT, old_s)
     assert int(info.item()) == info_o == 0
     L = host(LU)
     assert np.abs(L - LUo).max() <= 1e-12 * max(1.0, np.abs(LUo).max())
@@ -309,14 +315,19 @@ def test_backward_error_kernel(rbt):
     assert math.isclose(float(be.item()), be_o, rel_tol=1e-9)
 
 
+@pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("n,W", [(3000, 1024), (1000, 256), (2200, 512)])
-def test_lookahead_factors_identical(rbt, n, W):
+def test_lookahead_factors_identical(rbt, n, W, split):
     """The lookahead only reorders launches over disjoint columns on two
     streams: FP64, FP32 and BF16-update factors are bit-identical with it on
-    and off, and the mixed solves give the same solution."""
+    and off, and the mixed solves give the same solution; in both orders of
+    the work inside a panel (the lookahead's block-row solves follow the
+    panel's order)."""
     A = workloads.shifted(n, seed=n)
     old_w = rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)
+    old_s = rbt.get_option(rbt._lib.RBT_OPT_PANEL_SPLIT)
     rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, W)
+    rbt.set_option(rbt._lib.RBT_OPT_PANEL_SPLIT, split)
     try:
         out = {}
         for la in (0, 1):
@@ -338,6 +349,7 @@ def test_lookahead_factors_identical(rbt, n, W):
     finally:
         rbt.set_option(rbt._lib.RBT_OPT_LOOKAHEAD, 0)
         rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, old_w)
+        rbt.set_option(rbt._lib.RBT_OPT_PANEL_SPLIT, old_s)
 
 
 def test_stage_timing_mask(rbt):
@@ -347,6 +359,8 @@ def test_stage_timing_mask(rbt):
     from paper_2312_09376_amd import _lib
     n = 2100  # two panels of width 1024 plus the remainder: two trailing updates
     A = dev(workloads.shifted(n, seed=4))
+    old_w = rbt.get_option(_lib.RBT_OPT_OUTER_NB)
+    rbt.set_option(_lib.RBT_OPT_OUTER_NB, 1024)
     try:
         rbt.timing_read()
         rbt.timing_enable(True, stages=("trailing",))
@@ -368,4 +382,5 @@ def test_stage_timing_mask(rbt):
     finally:
         rbt.timing_enable(False)
         rbt.set_option(_lib.RBT_OPT_TIMING_STAGES, (1 << _lib.RBT_STAGE_COUNT) - 1)
+        rbt.set_option(_lib.RBT_OPT_OUTER_NB, old_w)
         rbt.timing_read()
