@@ -196,12 +196,6 @@ def mixed_mode(args):
     BF16 updates, FP64 refinement to 10 n eps (or max_iter)."""
     import torch
     from paper_2312_09376_amd import rbt, workloads
-    if args.outer_nb:
-        rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, args.outer_nb)
-    if args.lookahead >= 0:
-        rbt.set_option(rbt._lib.RBT_OPT_LOOKAHEAD, args.lookahead)
-    if args.panel_split >= 0:
-        rbt.set_option(rbt._lib.RBT_OPT_PANEL_SPLIT, args.panel_split)
 
     n, k, d = args.n, args.nrhs, args.depth
     tol = 10.0 * n * 2.0 ** -52
@@ -730,6 +724,13 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    # elimination options, for every mode that factors
+    if args.outer_nb:
+        rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, args.outer_nb)
+    if args.lookahead >= 0:
+        rbt.set_option(rbt._lib.RBT_OPT_LOOKAHEAD, args.lookahead)
+    if args.panel_split >= 0:
+        rbt.set_option(rbt._lib.RBT_OPT_PANEL_SPLIT, args.panel_split)
     if args.mode == "copy":
         copy_mode(args)
         return
@@ -745,12 +746,6 @@ def main():
     if args.mode == "small":
         small_mode(args)
         return
-    if args.outer_nb:
-        rbt.set_option(rbt._lib.RBT_OPT_OUTER_NB, args.outer_nb)
-    if args.lookahead >= 0:
-        rbt.set_option(rbt._lib.RBT_OPT_LOOKAHEAD, args.lookahead)
-    if args.panel_split >= 0:
-        rbt.set_option(rbt._lib.RBT_OPT_PANEL_SPLIT, args.panel_split)
 
     n, k, d = args.n, args.nrhs, args.depth
     tol = 10.0 * n * 2.0 ** -52

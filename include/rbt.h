@@ -514,7 +514,9 @@ int rbt_solve_backward_mixed(int64_t n, int64_t nrhs, const float *LU, int64_t l
  *   element receives the same updates, grouped into fewer, deeper products
  *   (a different order of the roundings, not a different method); the
  *   lookahead's block-row solves follow the same order, so the factors stay
- *   identical with and without lookahead. Default 1. */
+ *   identical with and without lookahead. 2 (default): order 1 for panels
+ *   with at least 8192 rows from their first row down, order 0 for the
+ *   others (whose deeper updates have too few tiles to gain). */
 #define RBT_OPT_PANEL_SPLIT 14
 /* Returns 0, -1 for an unknown option, -2 for an invalid value. */
 int rbt_set_option(int option, int64_t value);

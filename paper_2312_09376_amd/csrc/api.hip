@@ -74,6 +74,12 @@ namespace {
 
 inline int64_t nblocks(int64_t n) { return (n + kNB - 1) / kNB; }
 
+// Rows (from the panel's first row down) from which a panel takes the
+// recursive order by default: shorter panels have too few tiles in their
+// deeper updates to gain (measured: n = 1000 5-9 % and n = 8191 1 % slower
+// with recursive halves, n = 20000 1.5 % faster).
+constexpr int64_t kHalvesMinRows = 8192;
+
 // Tunable options (rbt_set_option).
 struct Options {
   int64_t outer_nb = 2048;  // width of the panel whose trailing update is one GEMM
@@ -90,7 +96,8 @@ struct Options {
   int64_t kind = 0;              // butterflies: 0 Eq. 3 (random diagonals), 1 rotations
   int64_t sides = 2;             // 2: U^T A V; 1: U^T A (one-sided)
   int64_t capturable = 0;        // refinement without host tests (graph capturable)
-  int64_t panel_split = 1;       // panel: 0 one 128-block after another, 1 recursive halves
+  int64_t panel_split = 2;       // panel: 0 one 128-block after another, 1 recursive halves,
+                                 // 2 recursive halves for panels of >= kHalvesMinRows rows
 };
 Options &options() {
   static Options o;
@@ -331,7 +338,8 @@ int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t
   // the block joins the panel's own update in one launch (the same
   // operations on every element as solving the block row after the panel,
   // in fewer launches). ----
-  const bool halves = options().panel_split != 0;
+  const int64_t split = options().panel_split;
+  auto halves = [&](int64_t k0) { return split == 1 || (split == 2 && n - k0 >= kHalvesMinRows); };
   // ---- recursive order of the same panel (RBT_OPT_PANEL_SPLIT = 1): the
   // columns [k, k + w) of a panel whose block-row solves reach column e are
   // split into a left part of ceil(blocks / 2) whole 128-blocks and the
@@ -393,7 +401,7 @@ int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t
     return halves_rows(k + h, w - h, c0, nc, st);
   };
   auto panel = [&](int64_t k0, int64_t w, int64_t nt) -> int {
-    if (halves) return halves_panel(k0, w, k0 + w + nt);
+    if (halves(k0)) return halves_panel(k0, w, k0 + w + nt);
     for (int64_t k = k0; k < k0 + w; k += kNB) {
       const int kb = int(k0 + w - k < kNB ? k0 + w - k : kNB);
       T *A11 = A + k + k * lda;
@@ -423,7 +431,7 @@ int genp_impl(int64_t n, T *A, int64_t lda, int32_t *info, int prec, hipStream_t
   // of depth w (on stream st) ----
   auto update = [&](int64_t k0, int64_t w, int64_t c0, int64_t nc, hipStream_t st,
                     bool rows_done) -> int {
-    if (halves && !rows_done) {
+    if (halves(k0) && !rows_done) {
       const int rc = halves_rows(k0, w, c0, nc, st);
       if (rc) return rc;
       rows_done = true;
@@ -1787,7 +1795,7 @@ extern "C" int rbt_set_option(int option, int64_t value) {
       options().capturable = value;
       return 0;
     case RBT_OPT_PANEL_SPLIT:
-      if (value != 0 && value != 1) return -2;
+      if (value < 0 || value > 2) return -2;
       options().panel_split = value;
       return 0;
     case RBT_OPT_TIMING_STAGES:

@@ -48,12 +48,12 @@ def test_panel_options(lib):
     lib.rbt_set_option.argtypes = [ctypes.c_int, ctypes.c_int64]
     get = lambda o: lib.rbt_get_option(o)
     w0, s0 = get(_lib.RBT_OPT_OUTER_NB), get(_lib.RBT_OPT_PANEL_SPLIT)
-    assert (w0, s0) == (2048, 1)
+    assert (w0, s0) == (2048, 2)
     try:
-        for v in (0, 1):
+        for v in (0, 1, 2):
             assert lib.rbt_set_option(_lib.RBT_OPT_PANEL_SPLIT, v) == 0
             assert get(_lib.RBT_OPT_PANEL_SPLIT) == v
-        assert lib.rbt_set_option(_lib.RBT_OPT_PANEL_SPLIT, 2) == -2
+        assert lib.rbt_set_option(_lib.RBT_OPT_PANEL_SPLIT, 3) == -2
         assert lib.rbt_set_option(_lib.RBT_OPT_PANEL_SPLIT, -1) == -2
         for v in (128, 1152, 2048):
             assert lib.rbt_set_option(_lib.RBT_OPT_OUTER_NB, v) == 0

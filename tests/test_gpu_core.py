@@ -315,14 +315,16 @@ def test_backward_error_kernel(rbt):
     assert math.isclose(float(be.item()), be_o, rel_tol=1e-9)
 
 
-@pytest.mark.parametrize("split", [0, 1])
-@pytest.mark.parametrize("n,W", [(3000, 1024), (1000, 256), (2200, 512)])
+@pytest.mark.parametrize("n,W,split", [(3000, 1024, 0), (1000, 256, 0), (2200, 512, 0),
+                                       (3000, 1024, 1), (1000, 256, 1), (2200, 512, 1),
+                                       (8700, 2048, 2)])
 def test_lookahead_factors_identical(rbt, n, W, split):
     """The lookahead only reorders launches over disjoint columns on two
     streams: FP64, FP32 and BF16-update factors are bit-identical with it on
     and off, and the mixed solves give the same solution; in both orders of
     the work inside a panel (the lookahead's block-row solves follow the
-    panel's order)."""
+    panel's order; with the default order the first panels of n = 8700 take
+    recursive halves and the last ones the block-by-block order)."""
     A = workloads.shifted(n, seed=n)
     old_w = rbt.get_option(rbt._lib.RBT_OPT_OUTER_NB)
     old_s = rbt.get_option(rbt._lib.RBT_OPT_PANEL_SPLIT)
