@@ -42,6 +42,10 @@ KERNEL_TRAFFIC = {
              # k_hgemm plus its two operand conversions (the timed trailing stage)
              "bytes_per_launch": ((2 * 1811397.4 + 1448020.9) + (2 * 65548.8 + 109875.7)
                                   + (2 * 65561.2 + 65536.0)) * 1024},
+    "fp32": {"source": "paper_2312_09376_amd/csrc/k_sgemm.hip",
+             "sha256": "914e1c235a5d3585ae2df9a60cb5770fbc189fdfee042a5b89fd31e4ba59f081",
+             "config": {"n": 32768, "nrhs": 1, "depth": 2, "outer_nb": 2048, "matrix": "dominant"},
+             "bytes_per_launch": (2 * 4755728.4 + 1354453.7) * 1024},
     "batched_fp32": {"source": "paper_2312_09376_amd/csrc/k_batched.hip",
                      "sha256": "3e931707a2cec70653f35bda832c91770d0af62339d4936353ee0a6cb2850d32",
                      "config": {"batch": 2048, "depth": 2, "matrix": "randn"},
@@ -273,8 +277,8 @@ def mixed_mode(args):
                    if staged else f"trailing-update GEMM (k_sgemm, {args.prec.upper()} MFMA)"),
         "achieved": round(gemm_tflops, 3), "peak": peak, "unit": "TFLOP/s",
         "frac": round(gemm_tflops / peak, 4),
-        "traffic": (measured_traffic("bf16", n=n, nrhs=k, depth=d, outer_nb=W,
-                                     matrix=args.matrix) if staged else None),
+        "traffic": measured_traffic("bf16" if staged else args.prec, n=n, nrhs=k, depth=d,
+                                    outer_nb=W, matrix=args.matrix),
         "algorithmic_bytes_per_launch": tr_bytes / max(lp_cnt, 1),
         "launches": lp_cnt, "avg_launch_ms": round(lp_ms / max(lp_cnt, 1), 4),
         "flops_per_launch": lp_work / max(lp_cnt, 1)}
