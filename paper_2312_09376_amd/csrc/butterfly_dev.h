@@ -118,7 +118,10 @@ __device__ __forceinline__ float convert_out<float>(double x) { return float(x);
 // read once, all layers of the pass in registers, write once.
 // (Pointer types are template parameters so that callers can pass pointers
 // qualified with the global address space.)
-template <int P, typename TO, typename PA, typename PO, typename PC>
+// STREAM: A is read and the output written with non-temporal hints (data
+// touched once, larger than the caches); callers that read the output back
+// soon (the batched kernel) keep the default.
+template <int P, typename TO, bool STREAM = false, typename PA, typename PO, typename PC>
 __device__ __forceinline__ void transform2_block(PA __restrict__ A, int64_t lda,
                                                  PO __restrict__ Out, int64_t ldo,
                                                  PC __restrict__ U, PC __restrict__ V,
@@ -137,7 +140,12 @@ __device__ __forceinline__ void transform2_block(PA __restrict__ A, int64_t lda,
 #pragma unroll
   for (int c = 0; c < G; ++c)
 #pragma unroll
-    for (int r = 0; r < G; ++r) x[r][c] = (rv[r] && cv[c]) ? A[ri[r] + ci[c] * lda] : 0.0;
+    for (int r = 0; r < G; ++r) {
+      if constexpr (STREAM)
+        x[r][c] = (rv[r] && cv[c]) ? __builtin_nontemporal_load(&A[ri[r] + ci[c] * lda]) : 0.0;
+      else
+        x[r][c] = (rv[r] && cv[c]) ? A[ri[r] + ci[c] * lda] : 0.0;
+    }
   const bool two = ps.sides != 1;
 #pragma unroll
   for (int bit = 0; bit < P; ++bit) {
@@ -217,7 +225,12 @@ __device__ __forceinline__ void transform2_block(PA __restrict__ A, int64_t lda,
   for (int c = 0; c < G; ++c)
 #pragma unroll
     for (int r = 0; r < G; ++r)
-      if (rv[r] && cv[c]) Out[ri[r] + ci[c] * ldo] = convert_out<TO>(x[r][c]);
+      if (rv[r] && cv[c]) {
+        if constexpr (STREAM)
+          __builtin_nontemporal_store(convert_out<TO>(x[r][c]), &Out[ri[r] + ci[c] * ldo]);
+        else
+          Out[ri[r] + ci[c] * ldo] = convert_out<TO>(x[r][c]);
+      }
 }
 
 // One-sided pass on column j of B for the group at rb. op T (U^T b):
