@@ -49,9 +49,9 @@ KERNEL_TRAFFIC = {
              "config": {"n": 32768, "nrhs": 1, "depth": 2, "outer_nb": 2048, "matrix": "dominant"},
              "bytes_per_launch": (2 * 4755728.4 + 1354453.7) * 1024},
     "batched_fp32": {"source": "paper_2312_09376_amd/csrc/k_batched.hip",
-                     "sha256": "3e931707a2cec70653f35bda832c91770d0af62339d4936353ee0a6cb2850d32",
+                     "sha256": "7e5d2b3d29a20b2468be1b6161cc084487143fdd8f6bf71a4c5aabd6ae2384d9",
                      "config": {"batch": 2048, "depth": 2, "matrix": "randn"},
-                     "bytes_per_launch": (2 * 187575530.8 + 92377023.8) * 1024},
+                     "bytes_per_launch": (2 * 172929152.5 + 95883867.0) * 1024},
 }
 
 

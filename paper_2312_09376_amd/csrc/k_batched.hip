@@ -1216,9 +1216,14 @@ __device__ __noinline__ double residual(const Sys &s, double *L0, bool with_anor
 // X = V (LU)^-1 U^T B with the factors of storage type TF, then classical
 // refinement in FP64 until the Eq. 7 backward error is <= tol, max_iter
 // corrections, stagnation or NaN.
+// project: when a fallback follows (the low-precision pass with FP64 factors
+// available), also stop once the observed rate of the last correction,
+// extrapolated, cannot reach tol within max_iter steps (the batch's slowest
+// systems are the large ones whose refinement fails; their hopeless steps
+// are spent before the fallback's elimination).
 template <int NRT, typename TF>
 __device__ void refine_system(const Sys &s, int d, double tol, int max_iter, double *L0,
-                              double *anorm_sh, int *it_out, double *be_out) {
+                              double *anorm_sh, int *it_out, double *be_out, bool project) {
   const int64_t n = s.n;
   double RBT_AS_GLOBAL *Xg = (double RBT_AS_GLOBAL *)s.Xm;
   const double RBT_AS_GLOBAL *Bg = (const double RBT_AS_GLOBAL *)s.Bm;
@@ -1238,6 +1243,11 @@ __device__ void refine_system(const Sys &s, int d, double tol, int max_iter, dou
     // stagnation: two corrections in a row that do not improve the best
     // backward error by 10 % end the refinement (reported not converged)
     stalled = (be < 0.9 * best) ? 0 : stalled + 1;
+    if (project && it >= 1 && be < best) {
+      // steps still needed at rate be / best: log(tol / be) / log(be / best)
+      const double need = log(tol / be) / log(be / best);
+      if (double(it) + need > double(max_iter)) break;
+    }
     if (be < best) best = be;
     if (stalled >= 2 || be != be) break;
     transform_vec_sys<RBT_OP_T>(s, d, s.R, n, s.U);
@@ -1356,18 +1366,18 @@ __device__ void solve_system(const Args &a, const BatchDesc &D, float *fbase, do
     int it_p = 0;
     if (pass == 0) {
       if (s.nrhs <= 1)
-        refine_system<1, float>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be);
+        refine_system<1, float>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be, s.F64 != nullptr);
       else if (s.nrhs <= 4)
-        refine_system<4, float>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be);
+        refine_system<4, float>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be, s.F64 != nullptr);
       else
-        refine_system<NR, float>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be);
+        refine_system<NR, float>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be, s.F64 != nullptr);
     } else {
       if (s.nrhs <= 1)
-        refine_system<1, double>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be);
+        refine_system<1, double>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be, false);
       else if (s.nrhs <= 4)
-        refine_system<4, double>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be);
+        refine_system<4, double>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be, false);
       else
-        refine_system<NR, double>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be);
+        refine_system<NR, double>(s, d, tol, a.max_iter, L0, anorm_sh, &it_p, &be, false);
     }
     it += it_p;
   }
